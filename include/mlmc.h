@@ -1,0 +1,267 @@
+/*
+ * mlmc.h -- C ABI of the MI355X (gfx950) library for the per-sample hot path
+ * of the multigrid multilevel (quasi-)Monte Carlo method with sample
+ * recycling (Robbe, Nuyens, Vandewalle).
+ *
+ * Problem (Section 1, eq. PDE; Section 6 "Discretization"):
+ *   -div(a(x,y) grad u(x,y)) = 1 on D = [0,1]^2, u = 0 on the boundary,
+ *   a = exp(z), z a zero-mean Gaussian field given by its truncated KL
+ *   expansion (Section 5, eq. truncatedKL) with the separable exponential
+ *   covariance sigma^2 exp(-|x1-x1'|/lambda - |x2-x2'|/lambda).
+ * Per sample: points (Section 3.2) -> KL field on every grid of the
+ * hierarchy -> full multigrid (Section 4, figure FMG) -> the QoI of every FMG
+ * stage, i.e. of every level l <= k, recycled into the level differences
+ * F_l - F_{l-1} (Section 3.2, eq. Upsilon-reuse) -> estimators.
+ *
+ * Grids.  Multigrid level g has n_g = 2^(g+1) cells per side (g = 0 is 2x2,
+ * solved exactly).  MLMC level l has n0 * 2^l cells per side, i.e. it is
+ * multigrid level g0 + l with g0 = log2(n0) - 1.  Cell (i,j) of an n x n grid
+ * has centre ((i+1/2)/n, (j+1/2)/n) and flat index i + n*j (i fastest).
+ * A per-sample field over levels 0..G is stored level after level.
+ *
+ * Discretisation: cell-centred finite volumes; an interior face carries the
+ * harmonic mean 2 a_P a_N / (a_P + a_N), a boundary face 2 a_P (the cell value
+ * at distance h/2 from the wall).  Smoother: red-black Gauss-Seidel, red =
+ * (i+j) even, red first before the coarse-grid correction, black first after.
+ * Restriction: mean of the four children.  Prolongation and FMG
+ * interpolation: bilinear (9,3,3,1)/16 with odd reflection across walls.
+ *
+ * Conventions for every entry point:
+ *  - Return value: mlmc_status, 0 on success, negative on error.  No C++
+ *    exception or longjmp crosses the ABI.
+ *  - Pointers named *_dev are device pointers on the context's device; all
+ *    other pointers are host pointers.  The caller owns every buffer it
+ *    passes; the context owns its own workspace (allocated at create).
+ *  - Calls that take a stream enqueue their work on that hipStream_t (NULL =
+ *    the default stream) and return without waiting, except where stated.
+ *  - Argument errors (MLMC_E_INVAL) are detected before any GPU work is
+ *    enqueued and leave every output untouched.
+ *  - A context must not be used by two host threads at once; calls that
+ *    share a context are ordered by the host, and their device work is
+ *    ordered by the streams the caller passes.
+ */
+#ifndef MLMC_H
+#define MLMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MLMC_OK = 0,
+    MLMC_E_INVAL = -1,   /* invalid argument; nothing was written */
+    MLMC_E_NOMEM = -2,   /* device memory (HBM) budget exceeded */
+    MLMC_E_HIP = -3,     /* a HIP runtime call failed; see mlmc_last_error */
+    MLMC_E_NOCONV = -4,  /* refinement hit max_iters before rtol; outputs written */
+    MLMC_E_STATE = -5    /* context unusable (e.g. earlier HIP failure) */
+} mlmc_status;
+
+enum { MLMC_FP64 = 0, MLMC_MIXED = 1 };
+
+/* QoI selection (Section 6 "Quantity of interest" and its readings):
+ * MEAN   = n^-2 sum_P u_P (midpoint rule for the mean of u),
+ * CENTER = mean of the four cells touching (1/2,1/2) (a grid vertex). */
+enum { MLMC_QOI_MEAN = 1u, MLMC_QOI_CENTER = 2u };
+
+enum { MLMC_POINTS_LATTICE = 0, MLMC_POINTS_EXPLICIT = 1 };
+
+typedef struct mlmc_ctx_s *mlmc_ctx;
+
+typedef struct {
+    int32_t n0;           /* cells per side on MLMC level 0; power of two >= 2 */
+    int32_t num_levels;   /* MLMC levels 0..num_levels-1; finest n0 * 2^(L) <= 4096 */
+    int32_t s;            /* number of KL terms (stochastic dimension), 1..4096 */
+    double corr_len;      /* correlation length lambda > 0 */
+    double sigma2;        /* pointwise variance sigma^2 >= 0 of the full field z */
+    int32_t mu0;          /* V-cycles per FMG stage (fixed-cycle mode), >= 1 */
+    int32_t mu1, mu2;     /* pre-/post-smoothing red-black sweeps, >= 0, sum >= 1 */
+    double rtol;          /* 0: fixed mu0 cycles.  > 0: every stage iterates
+                             V-cycles on the residual until ||f-Au||_2/||f||_2 <= rtol */
+    int32_t max_iters;    /* refinement cap per stage when rtol > 0 (>= 1) */
+    int32_t precision;    /* MLMC_FP64, or MLMC_MIXED (FP32 field and V-cycles
+                             inside FP64 residual refinement; needs rtol > 0) */
+    uint32_t qoi_mask;    /* non-empty subset of MLMC_QOI_MEAN | MLMC_QOI_CENTER;
+                             nq = number of bits, QoI q in increasing bit order */
+    int32_t num_shifts;   /* R, number of random shifts (>= 1 if shifts given) */
+    const uint32_t *genvec;  /* host [s]: generating vector z mod 2^32 (odd
+                                entries give full projections); NULL disables
+                                lattice points.  Copied at create. */
+    const uint64_t *shifts;  /* host [num_levels][num_shifts][s]: shift
+                                Delta_l^(r)_j as 64-bit fixed point (value / 2^64);
+                                NULL disables lattice points.  Copied at create. */
+    int64_t max_batch;    /* samples of the finest level solved at once; sizes
+                             the workspace (coarser levels run larger chunks) */
+} mlmc_config;
+
+/* A set of samples, all with finest MLMC level `level` (Algorithm 1,
+ * SampleAndSolve: the solve yields every level tau <= level).
+ * LATTICE (Section 3.2, and the lattice sequence of Section 6 "QMC method"):
+ *   point n of shift r is x_j = (bitrev32(n) z_j mod 2^32) 2^32 + Delta_{level,r,j}
+ *   (mod 2^64), u_j = (2 floor(x_j / 2^12) + 1) 2^-53, y_j = Phi^-1(u_j).
+ *   Samples are ordered shift-major: b = (r - shift_begin) * (n_end - n_begin)
+ *   + (n - n_begin), B = (shift_end - shift_begin) * (n_end - n_begin).
+ *   Requires 0 <= n_begin <= n_end <= 2^32 and
+ *   0 <= shift_begin < shift_end <= num_shifts.
+ * EXPLICIT (plain Monte Carlo or any caller-chosen y): y_dev [B][s] FP64 on the
+ *   device, B = n_end - n_begin, shift_end - shift_begin must be 1 (the
+ *   replica index is only a label). */
+typedef struct {
+    int32_t kind;
+    int32_t level;
+    int32_t shift_begin, shift_end;
+    int64_t n_begin, n_end;
+    const double *y_dev;
+} mlmc_points;
+
+typedef struct {
+    int64_t samples;          /* B */
+    int32_t max_iters_used;   /* rtol mode: largest refinement count of any
+                                 stage of any sample; fixed mode: mu0 */
+    double max_rel_residual;  /* rtol mode: largest final ||f-Au||/||f||;
+                                 fixed mode: -1 */
+    int64_t not_converged;    /* rtol mode: samples with a stage at max_iters */
+} mlmc_solve_info;
+
+/* Create a context on `device`: validates cfg, builds the KL mode table and
+ * basis (analytic 1-D eigenpairs, Section 5 with the exponential kernel),
+ * uploads generating vector and shifts, allocates the workspace for
+ * max_batch finest-level samples.  E_NOMEM if it does not fit in free HBM.
+ * Synchronous.  device < 0 creates a host-only context that makes no HIP
+ * call: mlmc_kl_modes, mlmc_fmg_trace, mlmc_field_size and mlmc_num_qoi work,
+ * the GPU entry points return MLMC_E_STATE. */
+mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out);
+
+/* Free the context and its device memory.  Synchronises the device first.
+ * NULL is accepted. */
+mlmc_status mlmc_destroy(mlmc_ctx ctx);
+
+/* Values per sample of a field over MG levels 0..G(level), i.e.
+ * sum_{g <= g0+level} n_g^2; 0 for an invalid level. */
+int64_t mlmc_field_size(mlmc_ctx ctx, int32_t level);
+
+/* Number of QoIs selected by qoi_mask (1 or 2); 0 for a NULL context. */
+int32_t mlmc_num_qoi(mlmc_ctx ctx);
+
+/* Section 3.2: the points of `pts`.  x_dev [B][s] receives the shifted lattice
+ * points in 64-bit fixed point (LATTICE only; NULL to skip), y_dev [B][s] the
+ * normals y = Phi^-1(u) (NULL to skip; EXPLICIT copies the input). */
+mlmc_status mlmc_points_gen(mlmc_ctx ctx, const mlmc_points *pts,
+                            uint64_t *x_dev, double *y_dev, void *hip_stream);
+
+/* Section 5, eq. truncatedKL: z(x) = sigma sum_{m<s} sqrt(theta_m) psi_m(x) y_m
+ * at the cell centres of every MG level 0..G(level) of every sample, as one
+ * dense product Y [B][s] x basis [s][M].  z_dev [B][M], M = mlmc_field_size
+ * (sample-major, levels in order).  FP64 in both precision modes (the MIXED
+ * solve uses its own reduced-precision product internally). */
+mlmc_status mlmc_field(mlmc_ctx ctx, const mlmc_points *pts, double *z_dev,
+                       void *hip_stream);
+
+/* The hot path for one set of samples (Algorithm 1, SampleAndSolve body):
+ * field (unless z_dev is given) -> a = exp(z) -> FMG from the 2x2 grid up to
+ * level g0+pts->level, recording the QoI at the end of every stage that is an
+ * MLMC level (Section 4, the circled solutions of the FMG figure) -> level
+ * differences.
+ *   z_dev    [B][M] or NULL: log-coefficient to use instead of computing it.
+ *   qoi_dev  [B][level+1][nq] or NULL: F_l of every sample and level.
+ *   sums_dev [R_b][nq][level+1][2] or NULL, R_b = shift_end - shift_begin:
+ *            sum over the samples of shift r of (F_l - F_{l-1}) and of its
+ *            square (F_{-1} = 0), compensated FP64 sums.
+ *   info     host, optional; filling it synchronises the stream.
+ * Returns MLMC_E_NOCONV (outputs still written) if info was requested and
+ * some sample hit max_iters. */
+mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts,
+                           const double *z_dev, double *qoi_dev,
+                           double *sums_dev, mlmc_solve_info *info,
+                           void *hip_stream);
+
+/* Estimator input (Section 3.2, eqs. MLQMC, Upsilon-reuse, MGMLQMC):
+ * sums[k][r][q][l][2] as produced by mlmc_fmg_solve for the samples of shift r
+ * with finest level k (entries with l > k are ignored), n_per_level[k] = N_k
+ * samples per shift with finest level k. */
+typedef struct {
+    int32_t num_levels;       /* L + 1 */
+    int32_t num_shifts;       /* R >= 1 */
+    int32_t nq;               /* 1 or 2 */
+    int32_t reuse;            /* 1: recycle coarse solutions (MG-MLQMC) */
+    const int64_t *n_per_level;
+    const double *sums;
+} mlmc_est_input;
+
+/* Estimator outputs (host arrays, caller-allocated):
+ *   upsilon     [nq][L+1][R]  Upsilon_{l,r} (eq. Upsilon-reuse, or its
+ *                             no-recycling form 1/N_l sum over level-l samples)
+ *   upsilon_bar [nq][L+1]     mean over shifts (eq. Upsilon-reuse-bar)
+ *   var_level   [nq][L+1]     R >= 2: sum_r (Upsilon_{l,r}-bar)^2 / (R(R-1))
+ *                             (eq. sample_variances); R = 1 without reuse:
+ *                             s_l^2 / N_l (eq. vardecomp); R = 1 with reuse: NaN
+ *   q_shift     [nq][R]       Q_r = sum_l Upsilon_{l,r}
+ *   q_bar       [nq]          mean over shifts (eq. MLQMC / MGMLQMC)
+ *   var_q       [nq]          eq. varovershifts / var_of_mgmlqmc (R >= 2);
+ *                             sum of var_level (R = 1, no reuse); NaN otherwise */
+typedef struct {
+    double *upsilon;
+    double *upsilon_bar;
+    double *var_level;
+    double *q_shift;
+    double *q_bar;
+    double *var_q;
+} mlmc_est_output;
+
+/* Host-only and synchronous; touches no GPU.  Levels without samples at or
+ * above them (sum_{i>=l} N_i = 0) give Upsilon = 0. */
+mlmc_status mlmc_estimate(const mlmc_est_input *in, mlmc_est_output *out);
+
+/* The ordered 2-D KL mode table (descending theta_i theta_j, ties by i
+ * ascending): i_out, j_out [s] 1-based 1-D indices, theta_out [s] products.
+ * Any output may be NULL.  Host-only. */
+mlmc_status mlmc_kl_modes(mlmc_ctx ctx, int32_t *i_out, int32_t *j_out,
+                          double *theta_out);
+
+/* The level-visit sequence of the FMG schedule the library runs for finest
+ * MLMC level `level` (Section 4, figure FMG): levels[len] are multigrid levels,
+ * marks[len] is 1 where a stage solution is recorded.  Consecutive repeats
+ * are merged; the initial descent G..1 (problem set-up) is included.  In rtol
+ * mode the schedule depends on convergence, so E_INVAL.  Host-only; writes at
+ * most cap entries and the full length to *len. */
+mlmc_status mlmc_fmg_trace(mlmc_ctx ctx, int32_t level, int32_t *levels,
+                           int32_t *marks, int64_t cap, int64_t *len);
+
+/* Live timing of one kernel kind, for measuring the path against its
+ * roofline.  Between mlmc_profile_begin and mlmc_profile_end every launch of
+ * that kind is bracketed by HIP events on the stream it is launched on, and
+ * its algorithmic HBM bytes and flops are accumulated:
+ *   SMOOTH   one red-black colour on n^2 cells: a (n^2) + u of the other colour
+ *            (n^2/2) + f of the colour (n^2/2, absent when f = 1) read, u of the
+ *            colour (n^2/2) written, per sample
+ *   RESTRICT residual + restriction: a, u (and f) read on n^2, f_c and the
+ *            cleared coarse iterate written on n^2/4
+ *   PROLONG  coarse-grid correction: e_c (n^2/4) read, u read and written;
+ *            FMG interpolation: e_c read, u written
+ *   FIELD    dense product: 2 B s M flops; Y, basis and the output once
+ *   QOI, COARSE, POINTS, SUMS: their inputs and outputs once
+ * Host-synchronous at end.  At most one kind is profiled at a time. */
+enum {
+    MLMC_KERNEL_POINTS = 0, MLMC_KERNEL_FIELD = 1, MLMC_KERNEL_SMOOTH = 2,
+    MLMC_KERNEL_RESTRICT = 3, MLMC_KERNEL_PROLONG = 4, MLMC_KERNEL_COARSE = 5,
+    MLMC_KERNEL_QOI = 6, MLMC_KERNEL_SUMS = 7
+};
+typedef struct {
+    int64_t launches;
+    double total_ms;      /* sum of the event-measured launch durations */
+    double bytes;         /* sum of algorithmic HBM bytes over the launches */
+    double flops;         /* sum of algorithmic flops over the launches */
+} mlmc_profile_result;
+mlmc_status mlmc_profile_begin(mlmc_ctx ctx, int32_t kernel_kind);
+mlmc_status mlmc_profile_end(mlmc_ctx ctx, mlmc_profile_result *out);
+
+const char *mlmc_status_str(mlmc_status st);
+/* Text of the last error on ctx (empty string if none); NULL ctx gives the
+ * last error of a failed mlmc_create on this thread. */
+const char *mlmc_last_error(mlmc_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLMC_H */

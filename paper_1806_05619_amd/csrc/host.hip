@@ -1,0 +1,893 @@
+// Host side of the MI355X MG-MLQMC library: context, argument checking, KL
+// tables, the full-multigrid schedule (Section 4) driven from the host over
+// batched kernels, and the estimators (Sections 2-3).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace mlmc;
+
+struct mlmc_ctx_s {
+    mlmc_config cfg{};
+    int device = 0;
+    int g0 = 0, Gmax = 0, nq = 0;
+    bool have_lattice = false;
+    bool broken = false;
+    bool host_only = false;      // device < 0: tables and schedule only
+    std::string err;
+
+    // KL mode table (host)
+    std::vector<int32_t> mi, mj;
+    std::vector<double> theta2;
+
+    // device memory
+    uint32_t *d_z = nullptr;
+    uint64_t *d_shifts = nullptr;
+    double *d_basis = nullptr;   // [s][Mmax]
+    int64_t Mmax = 0;
+    int64_t pool = 0;            // doubles per pool
+    double *d_a = nullptr, *d_u = nullptr, *d_f = nullptr;
+    double *d_e = nullptr;       // rtol: top-level correction, ecap doubles
+    int64_t ecap = 0;
+    int64_t chunk_max = 0;       // upper bound of samples per chunk
+    double *d_y = nullptr;       // [chunk_max][s]
+    double *d_qoi = nullptr;     // [chunk_max][num_levels][nq]
+    double *d_state = nullptr;   // [max shifts][nq][num_levels][4]
+    int64_t state_tuples = 0;
+    double *d_rho = nullptr;
+    int32_t *d_active = nullptr, *d_iters = nullptr;
+    int32_t *h_active = nullptr, *h_iters = nullptr;
+    double *h_rho = nullptr;
+    std::vector<void *> allocs;
+
+    // live per-kernel timing (mlmc_profile_begin/end)
+    struct {
+        int kind = -1;
+        std::vector<hipEvent_t> ev;   // start/stop pairs, reused across sessions
+        size_t used = 0;
+        int64_t launches = 0;
+        double bytes = 0.0, flops = 0.0;
+    } prof;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+const char *kStatusText[] = {"ok", "invalid argument", "out of device memory", "HIP error",
+                             "not converged", "context unusable"};
+
+#define HIPCHK(ctx, call)                                                            \
+    do {                                                                             \
+        hipError_t _e = (call);                                                      \
+        if (_e != hipSuccess) {                                                      \
+            (ctx)->err = std::string(#call) + ": " + hipGetErrorString(_e);          \
+            (ctx)->broken = true;                                                    \
+            return MLMC_E_HIP;                                                       \
+        }                                                                            \
+    } while (0)
+
+mlmc_status inval(mlmc_ctx ctx, const char *msg)
+{
+    if (ctx)
+        ctx->err = msg;
+    return MLMC_E_INVAL;
+}
+
+int ilog2_exact(int v)
+{
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return (1 << r) == v ? r : -1;
+}
+
+// ---- Section 5: eigenpairs of exp(-|x-t|/lam) on [0,1] ---------------------
+// Characteristic equation F(w) = (lam^2 w^2 - 1) sin w - 2 lam w cos w = 0 with
+// one root in each ((k-1) pi, k pi); found by Newton's method kept inside a
+// shrinking sign bracket.
+double char_eq(double lam, double w, double *deriv)
+{
+    double sw = std::sin(w), cw = std::cos(w), l2w2 = lam * lam * w * w;
+    *deriv = (2.0 * lam * lam * w + 2.0 * lam * w) * sw + (l2w2 - 1.0 - 2.0 * lam) * cw;
+    return (l2w2 - 1.0) * sw - 2.0 * lam * w * cw;
+}
+
+double kl_root(double lam, int k)
+{
+    const double pi = 3.14159265358979323846;
+    double lo = (k - 1) * pi, hi = k * pi;
+    const bool lo_pos = (k % 2 == 0);   // F just above (k-1) pi: < 0 for k = 1, sign (-1)^k else
+    double w = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+        double d;
+        double f = char_eq(lam, w, &d);
+        if (f == 0.0)
+            return w;
+        if ((f > 0.0) == lo_pos) lo = w; else hi = w;
+        double wn = (d != 0.0) ? w - f / d : 0.5 * (lo + hi);
+        if (!(wn > lo && wn < hi))
+            wn = 0.5 * (lo + hi);
+        if (std::fabs(wn - w) <= 2.0 * std::nextafter(w, 2.0 * hi) - 2.0 * w || hi <= std::nextafter(lo, hi))
+            return wn;
+        w = wn;
+    }
+    return w;
+}
+
+double kl_eigenvalue(double lam, double w) { return 2.0 * lam / (1.0 + lam * lam * w * w); }
+
+double kl_eigenfunction(double lam, double w, double x)
+{
+    return (std::sin(w * x) + lam * w * std::cos(w * x)) /
+           std::sqrt(lam + 0.5 * (1.0 + lam * lam * w * w));
+}
+
+int64_t field_size_g(int G) { return level_offset(G + 1); }
+
+void free_all(mlmc_ctx c)
+{
+    for (hipEvent_t e : c->prof.ev) (void)hipEventDestroy(e);
+    c->prof.ev.clear();
+    for (void *p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    if (c->h_active) (void)hipHostFree(c->h_active);
+    if (c->h_iters) (void)hipHostFree(c->h_iters);
+    if (c->h_rho) (void)hipHostFree(c->h_rho);
+    c->h_active = nullptr;
+    c->h_iters = nullptr;
+    c->h_rho = nullptr;
+}
+
+template <typename T>
+hipError_t dev_alloc(mlmc_ctx c, T **p, int64_t count)
+{
+    *p = nullptr;
+    if (count <= 0)
+        return hipSuccess;
+    void *v = nullptr;
+    hipError_t e = hipMalloc(&v, (size_t)count * sizeof(T));
+    if (e == hipSuccess) {
+        c->allocs.push_back(v);
+        *p = (T *)v;
+    }
+    return e;
+}
+
+// samples per chunk for finest MLMC level k
+int64_t chunk_capacity(mlmc_ctx c, int k)
+{
+    int G = c->g0 + k;
+    int64_t cap = c->pool / field_size_g(G);
+    if (c->cfg.rtol > 0.0)
+        cap = std::min(cap, c->ecap / level_cells(G));
+    return std::max<int64_t>(1, std::min(cap, c->chunk_max));
+}
+
+mlmc_status check_points(mlmc_ctx c, const mlmc_points *p, int64_t *B, int64_t *npts, int *nsh)
+{
+    if (!p)
+        return inval(c, "points is NULL");
+    if (p->level < 0 || p->level >= c->cfg.num_levels)
+        return inval(c, "points.level out of range");
+    if (p->n_begin < 0 || p->n_end < p->n_begin)
+        return inval(c, "points range must satisfy 0 <= n_begin <= n_end");
+    if (p->kind == MLMC_POINTS_LATTICE) {
+        if (!c->have_lattice)
+            return inval(c, "lattice points need genvec and shifts at create");
+        if (p->n_end > ((int64_t)1 << 32))
+            return inval(c, "lattice index beyond 2^32");
+        if (p->shift_begin < 0 || p->shift_end <= p->shift_begin ||
+            p->shift_end > c->cfg.num_shifts)
+            return inval(c, "shift range out of [0, num_shifts)");
+    } else if (p->kind == MLMC_POINTS_EXPLICIT) {
+        if (p->shift_end - p->shift_begin != 1)
+            return inval(c, "explicit points take exactly one replica (shift_end - shift_begin == 1)");
+        if (!p->y_dev && p->n_end > p->n_begin)
+            return inval(c, "explicit points need y_dev");
+    } else {
+        return inval(c, "unknown points.kind");
+    }
+    *npts = p->n_end - p->n_begin;
+    *nsh = p->shift_end - p->shift_begin;
+    *B = *npts * *nsh;
+    return MLMC_OK;
+}
+
+// y of samples [b0, b0+Bc) of a point set, on the device
+const double *chunk_y(mlmc_ctx c, hipStream_t st, const mlmc_points *p, int64_t npts, int64_t b0,
+                      int64_t Bc, uint64_t *x_out)
+{
+    if (p->kind == MLMC_POINTS_EXPLICIT)
+        return p->y_dev + b0 * c->cfg.s;
+    launch_points(st, c->d_z, c->d_shifts, c->cfg.s, c->cfg.num_shifts, p->level, p->shift_begin,
+                  p->n_begin, npts, b0, Bc, x_out, c->d_y);
+    return c->d_y;
+}
+
+Hier make_hier(mlmc_ctx c, int G, int64_t Bc)
+{
+    Hier h;
+    h.G = G;
+    h.Bc = Bc;
+    for (int g = 0; g <= G; ++g) {
+        int64_t off = Bc * level_offset(g);
+        h.a[g] = c->d_a + off;
+        h.u[g] = c->d_u + off;
+        h.f[g] = c->d_f + off;
+    }
+    return h;
+}
+
+// Brackets one launch with events when its kind is being profiled.
+struct ProfScope {
+    mlmc_ctx c;
+    hipStream_t st;
+    bool on = false;
+    size_t idx = 0;
+    ProfScope(mlmc_ctx c_, hipStream_t st_, int kind, double bytes, double flops) : c(c_), st(st_)
+    {
+        if (c->prof.kind != kind) return;
+        idx = c->prof.used;
+        while (c->prof.ev.size() < 2 * (idx + 1)) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            c->prof.ev.push_back(e);
+        }
+        on = hipEventRecord(c->prof.ev[2 * idx], st) == hipSuccess;
+        if (!on) return;
+        c->prof.launches++;
+        c->prof.bytes += bytes;
+        c->prof.flops += flops;
+    }
+    ~ProfScope()
+    {
+        if (!on) return;
+        (void)hipEventRecord(c->prof.ev[2 * idx + 1], st);
+        c->prof.used++;
+    }
+};
+
+// ---- Section 4: correction scheme / V-cycle / FMG --------------------------
+struct Trace {
+    std::vector<int32_t> lev, mark;
+    void visit(int g)
+    {
+        if (!lev.empty() && lev.back() == g) return;
+        lev.push_back(g);
+        mark.push_back(0);
+    }
+    void record()
+    {
+        if (!mark.empty()) mark.back() = 1;
+    }
+};
+
+struct Runner {
+    mlmc_ctx c;
+    hipStream_t st;
+    Hier h;
+    Trace *tr;                 // dry run when non-null
+    const int32_t *active;     // refinement: skip converged samples
+
+    double cells(int n) const { return (double)h.Bc * n * n; }
+
+    void smooth(int g, const double *f, double *x, int colour)
+    {
+        const int n = 2 << g;
+        ProfScope ps(c, st, MLMC_KERNEL_SMOOTH, 8.0 * cells(n) * (f ? 2.5 : 2.0), 0.0);
+        launch_rbgs(st, h.a[g], f, x, n, h.Bc, colour, active);
+    }
+    void restrict_to(int g, const double *f, const double *x)
+    {
+        const int n = 2 << g;
+        ProfScope ps(c, st, MLMC_KERNEL_RESTRICT, 8.0 * cells(n) * ((f ? 3.0 : 2.0) + 0.5), 0.0);
+        launch_resid_restrict(st, h.a[g], f, x, n, h.Bc, h.f[g - 1], h.u[g - 1], active);
+    }
+    void prolong(int g, const double *ec, double *x, int add, const int32_t *act)
+    {
+        const int n = 2 << g;
+        ProfScope ps(c, st, MLMC_KERNEL_PROLONG, 8.0 * cells(n) * (add ? 2.25 : 1.25), 0.0);
+        launch_prolong(st, ec, x, n, h.Bc, add, act);
+    }
+    void coarse(const double *f, double *x)
+    {
+        ProfScope ps(c, st, MLMC_KERNEL_COARSE, 8.0 * h.Bc * 4 * (f ? 3 : 2), 0.0);
+        launch_coarse_solve(st, h.a[0], f, x, h.Bc, active);
+    }
+
+    // V(mu1,mu2) on level g for the iterate x[g] (x = u pool below the top).
+    // top_x / top_f override the iterate and rhs of level g (nullptr f = 1).
+    void vcycle(int g, double *top_x, const double *top_f)
+    {
+        if (tr) tr->visit(g);
+        double *x = top_x ? top_x : h.u[g];
+        const double *f = top_x ? top_f : h.f[g];
+        if (g == 0) {
+            if (!tr) coarse(f, x);
+            return;
+        }
+        for (int it = 0; it < c->cfg.mu1; ++it) {
+            if (!tr) {
+                smooth(g, f, x, 0);
+                smooth(g, f, x, 1);
+            }
+        }
+        if (!tr) restrict_to(g, f, x);
+        vcycle(g - 1, nullptr, nullptr);
+        if (tr) tr->visit(g);
+        if (!tr) prolong(g, h.u[g - 1], x, 1, active);
+        for (int it = 0; it < c->cfg.mu2; ++it) {
+            if (!tr) {
+                smooth(g, f, x, 1);
+                smooth(g, f, x, 0);
+            }
+        }
+    }
+};
+
+struct StageStats {
+    int max_iters = 0;
+    double max_rho = -1.0;
+    int64_t noconv = 0;            // samples with any stage stopped at max_iters
+    std::vector<uint8_t> bad;      // per sample of the current chunk
+};
+
+// FMG for one chunk; qoi rows of the chunk at qoi [Bc][k+1][nq].
+mlmc_status run_fmg(mlmc_ctx c, hipStream_t st, const Hier &h, int k, double *qoi, Trace *tr,
+                    StageStats *stats)
+{
+    const int G = h.G, g0 = c->g0, nlev = k + 1;
+    Runner R{c, st, h, tr, nullptr};
+    if (stats) stats->bad.assign((size_t)h.Bc, 0);
+    if (tr)
+        for (int g = G; g > 0; --g) tr->visit(g);   // initial descent: set-up
+    // stage 0: exact solve with f = 1 on the 2x2 grid
+    R.vcycle(0, h.u[0], nullptr);
+    if (tr) tr->record();
+    if (!tr && g0 == 0) {
+        ProfScope ps(c, st, MLMC_KERNEL_QOI, 8.0 * h.Bc * 4, 0.0);
+        launch_qoi(st, h.u[0], 2, h.Bc, qoi, nlev, 0, c->cfg.qoi_mask);
+    }
+    for (int g = 1; g <= G; ++g) {
+        const int n = 2 << g;
+        if (tr) tr->visit(g);
+        // nested iteration: interpolate the previous stage's solution
+        if (!tr) R.prolong(g, h.u[g - 1], h.u[g], 0, nullptr);
+        if (c->cfg.rtol <= 0.0) {
+            for (int cyc = 0; cyc < c->cfg.mu0; ++cyc) R.vcycle(g, h.u[g], nullptr);
+            if (stats) stats->max_iters = std::max(stats->max_iters, c->cfg.mu0);
+        } else {
+            // FP64 refinement in correction form: r = 1 - A u, stop when
+            // ||r||/||f|| <= rtol, else e = V(0; r), u += e.
+            launch_fill_i32(st, c->d_active, h.Bc, 1);
+            launch_fill_i32(st, c->d_iters, h.Bc, 0);
+            R.active = c->d_active;
+            for (;;) {
+                launch_residual_norm(st, h.a[g], h.u[g], n, h.Bc, h.f[g], c->d_rho, c->d_active,
+                                     c->d_iters, c->cfg.rtol, c->cfg.max_iters, nullptr);
+                HIPCHK(c, hipMemcpyAsync(c->h_active, c->d_active, sizeof(int32_t) * h.Bc,
+                                         hipMemcpyDeviceToHost, st));
+                HIPCHK(c, hipStreamSynchronize(st));
+                int64_t nact = 0;
+                for (int64_t b = 0; b < h.Bc; ++b) nact += c->h_active[b];
+                if (nact == 0)
+                    break;
+                launch_fill(st, c->d_e, h.Bc * (int64_t)n * n, 0.0);
+                R.vcycle(g, c->d_e, h.f[g]);
+                launch_axpy_active(st, h.u[g], c->d_e, n, h.Bc, c->d_active);
+            }
+            R.active = nullptr;
+            HIPCHK(c, hipMemcpyAsync(c->h_iters, c->d_iters, sizeof(int32_t) * h.Bc,
+                                     hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipMemcpyAsync(c->h_rho, c->d_rho, sizeof(double) * h.Bc,
+                                     hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            if (stats) {
+                for (int64_t b = 0; b < h.Bc; ++b) {
+                    stats->max_iters = std::max(stats->max_iters, (int)c->h_iters[b]);
+                    stats->max_rho = std::max(stats->max_rho, c->h_rho[b]);
+                    if (c->h_rho[b] > c->cfg.rtol) stats->bad[b] = 1;
+                }
+            }
+        }
+        if (tr) tr->record();
+        if (!tr && g >= g0) {
+            ProfScope ps(c, st, MLMC_KERNEL_QOI, 8.0 * R.cells(n), 0.0);
+            launch_qoi(st, h.u[g], n, h.Bc, qoi, nlev, g - g0, c->cfg.qoi_mask);
+        }
+    }
+    if (stats)
+        for (uint8_t v : stats->bad) stats->noconv += v;
+    return MLMC_OK;
+}
+
+double fsum_pair(double a, double b) { return a + b; }
+
+// Neumaier summation on the host
+struct HostSum {
+    double s = 0.0, c = 0.0;
+    void add(double v)
+    {
+        double t = s + v;
+        if (std::fabs(s) >= std::fabs(v)) c += (s - t) + v; else c += (v - t) + s;
+        s = t;
+    }
+    double value() const { return s + c; }
+};
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char *mlmc_status_str(mlmc_status st)
+{
+    int i = -(int)st;
+    if (i < 0 || i > 5) return "unknown status";
+    return kStatusText[i];
+}
+
+const char *mlmc_last_error(mlmc_ctx ctx)
+{
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
+{
+    g_create_error.clear();
+    if (!out) { g_create_error = "out is NULL"; return MLMC_E_INVAL; }
+    *out = nullptr;
+    if (!cfg) { g_create_error = "cfg is NULL"; return MLMC_E_INVAL; }
+    const mlmc_config &c = *cfg;
+    auto bad = [](const char *m) { g_create_error = m; return MLMC_E_INVAL; };
+    int lg = ilog2_exact(c.n0);
+    if (c.n0 < 2 || lg < 0) return bad("n0 must be a power of two >= 2");
+    if (c.num_levels < 1) return bad("num_levels must be >= 1");
+    int g0 = lg - 1, Gmax = g0 + c.num_levels - 1;
+    if (Gmax >= kMaxMgLevels) return bad("finest grid beyond 4096 cells per side");
+    if (c.s < 1 || c.s > 4096) return bad("s must be in 1..4096");
+    if (!(c.corr_len > 0.0) || !std::isfinite(c.corr_len)) return bad("corr_len must be > 0");
+    if (!(c.sigma2 >= 0.0) || !std::isfinite(c.sigma2)) return bad("sigma2 must be >= 0");
+    if (c.mu1 < 0 || c.mu2 < 0 || c.mu1 + c.mu2 < 1) return bad("need mu1, mu2 >= 0 and mu1 + mu2 >= 1");
+    if (!(c.rtol >= 0.0) || !std::isfinite(c.rtol)) return bad("rtol must be >= 0");
+    if (c.rtol == 0.0 && c.mu0 < 1) return bad("mu0 must be >= 1 in fixed-cycle mode");
+    if (c.rtol > 0.0 && c.max_iters < 1) return bad("max_iters must be >= 1 when rtol > 0");
+    if (c.precision != MLMC_FP64 && c.precision != MLMC_MIXED) return bad("unknown precision");
+    if (c.precision == MLMC_MIXED) return bad("MLMC_MIXED is not available in this build");
+    if (c.qoi_mask == 0 || (c.qoi_mask & ~3u)) return bad("qoi_mask must be a non-empty subset of {MEAN, CENTER}");
+    if (c.max_batch < 1) return bad("max_batch must be >= 1");
+    bool lattice = c.genvec && c.shifts;
+    if (lattice && c.num_shifts < 1) return bad("num_shifts must be >= 1 with shifts");
+
+    mlmc_ctx ctx = new (std::nothrow) mlmc_ctx_s();
+    if (!ctx) { g_create_error = "host allocation failed"; return MLMC_E_NOMEM; }
+    ctx->cfg = c;
+    ctx->cfg.genvec = nullptr;
+    ctx->cfg.shifts = nullptr;
+    if (!lattice) ctx->cfg.num_shifts = std::max(ctx->cfg.num_shifts, 1);
+    ctx->device = device;
+    ctx->g0 = g0;
+    ctx->Gmax = Gmax;
+    ctx->nq = (c.qoi_mask & 1u ? 1 : 0) + (c.qoi_mask & 2u ? 1 : 0);
+    ctx->have_lattice = lattice;
+
+    auto fail = [&](mlmc_status s) {
+        g_create_error = ctx->err;
+        free_all(ctx);
+        delete ctx;
+        return s;
+    };
+#define CHK(call)                                                                    \
+    do {                                                                             \
+        hipError_t _e = (call);                                                      \
+        if (_e != hipSuccess) {                                                      \
+            ctx->err = std::string(#call) + ": " + hipGetErrorString(_e);            \
+            return fail(_e == hipErrorOutOfMemory ? MLMC_E_NOMEM : MLMC_E_HIP);      \
+        }                                                                            \
+    } while (0)
+
+    ctx->host_only = device < 0;
+    if (!ctx->host_only) CHK(hipSetDevice(device));
+
+    // KL mode table: the s largest products theta_i theta_j (i, j <= s),
+    // descending, exact ties ordered by i ascending.
+    const int s = c.s;
+    const double lam = c.corr_len;
+    std::vector<double> w(s), th(s);
+    for (int k = 1; k <= s; ++k) {
+        w[k - 1] = kl_root(lam, k);
+        th[k - 1] = kl_eigenvalue(lam, w[k - 1]);
+    }
+    struct Pair { double t; int32_t i, j; };
+    std::vector<Pair> pairs;
+    pairs.reserve((size_t)s * s);
+    for (int i = 1; i <= s; ++i)
+        for (int j = 1; j <= s; ++j) pairs.push_back({th[i - 1] * th[j - 1], i, j});
+    std::partial_sort(pairs.begin(), pairs.begin() + s, pairs.end(), [](const Pair &a, const Pair &b) {
+        if (a.t != b.t) return a.t > b.t;
+        if (a.i != b.i) return a.i < b.i;
+        return a.j < b.j;
+    });
+    ctx->mi.resize(s);
+    ctx->mj.resize(s);
+    ctx->theta2.resize(s);
+    int pmax = 1;
+    for (int m = 0; m < s; ++m) {
+        ctx->mi[m] = pairs[m].i;
+        ctx->mj[m] = pairs[m].j;
+        ctx->theta2[m] = pairs[m].t;
+        pmax = std::max(pmax, std::max(pairs[m].i, pairs[m].j));
+    }
+    std::vector<Pair>().swap(pairs);
+    const double sigma = std::sqrt(c.sigma2);
+    std::vector<double> coef(s);
+    for (int m = 0; m < s; ++m)
+        coef[m] = sigma * std::sqrt(th[ctx->mi[m] - 1]) * std::sqrt(th[ctx->mj[m] - 1]);
+    // 1-D eigenfunctions at the cell centres of every level
+    std::vector<int64_t> psi_off(Gmax + 2);
+    std::vector<double> psi;
+    for (int g = 0; g <= Gmax; ++g) {
+        int n = 2 << g;
+        psi_off[g] = (int64_t)psi.size();
+        for (int k = 0; k < pmax; ++k)
+            for (int cc = 0; cc < n; ++cc)
+                psi.push_back(kl_eigenfunction(lam, w[k], (cc + 0.5) / n));
+    }
+
+    ctx->Mmax = field_size_g(Gmax);
+    if (ctx->host_only) {
+        *out = ctx;
+        return MLMC_OK;
+    }
+    // workspace sizes
+    ctx->pool = c.max_batch * ctx->Mmax;
+    ctx->chunk_max = std::max<int64_t>(c.max_batch, 65536);
+    if (c.rtol > 0.0) ctx->ecap = c.max_batch * level_cells(Gmax);
+    int nshift_max = std::max(ctx->cfg.num_shifts, 1);
+    ctx->state_tuples = (int64_t)nshift_max * ctx->nq * c.num_levels;
+    size_t need = sizeof(double) * ((size_t)s * ctx->Mmax + 3 * (size_t)ctx->pool + ctx->ecap +
+                                    (size_t)ctx->chunk_max * (s + c.num_levels * ctx->nq + 1) +
+                                    4 * ctx->state_tuples) +
+                  sizeof(int32_t) * 2 * ctx->chunk_max;
+    size_t free_b = 0, total_b = 0;
+    CHK(hipMemGetInfo(&free_b, &total_b));
+    if (need > free_b) {
+        char msg[200];
+        snprintf(msg, sizeof msg, "workspace needs %.3g GB, %.3g GB free", need / 1e9, free_b / 1e9);
+        ctx->err = msg;
+        return fail(MLMC_E_NOMEM);
+    }
+    CHK(dev_alloc(ctx, &ctx->d_basis, (int64_t)s * ctx->Mmax));
+    CHK(dev_alloc(ctx, &ctx->d_a, ctx->pool));
+    CHK(dev_alloc(ctx, &ctx->d_u, ctx->pool));
+    CHK(dev_alloc(ctx, &ctx->d_f, ctx->pool));
+    CHK(dev_alloc(ctx, &ctx->d_e, ctx->ecap));
+    CHK(dev_alloc(ctx, &ctx->d_y, ctx->chunk_max * s));
+    CHK(dev_alloc(ctx, &ctx->d_qoi, ctx->chunk_max * c.num_levels * ctx->nq));
+    CHK(dev_alloc(ctx, &ctx->d_state, 4 * ctx->state_tuples));
+    CHK(dev_alloc(ctx, &ctx->d_rho, ctx->chunk_max));
+    CHK(dev_alloc(ctx, &ctx->d_active, ctx->chunk_max));
+    CHK(dev_alloc(ctx, &ctx->d_iters, ctx->chunk_max));
+    CHK(hipHostMalloc((void **)&ctx->h_active, sizeof(int32_t) * ctx->chunk_max, hipHostMallocDefault));
+    CHK(hipHostMalloc((void **)&ctx->h_iters, sizeof(int32_t) * ctx->chunk_max, hipHostMallocDefault));
+    CHK(hipHostMalloc((void **)&ctx->h_rho, sizeof(double) * ctx->chunk_max, hipHostMallocDefault));
+    if (lattice) {
+        CHK(dev_alloc(ctx, &ctx->d_z, s));
+        CHK(dev_alloc(ctx, &ctx->d_shifts, (int64_t)c.num_levels * c.num_shifts * s));
+        CHK(hipMemcpy(ctx->d_z, c.genvec, sizeof(uint32_t) * s, hipMemcpyHostToDevice));
+        CHK(hipMemcpy(ctx->d_shifts, c.shifts, sizeof(uint64_t) * (size_t)c.num_levels * c.num_shifts * s,
+                      hipMemcpyHostToDevice));
+    }
+    // build the dense basis on the device from the 1-D tables
+    double *d_psi = nullptr, *d_coef = nullptr;
+    int64_t *d_psi_off = nullptr;
+    int32_t *d_mi = nullptr, *d_mj = nullptr;
+    CHK(hipMalloc((void **)&d_psi, sizeof(double) * psi.size()));
+    ctx->allocs.push_back(d_psi);
+    CHK(hipMalloc((void **)&d_coef, sizeof(double) * s));
+    ctx->allocs.push_back(d_coef);
+    CHK(hipMalloc((void **)&d_psi_off, sizeof(int64_t) * psi_off.size()));
+    ctx->allocs.push_back(d_psi_off);
+    CHK(hipMalloc((void **)&d_mi, sizeof(int32_t) * s));
+    ctx->allocs.push_back(d_mi);
+    CHK(hipMalloc((void **)&d_mj, sizeof(int32_t) * s));
+    ctx->allocs.push_back(d_mj);
+    CHK(hipMemcpy(d_psi, psi.data(), sizeof(double) * psi.size(), hipMemcpyHostToDevice));
+    CHK(hipMemcpy(d_coef, coef.data(), sizeof(double) * s, hipMemcpyHostToDevice));
+    CHK(hipMemcpy(d_psi_off, psi_off.data(), sizeof(int64_t) * psi_off.size(), hipMemcpyHostToDevice));
+    CHK(hipMemcpy(d_mi, ctx->mi.data(), sizeof(int32_t) * s, hipMemcpyHostToDevice));
+    CHK(hipMemcpy(d_mj, ctx->mj.data(), sizeof(int32_t) * s, hipMemcpyHostToDevice));
+    launch_build_basis(nullptr, d_psi, d_psi_off, d_mi, d_mj, d_coef, s, Gmax, ctx->d_basis, ctx->Mmax);
+    CHK(hipGetLastError());
+    CHK(hipDeviceSynchronize());
+    // the 1-D tables are no longer needed
+    for (void *p : {(void *)d_psi, (void *)d_coef, (void *)d_psi_off, (void *)d_mi, (void *)d_mj}) {
+        (void)hipFree(p);
+        ctx->allocs.erase(std::find(ctx->allocs.begin(), ctx->allocs.end(), p));
+    }
+#undef CHK
+    *out = ctx;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_destroy(mlmc_ctx ctx)
+{
+    if (!ctx) return MLMC_OK;
+    if (!ctx->host_only) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+    }
+    free_all(ctx);
+    delete ctx;
+    return MLMC_OK;
+}
+
+int64_t mlmc_field_size(mlmc_ctx ctx, int32_t level)
+{
+    if (!ctx || level < 0 || level >= ctx->cfg.num_levels) return 0;
+    return field_size_g(ctx->g0 + level);
+}
+
+int32_t mlmc_num_qoi(mlmc_ctx ctx) { return ctx ? ctx->nq : 0; }
+
+mlmc_status mlmc_points_gen(mlmc_ctx ctx, const mlmc_points *pts, uint64_t *x_dev, double *y_dev,
+                            void *hip_stream)
+{
+    if (!ctx) return MLMC_E_INVAL;
+    if (ctx->broken || ctx->host_only) return MLMC_E_STATE;
+    int64_t B, npts;
+    int nsh;
+    mlmc_status st = check_points(ctx, pts, &B, &npts, &nsh);
+    if (st) return st;
+    if (x_dev && pts->kind != MLMC_POINTS_LATTICE) return inval(ctx, "x_dev only for lattice points");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (B == 0) return MLMC_OK;
+    if (pts->kind == MLMC_POINTS_EXPLICIT) {
+        if (y_dev)
+            HIPCHK(ctx, hipMemcpyAsync(y_dev, pts->y_dev, sizeof(double) * B * ctx->cfg.s,
+                                       hipMemcpyDeviceToDevice, s));
+        return MLMC_OK;
+    }
+    for (int64_t b0 = 0; b0 < B; b0 += ctx->chunk_max) {
+        int64_t Bc = std::min(ctx->chunk_max, B - b0);
+        launch_points(s, ctx->d_z, ctx->d_shifts, ctx->cfg.s, ctx->cfg.num_shifts, pts->level,
+                      pts->shift_begin, pts->n_begin, npts, b0, Bc,
+                      x_dev ? x_dev + b0 * ctx->cfg.s : nullptr,
+                      y_dev ? y_dev + b0 * ctx->cfg.s : ctx->d_y);
+    }
+    HIPCHK(ctx, hipGetLastError());
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_field(mlmc_ctx ctx, const mlmc_points *pts, double *z_dev, void *hip_stream)
+{
+    if (!ctx) return MLMC_E_INVAL;
+    if (ctx->broken || ctx->host_only) return MLMC_E_STATE;
+    int64_t B, npts;
+    int nsh;
+    mlmc_status st = check_points(ctx, pts, &B, &npts, &nsh);
+    if (st) return st;
+    if (!z_dev && B > 0) return inval(ctx, "z_dev is NULL");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t M = field_size_g(ctx->g0 + pts->level);
+    for (int64_t b0 = 0; b0 < B; b0 += ctx->chunk_max) {
+        int64_t Bc = std::min(ctx->chunk_max, B - b0);
+        const double *Y = chunk_y(ctx, s, pts, npts, b0, Bc, nullptr);
+        launch_field_gemm(s, Y, ctx->cfg.s, ctx->d_basis, ctx->Mmax, M, Bc, z_dev + b0 * M, 0);
+    }
+    HIPCHK(ctx, hipGetLastError());
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts, const double *z_dev,
+                           double *qoi_dev, double *sums_dev, mlmc_solve_info *info,
+                           void *hip_stream)
+{
+    if (!ctx) return MLMC_E_INVAL;
+    if (ctx->broken || ctx->host_only) return MLMC_E_STATE;
+    int64_t B, npts;
+    int nsh;
+    mlmc_status st = check_points(ctx, pts, &B, &npts, &nsh);
+    if (st) return st;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int k = pts->level, G = ctx->g0 + k, nlev = k + 1, nq = ctx->nq;
+    const int64_t M = field_size_g(G);
+    const int64_t cap = chunk_capacity(ctx, k);
+    const int64_t ntup = (int64_t)nsh * nq * nlev;
+    if (sums_dev) launch_fill(s, ctx->d_state, 4 * ntup, 0.0);
+    StageStats stats;
+    for (int64_t b0 = 0; b0 < B; b0 += cap) {
+        const int64_t Bc = std::min(cap, B - b0);
+        Hier h = make_hier(ctx, G, Bc);
+        if (z_dev) {
+            launch_exp_to_levels(s, z_dev + b0 * M, M, Bc, ctx->d_a);
+        } else {
+            const double *Y;
+            {
+                ProfScope ps(ctx, s, MLMC_KERNEL_POINTS, 16.0 * Bc * ctx->cfg.s, 0.0);
+                Y = chunk_y(ctx, s, pts, npts, b0, Bc, nullptr);
+            }
+            const double sd = ctx->cfg.s;
+            ProfScope ps(ctx, s, MLMC_KERNEL_FIELD, 8.0 * (Bc * sd + sd * M + (double)Bc * M),
+                         2.0 * Bc * sd * M);
+            launch_field_gemm(s, Y, ctx->cfg.s, ctx->d_basis, ctx->Mmax, M, Bc, ctx->d_a, 1);
+        }
+        double *q = qoi_dev ? qoi_dev + b0 * nlev * nq : ctx->d_qoi;
+        st = run_fmg(ctx, s, h, k, q, nullptr, &stats);
+        if (st) return st;
+        if (sums_dev) {
+            ProfScope ps(ctx, s, MLMC_KERNEL_SUMS, 8.0 * Bc * nlev * nq, 0.0);
+            launch_sums(s, q, nlev, nq, b0, Bc, npts, nsh, ctx->d_state);
+        }
+    }
+    if (sums_dev) launch_sums_final(s, ctx->d_state, ntup, sums_dev);
+    HIPCHK(ctx, hipGetLastError());
+    if (info) {
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        info->samples = B;
+        info->max_iters_used = stats.max_iters;
+        info->max_rel_residual = ctx->cfg.rtol > 0.0 ? stats.max_rho : -1.0;
+        info->not_converged = stats.noconv;
+        if (stats.noconv > 0) {
+            ctx->err = "refinement reached max_iters before rtol";
+            return MLMC_E_NOCONV;
+        }
+    }
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_kl_modes(mlmc_ctx ctx, int32_t *i_out, int32_t *j_out, double *theta_out)
+{
+    if (!ctx) return MLMC_E_INVAL;
+    const int s = ctx->cfg.s;
+    if (i_out) std::memcpy(i_out, ctx->mi.data(), sizeof(int32_t) * s);
+    if (j_out) std::memcpy(j_out, ctx->mj.data(), sizeof(int32_t) * s);
+    if (theta_out) std::memcpy(theta_out, ctx->theta2.data(), sizeof(double) * s);
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_fmg_trace(mlmc_ctx ctx, int32_t level, int32_t *levels, int32_t *marks,
+                           int64_t cap, int64_t *len)
+{
+    if (!ctx) return MLMC_E_INVAL;
+    if (level < 0 || level >= ctx->cfg.num_levels) return inval(ctx, "level out of range");
+    if (ctx->cfg.rtol > 0.0) return inval(ctx, "trace is data dependent in rtol mode");
+    if (cap < 0 || (cap > 0 && (!levels || !marks))) return inval(ctx, "bad trace buffers");
+    Trace tr;
+    Hier h;
+    h.G = ctx->g0 + level;
+    run_fmg(ctx, nullptr, h, level, nullptr, &tr, nullptr);
+    int64_t n = (int64_t)tr.lev.size();
+    for (int64_t i = 0; i < std::min(n, cap); ++i) {
+        levels[i] = tr.lev[i];
+        marks[i] = tr.mark[i];
+    }
+    if (len) *len = n;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_profile_begin(mlmc_ctx ctx, int32_t kernel_kind)
+{
+    if (!ctx) return MLMC_E_INVAL;
+    if (ctx->host_only) return MLMC_E_STATE;
+    if (kernel_kind < MLMC_KERNEL_POINTS || kernel_kind > MLMC_KERNEL_SUMS)
+        return inval(ctx, "unknown kernel kind");
+    ctx->prof.kind = kernel_kind;
+    ctx->prof.used = 0;
+    ctx->prof.launches = 0;
+    ctx->prof.bytes = ctx->prof.flops = 0.0;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_profile_end(mlmc_ctx ctx, mlmc_profile_result *out)
+{
+    if (!ctx || !out) return MLMC_E_INVAL;
+    if (ctx->host_only) return MLMC_E_STATE;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipDeviceSynchronize());
+    double ms_total = 0.0;
+    for (size_t i = 0; i < ctx->prof.used; ++i) {
+        float ms = 0.0f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->prof.ev[2 * i], ctx->prof.ev[2 * i + 1]));
+        ms_total += ms;
+    }
+    out->launches = ctx->prof.launches;
+    out->total_ms = ms_total;
+    out->bytes = ctx->prof.bytes;
+    out->flops = ctx->prof.flops;
+    ctx->prof.kind = -1;
+    ctx->prof.used = 0;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_estimate(const mlmc_est_input *in, mlmc_est_output *out)
+{
+    if (!in || !out || !in->n_per_level || !in->sums) return MLMC_E_INVAL;
+    const int L1 = in->num_levels, R = in->num_shifts, nq = in->nq;
+    if (L1 < 1 || R < 1 || nq < 1 || nq > 2) return MLMC_E_INVAL;
+    for (int k = 0; k < L1; ++k)
+        if (in->n_per_level[k] < 0) return MLMC_E_INVAL;
+    if (!out->upsilon || !out->upsilon_bar || !out->var_level || !out->q_shift || !out->q_bar ||
+        !out->var_q)
+        return MLMC_E_INVAL;
+    const bool reuse = in->reuse != 0;
+    const double nan = std::nan("");
+    // sums[k][r][q][l][2]
+    auto S = [&](int k, int r, int q, int l, int w) {
+        return in->sums[((((int64_t)k * R + r) * nq + q) * L1 + l) * 2 + w];
+    };
+    for (int q = 0; q < nq; ++q) {
+        double *ups = out->upsilon + (int64_t)q * L1 * R;
+        for (int l = 0; l < L1; ++l) {
+            int64_t den = 0;
+            for (int k = (reuse ? l : l); k <= (reuse ? L1 - 1 : l); ++k) den += in->n_per_level[k];
+            for (int r = 0; r < R; ++r) {
+                HostSum num;
+                for (int k = l; k <= (reuse ? L1 - 1 : l); ++k) num.add(S(k, r, q, l, 0));
+                ups[(int64_t)l * R + r] = den > 0 ? num.value() / (double)den : 0.0;
+            }
+        }
+        double *qs = out->q_shift + (int64_t)q * R;
+        for (int r = 0; r < R; ++r) {
+            HostSum t;
+            for (int l = 0; l < L1; ++l) t.add(ups[(int64_t)l * R + r]);
+            qs[r] = t.value();
+        }
+        HostSum qb;
+        for (int r = 0; r < R; ++r) qb.add(qs[r]);
+        out->q_bar[q] = qb.value() / R;
+        for (int l = 0; l < L1; ++l) {
+            HostSum ub;
+            for (int r = 0; r < R; ++r) ub.add(ups[(int64_t)l * R + r]);
+            out->upsilon_bar[(int64_t)q * L1 + l] = ub.value() / R;
+        }
+        if (R >= 2) {
+            HostSum v;
+            for (int r = 0; r < R; ++r) {
+                double d = qs[r] - out->q_bar[q];
+                v.add(d * d);
+            }
+            out->var_q[q] = v.value() / ((double)R * (R - 1));
+            for (int l = 0; l < L1; ++l) {
+                HostSum vl;
+                double m = out->upsilon_bar[(int64_t)q * L1 + l];
+                for (int r = 0; r < R; ++r) {
+                    double d = ups[(int64_t)l * R + r] - m;
+                    vl.add(d * d);
+                }
+                out->var_level[(int64_t)q * L1 + l] = vl.value() / ((double)R * (R - 1));
+            }
+        } else if (!reuse) {
+            // eq. vardecomp: V = sum_l s_l^2 / N_l from sum dF and sum dF^2
+            HostSum v;
+            for (int l = 0; l < L1; ++l) {
+                int64_t N = in->n_per_level[l];
+                double vl = nan;
+                if (N > 1) {
+                    double s1 = S(l, 0, q, l, 0), s2 = S(l, 0, q, l, 1);
+                    double var = (s2 - s1 * s1 / (double)N) / (double)(N - 1);
+                    vl = var / (double)N;
+                }
+                out->var_level[(int64_t)q * L1 + l] = vl;
+                v.add(vl);
+            }
+            out->var_q[q] = v.value();
+        } else {
+            for (int l = 0; l < L1; ++l) out->var_level[(int64_t)q * L1 + l] = nan;
+            out->var_q[q] = nan;
+        }
+    }
+    return MLMC_OK;
+}
+
+}  // extern "C"

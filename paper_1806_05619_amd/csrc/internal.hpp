@@ -1,0 +1,68 @@
+// Internal declarations of the MI355X MG-MLQMC library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mlmc.h"
+
+namespace mlmc {
+
+constexpr int kMaxMgLevels = 12;   // n_g = 2^(g+1) <= 4096
+constexpr int kBlock = 256;
+
+// Offset (in cells) of multigrid level g inside a level-major per-sample
+// field: sum_{g' < g} 4^(g'+1) = 4 (4^g - 1) / 3.
+__host__ __device__ inline int64_t level_offset(int g) { return 4 * (((int64_t)1 << (2 * g)) - 1) / 3; }
+__host__ __device__ inline int64_t level_cells(int g) { return (int64_t)4 << (2 * g); }
+
+// Views of one chunk's multigrid hierarchy in the workspace pools.  Level g
+// holds Bc samples back to back: sample b, cell p at base_g + b*n_g^2 + p.
+struct Hier {
+    int G = 0;            // finest multigrid level of the chunk
+    int64_t Bc = 0;       // samples in the chunk
+    double *a[kMaxMgLevels] = {};
+    double *u[kMaxMgLevels] = {};
+    double *f[kMaxMgLevels] = {};
+};
+
+// ---- kernel launchers (kernels.hip) ----
+void launch_points(hipStream_t st, const uint32_t *z, const uint64_t *shifts, int s, int R,
+                   int level, int shift_begin, int64_t n_begin, int64_t npts, int64_t b0,
+                   int64_t Bc, uint64_t *x_out, double *y_out);
+void launch_build_basis(hipStream_t st, const double *psi, const int64_t *psi_off,
+                        const int32_t *mi, const int32_t *mj, const double *coef, int s,
+                        int G, double *basis, int64_t ld);
+// z = Y basis (first M columns); mode 0 writes z to out[b*M + m];
+// mode 1 writes exp(z) into the level-major chunk pool `out` (Bc samples).
+void launch_field_gemm(hipStream_t st, const double *Y, int s, const double *basis, int64_t ld,
+                       int64_t M, int64_t Bc, double *out, int mode);
+void launch_exp_to_levels(hipStream_t st, const double *z, int64_t M, int64_t Bc, double *pool);
+
+void launch_coarse_solve(hipStream_t st, const double *a, const double *f, double *u, int64_t Bc,
+                         const int32_t *active);
+void launch_rbgs(hipStream_t st, const double *a, const double *f, double *u, int n, int64_t Bc,
+                 int colour, const int32_t *active);
+void launch_resid_restrict(hipStream_t st, const double *a, const double *f, const double *u,
+                           int n, int64_t Bc, double *fc, double *uc, const int32_t *active);
+void launch_prolong(hipStream_t st, const double *ec, double *u, int n, int64_t Bc, int add,
+                    const int32_t *active);
+void launch_qoi(hipStream_t st, const double *u, int n, int64_t Bc, double *qoi, int nlev,
+                int l, uint32_t mask);
+void launch_fill(hipStream_t st, double *p, int64_t count, double v);
+void launch_fill_i32(hipStream_t st, int32_t *p, int64_t count, int32_t v);
+void launch_sums(hipStream_t st, const double *qoi, int nlev, int nq, int64_t b0, int64_t Bc,
+                 int64_t npts, int nshift, double *state);
+void launch_sums_final(hipStream_t st, const double *state, int64_t count, double *out);
+// rtol refinement (FP64): r = 1 - A u on level n, rho_b = ||r||/||1||; then
+// active_b = rho_b > rtol && iters_b < max_iters (iters_b counted here).
+void launch_residual_norm(hipStream_t st, const double *a, const double *u, int n, int64_t Bc,
+                          double *r, double *rho, int32_t *active, int32_t *iters, double rtol,
+                          int max_iters, int32_t *n_active);
+void launch_axpy_active(hipStream_t st, double *u, const double *e, int n, int64_t Bc,
+                        const int32_t *active);
+
+}  // namespace mlmc

@@ -1,0 +1,616 @@
+// Device kernels of the MG-MLQMC sample path for gfx950.
+//
+// Sampler (Section 3.2), KL field (Section 5, eq. truncatedKL), the multigrid
+// components of the correction scheme and full multigrid (Section 4), QoI
+// read-off of every FMG stage and the level-difference sums that feed the
+// recycling estimator (Section 3.2, eq. Upsilon-reuse).
+//
+// Layout: a chunk of Bc samples stores multigrid level g as Bc contiguous
+// n_g x n_g grids (cell (i,j) at i + n*j).  Every kernel bounds-checks its
+// flat thread index against the element count it was launched for.
+#include "internal.hpp"
+
+namespace mlmc {
+namespace {
+
+inline unsigned blocks_for(int64_t n, int per_block = kBlock)
+{
+    int64_t b = (n + per_block - 1) / per_block;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+__device__ __forceinline__ double harmonic(double ap, double an)
+{
+    return 2.0 * ap * an / (ap + an);
+}
+
+// Neumaier/TwoSum helpers for deterministic compensated reductions.
+struct Comp {
+    double s, c;
+};
+__device__ __forceinline__ void comp_add(Comp &k, double v)
+{
+    double t = k.s + v;
+    if (fabs(k.s) >= fabs(v))
+        k.c += (k.s - t) + v;
+    else
+        k.c += (v - t) + k.s;
+    k.s = t;
+}
+__device__ __forceinline__ Comp comp_merge(Comp x, Comp y)
+{
+    double s = x.s + y.s;
+    double bb = s - x.s;
+    double err = (x.s - (s - bb)) + (y.s - bb);
+    return Comp{s, x.c + y.c + err};
+}
+// Butterfly over the 64 lanes of a wavefront (fixed order: deterministic).
+__device__ __forceinline__ Comp wave_reduce(Comp k)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        Comp o{__shfl_xor(k.s, m, 64), __shfl_xor(k.c, m, 64)};
+        k = comp_merge(k, o);
+    }
+    return k;
+}
+
+// ---------------------------------------------------------------------------
+// Phi^-1(u): the device library's normcdfinv, then one Newton step on
+// Phi(y) = u whose residual is formed without cancellation (u - 1/2 and 1 - u
+// are exact for the u this path produces).
+__device__ __forceinline__ double inverse_normal(double u)
+{
+    double y = normcdfinv(u);
+    const double r2 = 0.70710678118654752440;    // 1/sqrt(2)
+    double g;
+    if (u < 0.25)
+        g = 0.5 * erfc(-y * r2) - u;
+    else if (u <= 0.75)
+        g = 0.5 * erf(y * r2) - (u - 0.5);
+    else
+        g = (1.0 - u) - 0.5 * erfc(y * r2);
+    double pdf = 0.39894228040143267794 * exp(-0.5 * y * y);   // 1/sqrt(2 pi)
+    return y - g / pdf;
+}
+
+// Section 3.2: shifted lattice sequence point -> (0,1) -> inverse normal.
+__global__ void k_points(const uint32_t *__restrict__ z, const uint64_t *__restrict__ shifts,
+                         int s, int R, int level, int shift_begin, int64_t n_begin,
+                         int64_t npts, int64_t b0, int64_t Bc, uint64_t *__restrict__ x_out,
+                         double *__restrict__ y_out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Bc * s)
+        return;
+    int64_t bl = t / s;
+    int j = (int)(t - bl * s);
+    int64_t b = b0 + bl;
+    int64_t rl = b / npts;
+    int64_t n = n_begin + (b - rl * npts);
+    int r = shift_begin + (int)rl;
+    uint32_t rn = __brev((uint32_t)n);           // radical inverse in base 2
+    uint32_t k = rn * z[j];                      // {rev(n) z_j / 2^32}
+    uint64_t x = ((uint64_t)k << 32) + shifts[((int64_t)level * R + r) * s + j];
+    if (x_out)
+        x_out[t] = x;
+    double u = (2.0 * (double)(x >> 12) + 1.0) * 0x1p-53;
+    y_out[t] = inverse_normal(u);
+}
+
+// ---------------------------------------------------------------------------
+// KL basis: basis[m][col] = coef_m psi_{i_m}(x1) psi_{j_m}(x2) at the cell
+// centres of every level; psi tabulated per level: psi[psi_off[g] + k*n_g + c].
+__global__ void k_build_basis(const double *__restrict__ psi, const int64_t *__restrict__ psi_off,
+                              const int32_t *__restrict__ mi, const int32_t *__restrict__ mj,
+                              const double *__restrict__ coef, int s, int G, int64_t M,
+                              double *__restrict__ basis, int64_t ld)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M * s)
+        return;
+    int m = (int)(t / M);
+    int64_t col = t - (int64_t)m * M;
+    int g = 0;
+    while (g < G && level_offset(g + 1) <= col)
+        ++g;
+    int n = 2 << g;
+    int64_t p = col - level_offset(g);
+    int i = (int)(p % n), j = (int)(p / n);
+    const double *pg = psi + psi_off[g];
+    basis[(int64_t)m * ld + col] =
+        coef[m] * pg[(int64_t)(mi[m] - 1) * n + i] * pg[(int64_t)(mj[m] - 1) * n + j];
+}
+
+// ---------------------------------------------------------------------------
+// Section 5: z = Y basis as a tiled FP64 product.  Tile 64 samples x 64 columns,
+// K step 16, 256 threads each owning a 4x4 strided sub-tile (coalesced stores).
+constexpr int GM = 64, GN = 64, GK = 16;
+
+__device__ __forceinline__ int64_t level_major_index(int64_t m, int64_t b, int64_t Bc)
+{
+    int g = 0;
+    while (g < kMaxMgLevels - 1 && level_offset(g + 1) <= m)
+        ++g;
+    int64_t lo = level_offset(g);
+    return Bc * lo + b * level_cells(g) + (m - lo);
+}
+
+__global__ __launch_bounds__(256) void k_field_gemm(const double *__restrict__ Y, int s,
+                                                    const double *__restrict__ basis, int64_t ld,
+                                                    int64_t M, int64_t Bc,
+                                                    double *__restrict__ out, int mode)
+{
+    __shared__ double As[GK][GM + 1];
+    __shared__ double Bs[GK][GN];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int64_t row0 = (int64_t)blockIdx.y * GM;
+    const int64_t col0 = (int64_t)blockIdx.x * GN;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < s; k0 += GK) {
+        for (int e = threadIdx.x; e < GM * GK; e += 256) {
+            int r = e / GK, kk = e % GK;
+            int64_t gr = row0 + r;
+            int gk = k0 + kk;
+            As[kk][r] = (gr < Bc && gk < s) ? Y[gr * s + gk] : 0.0;
+        }
+        for (int e = threadIdx.x; e < GK * GN; e += 256) {
+            int kk = e / GN, c = e % GN;
+            int64_t gc = col0 + c;
+            int gk = k0 + kk;
+            Bs[kk][c] = (gc < M && gk < s) ? basis[(int64_t)gk * ld + gc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GK; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = As[kk][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int64_t b = row0 + ty + 16 * i;
+        if (b >= Bc)
+            continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int64_t m = col0 + tx + 16 * j;
+            if (m >= M)
+                continue;
+            if (mode == 0)
+                out[b * M + m] = acc[i][j];
+            else
+                out[level_major_index(m, b, Bc)] = exp(acc[i][j]);
+        }
+    }
+}
+
+__global__ void k_exp_to_levels(const double *__restrict__ z, int64_t M, int64_t Bc,
+                                double *__restrict__ pool)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M * Bc)
+        return;
+    int64_t b = t / M, m = t - b * M;
+    pool[level_major_index(m, b, Bc)] = exp(z[t]);
+}
+
+// ---------------------------------------------------------------------------
+// Section 4: exact solve on the 2x2 coarsest grid (h^2 = 1/4), one sample per
+// thread, dense 4x4 Cholesky.  Cells 0:(0,0) 1:(1,0) 2:(0,1) 3:(1,1).
+__global__ void k_coarse_solve(const double *__restrict__ a, const double *__restrict__ f,
+                               double *__restrict__ u, int64_t Bc,
+                               const int32_t *__restrict__ active)
+{
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= Bc)
+        return;
+    if (active && !active[b])
+        return;
+    const double *ab = a + 4 * b;
+    double w01 = harmonic(ab[0], ab[1]), w02 = harmonic(ab[0], ab[2]);
+    double w13 = harmonic(ab[1], ab[3]), w23 = harmonic(ab[2], ab[3]);
+    double A[4][4] = {{w01 + w02 + 4.0 * ab[0], -w01, -w02, 0.0},
+                      {-w01, w01 + w13 + 4.0 * ab[1], 0.0, -w13},
+                      {-w02, 0.0, w02 + w23 + 4.0 * ab[2], -w23},
+                      {0.0, -w13, -w23, w13 + w23 + 4.0 * ab[3]}};
+    double rhs[4];
+    for (int p = 0; p < 4; ++p) rhs[p] = 0.25 * (f ? f[4 * b + p] : 1.0);
+    double L[4][4] = {};
+    for (int p = 0; p < 4; ++p)
+        for (int q = 0; q <= p; ++q) {
+            double sum = A[p][q];
+            for (int t = 0; t < q; ++t) sum -= L[p][t] * L[q][t];
+            L[p][q] = (p == q) ? sqrt(sum) : sum / L[q][q];
+        }
+    double v[4];
+    for (int p = 0; p < 4; ++p) {
+        double sum = rhs[p];
+        for (int q = 0; q < p; ++q) sum -= L[p][q] * v[q];
+        v[p] = sum / L[p][p];
+    }
+    for (int p = 3; p >= 0; --p) {
+        double sum = v[p];
+        for (int q = p + 1; q < 4; ++q) sum -= L[q][p] * v[q];
+        v[p] = sum / L[p][p];
+    }
+    for (int p = 0; p < 4; ++p) u[4 * b + p] = v[p];
+}
+
+// One colour of red-black Gauss-Seidel: u_P = (h^2 f_P + sum w u_nbr) / sum w.
+// f == nullptr means f = 1.  One thread per cell of the colour.
+__global__ void k_rbgs(const double *__restrict__ a, const double *__restrict__ f,
+                       double *__restrict__ u, int n, int64_t Bc, int colour,
+                       const int32_t *__restrict__ active)
+{
+    const int half = n / 2;
+    const int64_t per = (int64_t)n * half;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Bc * per)
+        return;
+    int64_t b = t / per;
+    if (active && !active[b])
+        return;
+    int rem = (int)(t - b * per);
+    int j = rem / half;
+    int i = 2 * (rem - j * half) + ((j + colour) & 1);
+    const int64_t base = b * n * n;
+    const double *ab = a + base;
+    double *ub = u + base;
+    const int p = i + n * j;
+    const double ap = ab[p];
+    const double h2 = 1.0 / ((double)n * (double)n);
+    double num = h2 * (f ? f[base + p] : 1.0);
+    double d = 0.0, w;
+    if (i + 1 < n) { w = harmonic(ap, ab[p + 1]); d += w; num += w * ub[p + 1]; } else d += 2.0 * ap;
+    if (i > 0)     { w = harmonic(ap, ab[p - 1]); d += w; num += w * ub[p - 1]; } else d += 2.0 * ap;
+    if (j + 1 < n) { w = harmonic(ap, ab[p + n]); d += w; num += w * ub[p + n]; } else d += 2.0 * ap;
+    if (j > 0)     { w = harmonic(ap, ab[p - n]); d += w; num += w * ub[p - n]; } else d += 2.0 * ap;
+    ub[p] = num / d;
+}
+
+__device__ __forceinline__ double residual_at(const double *ab, const double *fb,
+                                              const double *ub, int n, int i, int j,
+                                              double inv_h2)
+{
+    const int p = i + n * j;
+    const double ap = ab[p];
+    double d = 0.0, off = 0.0, w;
+    if (i + 1 < n) { w = harmonic(ap, ab[p + 1]); d += w; off += w * ub[p + 1]; } else d += 2.0 * ap;
+    if (i > 0)     { w = harmonic(ap, ab[p - 1]); d += w; off += w * ub[p - 1]; } else d += 2.0 * ap;
+    if (j + 1 < n) { w = harmonic(ap, ab[p + n]); d += w; off += w * ub[p + n]; } else d += 2.0 * ap;
+    if (j > 0)     { w = harmonic(ap, ab[p - n]); d += w; off += w * ub[p - n]; } else d += 2.0 * ap;
+    return (fb ? fb[p] : 1.0) - inv_h2 * (d * ub[p] - off);
+}
+
+// r = f - A u on the fine grid, restricted by the 4-cell mean to fc; the
+// coarse iterate uc is cleared (zero initial guess).  One thread per coarse cell.
+__global__ void k_resid_restrict(const double *__restrict__ a, const double *__restrict__ f,
+                                 const double *__restrict__ u, int n, int64_t Bc,
+                                 double *__restrict__ fc, double *__restrict__ uc,
+                                 const int32_t *__restrict__ active)
+{
+    const int nc = n / 2;
+    const int64_t per = (int64_t)nc * nc;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Bc * per)
+        return;
+    int64_t b = t / per;
+    if (active && !active[b])
+        return;
+    int pc = (int)(t - b * per);
+    int J = pc / nc, I = pc - J * nc;
+    const int64_t base = b * n * n;
+    const double *fb = f ? f + base : nullptr;
+    const double inv_h2 = (double)n * (double)n;
+    double r00 = residual_at(a + base, fb, u + base, n, 2 * I, 2 * J, inv_h2);
+    double r10 = residual_at(a + base, fb, u + base, n, 2 * I + 1, 2 * J, inv_h2);
+    double r01 = residual_at(a + base, fb, u + base, n, 2 * I, 2 * J + 1, inv_h2);
+    double r11 = residual_at(a + base, fb, u + base, n, 2 * I + 1, 2 * J + 1, inv_h2);
+    fc[t] = 0.25 * (r00 + r10 + r01 + r11);
+    uc[t] = 0.0;
+}
+
+__device__ __forceinline__ double coarse_odd(const double *e, int nc, int I, int J)
+{
+    double sg = 1.0;
+    if (I < 0) { I = 0; sg = -sg; }
+    if (I >= nc) { I = nc - 1; sg = -sg; }
+    if (J < 0) { J = 0; sg = -sg; }
+    if (J >= nc) { J = nc - 1; sg = -sg; }
+    return sg * e[I + nc * J];
+}
+
+// Bilinear (9,3,3,1)/16 prolongation with odd reflection at the walls:
+// u = P ec (add == 0, FMG interpolation) or u += P ec (coarse-grid correction).
+__global__ void k_prolong(const double *__restrict__ ec, double *__restrict__ u, int n,
+                          int64_t Bc, int add, const int32_t *__restrict__ active)
+{
+    const int64_t per = (int64_t)n * n;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Bc * per)
+        return;
+    int64_t b = t / per;
+    if (active && !active[b])
+        return;
+    int p = (int)(t - b * per);
+    int j = p / n, i = p - j * n;
+    const int nc = n / 2;
+    const double *eb = ec + b * nc * nc;
+    int I = i / 2, J = j / 2;
+    int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1;
+    double v = (9.0 * coarse_odd(eb, nc, I, J) + 3.0 * coarse_odd(eb, nc, I + sx, J) +
+                3.0 * coarse_odd(eb, nc, I, J + sy) + coarse_odd(eb, nc, I + sx, J + sy)) /
+               16.0;
+    if (add)
+        u[t] += v;
+    else
+        u[t] = v;
+}
+
+// QoI of one level, one wavefront per sample: mean (compensated) and centre.
+__global__ __launch_bounds__(256) void k_qoi(const double *__restrict__ u, int n, int64_t Bc,
+                                             double *__restrict__ qoi, int nlev, int l,
+                                             uint32_t mask)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    if (b >= Bc)
+        return;
+    const int64_t cells = (int64_t)n * n;
+    const double *ub = u + b * cells;
+    Comp k{0.0, 0.0};
+    for (int64_t p = lane; p < cells; p += 64)
+        comp_add(k, ub[p]);
+    k = wave_reduce(k);
+    if (lane == 0) {
+        const int nq = (mask & 1u ? 1 : 0) + (mask & 2u ? 1 : 0);
+        double *qb = qoi + (b * nlev + l) * nq;
+        int q = 0;
+        if (mask & 1u)
+            qb[q++] = (k.s + k.c) / (double)cells;
+        if (mask & 2u) {
+            int c = n / 2;
+            qb[q] = 0.25 * (ub[(c - 1) + n * (c - 1)] + ub[c + n * (c - 1)] +
+                            ub[(c - 1) + n * c] + ub[c + n * c]);
+        }
+    }
+}
+
+__global__ void k_fill(double *p, int64_t count, double v)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count)
+        p[t] = v;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t count, int32_t v)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count)
+        p[t] = v;
+}
+
+// Level-difference sums for the estimator: one wavefront per (shift, q, l)
+// accumulates sum dF and sum dF^2 over the chunk's samples of that shift into
+// the compensated state [tuple][4] = (s1, c1, s2, c2).
+__global__ __launch_bounds__(256) void k_sums(const double *__restrict__ qoi, int nlev, int nq,
+                                              int64_t b0, int64_t Bc, int64_t npts, int nshift,
+                                              double *__restrict__ state)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t tuple = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const int64_t ntup = (int64_t)nshift * nq * nlev;
+    if (tuple >= ntup)
+        return;
+    const int l = (int)(tuple % nlev);
+    const int q = (int)((tuple / nlev) % nq);
+    const int rl = (int)(tuple / ((int64_t)nlev * nq));
+    int64_t lo = (int64_t)rl * npts, hi = lo + npts;   // global sample range of this shift
+    if (lo < b0) lo = b0;
+    if (hi > b0 + Bc) hi = b0 + Bc;
+    Comp k1{0.0, 0.0}, k2{0.0, 0.0};
+    for (int64_t b = lo + lane; b < hi; b += 64) {
+        const double *qb = qoi + (b - b0) * nlev * nq;
+        double d = qb[l * nq + q] - (l > 0 ? qb[(l - 1) * nq + q] : 0.0);
+        comp_add(k1, d);
+        comp_add(k2, d * d);
+    }
+    k1 = wave_reduce(k1);
+    k2 = wave_reduce(k2);
+    if (lane == 0) {
+        double *st = state + tuple * 4;
+        Comp a1 = comp_merge(Comp{st[0], st[1]}, k1);
+        Comp a2 = comp_merge(Comp{st[2], st[3]}, k2);
+        st[0] = a1.s;
+        st[1] = a1.c;
+        st[2] = a2.s;
+        st[3] = a2.c;
+    }
+}
+
+__global__ void k_sums_final(const double *__restrict__ state, int64_t count,
+                             double *__restrict__ out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count)
+        return;
+    out[2 * t] = state[4 * t] + state[4 * t + 1];
+    out[2 * t + 1] = state[4 * t + 2] + state[4 * t + 3];
+}
+
+// FP64 residual of the top level (f = 1) with per-sample relative norm and
+// the convergence flags of the refinement loop.  One wavefront per sample.
+__global__ __launch_bounds__(256) void k_residual_norm(const double *__restrict__ a,
+                                                       const double *__restrict__ u, int n,
+                                                       int64_t Bc, double *__restrict__ r,
+                                                       double *__restrict__ rho,
+                                                       int32_t *__restrict__ active,
+                                                       int32_t *__restrict__ iters, double rtol,
+                                                       int max_iters)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    if (b >= Bc)
+        return;
+    if (!active[b])
+        return;
+    const int64_t cells = (int64_t)n * n;
+    const int64_t base = b * cells;
+    const double inv_h2 = (double)n * (double)n;
+    Comp k{0.0, 0.0};
+    for (int64_t p = lane; p < cells; p += 64) {
+        int j = (int)(p / n), i = (int)(p - (int64_t)j * n);
+        double rv = residual_at(a + base, nullptr, u + base, n, i, j, inv_h2);
+        r[base + p] = rv;
+        comp_add(k, rv * rv);
+    }
+    k = wave_reduce(k);
+    if (lane == 0) {
+        double v = sqrt(k.s + k.c) / (double)n;   // ||f||_2 = n for f = 1
+        rho[b] = v;
+        int it = iters[b];
+        int go = (v > rtol) && (it < max_iters);
+        active[b] = go;
+        if (go)
+            iters[b] = it + 1;
+    }
+}
+
+__global__ void k_axpy_active(double *__restrict__ u, const double *__restrict__ e, int n,
+                              int64_t Bc, const int32_t *__restrict__ active)
+{
+    const int64_t per = (int64_t)n * n;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Bc * per)
+        return;
+    if (!active[t / per])
+        return;
+    u[t] += e[t];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+void launch_points(hipStream_t st, const uint32_t *z, const uint64_t *shifts, int s, int R,
+                   int level, int shift_begin, int64_t n_begin, int64_t npts, int64_t b0,
+                   int64_t Bc, uint64_t *x_out, double *y_out)
+{
+    hipLaunchKernelGGL(k_points, dim3(blocks_for(Bc * s)), dim3(kBlock), 0, st, z, shifts, s, R,
+                       level, shift_begin, n_begin, npts, b0, Bc, x_out, y_out);
+}
+
+void launch_build_basis(hipStream_t st, const double *psi, const int64_t *psi_off,
+                        const int32_t *mi, const int32_t *mj, const double *coef, int s, int G,
+                        double *basis, int64_t ld)
+{
+    int64_t M = level_offset(G + 1);
+    hipLaunchKernelGGL(k_build_basis, dim3(blocks_for(M * s)), dim3(kBlock), 0, st, psi, psi_off,
+                       mi, mj, coef, s, G, M, basis, ld);
+}
+
+void launch_field_gemm(hipStream_t st, const double *Y, int s, const double *basis, int64_t ld,
+                       int64_t M, int64_t Bc, double *out, int mode)
+{
+    dim3 grid((unsigned)((M + GN - 1) / GN), (unsigned)((Bc + GM - 1) / GM));
+    hipLaunchKernelGGL(k_field_gemm, grid, dim3(256), 0, st, Y, s, basis, ld, M, Bc, out, mode);
+}
+
+void launch_exp_to_levels(hipStream_t st, const double *z, int64_t M, int64_t Bc, double *pool)
+{
+    hipLaunchKernelGGL(k_exp_to_levels, dim3(blocks_for(M * Bc)), dim3(kBlock), 0, st, z, M, Bc,
+                       pool);
+}
+
+void launch_coarse_solve(hipStream_t st, const double *a, const double *f, double *u, int64_t Bc,
+                         const int32_t *active)
+{
+    hipLaunchKernelGGL(k_coarse_solve, dim3(blocks_for(Bc)), dim3(kBlock), 0, st, a, f, u, Bc,
+                       active);
+}
+
+void launch_rbgs(hipStream_t st, const double *a, const double *f, double *u, int n, int64_t Bc,
+                 int colour, const int32_t *active)
+{
+    int64_t cnt = Bc * (int64_t)n * (n / 2);
+    hipLaunchKernelGGL(k_rbgs, dim3(blocks_for(cnt)), dim3(kBlock), 0, st, a, f, u, n, Bc, colour,
+                       active);
+}
+
+void launch_resid_restrict(hipStream_t st, const double *a, const double *f, const double *u,
+                           int n, int64_t Bc, double *fc, double *uc, const int32_t *active)
+{
+    int64_t cnt = Bc * (int64_t)(n / 2) * (n / 2);
+    hipLaunchKernelGGL(k_resid_restrict, dim3(blocks_for(cnt)), dim3(kBlock), 0, st, a, f, u, n,
+                       Bc, fc, uc, active);
+}
+
+void launch_prolong(hipStream_t st, const double *ec, double *u, int n, int64_t Bc, int add,
+                    const int32_t *active)
+{
+    int64_t cnt = Bc * (int64_t)n * n;
+    hipLaunchKernelGGL(k_prolong, dim3(blocks_for(cnt)), dim3(kBlock), 0, st, ec, u, n, Bc, add,
+                       active);
+}
+
+void launch_qoi(hipStream_t st, const double *u, int n, int64_t Bc, double *qoi, int nlev, int l,
+                uint32_t mask)
+{
+    hipLaunchKernelGGL(k_qoi, dim3(blocks_for(Bc, kBlock / 64)), dim3(kBlock), 0, st, u, n, Bc,
+                       qoi, nlev, l, mask);
+}
+
+void launch_fill(hipStream_t st, double *p, int64_t count, double v)
+{
+    if (count <= 0)
+        return;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(count)), dim3(kBlock), 0, st, p, count, v);
+}
+
+void launch_fill_i32(hipStream_t st, int32_t *p, int64_t count, int32_t v)
+{
+    if (count <= 0)
+        return;
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(count)), dim3(kBlock), 0, st, p, count, v);
+}
+
+void launch_sums(hipStream_t st, const double *qoi, int nlev, int nq, int64_t b0, int64_t Bc,
+                 int64_t npts, int nshift, double *state)
+{
+    int64_t ntup = (int64_t)nshift * nq * nlev;
+    hipLaunchKernelGGL(k_sums, dim3(blocks_for(ntup, kBlock / 64)), dim3(kBlock), 0, st, qoi, nlev,
+                       nq, b0, Bc, npts, nshift, state);
+}
+
+void launch_sums_final(hipStream_t st, const double *state, int64_t count, double *out)
+{
+    hipLaunchKernelGGL(k_sums_final, dim3(blocks_for(count)), dim3(kBlock), 0, st, state, count,
+                       out);
+}
+
+void launch_residual_norm(hipStream_t st, const double *a, const double *u, int n, int64_t Bc,
+                          double *r, double *rho, int32_t *active, int32_t *iters, double rtol,
+                          int max_iters, int32_t *)
+{
+    hipLaunchKernelGGL(k_residual_norm, dim3(blocks_for(Bc, kBlock / 64)), dim3(kBlock), 0, st, a,
+                       u, n, Bc, r, rho, active, iters, rtol, max_iters);
+}
+
+void launch_axpy_active(hipStream_t st, double *u, const double *e, int n, int64_t Bc,
+                        const int32_t *active)
+{
+    int64_t cnt = Bc * (int64_t)n * n;
+    hipLaunchKernelGGL(k_axpy_active, dim3(blocks_for(cnt)), dim3(kBlock), 0, st, u, e, n, Bc,
+                       active);
+}
+
+}  // namespace mlmc

@@ -1,0 +1,154 @@
+"""CPU tests of the C ABI: the library loads and exports every declared
+symbol, arguments are validated before any GPU work, and the host-side parts
+(KL mode table, FMG schedule, estimator) agree with the oracle.  No compute
+runs on a GPU here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+import paper_1806_05619_amd as m
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mlmc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mlmc_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = m.lib()
+    declared = _declared_symbols()
+    assert len(declared) >= 12
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(m.EXPORTS)
+
+
+def test_status_strings():
+    L = m.lib()
+    assert L.mlmc_status_str(0) == b"ok"
+    assert L.mlmc_status_str(-1) == b"invalid argument"
+    assert L.mlmc_status_str(-4) == b"not converged"
+
+
+def _cfg(**kw):
+    base = dict(n0=4, num_levels=3, s=10, corr_len=0.3, sigma2=1.0, mu0=2, mu1=2, mu2=2,
+                rtol=0.0, max_iters=0, precision=0, qoi_mask=1, num_shifts=0, genvec=None,
+                shifts=None, max_batch=16)
+    base.update(kw)
+    return m.mlmc_config(**base)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n0=3), dict(n0=1), dict(num_levels=0), dict(n0=4, num_levels=12), dict(s=0),
+    dict(corr_len=0.0), dict(sigma2=-1.0), dict(mu1=0, mu2=0), dict(mu0=0),
+    dict(rtol=1e-8, max_iters=0), dict(precision=7), dict(qoi_mask=0), dict(qoi_mask=4),
+    dict(max_batch=0),
+])
+def test_create_rejects_invalid_config(bad):
+    L = m.lib()
+    h = C.c_void_p()
+    cfg = _cfg(**bad)
+    assert L.mlmc_create(C.byref(cfg), 0, C.byref(h)) == m.MLMC_E_INVAL
+    assert not h.value
+    assert len(L.mlmc_last_error(None)) > 0
+
+
+def _host_ctx(**kw):
+    cfg = dict(n0=4, num_levels=3, s=10, corr_len=0.3, sigma2=1.0)
+    cfg.update(kw)
+    return m.Context(**cfg, device=-1)
+
+
+def test_host_only_context_refuses_gpu_calls():
+    ctx = _host_ctx()
+    pts = m.Context.lattice(0, 0, 4)
+    with pytest.raises(m.MlmcError):
+        ctx.fmg_solve(pts)
+    with pytest.raises(m.MlmcError):
+        ctx.field(pts, None)
+
+
+def test_field_size_and_levels():
+    ctx = _host_ctx(n0=16, num_levels=3)
+    # multigrid levels 2^2 .. 16^2 below MLMC level 0
+    assert ctx.field_size(0) == 4 + 16 + 64 + 256
+    assert ctx.field_size(2) == 4 + 16 + 64 + 256 + 1024 + 4096
+    assert ctx.field_size(3) == 0
+    assert ctx.nq == 1
+    assert _host_ctx(qoi_mask=3).nq == 2
+
+
+@pytest.mark.parametrize("lam,s", [(0.3, 10), (0.3, 100), (0.1, 400), (0.05, 1000)])
+def test_mode_table_bit_exact_with_oracle(oracle_mod, lam, s):
+    ctx = _host_ctx(s=s, corr_len=lam)
+    i, j, t = ctx.kl_modes()
+    oi, oj, ot = oracle_mod.kl_modes(lam, s)
+    assert np.array_equal(i, oi) and np.array_equal(j, oj)
+    assert np.allclose(t, ot, rtol=1e-14, atol=0)
+
+
+def test_fmg_trace_matches_figure_and_oracle(oracle_mod):
+    golden = open(os.path.join(ROOT, "tests", "golden", "fmg_trace_mu0_1_level3.txt")).read().split()
+    want = [int(v) for v in golden[0].split(",")]
+    circled = [int(v) for v in golden[1].split(",")]
+    ctx = _host_ctx(n0=2, num_levels=4, mu0=1)
+    lv, mk = ctx.fmg_trace(3)
+    assert lv == want
+    assert [i + 1 for i, v in enumerate(mk) if v] == circled
+    # other cycle counts and hierarchies: identical to the oracle's recursion
+    for n0, L, mu0, k in [(4, 5, 2, 4), (16, 3, 2, 2), (2, 3, 3, 2)]:
+        ctx = _host_ctx(n0=n0, num_levels=L, mu0=mu0)
+        lv, mk = ctx.fmg_trace(k)
+        P = oracle_mod.Problem(n0, L, 4, 0.3, 1.0, mu0=mu0)
+        G = P.finest_mg_level(k)
+        r = P.fmg(G, np.ones(P.field_size(k)), trace_cap=10000)
+        assert lv == r["trace"] and mk == r["marks"]
+
+
+def _F_from_sums(F, nq_index=0):
+    """mlmc_estimate's input sums [k][r][q][l][2] built from per-sample F."""
+    L1 = len(F)
+    R = F[0].shape[0]
+    sums = np.zeros((L1, R, 1, L1, 2))
+    for k in range(L1):
+        for r in range(R):
+            for l in range(k + 1):
+                d = F[k][r, :, l] - (F[k][r, :, l - 1] if l else 0.0)
+                sums[k, r, 0, l, 0] = np.sum(d)
+                sums[k, r, 0, l, 1] = np.sum(d * d)
+    return sums
+
+
+@pytest.mark.parametrize("R,reuse", [(5, True), (5, False), (1, False), (1, True)])
+def test_estimate_matches_oracle(R, reuse):
+    from oracle import estimators as est
+    rng = np.random.default_rng(R + 10 * reuse)
+    N = [40, 17, 6, 3]
+    F = []
+    for k in range(4):
+        base = rng.standard_normal((R, N[k], 1)) + 3.0
+        F.append(base + 0.2 * np.cumsum(rng.standard_normal((R, N[k], k + 1)), axis=2))
+    want = est.mlmc_estimate(F, reuse)
+    got = m.mlmc_estimate(np.array(N), _F_from_sums(F), R, 1, reuse)
+    tol = dict(rtol=1e-12, atol=1e-14)
+    assert np.allclose(got["upsilon"][0], want["upsilon"], **tol)
+    assert np.allclose(got["q_shift"][0], want["q_shift"], **tol)
+    assert np.allclose(got["q_bar"][0], want["q_bar"], **tol)
+    assert np.allclose(got["upsilon_bar"][0], want["upsilon_bar"], **tol)
+    if R == 1 and reuse:
+        assert np.isnan(got["var_q"][0]) and np.all(np.isnan(got["var_level"][0]))
+    else:
+        assert np.allclose(got["var_level"][0], want["var_level"], rtol=1e-10, atol=1e-16)
+        assert np.allclose(got["var_q"][0], want["var_q"], rtol=1e-10, atol=1e-16)
+
+
+def test_estimate_rejects_bad_input():
+    with pytest.raises(m.MlmcError):
+        m.mlmc_estimate(np.array([-1, 2]), np.zeros((2, 2, 1, 2, 2)), 2, 1, True)

@@ -1,0 +1,277 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same seeded inputs.
+
+Tolerances (derived from the arithmetic, see the design notes):
+  lattice points x ............ bit-exact (integer arithmetic)
+  normals y ................... |dy| <= 4 ulp(|y|) (two independent FP64 inverse-CDF methods)
+  field z (FP64) .............. |dz| <= 1e-13 (s-term dot products of O(1) terms)
+  QoI, fixed-cycle FMG ........ relative 1e-12 (same algorithm, different rounding order)
+  QoI, rtol refinement ........ relative 1e-10 against the direct band solve
+  level-difference sums ....... relative 1e-13 against exactly rounded sums
+"""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1806_05619_amd as m  # noqa: E402
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _ctx(name, **over):
+    w = synth.workload(name)
+    w.update(over)
+    kw = dict(n0=w["n0"], num_levels=w["num_levels"], s=w["s"], corr_len=w["corr_len"],
+              sigma2=w["sigma2"], mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"],
+              max_iters=w["max_iters"], precision=m.MLMC_FP64,
+              qoi_mask=m.MLMC_QOI_MEAN | (m.MLMC_QOI_CENTER if "center" in w["qoi"] else 0),
+              max_batch=w.get("max_batch", 64))
+    if w["sampling"] == "lattice":
+        kw["genvec"] = synth.korobov_vector(w["seed"], w["s"])
+        kw["shifts"] = synth.shift_table(w["seed"], w["num_levels"], w["num_shifts"], w["s"])
+    return w, m.Context(**kw, device=0)
+
+
+def _oracle_problem(oracle_mod, w, **over):
+    p = dict(mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"], max_iters=w["max_iters"])
+    p.update(over)
+    return oracle_mod.Problem(w["n0"], w["num_levels"], w["s"], w["corr_len"], w["sigma2"], **p)
+
+
+def _lattice_y(oracle_mod, w, level, shifts, n_begin, n_end):
+    z = synth.korobov_vector(w["seed"], w["s"])
+    D = synth.shift_table(w["seed"], w["num_levels"], w["num_shifts"], w["s"])
+    xs, ys = [], []
+    for r in shifts:
+        x, y = oracle_mod.points(z, D[level, r], n_begin, n_end)
+        xs.append(x)
+        ys.append(y)
+    return np.concatenate(xs), np.concatenate(ys)
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300))
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n_begin,n_end,shifts", [(0, 1024, (0, 4)), (5, 1000, (3, 5)), (1000, 1001, (15, 16))])
+def test_points_bit_exact(oracle_mod, n_begin, n_end, shifts):
+    dev = _dev()
+    w, ctx = _ctx("mlqmc_fp64_s100")
+    level = 3
+    pts = ctx.lattice(level, n_begin, n_end, *shifts)
+    B = ctx.count(pts)
+    x = torch.zeros((B, w["s"]), dtype=torch.int64, device=dev)
+    y = torch.zeros((B, w["s"]), dtype=torch.float64, device=dev)
+    ctx.points_gen(pts, x, y)
+    torch.cuda.synchronize()
+    xo, yo = _lattice_y(oracle_mod, w, level, range(*shifts), n_begin, n_end)
+    assert np.array_equal(x.cpu().numpy().view(np.uint64), xo)
+    yg = y.cpu().numpy()
+    ulps = np.abs(yg - yo) / np.spacing(np.abs(yo))
+    worst = np.unravel_index(np.argmax(ulps), ulps.shape)
+    assert ulps.max() <= 4, f"max {ulps.max():.1f} ulp at y={yo[worst]!r} (gpu {yg[worst]!r})"
+
+
+@pytest.mark.parametrize("name,k,B", [("mlmc_fp64_s10", 2, 37), ("mlqmc_fp64_s100", 4, 70)])
+def test_field_matches_direct_sum(oracle_mod, name, k, B):
+    dev = _dev()
+    w, ctx = _ctx(name)
+    P = _oracle_problem(oracle_mod, w)
+    if w["sampling"] == "mc":
+        yo = synth.mc_normals(w["seed"], k, B, w["s"])
+        pts = ctx.explicit(k, torch.tensor(yo, device=dev))
+        keep = pts
+    else:
+        pts = ctx.lattice(k, 0, B // 2, 0, 2)
+        _, yo = _lattice_y(oracle_mod, w, k, range(2), 0, B // 2)
+        B = ctx.count(pts)
+    M = ctx.field_size(k)
+    assert M == P.field_size(k)
+    z = torch.zeros((B, M), dtype=torch.float64, device=dev)
+    ctx.field(pts, z)
+    torch.cuda.synchronize()
+    zg = z.cpu().numpy()
+    for b in range(B):
+        zo = P.field(yo[b], k)
+        assert np.max(np.abs(zg[b] - zo)) <= 1e-13, b
+
+
+def _solve(ctx, pts, nlev, z=None, sums=False, info=False):
+    dev = torch.device("cuda:0")
+    B = ctx.count(pts)
+    q = torch.full((B, nlev, ctx.nq), float("nan"), dtype=torch.float64, device=dev)
+    s = torch.zeros((pts.shift_end - pts.shift_begin, ctx.nq, nlev, 2), dtype=torch.float64,
+                    device=dev) if sums else None
+    res = ctx.fmg_solve(pts, z=z, qoi=q, sums=s, want_info=info)
+    torch.cuda.synchronize()
+    return q.cpu().numpy(), (s.cpu().numpy() if sums else None), res
+
+
+@pytest.mark.parametrize("name,ks,B", [("mlmc_fp64_s10", (0, 1, 2), 21), ("mlqmc_fp64_s100", (0, 2, 5), 9)])
+def test_fmg_fixed_cycles_match_oracle_fmg(oracle_mod, name, ks, B):
+    """Same field (the oracle's) on both sides: isolates the multigrid."""
+    dev = _dev()
+    w, ctx = _ctx(name)
+    P = _oracle_problem(oracle_mod, w)
+    rng = np.random.default_rng(100)
+    for k in ks:
+        ys = rng.standard_normal((B, w["s"]))
+        zs = np.stack([P.field(y, k) for y in ys])
+        pts = ctx.explicit(k, torch.tensor(ys, device=dev))
+        qg, _, _ = _solve(ctx, pts, k + 1, z=torch.tensor(zs, device=dev))
+        for b in range(B):
+            qo = P.sample_from_field(k, zs[b], 0)["qoi"][:, : ctx.nq]
+            assert _rel(qg[b], qo) <= 1e-12, (k, b, qg[b], qo)
+
+
+def test_full_path_matches_oracle(oracle_mod):
+    """Points, field, FMG and QoI all on the GPU for lattice samples."""
+    _dev()
+    w, ctx = _ctx("mlqmc_fp64_s100")
+    P = _oracle_problem(oracle_mod, w)
+    k = 4
+    pts = ctx.lattice(k, 3, 35, 6, 8)
+    qg, _, _ = _solve(ctx, pts, k + 1)
+    _, yo = _lattice_y(oracle_mod, w, k, range(6, 8), 3, 35)
+    qo, bad = P.batch(k, yo, 0)
+    assert bad == 0
+    assert _rel(qg, qo[:, :, : ctx.nq]) <= 1e-11
+
+
+def test_rtol_refinement_matches_direct_solve(oracle_mod):
+    dev = _dev()
+    w, ctx = _ctx("mlqmc_fp64_s100", rtol=1e-12, max_iters=40, mu0=1)
+    P = _oracle_problem(oracle_mod, w)
+    k = 3
+    ys = np.random.default_rng(7).standard_normal((6, w["s"]))
+    pts = ctx.explicit(k, torch.tensor(ys, device=dev))
+    qg, _, info = _solve(ctx, pts, k + 1, info=True)
+    assert info["status"] == m.MLMC_OK and info["not_converged"] == 0
+    assert 0 < info["max_rel_residual"] <= 1e-12
+    for b in range(len(ys)):
+        qd = P.sample(k, ys[b], 1)[:, : ctx.nq]
+        assert _rel(qg[b], qd) <= 1e-10, b
+
+
+def test_rtol_not_converged_reports(oracle_mod):
+    dev = _dev()
+    w, ctx = _ctx("mlqmc_fp64_s100", rtol=1e-15, max_iters=1, mu0=1)
+    ys = np.random.default_rng(8).standard_normal((3, w["s"]))
+    pts = ctx.explicit(2, torch.tensor(ys, device=dev))
+    qg, _, info = _solve(ctx, pts, 3, info=True)
+    assert info["status"] == m.MLMC_E_NOCONV
+    assert info["not_converged"] == 3 and info["max_iters_used"] == 1
+    assert np.all(np.isfinite(qg))
+
+
+def test_mlmc_estimate_end_to_end(oracle_mod):
+    """Plain MLMC, FP64, N(0,1) samples 256/64/16 on 16^2..64^2: per-sample QoI,
+    level-difference sums and the estimator against the oracle."""
+    from oracle import estimators as est
+    dev = _dev()
+    w, ctx = _ctx("mlmc_fp64_s10", max_batch=256)
+    P = _oracle_problem(oracle_mod, w)
+    L1 = w["num_levels"]
+    sums_all = np.zeros((L1, 1, 1, L1, 2))
+    F_oracle = []
+    for k, N in enumerate(w["samples_per_level"]):
+        ys = synth.mc_normals(w["seed"], k, N, w["s"])
+        pts = ctx.explicit(k, torch.tensor(ys, device=dev))
+        qg, sg, _ = _solve(ctx, pts, k + 1, sums=True)
+        qo, bad = P.batch(k, ys, 0)
+        assert bad == 0
+        assert _rel(qg[:, :, 0], qo[:, :, 0]) <= 1e-12
+        # sums against exactly rounded sums of the GPU's own QoI
+        for l in range(k + 1):
+            d = qg[:, l, 0] - (qg[:, l - 1, 0] if l else 0.0)
+            assert abs(sg[0, 0, l, 0] - math.fsum(d)) <= 1e-13 * abs(math.fsum(np.abs(d)))
+            assert abs(sg[0, 0, l, 1] - math.fsum(d * d)) <= 1e-13 * math.fsum(d * d)
+        sums_all[k, 0, 0, : k + 1] = sg[0, 0]
+        F_oracle.append(qo[None, :, :, 0])
+    for reuse in (False, True):
+        got = m.mlmc_estimate(np.array(w["samples_per_level"]), sums_all, 1, 1, reuse)
+        want = est.mlmc_estimate(F_oracle, reuse)
+        assert abs(got["q_bar"][0] - want["q_bar"]) <= 1e-11 * abs(want["q_bar"])
+        assert np.allclose(got["upsilon"][0, :, 0], want["upsilon"][:, 0], rtol=1e-10, atol=1e-15)
+        if not reuse:
+            assert abs(got["var_q"][0] - want["var_q"]) <= 1e-8 * want["var_q"]
+
+
+def test_deterministic_alone_vs_in_batch():
+    _dev()
+    w, ctx = _ctx("mlqmc_fp64_s100")
+    k = 3
+    pts = ctx.lattice(k, 0, 40, 1, 3)
+    q1, _, _ = _solve(ctx, pts, k + 1)
+    q2, _, _ = _solve(ctx, pts, k + 1)
+    assert np.array_equal(q1, q2)
+    for r in (1, 2):
+        for n in (0, 17, 39):
+            qa, _, _ = _solve(ctx, ctx.lattice(k, n, n + 1, r, r + 1), k + 1)
+            assert np.array_equal(qa[0], q1[(r - 1) * 40 + n])
+
+
+def test_chunked_equals_single_chunk():
+    """max_batch = 3 forces several chunks with a ragged tail."""
+    _dev()
+    w, big = _ctx("mlqmc_fp64_s100", max_batch=64)
+    _, small = _ctx("mlqmc_fp64_s100", max_batch=3)
+    k = w["num_levels"] - 1 - 2
+    pts = big.lattice(k, 0, 23, 0, 1)
+    qa, sa, _ = _solve(big, pts, k + 1, sums=True)
+    qb, sb, _ = _solve(small, pts, k + 1, sums=True)
+    assert np.array_equal(qa, qb)
+    assert np.allclose(sa, sb, rtol=1e-14, atol=0)
+
+
+def test_empty_batch_and_invalid_points():
+    dev = _dev()
+    w, ctx = _ctx("mlqmc_fp64_s100")
+    q, s, _ = _solve(ctx, ctx.lattice(2, 5, 5, 0, 2), 3, sums=True)
+    assert q.shape[0] == 0 and np.all(s == 0.0)
+    sentinel = torch.full((4, 3, ctx.nq), 7.0, dtype=torch.float64, device=dev)
+    for bad in [ctx.lattice(9, 0, 4), ctx.lattice(2, 0, 4, 0, 17), ctx.lattice(2, 0, 4, 3, 3),
+                m.mlmc_points(m.MLMC_POINTS_LATTICE, 2, 0, 1, 0, (1 << 32) + 1, None)]:
+        with pytest.raises(m.MlmcError) as e:
+            ctx.fmg_solve(bad, qoi=sentinel)
+        assert e.value.status == m.MLMC_E_INVAL
+    torch.cuda.synchronize()
+    assert torch.all(sentinel == 7.0)
+
+
+def test_full_size_bench_workload_sampled(oracle_mod):
+    """The benchmark's launch configuration: 2^10 lattice points x 16 shifts on
+    4^2..256^2 in one call.  Sampled samples against the oracle; sums against
+    exactly rounded sums of the whole QoI table."""
+    _dev()
+    w, ctx = _ctx("mlqmc_fp64_s100", max_batch=16384)
+    P = _oracle_problem(oracle_mod, w)
+    k = w["num_levels"] - 1
+    npts = 1 << w["lattice_log2n"]
+    R = w["num_shifts"]
+    pts = ctx.lattice(k, 0, npts, 0, R)
+    qg, sg, _ = _solve(ctx, pts, k + 1, sums=True)
+    assert np.all(np.isfinite(qg))
+    picks = [(r, n) for r in (0, 7, 15) for n in (0, 1, 511, 1023)]
+    for r, n in picks:
+        _, yo = _lattice_y(oracle_mod, w, k, [r], n, n + 1)
+        qo = P.sample(k, yo[0], 0)[:, : ctx.nq]
+        assert _rel(qg[r * npts + n], qo) <= 1e-11, (r, n)
+    for r in (0, 9, 15):
+        for q in range(ctx.nq):
+            for l in range(k + 1):
+                blk = qg[r * npts:(r + 1) * npts, :, q]
+                d = blk[:, l] - (blk[:, l - 1] if l else 0.0)
+                assert abs(sg[r, q, l, 0] - math.fsum(d)) <= 1e-13 * math.fsum(np.abs(d))
