@@ -1,0 +1,208 @@
+"""Benchmark of the MG-MLQMC per-sample hot path on one MI355X.
+
+One step = one pass of the whole path over one batch: lattice points, KL field
+(dense product + exp), FMG with the QoI of every stage, level-difference sums,
+their device-to-host copy and the estimator.  The batch is the finest level of
+the MLQMC FP64 workload: 2^10 Korobov lattice points x 16 random shifts =
+16384 samples solved on 4^2 .. 256^2 (s = 100 KL terms, lambda = 0.3,
+sigma = 1, FMG with 2 V(2,2) cycles per stage, QoI mean of u and u(1/2,1/2)).
+Inputs (generating vector, shifts, KL basis) are resident in HBM before the
+timed region.
+
+Prints one JSON line (rank 0) with the throughput, the roofline of the
+dominant kernel measured live with HIP events on the library's stream, the
+per-level throughput, request latency percentiles and the oracle timed on the
+host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("samples/s per level (KL+FMG) mixed vs FP64 at equal QoI error; p50/p99 latency")
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_context(m, w, max_batch):
+    import synth
+    return m.Context(w["n0"], w["num_levels"], w["s"], w["corr_len"], w["sigma2"],
+                     mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"],
+                     max_iters=w["max_iters"], precision=m.MLMC_FP64,
+                     qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
+                     genvec=synth.korobov_vector(w["seed"], w["s"]),
+                     shifts=synth.shift_table(w["seed"], w["num_levels"], w["num_shifts"], w["s"]),
+                     max_batch=max_batch, device=0)
+
+
+def cpu_baseline(w, level, seconds):
+    """The oracle (field by direct summation + CPU FMG + QoI) on the host's
+    cores, over the first lattice points of shift 0 at the same level, run in
+    batches until `seconds` of wall time have passed."""
+    import oracle
+    import synth
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    threads = max(1, min(threads, 16))
+    P = oracle.Problem(w["n0"], w["num_levels"], w["s"], w["corr_len"], w["sigma2"],
+                       mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"])
+    z = synth.korobov_vector(w["seed"], w["s"])
+    D = synth.shift_table(w["seed"], w["num_levels"], w["num_shifts"], w["s"])
+    done, n0 = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        nb = 2 * threads
+        _, y = oracle.points(z, D[level, 0], n0, n0 + nb)
+        P.batch(level, y, 0, nthreads=threads)
+        done += nb
+        n0 += nb
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="samples/s", cores=threads, kind="oracle",
+                sample=f"{done} lattice samples (shift 0, points 0..{done - 1}) at level "
+                       f"{level} ({w['n0'] << level}^2): direct-sum KL field + CPU FMG + QoI, "
+                       f"{dt:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip per-level, latency and CPU-baseline measurements")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path "
+              "shards by shift or lattice range with one small all-reduce of the sums, "
+              "which this build does not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_1806_05619_amd as m
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w = synth.workload("mlqmc_fp64_s100")
+    k = w["num_levels"] - 1
+    npts = 1 << w["lattice_log2n"]
+    R = w["num_shifts"]
+    B = npts * R
+    nq = 2
+    ctx = make_context(m, w, max_batch=B)
+    pts = ctx.lattice(k, 0, npts, 0, R)
+    sums = torch.zeros((R, nq, k + 1, 2), dtype=torch.float64, device=dev)
+    n_per_level = np.zeros(k + 1, dtype=np.int64)
+    n_per_level[k] = npts
+    host_sums = np.zeros((k + 1, R, nq, k + 1, 2))
+    est = {}
+
+    def step():
+        ctx.fmg_solve(pts, sums=sums)
+        host_sums[k] = sums.cpu().numpy()          # synchronising device-to-host copy
+        est.update(m.mlmc_estimate(n_per_level, host_sums, R, nq, True))
+
+    log(f"[bench] workload mlqmc_fp64_s100 level {k}: {B} samples, warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    ctx.profile_begin("smooth")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_end()
+    elapsed = t1 - t0
+    value = B * args.steps / elapsed
+    log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s -> {value:.1f} samples/s")
+
+    avg_ms = prof["total_ms"] / max(prof["launches"], 1)
+    bytes_per_launch = prof["bytes"] / max(prof["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = dict(kernel="k_rbgs (one red-black colour, all levels)", bound="hbm",
+                    achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS, traffic=None,
+                    avg_launch_ms=avg_ms, launches_per_step=prof["launches"] / args.steps,
+                    algorithmic_bytes_per_launch=bytes_per_launch,
+                    share_of_step=prof["total_ms"] / (elapsed * 1e3))
+
+    out = dict(metric=METRIC, value=value, unit="samples/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=elapsed * 1e3 / args.steps,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+               data="synthetic",
+               config=dict(workload="mlqmc_fp64_s100: MLQMC FP64, lognormal KL field "
+                                    "(separable exponential, lambda 0.3, sigma 1, s = 100), "
+                                    "FMG 2 x V(2,2) from 2^2, finest level 256^2 "
+                                    "(MLMC levels 4^2..256^2), 2^10 Korobov lattice points "
+                                    "x 16 shifts = 16384 samples per step, QoI mean(u) and "
+                                    "u(1/2,1/2)",
+                           samples_per_step=B, level=k, finest_grid=f"{w['n0'] << k}^2",
+                           precision="fp64"),
+               roofline=roofline, mixed=None,
+               estimate=dict(q_bar=float(est["q_bar"][0]), std=float(np.sqrt(est["var_q"][0]))))
+
+    if not args.no_extras:
+        # kernel-time breakdown of one step (untimed)
+        breakdown = {}
+        for kind in ("points", "field", "smooth", "restrict", "prolong", "coarse", "qoi", "sums"):
+            ctx.profile_begin(kind)
+            step()
+            r = ctx.profile_end()
+            breakdown[kind] = dict(ms=r["total_ms"], launches=r["launches"],
+                                   gbs=(r["bytes"] / (r["total_ms"] * 1e-3) / 1e9) if r["total_ms"] > 0 else None,
+                                   tflops=(r["flops"] / (r["total_ms"] * 1e-3) / 1e12) if r["flops"] else None)
+        out["kernel_breakdown_one_step"] = breakdown
+        # samples/s per level, same batch size (16384 samples finest at each level)
+        per_level = {}
+        for lev in range(k + 1):
+            p = ctx.lattice(lev, 0, npts, 0, R)
+            s2 = torch.zeros((R, nq, lev + 1, 2), dtype=torch.float64, device=dev)
+            ctx.fmg_solve(p, sums=s2)
+            torch.cuda.synchronize()
+            reps = 3
+            ta = time.perf_counter()
+            for _ in range(reps):
+                ctx.fmg_solve(p, sums=s2)
+                s2.cpu()
+            torch.cuda.synchronize()
+            per_level[f"{w['n0'] << lev}^2"] = B * reps / (time.perf_counter() - ta)
+        out["samples_per_s_per_level"] = per_level
+        # request latency: (level, lattice range, shift) calls, host-visible sums
+        lat = {}
+        for nreq in (1, 64, 1024):
+            p = ctx.lattice(k, 0, nreq, 3, 4)
+            s3 = torch.zeros((1, nq, k + 1, 2), dtype=torch.float64, device=dev)
+            times = []
+            for i in range(40 if nreq < 1024 else 15):
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                ctx.fmg_solve(p, sums=s3)
+                s3.cpu()
+                times.append((time.perf_counter() - ta) * 1e3)
+            times = np.array(times[3:])
+            lat[f"level{k}_n{nreq}"] = dict(p50_ms=float(np.percentile(times, 50)),
+                                            p99_ms=float(np.percentile(times, 99)))
+        out["latency"] = lat
+        log("[bench] extras done; CPU baseline ...")
+        out["cpu_baseline"] = cpu_baseline(w, k, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
