@@ -245,7 +245,18 @@ mlmc_status mlmc_fmg_trace(mlmc_ctx ctx, int32_t level, int32_t *levels,
 enum {
     MLMC_KERNEL_POINTS = 0, MLMC_KERNEL_FIELD = 1, MLMC_KERNEL_SMOOTH = 2,
     MLMC_KERNEL_RESTRICT = 3, MLMC_KERNEL_PROLONG = 4, MLMC_KERNEL_COARSE = 5,
-    MLMC_KERNEL_QOI = 6, MLMC_KERNEL_SUMS = 7
+    MLMC_KERNEL_QOI = 6, MLMC_KERNEL_SUMS = 7,
+    MLMC_KERNEL_PRE = 8,   /* fused tile pass: mu1 sweeps + residual + restriction;
+                              bytes a, u (unless zero or interpolated start), f
+                              (unless f = 1) read on n^2, u written on n^2,
+                              coarse f written on n^2/4 (+ coarse u read on n^2/4
+                              when interpolating) */
+    MLMC_KERNEL_POST = 9,  /* fused tile pass: prolongation + correction + mu2
+                              sweeps; bytes e_c (n^2/4), a, u, f (unless 1) read,
+                              u written */
+    MLMC_KERNEL_LDS = 10   /* LDS-resident hierarchy <= 32^2: a of all its grids
+                              read, f of its top grid read (V-cycle mode), u of
+                              its top grid written */
 };
 typedef struct {
     int64_t launches;

@@ -407,7 +407,70 @@ mlmc_status run_fmg(mlmc_ctx c, hipStream_t st, const Hier &h, int k, double *qo
     return MLMC_OK;
 }
 
-double fsum_pair(double a, double b) { return a + b; }
+// ---- fused schedule: LDS-resident grids <= 32^2, tile passes above --------
+struct FusedRunner {
+    mlmc_ctx c;
+    hipStream_t st;
+    Hier h;
+    int Gs;
+
+    double cells(int n) const { return (double)h.Bc * n * n; }
+
+    void lds(int mode, double *qoi, int nlev)
+    {
+        const int n = 2 << Gs;
+        double bytes = 8.0 * h.Bc * level_offset(Gs + 1) + 8.0 * cells(n) * (mode == 1 ? 2.0 : 1.0);
+        ProfScope ps(c, st, MLMC_KERNEL_LDS, bytes, 0.0);
+        launch_lds_mg(st, c->d_a, c->d_f, c->d_u, h.Bc, Gs, mode, c->cfg.mu0, c->cfg.mu1, c->cfg.mu2,
+                      c->g0, qoi, nlev, c->cfg.qoi_mask, nullptr);
+    }
+
+    // V(mu1,mu2) at level g > Gs.  init_top: 0 read u, 1 zero, 2 interpolate
+    // the previous stage's solution.  top_f nullptr means f = 1.
+    void vcycle(int g, double *top_u, int init_top, const double *top_f)
+    {
+        for (int l = g; l > Gs; --l) {
+            const int n = 2 << l;
+            const int init = (l == g) ? init_top : 1;
+            const double *f = (l == g) ? top_f : h.f[l];
+            double *u = (l == g) ? top_u : h.u[l];
+            double words = 1.0 + (init == 0 ? 1.0 : 0.0) + (f ? 1.0 : 0.0) + 1.0 + 0.25 +
+                           (init == 2 ? 0.25 : 0.0);
+            ProfScope ps(c, st, MLMC_KERNEL_PRE, 8.0 * cells(n) * words, 0.0);
+            launch_pre_tile(st, c->cfg.mu1, h.a[l], f, u, h.u[l - 1], n, h.Bc, init, h.f[l - 1],
+                            nullptr);
+        }
+        lds(1, nullptr, 0);
+        for (int l = Gs + 1; l <= g; ++l) {
+            const int n = 2 << l;
+            const double *f = (l == g) ? top_f : h.f[l];
+            double *u = (l == g) ? top_u : h.u[l];
+            ProfScope ps(c, st, MLMC_KERNEL_POST, 8.0 * cells(n) * (3.25 + (f ? 1.0 : 0.0)), 0.0);
+            launch_post_tile(st, c->cfg.mu2, h.a[l], f, u, h.u[l - 1], n, h.Bc, nullptr);
+        }
+    }
+};
+
+bool use_fused(mlmc_ctx c) { return c->cfg.rtol <= 0.0 && fused_supported(c->cfg.mu1, c->cfg.mu2); }
+
+mlmc_status run_fmg_fused(mlmc_ctx c, hipStream_t st, const Hier &h, int k, double *qoi,
+                          StageStats *stats)
+{
+    const int G = h.G, nlev = k + 1;
+    FusedRunner R{c, st, h, std::min(G, kLdsMaxLevel)};
+    R.lds(0, qoi, nlev);                       // FMG stages 0..Gs with their QoIs
+    for (int g = R.Gs + 1; g <= G; ++g) {
+        const int n = 2 << g;
+        for (int cyc = 0; cyc < c->cfg.mu0; ++cyc)
+            R.vcycle(g, h.u[g], cyc == 0 ? 2 : 0, nullptr);
+        if (g >= c->g0) {
+            ProfScope ps(c, st, MLMC_KERNEL_QOI, 8.0 * R.cells(n), 0.0);
+            launch_qoi(st, h.u[g], n, h.Bc, qoi, nlev, g - c->g0, c->cfg.qoi_mask);
+        }
+    }
+    if (stats) stats->max_iters = std::max(stats->max_iters, c->cfg.mu0);
+    return MLMC_OK;
+}
 
 // Neumaier summation on the host
 struct HostSum {
@@ -723,7 +786,8 @@ mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts, const double *z
             launch_field_gemm(s, Y, ctx->cfg.s, ctx->d_basis, ctx->Mmax, M, Bc, ctx->d_a, 1);
         }
         double *q = qoi_dev ? qoi_dev + b0 * nlev * nq : ctx->d_qoi;
-        st = run_fmg(ctx, s, h, k, q, nullptr, &stats);
+        st = use_fused(ctx) ? run_fmg_fused(ctx, s, h, k, q, &stats)
+                            : run_fmg(ctx, s, h, k, q, nullptr, &stats);
         if (st) return st;
         if (sums_dev) {
             ProfScope ps(ctx, s, MLMC_KERNEL_SUMS, 8.0 * Bc * nlev * nq, 0.0);
@@ -780,7 +844,7 @@ mlmc_status mlmc_profile_begin(mlmc_ctx ctx, int32_t kernel_kind)
 {
     if (!ctx) return MLMC_E_INVAL;
     if (ctx->host_only) return MLMC_E_STATE;
-    if (kernel_kind < MLMC_KERNEL_POINTS || kernel_kind > MLMC_KERNEL_SUMS)
+    if (kernel_kind < MLMC_KERNEL_POINTS || kernel_kind > MLMC_KERNEL_LDS)
         return inval(ctx, "unknown kernel kind");
     ctx->prof.kind = kernel_kind;
     ctx->prof.used = 0;

@@ -13,6 +13,7 @@ namespace mlmc {
 
 constexpr int kMaxMgLevels = 12;   // n_g = 2^(g+1) <= 4096
 constexpr int kBlock = 256;
+constexpr int kLdsMaxLevel = 4;    // grids up to 32^2 run LDS-resident (one workgroup per sample)
 
 // Offset (in cells) of multigrid level g inside a level-major per-sample
 // field: sum_{g' < g} 4^(g'+1) = 4 (4^g - 1) / 3.
@@ -64,5 +65,20 @@ void launch_residual_norm(hipStream_t st, const double *a, const double *u, int 
                           int max_iters, int32_t *n_active);
 void launch_axpy_active(hipStream_t st, double *u, const double *e, int n, int64_t Bc,
                         const int32_t *active);
+
+// ---- fused kernels (kernels_fused.hip) ----
+bool fused_supported(int mu1, int mu2);
+// pre pass on level n: init 0 read u, 1 zero guess, 2 u = P uc; writes u and fc
+void launch_pre_tile(hipStream_t st, int mu1, const double *a, const double *f, double *u,
+                     const double *uc, int n, int64_t Bc, int init, double *fc,
+                     const int32_t *active);
+// post pass on level n: u += P ec, then mu2 sweeps
+void launch_post_tile(hipStream_t st, int mu2, const double *a, const double *f, double *u,
+                      const double *ec, int n, int64_t Bc, const int32_t *active);
+// LDS-resident hierarchy: mode 0 FMG stages 0..G with QoI, mode 1 one V-cycle
+// at level G (zero guess, f from the f pool) -> correction in the u pool
+void launch_lds_mg(hipStream_t st, const double *a_pool, const double *f_pool, double *u_pool,
+                   int64_t Bc, int G, int mode, int mu0, int mu1, int mu2, int g0, double *qoi,
+                   int nlev, uint32_t mask, const int32_t *active);
 
 }  // namespace mlmc
