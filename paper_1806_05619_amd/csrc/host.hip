@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -407,6 +408,21 @@ mlmc_status run_fmg(mlmc_ctx c, hipStream_t st, const Hier &h, int k, double *qo
     return MLMC_OK;
 }
 
+// Large-grid pass kind per pass, chosen by measurement on MI355X (256^2 FP64,
+// 16384 samples): LDS tiles for the pre pass, row streaming for the post pass.
+// MLMC_LARGE_PASS=tile|stream forces one kind for both (tuning runs).
+int large_pass_override()
+{
+    static int mode = -2;
+    if (mode == -2) {
+        const char *e = std::getenv("MLMC_LARGE_PASS");
+        mode = !e ? -1 : (std::strcmp(e, "tile") == 0 ? 0 : (std::strcmp(e, "stream") == 0 ? 1 : -1));
+    }
+    return mode;
+}
+bool pre_uses_stream(int n) { return large_pass_override() == 1 && stream_supported(n); }
+bool post_uses_stream(int n) { return large_pass_override() != 0 && stream_supported(n); }
+
 // ---- fused schedule: LDS-resident grids <= 32^2, tile passes above --------
 struct FusedRunner {
     mlmc_ctx c;
@@ -437,8 +453,12 @@ struct FusedRunner {
             double words = 1.0 + (init == 0 ? 1.0 : 0.0) + (f ? 1.0 : 0.0) + 1.0 + 0.25 +
                            (init == 2 ? 0.25 : 0.0);
             ProfScope ps(c, st, MLMC_KERNEL_PRE, 8.0 * cells(n) * words, 0.0);
-            launch_pre_tile(st, c->cfg.mu1, h.a[l], f, u, h.u[l - 1], n, h.Bc, init, h.f[l - 1],
-                            nullptr);
+            if (pre_uses_stream(n))
+                launch_pre_stream(st, c->cfg.mu1, h.a[l], f, u, h.u[l - 1], n, h.Bc, init,
+                                  h.f[l - 1], nullptr);
+            else
+                launch_pre_tile(st, c->cfg.mu1, h.a[l], f, u, h.u[l - 1], n, h.Bc, init,
+                                h.f[l - 1], nullptr);
         }
         lds(1, nullptr, 0);
         for (int l = Gs + 1; l <= g; ++l) {
@@ -446,7 +466,10 @@ struct FusedRunner {
             const double *f = (l == g) ? top_f : h.f[l];
             double *u = (l == g) ? top_u : h.u[l];
             ProfScope ps(c, st, MLMC_KERNEL_POST, 8.0 * cells(n) * (3.25 + (f ? 1.0 : 0.0)), 0.0);
-            launch_post_tile(st, c->cfg.mu2, h.a[l], f, u, h.u[l - 1], n, h.Bc, nullptr);
+            if (post_uses_stream(n))
+                launch_post_stream(st, c->cfg.mu2, h.a[l], f, u, h.u[l - 1], n, h.Bc, nullptr);
+            else
+                launch_post_tile(st, c->cfg.mu2, h.a[l], f, u, h.u[l - 1], n, h.Bc, nullptr);
         }
     }
 };

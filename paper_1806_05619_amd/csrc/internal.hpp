@@ -81,4 +81,12 @@ void launch_lds_mg(hipStream_t st, const double *a_pool, const double *f_pool, d
                    int64_t Bc, int G, int mode, int mu0, int mu1, int mu2, int g0, double *qoi,
                    int nlev, uint32_t mask, const int32_t *active);
 
+// ---- row-streaming passes (kernels_stream.hip), one workgroup per sample ----
+bool stream_supported(int n);
+void launch_pre_stream(hipStream_t st, int mu1, const double *a, const double *f, double *u,
+                       const double *uc, int n, int64_t Bc, int init, double *fc,
+                       const int32_t *active);
+void launch_post_stream(hipStream_t st, int mu2, const double *a, const double *f, double *u,
+                        const double *ec, int n, int64_t Bc, const int32_t *active);
+
 }  // namespace mlmc

@@ -185,18 +185,30 @@ __global__ __launch_bounds__(NT) void k_pre_tile(const double *__restrict__ a,
         __syncthreads();
     }
 
-    for (int e = threadIdx.x; e < S * S; e += NT) {
+    // all global loads of the region first (memory-level parallelism), then LDS
+    constexpr int PERT = (S * S + NT - 1) / NT;
+    double av[PERT], uv[PERT];
+#pragma unroll
+    for (int k = 0; k < PERT; ++k) {
+        const int e = threadIdx.x + NT * k;
         const int lj = e / S, li = e - lj * S;
         const int gi = i0 - H + li, gj = j0 - H + lj;
-        double av = 0.0, uv = 0.0;
-        if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
+        av[k] = 0.0;
+        uv[k] = 0.0;
+        if (e < S * S && gi >= 0 && gi < n && gj >= 0 && gj < n) {
             const int64_t p = gi + (int64_t)n * gj;
-            av = ab[p];
-            if (init == 0) uv = ub[p];
-            else if (init == 2) uv = CSt::at(c_s, cI0, cJ0, gi, gj);
+            av[k] = ab[p];
+            if (init == 0) uv[k] = ub[p];
+            else if (init == 2) uv[k] = CSt::at(c_s, cI0, cJ0, gi, gj);
         }
-        a_s[e] = av;
-        u_s[e] = uv;
+    }
+#pragma unroll
+    for (int k = 0; k < PERT; ++k) {
+        const int e = threadIdx.x + NT * k;
+        if (e < S * S) {
+            a_s[e] = av[k];
+            u_s[e] = uv[k];
+        }
     }
     __syncthreads();
 
@@ -319,17 +331,28 @@ __global__ __launch_bounds__(NT) void k_post_tile(const double *__restrict__ a,
     CSt::load(c_s, ec + b * (int64_t)nc * nc, nc, cI0, cJ0);
     __syncthreads();
 
-    for (int e = threadIdx.x; e < S * S; e += NT) {
+    constexpr int PERT = (S * S + NT - 1) / NT;
+    double av[PERT], uv[PERT];
+#pragma unroll
+    for (int k = 0; k < PERT; ++k) {
+        const int e = threadIdx.x + NT * k;
         const int lj = e / S, li = e - lj * S;
         const int gi = i0 - H + li, gj = j0 - H + lj;
-        double av = 0.0, uv = 0.0;
-        if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
+        av[k] = 0.0;
+        uv[k] = 0.0;
+        if (e < S * S && gi >= 0 && gi < n && gj >= 0 && gj < n) {
             const int64_t p = gi + (int64_t)n * gj;
-            av = ab[p];
-            uv = ub[p] + CSt::at(c_s, cI0, cJ0, gi, gj);
+            av[k] = ab[p];
+            uv[k] = ub[p] + CSt::at(c_s, cI0, cJ0, gi, gj);
         }
-        a_s[e] = av;
-        u_s[e] = uv;
+    }
+#pragma unroll
+    for (int k = 0; k < PERT; ++k) {
+        const int e = threadIdx.x + NT * k;
+        if (e < S * S) {
+            a_s[e] = av[k];
+            u_s[e] = uv[k];
+        }
     }
     __syncthreads();
 
