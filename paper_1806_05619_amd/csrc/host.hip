@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <new>
 #include <string>
 #include <vector>
@@ -43,6 +44,10 @@ struct mlmc_ctx_s {
     int64_t state_tuples = 0;
     double *d_rho = nullptr;
     int32_t *d_active = nullptr, *d_iters = nullptr;
+    double *d_w = nullptr;           // refinement modes: FP64 stage solutions (pool elements)
+    int32_t *d_st_iters = nullptr, *d_st_bad = nullptr;
+    double *d_st_rho = nullptr;      // per-sample refinement statistics of a chunk
+    int elem = 8;                    // bytes per pool element (4 in the mixed mode)
     int32_t *h_active = nullptr, *h_iters = nullptr;
     double *h_rho = nullptr;
     std::vector<void *> allocs;
@@ -165,7 +170,7 @@ int64_t chunk_capacity(mlmc_ctx c, int k)
 {
     int G = c->g0 + k;
     int64_t cap = c->pool / field_size_g(G);
-    if (c->cfg.rtol > 0.0)
+    if (c->cfg.rtol > 0.0 && !fused_supported(c->cfg.mu1, c->cfg.mu2))
         cap = std::min(cap, c->ecap / level_cells(G));
     return std::max<int64_t>(1, std::min(cap, c->chunk_max));
 }
@@ -424,74 +429,178 @@ bool pre_uses_stream(int n) { return large_pass_override() == 1 && stream_suppor
 bool post_uses_stream(int n) { return large_pass_override() != 0 && stream_supported(n); }
 
 // ---- fused schedule: LDS-resident grids <= 32^2, tile passes above --------
+// Typed views of one chunk's pools: a, u, f in the V-cycle type T; w holds the
+// FP64 stage solutions of the refinement modes.
+template <typename T>
+struct HierT {
+    int G = 0;
+    int64_t Bc = 0;
+    T *a[kMaxMgLevels] = {};
+    T *u[kMaxMgLevels] = {};
+    T *f[kMaxMgLevels] = {};
+    double *w[kMaxMgLevels] = {};
+};
+
+template <typename T>
+HierT<T> make_hier_t(mlmc_ctx c, int G, int64_t Bc)
+{
+    HierT<T> h;
+    h.G = G;
+    h.Bc = Bc;
+    for (int g = 0; g <= G; ++g) {
+        const int64_t off = Bc * level_offset(g);
+        h.a[g] = (T *)c->d_a + off;
+        h.u[g] = (T *)c->d_u + off;
+        h.f[g] = (T *)c->d_f + off;
+        h.w[g] = c->d_w ? c->d_w + off : nullptr;
+    }
+    return h;
+}
+
+template <typename T>
 struct FusedRunner {
     mlmc_ctx c;
     hipStream_t st;
-    Hier h;
+    HierT<T> h;
     int Gs;
+    static constexpr double W = sizeof(T);
 
     double cells(int n) const { return (double)h.Bc * n * n; }
 
-    void lds(int mode, double *qoi, int nlev)
+    // one V-cycle on the LDS-resident levels <= Gs (zero guess, f from the pool)
+    void lds_vcycle(const int32_t *active)
     {
         const int n = 2 << Gs;
-        double bytes = 8.0 * h.Bc * level_offset(Gs + 1) + 8.0 * cells(n) * (mode == 1 ? 2.0 : 1.0);
-        ProfScope ps(c, st, MLMC_KERNEL_LDS, bytes, 0.0);
-        launch_lds_mg(st, c->d_a, c->d_f, c->d_u, h.Bc, Gs, mode, c->cfg.mu0, c->cfg.mu1, c->cfg.mu2,
-                      c->g0, qoi, nlev, c->cfg.qoi_mask, nullptr);
+        ProfScope ps(c, st, MLMC_KERNEL_LDS, W * h.Bc * level_offset(Gs + 1) + W * cells(n) * 2.0, 0.0);
+        launch_lds_vcycle<T>(st, h.a[0], h.f[0], h.u[0], h.Bc, Gs, c->cfg.mu1, c->cfg.mu2, active);
     }
 
     // V(mu1,mu2) at level g > Gs.  init_top: 0 read u, 1 zero, 2 interpolate
     // the previous stage's solution.  top_f nullptr means f = 1.
-    void vcycle(int g, double *top_u, int init_top, const double *top_f)
+    void vcycle(int g, T *top_u, int init_top, const T *top_f, const int32_t *active)
     {
         for (int l = g; l > Gs; --l) {
             const int n = 2 << l;
             const int init = (l == g) ? init_top : 1;
-            const double *f = (l == g) ? top_f : h.f[l];
-            double *u = (l == g) ? top_u : h.u[l];
+            const T *f = (l == g) ? top_f : h.f[l];
+            T *u = (l == g) ? top_u : h.u[l];
             double words = 1.0 + (init == 0 ? 1.0 : 0.0) + (f ? 1.0 : 0.0) + 1.0 + 0.25 +
                            (init == 2 ? 0.25 : 0.0);
-            ProfScope ps(c, st, MLMC_KERNEL_PRE, 8.0 * cells(n) * words, 0.0);
-            if (pre_uses_stream(n))
-                launch_pre_stream(st, c->cfg.mu1, h.a[l], f, u, h.u[l - 1], n, h.Bc, init,
-                                  h.f[l - 1], nullptr);
-            else
-                launch_pre_tile(st, c->cfg.mu1, h.a[l], f, u, h.u[l - 1], n, h.Bc, init,
-                                h.f[l - 1], nullptr);
+            ProfScope ps(c, st, MLMC_KERNEL_PRE, W * cells(n) * words, 0.0);
+            if constexpr (std::is_same<T, double>::value) {
+                if (pre_uses_stream(n)) {
+                    launch_pre_stream(st, c->cfg.mu1, h.a[l], f, u, h.u[l - 1], n, h.Bc, init,
+                                      h.f[l - 1], active);
+                    continue;
+                }
+            }
+            launch_pre_tile<T>(st, c->cfg.mu1, h.a[l], f, u, h.u[l - 1], n, h.Bc, init, h.f[l - 1],
+                               active);
         }
-        lds(1, nullptr, 0);
+        lds_vcycle(active);
         for (int l = Gs + 1; l <= g; ++l) {
             const int n = 2 << l;
-            const double *f = (l == g) ? top_f : h.f[l];
-            double *u = (l == g) ? top_u : h.u[l];
-            ProfScope ps(c, st, MLMC_KERNEL_POST, 8.0 * cells(n) * (3.25 + (f ? 1.0 : 0.0)), 0.0);
-            if (post_uses_stream(n))
-                launch_post_stream(st, c->cfg.mu2, h.a[l], f, u, h.u[l - 1], n, h.Bc, nullptr);
-            else
-                launch_post_tile(st, c->cfg.mu2, h.a[l], f, u, h.u[l - 1], n, h.Bc, nullptr);
+            const T *f = (l == g) ? top_f : h.f[l];
+            T *u = (l == g) ? top_u : h.u[l];
+            ProfScope ps(c, st, MLMC_KERNEL_POST, W * cells(n) * (3.25 + (f ? 1.0 : 0.0)), 0.0);
+            if constexpr (std::is_same<T, double>::value) {
+                if (post_uses_stream(n)) {
+                    launch_post_stream(st, c->cfg.mu2, h.a[l], f, u, h.u[l - 1], n, h.Bc, active);
+                    continue;
+                }
+            }
+            launch_post_tile<T>(st, c->cfg.mu2, h.a[l], f, u, h.u[l - 1], n, h.Bc, active);
         }
     }
 };
 
-bool use_fused(mlmc_ctx c) { return c->cfg.rtol <= 0.0 && fused_supported(c->cfg.mu1, c->cfg.mu2); }
+bool use_fused(mlmc_ctx c) { return fused_supported(c->cfg.mu1, c->cfg.mu2); }
 
-mlmc_status run_fmg_fused(mlmc_ctx c, hipStream_t st, const Hier &h, int k, double *qoi,
+// Fixed mu0 cycles per stage (FP64).
+mlmc_status run_fmg_fixed(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k, double *qoi,
                           StageStats *stats)
 {
-    const int G = h.G, nlev = k + 1;
-    FusedRunner R{c, st, h, std::min(G, kLdsMaxLevel)};
-    R.lds(0, qoi, nlev);                       // FMG stages 0..Gs with their QoIs
+    const int nlev = k + 1;
+    FusedRunner<double> R{c, st, make_hier_t<double>(c, G, Bc), std::min(G, kLdsMaxLevel)};
+    {
+        const int n = 2 << R.Gs;
+        ProfScope ps(c, st, MLMC_KERNEL_LDS, 8.0 * Bc * level_offset(R.Gs + 1) + 8.0 * R.cells(n), 0.0);
+        launch_lds_fmg_fixed(st, c->d_a, c->d_u, Bc, R.Gs, c->cfg.mu0, c->cfg.mu1, c->cfg.mu2,
+                             c->g0, qoi, nlev, c->cfg.qoi_mask);
+    }
     for (int g = R.Gs + 1; g <= G; ++g) {
         const int n = 2 << g;
         for (int cyc = 0; cyc < c->cfg.mu0; ++cyc)
-            R.vcycle(g, h.u[g], cyc == 0 ? 2 : 0, nullptr);
+            R.vcycle(g, R.h.u[g], cyc == 0 ? 2 : 0, nullptr, nullptr);
         if (g >= c->g0) {
             ProfScope ps(c, st, MLMC_KERNEL_QOI, 8.0 * R.cells(n), 0.0);
-            launch_qoi(st, h.u[g], n, h.Bc, qoi, nlev, g - c->g0, c->cfg.qoi_mask);
+            launch_qoi(st, R.h.u[g], n, Bc, qoi, nlev, g - c->g0, c->cfg.qoi_mask);
         }
     }
     if (stats) stats->max_iters = std::max(stats->max_iters, c->cfg.mu0);
+    return MLMC_OK;
+}
+
+// Refinement to rtol with an FP64 residual and V-cycles of type T (double:
+// FP64 path, float: mixed path).  Per stage: u64 = P u64_prev; repeat
+// { r = 1 - A u64 ; stop at rtol or max_iters ; e = V_T(0; r) ; u64 += e }.
+template <typename T>
+mlmc_status run_fmg_refine(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k, double *qoi,
+                           StageStats *stats)
+{
+    const int nlev = k + 1;
+    FusedRunner<T> R{c, st, make_hier_t<T>(c, G, Bc), std::min(G, kLdsMaxLevel)};
+    const auto &h = R.h;
+    {
+        const int n = 2 << R.Gs;
+        ProfScope ps(c, st, MLMC_KERNEL_LDS, R.W * Bc * level_offset(R.Gs + 1) + 8.0 * R.cells(n), 0.0);
+        launch_lds_fmg_refine<T>(st, h.a[0], c->d_w, Bc, R.Gs, c->cfg.mu1, c->cfg.mu2, c->cfg.rtol,
+                                 c->cfg.max_iters, c->g0, qoi, nlev, c->cfg.qoi_mask, c->d_st_iters,
+                                 c->d_st_rho, c->d_st_bad);
+    }
+    for (int g = R.Gs + 1; g <= G; ++g) {
+        const int n = 2 << g;
+        {
+            ProfScope ps(c, st, MLMC_KERNEL_PROLONG, 8.0 * R.cells(n) * 1.25, 0.0);
+            launch_prolong(st, h.w[g - 1], h.w[g], n, Bc, 0, nullptr);
+        }
+        launch_fill_i32(st, c->d_active, Bc, 1);
+        launch_fill_i32(st, c->d_iters, Bc, 0);
+        for (;;) {
+            {
+                ProfScope ps(c, st, MLMC_KERNEL_RESTRICT, R.cells(n) * (R.W + 8.0 + R.W), 0.0);
+                launch_refine_residual<T>(st, h.a[g], h.w[g], n, Bc, h.f[g], c->d_rho, c->d_active,
+                                          c->d_iters, c->cfg.rtol, c->cfg.max_iters);
+            }
+            HIPCHK(c, hipMemcpyAsync(c->h_active, c->d_active, sizeof(int32_t) * Bc,
+                                     hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            int64_t nact = 0;
+            for (int64_t b = 0; b < Bc; ++b) nact += c->h_active[b];
+            if (nact == 0) break;
+            R.vcycle(g, h.u[g], 1, h.f[g], c->d_active);
+            launch_refine_update<T>(st, h.w[g], h.u[g], n, Bc, c->d_active);
+        }
+        launch_refine_stats(st, c->d_iters, c->d_rho, Bc, c->cfg.rtol, c->d_st_iters, c->d_st_rho,
+                            c->d_st_bad);
+        if (g >= c->g0) {
+            ProfScope ps(c, st, MLMC_KERNEL_QOI, 8.0 * R.cells(n), 0.0);
+            launch_qoi(st, h.w[g], n, Bc, qoi, nlev, g - c->g0, c->cfg.qoi_mask);
+        }
+    }
+    if (stats) {
+        HIPCHK(c, hipMemcpyAsync(c->h_iters, c->d_st_iters, sizeof(int32_t) * Bc,
+                                 hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(c->h_rho, c->d_st_rho, sizeof(double) * Bc, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(c->h_active, c->d_st_bad, sizeof(int32_t) * Bc,
+                                 hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        for (int64_t b = 0; b < Bc; ++b) {
+            stats->max_iters = std::max(stats->max_iters, (int)c->h_iters[b]);
+            stats->max_rho = std::max(stats->max_rho, c->h_rho[b]);
+            stats->noconv += c->h_active[b] != 0;
+        }
+    }
     return MLMC_OK;
 }
 
@@ -546,7 +655,10 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     if (c.rtol == 0.0 && c.mu0 < 1) return bad("mu0 must be >= 1 in fixed-cycle mode");
     if (c.rtol > 0.0 && c.max_iters < 1) return bad("max_iters must be >= 1 when rtol > 0");
     if (c.precision != MLMC_FP64 && c.precision != MLMC_MIXED) return bad("unknown precision");
-    if (c.precision == MLMC_MIXED) return bad("MLMC_MIXED is not available in this build");
+    if (c.precision == MLMC_MIXED && !(c.rtol > 0.0))
+        return bad("MLMC_MIXED refines an FP64 residual: it needs rtol > 0");
+    if (c.precision == MLMC_MIXED && !fused_supported(c.mu1, c.mu2))
+        return bad("MLMC_MIXED supports mu1, mu2 in {1, 2}");
     if (c.qoi_mask == 0 || (c.qoi_mask & ~3u)) return bad("qoi_mask must be a non-empty subset of {MEAN, CENTER}");
     if (c.max_batch < 1) return bad("max_batch must be >= 1");
     bool lattice = c.genvec && c.shifts;
@@ -633,15 +745,19 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
         return MLMC_OK;
     }
     // workspace sizes
-    ctx->pool = c.max_batch * ctx->Mmax;
+    ctx->pool = c.max_batch * ctx->Mmax;          // elements per pool
+    ctx->elem = c.precision == MLMC_MIXED ? 4 : 8;
     ctx->chunk_max = std::max<int64_t>(c.max_batch, 65536);
-    if (c.rtol > 0.0) ctx->ecap = c.max_batch * level_cells(Gmax);
+    const bool fused = fused_supported(c.mu1, c.mu2);
+    if (c.rtol > 0.0 && !fused) ctx->ecap = c.max_batch * level_cells(Gmax);
+    const int64_t wcap = (c.rtol > 0.0 && fused) ? ctx->pool : 0;
     int nshift_max = std::max(ctx->cfg.num_shifts, 1);
     ctx->state_tuples = (int64_t)nshift_max * ctx->nq * c.num_levels;
-    size_t need = sizeof(double) * ((size_t)s * ctx->Mmax + 3 * (size_t)ctx->pool + ctx->ecap +
-                                    (size_t)ctx->chunk_max * (s + c.num_levels * ctx->nq + 1) +
+    size_t need = (size_t)ctx->elem * 3 * (size_t)ctx->pool +
+                  sizeof(double) * ((size_t)s * ctx->Mmax + ctx->ecap + wcap +
+                                    (size_t)ctx->chunk_max * (s + c.num_levels * ctx->nq + 2) +
                                     4 * ctx->state_tuples) +
-                  sizeof(int32_t) * 2 * ctx->chunk_max;
+                  sizeof(int32_t) * 4 * ctx->chunk_max;
     size_t free_b = 0, total_b = 0;
     CHK(hipMemGetInfo(&free_b, &total_b));
     if (need > free_b) {
@@ -651,10 +767,20 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
         return fail(MLMC_E_NOMEM);
     }
     CHK(dev_alloc(ctx, &ctx->d_basis, (int64_t)s * ctx->Mmax));
-    CHK(dev_alloc(ctx, &ctx->d_a, ctx->pool));
-    CHK(dev_alloc(ctx, &ctx->d_u, ctx->pool));
-    CHK(dev_alloc(ctx, &ctx->d_f, ctx->pool));
+    {
+        char *pa = nullptr, *pu = nullptr, *pf = nullptr;
+        CHK(dev_alloc(ctx, &pa, ctx->pool * ctx->elem));
+        CHK(dev_alloc(ctx, &pu, ctx->pool * ctx->elem));
+        CHK(dev_alloc(ctx, &pf, ctx->pool * ctx->elem));
+        ctx->d_a = (double *)pa;      // float storage in the mixed mode
+        ctx->d_u = (double *)pu;
+        ctx->d_f = (double *)pf;
+    }
     CHK(dev_alloc(ctx, &ctx->d_e, ctx->ecap));
+    CHK(dev_alloc(ctx, &ctx->d_w, wcap));
+    CHK(dev_alloc(ctx, &ctx->d_st_iters, ctx->chunk_max));
+    CHK(dev_alloc(ctx, &ctx->d_st_bad, ctx->chunk_max));
+    CHK(dev_alloc(ctx, &ctx->d_st_rho, ctx->chunk_max));
     CHK(dev_alloc(ctx, &ctx->d_y, ctx->chunk_max * s));
     CHK(dev_alloc(ctx, &ctx->d_qoi, ctx->chunk_max * c.num_levels * ctx->nq));
     CHK(dev_alloc(ctx, &ctx->d_state, 4 * ctx->state_tuples));
@@ -795,8 +921,9 @@ mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts, const double *z
     for (int64_t b0 = 0; b0 < B; b0 += cap) {
         const int64_t Bc = std::min(cap, B - b0);
         Hier h = make_hier(ctx, G, Bc);
+        const bool mixed = ctx->cfg.precision == MLMC_MIXED;
         if (z_dev) {
-            launch_exp_to_levels(s, z_dev + b0 * M, M, Bc, ctx->d_a);
+            launch_exp_to_levels(s, z_dev + b0 * M, M, Bc, ctx->d_a, mixed);
         } else {
             const double *Y;
             {
@@ -806,11 +933,18 @@ mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts, const double *z
             const double sd = ctx->cfg.s;
             ProfScope ps(ctx, s, MLMC_KERNEL_FIELD, 8.0 * (Bc * sd + sd * M + (double)Bc * M),
                          2.0 * Bc * sd * M);
-            launch_field_gemm(s, Y, ctx->cfg.s, ctx->d_basis, ctx->Mmax, M, Bc, ctx->d_a, 1);
+            launch_field_gemm(s, Y, ctx->cfg.s, ctx->d_basis, ctx->Mmax, M, Bc, ctx->d_a,
+                              mixed ? 2 : 1);
         }
         double *q = qoi_dev ? qoi_dev + b0 * nlev * nq : ctx->d_qoi;
-        st = use_fused(ctx) ? run_fmg_fused(ctx, s, h, k, q, &stats)
-                            : run_fmg(ctx, s, h, k, q, nullptr, &stats);
+        if (!use_fused(ctx))
+            st = run_fmg(ctx, s, h, k, q, nullptr, &stats);
+        else if (ctx->cfg.rtol <= 0.0)
+            st = run_fmg_fixed(ctx, s, G, Bc, k, q, &stats);
+        else if (mixed)
+            st = run_fmg_refine<float>(ctx, s, G, Bc, k, q, &stats);
+        else
+            st = run_fmg_refine<double>(ctx, s, G, Bc, k, q, &stats);
         if (st) return st;
         if (sums_dev) {
             ProfScope ps(ctx, s, MLMC_KERNEL_SUMS, 8.0 * Bc * nlev * nq, 0.0);

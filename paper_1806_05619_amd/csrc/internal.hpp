@@ -38,10 +38,12 @@ void launch_build_basis(hipStream_t st, const double *psi, const int64_t *psi_of
                         const int32_t *mi, const int32_t *mj, const double *coef, int s,
                         int G, double *basis, int64_t ld);
 // z = Y basis (first M columns); mode 0 writes z to out[b*M + m];
-// mode 1 writes exp(z) into the level-major chunk pool `out` (Bc samples).
+// mode 1 writes exp(z) into the level-major chunk pool `out` (Bc samples);
+// mode 2 the same as float.
 void launch_field_gemm(hipStream_t st, const double *Y, int s, const double *basis, int64_t ld,
-                       int64_t M, int64_t Bc, double *out, int mode);
-void launch_exp_to_levels(hipStream_t st, const double *z, int64_t M, int64_t Bc, double *pool);
+                       int64_t M, int64_t Bc, void *out, int mode);
+void launch_exp_to_levels(hipStream_t st, const double *z, int64_t M, int64_t Bc, void *pool,
+                          bool to_float);
 
 void launch_coarse_solve(hipStream_t st, const double *a, const double *f, double *u, int64_t Bc,
                          const int32_t *active);
@@ -66,20 +68,41 @@ void launch_residual_norm(hipStream_t st, const double *a, const double *u, int 
 void launch_axpy_active(hipStream_t st, double *u, const double *e, int n, int64_t Bc,
                         const int32_t *active);
 
-// ---- fused kernels (kernels_fused.hip) ----
+// ---- fused kernels (kernels_fused.hip), T = double or float ----
 bool fused_supported(int mu1, int mu2);
 // pre pass on level n: init 0 read u, 1 zero guess, 2 u = P uc; writes u and fc
-void launch_pre_tile(hipStream_t st, int mu1, const double *a, const double *f, double *u,
-                     const double *uc, int n, int64_t Bc, int init, double *fc,
-                     const int32_t *active);
+template <typename T>
+void launch_pre_tile(hipStream_t st, int mu1, const T *a, const T *f, T *u, const T *uc, int n,
+                     int64_t Bc, int init, T *fc, const int32_t *active);
 // post pass on level n: u += P ec, then mu2 sweeps
-void launch_post_tile(hipStream_t st, int mu2, const double *a, const double *f, double *u,
-                      const double *ec, int n, int64_t Bc, const int32_t *active);
-// LDS-resident hierarchy: mode 0 FMG stages 0..G with QoI, mode 1 one V-cycle
-// at level G (zero guess, f from the f pool) -> correction in the u pool
-void launch_lds_mg(hipStream_t st, const double *a_pool, const double *f_pool, double *u_pool,
-                   int64_t Bc, int G, int mode, int mu0, int mu1, int mu2, int g0, double *qoi,
-                   int nlev, uint32_t mask, const int32_t *active);
+template <typename T>
+void launch_post_tile(hipStream_t st, int mu2, const T *a, const T *f, T *u, const T *ec, int n,
+                      int64_t Bc, const int32_t *active);
+// LDS-resident hierarchy <= 32^2, one workgroup per sample:
+// FP64 FMG stages 0..G with fixed cycles and QoI, final u of level G to the pool
+void launch_lds_fmg_fixed(hipStream_t st, const double *a_pool, double *u_pool, int64_t Bc, int G,
+                          int mu0, int mu1, int mu2, int g0, double *qoi, int nlev, uint32_t mask);
+// one V-cycle at level G, zero guess, f from the f pool -> correction in the u pool
+template <typename T>
+void launch_lds_vcycle(hipStream_t st, const T *a_pool, const T *f_pool, T *u_pool, int64_t Bc,
+                       int G, int mu1, int mu2, const int32_t *active);
+// FMG stages 0..G with FP64-residual refinement of T V-cycles; u64 of level G
+// to u64_pool; per-sample statistics
+template <typename T>
+void launch_lds_fmg_refine(hipStream_t st, const T *a_pool, double *u64_pool, int64_t Bc, int G,
+                           int mu1, int mu2, double rtol, int max_iters, int g0, double *qoi,
+                           int nlev, uint32_t mask, int32_t *st_iters, double *st_rho,
+                           int32_t *st_bad);
+// refinement on a large grid: FP64 residual -> f (T), norms and flags; u64 += e
+template <typename T>
+void launch_refine_residual(hipStream_t st, const T *a, const double *u, int n, int64_t Bc, T *f,
+                            double *rho, int32_t *active, int32_t *iters, double rtol,
+                            int max_iters);
+template <typename T>
+void launch_refine_update(hipStream_t st, double *u, const T *e, int n, int64_t Bc,
+                          const int32_t *active);
+void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho, int64_t Bc,
+                         double rtol, int32_t *st_iters, double *st_rho, int32_t *st_bad);
 
 // ---- row-streaming passes (kernels_stream.hip), one workgroup per sample ----
 bool stream_supported(int n);

@@ -139,7 +139,7 @@ __device__ __forceinline__ int64_t level_major_index(int64_t m, int64_t b, int64
 __global__ __launch_bounds__(256) void k_field_gemm(const double *__restrict__ Y, int s,
                                                     const double *__restrict__ basis, int64_t ld,
                                                     int64_t M, int64_t Bc,
-                                                    double *__restrict__ out, int mode)
+                                                    void *__restrict__ out, int mode)
 {
     __shared__ double As[GK][GM + 1];
     __shared__ double Bs[GK][GN];
@@ -186,21 +186,26 @@ __global__ __launch_bounds__(256) void k_field_gemm(const double *__restrict__ Y
             if (m >= M)
                 continue;
             if (mode == 0)
-                out[b * M + m] = acc[i][j];
+                ((double *)out)[b * M + m] = acc[i][j];
+            else if (mode == 1)
+                ((double *)out)[level_major_index(m, b, Bc)] = exp(acc[i][j]);
             else
-                out[level_major_index(m, b, Bc)] = exp(acc[i][j]);
+                ((float *)out)[level_major_index(m, b, Bc)] = (float)exp(acc[i][j]);
         }
     }
 }
 
 __global__ void k_exp_to_levels(const double *__restrict__ z, int64_t M, int64_t Bc,
-                                double *__restrict__ pool)
+                                void *__restrict__ pool, int to_float)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= M * Bc)
         return;
     int64_t b = t / M, m = t - b * M;
-    pool[level_major_index(m, b, Bc)] = exp(z[t]);
+    if (to_float)
+        ((float *)pool)[level_major_index(m, b, Bc)] = (float)exp(z[t]);
+    else
+        ((double *)pool)[level_major_index(m, b, Bc)] = exp(z[t]);
 }
 
 // ---------------------------------------------------------------------------
@@ -519,16 +524,17 @@ void launch_build_basis(hipStream_t st, const double *psi, const int64_t *psi_of
 }
 
 void launch_field_gemm(hipStream_t st, const double *Y, int s, const double *basis, int64_t ld,
-                       int64_t M, int64_t Bc, double *out, int mode)
+                       int64_t M, int64_t Bc, void *out, int mode)
 {
     dim3 grid((unsigned)((M + GN - 1) / GN), (unsigned)((Bc + GM - 1) / GM));
     hipLaunchKernelGGL(k_field_gemm, grid, dim3(256), 0, st, Y, s, basis, ld, M, Bc, out, mode);
 }
 
-void launch_exp_to_levels(hipStream_t st, const double *z, int64_t M, int64_t Bc, double *pool)
+void launch_exp_to_levels(hipStream_t st, const double *z, int64_t M, int64_t Bc, void *pool,
+                          bool to_float)
 {
     hipLaunchKernelGGL(k_exp_to_levels, dim3(blocks_for(M * Bc)), dim3(kBlock), 0, st, z, M, Bc,
-                       pool);
+                       pool, (int)to_float);
 }
 
 void launch_coarse_solve(hipStream_t st, const double *a, const double *f, double *u, int64_t Bc,

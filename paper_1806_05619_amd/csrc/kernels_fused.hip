@@ -1,8 +1,9 @@
 // Fused multigrid kernels for gfx950 (Section 4: correction scheme, V-cycle,
-// full multigrid), FP64.
+// full multigrid), templated on the value type T of the V-cycle (double for
+// the FP64 path, float for the FP32 V-cycles of the mixed-precision path).
 //
 // Large grids (n >= 64): temporally blocked tile passes.  One workgroup owns a
-// T x T tile of one sample and stages the tile plus a halo of u and a in LDS:
+// 32 x 32 tile of one sample and stages the tile plus a halo of u and a in LDS:
 //   pre pass  : mu1 red-black sweeps (red first), residual, 4-cell restriction
 //               -> writes u (tile) and the coarse right-hand side;
 //   post pass : bilinear prolongation of the coarse correction, mu2 sweeps
@@ -13,11 +14,15 @@
 // updates are computed once and kept in registers for all half-sweeps.
 //
 // Small grids (n <= 32): one workgroup per sample keeps the whole hierarchy
-// 2^2 .. n^2 in LDS and runs the FMG stages (or one V-cycle) without leaving
-// the CU.
+// 2^2 .. n^2 in LDS and runs the FMG stages (fixed cycles, or refinement to a
+// residual tolerance with an FP64 residual), or one V-cycle.
 //
-// Block ids are remapped so that consecutive tiles of a sample run on the
-// same XCD (the dispatcher deals blocks round-robin over the 8 XCDs), which
+// Refinement kernels: FP64 residual of the top grid from the stored
+// coefficient (T) and the FP64 iterate, with per-sample norms and the
+// convergence flags of the loop; u64 += e.
+//
+// Block ids of tile passes are remapped so that consecutive tiles of a sample
+// run on the same XCD (blocks are dealt round-robin over the 8 XCDs), which
 // keeps the overlapping halos in that XCD's L2.
 #include "internal.hpp"
 
@@ -28,9 +33,8 @@ constexpr int TILE = 32;
 constexpr int NT = 256;                 // threads per tile workgroup
 
 // 1/x for the well-scaled positive values of this path (coefficients within
-// e^+-15, diagonals of their sums): hardware reciprocal estimate refined by two
-// Newton steps, accurate to about one ulp without the special-case handling of
-// IEEE division.
+// e^+-15 and sums of them): hardware reciprocal estimate refined by Newton
+// steps, about one ulp, without the special-case handling of IEEE division.
 __device__ __forceinline__ double frcp(double x)
 {
     double y = __builtin_amdgcn_rcp(x);
@@ -39,9 +43,16 @@ __device__ __forceinline__ double frcp(double x)
     e = fma(-x, y, 1.0);
     return fma(y, e, y);
 }
+__device__ __forceinline__ float frcp(float x)
+{
+    float y = __builtin_amdgcn_rcpf(x);
+    float e = fmaf(-x, y, 1.0f);
+    return fmaf(y, e, y);
+}
 
 // harmonic face weight 2 a_P a_N / (a_P + a_N)
-__device__ __forceinline__ double hm(double ap, double an) { return 2.0 * ap * an * frcp(ap + an); }
+template <typename T>
+__device__ __forceinline__ T hm(T ap, T an) { return T(2) * ap * an * frcp(ap + an); }
 
 __device__ __forceinline__ int xcd_remap(int bid, int nb)
 {
@@ -50,9 +61,10 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb)
 }
 
 // value of the coarse grid e (nc x nc) at coarse index (I, J), odd reflection
-__device__ __forceinline__ double codd(const double *__restrict__ e, int nc, int I, int J)
+template <typename T>
+__device__ __forceinline__ T codd(const T *__restrict__ e, int nc, int I, int J)
 {
-    double sg = 1.0;
+    T sg = T(1);
     if (I < 0) { I = 0; sg = -sg; }
     if (I >= nc) { I = nc - 1; sg = -sg; }
     if (J < 0) { J = 0; sg = -sg; }
@@ -60,67 +72,59 @@ __device__ __forceinline__ double codd(const double *__restrict__ e, int nc, int
     return sg * e[I + nc * J];
 }
 
-// bilinear (9,3,3,1)/16 value of P e at fine cell (i, j)
-__device__ __forceinline__ double prolong_at(const double *__restrict__ e, int nc, int i, int j)
-{
-    const int I = i >> 1, J = j >> 1;
-    const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1;
-    return (9.0 * codd(e, nc, I, J) + 3.0 * codd(e, nc, I + sx, J) + 3.0 * codd(e, nc, I, J + sy) +
-            codd(e, nc, I + sx, J + sy)) / 16.0;
-}
-
 // Coarse values needed to prolongate onto a fine region [fi0, fi0+S)^2, staged
 // in LDS with the odd wall reflection already applied (indices -1 and nc).
-template <int S>
+template <int S, typename T>
 struct CoarseStage {
     static constexpr int CS = S / 2 + 3;
-    __device__ static void load(double *cs, const double *__restrict__ e, int nc, int cI0, int cJ0)
+    __device__ static void load(T *cs, const T *__restrict__ e, int nc, int cI0, int cJ0)
     {
         for (int q = threadIdx.x; q < CS * CS; q += NT) {
             const int cj = q / CS, ci = q - cj * CS;
             const int I = cI0 + ci, J = cJ0 + cj;
-            cs[q] = (I >= -1 && I <= nc && J >= -1 && J <= nc) ? codd(e, nc, I, J) : 0.0;
+            cs[q] = (I >= -1 && I <= nc && J >= -1 && J <= nc) ? codd(e, nc, I, J) : T(0);
         }
     }
-    // P e at in-domain fine cell (gi, gj)
-    __device__ static double at(const double *cs, int cI0, int cJ0, int gi, int gj)
+    // P e at in-domain fine cell (gi, gj): (9, 3, 3, 1) / 16
+    __device__ static T at(const T *cs, int cI0, int cJ0, int gi, int gj)
     {
         const int I = (gi >> 1) - cI0, J = (gj >> 1) - cJ0;
         const int sx = (gi & 1) ? 1 : -1, sy = (gj & 1) ? CS : -CS;
         const int q = I + CS * J;
-        return (9.0 * cs[q] + 3.0 * cs[q + sx] + 3.0 * cs[q + sy] + cs[q + sx + sy]) / 16.0;
+        return (T(9) * cs[q] + T(3) * cs[q + sx] + T(3) * cs[q + sy] + cs[q + sx + sy]) / T(16);
     }
 };
 
 // Per-cell stencil kept in registers.
+template <typename T>
 struct Cell {
     int l;                        // LDS index li + S*lj, -1 if not owned / outside
-    double wE, wW, wN, wS, d, inv, rhs;   // d = sum of face weights, rhs = h^2 f
+    T wE, wW, wN, wS, d, inv, rhs;   // d = sum of face weights, rhs = h^2 f
 };
 
-template <int S>
-__device__ __forceinline__ void make_cell(Cell &c, const double *a_s, int li, int lj, int gi, int gj,
-                                          int n, double rhs)
+template <int S, typename T>
+__device__ __forceinline__ void make_cell(Cell<T> &c, const T *a_s, int li, int lj, int gi, int gj,
+                                          int n, T rhs)
 {
     const int l = li + S * lj;
-    const double ap = a_s[l];
-    double d = 0.0;
-    c.wE = c.wW = c.wN = c.wS = 0.0;
-    if (gi + 1 < n) { c.wE = hm(ap, a_s[l + 1]); d += c.wE; } else d += 2.0 * ap;
-    if (gi > 0)     { c.wW = hm(ap, a_s[l - 1]); d += c.wW; } else d += 2.0 * ap;
-    if (gj + 1 < n) { c.wN = hm(ap, a_s[l + S]); d += c.wN; } else d += 2.0 * ap;
-    if (gj > 0)     { c.wS = hm(ap, a_s[l - S]); d += c.wS; } else d += 2.0 * ap;
+    const T ap = a_s[l];
+    T d = T(0);
+    c.wE = c.wW = c.wN = c.wS = T(0);
+    if (gi + 1 < n) { c.wE = hm(ap, a_s[l + 1]); d += c.wE; } else d += T(2) * ap;
+    if (gi > 0)     { c.wW = hm(ap, a_s[l - 1]); d += c.wW; } else d += T(2) * ap;
+    if (gj + 1 < n) { c.wN = hm(ap, a_s[l + S]); d += c.wN; } else d += T(2) * ap;
+    if (gj > 0)     { c.wS = hm(ap, a_s[l - S]); d += c.wS; } else d += T(2) * ap;
     c.d = d;
     c.inv = frcp(d);
     c.rhs = rhs;
     c.l = l;
 }
 
-template <int S>
-__device__ __forceinline__ void relax(const Cell &c, double *u_s)
+template <int S, typename T>
+__device__ __forceinline__ void relax(const Cell<T> &c, T *u_s)
 {
     const int l = c.l;
-    double num = c.rhs;
+    T num = c.rhs;
     num += c.wE * u_s[l + 1];
     num += c.wW * u_s[l - 1];
     num += c.wN * u_s[l + S];
@@ -146,60 +150,28 @@ struct OwnSet {
     }
 };
 
-// ---------------------------------------------------------------------------
-// Pre pass: mu1 red-black sweeps + residual + restriction on one tile.
-// init: 0 = read u, 1 = zero initial guess, 2 = FMG interpolation from uc.
-template <int MU>
-__global__ __launch_bounds__(NT) void k_pre_tile(const double *__restrict__ a,
-                                                 const double *__restrict__ f, double *__restrict__ u,
-                                                 const double *__restrict__ uc, int n, int64_t Bc,
-                                                 int init, double *__restrict__ fc,
-                                                 const int32_t *__restrict__ active)
+// Region loads: all global loads first (memory-level parallelism), then LDS.
+// mode 0: u = u; 1: u = 0; 2: u = P(coarse); 3: u = u + P(coarse)
+template <int S, int H, typename T>
+__device__ __forceinline__ void load_region(T *a_s, T *u_s, const T *c_s, const T *ab, const T *ub,
+                                            int n, int i0, int j0, int cI0, int cJ0, int mode)
 {
-    constexpr int H = 2 * MU + 1;
-    constexpr int S = TILE + 2 * H;
-    using Red = OwnSet<S, 1, 0>;              // red cells are updated within ring H-1
-    using Blk = OwnSet<S, 2, 1>;              // black cells within ring H-2
-    using CSt = CoarseStage<S>;
-    __shared__ double u_s[S * S];
-    __shared__ double a_s[S * S];
-    __shared__ double c_s[CSt::CS * CSt::CS];
-
-    const int tiles_side = n / TILE;
-    const int tps = tiles_side * tiles_side;
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t b = L / tps;
-    if (b >= Bc) return;
-    if (active && !active[b]) return;
-    const int tile = L - (int)(b * tps);
-    const int i0 = (tile % tiles_side) * TILE, j0 = (tile / tiles_side) * TILE;
-    const int64_t cells = (int64_t)n * n;
-    const double *ab = a + b * cells;
-    double *ub = u + b * cells;
-    const double *fb = f ? f + b * cells : nullptr;
-    const int nc = n / 2;
-    const double h2 = 1.0 / ((double)n * (double)n);
-    const int cI0 = i0 / 2 - (H + 1) / 2 - 1, cJ0 = j0 / 2 - (H + 1) / 2 - 1;
-    if (init == 2) {
-        CSt::load(c_s, uc + b * (int64_t)nc * nc, nc, cI0, cJ0);
-        __syncthreads();
-    }
-
-    // all global loads of the region first (memory-level parallelism), then LDS
+    using CSt = CoarseStage<S, T>;
     constexpr int PERT = (S * S + NT - 1) / NT;
-    double av[PERT], uv[PERT];
+    T av[PERT], uv[PERT];
 #pragma unroll
     for (int k = 0; k < PERT; ++k) {
         const int e = threadIdx.x + NT * k;
         const int lj = e / S, li = e - lj * S;
         const int gi = i0 - H + li, gj = j0 - H + lj;
-        av[k] = 0.0;
-        uv[k] = 0.0;
+        av[k] = T(0);
+        uv[k] = T(0);
         if (e < S * S && gi >= 0 && gi < n && gj >= 0 && gj < n) {
             const int64_t p = gi + (int64_t)n * gj;
             av[k] = ab[p];
-            if (init == 0) uv[k] = ub[p];
-            else if (init == 2) uv[k] = CSt::at(c_s, cI0, cJ0, gi, gj);
+            if (mode == 0) uv[k] = ub[p];
+            else if (mode == 2) uv[k] = CSt::at(c_s, cI0, cJ0, gi, gj);
+            else if (mode == 3) uv[k] = ub[p] + CSt::at(c_s, cI0, cJ0, gi, gj);
         }
     }
 #pragma unroll
@@ -211,62 +183,95 @@ __global__ __launch_bounds__(NT) void k_pre_tile(const double *__restrict__ a,
         }
     }
     __syncthreads();
+}
 
-    Cell red[Red::PER], blk[Blk::PER];
+template <int S, int LO, int COLOUR, typename T>
+__device__ __forceinline__ void make_cells(Cell<T> *cs, const T *a_s, const T *fb, int n, int i0,
+                                           int j0, int H, T h2)
+{
+    using Own = OwnSet<S, LO, COLOUR>;
 #pragma unroll
-    for (int k = 0; k < Red::PER; ++k) {
+    for (int k = 0; k < Own::PER; ++k) {
         const int q = threadIdx.x + NT * k;
-        red[k].l = -1;
-        if (q < Red::COUNT) {
+        cs[k].l = -1;
+        if (q < Own::COUNT) {
             int li, lj;
-            Red::coords(q, li, lj);
+            Own::coords(q, li, lj);
             const int gi = i0 - H + li, gj = j0 - H + lj;
             if (gi >= 0 && gi < n && gj >= 0 && gj < n)
-                make_cell<S>(red[k], a_s, li, lj, gi, gj, n, h2 * (fb ? fb[gi + (int64_t)n * gj] : 1.0));
+                make_cell<S>(cs[k], a_s, li, lj, gi, gj, n, h2 * (fb ? fb[gi + (int64_t)n * gj] : T(1)));
         }
     }
+}
+
+template <int S, int PER, typename T>
+__device__ __forceinline__ void sweep_ring(const Cell<T> *cs, T *u_s, int lo, int hi)
+{
 #pragma unroll
-    for (int k = 0; k < Blk::PER; ++k) {
-        const int q = threadIdx.x + NT * k;
-        blk[k].l = -1;
-        if (q < Blk::COUNT) {
-            int li, lj;
-            Blk::coords(q, li, lj);
-            const int gi = i0 - H + li, gj = j0 - H + lj;
-            if (gi >= 0 && gi < n && gj >= 0 && gj < n)
-                make_cell<S>(blk[k], a_s, li, lj, gi, gj, n, h2 * (fb ? fb[gi + (int64_t)n * gj] : 1.0));
-        }
+    for (int k = 0; k < PER; ++k) {
+        const int l = cs[k].l;
+        if (l < 0) continue;
+        const int lj = l / S, li = l - lj * S;
+        if (li >= lo && li < hi && lj >= lo && lj < hi) relax<S>(cs[k], u_s);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Pre pass: mu1 red-black sweeps + residual + restriction on one tile.
+// init: 0 = read u, 1 = zero initial guess, 2 = FMG interpolation from uc.
+template <int MU, typename T>
+__global__ __launch_bounds__(NT) void k_pre_tile(const T *__restrict__ a, const T *__restrict__ f,
+                                                 T *__restrict__ u, const T *__restrict__ uc, int n,
+                                                 int64_t Bc, int init, T *__restrict__ fc,
+                                                 const int32_t *__restrict__ active)
+{
+    constexpr int H = 2 * MU + 1;
+    constexpr int S = TILE + 2 * H;
+    using Red = OwnSet<S, 1, 0>;              // red cells are updated within ring H-1
+    using Blk = OwnSet<S, 2, 1>;              // black cells within ring H-2
+    using CSt = CoarseStage<S, T>;
+    __shared__ T u_s[S * S];
+    __shared__ T a_s[S * S];
+    __shared__ T c_s[CSt::CS * CSt::CS];
+
+    const int tiles_side = n / TILE;
+    const int tps = tiles_side * tiles_side;
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t b = L / tps;
+    if (b >= Bc) return;
+    if (active && !active[b]) return;
+    const int tile = L - (int)(b * tps);
+    const int i0 = (tile % tiles_side) * TILE, j0 = (tile / tiles_side) * TILE;
+    const int64_t cells = (int64_t)n * n;
+    const T *ab = a + b * cells;
+    T *ub = u + b * cells;
+    const T *fb = f ? f + b * cells : nullptr;
+    const int nc = n / 2;
+    const T h2 = T(1) / (T(n) * T(n));
+    const int cI0 = i0 / 2 - (H + 1) / 2 - 1, cJ0 = j0 / 2 - (H + 1) / 2 - 1;
+    if (init == 2) {
+        CSt::load(c_s, uc + b * (int64_t)nc * nc, nc, cI0, cJ0);
+        __syncthreads();
+    }
+    load_region<S, H>(a_s, u_s, c_s, ab, ub, n, i0, j0, cI0, cJ0, init);
+
+    Cell<T> red[Red::PER], blk[Blk::PER];
+    make_cells<S, 1, 0>(red, a_s, fb, n, i0, j0, H, h2);
+    make_cells<S, 2, 1>(blk, a_s, fb, n, i0, j0, H, h2);
     // half-sweep t (1-based) covers ring H - t around the tile
 #pragma unroll
     for (int t = 1; t <= 2 * MU; ++t) {
-        const int lo = t, hi = S - t;          // region index range [lo, hi)
-        if (t & 1) {
-#pragma unroll
-            for (int k = 0; k < Red::PER; ++k) {
-                const int l = red[k].l;
-                if (l < 0) continue;
-                const int lj = l / S, li = l - lj * S;
-                if (li >= lo && li < hi && lj >= lo && lj < hi) relax<S>(red[k], u_s);
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < Blk::PER; ++k) {
-                const int l = blk[k].l;
-                if (l < 0) continue;
-                const int lj = l / S, li = l - lj * S;
-                if (li >= lo && li < hi && lj >= lo && lj < hi) relax<S>(blk[k], u_s);
-            }
-        }
+        if (t & 1) sweep_ring<S, Red::PER>(red, u_s, t, S - t);
+        else sweep_ring<S, Blk::PER>(blk, u_s, t, S - t);
         __syncthreads();
     }
     // residual r = f - A u on the tile, into a_s (a is no longer read)
-    const double inv_h2 = (double)n * (double)n;
-    auto resid = [&](const Cell &c) {
+    const T inv_h2 = T(n) * T(n);
+    auto resid = [&](const Cell<T> &c) {
         const int l = c.l;
         const int lj = l / S, li = l - lj * S;
         if (li < H || li >= H + TILE || lj < H || lj >= H + TILE) return;
-        double off = c.wE * u_s[l + 1];
+        T off = c.wE * u_s[l + 1];
         off += c.wW * u_s[l - 1];
         off += c.wN * u_s[l + S];
         off += c.wS * u_s[l - S];
@@ -281,37 +286,33 @@ __global__ __launch_bounds__(NT) void k_pre_tile(const double *__restrict__ a,
         if (blk[k].l >= 0) resid(blk[k]);
     __syncthreads();
     // restriction (mean of the 4 children) and write-back of the tile
-    {
-        constexpr int CT = TILE / 2;
-        for (int e = threadIdx.x; e < CT * CT; e += NT) {
-            const int J = e / CT, I = e - J * CT;
-            const int l = (H + 2 * I) + S * (H + 2 * J);
-            const double v = 0.25 * (a_s[l] + a_s[l + 1] + a_s[l + S] + a_s[l + S + 1]);
-            fc[b * (int64_t)nc * nc + (i0 / 2 + I) + (int64_t)nc * (j0 / 2 + J)] = v;
-        }
-        for (int e = threadIdx.x; e < TILE * TILE; e += NT) {
-            const int lj = e / TILE, li = e - lj * TILE;
-            ub[(i0 + li) + (int64_t)n * (j0 + lj)] = u_s[(H + li) + S * (H + lj)];
-        }
+    constexpr int CT = TILE / 2;
+    for (int e = threadIdx.x; e < CT * CT; e += NT) {
+        const int J = e / CT, I = e - J * CT;
+        const int l = (H + 2 * I) + S * (H + 2 * J);
+        const T v = T(0.25) * (a_s[l] + a_s[l + 1] + a_s[l + S] + a_s[l + S + 1]);
+        fc[b * (int64_t)nc * nc + (i0 / 2 + I) + (int64_t)nc * (j0 / 2 + J)] = v;
+    }
+    for (int e = threadIdx.x; e < TILE * TILE; e += NT) {
+        const int lj = e / TILE, li = e - lj * TILE;
+        ub[(i0 + li) + (int64_t)n * (j0 + lj)] = u_s[(H + li) + S * (H + lj)];
     }
 }
 
 // Post pass: u += P ec on the tile and its halo, then mu2 sweeps black first.
-template <int MU>
-__global__ __launch_bounds__(NT) void k_post_tile(const double *__restrict__ a,
-                                                  const double *__restrict__ f,
-                                                  double *__restrict__ u,
-                                                  const double *__restrict__ ec, int n, int64_t Bc,
-                                                  const int32_t *__restrict__ active)
+template <int MU, typename T>
+__global__ __launch_bounds__(NT) void k_post_tile(const T *__restrict__ a, const T *__restrict__ f,
+                                                  T *__restrict__ u, const T *__restrict__ ec, int n,
+                                                  int64_t Bc, const int32_t *__restrict__ active)
 {
     constexpr int H = 2 * MU;
     constexpr int S = TILE + 2 * H;
     using Blk = OwnSet<S, 1, 1>;              // first half-sweep (black): ring H-1
     using Red = OwnSet<S, 2, 0>;              // second (red): ring H-2
-    using CSt = CoarseStage<S>;
-    __shared__ double u_s[S * S];
-    __shared__ double a_s[S * S];
-    __shared__ double c_s[CSt::CS * CSt::CS];
+    using CSt = CoarseStage<S, T>;
+    __shared__ T u_s[S * S];
+    __shared__ T a_s[S * S];
+    __shared__ T c_s[CSt::CS * CSt::CS];
 
     const int tiles_side = n / TILE;
     const int tps = tiles_side * tiles_side;
@@ -322,85 +323,23 @@ __global__ __launch_bounds__(NT) void k_post_tile(const double *__restrict__ a,
     const int tile = L - (int)(b * tps);
     const int i0 = (tile % tiles_side) * TILE, j0 = (tile / tiles_side) * TILE;
     const int64_t cells = (int64_t)n * n;
-    const double *ab = a + b * cells;
-    double *ub = u + b * cells;
-    const double *fb = f ? f + b * cells : nullptr;
+    const T *ab = a + b * cells;
+    T *ub = u + b * cells;
+    const T *fb = f ? f + b * cells : nullptr;
     const int nc = n / 2;
-    const double h2 = 1.0 / ((double)n * (double)n);
+    const T h2 = T(1) / (T(n) * T(n));
     const int cI0 = i0 / 2 - (H + 1) / 2 - 1, cJ0 = j0 / 2 - (H + 1) / 2 - 1;
     CSt::load(c_s, ec + b * (int64_t)nc * nc, nc, cI0, cJ0);
     __syncthreads();
+    load_region<S, H>(a_s, u_s, c_s, ab, ub, n, i0, j0, cI0, cJ0, 3);
 
-    constexpr int PERT = (S * S + NT - 1) / NT;
-    double av[PERT], uv[PERT];
-#pragma unroll
-    for (int k = 0; k < PERT; ++k) {
-        const int e = threadIdx.x + NT * k;
-        const int lj = e / S, li = e - lj * S;
-        const int gi = i0 - H + li, gj = j0 - H + lj;
-        av[k] = 0.0;
-        uv[k] = 0.0;
-        if (e < S * S && gi >= 0 && gi < n && gj >= 0 && gj < n) {
-            const int64_t p = gi + (int64_t)n * gj;
-            av[k] = ab[p];
-            uv[k] = ub[p] + CSt::at(c_s, cI0, cJ0, gi, gj);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < PERT; ++k) {
-        const int e = threadIdx.x + NT * k;
-        if (e < S * S) {
-            a_s[e] = av[k];
-            u_s[e] = uv[k];
-        }
-    }
-    __syncthreads();
-
-    Cell blk[Blk::PER], red[Red::PER];
-#pragma unroll
-    for (int k = 0; k < Blk::PER; ++k) {
-        const int q = threadIdx.x + NT * k;
-        blk[k].l = -1;
-        if (q < Blk::COUNT) {
-            int li, lj;
-            Blk::coords(q, li, lj);
-            const int gi = i0 - H + li, gj = j0 - H + lj;
-            if (gi >= 0 && gi < n && gj >= 0 && gj < n)
-                make_cell<S>(blk[k], a_s, li, lj, gi, gj, n, h2 * (fb ? fb[gi + (int64_t)n * gj] : 1.0));
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < Red::PER; ++k) {
-        const int q = threadIdx.x + NT * k;
-        red[k].l = -1;
-        if (q < Red::COUNT) {
-            int li, lj;
-            Red::coords(q, li, lj);
-            const int gi = i0 - H + li, gj = j0 - H + lj;
-            if (gi >= 0 && gi < n && gj >= 0 && gj < n)
-                make_cell<S>(red[k], a_s, li, lj, gi, gj, n, h2 * (fb ? fb[gi + (int64_t)n * gj] : 1.0));
-        }
-    }
+    Cell<T> blk[Blk::PER], red[Red::PER];
+    make_cells<S, 1, 1>(blk, a_s, fb, n, i0, j0, H, h2);
+    make_cells<S, 2, 0>(red, a_s, fb, n, i0, j0, H, h2);
 #pragma unroll
     for (int t = 1; t <= 2 * MU; ++t) {
-        const int lo = t, hi = S - t;
-        if (t & 1) {
-#pragma unroll
-            for (int k = 0; k < Blk::PER; ++k) {
-                const int l = blk[k].l;
-                if (l < 0) continue;
-                const int lj = l / S, li = l - lj * S;
-                if (li >= lo && li < hi && lj >= lo && lj < hi) relax<S>(blk[k], u_s);
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < Red::PER; ++k) {
-                const int l = red[k].l;
-                if (l < 0) continue;
-                const int lj = l / S, li = l - lj * S;
-                if (li >= lo && li < hi && lj >= lo && lj < hi) relax<S>(red[k], u_s);
-            }
-        }
+        if (t & 1) sweep_ring<S, Blk::PER>(blk, u_s, t, S - t);
+        else sweep_ring<S, Red::PER>(red, u_s, t, S - t);
         __syncthreads();
     }
     for (int e = threadIdx.x; e < TILE * TILE; e += NT) {
@@ -419,35 +358,39 @@ struct LdsHier {
     static __device__ constexpr int off(int g) { return (int)(4 * ((1LL << (2 * g)) - 1) / 3); }
 };
 
-__device__ __forceinline__ void lds_stencil(const double *a, int n, int i, int j, double &wE,
-                                            double &wW, double &wN, double &wS, double &d)
+// stencil of cell (i, j) from coefficients of type TA, weights in type TW
+template <typename TW, typename TA>
+__device__ __forceinline__ void lds_stencil(const TA *a, int n, int i, int j, TW &wE, TW &wW,
+                                            TW &wN, TW &wS, TW &d)
 {
     const int p = i + n * j;
-    const double ap = a[p];
-    d = 0.0;
-    wE = wW = wN = wS = 0.0;
-    if (i + 1 < n) { wE = hm(ap, a[p + 1]); d += wE; } else d += 2.0 * ap;
-    if (i > 0)     { wW = hm(ap, a[p - 1]); d += wW; } else d += 2.0 * ap;
-    if (j + 1 < n) { wN = hm(ap, a[p + n]); d += wN; } else d += 2.0 * ap;
-    if (j > 0)     { wS = hm(ap, a[p - n]); d += wS; } else d += 2.0 * ap;
+    const TW ap = TW(a[p]);
+    d = TW(0);
+    wE = wW = wN = wS = TW(0);
+    if (i + 1 < n) { wE = hm(ap, TW(a[p + 1])); d += wE; } else d += TW(2) * ap;
+    if (i > 0)     { wW = hm(ap, TW(a[p - 1])); d += wW; } else d += TW(2) * ap;
+    if (j + 1 < n) { wN = hm(ap, TW(a[p + n])); d += wN; } else d += TW(2) * ap;
+    if (j > 0)     { wS = hm(ap, TW(a[p - n])); d += wS; } else d += TW(2) * ap;
 }
 
-__device__ __forceinline__ double lds_nb(const double *u, int n, int i, int j)
+template <typename T>
+__device__ __forceinline__ T lds_nb(const T *u, int n, int i, int j)
 {
-    return (i < 0 || j < 0 || i >= n || j >= n) ? 0.0 : u[i + n * j];
+    return (i < 0 || j < 0 || i >= n || j >= n) ? T(0) : u[i + n * j];
 }
 
 // one colour; f == nullptr means f = 1
-__device__ void lds_sweep(const double *a, const double *f, double *u, int n, int colour)
+template <typename T>
+__device__ void lds_sweep(const T *a, const T *f, T *u, int n, int colour)
 {
     const int half = n / 2;
-    const double h2 = 1.0 / ((double)n * (double)n);
+    const T h2 = T(1) / (T(n) * T(n));
     for (int q = threadIdx.x; q < n * half; q += LT) {
         const int j = q / half;
         const int i = 2 * (q - j * half) + ((j + colour) & 1);
-        double wE, wW, wN, wS, d;
-        lds_stencil(a, n, i, j, wE, wW, wN, wS, d);
-        double num = h2 * (f ? f[i + n * j] : 1.0);
+        T wE, wW, wN, wS, d;
+        lds_stencil<T>(a, n, i, j, wE, wW, wN, wS, d);
+        T num = h2 * (f ? f[i + n * j] : T(1));
         num += wE * lds_nb(u, n, i + 1, j);
         num += wW * lds_nb(u, n, i - 1, j);
         num += wN * lds_nb(u, n, i, j + 1);
@@ -457,40 +400,44 @@ __device__ void lds_sweep(const double *a, const double *f, double *u, int n, in
     __syncthreads();
 }
 
-__device__ __forceinline__ double lds_resid(const double *a, const double *f, const double *u,
-                                            int n, int i, int j)
+// r = f - A u at one cell, in the arithmetic of TU (coefficients TA promoted)
+template <typename TU, typename TA>
+__device__ __forceinline__ TU lds_resid(const TA *a, const TU *f, const TU *u, int n, int i, int j)
 {
-    double wE, wW, wN, wS, d;
-    lds_stencil(a, n, i, j, wE, wW, wN, wS, d);
-    double off = wE * lds_nb(u, n, i + 1, j);
+    TU wE, wW, wN, wS, d;
+    lds_stencil<TU>(a, n, i, j, wE, wW, wN, wS, d);
+    TU off = wE * lds_nb(u, n, i + 1, j);
     off += wW * lds_nb(u, n, i - 1, j);
     off += wN * lds_nb(u, n, i, j + 1);
     off += wS * lds_nb(u, n, i, j - 1);
-    return (f ? f[i + n * j] : 1.0) - (double)n * (double)n * (d * u[i + n * j] - off);
+    return (f ? f[i + n * j] : TU(1)) - TU(n) * TU(n) * (d * u[i + n * j] - off);
 }
 
-__device__ void lds_coarse_solve(const double *a, const double *f, double *u)
+// exact 2x2 solve A u = f (f nullptr: f = 1) in the arithmetic of TU
+template <typename TU, typename TA>
+__device__ void lds_coarse_solve(const TA *a, const TU *f, TU *u)
 {
     if (threadIdx.x == 0) {
-        double w01 = hm(a[0], a[1]), w02 = hm(a[0], a[2]), w13 = hm(a[1], a[3]), w23 = hm(a[2], a[3]);
-        double A[4][4] = {{w01 + w02 + 4.0 * a[0], -w01, -w02, 0.0},
-                          {-w01, w01 + w13 + 4.0 * a[1], 0.0, -w13},
-                          {-w02, 0.0, w02 + w23 + 4.0 * a[2], -w23},
-                          {0.0, -w13, -w23, w13 + w23 + 4.0 * a[3]}};
-        double L[4][4] = {}, v[4];
+        const TU a0 = TU(a[0]), a1 = TU(a[1]), a2 = TU(a[2]), a3 = TU(a[3]);
+        const TU w01 = hm(a0, a1), w02 = hm(a0, a2), w13 = hm(a1, a3), w23 = hm(a2, a3);
+        TU A[4][4] = {{w01 + w02 + TU(4) * a0, -w01, -w02, TU(0)},
+                      {-w01, w01 + w13 + TU(4) * a1, TU(0), -w13},
+                      {-w02, TU(0), w02 + w23 + TU(4) * a2, -w23},
+                      {TU(0), -w13, -w23, w13 + w23 + TU(4) * a3}};
+        TU L[4][4] = {}, v[4];
         for (int p = 0; p < 4; ++p)
             for (int q = 0; q <= p; ++q) {
-                double s = A[p][q];
+                TU s = A[p][q];
                 for (int t = 0; t < q; ++t) s -= L[p][t] * L[q][t];
                 L[p][q] = (p == q) ? sqrt(s) : s / L[q][q];
             }
         for (int p = 0; p < 4; ++p) {
-            double s = 0.25 * (f ? f[p] : 1.0);
+            TU s = TU(0.25) * (f ? f[p] : TU(1));
             for (int q = 0; q < p; ++q) s -= L[p][q] * v[q];
             v[p] = s / L[p][p];
         }
         for (int p = 3; p >= 0; --p) {
-            double s = v[p];
+            TU s = v[p];
             for (int q = p + 1; q < 4; ++q) s -= L[q][p] * v[q];
             v[p] = s / L[p][p];
         }
@@ -499,64 +446,55 @@ __device__ void lds_coarse_solve(const double *a, const double *f, double *u)
     __syncthreads();
 }
 
-__device__ __forceinline__ double lds_codd(const double *e, int nc, int I, int J)
-{
-    double sg = 1.0;
-    if (I < 0) { I = 0; sg = -sg; }
-    if (I >= nc) { I = nc - 1; sg = -sg; }
-    if (J < 0) { J = 0; sg = -sg; }
-    if (J >= nc) { J = nc - 1; sg = -sg; }
-    return sg * e[I + nc * J];
-}
-
 // u = P e (add = false) or u += P e on the n x n grid
-__device__ void lds_prolong(const double *e, double *u, int n, bool add)
+template <typename T>
+__device__ void lds_prolong(const T *e, T *u, int n, bool add)
 {
     const int nc = n / 2;
     for (int p = threadIdx.x; p < n * n; p += LT) {
         const int j = p / n, i = p - j * n;
         const int I = i >> 1, J = j >> 1, sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1;
-        const double v = (9.0 * lds_codd(e, nc, I, J) + 3.0 * lds_codd(e, nc, I + sx, J) +
-                          3.0 * lds_codd(e, nc, I, J + sy) + lds_codd(e, nc, I + sx, J + sy)) / 16.0;
+        const T v = (T(9) * codd(e, nc, I, J) + T(3) * codd(e, nc, I + sx, J) +
+                     T(3) * codd(e, nc, I, J + sy) + codd(e, nc, I + sx, J + sy)) / T(16);
         u[p] = add ? u[p] + v : v;
     }
     __syncthreads();
 }
 
-template <int GS>
+template <int GS, typename T>
 struct LdsVcycle {
-    double *a, *u, *f;   // LDS bases, level g at LdsHier<GS>::off(g)
+    T *a, *u, *f;   // LDS bases, level g at LdsHier<GS>::off(g)
     int mu1, mu2;
     // V(mu1,mu2) at level g (one coarse-grid correction per level, so the
     // recursion unrolls into a descent and an ascent).  The top right-hand
     // side may be nullptr (f = 1); the coarser ones live in LDS.
-    __device__ void run(int g, const double *ftop)
+    __device__ void run(int g, const T *ftop)
     {
         for (int l = g; l >= 1; --l) {
             const int n = 2 << l, nc = n / 2;
-            double *al = a + LdsHier<GS>::off(l), *ul = u + LdsHier<GS>::off(l);
-            const double *fl = (l == g) ? ftop : f + LdsHier<GS>::off(l);
+            T *al = a + LdsHier<GS>::off(l), *ul = u + LdsHier<GS>::off(l);
+            const T *fl = (l == g) ? ftop : f + LdsHier<GS>::off(l);
             for (int it = 0; it < mu1; ++it) {
                 lds_sweep(al, fl, ul, n, 0);
                 lds_sweep(al, fl, ul, n, 1);
             }
-            double *fcl = f + LdsHier<GS>::off(l - 1), *ucl = u + LdsHier<GS>::off(l - 1);
+            T *fcl = f + LdsHier<GS>::off(l - 1), *ucl = u + LdsHier<GS>::off(l - 1);
             for (int q = threadIdx.x; q < nc * nc; q += LT) {
                 const int J = q / nc, I = q - J * nc;
-                const double r00 = lds_resid(al, fl, ul, n, 2 * I, 2 * J);
-                const double r10 = lds_resid(al, fl, ul, n, 2 * I + 1, 2 * J);
-                const double r01 = lds_resid(al, fl, ul, n, 2 * I, 2 * J + 1);
-                const double r11 = lds_resid(al, fl, ul, n, 2 * I + 1, 2 * J + 1);
-                fcl[q] = 0.25 * (r00 + r10 + r01 + r11);
-                ucl[q] = 0.0;
+                const T r00 = lds_resid<T>(al, fl, ul, n, 2 * I, 2 * J);
+                const T r10 = lds_resid<T>(al, fl, ul, n, 2 * I + 1, 2 * J);
+                const T r01 = lds_resid<T>(al, fl, ul, n, 2 * I, 2 * J + 1);
+                const T r11 = lds_resid<T>(al, fl, ul, n, 2 * I + 1, 2 * J + 1);
+                fcl[q] = T(0.25) * (r00 + r10 + r01 + r11);
+                ucl[q] = T(0);
             }
             __syncthreads();
         }
-        lds_coarse_solve(a, g == 0 ? ftop : f, u);
+        lds_coarse_solve<T>(a, g == 0 ? ftop : f, u);
         for (int l = 1; l <= g; ++l) {
             const int n = 2 << l;
-            double *al = a + LdsHier<GS>::off(l), *ul = u + LdsHier<GS>::off(l);
-            const double *fl = (l == g) ? ftop : f + LdsHier<GS>::off(l);
+            T *al = a + LdsHier<GS>::off(l), *ul = u + LdsHier<GS>::off(l);
+            const T *fl = (l == g) ? ftop : f + LdsHier<GS>::off(l);
             lds_prolong(u + LdsHier<GS>::off(l - 1), ul, n, true);
             for (int it = 0; it < mu2; ++it) {
                 lds_sweep(al, fl, ul, n, 1);
@@ -566,16 +504,10 @@ struct LdsVcycle {
     }
 };
 
-// deterministic block sum (Neumaier per thread, fixed pairwise tree)
-__device__ double lds_block_sum(const double *v, int count, double *scratch)
+// Deterministic block reduction of per-thread compensated partial sums
+// (fixed pairwise tree).  Returns the total in every thread.
+__device__ double lds_reduce(double s, double c, double *scratch)
 {
-    double s = 0.0, c = 0.0;
-    for (int p = threadIdx.x; p < count; p += LT) {
-        const double x = v[p];
-        const double t = s + x;
-        if (fabs(s) >= fabs(x)) c += (s - t) + x; else c += (x - t) + s;
-        s = t;
-    }
     scratch[2 * threadIdx.x] = s;
     scratch[2 * threadIdx.x + 1] = c;
     __syncthreads();
@@ -584,9 +516,8 @@ __device__ double lds_block_sum(const double *v, int count, double *scratch)
             const double s1 = scratch[2 * threadIdx.x], c1 = scratch[2 * threadIdx.x + 1];
             const double s2 = scratch[2 * (threadIdx.x + w)], c2 = scratch[2 * (threadIdx.x + w) + 1];
             const double t = s1 + s2, bb = t - s1;
-            const double err = (s1 - (t - bb)) + (s2 - bb);
             scratch[2 * threadIdx.x] = t;
-            scratch[2 * threadIdx.x + 1] = c1 + c2 + err;
+            scratch[2 * threadIdx.x + 1] = c1 + c2 + ((s1 - (t - bb)) + (s2 - bb));
         }
         __syncthreads();
     }
@@ -595,109 +526,344 @@ __device__ double lds_block_sum(const double *v, int count, double *scratch)
     return r;
 }
 
-// mode 0: FMG stages 0..G (G <= GS), QoI of stages g >= g0, final u to HBM.
-// mode 1: one V-cycle at level G with zero initial guess and f read from HBM,
-//         correction written to the u pool at level G.
+__device__ __forceinline__ void neumaier(double &s, double &c, double x)
+{
+    const double t = s + x;
+    if (fabs(s) >= fabs(x)) c += (s - t) + x; else c += (x - t) + s;
+    s = t;
+}
+
+__device__ void lds_write_qoi(const double *ug, int n, double *qoi, int64_t b, int nlev, int l,
+                              uint32_t mask, double *scratch)
+{
+    const int nq = (mask & 1u ? 1 : 0) + (mask & 2u ? 1 : 0);
+    double qm = 0.0;
+    if (mask & 1u) {
+        double s = 0.0, c = 0.0;
+        for (int p = threadIdx.x; p < n * n; p += LT) neumaier(s, c, ug[p]);
+        qm = lds_reduce(s, c, scratch) / ((double)n * n);
+    }
+    if (threadIdx.x == 0) {
+        double *qb = qoi + (b * nlev + l) * nq;
+        int q = 0;
+        if (mask & 1u) qb[q++] = qm;
+        if (mask & 2u) {
+            const int c = n / 2;
+            qb[q] = 0.25 * (ug[(c - 1) + n * (c - 1)] + ug[c + n * (c - 1)] + ug[(c - 1) + n * c] +
+                            ug[c + n * c]);
+        }
+    }
+}
+
+// FMG stages 0..G (G <= GS) with fixed mu0 cycles, FP64; QoI of stages g >= g0;
+// final u of level G to the u pool.
 template <int GS>
-__global__ __launch_bounds__(LT) void k_lds_mg(const double *__restrict__ a_pool,
-                                               const double *__restrict__ f_pool,
-                                               double *__restrict__ u_pool, int64_t Bc, int G,
-                                               int mode, int mu0, int mu1, int mu2, int g0,
-                                               double *__restrict__ qoi, int nlev, uint32_t mask,
-                                               const int32_t *__restrict__ active)
+__global__ __launch_bounds__(LT) void k_lds_fmg_fixed(const double *__restrict__ a_pool,
+                                                      double *__restrict__ u_pool, int64_t Bc,
+                                                      int G, int mu0, int mu1, int mu2, int g0,
+                                                      double *__restrict__ qoi, int nlev,
+                                                      uint32_t mask)
 {
     constexpr int TOT = LdsHier<GS>::TOTAL;
     __shared__ double a_s[TOT], u_s[TOT], f_s[TOT];
     __shared__ double red_s[2 * LT];
     const int64_t b = blockIdx.x;
     if (b >= Bc) return;
-    if (active && !active[b]) return;
     for (int g = 0; g <= G; ++g) {
         const int cnt = 4 << (2 * g);
         const double *src = a_pool + Bc * level_offset(g) + b * (int64_t)cnt;
         for (int p = threadIdx.x; p < cnt; p += LT) a_s[LdsHier<GS>::off(g) + p] = src[p];
     }
-    const int cntG = 4 << (2 * G);
-    if (mode == 1) {
-        const double *src = f_pool + Bc * level_offset(G) + b * (int64_t)cntG;
-        for (int p = threadIdx.x; p < cntG; p += LT) {
-            f_s[LdsHier<GS>::off(G) + p] = src[p];
-            u_s[LdsHier<GS>::off(G) + p] = 0.0;
-        }
-    }
     __syncthreads();
-    LdsVcycle<GS> V{a_s, u_s, f_s, mu1, mu2};
-    const int nq = (mask & 1u ? 1 : 0) + (mask & 2u ? 1 : 0);
-    if (mode == 1) {
-        V.run(G, f_s + LdsHier<GS>::off(G));
-    } else {
-        for (int g = 0; g <= G; ++g) {
-            const int n = 2 << g;
-            double *ug = u_s + LdsHier<GS>::off(g);
-            if (g == 0) {
-                V.run(0, nullptr);
-            } else {
-                lds_prolong(u_s + LdsHier<GS>::off(g - 1), ug, n, false);
-                for (int c = 0; c < mu0; ++c) V.run(g, nullptr);
-            }
-            if (g >= g0) {
-                double qm = 0.0;
-                if (mask & 1u) qm = lds_block_sum(ug, n * n, red_s) / ((double)n * n);
-                if (threadIdx.x == 0) {
-                    double *qb = qoi + (b * nlev + (g - g0)) * nq;
-                    int q = 0;
-                    if (mask & 1u) qb[q++] = qm;
-                    if (mask & 2u) {
-                        const int c = n / 2;
-                        qb[q] = 0.25 * (ug[(c - 1) + n * (c - 1)] + ug[c + n * (c - 1)] +
-                                        ug[(c - 1) + n * c] + ug[c + n * c]);
-                    }
-                }
-            }
+    LdsVcycle<GS, double> V{a_s, u_s, f_s, mu1, mu2};
+    for (int g = 0; g <= G; ++g) {
+        const int n = 2 << g;
+        double *ug = u_s + LdsHier<GS>::off(g);
+        if (g == 0) {
+            V.run(0, nullptr);
+        } else {
+            lds_prolong(u_s + LdsHier<GS>::off(g - 1), ug, n, false);
+            for (int c = 0; c < mu0; ++c) V.run(g, nullptr);
         }
+        if (g >= g0) lds_write_qoi(ug, n, qoi, b, nlev, g - g0, mask, red_s);
     }
+    const int cntG = 4 << (2 * G);
     double *dst = u_pool + Bc * level_offset(G) + b * (int64_t)cntG;
     for (int p = threadIdx.x; p < cntG; p += LT) dst[p] = u_s[LdsHier<GS>::off(G) + p];
 }
 
+// One V-cycle at level G (<= GS) with zero initial guess, f from the f pool,
+// correction to the u pool.
+template <int GS, typename T>
+__global__ __launch_bounds__(LT) void k_lds_vcycle(const T *__restrict__ a_pool,
+                                                   const T *__restrict__ f_pool, T *__restrict__ u_pool,
+                                                   int64_t Bc, int G, int mu1, int mu2,
+                                                   const int32_t *__restrict__ active)
+{
+    constexpr int TOT = LdsHier<GS>::TOTAL;
+    __shared__ T a_s[TOT], u_s[TOT], f_s[TOT];
+    const int64_t b = blockIdx.x;
+    if (b >= Bc) return;
+    if (active && !active[b]) return;
+    for (int g = 0; g <= G; ++g) {
+        const int cnt = 4 << (2 * g);
+        const T *src = a_pool + Bc * level_offset(g) + b * (int64_t)cnt;
+        for (int p = threadIdx.x; p < cnt; p += LT) a_s[LdsHier<GS>::off(g) + p] = src[p];
+    }
+    const int cntG = 4 << (2 * G);
+    const T *fsrc = f_pool + Bc * level_offset(G) + b * (int64_t)cntG;
+    for (int p = threadIdx.x; p < cntG; p += LT) {
+        f_s[LdsHier<GS>::off(G) + p] = fsrc[p];
+        u_s[LdsHier<GS>::off(G) + p] = T(0);
+    }
+    __syncthreads();
+    LdsVcycle<GS, T> V{a_s, u_s, f_s, mu1, mu2};
+    V.run(G, f_s + LdsHier<GS>::off(G));
+    T *dst = u_pool + Bc * level_offset(G) + b * (int64_t)cntG;
+    for (int p = threadIdx.x; p < cntG; p += LT) dst[p] = u_s[LdsHier<GS>::off(G) + p];
+}
+
+// FMG stages 0..G (G <= GS) with refinement: per stage, u64 = P u64_prev, then
+// { r = 1 - A u64 in FP64 ; stop if ||r||_2 / ||1||_2 <= rtol or after max_iters ;
+//   e = V(0; r) in T ; u64 += e }.  QoI of stages g >= g0 from u64; u64 of
+// level G to u64_pool; per sample the largest iteration count, the largest
+// final relative residual and whether a stage stopped short of rtol.
+template <int GS, typename T>
+__global__ __launch_bounds__(LT) void k_lds_fmg_refine(
+    const T *__restrict__ a_pool, double *__restrict__ u64_pool, int64_t Bc, int G, int mu1,
+    int mu2, double rtol, int max_iters, int g0, double *__restrict__ qoi, int nlev, uint32_t mask,
+    int32_t *__restrict__ st_iters, double *__restrict__ st_rho, int32_t *__restrict__ st_bad)
+{
+    constexpr int TOT = LdsHier<GS>::TOTAL;
+    __shared__ T a_s[TOT], u_s[TOT], f_s[TOT];
+    __shared__ double w_s[TOT];          // FP64 stage solutions
+    __shared__ double red_s[2 * LT];
+    const int64_t b = blockIdx.x;
+    if (b >= Bc) return;
+    for (int g = 0; g <= G; ++g) {
+        const int cnt = 4 << (2 * g);
+        const T *src = a_pool + Bc * level_offset(g) + b * (int64_t)cnt;
+        for (int p = threadIdx.x; p < cnt; p += LT) a_s[LdsHier<GS>::off(g) + p] = src[p];
+    }
+    __syncthreads();
+    LdsVcycle<GS, T> V{a_s, u_s, f_s, mu1, mu2};
+    int it_max = 0, bad = 0;
+    double rho_max = 0.0;
+    for (int g = 0; g <= G; ++g) {
+        const int n = 2 << g;
+        double *wg = w_s + LdsHier<GS>::off(g);
+        T *ug = u_s + LdsHier<GS>::off(g), *fg = f_s + LdsHier<GS>::off(g);
+        const T *ag = a_s + LdsHier<GS>::off(g);
+        if (g == 0) lds_coarse_solve<double>(a_s, (const double *)nullptr, wg);
+        else lds_prolong(w_s + LdsHier<GS>::off(g - 1), wg, n, false);
+        int it = 0;
+        double rho = 0.0;
+        for (;;) {
+            // FP64 residual, staged as the T right-hand side of the correction
+            double s = 0.0, c = 0.0;
+            for (int p = threadIdx.x; p < n * n; p += LT) {
+                const int j = p / n, i = p - j * n;
+                const double r = lds_resid<double>(ag, (const double *)nullptr, wg, n, i, j);
+                fg[p] = T(r);
+                ug[p] = T(0);
+                neumaier(s, c, r * r);
+            }
+            rho = sqrt(lds_reduce(s, c, red_s)) / (double)n;   // ||1||_2 = n
+            if (rho <= rtol || it >= max_iters) break;
+            V.run(g, fg);
+            for (int p = threadIdx.x; p < n * n; p += LT) wg[p] += double(ug[p]);
+            __syncthreads();
+            ++it;
+        }
+        if (rho > rtol) bad = 1;
+        it_max = it > it_max ? it : it_max;
+        rho_max = rho > rho_max ? rho : rho_max;
+        if (g >= g0) lds_write_qoi(wg, n, qoi, b, nlev, g - g0, mask, red_s);
+    }
+    const int cntG = 4 << (2 * G);
+    double *dst = u64_pool + Bc * level_offset(G) + b * (int64_t)cntG;
+    for (int p = threadIdx.x; p < cntG; p += LT) dst[p] = w_s[LdsHier<GS>::off(G) + p];
+    if (threadIdx.x == 0) {
+        st_iters[b] = it_max;
+        st_rho[b] = rho_max;
+        st_bad[b] = bad;
+    }
+}
+
+// Top-grid FP64 residual r = 1 - A u64 (coefficients T promoted) of every
+// active sample, one wavefront per sample: r -> f (as T), rho_b = ||r||/||1||,
+// active_b = rho_b > rtol && iters_b < max_iters (iters counted here).
+template <typename T>
+__global__ __launch_bounds__(256) void k_refine_residual(const T *__restrict__ a,
+                                                         const double *__restrict__ u, int n,
+                                                         int64_t Bc, T *__restrict__ f,
+                                                         double *__restrict__ rho,
+                                                         int32_t *__restrict__ active,
+                                                         int32_t *__restrict__ iters, double rtol,
+                                                         int max_iters)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    if (b >= Bc) return;
+    if (!active[b]) return;
+    const int64_t cells = (int64_t)n * n, base = b * cells;
+    const T *ab = a + base;
+    const double *ub = u + base;
+    const double inv_h2 = (double)n * (double)n;
+    double s = 0.0, c = 0.0;
+    for (int64_t p = lane; p < cells; p += 64) {
+        const int j = (int)(p / n), i = (int)(p - (int64_t)j * n);
+        const double ap = double(ab[p]);
+        double d = 0.0, off = 0.0, w;
+        if (i + 1 < n) { w = hm(ap, double(ab[p + 1])); d += w; off += w * ub[p + 1]; } else d += 2.0 * ap;
+        if (i > 0)     { w = hm(ap, double(ab[p - 1])); d += w; off += w * ub[p - 1]; } else d += 2.0 * ap;
+        if (j + 1 < n) { w = hm(ap, double(ab[p + n])); d += w; off += w * ub[p + n]; } else d += 2.0 * ap;
+        if (j > 0)     { w = hm(ap, double(ab[p - n])); d += w; off += w * ub[p - n]; } else d += 2.0 * ap;
+        const double r = 1.0 - inv_h2 * (d * ub[p] - off);
+        f[base + p] = T(r);
+        neumaier(s, c, r * r);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const double s2 = __shfl_xor(s, m, 64), c2 = __shfl_xor(c, m, 64);
+        const double t = s + s2, bb = t - s;
+        c = c + c2 + ((s - (t - bb)) + (s2 - bb));
+        s = t;
+    }
+    if (lane == 0) {
+        const double v = sqrt(s + c) / (double)n;
+        rho[b] = v;
+        const int it = iters[b];
+        const int go = (v > rtol) && (it < max_iters);
+        active[b] = go;
+        if (go) iters[b] = it + 1;
+    }
+}
+
+// u64 += e (type T) for active samples
+template <typename T>
+__global__ void k_refine_update(double *__restrict__ u, const T *__restrict__ e, int n, int64_t Bc,
+                                const int32_t *__restrict__ active)
+{
+    const int64_t per = (int64_t)n * n;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Bc * per) return;
+    if (!active[t / per]) return;
+    u[t] += double(e[t]);
+}
+
+// fold one stage's final per-sample state into the per-sample statistics
+__global__ void k_refine_stats(const int32_t *__restrict__ iters, const double *__restrict__ rho,
+                               int64_t Bc, double rtol, int32_t *__restrict__ st_iters,
+                               double *__restrict__ st_rho, int32_t *__restrict__ st_bad)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= Bc) return;
+    if (iters[b] > st_iters[b]) st_iters[b] = iters[b];
+    if (rho[b] > st_rho[b]) st_rho[b] = rho[b];
+    if (rho[b] > rtol) st_bad[b] = 1;
+}
+
 inline unsigned nblocks(int64_t n) { return (unsigned)(n < 1 ? 1 : n); }
+inline unsigned blocks_of(int64_t n, int per) { return nblocks((n + per - 1) / per); }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
 bool fused_supported(int mu1, int mu2) { return mu1 >= 1 && mu1 <= 2 && mu2 >= 1 && mu2 <= 2; }
 
-void launch_pre_tile(hipStream_t st, int mu1, const double *a, const double *f, double *u,
-                     const double *uc, int n, int64_t Bc, int init, double *fc,
-                     const int32_t *active)
+template <typename T>
+void launch_pre_tile(hipStream_t st, int mu1, const T *a, const T *f, T *u, const T *uc, int n,
+                     int64_t Bc, int init, T *fc, const int32_t *active)
 {
     const int64_t blocks = Bc * (int64_t)(n / TILE) * (n / TILE);
     if (mu1 == 2)
-        hipLaunchKernelGGL(k_pre_tile<2>, dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u, uc, n, Bc,
-                           init, fc, active);
+        hipLaunchKernelGGL((k_pre_tile<2, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u, uc, n,
+                           Bc, init, fc, active);
     else
-        hipLaunchKernelGGL(k_pre_tile<1>, dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u, uc, n, Bc,
-                           init, fc, active);
+        hipLaunchKernelGGL((k_pre_tile<1, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u, uc, n,
+                           Bc, init, fc, active);
 }
 
-void launch_post_tile(hipStream_t st, int mu2, const double *a, const double *f, double *u,
-                      const double *ec, int n, int64_t Bc, const int32_t *active)
+template <typename T>
+void launch_post_tile(hipStream_t st, int mu2, const T *a, const T *f, T *u, const T *ec, int n,
+                      int64_t Bc, const int32_t *active)
 {
     const int64_t blocks = Bc * (int64_t)(n / TILE) * (n / TILE);
     if (mu2 == 2)
-        hipLaunchKernelGGL(k_post_tile<2>, dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u, ec, n,
-                           Bc, active);
+        hipLaunchKernelGGL((k_post_tile<2, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u, ec,
+                           n, Bc, active);
     else
-        hipLaunchKernelGGL(k_post_tile<1>, dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u, ec, n,
-                           Bc, active);
+        hipLaunchKernelGGL((k_post_tile<1, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u, ec,
+                           n, Bc, active);
 }
 
-void launch_lds_mg(hipStream_t st, const double *a_pool, const double *f_pool, double *u_pool,
-                   int64_t Bc, int G, int mode, int mu0, int mu1, int mu2, int g0, double *qoi,
-                   int nlev, uint32_t mask, const int32_t *active)
+void launch_lds_fmg_fixed(hipStream_t st, const double *a_pool, double *u_pool, int64_t Bc, int G,
+                          int mu0, int mu1, int mu2, int g0, double *qoi, int nlev, uint32_t mask)
 {
-    hipLaunchKernelGGL(k_lds_mg<kLdsMaxLevel>, dim3(nblocks(Bc)), dim3(LT), 0, st, a_pool, f_pool,
-                       u_pool, Bc, G, mode, mu0, mu1, mu2, g0, qoi, nlev, mask, active);
+    hipLaunchKernelGGL(k_lds_fmg_fixed<kLdsMaxLevel>, dim3(nblocks(Bc)), dim3(LT), 0, st, a_pool,
+                       u_pool, Bc, G, mu0, mu1, mu2, g0, qoi, nlev, mask);
 }
+
+template <typename T>
+void launch_lds_vcycle(hipStream_t st, const T *a_pool, const T *f_pool, T *u_pool, int64_t Bc,
+                       int G, int mu1, int mu2, const int32_t *active)
+{
+    hipLaunchKernelGGL((k_lds_vcycle<kLdsMaxLevel, T>), dim3(nblocks(Bc)), dim3(LT), 0, st, a_pool,
+                       f_pool, u_pool, Bc, G, mu1, mu2, active);
+}
+
+template <typename T>
+void launch_lds_fmg_refine(hipStream_t st, const T *a_pool, double *u64_pool, int64_t Bc, int G,
+                           int mu1, int mu2, double rtol, int max_iters, int g0, double *qoi,
+                           int nlev, uint32_t mask, int32_t *st_iters, double *st_rho,
+                           int32_t *st_bad)
+{
+    hipLaunchKernelGGL((k_lds_fmg_refine<kLdsMaxLevel, T>), dim3(nblocks(Bc)), dim3(LT), 0, st,
+                       a_pool, u64_pool, Bc, G, mu1, mu2, rtol, max_iters, g0, qoi, nlev, mask,
+                       st_iters, st_rho, st_bad);
+}
+
+template <typename T>
+void launch_refine_residual(hipStream_t st, const T *a, const double *u, int n, int64_t Bc, T *f,
+                            double *rho, int32_t *active, int32_t *iters, double rtol,
+                            int max_iters)
+{
+    hipLaunchKernelGGL((k_refine_residual<T>), dim3(blocks_of(Bc, 4)), dim3(256), 0, st, a, u, n, Bc,
+                       f, rho, active, iters, rtol, max_iters);
+}
+
+template <typename T>
+void launch_refine_update(hipStream_t st, double *u, const T *e, int n, int64_t Bc,
+                          const int32_t *active)
+{
+    hipLaunchKernelGGL((k_refine_update<T>), dim3(blocks_of(Bc * (int64_t)n * n, 256)), dim3(256), 0,
+                       st, u, e, n, Bc, active);
+}
+
+void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho, int64_t Bc,
+                         double rtol, int32_t *st_iters, double *st_rho, int32_t *st_bad)
+{
+    hipLaunchKernelGGL(k_refine_stats, dim3(blocks_of(Bc, 256)), dim3(256), 0, st, iters, rho, Bc,
+                       rtol, st_iters, st_rho, st_bad);
+}
+
+#define MLMC_INSTANTIATE(T)                                                                        \
+    template void launch_pre_tile<T>(hipStream_t, int, const T *, const T *, T *, const T *, int, \
+                                     int64_t, int, T *, const int32_t *);                          \
+    template void launch_post_tile<T>(hipStream_t, int, const T *, const T *, T *, const T *, int,\
+                                      int64_t, const int32_t *);                                   \
+    template void launch_lds_vcycle<T>(hipStream_t, const T *, const T *, T *, int64_t, int, int, \
+                                       int, const int32_t *);                                      \
+    template void launch_lds_fmg_refine<T>(hipStream_t, const T *, double *, int64_t, int, int,   \
+                                           int, double, int, int, double *, int, uint32_t,        \
+                                           int32_t *, double *, int32_t *);                        \
+    template void launch_refine_residual<T>(hipStream_t, const T *, const double *, int, int64_t, \
+                                            T *, double *, int32_t *, int32_t *, double, int);     \
+    template void launch_refine_update<T>(hipStream_t, double *, const T *, int, int64_t,         \
+                                          const int32_t *);
+MLMC_INSTANTIATE(double)
+MLMC_INSTANTIATE(float)
+#undef MLMC_INSTANTIATE
 
 }  // namespace mlmc

@@ -99,7 +99,7 @@ WORKLOADS = {
     # mixed precision, 2^12 points x 16 shifts, 4^2 .. 1024^2, refinement to 1e-10
     "mlqmc_mixed_s400": dict(
         n0=4, num_levels=9, s=400, corr_len=0.1, sigma2=2.0,
-        mu0=1, mu1=2, mu2=2, rtol=1e-10, max_iters=30, precision="mixed",
+        mu0=1, mu1=2, mu2=2, rtol=1e-10, max_iters=60, precision="mixed",
         qoi=("mean", "center"), sampling="lattice", lattice_log2n=12,
         num_shifts=16, seed=3,
     ),

@@ -275,3 +275,40 @@ def test_full_size_bench_workload_sampled(oracle_mod):
                 blk = qg[r * npts:(r + 1) * npts, :, q]
                 d = blk[:, l] - (blk[:, l - 1] if l else 0.0)
                 assert abs(sg[r, q, l, 0] - math.fsum(d)) <= 1e-13 * math.fsum(np.abs(d))
+
+
+def _mixed_ctx(**over):
+    w = synth.workload("mlqmc_mixed_s400")
+    w.update(over)
+    ctx = m.Context(w["n0"], w["num_levels"], w["s"], w["corr_len"], w["sigma2"],
+                    mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"],
+                    max_iters=w["max_iters"], precision=over.get("precision", m.MLMC_MIXED),
+                    qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
+                    max_batch=w.get("max_batch", 16), device=0)
+    return w, ctx
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_refinement_high_contrast_matches_direct_solve(oracle_mod, precision):
+    """sigma^2 = 2, lambda = 0.1, s = 400: FP64 residual refinement to 1e-10
+    with FP64 or FP32 V-cycles, against the oracle's FP64 field and band
+    Cholesky solve on every level up to 128^2 (the batched tile path).  The
+    mixed-precision error is the FP32 rounding of the coefficient plus the
+    solve tolerance; it is reported per level."""
+    dev = _dev()
+    prec = m.MLMC_MIXED if precision == "mixed" else m.MLMC_FP64
+    w, ctx = _mixed_ctx(precision=prec)
+    P = _oracle_problem(oracle_mod, w)
+    k = 5
+    ys = np.random.default_rng(31).standard_normal((3, w["s"]))
+    pts = ctx.explicit(k, torch.tensor(ys, device=dev))
+    qg, _, info = _solve(ctx, pts, k + 1, info=True)
+    assert info["status"] == m.MLMC_OK and info["not_converged"] == 0, info
+    assert 0 < info["max_rel_residual"] <= w["rtol"]
+    errs = np.zeros((k + 1, 2))
+    for b in range(len(ys)):
+        qd = P.sample(k, ys[b], 1)
+        errs = np.maximum(errs, np.abs(qg[b] - qd) / np.abs(qd))
+    print(f"\n{precision}: max relative QoI error per level (mean, centre):\n{errs}")
+    tol = 1e-9 if precision == "fp64" else 2e-6
+    assert errs.max() <= tol, errs
