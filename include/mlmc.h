@@ -80,8 +80,9 @@ typedef struct {
     double rtol;          /* 0: fixed mu0 cycles.  > 0: every stage iterates
                              V-cycles on the residual until ||f-Au||_2/||f||_2 <= rtol */
     int32_t max_iters;    /* refinement cap per stage when rtol > 0 (>= 1) */
-    int32_t precision;    /* MLMC_FP64, or MLMC_MIXED (FP32 field and V-cycles
-                             inside FP64 residual refinement; needs rtol > 0) */
+    int32_t precision;    /* MLMC_FP64, or MLMC_MIXED (bf16x3 matrix-core field
+                             stored as FP32, FP32 V-cycles inside FP64 residual
+                             refinement; needs rtol > 0) */
     uint32_t qoi_mask;    /* non-empty subset of MLMC_QOI_MEAN | MLMC_QOI_CENTER;
                              nq = number of bits, QoI q in increasing bit order */
     int32_t num_shifts;   /* R, number of random shifts (>= 1 if shifts given) */
@@ -153,8 +154,11 @@ mlmc_status mlmc_points_gen(mlmc_ctx ctx, const mlmc_points *pts,
 /* Section 5, eq. truncatedKL: z(x) = sigma sum_{m<s} sqrt(theta_m) psi_m(x) y_m
  * at the cell centres of every MG level 0..G(level) of every sample, as one
  * dense product Y [B][s] x basis [s][M].  z_dev [B][M], M = mlmc_field_size
- * (sample-major, levels in order).  FP64 in both precision modes (the MIXED
- * solve uses its own reduced-precision product internally). */
+ * (sample-major, levels in order).  FP64 context: FP64 product.  MIXED
+ * context: the product the MIXED solve uses, with Y and the basis each split
+ * into three bf16 terms and six term products on the matrix cores (FP32
+ * accumulation per 32 modes, FP64 across them); |error| stays within a few
+ * units of 2^-24 times sum_m |y_m| |basis_m(x)|, returned as double. */
 mlmc_status mlmc_field(mlmc_ctx ctx, const mlmc_points *pts, double *z_dev,
                        void *hip_stream);
 

@@ -32,6 +32,9 @@ struct mlmc_ctx_s {
     uint32_t *d_z = nullptr;
     uint64_t *d_shifts = nullptr;
     double *d_basis = nullptr;   // [s][Mmax]
+    uint16_t *d_bsplit[3] = {};  // mixed mode: bf16 splits of the basis, [Mpad][sp]
+    uint16_t *d_ysplit[3] = {};  // mixed mode: bf16 splits of a chunk's Y, [chunk_pad][sp]
+    int sp = 0;                  // s rounded up to the matrix-core K step
     int64_t Mmax = 0;
     int64_t pool = 0;            // doubles per pool
     double *d_a = nullptr, *d_u = nullptr, *d_f = nullptr;
@@ -753,7 +756,11 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     const int64_t wcap = (c.rtol > 0.0 && fused) ? ctx->pool : 0;
     int nshift_max = std::max(ctx->cfg.num_shifts, 1);
     ctx->state_tuples = (int64_t)nshift_max * ctx->nq * c.num_levels;
-    size_t need = (size_t)ctx->elem * 3 * (size_t)ctx->pool +
+    const bool mixed = c.precision == MLMC_MIXED;
+    if (mixed) ctx->sp = mixed_pad_k(s);
+    const int64_t bsplit = mixed ? mixed_pad_cols(ctx->Mmax) * ctx->sp : 0;
+    const int64_t ysplit = mixed ? mixed_pad_rows(ctx->chunk_max) * ctx->sp : 0;
+    size_t need = (size_t)ctx->elem * 3 * (size_t)ctx->pool + 6 * (size_t)(bsplit + ysplit) +
                   sizeof(double) * ((size_t)s * ctx->Mmax + ctx->ecap + wcap +
                                     (size_t)ctx->chunk_max * (s + c.num_levels * ctx->nq + 2) +
                                     4 * ctx->state_tuples) +
@@ -775,6 +782,10 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
         ctx->d_a = (double *)pa;      // float storage in the mixed mode
         ctx->d_u = (double *)pu;
         ctx->d_f = (double *)pf;
+    }
+    for (int i = 0; i < 3 && mixed; ++i) {
+        CHK(dev_alloc(ctx, &ctx->d_bsplit[i], bsplit));
+        CHK(dev_alloc(ctx, &ctx->d_ysplit[i], ysplit));
     }
     CHK(dev_alloc(ctx, &ctx->d_e, ctx->ecap));
     CHK(dev_alloc(ctx, &ctx->d_w, wcap));
@@ -818,6 +829,11 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     CHK(hipMemcpy(d_mj, ctx->mj.data(), sizeof(int32_t) * s, hipMemcpyHostToDevice));
     launch_build_basis(nullptr, d_psi, d_psi_off, d_mi, d_mj, d_coef, s, Gmax, ctx->d_basis, ctx->Mmax);
     CHK(hipGetLastError());
+    if (mixed) {   // basis row m of the split = field column m, K = KL mode
+        launch_split3(nullptr, ctx->d_basis, ctx->Mmax, s, 1, ctx->Mmax, mixed_pad_cols(ctx->Mmax),
+                      ctx->sp, ctx->d_bsplit);
+        CHK(hipGetLastError());
+    }
     CHK(hipDeviceSynchronize());
     // the 1-D tables are no longer needed
     for (void *p : {(void *)d_psi, (void *)d_coef, (void *)d_psi_off, (void *)d_mi, (void *)d_mj}) {
@@ -879,6 +895,17 @@ mlmc_status mlmc_points_gen(mlmc_ctx ctx, const mlmc_points *pts, uint64_t *x_de
     return MLMC_OK;
 }
 
+namespace {
+// mixed mode: split the chunk's Y into bf16 terms, then the matrix-core product
+void field_bf16x3(mlmc_ctx ctx, hipStream_t s, const double *Y, int64_t M, int64_t Bc, void *out,
+                  int mode)
+{
+    const int sd = ctx->cfg.s;
+    launch_split3(s, Y, Bc, sd, sd, 1, mixed_pad_rows(Bc), ctx->sp, ctx->d_ysplit);
+    launch_field_bf16x3(s, ctx->d_ysplit, ctx->d_bsplit, ctx->sp, M, Bc, out, mode);
+}
+}  // namespace
+
 mlmc_status mlmc_field(mlmc_ctx ctx, const mlmc_points *pts, double *z_dev, void *hip_stream)
 {
     if (!ctx) return MLMC_E_INVAL;
@@ -894,7 +921,10 @@ mlmc_status mlmc_field(mlmc_ctx ctx, const mlmc_points *pts, double *z_dev, void
     for (int64_t b0 = 0; b0 < B; b0 += ctx->chunk_max) {
         int64_t Bc = std::min(ctx->chunk_max, B - b0);
         const double *Y = chunk_y(ctx, s, pts, npts, b0, Bc, nullptr);
-        launch_field_gemm(s, Y, ctx->cfg.s, ctx->d_basis, ctx->Mmax, M, Bc, z_dev + b0 * M, 0);
+        if (ctx->cfg.precision == MLMC_MIXED)
+            field_bf16x3(ctx, s, Y, M, Bc, z_dev + b0 * M, 0);
+        else
+            launch_field_gemm(s, Y, ctx->cfg.s, ctx->d_basis, ctx->Mmax, M, Bc, z_dev + b0 * M, 0);
     }
     HIPCHK(ctx, hipGetLastError());
     return MLMC_OK;
@@ -931,10 +961,17 @@ mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts, const double *z
                 Y = chunk_y(ctx, s, pts, npts, b0, Bc, nullptr);
             }
             const double sd = ctx->cfg.s;
-            ProfScope ps(ctx, s, MLMC_KERNEL_FIELD, 8.0 * (Bc * sd + sd * M + (double)Bc * M),
-                         2.0 * Bc * sd * M);
-            launch_field_gemm(s, Y, ctx->cfg.s, ctx->d_basis, ctx->Mmax, M, Bc, ctx->d_a,
-                              mixed ? 2 : 1);
+            if (mixed) {
+                // six bf16 products per term; operands 3 x 2 bytes, a stored as float
+                ProfScope ps(ctx, s, MLMC_KERNEL_FIELD,
+                             8.0 * Bc * sd + 6.0 * (Bc + (double)M) * sd + 4.0 * Bc * M,
+                             12.0 * Bc * sd * M);
+                field_bf16x3(ctx, s, Y, M, Bc, ctx->d_a, 2);
+            } else {
+                ProfScope ps(ctx, s, MLMC_KERNEL_FIELD, 8.0 * (Bc * sd + sd * M + (double)Bc * M),
+                             2.0 * Bc * sd * M);
+                launch_field_gemm(s, Y, ctx->cfg.s, ctx->d_basis, ctx->Mmax, M, Bc, ctx->d_a, 1);
+            }
         }
         double *q = qoi_dev ? qoi_dev + b0 * nlev * nq : ctx->d_qoi;
         if (!use_fused(ctx))

@@ -45,6 +45,19 @@ void launch_field_gemm(hipStream_t st, const double *Y, int s, const double *bas
 void launch_exp_to_levels(hipStream_t st, const double *z, int64_t M, int64_t Bc, void *pool,
                           bool to_float);
 
+// Mixed-precision field: operands split into three bf16 terms stored
+// K-contiguous ([rows_pad][sp], zero padded; bf16 bit patterns as uint16_t),
+// six-term product on the matrix cores.  mode 0 writes z (double) to
+// out[b*M + m]; mode 2 writes exp(z) as float into the level-major pool.
+int64_t mixed_pad_rows(int64_t rows);
+int64_t mixed_pad_cols(int64_t cols);
+int mixed_pad_k(int s);
+// element (r, k) of X at X[r*rs + k*ks], r < rows, k < cols
+void launch_split3(hipStream_t st, const double *X, int64_t rows, int cols, int64_t rs, int64_t ks,
+                   int64_t rows_pad, int sp, uint16_t *const X3[3]);
+void launch_field_bf16x3(hipStream_t st, uint16_t *const Y[3], uint16_t *const Bs[3], int sp,
+                         int64_t M, int64_t Bc, void *out, int mode);
+
 void launch_coarse_solve(hipStream_t st, const double *a, const double *f, double *u, int64_t Bc,
                          const int32_t *active);
 void launch_rbgs(hipStream_t st, const double *a, const double *f, double *u, int n, int64_t Bc,

@@ -288,13 +288,43 @@ def _mixed_ctx(**over):
     return w, ctx
 
 
+@pytest.mark.parametrize("k,B", [(3, 100), (5, 7)])
+def test_mixed_field_within_split_bound(oracle_mod, k, B):
+    """Mixed-precision field (Section 5 product as three-term bf16 splits on
+    the matrix cores): |z - z_fp64| <= 8 * 2^-24 * sum_j |y_j| |b_j(m)|.
+    The six kept products leave out terms below 2 * 2^-24 |y b|, the split
+    truncation adds at most about 2 * 2^-24 |y b|, and FP32 accumulation over
+    a 32-wide K chunk adds a few units of 2^-24 relative to the absolute sum;
+    chunk sums are added in FP64.  Ragged in both the sample and the column
+    tiles (M and B are not multiples of 128 and 64)."""
+    dev = _dev()
+    w, ctx = _mixed_ctx(num_levels=k + 1)
+    P = _oracle_problem(oracle_mod, w)
+    ys = np.random.default_rng(5 + k).standard_normal((B, w["s"]))
+    pts = ctx.explicit(k, torch.tensor(ys, device=dev))
+    M = ctx.field_size(k)
+    z = torch.full((B, M), float("nan"), dtype=torch.float64, device=dev)
+    ctx.field(pts, z)
+    torch.cuda.synchronize()
+    zg = z.cpu().numpy()
+    basis = np.stack([P.field(np.eye(w["s"])[j], k) for j in range(w["s"])])   # [s][M]
+    worst = 0.0
+    for b in range(B):
+        zo = P.field(ys[b], k)
+        bound = np.abs(ys[b]) @ np.abs(basis)
+        worst = max(worst, float(np.max(np.abs(zg[b] - zo) / bound)))
+    print(f"\nmax |z - z_fp64| / sum|y||b| = {worst:.3e} (= {worst * 2**24:.2f} * 2^-24)")
+    assert worst <= 8 * 2.0**-24
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_refinement_high_contrast_matches_direct_solve(oracle_mod, precision):
     """sigma^2 = 2, lambda = 0.1, s = 400: FP64 residual refinement to 1e-10
     with FP64 or FP32 V-cycles, against the oracle's FP64 field and band
     Cholesky solve on every level up to 128^2 (the batched tile path).  The
-    mixed-precision error is the FP32 rounding of the coefficient plus the
-    solve tolerance; it is reported per level."""
+    mixed-precision error is that of the bf16x3 field (a few 2^-24 relative
+    to sum |y||b|) and of its FP32 storage plus the solve tolerance; it is
+    reported per level (about 4e-8 relative here)."""
     dev = _dev()
     prec = m.MLMC_MIXED if precision == "mixed" else m.MLMC_FP64
     w, ctx = _mixed_ctx(precision=prec)
@@ -310,5 +340,5 @@ def test_refinement_high_contrast_matches_direct_solve(oracle_mod, precision):
         qd = P.sample(k, ys[b], 1)
         errs = np.maximum(errs, np.abs(qg[b] - qd) / np.abs(qd))
     print(f"\n{precision}: max relative QoI error per level (mean, centre):\n{errs}")
-    tol = 1e-9 if precision == "fp64" else 2e-6
+    tol = 1e-9 if precision == "fp64" else 2e-7
     assert errs.max() <= tol, errs
