@@ -575,12 +575,71 @@ static void vcycle(fmg_state *S, int g, double *u, const double *f)
     }
 }
 
-static double norm2(int64_t m, const double *v)
+static double dot(int64_t m, const double *x, const double *y)
 {
     ksum k = {0.0, 0.0};
     for (int64_t p = 0; p < m; ++p)
-        ksum_add(&k, v[p] * v[p]);
-    return sqrt(k.s + k.c);
+        ksum_add(&k, x[p] * y[p]);
+    return k.s + k.c;
+}
+
+static double norm2(int64_t m, const double *v)
+{
+    return sqrt(dot(m, v, v));
+}
+
+/* rtol mode, one FMG stage on level g: solve A_g x = 1 from the interpolated
+ * initial guess x to ||1 - A x||_2 / ||1||_2 <= rtol.  The paper runs a
+ * fixed number of V-cycles per stage and says nothing about iterating to a
+ * tolerance; this mode is flexible preconditioned conjugate gradients with one
+ * V(mu1, mu2) cycle from a zero initial guess as the preconditioner z = B r
+ * (Notay, SIAM J. Sci. Comput. 22 (2000): beta = (z, r - r_old) / (z_old,
+ * r_old)), and the residual is recomputed from x at every step.  Returns the
+ * number of preconditioner applications; *relres gets the final ratio;
+ * *bad = 1 if max_iters was reached first. */
+static int stage_refine(fmg_state *S, int g, double *x, const double *ones, double *relres,
+                        int *bad)
+{
+    int n = 2 << g;
+    int64_t m = (int64_t)n * n;
+    double *r = (double *)malloc(sizeof(double) * m);
+    double *r_old = (double *)malloc(sizeof(double) * m);
+    double *z = (double *)malloc(sizeof(double) * m);
+    double *p = (double *)calloc(m, sizeof(double));
+    double *q = (double *)malloc(sizeof(double) * m);
+    double nf = norm2(m, ones), rz_old = 0.0;
+    int it = 0;
+    residual(n, S->a[g], ones, x, r);
+    double rho = norm2(m, r) / nf;
+    *bad = 0;
+    while (rho > S->P->rtol) {
+        if (it >= S->P->max_iters) {
+            *bad = 1;
+            break;
+        }
+        memset(z, 0, sizeof(double) * m);
+        vcycle(S, g, z, r);                            /* z = B r */
+        double rz = dot(m, r, z);
+        double beta = it == 0 ? 0.0 : (rz - dot(m, r_old, z)) / rz_old;
+        for (int64_t i = 0; i < m; ++i)
+            p[i] = z[i] + beta * p[i];
+        oracle_apply(n, S->a[g], p, q);                /* q = A p */
+        double alpha = rz / dot(m, p, q);
+        for (int64_t i = 0; i < m; ++i)
+            x[i] += alpha * p[i];
+        memcpy(r_old, r, sizeof(double) * m);
+        residual(n, S->a[g], ones, x, r);
+        rho = norm2(m, r) / nf;
+        rz_old = rz;
+        ++it;
+    }
+    *relres = rho;
+    free(r);
+    free(r_old);
+    free(z);
+    free(p);
+    free(q);
+    return it;
 }
 
 int oracle_fmg(const oracle_problem *P, int G, const double *a_all,
@@ -596,7 +655,6 @@ int oracle_fmg(const oracle_problem *P, int G, const double *a_all,
     S.cap = trace_cap;
     double *sol[32];
     double *ones[32];
-    double *corr = NULL;
     int64_t off = 0;
     for (int g = 0; g <= G; ++g) {
         int64_t m = (int64_t)(2 << g) * (2 << g);
@@ -610,7 +668,6 @@ int oracle_fmg(const oracle_problem *P, int G, const double *a_all,
             ones[g][p] = 1.0;
         off += m;
     }
-    corr = (double *)calloc((size_t)(2 << G) * (2 << G), sizeof(double));
     int noconv = 0;
 
     /* initial descent of the FMG figure: problem set-up on every level */
@@ -627,22 +684,11 @@ int oracle_fmg(const oracle_problem *P, int G, const double *a_all,
             trace_visit(&S, g);
             prolong(n / 2, sol[g - 1], sol[g], 0);
             if (P->rtol > 0.0) {
-                /* iterative refinement in correction form until
-                 * ||f - A u||_2 / ||f||_2 <= rtol */
-                int it = 0;
-                for (;;) {
-                    residual(n, S.a[g], ones[g], sol[g], S.r[g]);
-                    double rho = norm2(m, S.r[g]) / norm2(m, ones[g]);
-                    if (relres) relres[g] = rho;
-                    if (rho <= P->rtol) break;
-                    if (it >= P->max_iters) { noconv = 1; break; }
-                    memcpy(S.f[g], S.r[g], sizeof(double) * m);
-                    memset(corr, 0, sizeof(double) * m);
-                    vcycle(&S, g, corr, S.f[g]);
-                    for (int64_t p = 0; p < m; ++p)
-                        sol[g][p] += corr[p];
-                    ++it;
-                }
+                double rho;
+                int bad;
+                int it = stage_refine(&S, g, sol[g], ones[g], &rho, &bad);
+                noconv |= bad;
+                if (relres) relres[g] = rho;
                 if (iters) iters[g] = it;
             } else {
                 for (int c = 0; c < P->mu0; ++c)
@@ -676,7 +722,6 @@ int oracle_fmg(const oracle_problem *P, int G, const double *a_all,
         free(sol[g]);
         free(ones[g]);
     }
-    free(corr);
     return noconv;
 }
 

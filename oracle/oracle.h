@@ -71,7 +71,8 @@ void oracle_qoi(int n, const double *u, double *q_mean, double *q_ctr);
 /* ---- Section 4: full multigrid with all coarse solutions kept ---------- */
 /* a_all: exp(z) on levels 0..G (level-major).  f = 1 on every level.
  * qoi [G+1][2]: QoI of the solution at the end of every FMG stage.
- * iters[G+1], relres[G+1]: per stage refinement iterations and final
+ * iters[G+1], relres[G+1]: per stage iterations (mu0 with fixed cycles; in
+ * rtol mode the flexible-CG steps, one V-cycle each) and the final
  * ||f - A u||_2 / ||f||_2 (relres only computed when rtol > 0, else -1).
  * u_out: final solution on level G (n_G^2), may be NULL.
  * trace/marks: visited levels (consecutive repeats merged) and 1 where the

@@ -163,17 +163,44 @@ def test_fmg_rtol_matches_direct(oracle_mod, cfg):
 
 def test_fmg_rtol_high_contrast(oracle_mod):
     """sigma^2 = 2, lambda = 0.1: FMG refinement still meets 1e-10 against the
-    direct solve.  Rediscretised coarse operators converge slowly for this
-    contrast (about 0.5 per V-cycle), so only a loose iteration bound holds."""
+    direct solve, in few flexible-CG steps."""
     P = oracle_mod.Problem(4, 6, 400, 0.1, 2.0, mu0=1, mu1=2, mu2=2, rtol=1e-10, max_iters=40)
     k = 4
     for z in _lognormal_fields(oracle_mod, P, k, 2, 23):
         fm = P.sample_from_field(k, z, 0)
         dr = P.sample_from_field(k, z, 1)
         assert fm["status"] == 0
-        assert np.max(fm["iters"]) <= 40
+        assert np.max(fm["iters"]) <= 25
         rel = np.abs(fm["qoi"] - dr["qoi"]) / np.abs(dr["qoi"])
         assert np.max(rel) <= 1e-9, rel
+
+
+def test_fmg_rtol_rough_lattice_samples_all_converge(oracle_mod):
+    """The s = 400, lambda = 0.1, sigma^2 = 2 lattice workload: coarse grids
+    (h >= lambda) see coefficients that the rediscretised coarse operators
+    represent badly, and plain V-cycle iteration on the residual diverges for
+    a sizeable share of these samples (roughly one in five at 16^2 and 32^2).
+    V-cycle-preconditioned flexible CG converges on every sample, and each
+    converged stage agrees with the band Cholesky solve."""
+    w = synth.workload("mlqmc_mixed_s400")
+    P = oracle_mod.Problem(w["n0"], 4, w["s"], w["corr_len"], w["sigma2"], mu0=w["mu0"],
+                           mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"], max_iters=w["max_iters"])
+    zv = synth.korobov_vector(w["seed"], w["s"])
+    D = synth.shift_table(w["seed"], w["num_levels"], w["num_shifts"], w["s"])
+    for k in range(4):
+        _, y = oracle_mod.points(zv, D[k, 0], 0, 96)
+        worst_it = 0
+        for b in range(len(y)):
+            z = P.field(y[b], k)
+            fm = P.sample_from_field(k, z, 0)
+            assert fm["status"] == 0, (k, b, fm)
+            assert np.all(fm["relres"][1:] <= w["rtol"])
+            worst_it = max(worst_it, int(np.max(fm["iters"])))
+            if b % 8 == 0:
+                dr = P.sample_from_field(k, z, 1)
+                rel = np.abs(fm["qoi"] - dr["qoi"]) / np.abs(dr["qoi"])
+                assert np.max(rel) <= 1e-8, (k, b, rel)
+        assert worst_it <= 30, (k, worst_it)
 
 
 def test_fmg_fixed_cycles_reach_discretisation_accuracy(oracle_mod):
@@ -205,8 +232,8 @@ def test_fmg_constant_coefficient_matches_series_order(oracle_mod):
 
 
 def test_vcycle_convergence_is_mesh_independent(oracle_mod):
-    """a = 1: refinement to 1e-12 takes the same few V(2,2) cycles on every
-    level (h-independent multigrid convergence, about 0.1 per cycle)."""
+    """a = 1: refinement to 1e-12 takes the same few V(2,2)-preconditioned
+    steps on every level (h-independent multigrid convergence)."""
     P = oracle_mod.Problem(4, 7, 4, 0.3, 0.0, mu0=1, mu1=2, mu2=2, rtol=1e-12, max_iters=60)
     r = P.sample_from_field(6, np.zeros(P.field_size(6)), 0)
     assert r["status"] == 0
