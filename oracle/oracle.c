@@ -345,16 +345,20 @@ static double nbr(int n, const double *u, int i, int j)
     return u[i + n * j];
 }
 
+/* (A u)_P = h^-2 times the net flux out of cell P, summed face by face: an
+ * interior face contributes w_f (u_P - u_N), a wall face 2 a_P u_P.  Summing
+ * the differences, rather than D u_P minus the neighbour terms, keeps the
+ * rounding error proportional to the fluxes instead of to a_P u_P / h^2. */
 void oracle_apply(int n, const double *a, const double *u, double *out)
 {
     double inv_h2 = (double)n * (double)n;
     for (int j = 0; j < n; ++j)
         for (int i = 0; i < n; ++i) {
-            double wE, wW, wN, wS, d;
-            stencil(n, a, i, j, &wE, &wW, &wN, &wS, &d);
-            double v = d * u[i + n * j] - wE * nbr(n, u, i + 1, j) -
-                       wW * nbr(n, u, i - 1, j) - wN * nbr(n, u, i, j + 1) -
-                       wS * nbr(n, u, i, j - 1);
+            double ap = a[i + n * j], up = u[i + n * j], v = 0.0;
+            v += i + 1 < n ? hmean(ap, a[i + 1 + n * j]) * (up - u[i + 1 + n * j]) : 2.0 * ap * up;
+            v += i > 0 ? hmean(ap, a[i - 1 + n * j]) * (up - u[i - 1 + n * j]) : 2.0 * ap * up;
+            v += j + 1 < n ? hmean(ap, a[i + n * (j + 1)]) * (up - u[i + n * (j + 1)]) : 2.0 * ap * up;
+            v += j > 0 ? hmean(ap, a[i + n * (j - 1)]) * (up - u[i + n * (j - 1)]) : 2.0 * ap * up;
             out[i + n * j] = inv_h2 * v;
         }
 }

@@ -53,7 +53,7 @@ class mlmc_profile_result(C.Structure):
 
 
 MLMC_KERNEL = dict(points=0, field=1, smooth=2, restrict=3, prolong=4, coarse=5, qoi=6, sums=7,
-                   pre=8, post=9, lds=10)
+                   pre=8, post=9, lds=10, refine=11)
 
 
 class mlmc_est_input(C.Structure):

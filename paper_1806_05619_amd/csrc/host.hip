@@ -38,8 +38,10 @@ struct mlmc_ctx_s {
     int64_t Mmax = 0;
     int64_t pool = 0;            // doubles per pool
     double *d_a = nullptr, *d_u = nullptr, *d_f = nullptr;
-    double *d_e = nullptr;       // rtol: top-level correction, ecap doubles
-    int64_t ecap = 0;
+    double *d_fcg = nullptr;     // rtol on grids >= 64^2: r, r_old, p of a chunk's top level
+    int64_t fcg_cells = 0;       // cells per vector (samples x top-level cells)
+    double *d_part = nullptr;    // per-block partial sums of those passes
+    double *d_fs = nullptr;      // per-sample CG scalars (4 doubles)
     int64_t chunk_max = 0;       // upper bound of samples per chunk
     double *d_y = nullptr;       // [chunk_max][s]
     double *d_qoi = nullptr;     // [chunk_max][num_levels][nq]
@@ -173,8 +175,8 @@ int64_t chunk_capacity(mlmc_ctx c, int k)
 {
     int G = c->g0 + k;
     int64_t cap = c->pool / field_size_g(G);
-    if (c->cfg.rtol > 0.0 && !fused_supported(c->cfg.mu1, c->cfg.mu2))
-        cap = std::min(cap, c->ecap / level_cells(G));
+    if (c->cfg.rtol > 0.0 && G > kLdsMaxLevel)
+        cap = std::min(cap, c->fcg_cells / level_cells(G));
     return std::max<int64_t>(1, std::min(cap, c->chunk_max));
 }
 
@@ -368,43 +370,9 @@ mlmc_status run_fmg(mlmc_ctx c, hipStream_t st, const Hier &h, int k, double *qo
         if (tr) tr->visit(g);
         // nested iteration: interpolate the previous stage's solution
         if (!tr) R.prolong(g, h.u[g - 1], h.u[g], 0, nullptr);
-        if (c->cfg.rtol <= 0.0) {
-            for (int cyc = 0; cyc < c->cfg.mu0; ++cyc) R.vcycle(g, h.u[g], nullptr);
-            if (stats) stats->max_iters = std::max(stats->max_iters, c->cfg.mu0);
-        } else {
-            // FP64 refinement in correction form: r = 1 - A u, stop when
-            // ||r||/||f|| <= rtol, else e = V(0; r), u += e.
-            launch_fill_i32(st, c->d_active, h.Bc, 1);
-            launch_fill_i32(st, c->d_iters, h.Bc, 0);
-            R.active = c->d_active;
-            for (;;) {
-                launch_residual_norm(st, h.a[g], h.u[g], n, h.Bc, h.f[g], c->d_rho, c->d_active,
-                                     c->d_iters, c->cfg.rtol, c->cfg.max_iters, nullptr);
-                HIPCHK(c, hipMemcpyAsync(c->h_active, c->d_active, sizeof(int32_t) * h.Bc,
-                                         hipMemcpyDeviceToHost, st));
-                HIPCHK(c, hipStreamSynchronize(st));
-                int64_t nact = 0;
-                for (int64_t b = 0; b < h.Bc; ++b) nact += c->h_active[b];
-                if (nact == 0)
-                    break;
-                launch_fill(st, c->d_e, h.Bc * (int64_t)n * n, 0.0);
-                R.vcycle(g, c->d_e, h.f[g]);
-                launch_axpy_active(st, h.u[g], c->d_e, n, h.Bc, c->d_active);
-            }
-            R.active = nullptr;
-            HIPCHK(c, hipMemcpyAsync(c->h_iters, c->d_iters, sizeof(int32_t) * h.Bc,
-                                     hipMemcpyDeviceToHost, st));
-            HIPCHK(c, hipMemcpyAsync(c->h_rho, c->d_rho, sizeof(double) * h.Bc,
-                                     hipMemcpyDeviceToHost, st));
-            HIPCHK(c, hipStreamSynchronize(st));
-            if (stats) {
-                for (int64_t b = 0; b < h.Bc; ++b) {
-                    stats->max_iters = std::max(stats->max_iters, (int)c->h_iters[b]);
-                    stats->max_rho = std::max(stats->max_rho, c->h_rho[b]);
-                    if (c->h_rho[b] > c->cfg.rtol) stats->bad[b] = 1;
-                }
-            }
-        }
+        // fixed cycles (rtol mode needs the fused passes, checked at create)
+        for (int cyc = 0; cyc < c->cfg.mu0; ++cyc) R.vcycle(g, h.u[g], nullptr);
+        if (stats) stats->max_iters = std::max(stats->max_iters, c->cfg.mu0);
         if (tr) tr->record();
         if (!tr && g >= g0) {
             ProfScope ps(c, st, MLMC_KERNEL_QOI, 8.0 * R.cells(n), 0.0);
@@ -428,8 +396,15 @@ int large_pass_override()
     }
     return mode;
 }
+// The row-streaming pass runs one workgroup per sample, so it needs a batch
+// that fills the chip (a few workgroups per CU) before it beats the tiles.
+constexpr int64_t kStreamMinBatch = 1024;
 bool pre_uses_stream(int n) { return large_pass_override() == 1 && stream_supported(n); }
-bool post_uses_stream(int n) { return large_pass_override() != 0 && stream_supported(n); }
+bool post_uses_stream(int n, int64_t Bc)
+{
+    const int o = large_pass_override();
+    return stream_supported(n) && (o == 1 || (o == -1 && Bc >= kStreamMinBatch));
+}
 
 // ---- fused schedule: LDS-resident grids <= 32^2, tile passes above --------
 // Typed views of one chunk's pools: a, u, f in the V-cycle type T; w holds the
@@ -507,7 +482,7 @@ struct FusedRunner {
             T *u = (l == g) ? top_u : h.u[l];
             ProfScope ps(c, st, MLMC_KERNEL_POST, W * cells(n) * (3.25 + (f ? 1.0 : 0.0)), 0.0);
             if constexpr (std::is_same<T, double>::value) {
-                if (post_uses_stream(n)) {
+                if (post_uses_stream(n, h.Bc)) {
                     launch_post_stream(st, c->cfg.mu2, h.a[l], f, u, h.u[l - 1], n, h.Bc, active);
                     continue;
                 }
@@ -567,14 +542,17 @@ mlmc_status run_fmg_refine(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k,
             ProfScope ps(c, st, MLMC_KERNEL_PROLONG, 8.0 * R.cells(n) * 1.25, 0.0);
             launch_prolong(st, h.w[g - 1], h.w[g], n, Bc, 0, nullptr);
         }
-        launch_fill_i32(st, c->d_active, Bc, 1);
-        launch_fill_i32(st, c->d_iters, Bc, 0);
+        // flexible CG on level g from x = P x_prev, preconditioner z = V(0; r)
+        const int64_t cells = (int64_t)n * n;
+        double *r = c->d_fcg, *ro = r + Bc * cells, *pv = ro + Bc * cells;
+        const double vec = R.cells(n);   // cells of all samples of the chunk
+        {
+            ProfScope ps(c, st, MLMC_KERNEL_REFINE, vec * (R.W + 8.0 + 8.0 + R.W), 0.0);
+            launch_fcg_resid<T>(st, h.a[g], h.w[g], n, Bc, r, h.f[g], c->d_part, nullptr);
+        }
+        launch_fcg_fin_rho(st, c->d_part, n, Bc, c->d_rho, c->d_active, c->d_iters, c->cfg.rtol,
+                           c->cfg.max_iters, 1);
         for (;;) {
-            {
-                ProfScope ps(c, st, MLMC_KERNEL_RESTRICT, R.cells(n) * (R.W + 8.0 + R.W), 0.0);
-                launch_refine_residual<T>(st, h.a[g], h.w[g], n, Bc, h.f[g], c->d_rho, c->d_active,
-                                          c->d_iters, c->cfg.rtol, c->cfg.max_iters);
-            }
             HIPCHK(c, hipMemcpyAsync(c->h_active, c->d_active, sizeof(int32_t) * Bc,
                                      hipMemcpyDeviceToHost, st));
             HIPCHK(c, hipStreamSynchronize(st));
@@ -582,7 +560,19 @@ mlmc_status run_fmg_refine(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k,
             for (int64_t b = 0; b < Bc; ++b) nact += c->h_active[b];
             if (nact == 0) break;
             R.vcycle(g, h.u[g], 1, h.f[g], c->d_active);
-            launch_refine_update<T>(st, h.w[g], h.u[g], n, Bc, c->d_active);
+            {
+                // dots (z, r, r_old; r_old written), p update, (p, A p), x update
+                ProfScope ps(c, st, MLMC_KERNEL_REFINE,
+                             vec * ((R.W + 24.0) + (R.W + 16.0) + (R.W + 8.0) + 24.0), 0.0);
+                launch_fcg_step<T>(st, h.a[g], h.u[g], h.w[g], r, ro, pv, n, Bc, c->d_part,
+                                   c->d_fs, c->d_active, c->d_iters);
+            }
+            {
+                ProfScope ps(c, st, MLMC_KERNEL_REFINE, vec * (R.W + 8.0 + 8.0 + R.W), 0.0);
+                launch_fcg_resid<T>(st, h.a[g], h.w[g], n, Bc, r, h.f[g], c->d_part, c->d_active);
+            }
+            launch_fcg_fin_rho(st, c->d_part, n, Bc, c->d_rho, c->d_active, c->d_iters,
+                               c->cfg.rtol, c->cfg.max_iters, 0);
         }
         launch_refine_stats(st, c->d_iters, c->d_rho, Bc, c->cfg.rtol, c->d_st_iters, c->d_st_rho,
                             c->d_st_bad);
@@ -660,8 +650,8 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     if (c.precision != MLMC_FP64 && c.precision != MLMC_MIXED) return bad("unknown precision");
     if (c.precision == MLMC_MIXED && !(c.rtol > 0.0))
         return bad("MLMC_MIXED refines an FP64 residual: it needs rtol > 0");
-    if (c.precision == MLMC_MIXED && !fused_supported(c.mu1, c.mu2))
-        return bad("MLMC_MIXED supports mu1, mu2 in {1, 2}");
+    if (c.rtol > 0.0 && !fused_supported(c.mu1, c.mu2))
+        return bad("rtol > 0 supports mu1, mu2 in {1, 2}");
     if (c.qoi_mask == 0 || (c.qoi_mask & ~3u)) return bad("qoi_mask must be a non-empty subset of {MEAN, CENTER}");
     if (c.max_batch < 1) return bad("max_batch must be >= 1");
     bool lattice = c.genvec && c.shifts;
@@ -751,9 +741,12 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     ctx->pool = c.max_batch * ctx->Mmax;          // elements per pool
     ctx->elem = c.precision == MLMC_MIXED ? 4 : 8;
     ctx->chunk_max = std::max<int64_t>(c.max_batch, 65536);
-    const bool fused = fused_supported(c.mu1, c.mu2);
-    if (c.rtol > 0.0 && !fused) ctx->ecap = c.max_batch * level_cells(Gmax);
-    const int64_t wcap = (c.rtol > 0.0 && fused) ? ctx->pool : 0;
+    const int64_t wcap = c.rtol > 0.0 ? ctx->pool : 0;
+    if (c.rtol > 0.0 && Gmax > kLdsMaxLevel) ctx->fcg_cells = c.max_batch * level_cells(Gmax);
+    // partial sums: 4 doubles per 1024-cell block, blocks of at most chunk_max samples
+    const int64_t parts = ctx->fcg_cells > 0 ? fcg_partials(64, ctx->chunk_max) +
+                                                   4 * (ctx->fcg_cells / 1024 + 1)
+                                             : 0;
     int nshift_max = std::max(ctx->cfg.num_shifts, 1);
     ctx->state_tuples = (int64_t)nshift_max * ctx->nq * c.num_levels;
     const bool mixed = c.precision == MLMC_MIXED;
@@ -761,7 +754,7 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     const int64_t bsplit = mixed ? mixed_pad_cols(ctx->Mmax) * ctx->sp : 0;
     const int64_t ysplit = mixed ? mixed_pad_rows(ctx->chunk_max) * ctx->sp : 0;
     size_t need = (size_t)ctx->elem * 3 * (size_t)ctx->pool + 6 * (size_t)(bsplit + ysplit) +
-                  sizeof(double) * ((size_t)s * ctx->Mmax + ctx->ecap + wcap +
+                  sizeof(double) * ((size_t)s * ctx->Mmax + 3 * ctx->fcg_cells + parts + wcap +
                                     (size_t)ctx->chunk_max * (s + c.num_levels * ctx->nq + 2) +
                                     4 * ctx->state_tuples) +
                   sizeof(int32_t) * 4 * ctx->chunk_max;
@@ -787,7 +780,9 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
         CHK(dev_alloc(ctx, &ctx->d_bsplit[i], bsplit));
         CHK(dev_alloc(ctx, &ctx->d_ysplit[i], ysplit));
     }
-    CHK(dev_alloc(ctx, &ctx->d_e, ctx->ecap));
+    CHK(dev_alloc(ctx, &ctx->d_fcg, 3 * ctx->fcg_cells));
+    CHK(dev_alloc(ctx, &ctx->d_part, parts));
+    CHK(dev_alloc(ctx, &ctx->d_fs, ctx->fcg_cells > 0 ? 4 * ctx->chunk_max : 0));
     CHK(dev_alloc(ctx, &ctx->d_w, wcap));
     CHK(dev_alloc(ctx, &ctx->d_st_iters, ctx->chunk_max));
     CHK(dev_alloc(ctx, &ctx->d_st_bad, ctx->chunk_max));
@@ -1038,7 +1033,7 @@ mlmc_status mlmc_profile_begin(mlmc_ctx ctx, int32_t kernel_kind)
 {
     if (!ctx) return MLMC_E_INVAL;
     if (ctx->host_only) return MLMC_E_STATE;
-    if (kernel_kind < MLMC_KERNEL_POINTS || kernel_kind > MLMC_KERNEL_LDS)
+    if (kernel_kind < MLMC_KERNEL_POINTS || kernel_kind > MLMC_KERNEL_REFINE)
         return inval(ctx, "unknown kernel kind");
     ctx->prof.kind = kernel_kind;
     ctx->prof.used = 0;

@@ -73,13 +73,6 @@ void launch_fill_i32(hipStream_t st, int32_t *p, int64_t count, int32_t v);
 void launch_sums(hipStream_t st, const double *qoi, int nlev, int nq, int64_t b0, int64_t Bc,
                  int64_t npts, int nshift, double *state);
 void launch_sums_final(hipStream_t st, const double *state, int64_t count, double *out);
-// rtol refinement (FP64): r = 1 - A u on level n, rho_b = ||r||/||1||; then
-// active_b = rho_b > rtol && iters_b < max_iters (iters_b counted here).
-void launch_residual_norm(hipStream_t st, const double *a, const double *u, int n, int64_t Bc,
-                          double *r, double *rho, int32_t *active, int32_t *iters, double rtol,
-                          int max_iters, int32_t *n_active);
-void launch_axpy_active(hipStream_t st, double *u, const double *e, int n, int64_t Bc,
-                        const int32_t *active);
 
 // ---- fused kernels (kernels_fused.hip), T = double or float ----
 bool fused_supported(int mu1, int mu2);
@@ -99,21 +92,30 @@ void launch_lds_fmg_fixed(hipStream_t st, const double *a_pool, double *u_pool, 
 template <typename T>
 void launch_lds_vcycle(hipStream_t st, const T *a_pool, const T *f_pool, T *u_pool, int64_t Bc,
                        int G, int mu1, int mu2, const int32_t *active);
-// FMG stages 0..G with FP64-residual refinement of T V-cycles; u64 of level G
-// to u64_pool; per-sample statistics
+// FMG stages 0..G, each stage g >= 1 solved to rtol by flexible CG in FP64
+// with one T V-cycle as the preconditioner; x of level G to u64_pool;
+// per-sample statistics
 template <typename T>
 void launch_lds_fmg_refine(hipStream_t st, const T *a_pool, double *u64_pool, int64_t Bc, int G,
                            int mu1, int mu2, double rtol, int max_iters, int g0, double *qoi,
                            int nlev, uint32_t mask, int32_t *st_iters, double *st_rho,
                            int32_t *st_bad);
-// refinement on a large grid: FP64 residual -> f (T), norms and flags; u64 += e
+// flexible CG of one stage on a large grid (Bc samples of n x n, FP64 vectors
+// x, r, r_old, p; z from the T V-cycle).  Partial-sum scratch: fcg_partials
+// doubles; fs: 4 doubles per sample.
+int64_t fcg_partials(int n, int64_t Bc);
+// r = 1 - A x, f = T(r), partial ||r||^2 (active nullptr: every sample)
 template <typename T>
-void launch_refine_residual(hipStream_t st, const T *a, const double *u, int n, int64_t Bc, T *f,
-                            double *rho, int32_t *active, int32_t *iters, double rtol,
-                            int max_iters);
+void launch_fcg_resid(hipStream_t st, const T *a, const double *x, int n, int64_t Bc, double *r, T *f,
+                      double *part, const int32_t *active);
+// rho = ||r||/||1||; active = rho > rtol && iters < max_iters; iters counts steps
+void launch_fcg_fin_rho(hipStream_t st, const double *part, int n, int64_t Bc, double *rho,
+                        int32_t *active, int32_t *iters, double rtol, int max_iters, int first);
+// one step after z = B r: beta, p = z + beta p, alpha = (r, z)/(p, A p), x += alpha p
 template <typename T>
-void launch_refine_update(hipStream_t st, double *u, const T *e, int n, int64_t Bc,
-                          const int32_t *active);
+void launch_fcg_step(hipStream_t st, const T *a, const T *z, double *x, double *r, double *ro,
+                     double *pv, int n, int64_t Bc, double *part, double *fs,
+                     const int32_t *active, const int32_t *iters);
 void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho, int64_t Bc,
                          double rtol, int32_t *st_iters, double *st_rho, int32_t *st_bad);
 

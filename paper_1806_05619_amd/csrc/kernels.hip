@@ -286,14 +286,15 @@ __device__ __forceinline__ double residual_at(const double *ab, const double *fb
                                               const double *ub, int n, int i, int j,
                                               double inv_h2)
 {
+    // net flux out of the cell, face by face: w (u_P - u_N), or 2 a_P u_P at a wall
     const int p = i + n * j;
-    const double ap = ab[p];
-    double d = 0.0, off = 0.0, w;
-    if (i + 1 < n) { w = harmonic(ap, ab[p + 1]); d += w; off += w * ub[p + 1]; } else d += 2.0 * ap;
-    if (i > 0)     { w = harmonic(ap, ab[p - 1]); d += w; off += w * ub[p - 1]; } else d += 2.0 * ap;
-    if (j + 1 < n) { w = harmonic(ap, ab[p + n]); d += w; off += w * ub[p + n]; } else d += 2.0 * ap;
-    if (j > 0)     { w = harmonic(ap, ab[p - n]); d += w; off += w * ub[p - n]; } else d += 2.0 * ap;
-    return (fb ? fb[p] : 1.0) - inv_h2 * (d * ub[p] - off);
+    const double ap = ab[p], up = ub[p];
+    double v = 0.0;
+    v += (i + 1 < n) ? harmonic(ap, ab[p + 1]) * (up - ub[p + 1]) : 2.0 * ap * up;
+    v += (i > 0) ? harmonic(ap, ab[p - 1]) * (up - ub[p - 1]) : 2.0 * ap * up;
+    v += (j + 1 < n) ? harmonic(ap, ab[p + n]) * (up - ub[p + n]) : 2.0 * ap * up;
+    v += (j > 0) ? harmonic(ap, ab[p - n]) * (up - ub[p - n]) : 2.0 * ap * up;
+    return (fb ? fb[p] : 1.0) - inv_h2 * v;
 }
 
 // r = f - A u on the fine grid, restricted by the 4-cell mean to fc; the
@@ -452,55 +453,6 @@ __global__ void k_sums_final(const double *__restrict__ state, int64_t count,
     out[2 * t + 1] = state[4 * t + 2] + state[4 * t + 3];
 }
 
-// FP64 residual of the top level (f = 1) with per-sample relative norm and
-// the convergence flags of the refinement loop.  One wavefront per sample.
-__global__ __launch_bounds__(256) void k_residual_norm(const double *__restrict__ a,
-                                                       const double *__restrict__ u, int n,
-                                                       int64_t Bc, double *__restrict__ r,
-                                                       double *__restrict__ rho,
-                                                       int32_t *__restrict__ active,
-                                                       int32_t *__restrict__ iters, double rtol,
-                                                       int max_iters)
-{
-    const int lane = threadIdx.x & 63;
-    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-    if (b >= Bc)
-        return;
-    if (!active[b])
-        return;
-    const int64_t cells = (int64_t)n * n;
-    const int64_t base = b * cells;
-    const double inv_h2 = (double)n * (double)n;
-    Comp k{0.0, 0.0};
-    for (int64_t p = lane; p < cells; p += 64) {
-        int j = (int)(p / n), i = (int)(p - (int64_t)j * n);
-        double rv = residual_at(a + base, nullptr, u + base, n, i, j, inv_h2);
-        r[base + p] = rv;
-        comp_add(k, rv * rv);
-    }
-    k = wave_reduce(k);
-    if (lane == 0) {
-        double v = sqrt(k.s + k.c) / (double)n;   // ||f||_2 = n for f = 1
-        rho[b] = v;
-        int it = iters[b];
-        int go = (v > rtol) && (it < max_iters);
-        active[b] = go;
-        if (go)
-            iters[b] = it + 1;
-    }
-}
-
-__global__ void k_axpy_active(double *__restrict__ u, const double *__restrict__ e, int n,
-                              int64_t Bc, const int32_t *__restrict__ active)
-{
-    const int64_t per = (int64_t)n * n;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= Bc * per)
-        return;
-    if (!active[t / per])
-        return;
-    u[t] += e[t];
-}
 
 }  // namespace
 
@@ -603,20 +555,5 @@ void launch_sums_final(hipStream_t st, const double *state, int64_t count, doubl
                        out);
 }
 
-void launch_residual_norm(hipStream_t st, const double *a, const double *u, int n, int64_t Bc,
-                          double *r, double *rho, int32_t *active, int32_t *iters, double rtol,
-                          int max_iters, int32_t *)
-{
-    hipLaunchKernelGGL(k_residual_norm, dim3(blocks_for(Bc, kBlock / 64)), dim3(kBlock), 0, st, a,
-                       u, n, Bc, r, rho, active, iters, rtol, max_iters);
-}
-
-void launch_axpy_active(hipStream_t st, double *u, const double *e, int n, int64_t Bc,
-                        const int32_t *active)
-{
-    int64_t cnt = Bc * (int64_t)n * n;
-    hipLaunchKernelGGL(k_axpy_active, dim3(blocks_for(cnt)), dim3(kBlock), 0, st, u, e, n, Bc,
-                       active);
-}
 
 }  // namespace mlmc

@@ -99,7 +99,8 @@ struct CoarseStage {
 template <typename T>
 struct Cell {
     int l;                        // LDS index li + S*lj, -1 if not owned / outside
-    T wE, wW, wN, wS, d, inv, rhs;   // d = sum of face weights, rhs = h^2 f
+    T wE, wW, wN, wS, dw, inv, rhs;  // face weights (0 at a wall), wall term
+                                     // 2 a_P per wall face, 1 / diagonal, h^2 f
 };
 
 template <int S, typename T>
@@ -108,13 +109,13 @@ __device__ __forceinline__ void make_cell(Cell<T> &c, const T *a_s, int li, int 
 {
     const int l = li + S * lj;
     const T ap = a_s[l];
-    T d = T(0);
+    T d = T(0), dw = T(0);
     c.wE = c.wW = c.wN = c.wS = T(0);
-    if (gi + 1 < n) { c.wE = hm(ap, a_s[l + 1]); d += c.wE; } else d += T(2) * ap;
-    if (gi > 0)     { c.wW = hm(ap, a_s[l - 1]); d += c.wW; } else d += T(2) * ap;
-    if (gj + 1 < n) { c.wN = hm(ap, a_s[l + S]); d += c.wN; } else d += T(2) * ap;
-    if (gj > 0)     { c.wS = hm(ap, a_s[l - S]); d += c.wS; } else d += T(2) * ap;
-    c.d = d;
+    if (gi + 1 < n) { c.wE = hm(ap, a_s[l + 1]); d += c.wE; } else { d += T(2) * ap; dw += T(2) * ap; }
+    if (gi > 0)     { c.wW = hm(ap, a_s[l - 1]); d += c.wW; } else { d += T(2) * ap; dw += T(2) * ap; }
+    if (gj + 1 < n) { c.wN = hm(ap, a_s[l + S]); d += c.wN; } else { d += T(2) * ap; dw += T(2) * ap; }
+    if (gj > 0)     { c.wS = hm(ap, a_s[l - S]); d += c.wS; } else { d += T(2) * ap; dw += T(2) * ap; }
+    c.dw = dw;
     c.inv = frcp(d);
     c.rhs = rhs;
     c.l = l;
@@ -271,12 +272,16 @@ __global__ __launch_bounds__(NT) void k_pre_tile(const T *__restrict__ a, const 
         const int l = c.l;
         const int lj = l / S, li = l - lj * S;
         if (li < H || li >= H + TILE || lj < H || lj >= H + TILE) return;
-        T off = c.wE * u_s[l + 1];
-        off += c.wW * u_s[l - 1];
-        off += c.wN * u_s[l + S];
-        off += c.wS * u_s[l - S];
-        // h^-2 (h^2 f - (D u - sum w u_nbr)); h^2, h^-2 are powers of two
-        a_s[l] = inv_h2 * (c.rhs - (c.d * u_s[l] - off));
+        // h^-2 (h^2 f - net flux); the flux is summed face by face as
+        // w (u_P - u_nbr) (0 at a wall, whose neighbour slot holds 0 and whose
+        // weight is 0) plus the wall term; h^2, h^-2 are powers of two
+        const T up = u_s[l];
+        T v = c.dw * up;
+        v += c.wE * (up - u_s[l + 1]);
+        v += c.wW * (up - u_s[l - 1]);
+        v += c.wN * (up - u_s[l + S]);
+        v += c.wS * (up - u_s[l - S]);
+        a_s[l] = inv_h2 * (c.rhs - v);
     };
 #pragma unroll
     for (int k = 0; k < Red::PER; ++k)
@@ -401,16 +406,25 @@ __device__ void lds_sweep(const T *a, const T *f, T *u, int n, int colour)
 }
 
 // r = f - A u at one cell, in the arithmetic of TU (coefficients TA promoted)
+// net flux out of cell (i, j) times h^2, face by face: w (u_P - u_nbr) for an
+// interior face, 2 a_P u_P for a wall face
+template <typename TU, typename TA>
+__device__ __forceinline__ TU lds_flux(const TA *a, const TU *u, int n, int i, int j)
+{
+    const int p = i + n * j;
+    const TU ap = TU(a[p]), up = u[p];
+    TU v = TU(0);
+    v += (i + 1 < n) ? hm(ap, TU(a[p + 1])) * (up - u[p + 1]) : TU(2) * ap * up;
+    v += (i > 0) ? hm(ap, TU(a[p - 1])) * (up - u[p - 1]) : TU(2) * ap * up;
+    v += (j + 1 < n) ? hm(ap, TU(a[p + n])) * (up - u[p + n]) : TU(2) * ap * up;
+    v += (j > 0) ? hm(ap, TU(a[p - n])) * (up - u[p - n]) : TU(2) * ap * up;
+    return v;
+}
+
 template <typename TU, typename TA>
 __device__ __forceinline__ TU lds_resid(const TA *a, const TU *f, const TU *u, int n, int i, int j)
 {
-    TU wE, wW, wN, wS, d;
-    lds_stencil<TU>(a, n, i, j, wE, wW, wN, wS, d);
-    TU off = wE * lds_nb(u, n, i + 1, j);
-    off += wW * lds_nb(u, n, i - 1, j);
-    off += wN * lds_nb(u, n, i, j + 1);
-    off += wS * lds_nb(u, n, i, j - 1);
-    return (f ? f[i + n * j] : TU(1)) - TU(n) * TU(n) * (d * u[i + n * j] - off);
+    return (f ? f[i + n * j] : TU(1)) - TU(n) * TU(n) * lds_flux<TU>(a, u, n, i, j);
 }
 
 // exact 2x2 solve A u = f (f nullptr: f = 1) in the arithmetic of TU
@@ -623,11 +637,48 @@ __global__ __launch_bounds__(LT) void k_lds_vcycle(const T *__restrict__ a_pool,
     for (int p = threadIdx.x; p < cntG; p += LT) dst[p] = u_s[LdsHier<GS>::off(G) + p];
 }
 
-// FMG stages 0..G (G <= GS) with refinement: per stage, u64 = P u64_prev, then
-// { r = 1 - A u64 in FP64 ; stop if ||r||_2 / ||1||_2 <= rtol or after max_iters ;
-//   e = V(0; r) in T ; u64 += e }.  QoI of stages g >= g0 from u64; u64 of
-// level G to u64_pool; per sample the largest iteration count, the largest
-// final relative residual and whether a stage stopped short of rtol.
+// Two compensated partial sums reduced together (fixed pairwise tree).
+__device__ void lds_reduce2(double s0, double c0, double s1, double c1, double *scratch,
+                            double &v0, double &v1)
+{
+    scratch[4 * threadIdx.x] = s0;
+    scratch[4 * threadIdx.x + 1] = c0;
+    scratch[4 * threadIdx.x + 2] = s1;
+    scratch[4 * threadIdx.x + 3] = c1;
+    __syncthreads();
+    for (int w = LT / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                double *x = scratch + 4 * threadIdx.x + 2 * v, *y = scratch + 4 * (threadIdx.x + w) + 2 * v;
+                const double s1_ = x[0], s2_ = y[0], t = s1_ + s2_, bb = t - s1_;
+                x[1] = x[1] + y[1] + ((s1_ - (t - bb)) + (s2_ - bb));
+                x[0] = t;
+            }
+        }
+        __syncthreads();
+    }
+    v0 = scratch[0] + scratch[1];
+    v1 = scratch[2] + scratch[3];
+    __syncthreads();
+}
+
+// (A u)_P in FP64 at cell (i, j) of the n x n grid, coefficients TA promoted
+template <typename TA>
+__device__ __forceinline__ double lds_apply(const TA *a, const double *u, int n, int i, int j)
+{
+    return double(n) * double(n) * lds_flux<double>(a, u, n, i, j);
+}
+
+// FMG stages 0..G (G <= GS) with every stage g >= 1 solved to
+// ||1 - A x||_2 / ||1||_2 <= rtol by flexible preconditioned CG in FP64 from
+// the interpolated x = P x_prev, the preconditioner z = B r being one
+// V(mu1, mu2) cycle in T from a zero guess:
+//   z = B r;  beta = (z, r - r_old) / (z_old, r_old)  (0 at the first step);
+//   p = z + beta p;  alpha = (z, r) / (p, A p);  x += alpha p;  r = 1 - A x.
+// QoI of stages g >= g0 from x; x of level G to u64_pool; per sample the
+// largest step count, the largest final relative residual and whether a stage
+// stopped at max_iters.
 template <int GS, typename T>
 __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
     const T *__restrict__ a_pool, double *__restrict__ u64_pool, int64_t Bc, int G, int mu1,
@@ -635,9 +686,11 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
     int32_t *__restrict__ st_iters, double *__restrict__ st_rho, int32_t *__restrict__ st_bad)
 {
     constexpr int TOT = LdsHier<GS>::TOTAL;
+    constexpr int TOP = 4 << (2 * GS);   // cells of the finest LDS level
     __shared__ T a_s[TOT], u_s[TOT], f_s[TOT];
-    __shared__ double w_s[TOT];          // FP64 stage solutions
-    __shared__ double red_s[2 * LT];
+    __shared__ double w_s[TOT];          // FP64 stage solutions x
+    __shared__ double r_s[TOP], ro_s[TOP], p_s[TOP];
+    __shared__ double red_s[4 * LT];
     const int64_t b = blockIdx.x;
     if (b >= Bc) return;
     for (int g = 0; g <= G; ++g) {
@@ -650,35 +703,57 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
     int it_max = 0, bad = 0;
     double rho_max = 0.0;
     for (int g = 0; g <= G; ++g) {
-        const int n = 2 << g;
-        double *wg = w_s + LdsHier<GS>::off(g);
-        T *ug = u_s + LdsHier<GS>::off(g), *fg = f_s + LdsHier<GS>::off(g);
+        const int n = 2 << g, cells = n * n;
+        double *xg = w_s + LdsHier<GS>::off(g);
+        T *zg = u_s + LdsHier<GS>::off(g), *fg = f_s + LdsHier<GS>::off(g);
         const T *ag = a_s + LdsHier<GS>::off(g);
-        if (g == 0) lds_coarse_solve<double>(a_s, (const double *)nullptr, wg);
-        else lds_prolong(w_s + LdsHier<GS>::off(g - 1), wg, n, false);
+        if (g == 0) lds_coarse_solve<double>(a_s, (const double *)nullptr, xg);
+        else lds_prolong(w_s + LdsHier<GS>::off(g - 1), xg, n, false);
         int it = 0;
-        double rho = 0.0;
+        double rho, rz_old = 1.0;
         for (;;) {
-            // FP64 residual, staged as the T right-hand side of the correction
+            // r = 1 - A x, staged as the T right-hand side of the preconditioner
             double s = 0.0, c = 0.0;
-            for (int p = threadIdx.x; p < n * n; p += LT) {
+            for (int p = threadIdx.x; p < cells; p += LT) {
                 const int j = p / n, i = p - j * n;
-                const double r = lds_resid<double>(ag, (const double *)nullptr, wg, n, i, j);
+                const double r = 1.0 - lds_apply(ag, xg, n, i, j);
+                r_s[p] = r;
                 fg[p] = T(r);
-                ug[p] = T(0);
+                zg[p] = T(0);
                 neumaier(s, c, r * r);
             }
             rho = sqrt(lds_reduce(s, c, red_s)) / (double)n;   // ||1||_2 = n
-            if (rho <= rtol || it >= max_iters) break;
-            V.run(g, fg);
-            for (int p = threadIdx.x; p < n * n; p += LT) wg[p] += double(ug[p]);
+            if (rho <= rtol || it >= max_iters || g == 0) break;
+            V.run(g, fg);                                       // z = B r
+            double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0;
+            for (int p = threadIdx.x; p < cells; p += LT) {
+                const double z = double(zg[p]);
+                neumaier(s0, c0, r_s[p] * z);
+                neumaier(s1, c1, it == 0 ? 0.0 : ro_s[p] * z);
+                ro_s[p] = r_s[p];
+            }
+            double rz, rzo;
+            lds_reduce2(s0, c0, s1, c1, red_s, rz, rzo);
+            const double beta = it == 0 ? 0.0 : (rz - rzo) / rz_old;
+            for (int p = threadIdx.x; p < cells; p += LT)
+                p_s[p] = it == 0 ? double(zg[p]) : double(zg[p]) + beta * p_s[p];
             __syncthreads();
+            s = 0.0;
+            c = 0.0;
+            for (int p = threadIdx.x; p < cells; p += LT) {
+                const int j = p / n, i = p - j * n;
+                neumaier(s, c, p_s[p] * lds_apply(ag, p_s, n, i, j));
+            }
+            const double alpha = rz / lds_reduce(s, c, red_s);
+            for (int p = threadIdx.x; p < cells; p += LT) xg[p] += alpha * p_s[p];
+            __syncthreads();
+            rz_old = rz;
             ++it;
         }
-        if (rho > rtol) bad = 1;
+        if (g > 0 && rho > rtol) bad = 1;
         it_max = it > it_max ? it : it_max;
         rho_max = rho > rho_max ? rho : rho_max;
-        if (g >= g0) lds_write_qoi(wg, n, qoi, b, nlev, g - g0, mask, red_s);
+        if (g >= g0) lds_write_qoi(xg, n, qoi, b, nlev, g - g0, mask, red_s);
     }
     const int cntG = 4 << (2 * G);
     double *dst = u64_pool + Bc * level_offset(G) + b * (int64_t)cntG;
@@ -690,66 +765,258 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
     }
 }
 
-// Top-grid FP64 residual r = 1 - A u64 (coefficients T promoted) of every
-// active sample, one wavefront per sample: r -> f (as T), rho_b = ||r||/||1||,
-// active_b = rho_b > rtol && iters_b < max_iters (iters counted here).
-template <typename T>
-__global__ __launch_bounds__(256) void k_refine_residual(const T *__restrict__ a,
-                                                         const double *__restrict__ u, int n,
-                                                         int64_t Bc, T *__restrict__ f,
-                                                         double *__restrict__ rho,
-                                                         int32_t *__restrict__ active,
-                                                         int32_t *__restrict__ iters, double rtol,
-                                                         int max_iters)
+// ---------------------------------------------------------------------------
+// Flexible CG of one FMG stage on a large grid (the same iteration as the
+// LDS-resident kernel above), one pass per vector operation over all active
+// samples.  A block owns FCH consecutive cells of one sample and leaves one
+// compensated partial sum (or two) per block; a wavefront per sample folds the
+// partials in a fixed order, so every sum is reproducible.
+constexpr int FCH = 1024;                 // cells per block (256 threads x 4)
+
+struct FcgMap {
+    int64_t b, c0;   // sample, first cell of the block
+    int nch;         // blocks per sample
+};
+__device__ __forceinline__ bool fcg_map(int n, int64_t Bc, const int32_t *active, FcgMap &m)
+{
+    const int64_t cells = (int64_t)n * n;
+    m.nch = (int)((cells + FCH - 1) / FCH);
+    const int64_t bid = blockIdx.x;
+    m.b = bid / m.nch;
+    m.c0 = (bid - m.b * m.nch) * (int64_t)FCH;
+    if (m.b >= Bc) return false;
+    return !active || active[m.b];
+}
+
+// (A u)_P in FP64 for cell p = i + n j of one sample (a, u at the sample base)
+template <typename TA>
+__device__ __forceinline__ double apply_cell(const TA *__restrict__ a, const double *__restrict__ u,
+                                             int n, int i, int j, int64_t p)
+{
+    const double ap = double(a[p]), up = u[p];
+    double v = 0.0;   // net flux, face by face
+    v += (i + 1 < n) ? hm(ap, double(a[p + 1])) * (up - u[p + 1]) : 2.0 * ap * up;
+    v += (i > 0) ? hm(ap, double(a[p - 1])) * (up - u[p - 1]) : 2.0 * ap * up;
+    v += (j + 1 < n) ? hm(ap, double(a[p + n])) * (up - u[p + n]) : 2.0 * ap * up;
+    v += (j > 0) ? hm(ap, double(a[p - n])) * (up - u[p - n]) : 2.0 * ap * up;
+    return double(n) * double(n) * v;
+}
+
+__device__ __forceinline__ void two_sum_fold(double &s, double &c, double s2, double c2)
+{
+    const double t = s + s2, bb = t - s;
+    c = c + c2 + ((s - (t - bb)) + (s2 - bb));
+    s = t;
+}
+
+// block (256 threads) compensated sums of NV values -> out[2 NV] (sum, comp)
+template <int NV>
+__device__ __forceinline__ void block_partials(double *s, double *c, double *out)
+{
+    __shared__ double red[4][2 * NV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1)
+            two_sum_fold(s[v], c[v], __shfl_xor(s[v], m, 64), __shfl_xor(c[v], m, 64));
+    if (lane == 0)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            red[wave][2 * v] = s[v];
+            red[wave][2 * v + 1] = c[v];
+        }
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double S = red[0][2 * v], Cc = red[0][2 * v + 1];
+            for (int w = 1; w < 4; ++w) two_sum_fold(S, Cc, red[w][2 * v], red[w][2 * v + 1]);
+            out[2 * v] = S;
+            out[2 * v + 1] = Cc;
+        }
+}
+
+// fold the per-block partials of sample b (one wavefront): value v of NV
+template <int NV>
+__device__ __forceinline__ double fold_partials(const double *__restrict__ part, int64_t b, int nch,
+                                                int v)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-    if (b >= Bc) return;
-    if (!active[b]) return;
-    const int64_t cells = (int64_t)n * n, base = b * cells;
-    const T *ab = a + base;
-    const double *ub = u + base;
-    const double inv_h2 = (double)n * (double)n;
     double s = 0.0, c = 0.0;
-    for (int64_t p = lane; p < cells; p += 64) {
-        const int j = (int)(p / n), i = (int)(p - (int64_t)j * n);
-        const double ap = double(ab[p]);
-        double d = 0.0, off = 0.0, w;
-        if (i + 1 < n) { w = hm(ap, double(ab[p + 1])); d += w; off += w * ub[p + 1]; } else d += 2.0 * ap;
-        if (i > 0)     { w = hm(ap, double(ab[p - 1])); d += w; off += w * ub[p - 1]; } else d += 2.0 * ap;
-        if (j + 1 < n) { w = hm(ap, double(ab[p + n])); d += w; off += w * ub[p + n]; } else d += 2.0 * ap;
-        if (j > 0)     { w = hm(ap, double(ab[p - n])); d += w; off += w * ub[p - n]; } else d += 2.0 * ap;
-        const double r = 1.0 - inv_h2 * (d * ub[p] - off);
-        f[base + p] = T(r);
-        neumaier(s, c, r * r);
+    for (int k = lane; k < nch; k += 64) {
+        const double *q = part + ((b * nch + k) * NV + v) * 2;
+        two_sum_fold(s, c, q[0], q[1]);
     }
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const double s2 = __shfl_xor(s, m, 64), c2 = __shfl_xor(c, m, 64);
-        const double t = s + s2, bb = t - s;
-        c = c + c2 + ((s - (t - bb)) + (s2 - bb));
-        s = t;
+    for (int m = 32; m >= 1; m >>= 1) two_sum_fold(s, c, __shfl_xor(s, m, 64), __shfl_xor(c, m, 64));
+    return s + c;
+}
+
+// r = 1 - A x; f = TF(r); partial ||r||^2
+template <typename TA, typename TF>
+__global__ __launch_bounds__(256) void k_fcg_resid(const TA *__restrict__ a,
+                                                   const double *__restrict__ x, int n, int64_t Bc,
+                                                   double *__restrict__ r, TF *__restrict__ f,
+                                                   double *__restrict__ part,
+                                                   const int32_t *__restrict__ active)
+{
+    FcgMap m;
+    if (!fcg_map(n, Bc, active, m)) return;
+    const int64_t cells = (int64_t)n * n, base = m.b * cells;
+    double s[1] = {0.0}, c[1] = {0.0};
+#pragma unroll
+    for (int q = 0; q < FCH / 256; ++q) {
+        const int64_t p = m.c0 + threadIdx.x + 256 * q;
+        if (p < cells) {
+            const int j = (int)(p / n), i = (int)(p - (int64_t)j * n);
+            const double v = 1.0 - apply_cell(a + base, x + base, n, i, j, p);
+            r[base + p] = v;
+            f[base + p] = TF(v);
+            neumaier(s[0], c[0], v * v);
+        }
     }
-    if (lane == 0) {
-        const double v = sqrt(s + c) / (double)n;
+    block_partials<1>(s, c, part + (m.b * m.nch + m.c0 / FCH) * 2);
+}
+
+// rho_b = ||r|| / ||1||.  first: every sample starts with iters = 0.  Then,
+// for the samples still iterating: active = rho > rtol && iters < max_iters,
+// and iters counts the step about to be taken.
+__global__ __launch_bounds__(256) void k_fcg_fin_rho(const double *__restrict__ part, int n,
+                                                     int64_t Bc, double *__restrict__ rho,
+                                                     int32_t *__restrict__ active,
+                                                     int32_t *__restrict__ iters, double rtol,
+                                                     int max_iters, int first)
+{
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= Bc) return;
+    if (!first && !active[b]) return;
+    const int nch = (int)(((int64_t)n * n + FCH - 1) / FCH);
+    const double v = sqrt(fold_partials<1>(part, b, nch, 0)) / (double)n;
+    if ((threadIdx.x & 63) == 0) {
+        const int it = first ? 0 : iters[b];
+        const int go = v > rtol && it < max_iters;
         rho[b] = v;
-        const int it = iters[b];
-        const int go = (v > rtol) && (it < max_iters);
         active[b] = go;
-        if (go) iters[b] = it + 1;
+        iters[b] = it + go;
     }
 }
 
-// u64 += e (type T) for active samples
-template <typename T>
-__global__ void k_refine_update(double *__restrict__ u, const T *__restrict__ e, int n, int64_t Bc,
-                                const int32_t *__restrict__ active)
+// partials of (r, z) and (r_old, z) (the second 0 at the first step); r_old = r
+template <typename TZ>
+__global__ __launch_bounds__(256) void k_fcg_dots(const TZ *__restrict__ z,
+                                                  const double *__restrict__ r,
+                                                  double *__restrict__ ro, int n, int64_t Bc,
+                                                  double *__restrict__ part,
+                                                  const int32_t *__restrict__ active,
+                                                  const int32_t *__restrict__ iters)
 {
-    const int64_t per = (int64_t)n * n;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= Bc * per) return;
-    if (!active[t / per]) return;
-    u[t] += double(e[t]);
+    FcgMap m;
+    if (!fcg_map(n, Bc, active, m)) return;
+    const int64_t cells = (int64_t)n * n, base = m.b * cells;
+    const bool first = iters[m.b] == 1;
+    double s[2] = {0.0, 0.0}, c[2] = {0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < FCH / 256; ++q) {
+        const int64_t p = m.c0 + threadIdx.x + 256 * q;
+        if (p < cells) {
+            const double zv = double(z[base + p]), rv = r[base + p];
+            neumaier(s[0], c[0], rv * zv);
+            neumaier(s[1], c[1], first ? 0.0 : ro[base + p] * zv);
+            ro[base + p] = rv;
+        }
+    }
+    block_partials<2>(s, c, part + (m.b * m.nch + m.c0 / FCH) * 4);
+}
+
+// fs[b] = {rz, rz_old, alpha, beta}: rz = (r, z), beta = (rz - (r_old, z)) / rz_old
+__global__ __launch_bounds__(256) void k_fcg_fin_beta(const double *__restrict__ part, int n,
+                                                      int64_t Bc, double *__restrict__ fs,
+                                                      const int32_t *__restrict__ active,
+                                                      const int32_t *__restrict__ iters)
+{
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= Bc || !active[b]) return;
+    const int nch = (int)(((int64_t)n * n + FCH - 1) / FCH);
+    const double rz = fold_partials<2>(part, b, nch, 0);
+    const double rzo = fold_partials<2>(part, b, nch, 1);
+    if ((threadIdx.x & 63) == 0) {
+        fs[4 * b] = rz;
+        fs[4 * b + 3] = iters[b] == 1 ? 0.0 : (rz - rzo) / fs[4 * b + 1];
+    }
+}
+
+// p = z + beta p (p = z at the first step)
+template <typename TZ>
+__global__ __launch_bounds__(256) void k_fcg_p(const TZ *__restrict__ z, double *__restrict__ pv,
+                                               int n, int64_t Bc, const double *__restrict__ fs,
+                                               const int32_t *__restrict__ active,
+                                               const int32_t *__restrict__ iters)
+{
+    FcgMap m;
+    if (!fcg_map(n, Bc, active, m)) return;
+    const int64_t cells = (int64_t)n * n, base = m.b * cells;
+    const bool first = iters[m.b] == 1;
+    const double beta = fs[4 * m.b + 3];
+#pragma unroll
+    for (int q = 0; q < FCH / 256; ++q) {
+        const int64_t p = m.c0 + threadIdx.x + 256 * q;
+        if (p < cells)
+            pv[base + p] = first ? double(z[base + p]) : double(z[base + p]) + beta * pv[base + p];
+    }
+}
+
+// partial (p, A p)
+template <typename TA>
+__global__ __launch_bounds__(256) void k_fcg_pq(const TA *__restrict__ a,
+                                                const double *__restrict__ pv, int n, int64_t Bc,
+                                                double *__restrict__ part,
+                                                const int32_t *__restrict__ active)
+{
+    FcgMap m;
+    if (!fcg_map(n, Bc, active, m)) return;
+    const int64_t cells = (int64_t)n * n, base = m.b * cells;
+    double s[1] = {0.0}, c[1] = {0.0};
+#pragma unroll
+    for (int q = 0; q < FCH / 256; ++q) {
+        const int64_t p = m.c0 + threadIdx.x + 256 * q;
+        if (p < cells) {
+            const int j = (int)(p / n), i = (int)(p - (int64_t)j * n);
+            neumaier(s[0], c[0], pv[base + p] * apply_cell(a + base, pv + base, n, i, j, p));
+        }
+    }
+    block_partials<1>(s, c, part + (m.b * m.nch + m.c0 / FCH) * 2);
+}
+
+// alpha = rz / (p, A p); rz_old = rz
+__global__ __launch_bounds__(256) void k_fcg_fin_alpha(const double *__restrict__ part, int n,
+                                                       int64_t Bc, double *__restrict__ fs,
+                                                       const int32_t *__restrict__ active)
+{
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= Bc || !active[b]) return;
+    const int nch = (int)(((int64_t)n * n + FCH - 1) / FCH);
+    const double pq = fold_partials<1>(part, b, nch, 0);
+    if ((threadIdx.x & 63) == 0) {
+        fs[4 * b + 2] = fs[4 * b] / pq;
+        fs[4 * b + 1] = fs[4 * b];
+    }
+}
+
+// x += alpha p
+__global__ __launch_bounds__(256) void k_fcg_x(double *__restrict__ x, const double *__restrict__ pv,
+                                               int n, int64_t Bc, const double *__restrict__ fs,
+                                               const int32_t *__restrict__ active)
+{
+    FcgMap m;
+    if (!fcg_map(n, Bc, active, m)) return;
+    const int64_t cells = (int64_t)n * n, base = m.b * cells;
+    const double alpha = fs[4 * m.b + 2];
+#pragma unroll
+    for (int q = 0; q < FCH / 256; ++q) {
+        const int64_t p = m.c0 + threadIdx.x + 256 * q;
+        if (p < cells) x[base + p] += alpha * pv[base + p];
+    }
 }
 
 // fold one stage's final per-sample state into the per-sample statistics
@@ -824,21 +1091,38 @@ void launch_lds_fmg_refine(hipStream_t st, const T *a_pool, double *u64_pool, in
                        st_iters, st_rho, st_bad);
 }
 
+int64_t fcg_partials(int n, int64_t Bc) { return Bc * (((int64_t)n * n + FCH - 1) / FCH) * 4; }
+
 template <typename T>
-void launch_refine_residual(hipStream_t st, const T *a, const double *u, int n, int64_t Bc, T *f,
-                            double *rho, int32_t *active, int32_t *iters, double rtol,
-                            int max_iters)
+void launch_fcg_resid(hipStream_t st, const T *a, const double *x, int n, int64_t Bc, double *r, T *f,
+                      double *part, const int32_t *active)
 {
-    hipLaunchKernelGGL((k_refine_residual<T>), dim3(blocks_of(Bc, 4)), dim3(256), 0, st, a, u, n, Bc,
-                       f, rho, active, iters, rtol, max_iters);
+    const int64_t nb = Bc * (((int64_t)n * n + FCH - 1) / FCH);
+    hipLaunchKernelGGL((k_fcg_resid<T, T>), dim3(nblocks(nb)), dim3(256), 0, st, a, x, n, Bc, r, f,
+                       part, active);
+}
+
+void launch_fcg_fin_rho(hipStream_t st, const double *part, int n, int64_t Bc, double *rho,
+                        int32_t *active, int32_t *iters, double rtol, int max_iters, int first)
+{
+    hipLaunchKernelGGL(k_fcg_fin_rho, dim3(blocks_of(Bc, 4)), dim3(256), 0, st, part, n, Bc, rho,
+                       active, iters, rtol, max_iters, first);
 }
 
 template <typename T>
-void launch_refine_update(hipStream_t st, double *u, const T *e, int n, int64_t Bc,
-                          const int32_t *active)
+void launch_fcg_step(hipStream_t st, const T *a, const T *z, double *x, double *r, double *ro,
+                     double *pv, int n, int64_t Bc, double *part, double *fs,
+                     const int32_t *active, const int32_t *iters)
 {
-    hipLaunchKernelGGL((k_refine_update<T>), dim3(blocks_of(Bc * (int64_t)n * n, 256)), dim3(256), 0,
-                       st, u, e, n, Bc, active);
+    const unsigned nb = nblocks(Bc * (((int64_t)n * n + FCH - 1) / FCH));
+    const unsigned ns = blocks_of(Bc, 4);
+    hipLaunchKernelGGL((k_fcg_dots<T>), dim3(nb), dim3(256), 0, st, z, r, ro, n, Bc, part, active,
+                       iters);
+    hipLaunchKernelGGL(k_fcg_fin_beta, dim3(ns), dim3(256), 0, st, part, n, Bc, fs, active, iters);
+    hipLaunchKernelGGL((k_fcg_p<T>), dim3(nb), dim3(256), 0, st, z, pv, n, Bc, fs, active, iters);
+    hipLaunchKernelGGL((k_fcg_pq<T>), dim3(nb), dim3(256), 0, st, a, pv, n, Bc, part, active);
+    hipLaunchKernelGGL(k_fcg_fin_alpha, dim3(ns), dim3(256), 0, st, part, n, Bc, fs, active);
+    hipLaunchKernelGGL(k_fcg_x, dim3(nb), dim3(256), 0, st, x, pv, n, Bc, fs, active);
 }
 
 void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho, int64_t Bc,
@@ -858,10 +1142,11 @@ void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho
     template void launch_lds_fmg_refine<T>(hipStream_t, const T *, double *, int64_t, int, int,   \
                                            int, double, int, int, double *, int, uint32_t,        \
                                            int32_t *, double *, int32_t *);                        \
-    template void launch_refine_residual<T>(hipStream_t, const T *, const double *, int, int64_t, \
-                                            T *, double *, int32_t *, int32_t *, double, int);     \
-    template void launch_refine_update<T>(hipStream_t, double *, const T *, int, int64_t,         \
-                                          const int32_t *);
+    template void launch_fcg_resid<T>(hipStream_t, const T *, const double *, int, int64_t,     \
+                                      double *, T *, double *, const int32_t *);                  \
+    template void launch_fcg_step<T>(hipStream_t, const T *, const T *, double *, double *,       \
+                                     double *, double *, int, int64_t, double *, double *,        \
+                                     const int32_t *, const int32_t *);
 MLMC_INSTANTIATE(double)
 MLMC_INSTANTIATE(float)
 #undef MLMC_INSTANTIATE

@@ -22,24 +22,36 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int WM = 32, WN = 64;        // tile of one wave: 2 x 4 MFMA tiles
 constexpr int BM = 64, BN = 128;       // tile of a 4-wave block (2 x 2 waves)
 
+// bf16 nearest to x (ties to even) via the FP32 value, as a bit pattern;
+// finite inputs only.  Written out so the split does not depend on the
+// rounding mode of a conversion instruction: a directed rounding would bias
+// every term the same way.
+__device__ __forceinline__ uint16_t bf16_rne(double x, double *value)
+{
+    uint32_t u = __float_as_uint((float)x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    const uint16_t h = (uint16_t)(u >> 16);
+    *value = (double)__uint_as_float((uint32_t)h << 16);
+    return h;
+}
+
 // split X (rows x cols, element (r, k) at X[r*rs + k*ks]) into three bf16
-// arrays [rows_pad][sp]; padding rows and columns are zero
+// arrays [rows_pad][sp]; padding rows and columns are zero.  Each residual is
+// exact in FP64.
 __global__ void k_split3(const double *__restrict__ X, int64_t rows, int cols, int64_t rs,
-                         int64_t ks, int64_t rows_pad, int sp, __bf16 *__restrict__ X1,
-                         __bf16 *__restrict__ X2, __bf16 *__restrict__ X3)
+                         int64_t ks, int64_t rows_pad, int sp, uint16_t *__restrict__ X1,
+                         uint16_t *__restrict__ X2, uint16_t *__restrict__ X3)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= rows_pad * sp) return;
     const int64_t r = t / sp;
     const int k = (int)(t - r * sp);
-    double x = (r < rows && k < cols) ? X[r * rs + (int64_t)k * ks] : 0.0;
-    const __bf16 x1 = (__bf16)(float)x;
-    const double r1 = x - (double)(float)x1;
-    const __bf16 x2 = (__bf16)(float)r1;
-    const double r2 = r1 - (double)(float)x2;
-    X1[t] = x1;
-    X2[t] = x2;
-    X3[t] = (__bf16)(float)r2;
+    const double x = (r < rows && k < cols) ? X[r * rs + (int64_t)k * ks] : 0.0;
+    double v1, v2, v3;
+    X1[t] = bf16_rne(x, &v1);
+    const double r1 = x - v1;
+    X2[t] = bf16_rne(r1, &v2);
+    X3[t] = bf16_rne(r1 - v2, &v3);
 }
 
 __device__ __forceinline__ int64_t level_major_index_m(int64_t m, int64_t b, int64_t Bc)
@@ -130,7 +142,7 @@ void launch_split3(hipStream_t st, const double *X, int64_t rows, int cols, int6
 {
     const int64_t n = rows_pad * sp;
     hipLaunchKernelGGL(k_split3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, rows, cols,
-                       rs, ks, rows_pad, sp, (__bf16 *)X3[0], (__bf16 *)X3[1], (__bf16 *)X3[2]);
+                       rs, ks, rows_pad, sp, X3[0], X3[1], X3[2]);
 }
 
 void launch_field_bf16x3(hipStream_t st, uint16_t *const Y[3], uint16_t *const Bs[3], int sp,

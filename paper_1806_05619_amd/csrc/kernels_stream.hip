@@ -57,22 +57,22 @@ __device__ __forceinline__ void static_for(F &&f)
 // in registers.  wS of a cell is wN of the cell below, which has the other
 // colour in the row below.
 struct RowW {
-    double wE_r, wW_r, wN_r, d_r, inv_r, rhs_r;
-    double wE_b, wW_b, wN_b, d_b, inv_b, rhs_b;
+    double wE_r, wW_r, wN_r, dw_r, inv_r, rhs_r;   // dw: wall term, 2 a_P per wall face
+    double wE_b, wW_b, wN_b, dw_b, inv_b, rhs_b;
 };
 
 // field-wise copy (a struct copy becomes a memcpy that keeps the window in
 // scratch memory)
 __device__ __forceinline__ void copy_row(RowW &d, const RowW &s)
 {
-    d.wE_r = s.wE_r; d.wW_r = s.wW_r; d.wN_r = s.wN_r; d.d_r = s.d_r; d.inv_r = s.inv_r; d.rhs_r = s.rhs_r;
-    d.wE_b = s.wE_b; d.wW_b = s.wW_b; d.wN_b = s.wN_b; d.d_b = s.d_b; d.inv_b = s.inv_b; d.rhs_b = s.rhs_b;
+    d.wE_r = s.wE_r; d.wW_r = s.wW_r; d.wN_r = s.wN_r; d.dw_r = s.dw_r; d.inv_r = s.inv_r; d.rhs_r = s.rhs_r;
+    d.wE_b = s.wE_b; d.wW_b = s.wW_b; d.wN_b = s.wN_b; d.dw_b = s.dw_b; d.inv_b = s.inv_b; d.rhs_b = s.rhs_b;
 }
 
 __device__ __forceinline__ void zero_row(RowW &d)
 {
-    d.wE_r = d.wW_r = d.wN_r = d.d_r = d.inv_r = d.rhs_r = 0.0;
-    d.wE_b = d.wW_b = d.wN_b = d.d_b = d.inv_b = d.rhs_b = 0.0;
+    d.wE_r = d.wW_r = d.wN_r = d.dw_r = d.inv_r = d.rhs_r = 0.0;
+    d.wE_b = d.wW_b = d.wN_b = d.dw_b = d.inv_b = d.rhs_b = 0.0;
 }
 
 // coarse values of row R's prolongation for lane L: columns L-1, L, L+1 of
@@ -211,12 +211,16 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
             d1 += wE0;
             d1 += (q + 1 < n) ? wN1 : 2.0 * ap1;
             d1 += (q > 0) ? wS1 : 2.0 * ap1;
+            const double dw0 = ((c0 > 0) ? 0.0 : 2.0 * ap0) + ((q + 1 < n) ? 0.0 : 2.0 * ap0) +
+                               ((q > 0) ? 0.0 : 2.0 * ap0);
+            const double dw1 = ((c1 + 1 < n) ? 0.0 : 2.0 * ap1) + ((q + 1 < n) ? 0.0 : 2.0 * ap1) +
+                               ((q > 0) ? 0.0 : 2.0 * ap1);
             const double i0 = frcp_s(d0), i1 = frcp_s(d1);
             RowW &r = w[0];
             r.wE_r = odd ? wE1 : wE0;   r.wE_b = odd ? wE0 : wE1;
             r.wW_r = odd ? wE0 : wW0;   r.wW_b = odd ? wW0 : wE0;
             r.wN_r = odd ? wN1 : wN0;   r.wN_b = odd ? wN0 : wN1;
-            r.d_r = odd ? d1 : d0;      r.d_b = odd ? d0 : d1;
+            r.dw_r = odd ? dw1 : dw0;   r.dw_b = odd ? dw0 : dw1;
             r.inv_r = odd ? i1 : i0;    r.inv_b = odd ? i0 : i1;
             r.rhs_r = odd ? rhs_prev1 : rhs_prev0;
             r.rhs_b = odd ? rhs_prev0 : rhs_prev1;
@@ -255,14 +259,16 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
                 const double *up = u_ring + ((rr + 1) & 7) * n, *dn = u_ring + ((rr - 1) & 7) * n;
                 const int cr = c0 + (rr & 1), cb = c1 - (rr & 1);
                 const double ur = row[cr], ubk = row[cb];
-                double offr = (cr + 1 < n) ? r.wE_r * row[cr + 1] : 0.0;
-                if (cr > 0) offr += r.wW_r * row[cr - 1];
-                double offb = (cb + 1 < n) ? r.wE_b * row[cb + 1] : 0.0;
-                if (cb > 0) offb += r.wW_b * row[cb - 1];
-                if (rr + 1 < n) { offr += r.wN_r * up[cr]; offb += r.wN_b * up[cb]; }
-                if (rr > 0) { offr += rs.wN_b * dn[cr]; offb += rs.wN_r * dn[cb]; }
-                const double resr = inv_h2 * (r.rhs_r - (r.d_r * ur - offr));
-                const double resb = inv_h2 * (r.rhs_b - (r.d_b * ubk - offb));
+                // net flux face by face: w (u_P - u_nbr), plus the wall term
+                double fr = r.dw_r * ur, fbk = r.dw_b * ubk;
+                if (cr + 1 < n) fr += r.wE_r * (ur - row[cr + 1]);
+                if (cr > 0) fr += r.wW_r * (ur - row[cr - 1]);
+                if (cb + 1 < n) fbk += r.wE_b * (ubk - row[cb + 1]);
+                if (cb > 0) fbk += r.wW_b * (ubk - row[cb - 1]);
+                if (rr + 1 < n) { fr += r.wN_r * (ur - up[cr]); fbk += r.wN_b * (ubk - up[cb]); }
+                if (rr > 0) { fr += rs.wN_b * (ur - dn[cr]); fbk += rs.wN_r * (ubk - dn[cb]); }
+                const double resr = inv_h2 * (r.rhs_r - fr);
+                const double resb = inv_h2 * (r.rhs_b - fbk);
                 const bool odd = rr & 1;
                 const double u0 = odd ? ubk : ur, u1 = odd ? ur : ubk;
                 const double res0 = odd ? resb : resr, res1 = odd ? resr : resb;

@@ -48,8 +48,9 @@ def _cfg(**kw):
 @pytest.mark.parametrize("bad", [
     dict(n0=3), dict(n0=1), dict(num_levels=0), dict(n0=4, num_levels=12), dict(s=0),
     dict(corr_len=0.0), dict(sigma2=-1.0), dict(mu1=0, mu2=0), dict(mu0=0),
-    dict(rtol=1e-8, max_iters=0), dict(precision=7), dict(qoi_mask=0), dict(qoi_mask=4),
-    dict(max_batch=0),
+    dict(rtol=1e-8, max_iters=0), dict(rtol=1e-8, max_iters=5, mu1=3),
+    dict(rtol=1e-8, max_iters=5, mu2=0), dict(precision=1), dict(precision=7),
+    dict(qoi_mask=0), dict(qoi_mask=4), dict(max_batch=0),
 ])
 def test_create_rejects_invalid_config(bad):
     L = m.lib()

@@ -318,6 +318,43 @@ def test_mixed_field_within_split_bound(oracle_mod, k, B):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_rough_lattice_workload_every_sample_converges(oracle_mod, precision):
+    """The s = 400, lambda = 0.1, sigma^2 = 2 lattice workload up to 128^2
+    (stages <= 32^2 in the LDS-resident kernel, 64^2 and 128^2 in the
+    grid-wide flexible-CG passes): every sample of a 96-point batch reaches
+    rtol within a few dozen preconditioned steps, and sampled QoIs agree with
+    the band Cholesky solve on every level."""
+    dev = _dev()
+    prec = m.MLMC_MIXED if precision == "mixed" else m.MLMC_FP64
+    k = 5
+    w = synth.workload("mlqmc_mixed_s400")
+    w["num_levels"] = k + 1
+    ctx = m.Context(w["n0"], w["num_levels"], w["s"], w["corr_len"], w["sigma2"],
+                    mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"],
+                    max_iters=w["max_iters"], precision=prec,
+                    qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
+                    genvec=synth.korobov_vector(w["seed"], w["s"]),
+                    shifts=synth.shift_table(w["seed"], w["num_levels"], w["num_shifts"], w["s"]),
+                    max_batch=96, device=0)
+    P = _oracle_problem(oracle_mod, w)
+    npts = 96
+    pts = ctx.lattice(k, 0, npts, 0, 1)
+    qg, _, info = _solve(ctx, pts, k + 1, info=True)
+    print(f"\n{precision}: max steps {info['max_iters_used']}, "
+          f"max relres {info['max_rel_residual']:.2e}")
+    assert info["status"] == m.MLMC_OK and info["not_converged"] == 0, info
+    assert info["max_iters_used"] <= 40
+    assert 0 < info["max_rel_residual"] <= w["rtol"]
+    assert np.all(np.isfinite(qg))
+    _, ys = _lattice_y(oracle_mod, w, k, [0], 0, npts)
+    tol = 1e-8 if precision == "fp64" else 2e-7
+    for b in range(0, npts, 24):
+        qd = P.sample(k, ys[b], 1)
+        rel = np.abs(qg[b] - qd) / np.abs(qd)
+        assert rel.max() <= tol, (b, rel)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_refinement_high_contrast_matches_direct_solve(oracle_mod, precision):
     """sigma^2 = 2, lambda = 0.1, s = 400: FP64 residual refinement to 1e-10
     with FP64 or FP32 V-cycles, against the oracle's FP64 field and band
