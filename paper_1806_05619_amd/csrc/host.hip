@@ -32,9 +32,12 @@ struct mlmc_ctx_s {
     uint32_t *d_z = nullptr;
     uint64_t *d_shifts = nullptr;
     double *d_basis = nullptr;   // [s][Mmax]
-    uint16_t *d_bsplit[3] = {};  // mixed mode: bf16 splits of the basis, [Mpad][sp]
-    uint16_t *d_ysplit[3] = {};  // mixed mode: bf16 splits of a chunk's Y, [chunk_pad][sp]
+    // mixed mode: bf16 digit arrays [rows_pad][sp] and per-row scale exponents
+    uint16_t *d_bdig[4] = {};    // basis, rows = field columns (Mpad)
+    uint16_t *d_ydig[4] = {};    // a chunk's Y, rows = samples (chunk_pad)
+    int32_t *d_bexp = nullptr, *d_yexp = nullptr;
     int sp = 0;                  // s rounded up to the matrix-core K step
+    double *d_a64 = nullptr;     // mixed mode: FP64 copy of the a pool (CG operator)
     int64_t Mmax = 0;
     int64_t pool = 0;            // doubles per pool
     double *d_a = nullptr, *d_u = nullptr, *d_f = nullptr;
@@ -417,6 +420,7 @@ struct HierT {
     T *u[kMaxMgLevels] = {};
     T *f[kMaxMgLevels] = {};
     double *w[kMaxMgLevels] = {};
+    const double *a64[kMaxMgLevels] = {};   // FP64 coefficients (a itself when T = double)
 };
 
 template <typename T>
@@ -431,6 +435,8 @@ HierT<T> make_hier_t(mlmc_ctx c, int G, int64_t Bc)
         h.u[g] = (T *)c->d_u + off;
         h.f[g] = (T *)c->d_f + off;
         h.w[g] = c->d_w ? c->d_w + off : nullptr;
+        h.a64[g] = sizeof(T) == sizeof(double) ? (const double *)h.a[g]
+                                               : (c->d_a64 ? c->d_a64 + off : nullptr);
     }
     return h;
 }
@@ -531,8 +537,11 @@ mlmc_status run_fmg_refine(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k,
     const auto &h = R.h;
     {
         const int n = 2 << R.Gs;
-        ProfScope ps(c, st, MLMC_KERNEL_LDS, R.W * Bc * level_offset(R.Gs + 1) + 8.0 * R.cells(n), 0.0);
-        launch_lds_fmg_refine<T>(st, h.a[0], c->d_w, Bc, R.Gs, c->cfg.mu1, c->cfg.mu2, c->cfg.rtol,
+        // a (and its FP64 copy in the mixed mode) of the LDS levels read, x of the top one written
+        const double wa = R.W + (sizeof(T) == sizeof(double) ? 0.0 : 8.0);
+        ProfScope ps(c, st, MLMC_KERNEL_LDS, wa * Bc * level_offset(R.Gs + 1) + 8.0 * R.cells(n), 0.0);
+        launch_lds_fmg_refine<T>(st, h.a[0], h.a64[0], c->d_w, Bc, R.Gs, c->cfg.mu1, c->cfg.mu2,
+                                 c->cfg.rtol,
                                  c->cfg.max_iters, c->g0, qoi, nlev, c->cfg.qoi_mask, c->d_st_iters,
                                  c->d_st_rho, c->d_st_bad);
     }
@@ -547,8 +556,9 @@ mlmc_status run_fmg_refine(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k,
         double *r = c->d_fcg, *ro = r + Bc * cells, *pv = ro + Bc * cells;
         const double vec = R.cells(n);   // cells of all samples of the chunk
         {
-            ProfScope ps(c, st, MLMC_KERNEL_REFINE, vec * (R.W + 8.0 + 8.0 + R.W), 0.0);
-            launch_fcg_resid<T>(st, h.a[g], h.w[g], n, Bc, r, h.f[g], c->d_part, nullptr);
+            // a (FP64), x read; r, f written
+            ProfScope ps(c, st, MLMC_KERNEL_REFINE, vec * (8.0 + 8.0 + 8.0 + R.W), 0.0);
+            launch_fcg_resid<T>(st, h.a64[g], h.w[g], n, Bc, r, h.f[g], c->d_part, nullptr);
         }
         launch_fcg_fin_rho(st, c->d_part, n, Bc, c->d_rho, c->d_active, c->d_iters, c->cfg.rtol,
                            c->cfg.max_iters, 1);
@@ -563,13 +573,13 @@ mlmc_status run_fmg_refine(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k,
             {
                 // dots (z, r, r_old; r_old written), p update, (p, A p), x update
                 ProfScope ps(c, st, MLMC_KERNEL_REFINE,
-                             vec * ((R.W + 24.0) + (R.W + 16.0) + (R.W + 8.0) + 24.0), 0.0);
-                launch_fcg_step<T>(st, h.a[g], h.u[g], h.w[g], r, ro, pv, n, Bc, c->d_part,
+                             vec * ((R.W + 24.0) + (R.W + 16.0) + 16.0 + 24.0), 0.0);
+                launch_fcg_step<T>(st, h.a64[g], h.u[g], h.w[g], r, ro, pv, n, Bc, c->d_part,
                                    c->d_fs, c->d_active, c->d_iters);
             }
             {
-                ProfScope ps(c, st, MLMC_KERNEL_REFINE, vec * (R.W + 8.0 + 8.0 + R.W), 0.0);
-                launch_fcg_resid<T>(st, h.a[g], h.w[g], n, Bc, r, h.f[g], c->d_part, c->d_active);
+                ProfScope ps(c, st, MLMC_KERNEL_REFINE, vec * (8.0 + 8.0 + 8.0 + R.W), 0.0);
+                launch_fcg_resid<T>(st, h.a64[g], h.w[g], n, Bc, r, h.f[g], c->d_part, c->d_active);
             }
             launch_fcg_fin_rho(st, c->d_part, n, Bc, c->d_rho, c->d_active, c->d_iters,
                                c->cfg.rtol, c->cfg.max_iters, 0);
@@ -751,9 +761,11 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     ctx->state_tuples = (int64_t)nshift_max * ctx->nq * c.num_levels;
     const bool mixed = c.precision == MLMC_MIXED;
     if (mixed) ctx->sp = mixed_pad_k(s);
-    const int64_t bsplit = mixed ? mixed_pad_cols(ctx->Mmax) * ctx->sp : 0;
-    const int64_t ysplit = mixed ? mixed_pad_rows(ctx->chunk_max) * ctx->sp : 0;
-    size_t need = (size_t)ctx->elem * 3 * (size_t)ctx->pool + 6 * (size_t)(bsplit + ysplit) +
+    const int64_t brows = mixed ? mixed_pad_cols(ctx->Mmax) : 0;
+    const int64_t yrows = mixed ? mixed_pad_rows(ctx->chunk_max) : 0;
+    const int64_t a64 = mixed ? ctx->pool : 0;
+    size_t need = (size_t)ctx->elem * 3 * (size_t)ctx->pool +
+                  (8 * (size_t)ctx->sp + 4) * (size_t)(brows + yrows) + 8 * (size_t)a64 +
                   sizeof(double) * ((size_t)s * ctx->Mmax + 3 * ctx->fcg_cells + parts + wcap +
                                     (size_t)ctx->chunk_max * (s + c.num_levels * ctx->nq + 2) +
                                     4 * ctx->state_tuples) +
@@ -776,10 +788,13 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
         ctx->d_u = (double *)pu;
         ctx->d_f = (double *)pf;
     }
-    for (int i = 0; i < 3 && mixed; ++i) {
-        CHK(dev_alloc(ctx, &ctx->d_bsplit[i], bsplit));
-        CHK(dev_alloc(ctx, &ctx->d_ysplit[i], ysplit));
+    for (int i = 0; i < 4 && mixed; ++i) {
+        CHK(dev_alloc(ctx, &ctx->d_bdig[i], brows * ctx->sp));
+        CHK(dev_alloc(ctx, &ctx->d_ydig[i], yrows * ctx->sp));
     }
+    CHK(dev_alloc(ctx, &ctx->d_bexp, brows));
+    CHK(dev_alloc(ctx, &ctx->d_yexp, yrows));
+    CHK(dev_alloc(ctx, &ctx->d_a64, a64));
     CHK(dev_alloc(ctx, &ctx->d_fcg, 3 * ctx->fcg_cells));
     CHK(dev_alloc(ctx, &ctx->d_part, parts));
     CHK(dev_alloc(ctx, &ctx->d_fs, ctx->fcg_cells > 0 ? 4 * ctx->chunk_max : 0));
@@ -825,8 +840,8 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     launch_build_basis(nullptr, d_psi, d_psi_off, d_mi, d_mj, d_coef, s, Gmax, ctx->d_basis, ctx->Mmax);
     CHK(hipGetLastError());
     if (mixed) {   // basis row m of the split = field column m, K = KL mode
-        launch_split3(nullptr, ctx->d_basis, ctx->Mmax, s, 1, ctx->Mmax, mixed_pad_cols(ctx->Mmax),
-                      ctx->sp, ctx->d_bsplit);
+        launch_digits_cols(nullptr, ctx->d_basis, ctx->Mmax, s, ctx->Mmax, brows, ctx->sp,
+                           ctx->d_bdig, ctx->d_bexp);
         CHK(hipGetLastError());
     }
     CHK(hipDeviceSynchronize());
@@ -892,12 +907,13 @@ mlmc_status mlmc_points_gen(mlmc_ctx ctx, const mlmc_points *pts, uint64_t *x_de
 
 namespace {
 // mixed mode: split the chunk's Y into bf16 terms, then the matrix-core product
-void field_bf16x3(mlmc_ctx ctx, hipStream_t s, const double *Y, int64_t M, int64_t Bc, void *out,
-                  int mode)
+void field_digits(mlmc_ctx ctx, hipStream_t s, const double *Y, int64_t M, int64_t Bc, void *out,
+                  double *out64, int mode)
 {
     const int sd = ctx->cfg.s;
-    launch_split3(s, Y, Bc, sd, sd, 1, mixed_pad_rows(Bc), ctx->sp, ctx->d_ysplit);
-    launch_field_bf16x3(s, ctx->d_ysplit, ctx->d_bsplit, ctx->sp, M, Bc, out, mode);
+    launch_digits_rows(s, Y, Bc, sd, sd, mixed_pad_rows(Bc), ctx->sp, ctx->d_ydig, ctx->d_yexp);
+    launch_field_digits(s, ctx->d_ydig, ctx->d_yexp, ctx->d_bdig, ctx->d_bexp, ctx->sp, M, Bc, out,
+                        out64, mode);
 }
 }  // namespace
 
@@ -917,7 +933,7 @@ mlmc_status mlmc_field(mlmc_ctx ctx, const mlmc_points *pts, double *z_dev, void
         int64_t Bc = std::min(ctx->chunk_max, B - b0);
         const double *Y = chunk_y(ctx, s, pts, npts, b0, Bc, nullptr);
         if (ctx->cfg.precision == MLMC_MIXED)
-            field_bf16x3(ctx, s, Y, M, Bc, z_dev + b0 * M, 0);
+            field_digits(ctx, s, Y, M, Bc, z_dev + b0 * M, nullptr, 0);
         else
             launch_field_gemm(s, Y, ctx->cfg.s, ctx->d_basis, ctx->Mmax, M, Bc, z_dev + b0 * M, 0);
     }
@@ -948,7 +964,7 @@ mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts, const double *z
         Hier h = make_hier(ctx, G, Bc);
         const bool mixed = ctx->cfg.precision == MLMC_MIXED;
         if (z_dev) {
-            launch_exp_to_levels(s, z_dev + b0 * M, M, Bc, ctx->d_a, mixed);
+            launch_exp_to_levels(s, z_dev + b0 * M, M, Bc, ctx->d_a, mixed, ctx->d_a64);
         } else {
             const double *Y;
             {
@@ -957,11 +973,12 @@ mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts, const double *z
             }
             const double sd = ctx->cfg.s;
             if (mixed) {
-                // six bf16 products per term; operands 3 x 2 bytes, a stored as float
+                // ten bf16 digit products per term; operands 4 x 2 bytes, a stored
+                // as float and double
                 ProfScope ps(ctx, s, MLMC_KERNEL_FIELD,
-                             8.0 * Bc * sd + 6.0 * (Bc + (double)M) * sd + 4.0 * Bc * M,
-                             12.0 * Bc * sd * M);
-                field_bf16x3(ctx, s, Y, M, Bc, ctx->d_a, 2);
+                             8.0 * Bc * sd + 8.0 * (Bc + (double)M) * sd + 12.0 * Bc * M,
+                             20.0 * Bc * sd * M);
+                field_digits(ctx, s, Y, M, Bc, ctx->d_a, ctx->d_a64, 2);
             } else {
                 ProfScope ps(ctx, s, MLMC_KERNEL_FIELD, 8.0 * (Bc * sd + sd * M + (double)Bc * M),
                              2.0 * Bc * sd * M);

@@ -42,21 +42,28 @@ void launch_build_basis(hipStream_t st, const double *psi, const int64_t *psi_of
 // mode 2 the same as float.
 void launch_field_gemm(hipStream_t st, const double *Y, int s, const double *basis, int64_t ld,
                        int64_t M, int64_t Bc, void *out, int mode);
+// a = exp(z) into the level-major pool; to_float: as float, with a double copy
+// in pool64 when that is not null
 void launch_exp_to_levels(hipStream_t st, const double *z, int64_t M, int64_t Bc, void *pool,
-                          bool to_float);
+                          bool to_float, double *pool64);
 
-// Mixed-precision field: operands split into three bf16 terms stored
-// K-contiguous ([rows_pad][sp], zero padded; bf16 bit patterns as uint16_t),
-// six-term product on the matrix cores.  mode 0 writes z (double) to
-// out[b*M + m]; mode 2 writes exp(z) as float into the level-major pool.
+// Mixed-precision field on the matrix cores: operands as four bf16 digit
+// arrays [rows_pad][sp] (bf16 bit patterns as uint16_t, zero padded) with a
+// power-of-two scale exponent per row; exact FP32 group sums folded in FP64.
+// mode 0 writes z (double) to out[b*M + m]; mode 2 writes exp(z) as float into
+// the level-major pool out and as double into out64.
 int64_t mixed_pad_rows(int64_t rows);
 int64_t mixed_pad_cols(int64_t cols);
 int mixed_pad_k(int s);
-// element (r, k) of X at X[r*rs + k*ks], r < rows, k < cols
-void launch_split3(hipStream_t st, const double *X, int64_t rows, int cols, int64_t rs, int64_t ks,
-                   int64_t rows_pad, int sp, uint16_t *const X3[3]);
-void launch_field_bf16x3(hipStream_t st, uint16_t *const Y[3], uint16_t *const Bs[3], int sp,
-                         int64_t M, int64_t Bc, void *out, int mode);
+// rows with unit mode stride: element (r, k) at X[r*rs + k], one wavefront per row
+void launch_digits_rows(hipStream_t st, const double *X, int64_t rows, int cols, int64_t rs,
+                        int64_t rows_pad, int sp, uint16_t *const D[4], int32_t *E);
+// rows at unit stride, modes at stride ks: element (r, k) at X[r + k*ks]
+void launch_digits_cols(hipStream_t st, const double *X, int64_t rows, int cols, int64_t ks,
+                        int64_t rows_pad, int sp, uint16_t *const D[4], int32_t *E);
+void launch_field_digits(hipStream_t st, uint16_t *const Y[4], const int32_t *EY,
+                         uint16_t *const Bs[4], const int32_t *EB, int sp, int64_t M, int64_t Bc,
+                         void *out, double *out64, int mode);
 
 void launch_coarse_solve(hipStream_t st, const double *a, const double *f, double *u, int64_t Bc,
                          const int32_t *active);
@@ -95,25 +102,26 @@ void launch_lds_vcycle(hipStream_t st, const T *a_pool, const T *f_pool, T *u_po
 // FMG stages 0..G, each stage g >= 1 solved to rtol by flexible CG in FP64
 // with one T V-cycle as the preconditioner; x of level G to u64_pool;
 // per-sample statistics
+// (a64_pool: FP64 coefficients of the CG operator, the a pool itself when T = double)
 template <typename T>
-void launch_lds_fmg_refine(hipStream_t st, const T *a_pool, double *u64_pool, int64_t Bc, int G,
-                           int mu1, int mu2, double rtol, int max_iters, int g0, double *qoi,
-                           int nlev, uint32_t mask, int32_t *st_iters, double *st_rho,
-                           int32_t *st_bad);
+void launch_lds_fmg_refine(hipStream_t st, const T *a_pool, const double *a64_pool,
+                           double *u64_pool, int64_t Bc, int G, int mu1, int mu2, double rtol,
+                           int max_iters, int g0, double *qoi, int nlev, uint32_t mask,
+                           int32_t *st_iters, double *st_rho, int32_t *st_bad);
 // flexible CG of one stage on a large grid (Bc samples of n x n, FP64 vectors
-// x, r, r_old, p; z from the T V-cycle).  Partial-sum scratch: fcg_partials
+// x, r, r_old, p and FP64 coefficients a; z from the T V-cycle).  Partial-sum scratch: fcg_partials
 // doubles; fs: 4 doubles per sample.
 int64_t fcg_partials(int n, int64_t Bc);
 // r = 1 - A x, f = T(r), partial ||r||^2 (active nullptr: every sample)
 template <typename T>
-void launch_fcg_resid(hipStream_t st, const T *a, const double *x, int n, int64_t Bc, double *r, T *f,
-                      double *part, const int32_t *active);
+void launch_fcg_resid(hipStream_t st, const double *a, const double *x, int n, int64_t Bc, double *r,
+                      T *f, double *part, const int32_t *active);
 // rho = ||r||/||1||; active = rho > rtol && iters < max_iters; iters counts steps
 void launch_fcg_fin_rho(hipStream_t st, const double *part, int n, int64_t Bc, double *rho,
                         int32_t *active, int32_t *iters, double rtol, int max_iters, int first);
 // one step after z = B r: beta, p = z + beta p, alpha = (r, z)/(p, A p), x += alpha p
 template <typename T>
-void launch_fcg_step(hipStream_t st, const T *a, const T *z, double *x, double *r, double *ro,
+void launch_fcg_step(hipStream_t st, const double *a, const T *z, double *x, double *r, double *ro,
                      double *pv, int n, int64_t Bc, double *part, double *fs,
                      const int32_t *active, const int32_t *iters);
 void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho, int64_t Bc,

@@ -196,16 +196,20 @@ __global__ __launch_bounds__(256) void k_field_gemm(const double *__restrict__ Y
 }
 
 __global__ void k_exp_to_levels(const double *__restrict__ z, int64_t M, int64_t Bc,
-                                void *__restrict__ pool, int to_float)
+                                void *__restrict__ pool, int to_float, double *__restrict__ pool64)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= M * Bc)
         return;
     int64_t b = t / M, m = t - b * M;
-    if (to_float)
-        ((float *)pool)[level_major_index(m, b, Bc)] = (float)exp(z[t]);
-    else
-        ((double *)pool)[level_major_index(m, b, Bc)] = exp(z[t]);
+    const int64_t q = level_major_index(m, b, Bc);
+    const double av = exp(z[t]);
+    if (to_float) {
+        ((float *)pool)[q] = (float)av;
+        if (pool64) pool64[q] = av;
+    } else {
+        ((double *)pool)[q] = av;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -483,10 +487,10 @@ void launch_field_gemm(hipStream_t st, const double *Y, int s, const double *bas
 }
 
 void launch_exp_to_levels(hipStream_t st, const double *z, int64_t M, int64_t Bc, void *pool,
-                          bool to_float)
+                          bool to_float, double *pool64)
 {
     hipLaunchKernelGGL(k_exp_to_levels, dim3(blocks_for(M * Bc)), dim3(kBlock), 0, st, z, M, Bc,
-                       pool, (int)to_float);
+                       pool, (int)to_float, pool64);
 }
 
 void launch_coarse_solve(hipStream_t st, const double *a, const double *f, double *u, int64_t Bc,

@@ -681,13 +681,16 @@ __device__ __forceinline__ double lds_apply(const TA *a, const double *u, int n,
 // stopped at max_iters.
 template <int GS, typename T>
 __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
-    const T *__restrict__ a_pool, double *__restrict__ u64_pool, int64_t Bc, int G, int mu1,
-    int mu2, double rtol, int max_iters, int g0, double *__restrict__ qoi, int nlev, uint32_t mask,
-    int32_t *__restrict__ st_iters, double *__restrict__ st_rho, int32_t *__restrict__ st_bad)
+    const T *__restrict__ a_pool, const double *__restrict__ a64_pool,
+    double *__restrict__ u64_pool, int64_t Bc, int G, int mu1, int mu2, double rtol, int max_iters,
+    int g0, double *__restrict__ qoi, int nlev, uint32_t mask, int32_t *__restrict__ st_iters,
+    double *__restrict__ st_rho, int32_t *__restrict__ st_bad)
 {
     constexpr int TOT = LdsHier<GS>::TOTAL;
     constexpr int TOP = 4 << (2 * GS);   // cells of the finest LDS level
+    constexpr bool F64 = sizeof(T) == sizeof(double);
     __shared__ T a_s[TOT], u_s[TOT], f_s[TOT];
+    __shared__ double a64_s[F64 ? 1 : TOT];   // FP64 coefficients of the CG operator
     __shared__ double w_s[TOT];          // FP64 stage solutions x
     __shared__ double r_s[TOP], ro_s[TOP], p_s[TOP];
     __shared__ double red_s[4 * LT];
@@ -695,10 +698,14 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
     if (b >= Bc) return;
     for (int g = 0; g <= G; ++g) {
         const int cnt = 4 << (2 * g);
-        const T *src = a_pool + Bc * level_offset(g) + b * (int64_t)cnt;
-        for (int p = threadIdx.x; p < cnt; p += LT) a_s[LdsHier<GS>::off(g) + p] = src[p];
+        const int64_t o = Bc * level_offset(g) + b * (int64_t)cnt;
+        for (int p = threadIdx.x; p < cnt; p += LT) {
+            a_s[LdsHier<GS>::off(g) + p] = a_pool[o + p];
+            if (!F64) a64_s[LdsHier<GS>::off(g) + p] = a64_pool[o + p];
+        }
     }
     __syncthreads();
+    const double *a64 = F64 ? (const double *)a_s : a64_s;
     LdsVcycle<GS, T> V{a_s, u_s, f_s, mu1, mu2};
     int it_max = 0, bad = 0;
     double rho_max = 0.0;
@@ -706,8 +713,8 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
         const int n = 2 << g, cells = n * n;
         double *xg = w_s + LdsHier<GS>::off(g);
         T *zg = u_s + LdsHier<GS>::off(g), *fg = f_s + LdsHier<GS>::off(g);
-        const T *ag = a_s + LdsHier<GS>::off(g);
-        if (g == 0) lds_coarse_solve<double>(a_s, (const double *)nullptr, xg);
+        const double *ag = a64 + LdsHier<GS>::off(g);
+        if (g == 0) lds_coarse_solve<double>(a64, (const double *)nullptr, xg);
         else lds_prolong(w_s + LdsHier<GS>::off(g - 1), xg, n, false);
         int it = 0;
         double rho, rz_old = 1.0;
@@ -854,8 +861,8 @@ __device__ __forceinline__ double fold_partials(const double *__restrict__ part,
 }
 
 // r = 1 - A x; f = TF(r); partial ||r||^2
-template <typename TA, typename TF>
-__global__ __launch_bounds__(256) void k_fcg_resid(const TA *__restrict__ a,
+template <typename TF>
+__global__ __launch_bounds__(256) void k_fcg_resid(const double *__restrict__ a,
                                                    const double *__restrict__ x, int n, int64_t Bc,
                                                    double *__restrict__ r, TF *__restrict__ f,
                                                    double *__restrict__ part,
@@ -967,8 +974,7 @@ __global__ __launch_bounds__(256) void k_fcg_p(const TZ *__restrict__ z, double 
 }
 
 // partial (p, A p)
-template <typename TA>
-__global__ __launch_bounds__(256) void k_fcg_pq(const TA *__restrict__ a,
+__global__ __launch_bounds__(256) void k_fcg_pq(const double *__restrict__ a,
                                                 const double *__restrict__ pv, int n, int64_t Bc,
                                                 double *__restrict__ part,
                                                 const int32_t *__restrict__ active)
@@ -1081,24 +1087,24 @@ void launch_lds_vcycle(hipStream_t st, const T *a_pool, const T *f_pool, T *u_po
 }
 
 template <typename T>
-void launch_lds_fmg_refine(hipStream_t st, const T *a_pool, double *u64_pool, int64_t Bc, int G,
-                           int mu1, int mu2, double rtol, int max_iters, int g0, double *qoi,
-                           int nlev, uint32_t mask, int32_t *st_iters, double *st_rho,
-                           int32_t *st_bad)
+void launch_lds_fmg_refine(hipStream_t st, const T *a_pool, const double *a64_pool,
+                           double *u64_pool, int64_t Bc, int G, int mu1, int mu2, double rtol,
+                           int max_iters, int g0, double *qoi, int nlev, uint32_t mask,
+                           int32_t *st_iters, double *st_rho, int32_t *st_bad)
 {
     hipLaunchKernelGGL((k_lds_fmg_refine<kLdsMaxLevel, T>), dim3(nblocks(Bc)), dim3(LT), 0, st,
-                       a_pool, u64_pool, Bc, G, mu1, mu2, rtol, max_iters, g0, qoi, nlev, mask,
-                       st_iters, st_rho, st_bad);
+                       a_pool, a64_pool, u64_pool, Bc, G, mu1, mu2, rtol, max_iters, g0, qoi, nlev,
+                       mask, st_iters, st_rho, st_bad);
 }
 
 int64_t fcg_partials(int n, int64_t Bc) { return Bc * (((int64_t)n * n + FCH - 1) / FCH) * 4; }
 
 template <typename T>
-void launch_fcg_resid(hipStream_t st, const T *a, const double *x, int n, int64_t Bc, double *r, T *f,
-                      double *part, const int32_t *active)
+void launch_fcg_resid(hipStream_t st, const double *a, const double *x, int n, int64_t Bc, double *r,
+                      T *f, double *part, const int32_t *active)
 {
     const int64_t nb = Bc * (((int64_t)n * n + FCH - 1) / FCH);
-    hipLaunchKernelGGL((k_fcg_resid<T, T>), dim3(nblocks(nb)), dim3(256), 0, st, a, x, n, Bc, r, f,
+    hipLaunchKernelGGL((k_fcg_resid<T>), dim3(nblocks(nb)), dim3(256), 0, st, a, x, n, Bc, r, f,
                        part, active);
 }
 
@@ -1110,7 +1116,7 @@ void launch_fcg_fin_rho(hipStream_t st, const double *part, int n, int64_t Bc, d
 }
 
 template <typename T>
-void launch_fcg_step(hipStream_t st, const T *a, const T *z, double *x, double *r, double *ro,
+void launch_fcg_step(hipStream_t st, const double *a, const T *z, double *x, double *r, double *ro,
                      double *pv, int n, int64_t Bc, double *part, double *fs,
                      const int32_t *active, const int32_t *iters)
 {
@@ -1120,7 +1126,7 @@ void launch_fcg_step(hipStream_t st, const T *a, const T *z, double *x, double *
                        iters);
     hipLaunchKernelGGL(k_fcg_fin_beta, dim3(ns), dim3(256), 0, st, part, n, Bc, fs, active, iters);
     hipLaunchKernelGGL((k_fcg_p<T>), dim3(nb), dim3(256), 0, st, z, pv, n, Bc, fs, active, iters);
-    hipLaunchKernelGGL((k_fcg_pq<T>), dim3(nb), dim3(256), 0, st, a, pv, n, Bc, part, active);
+    hipLaunchKernelGGL(k_fcg_pq, dim3(nb), dim3(256), 0, st, a, pv, n, Bc, part, active);
     hipLaunchKernelGGL(k_fcg_fin_alpha, dim3(ns), dim3(256), 0, st, part, n, Bc, fs, active);
     hipLaunchKernelGGL(k_fcg_x, dim3(nb), dim3(256), 0, st, x, pv, n, Bc, fs, active);
 }
@@ -1139,12 +1145,12 @@ void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho
                                       int64_t, const int32_t *);                                   \
     template void launch_lds_vcycle<T>(hipStream_t, const T *, const T *, T *, int64_t, int, int, \
                                        int, const int32_t *);                                      \
-    template void launch_lds_fmg_refine<T>(hipStream_t, const T *, double *, int64_t, int, int,   \
-                                           int, double, int, int, double *, int, uint32_t,        \
-                                           int32_t *, double *, int32_t *);                        \
-    template void launch_fcg_resid<T>(hipStream_t, const T *, const double *, int, int64_t,     \
+    template void launch_lds_fmg_refine<T>(hipStream_t, const T *, const double *, double *,      \
+                                           int64_t, int, int, int, double, int, int, double *,     \
+                                           int, uint32_t, int32_t *, double *, int32_t *);         \
+    template void launch_fcg_resid<T>(hipStream_t, const double *, const double *, int, int64_t,\
                                       double *, T *, double *, const int32_t *);                  \
-    template void launch_fcg_step<T>(hipStream_t, const T *, const T *, double *, double *,       \
+    template void launch_fcg_step<T>(hipStream_t, const double *, const T *, double *, double *,  \
                                      double *, double *, int, int64_t, double *, double *,        \
                                      const int32_t *, const int32_t *);
 MLMC_INSTANTIATE(double)

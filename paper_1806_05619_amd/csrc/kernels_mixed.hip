@@ -1,16 +1,26 @@
 // KL field of the mixed-precision path on the gfx950 matrix cores (Section 5,
-// eq. truncatedKL): z = Y basis with both operands split into three bf16
-// terms, x = x1 + x2 + x3 (x1 = bf16(x), x2 = bf16(x - x1), x3 = bf16(x - x1 -
-// x2)), and the six products x1 y1, x1 y2, x2 y1, x1 y3, x3 y1, x2 y2 issued as
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation over each 32-wide K chunk;
-// chunk sums are added in FP64 registers, a = exp(z) is formed in FP64 and
-// stored as FP32.
+// eq. truncatedKL): z = Y basis as a sum of exact bf16 products.
 //
-// Operands are stored K-contiguous (Y splits [rows][sp], basis splits
-// transposed [M][sp], sp = s rounded up to 32, zero padded) so that each lane
-// loads its 8 consecutive k values as one 16-byte vector.  MFMA lane layout
-// (16x16x32): A row l%16 and B column l%16 take k = 8*(l/16) .. +7; lane l
-// holds C rows 4*(l/16) .. +3 of column l%16.
+// Each row of Y (one sample, over the KL modes) and each field column of the
+// basis (one cell centre, over the modes) gets a power-of-two scale 2^E with
+// 2^E > max |x|; x 2^(7-E) is then written as four balanced base-256 digits,
+// x 2^(7-E) = d1 + d2 2^-8 + d3 2^-16 + d4 2^-24 + rest, |d| <= 128, |rest| <=
+// 2^-25.  Every digit is an integer of at most 8 bits, so it is exact in bf16,
+// every digit product is an integer below 2^14, and a sum of up to 256 of them
+// per group stays below 2^24: the FP32 accumulation of v_mfma_f32_16x16x32_bf16
+// is exact whatever its internal rounding.  The products are grouped by weight
+// (G0 = d1 e1; G1 = d1 e2 + d2 e1; G2 = d1 e3 + d3 e1 + d2 e2; G3 = d1 e4 + d4 e1
+// + d2 e3 + d3 e2; ten MFMAs per tile), and every 256 modes the groups are
+// folded exactly into FP64 accumulators.  The result is z times 2^(14 - E_r -
+// E_c) up to the dropped digit products of weight 2^-32 and the digit
+// remainders, about 2^-31 relative to max |y| max |b| per mode.  This is the
+// Ozaki splitting (Ozaki, Ogita, Oishi, Rump, Numer. Algorithms 59, 2012) with
+// fixed-point digits sized for bf16 matrix cores.
+//
+// Operands are stored K-contiguous ([rows_pad][sp], sp = s rounded up to 32,
+// zero padded) so that each lane loads its 8 consecutive k values as one
+// 16-byte vector.  MFMA lane layout (16x16x32): A row l%16 and B column l%16
+// take k = 8*(l/16) .. +7; lane l holds C rows 4*(l/16) .. +3 of column l%16.
 #include "internal.hpp"
 
 namespace mlmc {
@@ -19,39 +29,94 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int WM = 32, WN = 64;        // tile of one wave: 2 x 4 MFMA tiles
-constexpr int BM = 64, BN = 128;       // tile of a 4-wave block (2 x 2 waves)
+constexpr int WM = 32, WN = 32;        // tile of one wave: 2 x 2 MFMA tiles
+constexpr int BM = 64, BN = 64;        // tile of a 4-wave block (2 x 2 waves)
+constexpr int KFOLD = 8;               // K steps of 32 between folds into FP64
 
-// bf16 nearest to x (ties to even) via the FP32 value, as a bit pattern;
-// finite inputs only.  Written out so the split does not depend on the
-// rounding mode of a conversion instruction: a directed rounding would bias
-// every term the same way.
-__device__ __forceinline__ uint16_t bf16_rne(double x, double *value)
+// the bf16 bit pattern of an integer d with |d| <= 256 (exact)
+__device__ __forceinline__ uint16_t bf16_of_int(double d)
 {
-    uint32_t u = __float_as_uint((float)x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    const uint16_t h = (uint16_t)(u >> 16);
-    *value = (double)__uint_as_float((uint32_t)h << 16);
-    return h;
+    return (uint16_t)(__float_as_uint((float)d) >> 16);
 }
 
-// split X (rows x cols, element (r, k) at X[r*rs + k*ks]) into three bf16
-// arrays [rows_pad][sp]; padding rows and columns are zero.  Each residual is
-// exact in FP64.
-__global__ void k_split3(const double *__restrict__ X, int64_t rows, int cols, int64_t rs,
-                         int64_t ks, int64_t rows_pad, int sp, uint16_t *__restrict__ X1,
-                         uint16_t *__restrict__ X2, uint16_t *__restrict__ X3)
+// digits of x 2^(7-E), E the row scale
+__device__ __forceinline__ void digits4(double x, int E, uint16_t *d)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= rows_pad * sp) return;
-    const int64_t r = t / sp;
-    const int k = (int)(t - r * sp);
-    const double x = (r < rows && k < cols) ? X[r * rs + (int64_t)k * ks] : 0.0;
-    double v1, v2, v3;
-    X1[t] = bf16_rne(x, &v1);
-    const double r1 = x - v1;
-    X2[t] = bf16_rne(r1, &v2);
-    X3[t] = bf16_rne(r1 - v2, &v3);
+    double t = ldexp(x, 7 - E);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double v = rint(t);
+        d[q] = bf16_of_int(v);
+        t = (t - v) * 256.0;             // exact: |t - v| <= 1/2 has fewer bits than t
+    }
+}
+
+// scale exponent E with 2^(E-1) <= m < 2^E (m = max |x| > 0), 0 for m = 0
+__device__ __forceinline__ int scale_exp(double m)
+{
+    int e = 0;
+    if (m > 0.0) frexp(m, &e);
+    return e;
+}
+
+// one row per wavefront, modes along the lanes (rows with unit mode stride):
+// scale exponent and four digit arrays [rows_pad][sp]; padding is zero
+__global__ __launch_bounds__(256) void k_digits_wave(const double *__restrict__ X, int64_t rows,
+                                                     int cols, int64_t rs, int64_t rows_pad, int sp,
+                                                     uint16_t *__restrict__ D0,
+                                                     uint16_t *__restrict__ D1,
+                                                     uint16_t *__restrict__ D2,
+                                                     uint16_t *__restrict__ D3,
+                                                     int32_t *__restrict__ E)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows_pad) return;
+    const double *xr = X + r * rs;
+    const bool in = r < rows;
+    double m = 0.0;
+    for (int k = lane; k < cols && in; k += 64) m = fmax(m, fabs(xr[k]));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    const int e = scale_exp(m);
+    for (int k = lane; k < sp; k += 64) {
+        uint16_t d[4] = {0, 0, 0, 0};
+        if (in && k < cols) digits4(xr[k], e, d);
+        const int64_t o = r * sp + k;
+        D0[o] = d[0];
+        D1[o] = d[1];
+        D2[o] = d[2];
+        D3[o] = d[3];
+    }
+    if (lane == 0) E[r] = e;
+}
+
+// one row per thread (rows at unit stride, modes at stride ks: the basis
+// [s][ld] read as rows m = field columns)
+__global__ __launch_bounds__(256) void k_digits_thread(const double *__restrict__ X, int64_t rows,
+                                                       int cols, int64_t ks, int64_t rows_pad,
+                                                       int sp, uint16_t *__restrict__ D0,
+                                                       uint16_t *__restrict__ D1,
+                                                       uint16_t *__restrict__ D2,
+                                                       uint16_t *__restrict__ D3,
+                                                       int32_t *__restrict__ E)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows_pad) return;
+    const bool in = r < rows;
+    double m = 0.0;
+    for (int k = 0; k < cols && in; ++k) m = fmax(m, fabs(X[r + (int64_t)k * ks]));
+    const int e = scale_exp(m);
+    for (int k = 0; k < sp; ++k) {
+        uint16_t d[4] = {0, 0, 0, 0};
+        if (in && k < cols) digits4(X[r + (int64_t)k * ks], e, d);
+        const int64_t o = r * sp + k;
+        D0[o] = d[0];
+        D1[o] = d[1];
+        D2[o] = d[2];
+        D3[o] = d[3];
+    }
+    E[r] = e;
 }
 
 __device__ __forceinline__ int64_t level_major_index_m(int64_t m, int64_t b, int64_t Bc)
@@ -62,71 +127,105 @@ __device__ __forceinline__ int64_t level_major_index_m(int64_t m, int64_t b, int
     return Bc * lo + b * level_cells(g) + (m - lo);
 }
 
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
 // out mode 0: z (double) at out[b*M + m]; mode 2: exp(z) as float into the
-// level-major chunk pool.
-__global__ __launch_bounds__(256) void k_field_bf16x3(
-    const __bf16 *__restrict__ Y1, const __bf16 *__restrict__ Y2, const __bf16 *__restrict__ Y3,
-    const __bf16 *__restrict__ B1, const __bf16 *__restrict__ B2, const __bf16 *__restrict__ B3,
-    int sp, int64_t M, int64_t Bc, void *__restrict__ out, int mode)
+// level-major pool `out` and as double into `out64`.
+__global__ __launch_bounds__(256) void k_field_digits(
+    const uint16_t *__restrict__ Y0, const uint16_t *__restrict__ Y1,
+    const uint16_t *__restrict__ Y2, const uint16_t *__restrict__ Y3,
+    const int32_t *__restrict__ EY, const uint16_t *__restrict__ B0,
+    const uint16_t *__restrict__ B1, const uint16_t *__restrict__ B2,
+    const uint16_t *__restrict__ B3, const int32_t *__restrict__ EB, int sp, int64_t M, int64_t Bc,
+    void *__restrict__ out, double *__restrict__ out64, int mode)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t row0 = (int64_t)blockIdx.y * BM + (wave >> 1) * WM;    // sample rows
     const int64_t col0 = (int64_t)blockIdx.x * BN + (wave & 1) * WN;     // field columns
     const int lr = lane & 15, kg = 8 * (lane >> 4);
-    double acc[2][4][4];
+    const uint16_t *Yd[4] = {Y0, Y1, Y2, Y3};
+    const uint16_t *Bd[4] = {B0, B1, B2, B3};
+    double acc[2][2][4];
+    f32x4 G[4][2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 2; ++j) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc[i][j][e] = 0.0;
-
-    for (int k0 = 0; k0 < sp; k0 += 32) {
-        bf16x8 a[2][3], bb[4][3];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) G[g][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    const int nk = sp / 32;
+    for (int ks = 0; ks < nk; ++ks) {
+        const int k0 = 32 * ks;
+        bf16x8 a[2][4], b[2][4];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int64_t o = (row0 + 16 * i + lr) * sp + k0 + kg;
-            a[i][0] = *(const bf16x8 *)(Y1 + o);
-            a[i][1] = *(const bf16x8 *)(Y2 + o);
-            a[i][2] = *(const bf16x8 *)(Y3 + o);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) a[i][d] = *(const bf16x8 *)(Yd[d] + o);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 2; ++j) {
             const int64_t o = (col0 + 16 * j + lr) * sp + k0 + kg;
-            bb[j][0] = *(const bf16x8 *)(B1 + o);
-            bb[j][1] = *(const bf16x8 *)(B2 + o);
-            bb[j][2] = *(const bf16x8 *)(B3 + o);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) b[j][d] = *(const bf16x8 *)(Bd[d] + o);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                f32x4 c = {0.f, 0.f, 0.f, 0.f};
-                // smallest terms first
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], bb[j][1], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], bb[j][0], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], bb[j][2], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], bb[j][0], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], bb[j][1], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], bb[j][0], c, 0, 0, 0);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) acc[i][j][e] += (double)c[e];
+            for (int j = 0; j < 2; ++j) {
+                G[0][i][j] = mfma(a[i][0], b[j][0], G[0][i][j]);
+                G[1][i][j] = mfma(a[i][0], b[j][1], G[1][i][j]);
+                G[1][i][j] = mfma(a[i][1], b[j][0], G[1][i][j]);
+                G[2][i][j] = mfma(a[i][0], b[j][2], G[2][i][j]);
+                G[2][i][j] = mfma(a[i][2], b[j][0], G[2][i][j]);
+                G[2][i][j] = mfma(a[i][1], b[j][1], G[2][i][j]);
+                G[3][i][j] = mfma(a[i][0], b[j][3], G[3][i][j]);
+                G[3][i][j] = mfma(a[i][3], b[j][0], G[3][i][j]);
+                G[3][i][j] = mfma(a[i][1], b[j][2], G[3][i][j]);
+                G[3][i][j] = mfma(a[i][2], b[j][1], G[3][i][j]);
             }
+        if ((ks + 1) % KFOLD == 0 || ks + 1 == nk) {
+            // exact: the groups are integers below 2^24 and span < 53 bits
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        acc[i][j][e] += (double)G[0][i][j][e] + 0x1p-8 * (double)G[1][i][j][e] +
+                                        0x1p-16 * (double)G[2][i][j][e] +
+                                        0x1p-24 * (double)G[3][i][j][e];
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) G[g][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+                }
+        }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 2; ++j) {
         const int64_t m = col0 + 16 * j + lr;
         if (m >= M) continue;
+        const int ec = EB[m];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t b = row0 + 16 * i + 4 * (lane >> 4) + e;
                 if (b >= Bc) continue;
-                if (mode == 0)
-                    ((double *)out)[b * M + m] = acc[i][j][e];
-                else
-                    ((float *)out)[level_major_index_m(m, b, Bc)] = (float)exp(acc[i][j][e]);
+                const double z = ldexp(acc[i][j][e], EY[b] + ec - 14);
+                if (mode == 0) {
+                    ((double *)out)[b * M + m] = z;
+                } else {
+                    const int64_t q = level_major_index_m(m, b, Bc);
+                    const double av = exp(z);
+                    ((float *)out)[q] = (float)av;
+                    out64[q] = av;
+                }
             }
     }
 }
@@ -137,21 +236,27 @@ int64_t mixed_pad_rows(int64_t rows) { return (rows + BM - 1) / BM * BM; }
 int64_t mixed_pad_cols(int64_t cols) { return (cols + BN - 1) / BN * BN; }
 int mixed_pad_k(int s) { return (s + 31) / 32 * 32; }
 
-void launch_split3(hipStream_t st, const double *X, int64_t rows, int cols, int64_t rs, int64_t ks,
-                   int64_t rows_pad, int sp, uint16_t *const X3[3])
+void launch_digits_rows(hipStream_t st, const double *X, int64_t rows, int cols, int64_t rs,
+                        int64_t rows_pad, int sp, uint16_t *const D[4], int32_t *E)
 {
-    const int64_t n = rows_pad * sp;
-    hipLaunchKernelGGL(k_split3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, rows, cols,
-                       rs, ks, rows_pad, sp, X3[0], X3[1], X3[2]);
+    hipLaunchKernelGGL(k_digits_wave, dim3((unsigned)((rows_pad + 3) / 4)), dim3(256), 0, st, X, rows,
+                       cols, rs, rows_pad, sp, D[0], D[1], D[2], D[3], E);
 }
 
-void launch_field_bf16x3(hipStream_t st, uint16_t *const Y[3], uint16_t *const Bs[3], int sp,
-                         int64_t M, int64_t Bc, void *out, int mode)
+void launch_digits_cols(hipStream_t st, const double *X, int64_t rows, int cols, int64_t ks,
+                        int64_t rows_pad, int sp, uint16_t *const D[4], int32_t *E)
+{
+    hipLaunchKernelGGL(k_digits_thread, dim3((unsigned)((rows_pad + 255) / 256)), dim3(256), 0, st, X,
+                       rows, cols, ks, rows_pad, sp, D[0], D[1], D[2], D[3], E);
+}
+
+void launch_field_digits(hipStream_t st, uint16_t *const Y[4], const int32_t *EY,
+                         uint16_t *const Bs[4], const int32_t *EB, int sp, int64_t M, int64_t Bc,
+                         void *out, double *out64, int mode)
 {
     dim3 grid((unsigned)((M + BN - 1) / BN), (unsigned)((Bc + BM - 1) / BM));
-    hipLaunchKernelGGL(k_field_bf16x3, grid, dim3(256), 0, st, (const __bf16 *)Y[0],
-                       (const __bf16 *)Y[1], (const __bf16 *)Y[2], (const __bf16 *)Bs[0],
-                       (const __bf16 *)Bs[1], (const __bf16 *)Bs[2], sp, M, Bc, out, mode);
+    hipLaunchKernelGGL(k_field_digits, grid, dim3(256), 0, st, Y[0], Y[1], Y[2], Y[3], EY, Bs[0],
+                       Bs[1], Bs[2], Bs[3], EB, sp, M, Bc, out, out64, mode);
 }
 
 }  // namespace mlmc

@@ -289,14 +289,15 @@ def _mixed_ctx(**over):
 
 
 @pytest.mark.parametrize("k,B", [(3, 100), (5, 7)])
-def test_mixed_field_within_split_bound(oracle_mod, k, B):
-    """Mixed-precision field (Section 5 product as three-term bf16 splits on
-    the matrix cores): |z - z_fp64| <= 8 * 2^-24 * sum_j |y_j| |b_j(m)|.
-    The six kept products leave out terms below 2 * 2^-24 |y b|, the split
-    truncation adds at most about 2 * 2^-24 |y b|, and FP32 accumulation over
-    a 32-wide K chunk adds a few units of 2^-24 relative to the absolute sum;
-    chunk sums are added in FP64.  Ragged in both the sample and the column
-    tiles (M and B are not multiples of 128 and 64)."""
+def test_mixed_field_digit_bound(oracle_mod, k, B):
+    """Mixed-precision field (Section 5 product as bf16 digit products on the
+    matrix cores).  With 2^(E_r - 1) <= max_j |y_j| < 2^E_r per sample and
+    likewise E_m per cell over the basis column, each mode contributes at most
+    5 * 2^(E_r + E_m - 32) (digit remainders and dropped digit products), so
+    |z - z_fp64| <= 5 s 2^(E_r + E_m - 32).  The digit sums are exact, so the
+    error has no rounding bias: its mean over all cells stays below 1e-10
+    (FP32-accumulated bf16 splits leave a bias of a few 1e-8 here).
+    Ragged in both the sample and the column tiles (M, B not multiples of 64)."""
     dev = _dev()
     w, ctx = _mixed_ctx(num_levels=k + 1)
     P = _oracle_problem(oracle_mod, w)
@@ -308,13 +309,16 @@ def test_mixed_field_within_split_bound(oracle_mod, k, B):
     torch.cuda.synchronize()
     zg = z.cpu().numpy()
     basis = np.stack([P.field(np.eye(w["s"])[j], k) for j in range(w["s"])])   # [s][M]
-    worst = 0.0
-    for b in range(B):
-        zo = P.field(ys[b], k)
-        bound = np.abs(ys[b]) @ np.abs(basis)
-        worst = max(worst, float(np.max(np.abs(zg[b] - zo) / bound)))
-    print(f"\nmax |z - z_fp64| / sum|y||b| = {worst:.3e} (= {worst * 2**24:.2f} * 2^-24)")
-    assert worst <= 8 * 2.0**-24
+    zo = ys @ basis
+    Er = np.frexp(np.abs(ys).max(axis=1))[1].astype(float)              # per sample
+    Em = np.frexp(np.abs(basis).max(axis=0))[1].astype(float)           # per cell
+    bound = 5 * w["s"] * np.exp2(Er[:, None] + Em[None, :] - 32)
+    err = zg - zo
+    ratio = float(np.max(np.abs(err) / bound))
+    print(f"\nmax |z - z_fp64| = {np.abs(err).max():.2e} ({ratio:.2e} of the bound), "
+          f"mean error {err.mean():.2e}")
+    assert ratio <= 1.0
+    assert abs(err.mean()) <= 1e-10
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -347,7 +351,7 @@ def test_rough_lattice_workload_every_sample_converges(oracle_mod, precision):
     assert 0 < info["max_rel_residual"] <= w["rtol"]
     assert np.all(np.isfinite(qg))
     _, ys = _lattice_y(oracle_mod, w, k, [0], 0, npts)
-    tol = 1e-8 if precision == "fp64" else 2e-7
+    tol = 1e-8
     for b in range(0, npts, 24):
         qd = P.sample(k, ys[b], 1)
         rel = np.abs(qg[b] - qd) / np.abs(qd)
@@ -359,9 +363,9 @@ def test_refinement_high_contrast_matches_direct_solve(oracle_mod, precision):
     """sigma^2 = 2, lambda = 0.1, s = 400: FP64 residual refinement to 1e-10
     with FP64 or FP32 V-cycles, against the oracle's FP64 field and band
     Cholesky solve on every level up to 128^2 (the batched tile path).  The
-    mixed-precision error is that of the bf16x3 field (a few 2^-24 relative
-    to sum |y||b|) and of its FP32 storage plus the solve tolerance; it is
-    reported per level (about 4e-8 relative here)."""
+    mixed path converges to the operator of its FP64 coefficient copy, so its
+    error is that of the digit-product field plus the solve tolerance; it is
+    reported per level and held to 1e-8 relative."""
     dev = _dev()
     prec = m.MLMC_MIXED if precision == "mixed" else m.MLMC_FP64
     w, ctx = _mixed_ctx(precision=prec)
@@ -377,5 +381,5 @@ def test_refinement_high_contrast_matches_direct_solve(oracle_mod, precision):
         qd = P.sample(k, ys[b], 1)
         errs = np.maximum(errs, np.abs(qg[b] - qd) / np.abs(qd))
     print(f"\n{precision}: max relative QoI error per level (mean, centre):\n{errs}")
-    tol = 1e-9 if precision == "fp64" else 2e-7
+    tol = 1e-9 if precision == "fp64" else 1e-8
     assert errs.max() <= tol, errs
