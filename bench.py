@@ -34,17 +34,38 @@ FP64_PEAK_TFLOPS = 78.6
 
 
 KINDS = ("points", "field", "smooth", "restrict", "prolong", "coarse", "qoi", "sums", "pre", "post",
-         "lds")
+         "lds", "refine")
 KERNEL_NAMES = dict(
     points="k_points", field="k_field_gemm", smooth="k_rbgs (one colour)",
     restrict="k_resid_restrict", prolong="k_prolong", coarse="k_coarse_solve", qoi="k_qoi",
     sums="k_sums", pre="k_pre_tile<2> (2 red-black sweeps + residual + restriction, 64^2..256^2)",
     post="k_post_tile<2> (prolongation + correction + 2 sweeps, 64^2..256^2)",
-    lds="k_lds_mg<4> (LDS-resident grids <= 32^2)")
+    lds="k_lds_mg<4> (LDS-resident grids <= 32^2)",
+    refine="k_fcg_* (flexible-CG vector passes, grids >= 64^2)")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+# HBM bytes per launch of a kernel from two rocprofv3 --pmc passes (FETCH_SIZE,
+# WRITE_SIZE), scaled by the same counters on a 1 GiB copy; valid only while
+# the kernel source is the one the counters were taken on.
+TRAFFIC_RECORDS = dict(pre="profiles/pre_tile_mlqmc_fp64_s100_256_traffic.txt")
+
+
+def measured_traffic(kind):
+    import hashlib
+    rec = TRAFFIC_RECORDS.get(kind)
+    if not rec or not os.path.exists(os.path.join(ROOT, rec)):
+        return None, "no counter record"
+    with open(os.path.join(ROOT, rec)) as fh:
+        r = json.load(fh)
+    with open(os.path.join(ROOT, r["source"]), "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if sha != r["source_sha256"]:
+        return None, f"{rec}: kernel source changed since the counters were taken"
+    return r["hbm_bytes_per_launch"], rec
 
 
 def make_context(m, w, max_batch):
@@ -56,6 +77,61 @@ def make_context(m, w, max_batch):
                      genvec=synth.korobov_vector(w["seed"], w["s"]),
                      shifts=synth.shift_table(w["seed"], w["num_levels"], w["num_shifts"], w["s"]),
                      max_batch=max_batch, device=0)
+
+
+def mixed_vs_fp64(m, torch, dev, max_batch=64, min_seconds=0.25):
+    """The s = 400 workload (lambda 0.1, sigma^2 2, 4^2 .. 1024^2) with both
+    paths run to the same stopping rule (relative residual 1e-10 per FMG
+    stage): FP64 CG with FP64 V-cycles and an FP64 product field, against
+    FP64 CG with FP32 V-cycles and the bf16 digit-product field.  Per level:
+    samples/s of each (lattice points of shift 0, 2^26 / n^2 of them, at most
+    65536), their ratio, the largest relative QoI difference between the two,
+    step counts and unconverged samples."""
+    import synth
+    w = synth.workload("mlqmc_mixed_s400")
+    out = dict(workload="mlqmc_mixed_s400: lambda 0.1, sigma^2 2, s = 400, levels 4^2..1024^2, "
+                        "FMG with every stage solved to relative residual 1e-10 by V(2,2)-"
+                        "preconditioned flexible CG", rtol=w["rtol"], levels={})
+    ctxs = {}
+    for name, prec in (("fp64", m.MLMC_FP64), ("mixed", m.MLMC_MIXED)):
+        ctxs[name] = m.Context(w["n0"], w["num_levels"], w["s"], w["corr_len"], w["sigma2"],
+                               mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"],
+                               max_iters=w["max_iters"], precision=prec,
+                               qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
+                               genvec=synth.korobov_vector(w["seed"], w["s"]),
+                               shifts=synth.shift_table(w["seed"], w["num_levels"],
+                                                        w["num_shifts"], w["s"]),
+                               max_batch=max_batch, device=0)
+    for k in range(w["num_levels"]):
+        n = w["n0"] << k
+        npts = int(min(65536, max(16, (1 << 26) // (n * n))))
+        row = dict(samples=npts)
+        q = {}
+        for name, c in ctxs.items():
+            p = c.lattice(k, 0, npts, 0, 1)
+            qq = torch.zeros((npts, k + 1, 2), dtype=torch.float64, device=dev)
+            info = c.fmg_solve(p, qoi=qq, want_info=True)
+            torch.cuda.synchronize()
+            reps, t0 = 0, time.perf_counter()
+            while True:
+                c.fmg_solve(p, qoi=qq)
+                torch.cuda.synchronize()
+                reps += 1
+                if time.perf_counter() - t0 >= min_seconds:
+                    break
+            dt = (time.perf_counter() - t0) / reps
+            row[f"{name}_samples_per_s"] = npts / dt
+            row[f"{name}_max_steps"] = info["max_iters_used"]
+            row[f"{name}_not_converged"] = info["not_converged"]
+            q[name] = qq.cpu().numpy()
+        row["ratio_mixed_over_fp64"] = row["mixed_samples_per_s"] / row["fp64_samples_per_s"]
+        row["max_rel_qoi_diff"] = float(np.max(np.abs(q["mixed"] - q["fp64"]) / np.abs(q["fp64"])))
+        out["levels"][f"{n}^2"] = row
+        log(f"[bench] mixed vs fp64 {n}^2: {row['mixed_samples_per_s']:.0f} vs "
+            f"{row['fp64_samples_per_s']:.0f} samples/s (x{row['ratio_mixed_over_fp64']:.2f}), "
+            f"max rel diff {row['max_rel_qoi_diff']:.1e}")
+    del ctxs
+    return out
 
 
 def cpu_baseline(w, level, seconds):
@@ -95,6 +171,10 @@ def main():
                     help="skip per-level, latency and CPU-baseline measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-vs-FP64 comparison on the s = 400 workload")
+    ap.add_argument("--only-mixed", action="store_true",
+                    help="run only the mixed-vs-FP64 comparison (prints its JSON object)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path "
@@ -108,6 +188,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.only_mixed:
+        print(json.dumps(mixed_vs_fp64(m, torch, dev)), flush=True)
+        return
     w = synth.workload("mlqmc_fp64_s100")
     k = w["num_levels"] - 1
     npts = 1 << w["lattice_log2n"]
@@ -167,9 +250,10 @@ def main():
     avg_ms = prof["total_ms"] / max(prof["launches"], 1)
     bytes_per_launch = prof["bytes"] / max(prof["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic, traffic_src = measured_traffic(dominant)
     roofline = dict(kernel=KERNEL_NAMES[dominant], bound="hbm",
                     achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=None,
+                    frac=achieved / HBM_PEAK_GBS, traffic=traffic, traffic_source=traffic_src,
                     avg_launch_ms=avg_ms, launches_per_step=prof["launches"] / args.steps,
                     algorithmic_bytes_per_launch=bytes_per_launch,
                     share_of_step=prof["total_ms"] / (elapsed * 1e3))
@@ -222,6 +306,10 @@ def main():
             lat[f"level{k}_n{nreq}"] = dict(p50_ms=float(np.percentile(times, 50)),
                                             p99_ms=float(np.percentile(times, 99)))
         out["latency"] = lat
+        if not args.no_mixed:
+            del ctx
+            torch.cuda.empty_cache()
+            out["mixed"] = mixed_vs_fp64(m, torch, dev)
         log("[bench] extras done; CPU baseline ...")
         out["cpu_baseline"] = cpu_baseline(w, k, args.cpu_seconds)
     print(json.dumps(out), flush=True)
