@@ -354,8 +354,9 @@ __global__ __launch_bounds__(NT) void k_post_tile(const T *__restrict__ a, const
 }
 
 // ---------------------------------------------------------------------------
-// LDS-resident hierarchy 2^2 .. 2^(GS+1) for one sample per workgroup.
-constexpr int LT = 256;                 // threads per LDS workgroup
+// LDS-resident hierarchy 2^2 .. 2^(GS+1) for one sample per workgroup of LT
+// threads (LT is a template parameter of every routine below: one wavefront
+// for grids <= 8^2, up to 256 threads for 32^2).
 
 template <int GS>
 struct LdsHier {
@@ -385,7 +386,7 @@ __device__ __forceinline__ T lds_nb(const T *u, int n, int i, int j)
 }
 
 // one colour; f == nullptr means f = 1
-template <typename T>
+template <int LT, typename T>
 __device__ void lds_sweep(const T *a, const T *f, T *u, int n, int colour)
 {
     const int half = n / 2;
@@ -427,33 +428,50 @@ __device__ __forceinline__ TU lds_resid(const TA *a, const TU *f, const TU *u, i
     return (f ? f[i + n * j] : TU(1)) - TU(n) * TU(n) * lds_flux<TU>(a, u, n, i, j);
 }
 
-// exact 2x2 solve A u = f (f nullptr: f = 1) in the arithmetic of TU
+// Cholesky factor of h^2 A on the 2x2 grid (h^2 = 1/4), in the arithmetic of
+// TU, computed by thread 0 into L[10] (row-packed lower triangle).  The
+// coefficients do not change during a sample's solve, so it is factored once.
+// Cells 0:(0,0) 1:(1,0) 2:(0,1) 3:(1,1).
 template <typename TU, typename TA>
-__device__ void lds_coarse_solve(const TA *a, const TU *f, TU *u)
+__device__ void lds_chol4(const TA *a, TU *L)
 {
     if (threadIdx.x == 0) {
         const TU a0 = TU(a[0]), a1 = TU(a[1]), a2 = TU(a[2]), a3 = TU(a[3]);
         const TU w01 = hm(a0, a1), w02 = hm(a0, a2), w13 = hm(a1, a3), w23 = hm(a2, a3);
-        TU A[4][4] = {{w01 + w02 + TU(4) * a0, -w01, -w02, TU(0)},
-                      {-w01, w01 + w13 + TU(4) * a1, TU(0), -w13},
-                      {-w02, TU(0), w02 + w23 + TU(4) * a2, -w23},
-                      {TU(0), -w13, -w23, w13 + w23 + TU(4) * a3}};
-        TU L[4][4] = {}, v[4];
+        const TU A[4][4] = {{w01 + w02 + TU(4) * a0, -w01, -w02, TU(0)},
+                            {-w01, w01 + w13 + TU(4) * a1, TU(0), -w13},
+                            {-w02, TU(0), w02 + w23 + TU(4) * a2, -w23},
+                            {TU(0), -w13, -w23, w13 + w23 + TU(4) * a3}};
+        TU l[4][4] = {};
         for (int p = 0; p < 4; ++p)
             for (int q = 0; q <= p; ++q) {
                 TU s = A[p][q];
-                for (int t = 0; t < q; ++t) s -= L[p][t] * L[q][t];
-                L[p][q] = (p == q) ? sqrt(s) : s / L[q][q];
+                for (int k = 0; k < q; ++k) s -= l[p][k] * l[q][k];
+                l[p][q] = (p == q) ? sqrt(s) : s / l[q][q];
             }
+        int k = 0;
+        for (int p = 0; p < 4; ++p)
+            for (int q = 0; q <= p; ++q) L[k++] = l[p][q];
+    }
+}
+
+// exact 2x2 solve A u = f (f nullptr: f = 1) with the factor of lds_chol4
+template <typename TU>
+__device__ void lds_coarse_solve(const TU *L, const TU *f, TU *u)
+{
+    if (threadIdx.x == 0) {
+        // row p of the packed factor starts at p (p + 1) / 2
+        TU v[4];
         for (int p = 0; p < 4; ++p) {
+            const TU *lp = L + p * (p + 1) / 2;
             TU s = TU(0.25) * (f ? f[p] : TU(1));
-            for (int q = 0; q < p; ++q) s -= L[p][q] * v[q];
-            v[p] = s / L[p][p];
+            for (int q = 0; q < p; ++q) s -= lp[q] * v[q];
+            v[p] = s / lp[p];
         }
         for (int p = 3; p >= 0; --p) {
             TU s = v[p];
-            for (int q = p + 1; q < 4; ++q) s -= L[q][p] * v[q];
-            v[p] = s / L[p][p];
+            for (int q = p + 1; q < 4; ++q) s -= L[q * (q + 1) / 2 + p] * v[q];
+            v[p] = s / L[p * (p + 1) / 2 + p];
         }
         for (int p = 0; p < 4; ++p) u[p] = v[p];
     }
@@ -461,7 +479,7 @@ __device__ void lds_coarse_solve(const TA *a, const TU *f, TU *u)
 }
 
 // u = P e (add = false) or u += P e on the n x n grid
-template <typename T>
+template <int LT, typename T>
 __device__ void lds_prolong(const T *e, T *u, int n, bool add)
 {
     const int nc = n / 2;
@@ -475,9 +493,10 @@ __device__ void lds_prolong(const T *e, T *u, int n, bool add)
     __syncthreads();
 }
 
-template <int GS, typename T>
+template <int GS, typename T, int LT>
 struct LdsVcycle {
     T *a, *u, *f;   // LDS bases, level g at LdsHier<GS>::off(g)
+    const T *chol;  // Cholesky factor of the 2x2 grid (lds_chol4), in LDS
     int mu1, mu2;
     // V(mu1,mu2) at level g (one coarse-grid correction per level, so the
     // recursion unrolls into a descent and an ascent).  The top right-hand
@@ -489,8 +508,8 @@ struct LdsVcycle {
             T *al = a + LdsHier<GS>::off(l), *ul = u + LdsHier<GS>::off(l);
             const T *fl = (l == g) ? ftop : f + LdsHier<GS>::off(l);
             for (int it = 0; it < mu1; ++it) {
-                lds_sweep(al, fl, ul, n, 0);
-                lds_sweep(al, fl, ul, n, 1);
+                lds_sweep<LT>(al, fl, ul, n, 0);
+                lds_sweep<LT>(al, fl, ul, n, 1);
             }
             T *fcl = f + LdsHier<GS>::off(l - 1), *ucl = u + LdsHier<GS>::off(l - 1);
             for (int q = threadIdx.x; q < nc * nc; q += LT) {
@@ -504,41 +523,19 @@ struct LdsVcycle {
             }
             __syncthreads();
         }
-        lds_coarse_solve<T>(a, g == 0 ? ftop : f, u);
+        lds_coarse_solve<T>(chol, g == 0 ? ftop : f, u);
         for (int l = 1; l <= g; ++l) {
             const int n = 2 << l;
             T *al = a + LdsHier<GS>::off(l), *ul = u + LdsHier<GS>::off(l);
             const T *fl = (l == g) ? ftop : f + LdsHier<GS>::off(l);
-            lds_prolong(u + LdsHier<GS>::off(l - 1), ul, n, true);
+            lds_prolong<LT>(u + LdsHier<GS>::off(l - 1), ul, n, true);
             for (int it = 0; it < mu2; ++it) {
-                lds_sweep(al, fl, ul, n, 1);
-                lds_sweep(al, fl, ul, n, 0);
+                lds_sweep<LT>(al, fl, ul, n, 1);
+                lds_sweep<LT>(al, fl, ul, n, 0);
             }
         }
     }
 };
-
-// Deterministic block reduction of per-thread compensated partial sums
-// (fixed pairwise tree).  Returns the total in every thread.
-__device__ double lds_reduce(double s, double c, double *scratch)
-{
-    scratch[2 * threadIdx.x] = s;
-    scratch[2 * threadIdx.x + 1] = c;
-    __syncthreads();
-    for (int w = LT / 2; w >= 1; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            const double s1 = scratch[2 * threadIdx.x], c1 = scratch[2 * threadIdx.x + 1];
-            const double s2 = scratch[2 * (threadIdx.x + w)], c2 = scratch[2 * (threadIdx.x + w) + 1];
-            const double t = s1 + s2, bb = t - s1;
-            scratch[2 * threadIdx.x] = t;
-            scratch[2 * threadIdx.x + 1] = c1 + c2 + ((s1 - (t - bb)) + (s2 - bb));
-        }
-        __syncthreads();
-    }
-    const double r = scratch[0] + scratch[1];
-    __syncthreads();
-    return r;
-}
 
 __device__ __forceinline__ void neumaier(double &s, double &c, double x)
 {
@@ -547,6 +544,59 @@ __device__ __forceinline__ void neumaier(double &s, double &c, double x)
     s = t;
 }
 
+// (s, c) += (s2, c2) for compensated pairs (TwoSum of the leading parts)
+__device__ __forceinline__ void two_sum_fold(double &s, double &c, double s2, double c2)
+{
+    const double t = s + s2, bb = t - s;
+    c = c + c2 + ((s - (t - bb)) + (s2 - bb));
+    s = t;
+}
+
+// Deterministic block reduction of NV per-thread compensated partial sums:
+// a butterfly inside each wavefront, then every thread folds the wavefront
+// totals in wavefront order (scratch: 2 NV doubles per wavefront).  Returns
+// the totals in every thread.
+template <int LT, int NV>
+__device__ __forceinline__ void lds_reduce_n(double *s, double *c, double *scratch, double *v)
+{
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1)
+            two_sum_fold(s[k], c[k], __shfl_xor(s[k], m, 64), __shfl_xor(c[k], m, 64));
+    if constexpr (LT == 64) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = s[k] + c[k];
+        return;
+    }
+    constexpr int NW = LT / 64;
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            scratch[(wave * NV + k) * 2] = s[k];
+            scratch[(wave * NV + k) * 2 + 1] = c[k];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double S = scratch[k * 2], C = scratch[k * 2 + 1];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) two_sum_fold(S, C, scratch[(w * NV + k) * 2], scratch[(w * NV + k) * 2 + 1]);
+        v[k] = S + C;
+    }
+    __syncthreads();
+}
+
+template <int LT>
+__device__ __forceinline__ double lds_reduce(double s, double c, double *scratch)
+{
+    double v;
+    lds_reduce_n<LT, 1>(&s, &c, scratch, &v);
+    return v;
+}
+
+template <int LT>
 __device__ void lds_write_qoi(const double *ug, int n, double *qoi, int64_t b, int nlev, int l,
                               uint32_t mask, double *scratch)
 {
@@ -555,7 +605,7 @@ __device__ void lds_write_qoi(const double *ug, int n, double *qoi, int64_t b, i
     if (mask & 1u) {
         double s = 0.0, c = 0.0;
         for (int p = threadIdx.x; p < n * n; p += LT) neumaier(s, c, ug[p]);
-        qm = lds_reduce(s, c, scratch) / ((double)n * n);
+        qm = lds_reduce<LT>(s, c, scratch) / ((double)n * n);
     }
     if (threadIdx.x == 0) {
         double *qb = qoi + (b * nlev + l) * nq;
@@ -571,7 +621,7 @@ __device__ void lds_write_qoi(const double *ug, int n, double *qoi, int64_t b, i
 
 // FMG stages 0..G (G <= GS) with fixed mu0 cycles, FP64; QoI of stages g >= g0;
 // final u of level G to the u pool.
-template <int GS>
+template <int GS, int LT>
 __global__ __launch_bounds__(LT) void k_lds_fmg_fixed(const double *__restrict__ a_pool,
                                                       double *__restrict__ u_pool, int64_t Bc,
                                                       int G, int mu0, int mu1, int mu2, int g0,
@@ -580,7 +630,7 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_fixed(const double *__restrict__
 {
     constexpr int TOT = LdsHier<GS>::TOTAL;
     __shared__ double a_s[TOT], u_s[TOT], f_s[TOT];
-    __shared__ double red_s[2 * LT];
+    __shared__ double red_s[4 * (LT / 64)], chol_s[10];
     const int64_t b = blockIdx.x;
     if (b >= Bc) return;
     for (int g = 0; g <= G; ++g) {
@@ -589,17 +639,19 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_fixed(const double *__restrict__
         for (int p = threadIdx.x; p < cnt; p += LT) a_s[LdsHier<GS>::off(g) + p] = src[p];
     }
     __syncthreads();
-    LdsVcycle<GS, double> V{a_s, u_s, f_s, mu1, mu2};
+    lds_chol4<double>(a_s, chol_s);
+    __syncthreads();
+    LdsVcycle<GS, double, LT> V{a_s, u_s, f_s, chol_s, mu1, mu2};
     for (int g = 0; g <= G; ++g) {
         const int n = 2 << g;
         double *ug = u_s + LdsHier<GS>::off(g);
         if (g == 0) {
             V.run(0, nullptr);
         } else {
-            lds_prolong(u_s + LdsHier<GS>::off(g - 1), ug, n, false);
+            lds_prolong<LT>(u_s + LdsHier<GS>::off(g - 1), ug, n, false);
             for (int c = 0; c < mu0; ++c) V.run(g, nullptr);
         }
-        if (g >= g0) lds_write_qoi(ug, n, qoi, b, nlev, g - g0, mask, red_s);
+        if (g >= g0) lds_write_qoi<LT>(ug, n, qoi, b, nlev, g - g0, mask, red_s);
     }
     const int cntG = 4 << (2 * G);
     double *dst = u_pool + Bc * level_offset(G) + b * (int64_t)cntG;
@@ -608,14 +660,14 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_fixed(const double *__restrict__
 
 // One V-cycle at level G (<= GS) with zero initial guess, f from the f pool,
 // correction to the u pool.
-template <int GS, typename T>
+template <int GS, typename T, int LT>
 __global__ __launch_bounds__(LT) void k_lds_vcycle(const T *__restrict__ a_pool,
                                                    const T *__restrict__ f_pool, T *__restrict__ u_pool,
                                                    int64_t Bc, int G, int mu1, int mu2,
                                                    const int32_t *__restrict__ active)
 {
     constexpr int TOT = LdsHier<GS>::TOTAL;
-    __shared__ T a_s[TOT], u_s[TOT], f_s[TOT];
+    __shared__ T a_s[TOT], u_s[TOT], f_s[TOT], chol_s[10];
     const int64_t b = blockIdx.x;
     if (b >= Bc) return;
     if (active && !active[b]) return;
@@ -631,36 +683,23 @@ __global__ __launch_bounds__(LT) void k_lds_vcycle(const T *__restrict__ a_pool,
         u_s[LdsHier<GS>::off(G) + p] = T(0);
     }
     __syncthreads();
-    LdsVcycle<GS, T> V{a_s, u_s, f_s, mu1, mu2};
+    lds_chol4<T>(a_s, chol_s);
+    __syncthreads();
+    LdsVcycle<GS, T, LT> V{a_s, u_s, f_s, chol_s, mu1, mu2};
     V.run(G, f_s + LdsHier<GS>::off(G));
     T *dst = u_pool + Bc * level_offset(G) + b * (int64_t)cntG;
     for (int p = threadIdx.x; p < cntG; p += LT) dst[p] = u_s[LdsHier<GS>::off(G) + p];
 }
 
-// Two compensated partial sums reduced together (fixed pairwise tree).
-__device__ void lds_reduce2(double s0, double c0, double s1, double c1, double *scratch,
-                            double &v0, double &v1)
+// Two compensated partial sums reduced together.
+template <int LT>
+__device__ __forceinline__ void lds_reduce2(double s0, double c0, double s1, double c1,
+                                            double *scratch, double &v0, double &v1)
 {
-    scratch[4 * threadIdx.x] = s0;
-    scratch[4 * threadIdx.x + 1] = c0;
-    scratch[4 * threadIdx.x + 2] = s1;
-    scratch[4 * threadIdx.x + 3] = c1;
-    __syncthreads();
-    for (int w = LT / 2; w >= 1; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-#pragma unroll
-            for (int v = 0; v < 2; ++v) {
-                double *x = scratch + 4 * threadIdx.x + 2 * v, *y = scratch + 4 * (threadIdx.x + w) + 2 * v;
-                const double s1_ = x[0], s2_ = y[0], t = s1_ + s2_, bb = t - s1_;
-                x[1] = x[1] + y[1] + ((s1_ - (t - bb)) + (s2_ - bb));
-                x[0] = t;
-            }
-        }
-        __syncthreads();
-    }
-    v0 = scratch[0] + scratch[1];
-    v1 = scratch[2] + scratch[3];
-    __syncthreads();
+    double s[2] = {s0, s1}, c[2] = {c0, c1}, v[2];
+    lds_reduce_n<LT, 2>(s, c, scratch, v);
+    v0 = v[0];
+    v1 = v[1];
 }
 
 // (A u)_P in FP64 at cell (i, j) of the n x n grid, coefficients TA promoted
@@ -679,7 +718,7 @@ __device__ __forceinline__ double lds_apply(const TA *a, const double *u, int n,
 // QoI of stages g >= g0 from x; x of level G to u64_pool; per sample the
 // largest step count, the largest final relative residual and whether a stage
 // stopped at max_iters.
-template <int GS, typename T>
+template <int GS, typename T, int LT>
 __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
     const T *__restrict__ a_pool, const double *__restrict__ a64_pool,
     double *__restrict__ u64_pool, int64_t Bc, int G, int mu1, int mu2, double rtol, int max_iters,
@@ -689,11 +728,13 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
     constexpr int TOT = LdsHier<GS>::TOTAL;
     constexpr int TOP = 4 << (2 * GS);   // cells of the finest LDS level
     constexpr bool F64 = sizeof(T) == sizeof(double);
-    __shared__ T a_s[TOT], u_s[TOT], f_s[TOT];
+    constexpr int RPT = (TOP + LT - 1) / LT;   // top-level cells per thread
+    __shared__ T a_s[TOT], u_s[TOT], f_s[TOT], chol_s[10];
     __shared__ double a64_s[F64 ? 1 : TOT];   // FP64 coefficients of the CG operator
     __shared__ double w_s[TOT];          // FP64 stage solutions x
-    __shared__ double r_s[TOP], ro_s[TOP], p_s[TOP];
-    __shared__ double red_s[4 * LT];
+    __shared__ double p_s[TOP];          // search direction
+    __shared__ double red_s[4 * (LT / 64)], chol64_s[10];
+    double r_v[RPT], ro_v[RPT];          // r and r_old of this thread's cells p = tid + LT q
     const int64_t b = blockIdx.x;
     if (b >= Bc) return;
     for (int g = 0; g <= G; ++g) {
@@ -706,7 +747,10 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
     }
     __syncthreads();
     const double *a64 = F64 ? (const double *)a_s : a64_s;
-    LdsVcycle<GS, T> V{a_s, u_s, f_s, mu1, mu2};
+    lds_chol4<T>(a_s, chol_s);
+    lds_chol4<double>(a64, chol64_s);
+    __syncthreads();
+    LdsVcycle<GS, T, LT> V{a_s, u_s, f_s, chol_s, mu1, mu2};
     int it_max = 0, bad = 0;
     double rho_max = 0.0;
     for (int g = 0; g <= G; ++g) {
@@ -714,33 +758,41 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
         double *xg = w_s + LdsHier<GS>::off(g);
         T *zg = u_s + LdsHier<GS>::off(g), *fg = f_s + LdsHier<GS>::off(g);
         const double *ag = a64 + LdsHier<GS>::off(g);
-        if (g == 0) lds_coarse_solve<double>(a64, (const double *)nullptr, xg);
-        else lds_prolong(w_s + LdsHier<GS>::off(g - 1), xg, n, false);
+        if (g == 0) lds_coarse_solve<double>(chol64_s, (const double *)nullptr, xg);
+        else lds_prolong<LT>(w_s + LdsHier<GS>::off(g - 1), xg, n, false);
         int it = 0;
         double rho, rz_old = 1.0;
         for (;;) {
             // r = 1 - A x, staged as the T right-hand side of the preconditioner
             double s = 0.0, c = 0.0;
-            for (int p = threadIdx.x; p < cells; p += LT) {
-                const int j = p / n, i = p - j * n;
-                const double r = 1.0 - lds_apply(ag, xg, n, i, j);
-                r_s[p] = r;
-                fg[p] = T(r);
-                zg[p] = T(0);
-                neumaier(s, c, r * r);
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int p = threadIdx.x + LT * q;
+                if (p < cells) {
+                    const int j = p / n, i = p - j * n;
+                    const double r = 1.0 - lds_apply(ag, xg, n, i, j);
+                    r_v[q] = r;
+                    fg[p] = T(r);
+                    zg[p] = T(0);
+                    neumaier(s, c, r * r);
+                }
             }
-            rho = sqrt(lds_reduce(s, c, red_s)) / (double)n;   // ||1||_2 = n
+            rho = sqrt(lds_reduce<LT>(s, c, red_s)) / (double)n;   // ||1||_2 = n
             if (rho <= rtol || it >= max_iters || g == 0) break;
             V.run(g, fg);                                       // z = B r
             double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0;
-            for (int p = threadIdx.x; p < cells; p += LT) {
-                const double z = double(zg[p]);
-                neumaier(s0, c0, r_s[p] * z);
-                neumaier(s1, c1, it == 0 ? 0.0 : ro_s[p] * z);
-                ro_s[p] = r_s[p];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int p = threadIdx.x + LT * q;
+                if (p < cells) {
+                    const double z = double(zg[p]);
+                    neumaier(s0, c0, r_v[q] * z);
+                    neumaier(s1, c1, it == 0 ? 0.0 : ro_v[q] * z);
+                    ro_v[q] = r_v[q];
+                }
             }
             double rz, rzo;
-            lds_reduce2(s0, c0, s1, c1, red_s, rz, rzo);
+            lds_reduce2<LT>(s0, c0, s1, c1, red_s, rz, rzo);
             const double beta = it == 0 ? 0.0 : (rz - rzo) / rz_old;
             for (int p = threadIdx.x; p < cells; p += LT)
                 p_s[p] = it == 0 ? double(zg[p]) : double(zg[p]) + beta * p_s[p];
@@ -751,7 +803,7 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
                 const int j = p / n, i = p - j * n;
                 neumaier(s, c, p_s[p] * lds_apply(ag, p_s, n, i, j));
             }
-            const double alpha = rz / lds_reduce(s, c, red_s);
+            const double alpha = rz / lds_reduce<LT>(s, c, red_s);
             for (int p = threadIdx.x; p < cells; p += LT) xg[p] += alpha * p_s[p];
             __syncthreads();
             rz_old = rz;
@@ -760,7 +812,7 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
         if (g > 0 && rho > rtol) bad = 1;
         it_max = it > it_max ? it : it_max;
         rho_max = rho > rho_max ? rho : rho_max;
-        if (g >= g0) lds_write_qoi(xg, n, qoi, b, nlev, g - g0, mask, red_s);
+        if (g >= g0) lds_write_qoi<LT>(xg, n, qoi, b, nlev, g - g0, mask, red_s);
     }
     const int cntG = 4 << (2 * G);
     double *dst = u64_pool + Bc * level_offset(G) + b * (int64_t)cntG;
@@ -807,13 +859,6 @@ __device__ __forceinline__ double apply_cell(const TA *__restrict__ a, const dou
     v += (j + 1 < n) ? hm(ap, double(a[p + n])) * (up - u[p + n]) : 2.0 * ap * up;
     v += (j > 0) ? hm(ap, double(a[p - n])) * (up - u[p - n]) : 2.0 * ap * up;
     return double(n) * double(n) * v;
-}
-
-__device__ __forceinline__ void two_sum_fold(double &s, double &c, double s2, double c2)
-{
-    const double t = s + s2, bb = t - s;
-    c = c + c2 + ((s - (t - bb)) + (s2 - bb));
-    s = t;
 }
 
 // block (256 threads) compensated sums of NV values -> out[2 NV] (sum, comp)
@@ -1071,19 +1116,36 @@ void launch_post_tile(hipStream_t st, int mu2, const T *a, const T *f, T *u, con
                            n, Bc, active);
 }
 
+// Workgroups sized to the top LDS grid: LDS for exactly levels 0..G, one
+// wavefront for grids <= 8^2, 128 threads for 16^2, 256 for 32^2.
+#define MLMC_LDS_DISPATCH(G, LAUNCH)                                                               \
+    switch (G) {                                                                                   \
+    case 0:                                                                                        \
+    case 1: LAUNCH(1, 64); break;                                                                  \
+    case 2: LAUNCH(2, 64); break;                                                                  \
+    case 3: LAUNCH(3, 128); break;                                                                 \
+    default: LAUNCH(4, 256); break;                                                                \
+    }
+
 void launch_lds_fmg_fixed(hipStream_t st, const double *a_pool, double *u_pool, int64_t Bc, int G,
                           int mu0, int mu1, int mu2, int g0, double *qoi, int nlev, uint32_t mask)
 {
-    hipLaunchKernelGGL(k_lds_fmg_fixed<kLdsMaxLevel>, dim3(nblocks(Bc)), dim3(LT), 0, st, a_pool,
-                       u_pool, Bc, G, mu0, mu1, mu2, g0, qoi, nlev, mask);
+#define L(GS, NTH)                                                                                 \
+    hipLaunchKernelGGL((k_lds_fmg_fixed<GS, NTH>), dim3(nblocks(Bc)), dim3(NTH), 0, st, a_pool,   \
+                       u_pool, Bc, G, mu0, mu1, mu2, g0, qoi, nlev, mask)
+    MLMC_LDS_DISPATCH(G, L)
+#undef L
 }
 
 template <typename T>
 void launch_lds_vcycle(hipStream_t st, const T *a_pool, const T *f_pool, T *u_pool, int64_t Bc,
                        int G, int mu1, int mu2, const int32_t *active)
 {
-    hipLaunchKernelGGL((k_lds_vcycle<kLdsMaxLevel, T>), dim3(nblocks(Bc)), dim3(LT), 0, st, a_pool,
-                       f_pool, u_pool, Bc, G, mu1, mu2, active);
+#define L(GS, NTH)                                                                                 \
+    hipLaunchKernelGGL((k_lds_vcycle<GS, T, NTH>), dim3(nblocks(Bc)), dim3(NTH), 0, st, a_pool,   \
+                       f_pool, u_pool, Bc, G, mu1, mu2, active)
+    MLMC_LDS_DISPATCH(G, L)
+#undef L
 }
 
 template <typename T>
@@ -1092,10 +1154,14 @@ void launch_lds_fmg_refine(hipStream_t st, const T *a_pool, const double *a64_po
                            int max_iters, int g0, double *qoi, int nlev, uint32_t mask,
                            int32_t *st_iters, double *st_rho, int32_t *st_bad)
 {
-    hipLaunchKernelGGL((k_lds_fmg_refine<kLdsMaxLevel, T>), dim3(nblocks(Bc)), dim3(LT), 0, st,
-                       a_pool, a64_pool, u64_pool, Bc, G, mu1, mu2, rtol, max_iters, g0, qoi, nlev,
-                       mask, st_iters, st_rho, st_bad);
+#define L(GS, NTH)                                                                                 \
+    hipLaunchKernelGGL((k_lds_fmg_refine<GS, T, NTH>), dim3(nblocks(Bc)), dim3(NTH), 0, st,       \
+                       a_pool, a64_pool, u64_pool, Bc, G, mu1, mu2, rtol, max_iters, g0, qoi,     \
+                       nlev, mask, st_iters, st_rho, st_bad)
+    MLMC_LDS_DISPATCH(G, L)
+#undef L
 }
+#undef MLMC_LDS_DISPATCH
 
 int64_t fcg_partials(int n, int64_t Bc) { return Bc * (((int64_t)n * n + FCH - 1) / FCH) * 4; }
 
