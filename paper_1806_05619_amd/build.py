@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmlmc.so")
-SOURCES = ["host.hip", "kernels.hip", "kernels_fused.hip", "kernels_stream.hip", "kernels_mixed.hip"]
+SOURCES = ["host.hip", "kernels.hip", "kernels_fused.hip", "kernels_stream.hip", "kernels_mixed.hip",
+           "kernels_field.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

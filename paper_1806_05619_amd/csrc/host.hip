@@ -41,7 +41,8 @@ struct mlmc_ctx_s {
     int64_t Mmax = 0;
     int64_t pool = 0;            // doubles per pool
     double *d_a = nullptr, *d_u = nullptr, *d_f = nullptr;
-    double *d_fcg = nullptr;     // rtol on grids >= 64^2: r, r_old, p of a chunk's top level
+    double *d_fcg = nullptr;     // rtol on grids >= 64^2: second iterate buffer (FP64), r_old
+                                 // and two search directions (V-cycle type) of a chunk's top level
     int64_t fcg_cells = 0;       // cells per vector (samples x top-level cells)
     double *d_part = nullptr;    // per-block partial sums of those passes
     double *d_fs = nullptr;      // per-sample CG scalars (4 doubles)
@@ -552,13 +553,27 @@ mlmc_status run_fmg_refine(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k,
             launch_prolong(st, h.w[g - 1], h.w[g], n, Bc, 0, nullptr);
         }
         // flexible CG on level g from x = P x_prev, preconditioner z = V(0; r)
-        const int64_t cells = (int64_t)n * n;
-        double *r = c->d_fcg, *ro = r + Bc * cells, *pv = ro + Bc * cells;
+        const int64_t cells = Bc * (int64_t)n * n;
+        FcgBufs<T> v;
+        v.a = h.a[g];
+        v.a64 = h.a64[g];
+        v.z = h.u[g];
+        v.f = h.f[g];
+        v.x0 = h.w[g];
+        v.x1 = c->d_fcg;
+        v.fo = (T *)(c->d_fcg + cells);
+        v.p0 = v.fo + cells;
+        v.p1 = v.p0 + cells;
+        v.part = c->d_part;
+        v.fs = c->d_fs;
+        v.rho = c->d_rho;
+        v.active = c->d_active;
+        v.iters = c->d_iters;
         const double vec = R.cells(n);   // cells of all samples of the chunk
         {
-            // a (FP64), x read; r, f written
-            ProfScope ps(c, st, MLMC_KERNEL_REFINE, vec * (8.0 + 8.0 + 8.0 + R.W), 0.0);
-            launch_fcg_resid<T>(st, h.a64[g], h.w[g], n, Bc, r, h.f[g], c->d_part, nullptr);
+            // a (FP64), x read; f written
+            ProfScope ps(c, st, MLMC_KERNEL_REFINE, vec * (16.0 + R.W), 0.0);
+            launch_fcg_resid<T>(st, h.a64[g], h.w[g], n, Bc, h.f[g], c->d_part);
         }
         launch_fcg_fin_rho(st, c->d_part, n, Bc, c->d_rho, c->d_active, c->d_iters, c->cfg.rtol,
                            c->cfg.max_iters, 1);
@@ -571,19 +586,13 @@ mlmc_status run_fmg_refine(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k,
             if (nact == 0) break;
             R.vcycle(g, h.u[g], 1, h.f[g], c->d_active);
             {
-                // dots (z, r, r_old; r_old written), p update, (p, A p), x update
-                ProfScope ps(c, st, MLMC_KERNEL_REFINE,
-                             vec * ((R.W + 24.0) + (R.W + 16.0) + 16.0 + 24.0), 0.0);
-                launch_fcg_step<T>(st, h.a64[g], h.u[g], h.w[g], r, ro, pv, n, Bc, c->d_part,
-                                   c->d_fs, c->d_active, c->d_iters);
+                // dots: z, r, r_old read, r_old written; p: a, z, p_prev read, p
+                // written; x: a (FP64), x_prev, p read, x and r written
+                ProfScope ps(c, st, MLMC_KERNEL_REFINE, vec * (24.0 + 10.0 * R.W), 0.0);
+                launch_fcg_step<T>(st, v, n, Bc, c->cfg.rtol, c->cfg.max_iters);
             }
-            {
-                ProfScope ps(c, st, MLMC_KERNEL_REFINE, vec * (8.0 + 8.0 + 8.0 + R.W), 0.0);
-                launch_fcg_resid<T>(st, h.a64[g], h.w[g], n, Bc, r, h.f[g], c->d_part, c->d_active);
-            }
-            launch_fcg_fin_rho(st, c->d_part, n, Bc, c->d_rho, c->d_active, c->d_iters,
-                               c->cfg.rtol, c->cfg.max_iters, 0);
         }
+        launch_fcg_copyback(st, h.w[g], v.x1, n, Bc, c->d_iters);
         launch_refine_stats(st, c->d_iters, c->d_rho, Bc, c->cfg.rtol, c->d_st_iters, c->d_st_rho,
                             c->d_st_bad);
         if (g >= c->g0) {
@@ -766,7 +775,7 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     const int64_t a64 = mixed ? ctx->pool : 0;
     size_t need = (size_t)ctx->elem * 3 * (size_t)ctx->pool +
                   (8 * (size_t)ctx->sp + 4) * (size_t)(brows + yrows) + 8 * (size_t)a64 +
-                  sizeof(double) * ((size_t)s * ctx->Mmax + 3 * ctx->fcg_cells + parts + wcap +
+                  sizeof(double) * ((size_t)s * ctx->Mmax + 4 * ctx->fcg_cells + parts + wcap +
                                     (size_t)ctx->chunk_max * (s + c.num_levels * ctx->nq + 2) +
                                     4 * ctx->state_tuples) +
                   sizeof(int32_t) * 4 * ctx->chunk_max;
@@ -795,7 +804,7 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     CHK(dev_alloc(ctx, &ctx->d_bexp, brows));
     CHK(dev_alloc(ctx, &ctx->d_yexp, yrows));
     CHK(dev_alloc(ctx, &ctx->d_a64, a64));
-    CHK(dev_alloc(ctx, &ctx->d_fcg, 3 * ctx->fcg_cells));
+    CHK(dev_alloc(ctx, &ctx->d_fcg, 4 * ctx->fcg_cells));
     CHK(dev_alloc(ctx, &ctx->d_part, parts));
     CHK(dev_alloc(ctx, &ctx->d_fs, ctx->fcg_cells > 0 ? 4 * ctx->chunk_max : 0));
     CHK(dev_alloc(ctx, &ctx->d_w, wcap));

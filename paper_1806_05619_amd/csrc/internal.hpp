@@ -37,9 +37,9 @@ void launch_points(hipStream_t st, const uint32_t *z, const uint64_t *shifts, in
 void launch_build_basis(hipStream_t st, const double *psi, const int64_t *psi_off,
                         const int32_t *mi, const int32_t *mj, const double *coef, int s,
                         int G, double *basis, int64_t ld);
-// z = Y basis (first M columns); mode 0 writes z to out[b*M + m];
-// mode 1 writes exp(z) into the level-major chunk pool `out` (Bc samples);
-// mode 2 the same as float.
+// z = Y basis (first M columns) in FP64 on the matrix cores; mode 0 writes z
+// to out[b*M + m]; mode 1 writes exp(z) into the level-major FP64 chunk pool
+// `out` (Bc samples).
 void launch_field_gemm(hipStream_t st, const double *Y, int s, const double *basis, int64_t ld,
                        int64_t M, int64_t Bc, void *out, int mode);
 // a = exp(z) into the level-major pool; to_float: as float, with a double copy
@@ -108,22 +108,37 @@ void launch_lds_fmg_refine(hipStream_t st, const T *a_pool, const double *a64_po
                            double *u64_pool, int64_t Bc, int G, int mu1, int mu2, double rtol,
                            int max_iters, int g0, double *qoi, int nlev, uint32_t mask,
                            int32_t *st_iters, double *st_rho, int32_t *st_bad);
-// flexible CG of one stage on a large grid (Bc samples of n x n, FP64 vectors
-// x, r, r_old, p and FP64 coefficients a; z from the T V-cycle).  Partial-sum scratch: fcg_partials
-// doubles; fs: 4 doubles per sample.
+// flexible CG of one stage on a large grid (Bc samples of n x n).  Iterate x
+// in FP64 in two buffers (x0 = the stage solution pool), residual only as
+// f = T(r), r_old and the search direction (two buffers) in T; FP64
+// coefficients for the residual, T coefficients for (p, A p).
+// Partial-sum scratch: fcg_partials doubles; fs: 4 doubles per sample.
 int64_t fcg_partials(int n, int64_t Bc);
-// r = 1 - A x, f = T(r), partial ||r||^2 (active nullptr: every sample)
 template <typename T>
-void launch_fcg_resid(hipStream_t st, const double *a, const double *x, int n, int64_t Bc, double *r,
-                      T *f, double *part, const int32_t *active);
+struct FcgBufs {
+    const T *a;             // V-cycle coefficients (level n)
+    const double *a64;      // FP64 coefficients (level n)
+    const T *z;             // preconditioner output
+    T *f, *fo;              // r and r_old
+    T *p0, *p1;             // search directions
+    double *x0, *x1;        // iterates
+    double *part, *fs, *rho;
+    int32_t *active, *iters;
+};
+// r = 1 - A x0 (every sample), f = T(r), partial ||r||^2
+template <typename T>
+void launch_fcg_resid(hipStream_t st, const double *a, const double *x, int n, int64_t Bc, T *f,
+                      double *part);
 // rho = ||r||/||1||; active = rho > rtol && iters < max_iters; iters counts steps
 void launch_fcg_fin_rho(hipStream_t st, const double *part, int n, int64_t Bc, double *rho,
                         int32_t *active, int32_t *iters, double rtol, int max_iters, int first);
-// one step after z = B r: beta, p = z + beta p, alpha = (r, z)/(p, A p), x += alpha p
+// one step after z = B r: beta, p, alpha, x, new residual, convergence flags
 template <typename T>
-void launch_fcg_step(hipStream_t st, const double *a, const T *z, double *x, double *r, double *ro,
-                     double *pv, int n, int64_t Bc, double *part, double *fs,
-                     const int32_t *active, const int32_t *iters);
+void launch_fcg_step(hipStream_t st, const FcgBufs<T> &v, int n, int64_t Bc, double rtol,
+                     int max_iters);
+// after the last step: x1 -> x0 for samples whose step count is odd
+void launch_fcg_copyback(hipStream_t st, double *x0, const double *x1, int n, int64_t Bc,
+                         const int32_t *iters);
 void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho, int64_t Bc,
                          double rtol, int32_t *st_iters, double *st_rho, int32_t *st_bad);
 

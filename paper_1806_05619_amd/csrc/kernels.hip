@@ -123,10 +123,7 @@ __global__ void k_build_basis(const double *__restrict__ psi, const int64_t *__r
 }
 
 // ---------------------------------------------------------------------------
-// Section 5: z = Y basis as a tiled FP64 product.  Tile 64 samples x 64 columns,
-// K step 16, 256 threads each owning a 4x4 strided sub-tile (coalesced stores).
-constexpr int GM = 64, GN = 64, GK = 16;
-
+// Section 5: the level-major position of field column m of sample b.
 __device__ __forceinline__ int64_t level_major_index(int64_t m, int64_t b, int64_t Bc)
 {
     int g = 0;
@@ -134,65 +131,6 @@ __device__ __forceinline__ int64_t level_major_index(int64_t m, int64_t b, int64
         ++g;
     int64_t lo = level_offset(g);
     return Bc * lo + b * level_cells(g) + (m - lo);
-}
-
-__global__ __launch_bounds__(256) void k_field_gemm(const double *__restrict__ Y, int s,
-                                                    const double *__restrict__ basis, int64_t ld,
-                                                    int64_t M, int64_t Bc,
-                                                    void *__restrict__ out, int mode)
-{
-    __shared__ double As[GK][GM + 1];
-    __shared__ double Bs[GK][GN];
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    const int64_t row0 = (int64_t)blockIdx.y * GM;
-    const int64_t col0 = (int64_t)blockIdx.x * GN;
-    double acc[4][4] = {};
-    for (int k0 = 0; k0 < s; k0 += GK) {
-        for (int e = threadIdx.x; e < GM * GK; e += 256) {
-            int r = e / GK, kk = e % GK;
-            int64_t gr = row0 + r;
-            int gk = k0 + kk;
-            As[kk][r] = (gr < Bc && gk < s) ? Y[gr * s + gk] : 0.0;
-        }
-        for (int e = threadIdx.x; e < GK * GN; e += 256) {
-            int kk = e / GN, c = e % GN;
-            int64_t gc = col0 + c;
-            int gk = k0 + kk;
-            Bs[kk][c] = (gc < M && gk < s) ? basis[(int64_t)gk * ld + gc] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < GK; ++kk) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = As[kk][ty + 16 * i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx + 16 * j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        int64_t b = row0 + ty + 16 * i;
-        if (b >= Bc)
-            continue;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            int64_t m = col0 + tx + 16 * j;
-            if (m >= M)
-                continue;
-            if (mode == 0)
-                ((double *)out)[b * M + m] = acc[i][j];
-            else if (mode == 1)
-                ((double *)out)[level_major_index(m, b, Bc)] = exp(acc[i][j]);
-            else
-                ((float *)out)[level_major_index(m, b, Bc)] = (float)exp(acc[i][j]);
-        }
-    }
 }
 
 __global__ void k_exp_to_levels(const double *__restrict__ z, int64_t M, int64_t Bc,
@@ -479,12 +417,6 @@ void launch_build_basis(hipStream_t st, const double *psi, const int64_t *psi_of
                        mi, mj, coef, s, G, M, basis, ld);
 }
 
-void launch_field_gemm(hipStream_t st, const double *Y, int s, const double *basis, int64_t ld,
-                       int64_t M, int64_t Bc, void *out, int mode)
-{
-    dim3 grid((unsigned)((M + GN - 1) / GN), (unsigned)((Bc + GM - 1) / GM));
-    hipLaunchKernelGGL(k_field_gemm, grid, dim3(256), 0, st, Y, s, basis, ld, M, Bc, out, mode);
-}
 
 void launch_exp_to_levels(hipStream_t st, const double *z, int64_t M, int64_t Bc, void *pool,
                           bool to_float, double *pool64)

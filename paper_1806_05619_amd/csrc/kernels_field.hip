@@ -1,0 +1,109 @@
+// KL field of the FP64 path on the gfx950 matrix cores (Section 5, eq.
+// truncatedKL): z = Y basis with v_mfma_f64_16x16x4f64, a = exp(z) in the
+// epilogue.
+//
+// Block tile 64 samples x 128 field columns, 4 wavefronts of 32 x 64 (2 x 4
+// MFMA tiles, 32 FP64 accumulators per lane), K staged through LDS 16 modes at
+// a time.  MFMA lane layout (16x16x4 f64, checked on the device): A row l%16 and
+// B column l%16 take mode l/16; lane l holds D rows l/16 + 4 i (i = 0..3) of
+// column l%16.
+#include "internal.hpp"
+
+namespace mlmc {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int FBM = 64, FBN = 128, FKB = 16;
+
+__device__ __forceinline__ int64_t level_major_index_f(int64_t m, int64_t b, int64_t Bc)
+{
+    int g = 0;
+    while (g < kMaxMgLevels - 1 && level_offset(g + 1) <= m) ++g;
+    const int64_t lo = level_offset(g);
+    return Bc * lo + b * level_cells(g) + (m - lo);
+}
+
+// mode 0: z to out[b*M + m]; mode 1: exp(z) into the level-major FP64 pool
+__global__ __launch_bounds__(256) void k_field_mfma64(const double *__restrict__ Y, int s,
+                                                      const double *__restrict__ basis, int64_t ld,
+                                                      int64_t M, int64_t Bc,
+                                                      double *__restrict__ out, int mode)
+{
+    __shared__ double As[FKB][FBM];      // Y tile, mode-major
+    __shared__ double Bs[FKB][FBN];      // basis tile
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t row0 = (int64_t)blockIdx.y * FBM, col0 = (int64_t)blockIdx.x * FBN;
+    const int wr = wave >> 1, wc = wave & 1;
+    d4 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = 0; k0 < s; k0 += FKB) {
+        // Y: thread t reads 4 consecutive modes of sample row0 + t/4
+        {
+            const int r = t >> 2, kk = (t & 3) * 4;
+            const int64_t gr = row0 + r;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gk = k0 + kk + q;
+                As[kk + q][r] = (gr < Bc && gk < s) ? Y[gr * s + gk] : 0.0;
+            }
+        }
+        // basis: thread t reads 8 consecutive columns of mode k0 + t/16
+        {
+            const int kk = t >> 4, c = (t & 15) * 8;
+            const int gk = k0 + kk;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t gc = col0 + c + q;
+                Bs[kk][c + q] = (gk < s && gc < M) ? basis[(int64_t)gk * ld + gc] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < FKB / 4; ++ks) {
+            const int kr = 4 * ks + (lane >> 4);
+            double a[2], b[4];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = As[kr][32 * wr + 16 * i + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kr][64 * wc + 16 * j + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] =
+                        __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t m = col0 + 64 * wc + 16 * j + (lane & 15);
+        if (m >= M) continue;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t b = row0 + 32 * wr + 16 * i + (lane >> 4) + 4 * e;
+                if (b >= Bc) continue;
+                if (mode == 0) out[b * M + m] = acc[i][j][e];
+                else out[level_major_index_f(m, b, Bc)] = exp(acc[i][j][e]);
+            }
+    }
+}
+
+}  // namespace
+
+void launch_field_gemm(hipStream_t st, const double *Y, int s, const double *basis, int64_t ld,
+                       int64_t M, int64_t Bc, void *out, int mode)
+{
+    dim3 grid((unsigned)((M + FBN - 1) / FBN), (unsigned)((Bc + FBM - 1) / FBM));
+    hipLaunchKernelGGL(k_field_mfma64, grid, dim3(256), 0, st, Y, s, basis, ld, M, Bc,
+                       (double *)out, mode);
+}
+
+}  // namespace mlmc

@@ -91,7 +91,8 @@ struct CoarseStage {
         const int I = (gi >> 1) - cI0, J = (gj >> 1) - cJ0;
         const int sx = (gi & 1) ? 1 : -1, sy = (gj & 1) ? CS : -CS;
         const int q = I + CS * J;
-        return (T(9) * cs[q] + T(3) * cs[q + sx] + T(3) * cs[q + sy] + cs[q + sx + sy]) / T(16);
+        // times 1/16 (exact: a power of two)
+        return (T(9) * cs[q] + T(3) * cs[q + sx] + T(3) * cs[q + sy] + cs[q + sx + sy]) * T(0.0625);
     }
 };
 
@@ -392,7 +393,7 @@ __device__ void lds_sweep(const T *a, const T *f, T *u, int n, int colour)
     const int half = n / 2;
     const T h2 = T(1) / (T(n) * T(n));
     for (int q = threadIdx.x; q < n * half; q += LT) {
-        const int j = q / half;
+        const int j = q >> (__builtin_ctz(n) - 1);          // n / 2 cells per row
         const int i = 2 * (q - j * half) + ((j + colour) & 1);
         T wE, wW, wN, wS, d;
         lds_stencil<T>(a, n, i, j, wE, wW, wN, wS, d);
@@ -484,10 +485,10 @@ __device__ void lds_prolong(const T *e, T *u, int n, bool add)
 {
     const int nc = n / 2;
     for (int p = threadIdx.x; p < n * n; p += LT) {
-        const int j = p / n, i = p - j * n;
+        const int j = p >> __builtin_ctz(n), i = p & (n - 1);   // n is a power of two
         const int I = i >> 1, J = j >> 1, sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1;
         const T v = (T(9) * codd(e, nc, I, J) + T(3) * codd(e, nc, I + sx, J) +
-                     T(3) * codd(e, nc, I, J + sy) + codd(e, nc, I + sx, J + sy)) / T(16);
+                     T(3) * codd(e, nc, I, J + sy) + codd(e, nc, I + sx, J + sy)) * T(0.0625);
         u[p] = add ? u[p] + v : v;
     }
     __syncthreads();
@@ -513,7 +514,7 @@ struct LdsVcycle {
             }
             T *fcl = f + LdsHier<GS>::off(l - 1), *ucl = u + LdsHier<GS>::off(l - 1);
             for (int q = threadIdx.x; q < nc * nc; q += LT) {
-                const int J = q / nc, I = q - J * nc;
+                const int J = q >> __builtin_ctz(nc), I = q & (nc - 1);
                 const T r00 = lds_resid<T>(al, fl, ul, n, 2 * I, 2 * J);
                 const T r10 = lds_resid<T>(al, fl, ul, n, 2 * I + 1, 2 * J);
                 const T r01 = lds_resid<T>(al, fl, ul, n, 2 * I, 2 * J + 1);
@@ -769,7 +770,7 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
             for (int q = 0; q < RPT; ++q) {
                 const int p = threadIdx.x + LT * q;
                 if (p < cells) {
-                    const int j = p / n, i = p - j * n;
+                    const int j = p >> __builtin_ctz(n), i = p & (n - 1);
                     const double r = 1.0 - lds_apply(ag, xg, n, i, j);
                     r_v[q] = r;
                     fg[p] = T(r);
@@ -800,7 +801,7 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
             s = 0.0;
             c = 0.0;
             for (int p = threadIdx.x; p < cells; p += LT) {
-                const int j = p / n, i = p - j * n;
+                const int j = p >> __builtin_ctz(n), i = p & (n - 1);
                 neumaier(s, c, p_s[p] * lds_apply(ag, p_s, n, i, j));
             }
             const double alpha = rz / lds_reduce<LT>(s, c, red_s);
@@ -905,25 +906,29 @@ __device__ __forceinline__ double fold_partials(const double *__restrict__ part,
     return s + c;
 }
 
-// r = 1 - A x; f = TF(r); partial ||r||^2
+// Step k >= 1 of a stage (iters[b] = k while it runs).  The residual lives only
+// as f = T(r) (the preconditioner's right-hand side), r_old as T, the search
+// direction p as T in two buffers (p_k written from p_{k-1}), the iterate x in
+// FP64 in two buffers (x_k in X[k & 1], X[0] being the stage solution pool).
+// Inner products and step lengths see T-rounded r and p; the residual that
+// decides convergence is recomputed from x in FP64 with the FP64 coefficients.
+
+// r = 1 - A x (FP64, from X[0]); f = TF(r); partial ||r||^2
 template <typename TF>
 __global__ __launch_bounds__(256) void k_fcg_resid(const double *__restrict__ a,
                                                    const double *__restrict__ x, int n, int64_t Bc,
-                                                   double *__restrict__ r, TF *__restrict__ f,
-                                                   double *__restrict__ part,
-                                                   const int32_t *__restrict__ active)
+                                                   TF *__restrict__ f, double *__restrict__ part)
 {
     FcgMap m;
-    if (!fcg_map(n, Bc, active, m)) return;
+    if (!fcg_map(n, Bc, nullptr, m)) return;
     const int64_t cells = (int64_t)n * n, base = m.b * cells;
     double s[1] = {0.0}, c[1] = {0.0};
 #pragma unroll
     for (int q = 0; q < FCH / 256; ++q) {
         const int64_t p = m.c0 + threadIdx.x + 256 * q;
         if (p < cells) {
-            const int j = (int)(p / n), i = (int)(p - (int64_t)j * n);
+            const int j = (int)p >> __builtin_ctz(n), i = (int)p & (n - 1);
             const double v = 1.0 - apply_cell(a + base, x + base, n, i, j, p);
-            r[base + p] = v;
             f[base + p] = TF(v);
             neumaier(s[0], c[0], v * v);
         }
@@ -933,7 +938,7 @@ __global__ __launch_bounds__(256) void k_fcg_resid(const double *__restrict__ a,
 
 // rho_b = ||r|| / ||1||.  first: every sample starts with iters = 0.  Then,
 // for the samples still iterating: active = rho > rtol && iters < max_iters,
-// and iters counts the step about to be taken.
+// and iters becomes the number of the step about to be taken.
 __global__ __launch_bounds__(256) void k_fcg_fin_rho(const double *__restrict__ part, int n,
                                                      int64_t Bc, double *__restrict__ rho,
                                                      int32_t *__restrict__ active,
@@ -955,10 +960,9 @@ __global__ __launch_bounds__(256) void k_fcg_fin_rho(const double *__restrict__ 
 }
 
 // partials of (r, z) and (r_old, z) (the second 0 at the first step); r_old = r
-template <typename TZ>
-__global__ __launch_bounds__(256) void k_fcg_dots(const TZ *__restrict__ z,
-                                                  const double *__restrict__ r,
-                                                  double *__restrict__ ro, int n, int64_t Bc,
+template <typename T>
+__global__ __launch_bounds__(256) void k_fcg_dots(const T *__restrict__ z, const T *__restrict__ f,
+                                                  T *__restrict__ fo, int n, int64_t Bc,
                                                   double *__restrict__ part,
                                                   const int32_t *__restrict__ active,
                                                   const int32_t *__restrict__ iters)
@@ -972,10 +976,11 @@ __global__ __launch_bounds__(256) void k_fcg_dots(const TZ *__restrict__ z,
     for (int q = 0; q < FCH / 256; ++q) {
         const int64_t p = m.c0 + threadIdx.x + 256 * q;
         if (p < cells) {
-            const double zv = double(z[base + p]), rv = r[base + p];
-            neumaier(s[0], c[0], rv * zv);
-            neumaier(s[1], c[1], first ? 0.0 : ro[base + p] * zv);
-            ro[base + p] = rv;
+            const T rv = f[base + p];
+            const double zv = double(z[base + p]);
+            neumaier(s[0], c[0], double(rv) * zv);
+            neumaier(s[1], c[1], first ? 0.0 : double(fo[base + p]) * zv);
+            fo[base + p] = rv;
         }
     }
     block_partials<2>(s, c, part + (m.b * m.nch + m.c0 / FCH) * 4);
@@ -998,42 +1003,39 @@ __global__ __launch_bounds__(256) void k_fcg_fin_beta(const double *__restrict__
     }
 }
 
-// p = z + beta p (p = z at the first step)
-template <typename TZ>
-__global__ __launch_bounds__(256) void k_fcg_p(const TZ *__restrict__ z, double *__restrict__ pv,
-                                               int n, int64_t Bc, const double *__restrict__ fs,
+// p_k = z + beta p_{k-1} (p_1 = z), written to P[k & 1]; partial (p_k, A p_k)
+// with the neighbours' p_k formed from z and p_{k-1} on the fly
+template <typename T>
+__global__ __launch_bounds__(256) void k_fcg_p(const T *__restrict__ a, const T *__restrict__ z,
+                                               T *__restrict__ P0, T *__restrict__ P1, int n,
+                                               int64_t Bc, const double *__restrict__ fs,
+                                               double *__restrict__ part,
                                                const int32_t *__restrict__ active,
                                                const int32_t *__restrict__ iters)
 {
     FcgMap m;
     if (!fcg_map(n, Bc, active, m)) return;
     const int64_t cells = (int64_t)n * n, base = m.b * cells;
-    const bool first = iters[m.b] == 1;
-    const double beta = fs[4 * m.b + 3];
-#pragma unroll
-    for (int q = 0; q < FCH / 256; ++q) {
-        const int64_t p = m.c0 + threadIdx.x + 256 * q;
-        if (p < cells)
-            pv[base + p] = first ? double(z[base + p]) : double(z[base + p]) + beta * pv[base + p];
-    }
-}
-
-// partial (p, A p)
-__global__ __launch_bounds__(256) void k_fcg_pq(const double *__restrict__ a,
-                                                const double *__restrict__ pv, int n, int64_t Bc,
-                                                double *__restrict__ part,
-                                                const int32_t *__restrict__ active)
-{
-    FcgMap m;
-    if (!fcg_map(n, Bc, active, m)) return;
-    const int64_t cells = (int64_t)n * n, base = m.b * cells;
+    const int k = iters[m.b];
+    const double beta = k == 1 ? 0.0 : fs[4 * m.b + 3];
+    const T *ab = a + base, *zb = z + base;
+    const T *pold = ((k - 1) & 1 ? P1 : P0) + base;
+    T *pnew = (k & 1 ? P1 : P0) + base;
+    auto pk = [&](int64_t q) { return k == 1 ? double(zb[q]) : double(zb[q]) + beta * double(pold[q]); };
     double s[1] = {0.0}, c[1] = {0.0};
 #pragma unroll
-    for (int q = 0; q < FCH / 256; ++q) {
-        const int64_t p = m.c0 + threadIdx.x + 256 * q;
+    for (int qq = 0; qq < FCH / 256; ++qq) {
+        const int64_t p = m.c0 + threadIdx.x + 256 * qq;
         if (p < cells) {
-            const int j = (int)(p / n), i = (int)(p - (int64_t)j * n);
-            neumaier(s[0], c[0], pv[base + p] * apply_cell(a + base, pv + base, n, i, j, p));
+            const int j = (int)p >> __builtin_ctz(n), i = (int)p & (n - 1);
+            const double ap = double(ab[p]), pp = pk(p);
+            double v = 0.0;   // net flux of p, face by face
+            v += (i + 1 < n) ? hm(ap, double(ab[p + 1])) * (pp - pk(p + 1)) : 2.0 * ap * pp;
+            v += (i > 0) ? hm(ap, double(ab[p - 1])) * (pp - pk(p - 1)) : 2.0 * ap * pp;
+            v += (j + 1 < n) ? hm(ap, double(ab[p + n])) * (pp - pk(p + n)) : 2.0 * ap * pp;
+            v += (j > 0) ? hm(ap, double(ab[p - n])) * (pp - pk(p - n)) : 2.0 * ap * pp;
+            pnew[p] = T(pp);
+            neumaier(s[0], c[0], pp * double(n) * double(n) * v);
         }
     }
     block_partials<1>(s, c, part + (m.b * m.nch + m.c0 / FCH) * 2);
@@ -1054,19 +1056,61 @@ __global__ __launch_bounds__(256) void k_fcg_fin_alpha(const double *__restrict_
     }
 }
 
-// x += alpha p
-__global__ __launch_bounds__(256) void k_fcg_x(double *__restrict__ x, const double *__restrict__ pv,
-                                               int n, int64_t Bc, const double *__restrict__ fs,
-                                               const int32_t *__restrict__ active)
+// x_k = x_{k-1} + alpha p_k into X[k & 1]; r = 1 - A x_k in FP64 (neighbours'
+// x_k formed on the fly) -> f = T(r); partial ||r||^2
+template <typename T>
+__global__ __launch_bounds__(256) void k_fcg_x(const double *__restrict__ a64, double *__restrict__ X0,
+                                               double *__restrict__ X1, const T *__restrict__ P0,
+                                               const T *__restrict__ P1, T *__restrict__ f, int n,
+                                               int64_t Bc, const double *__restrict__ fs,
+                                               double *__restrict__ part,
+                                               const int32_t *__restrict__ active,
+                                               const int32_t *__restrict__ iters)
 {
     FcgMap m;
     if (!fcg_map(n, Bc, active, m)) return;
     const int64_t cells = (int64_t)n * n, base = m.b * cells;
+    const int k = iters[m.b];
     const double alpha = fs[4 * m.b + 2];
+    const double *ab = a64 + base;
+    const double *xold = ((k - 1) & 1 ? X1 : X0) + base;
+    double *xnew = (k & 1 ? X1 : X0) + base;
+    const T *pb = (k & 1 ? P1 : P0) + base;
+    auto xk = [&](int64_t q) { return xold[q] + alpha * double(pb[q]); };
+    double s[1] = {0.0}, c[1] = {0.0};
+#pragma unroll
+    for (int qq = 0; qq < FCH / 256; ++qq) {
+        const int64_t p = m.c0 + threadIdx.x + 256 * qq;
+        if (p < cells) {
+            const int j = (int)p >> __builtin_ctz(n), i = (int)p & (n - 1);
+            const double ap = ab[p], xp = xk(p);
+            double v = 0.0;   // net flux of x_k, face by face
+            v += (i + 1 < n) ? hm(ap, ab[p + 1]) * (xp - xk(p + 1)) : 2.0 * ap * xp;
+            v += (i > 0) ? hm(ap, ab[p - 1]) * (xp - xk(p - 1)) : 2.0 * ap * xp;
+            v += (j + 1 < n) ? hm(ap, ab[p + n]) * (xp - xk(p + n)) : 2.0 * ap * xp;
+            v += (j > 0) ? hm(ap, ab[p - n]) * (xp - xk(p - n)) : 2.0 * ap * xp;
+            const double r = 1.0 - double(n) * double(n) * v;
+            xnew[p] = xp;
+            f[base + p] = T(r);
+            neumaier(s[0], c[0], r * r);
+        }
+    }
+    block_partials<1>(s, c, part + (m.b * m.nch + m.c0 / FCH) * 2);
+}
+
+// samples whose last step wrote X[1]: copy it to the stage solution X[0]
+__global__ __launch_bounds__(256) void k_fcg_copyback(double *__restrict__ X0,
+                                                      const double *__restrict__ X1, int n,
+                                                      int64_t Bc, const int32_t *__restrict__ iters)
+{
+    FcgMap m;
+    if (!fcg_map(n, Bc, nullptr, m)) return;
+    if (!(iters[m.b] & 1)) return;
+    const int64_t cells = (int64_t)n * n, base = m.b * cells;
 #pragma unroll
     for (int q = 0; q < FCH / 256; ++q) {
         const int64_t p = m.c0 + threadIdx.x + 256 * q;
-        if (p < cells) x[base + p] += alpha * pv[base + p];
+        if (p < cells) X0[base + p] = X1[base + p];
     }
 }
 
@@ -1166,12 +1210,11 @@ void launch_lds_fmg_refine(hipStream_t st, const T *a_pool, const double *a64_po
 int64_t fcg_partials(int n, int64_t Bc) { return Bc * (((int64_t)n * n + FCH - 1) / FCH) * 4; }
 
 template <typename T>
-void launch_fcg_resid(hipStream_t st, const double *a, const double *x, int n, int64_t Bc, double *r,
-                      T *f, double *part, const int32_t *active)
+void launch_fcg_resid(hipStream_t st, const double *a, const double *x, int n, int64_t Bc, T *f,
+                      double *part)
 {
     const int64_t nb = Bc * (((int64_t)n * n + FCH - 1) / FCH);
-    hipLaunchKernelGGL((k_fcg_resid<T>), dim3(nblocks(nb)), dim3(256), 0, st, a, x, n, Bc, r, f,
-                       part, active);
+    hipLaunchKernelGGL((k_fcg_resid<T>), dim3(nblocks(nb)), dim3(256), 0, st, a, x, n, Bc, f, part);
 }
 
 void launch_fcg_fin_rho(hipStream_t st, const double *part, int n, int64_t Bc, double *rho,
@@ -1182,19 +1225,29 @@ void launch_fcg_fin_rho(hipStream_t st, const double *part, int n, int64_t Bc, d
 }
 
 template <typename T>
-void launch_fcg_step(hipStream_t st, const double *a, const T *z, double *x, double *r, double *ro,
-                     double *pv, int n, int64_t Bc, double *part, double *fs,
-                     const int32_t *active, const int32_t *iters)
+void launch_fcg_step(hipStream_t st, const FcgBufs<T> &v, int n, int64_t Bc, double rtol,
+                     int max_iters)
 {
     const unsigned nb = nblocks(Bc * (((int64_t)n * n + FCH - 1) / FCH));
     const unsigned ns = blocks_of(Bc, 4);
-    hipLaunchKernelGGL((k_fcg_dots<T>), dim3(nb), dim3(256), 0, st, z, r, ro, n, Bc, part, active,
-                       iters);
-    hipLaunchKernelGGL(k_fcg_fin_beta, dim3(ns), dim3(256), 0, st, part, n, Bc, fs, active, iters);
-    hipLaunchKernelGGL((k_fcg_p<T>), dim3(nb), dim3(256), 0, st, z, pv, n, Bc, fs, active, iters);
-    hipLaunchKernelGGL(k_fcg_pq, dim3(nb), dim3(256), 0, st, a, pv, n, Bc, part, active);
-    hipLaunchKernelGGL(k_fcg_fin_alpha, dim3(ns), dim3(256), 0, st, part, n, Bc, fs, active);
-    hipLaunchKernelGGL(k_fcg_x, dim3(nb), dim3(256), 0, st, x, pv, n, Bc, fs, active);
+    hipLaunchKernelGGL((k_fcg_dots<T>), dim3(nb), dim3(256), 0, st, v.z, v.f, v.fo, n, Bc, v.part,
+                       v.active, v.iters);
+    hipLaunchKernelGGL(k_fcg_fin_beta, dim3(ns), dim3(256), 0, st, v.part, n, Bc, v.fs, v.active,
+                       v.iters);
+    hipLaunchKernelGGL((k_fcg_p<T>), dim3(nb), dim3(256), 0, st, v.a, v.z, v.p0, v.p1, n, Bc, v.fs,
+                       v.part, v.active, v.iters);
+    hipLaunchKernelGGL(k_fcg_fin_alpha, dim3(ns), dim3(256), 0, st, v.part, n, Bc, v.fs, v.active);
+    hipLaunchKernelGGL((k_fcg_x<T>), dim3(nb), dim3(256), 0, st, v.a64, v.x0, v.x1, v.p0, v.p1, v.f,
+                       n, Bc, v.fs, v.part, v.active, v.iters);
+    hipLaunchKernelGGL(k_fcg_fin_rho, dim3(ns), dim3(256), 0, st, v.part, n, Bc, v.rho, v.active,
+                       v.iters, rtol, max_iters, 0);
+}
+
+void launch_fcg_copyback(hipStream_t st, double *x0, const double *x1, int n, int64_t Bc,
+                         const int32_t *iters)
+{
+    const int64_t nb = Bc * (((int64_t)n * n + FCH - 1) / FCH);
+    hipLaunchKernelGGL(k_fcg_copyback, dim3(nblocks(nb)), dim3(256), 0, st, x0, x1, n, Bc, iters);
 }
 
 void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho, int64_t Bc,
@@ -1215,10 +1268,8 @@ void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho
                                            int64_t, int, int, int, double, int, int, double *,     \
                                            int, uint32_t, int32_t *, double *, int32_t *);         \
     template void launch_fcg_resid<T>(hipStream_t, const double *, const double *, int, int64_t,\
-                                      double *, T *, double *, const int32_t *);                  \
-    template void launch_fcg_step<T>(hipStream_t, const double *, const T *, double *, double *,  \
-                                     double *, double *, int, int64_t, double *, double *,        \
-                                     const int32_t *, const int32_t *);
+                                      T *, double *);                                             \
+    template void launch_fcg_step<T>(hipStream_t, const FcgBufs<T> &, int, int64_t, double, int);
 MLMC_INSTANTIATE(double)
 MLMC_INSTANTIATE(float)
 #undef MLMC_INSTANTIATE
