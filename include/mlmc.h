@@ -261,11 +261,12 @@ enum {
     MLMC_KERNEL_LDS = 10,  /* LDS-resident hierarchy <= 32^2: a of all its grids
                               read, f of its top grid read (V-cycle mode), u of
                               its top grid written */
-    MLMC_KERNEL_REFINE = 11 /* rtol mode on grids >= 64^2, the flexible-CG vector
-                              passes of a stage: residual (a, x read; r, f
-                              written), dots (z, r, r_old read; r_old written),
-                              p update (z, p read; p written), (p, A p) (a, p
-                              read), x update (x, p read; x written), all on n^2 */
+    MLMC_KERNEL_REFINE = 11 /* rtol mode on grids >= 64^2, the flexible-CG passes
+                              of a stage: initial residual (FP64 a, x read; f
+                              written), then per step dots (z, r, r_old read;
+                              r_old written), p with (p, A p) (a, z, previous p
+                              read; p written), x with the new residual (FP64
+                              a, x, p read; x, f written), all on n^2 */
 };
 typedef struct {
     int64_t launches;

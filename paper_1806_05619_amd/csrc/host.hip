@@ -38,6 +38,7 @@ struct mlmc_ctx_s {
     int32_t *d_bexp = nullptr, *d_yexp = nullptr;
     int sp = 0;                  // s rounded up to the matrix-core K step
     double *d_a64 = nullptr;     // mixed mode: FP64 copy of the a pool (CG operator)
+    double *d_ua = nullptr;      // tile levels: pre-pass output (V-cycle type, pool elements)
     int64_t Mmax = 0;
     int64_t pool = 0;            // doubles per pool
     double *d_a = nullptr, *d_u = nullptr, *d_f = nullptr;
@@ -422,6 +423,7 @@ struct HierT {
     T *f[kMaxMgLevels] = {};
     double *w[kMaxMgLevels] = {};
     const double *a64[kMaxMgLevels] = {};   // FP64 coefficients (a itself when T = double)
+    T *ua[kMaxMgLevels] = {};               // pre-pass output of a tile level
 };
 
 template <typename T>
@@ -438,6 +440,7 @@ HierT<T> make_hier_t(mlmc_ctx c, int G, int64_t Bc)
         h.w[g] = c->d_w ? c->d_w + off : nullptr;
         h.a64[g] = sizeof(T) == sizeof(double) ? (const double *)h.a[g]
                                                : (c->d_a64 ? c->d_a64 + off : nullptr);
+        h.ua[g] = c->d_ua ? (T *)c->d_ua + off : nullptr;
     }
     return h;
 }
@@ -461,7 +464,9 @@ struct FusedRunner {
     }
 
     // V(mu1,mu2) at level g > Gs.  init_top: 0 read u, 1 zero, 2 interpolate
-    // the previous stage's solution.  top_f nullptr means f = 1.
+    // the previous stage's solution.  top_f nullptr means f = 1.  On every
+    // tile level the pre pass writes ua and the post pass reads ua and writes
+    // u (top_u on the top level), so no pass reads the array it writes.
     void vcycle(int g, T *top_u, int init_top, const T *top_f, const int32_t *active)
     {
         for (int l = g; l > Gs; --l) {
@@ -474,13 +479,13 @@ struct FusedRunner {
             ProfScope ps(c, st, MLMC_KERNEL_PRE, W * cells(n) * words, 0.0);
             if constexpr (std::is_same<T, double>::value) {
                 if (pre_uses_stream(n)) {
-                    launch_pre_stream(st, c->cfg.mu1, h.a[l], f, u, h.u[l - 1], n, h.Bc, init,
-                                      h.f[l - 1], active);
+                    launch_pre_stream(st, c->cfg.mu1, h.a[l], f, u, h.ua[l], h.u[l - 1], n, h.Bc,
+                                      init, h.f[l - 1], active);
                     continue;
                 }
             }
-            launch_pre_tile<T>(st, c->cfg.mu1, h.a[l], f, u, h.u[l - 1], n, h.Bc, init, h.f[l - 1],
-                               active);
+            launch_pre_tile<T>(st, c->cfg.mu1, h.a[l], f, u, h.ua[l], h.u[l - 1], n, h.Bc, init,
+                               h.f[l - 1], active);
         }
         lds_vcycle(active);
         for (int l = Gs + 1; l <= g; ++l) {
@@ -490,11 +495,13 @@ struct FusedRunner {
             ProfScope ps(c, st, MLMC_KERNEL_POST, W * cells(n) * (3.25 + (f ? 1.0 : 0.0)), 0.0);
             if constexpr (std::is_same<T, double>::value) {
                 if (post_uses_stream(n, h.Bc)) {
-                    launch_post_stream(st, c->cfg.mu2, h.a[l], f, u, h.u[l - 1], n, h.Bc, active);
+                    launch_post_stream(st, c->cfg.mu2, h.a[l], f, h.ua[l], u, h.u[l - 1], n, h.Bc,
+                                       active);
                     continue;
                 }
             }
-            launch_post_tile<T>(st, c->cfg.mu2, h.a[l], f, u, h.u[l - 1], n, h.Bc, active);
+            launch_post_tile<T>(st, c->cfg.mu2, h.a[l], f, h.ua[l], u, h.u[l - 1], n, h.Bc,
+                                active);
         }
     }
 };
@@ -773,7 +780,8 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     const int64_t brows = mixed ? mixed_pad_cols(ctx->Mmax) : 0;
     const int64_t yrows = mixed ? mixed_pad_rows(ctx->chunk_max) : 0;
     const int64_t a64 = mixed ? ctx->pool : 0;
-    size_t need = (size_t)ctx->elem * 3 * (size_t)ctx->pool +
+    const bool tile_levels = fused_supported(c.mu1, c.mu2) && Gmax > kLdsMaxLevel;
+    size_t need = (size_t)ctx->elem * (tile_levels ? 4 : 3) * (size_t)ctx->pool +
                   (8 * (size_t)ctx->sp + 4) * (size_t)(brows + yrows) + 8 * (size_t)a64 +
                   sizeof(double) * ((size_t)s * ctx->Mmax + 4 * ctx->fcg_cells + parts + wcap +
                                     (size_t)ctx->chunk_max * (s + c.num_levels * ctx->nq + 2) +
@@ -804,6 +812,11 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     CHK(dev_alloc(ctx, &ctx->d_bexp, brows));
     CHK(dev_alloc(ctx, &ctx->d_yexp, yrows));
     CHK(dev_alloc(ctx, &ctx->d_a64, a64));
+    if (tile_levels) {
+        char *pa2 = nullptr;
+        CHK(dev_alloc(ctx, &pa2, ctx->pool * ctx->elem));
+        ctx->d_ua = (double *)pa2;    // float storage in the mixed mode
+    }
     CHK(dev_alloc(ctx, &ctx->d_fcg, 4 * ctx->fcg_cells));
     CHK(dev_alloc(ctx, &ctx->d_part, parts));
     CHK(dev_alloc(ctx, &ctx->d_fs, ctx->fcg_cells > 0 ? 4 * ctx->chunk_max : 0));

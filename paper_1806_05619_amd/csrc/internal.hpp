@@ -83,14 +83,15 @@ void launch_sums_final(hipStream_t st, const double *state, int64_t count, doubl
 
 // ---- fused kernels (kernels_fused.hip), T = double or float ----
 bool fused_supported(int mu1, int mu2);
-// pre pass on level n: init 0 read u, 1 zero guess, 2 u = P uc; writes u and fc
+// pre pass on level n: init 0 read u_in, 1 zero guess, 2 u = P uc; writes u_out
+// (never u_in: tiles read their neighbours' cells) and fc
 template <typename T>
-void launch_pre_tile(hipStream_t st, int mu1, const T *a, const T *f, T *u, const T *uc, int n,
-                     int64_t Bc, int init, T *fc, const int32_t *active);
-// post pass on level n: u += P ec, then mu2 sweeps
+void launch_pre_tile(hipStream_t st, int mu1, const T *a, const T *f, const T *u_in, T *u_out,
+                     const T *uc, int n, int64_t Bc, int init, T *fc, const int32_t *active);
+// post pass on level n: u = u_in + P ec, then mu2 sweeps, into u_out (!= u_in)
 template <typename T>
-void launch_post_tile(hipStream_t st, int mu2, const T *a, const T *f, T *u, const T *ec, int n,
-                      int64_t Bc, const int32_t *active);
+void launch_post_tile(hipStream_t st, int mu2, const T *a, const T *f, const T *u_in, T *u_out,
+                      const T *ec, int n, int64_t Bc, const int32_t *active);
 // LDS-resident hierarchy <= 32^2, one workgroup per sample:
 // FP64 FMG stages 0..G with fixed cycles and QoI, final u of level G to the pool
 void launch_lds_fmg_fixed(hipStream_t st, const double *a_pool, double *u_pool, int64_t Bc, int G,
@@ -144,10 +145,11 @@ void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho
 
 // ---- row-streaming passes (kernels_stream.hip), one workgroup per sample ----
 bool stream_supported(int n);
-void launch_pre_stream(hipStream_t st, int mu1, const double *a, const double *f, double *u,
-                       const double *uc, int n, int64_t Bc, int init, double *fc,
-                       const int32_t *active);
-void launch_post_stream(hipStream_t st, int mu2, const double *a, const double *f, double *u,
-                        const double *ec, int n, int64_t Bc, const int32_t *active);
+void launch_pre_stream(hipStream_t st, int mu1, const double *a, const double *f,
+                       const double *u_in, double *u_out, const double *uc, int n, int64_t Bc,
+                       int init, double *fc, const int32_t *active);
+void launch_post_stream(hipStream_t st, int mu2, const double *a, const double *f,
+                        const double *u_in, double *u_out, const double *ec, int n, int64_t Bc,
+                        const int32_t *active);
 
 }  // namespace mlmc

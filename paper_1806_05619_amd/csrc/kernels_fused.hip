@@ -220,10 +220,13 @@ __device__ __forceinline__ void sweep_ring(const Cell<T> *cs, T *u_s, int lo, in
 
 // ---------------------------------------------------------------------------
 // Pre pass: mu1 red-black sweeps + residual + restriction on one tile.
-// init: 0 = read u, 1 = zero initial guess, 2 = FMG interpolation from uc.
+// init: 0 = read u_in, 1 = zero initial guess, 2 = FMG interpolation from uc.
+// The result goes to u_out, which no block of the launch reads: a tile reads
+// its neighbours' cells as halo, so an in-place write would race with them.
 template <int MU, typename T>
 __global__ __launch_bounds__(NT) void k_pre_tile(const T *__restrict__ a, const T *__restrict__ f,
-                                                 T *__restrict__ u, const T *__restrict__ uc, int n,
+                                                 const T *__restrict__ u_in, T *__restrict__ u_out,
+                                                 const T *__restrict__ uc, int n,
                                                  int64_t Bc, int init, T *__restrict__ fc,
                                                  const int32_t *__restrict__ active)
 {
@@ -246,7 +249,8 @@ __global__ __launch_bounds__(NT) void k_pre_tile(const T *__restrict__ a, const 
     const int i0 = (tile % tiles_side) * TILE, j0 = (tile / tiles_side) * TILE;
     const int64_t cells = (int64_t)n * n;
     const T *ab = a + b * cells;
-    T *ub = u + b * cells;
+    const T *ub = init == 0 ? u_in + b * cells : nullptr;
+    T *ob = u_out + b * cells;
     const T *fb = f ? f + b * cells : nullptr;
     const int nc = n / 2;
     const T h2 = T(1) / (T(n) * T(n));
@@ -301,14 +305,16 @@ __global__ __launch_bounds__(NT) void k_pre_tile(const T *__restrict__ a, const 
     }
     for (int e = threadIdx.x; e < TILE * TILE; e += NT) {
         const int lj = e / TILE, li = e - lj * TILE;
-        ub[(i0 + li) + (int64_t)n * (j0 + lj)] = u_s[(H + li) + S * (H + lj)];
+        ob[(i0 + li) + (int64_t)n * (j0 + lj)] = u_s[(H + li) + S * (H + lj)];
     }
 }
 
-// Post pass: u += P ec on the tile and its halo, then mu2 sweeps black first.
+// Post pass: u = u_in + P ec on the tile and its halo, then mu2 sweeps black
+// first; the result goes to u_out (not read by the launch).
 template <int MU, typename T>
 __global__ __launch_bounds__(NT) void k_post_tile(const T *__restrict__ a, const T *__restrict__ f,
-                                                  T *__restrict__ u, const T *__restrict__ ec, int n,
+                                                  const T *__restrict__ u_in, T *__restrict__ u_out,
+                                                  const T *__restrict__ ec, int n,
                                                   int64_t Bc, const int32_t *__restrict__ active)
 {
     constexpr int H = 2 * MU;
@@ -330,7 +336,8 @@ __global__ __launch_bounds__(NT) void k_post_tile(const T *__restrict__ a, const
     const int i0 = (tile % tiles_side) * TILE, j0 = (tile / tiles_side) * TILE;
     const int64_t cells = (int64_t)n * n;
     const T *ab = a + b * cells;
-    T *ub = u + b * cells;
+    const T *ub = u_in + b * cells;
+    T *ob = u_out + b * cells;
     const T *fb = f ? f + b * cells : nullptr;
     const int nc = n / 2;
     const T h2 = T(1) / (T(n) * T(n));
@@ -350,7 +357,7 @@ __global__ __launch_bounds__(NT) void k_post_tile(const T *__restrict__ a, const
     }
     for (int e = threadIdx.x; e < TILE * TILE; e += NT) {
         const int lj = e / TILE, li = e - lj * TILE;
-        ub[(i0 + li) + (int64_t)n * (j0 + lj)] = u_s[(H + li) + S * (H + lj)];
+        ob[(i0 + li) + (int64_t)n * (j0 + lj)] = u_s[(H + li) + S * (H + lj)];
     }
 }
 
@@ -1135,29 +1142,29 @@ inline unsigned blocks_of(int64_t n, int per) { return nblocks((n + per - 1) / p
 bool fused_supported(int mu1, int mu2) { return mu1 >= 1 && mu1 <= 2 && mu2 >= 1 && mu2 <= 2; }
 
 template <typename T>
-void launch_pre_tile(hipStream_t st, int mu1, const T *a, const T *f, T *u, const T *uc, int n,
-                     int64_t Bc, int init, T *fc, const int32_t *active)
+void launch_pre_tile(hipStream_t st, int mu1, const T *a, const T *f, const T *u_in, T *u_out,
+                     const T *uc, int n, int64_t Bc, int init, T *fc, const int32_t *active)
 {
     const int64_t blocks = Bc * (int64_t)(n / TILE) * (n / TILE);
     if (mu1 == 2)
-        hipLaunchKernelGGL((k_pre_tile<2, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u, uc, n,
-                           Bc, init, fc, active);
+        hipLaunchKernelGGL((k_pre_tile<2, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u_in,
+                           u_out, uc, n, Bc, init, fc, active);
     else
-        hipLaunchKernelGGL((k_pre_tile<1, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u, uc, n,
-                           Bc, init, fc, active);
+        hipLaunchKernelGGL((k_pre_tile<1, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u_in,
+                           u_out, uc, n, Bc, init, fc, active);
 }
 
 template <typename T>
-void launch_post_tile(hipStream_t st, int mu2, const T *a, const T *f, T *u, const T *ec, int n,
-                      int64_t Bc, const int32_t *active)
+void launch_post_tile(hipStream_t st, int mu2, const T *a, const T *f, const T *u_in, T *u_out,
+                      const T *ec, int n, int64_t Bc, const int32_t *active)
 {
     const int64_t blocks = Bc * (int64_t)(n / TILE) * (n / TILE);
     if (mu2 == 2)
-        hipLaunchKernelGGL((k_post_tile<2, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u, ec,
-                           n, Bc, active);
+        hipLaunchKernelGGL((k_post_tile<2, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u_in,
+                           u_out, ec, n, Bc, active);
     else
-        hipLaunchKernelGGL((k_post_tile<1, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u, ec,
-                           n, Bc, active);
+        hipLaunchKernelGGL((k_post_tile<1, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u_in,
+                           u_out, ec, n, Bc, active);
 }
 
 // Workgroups sized to the top LDS grid: LDS for exactly levels 0..G, one
@@ -1258,10 +1265,10 @@ void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho
 }
 
 #define MLMC_INSTANTIATE(T)                                                                        \
-    template void launch_pre_tile<T>(hipStream_t, int, const T *, const T *, T *, const T *, int, \
-                                     int64_t, int, T *, const int32_t *);                          \
-    template void launch_post_tile<T>(hipStream_t, int, const T *, const T *, T *, const T *, int,\
-                                      int64_t, const int32_t *);                                   \
+    template void launch_pre_tile<T>(hipStream_t, int, const T *, const T *, const T *, T *,      \
+                                     const T *, int, int64_t, int, T *, const int32_t *);          \
+    template void launch_post_tile<T>(hipStream_t, int, const T *, const T *, const T *, T *,     \
+                                      const T *, int, int64_t, const int32_t *);                   \
     template void launch_lds_vcycle<T>(hipStream_t, const T *, const T *, T *, int64_t, int, int, \
                                        int, const int32_t *);                                      \
     template void launch_lds_fmg_refine<T>(hipStream_t, const T *, const double *, double *,      \

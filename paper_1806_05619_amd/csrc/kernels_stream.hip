@@ -100,11 +100,12 @@ __device__ __forceinline__ void prolong2(const Coarse6 &k, double &v0, double &v
     v1 = (9.0 * k.c0 + 3.0 * k.p0 + 3.0 * k.c1 + k.p1) / 16.0;
 }
 
-// PRE: init 0 = read u, 1 = zero, 2 = u = P uc.  POST: u = u + P ec.
+// PRE: init 0 = read u_in, 1 = zero, 2 = u = P uc.  POST: u = u_in + P ec.
+// The result goes to u_out (may equal u_in: rows are read before written).
 template <int MU, bool PRE>
 __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
                                                  const double *__restrict__ f,
-                                                 double *__restrict__ u,
+                                                 const double *u_in, double *u_out,
                                                  const double *__restrict__ ec, int n, int64_t Bc,
                                                  int init, double *__restrict__ fc,
                                                  const int32_t *__restrict__ active)
@@ -125,7 +126,8 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
     const int64_t cells = (int64_t)n * n;
     const double *ab = a + b * cells;
     const double *fb = f ? f + b * cells : nullptr;
-    double *ub = u + b * cells;
+    const double *ub = u_in ? u_in + b * cells : nullptr;
+    double *ob = u_out + b * cells;
     const double *eb = ec ? ec + b * (int64_t)nc * nc : nullptr;
     double *fcb = PRE ? fc + b * (int64_t)nc * nc : nullptr;
     const double h2 = 1.0 / ((double)n * (double)n);
@@ -273,8 +275,8 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
                 const double u0 = odd ? ubk : ur, u1 = odd ? ur : ubk;
                 const double res0 = odd ? resb : resr, res1 = odd ? resr : resb;
                 const int64_t o = (int64_t)rr * n;
-                ub[o + c0] = u0;
-                ub[o + c1] = u1;
+                ob[o + c0] = u0;
+                ob[o + c1] = u1;
                 if (rr & 1) fcb[L + (int64_t)nc * (rr >> 1)] = 0.25 * (rkeep0 + rkeep1 + res0 + res1);
                 else { rkeep0 = res0; rkeep1 = res1; }
             }
@@ -283,16 +285,17 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
             if (rr >= 0 && rr < n && lane) {
                 const double *row = u_ring + (rr & 7) * n;
                 const int64_t o = (int64_t)rr * n;
-                ub[o + c0] = row[c0];
-                ub[o + c1] = row[c1];
+                ob[o + c0] = row[c0];
+                ob[o + c1] = row[c1];
             }
         }
     }
 }
 
 template <int MU, bool PRE>
-void launch_one(hipStream_t st, const double *a, const double *f, double *u, const double *ec,
-                int n, int64_t Bc, int init, double *fc, const int32_t *active)
+void launch_one(hipStream_t st, const double *a, const double *f, const double *u_in,
+                double *u_out, const double *ec, int n, int64_t Bc, int init, double *fc,
+                const int32_t *active)
 {
     static bool attr_set = false;
     const size_t lds = sizeof(double) * 10 * (size_t)n;
@@ -302,31 +305,32 @@ void launch_one(hipStream_t st, const double *a, const double *f, double *u, con
         attr_set = true;
     }
     const int threads = n / 2 < 64 ? 64 : n / 2;
-    hipLaunchKernelGGL((k_stream<MU, PRE>), dim3((unsigned)Bc), dim3(threads), lds, st, a, f, u, ec,
-                       n, Bc, init, fc, active);
+    hipLaunchKernelGGL((k_stream<MU, PRE>), dim3((unsigned)Bc), dim3(threads), lds, st, a, f, u_in,
+                       u_out, ec, n, Bc, init, fc, active);
 }
 
 }  // namespace
 
 bool stream_supported(int n) { return n >= 64 && n <= 512; }
 
-void launch_pre_stream(hipStream_t st, int mu1, const double *a, const double *f, double *u,
-                       const double *uc, int n, int64_t Bc, int init, double *fc,
-                       const int32_t *active)
+void launch_pre_stream(hipStream_t st, int mu1, const double *a, const double *f,
+                       const double *u_in, double *u_out, const double *uc, int n, int64_t Bc,
+                       int init, double *fc, const int32_t *active)
 {
     if (mu1 == 2)
-        launch_one<2, true>(st, a, f, u, uc, n, Bc, init, fc, active);
+        launch_one<2, true>(st, a, f, u_in, u_out, uc, n, Bc, init, fc, active);
     else
-        launch_one<1, true>(st, a, f, u, uc, n, Bc, init, fc, active);
+        launch_one<1, true>(st, a, f, u_in, u_out, uc, n, Bc, init, fc, active);
 }
 
-void launch_post_stream(hipStream_t st, int mu2, const double *a, const double *f, double *u,
-                        const double *ec, int n, int64_t Bc, const int32_t *active)
+void launch_post_stream(hipStream_t st, int mu2, const double *a, const double *f,
+                        const double *u_in, double *u_out, const double *ec, int n, int64_t Bc,
+                        const int32_t *active)
 {
     if (mu2 == 2)
-        launch_one<2, false>(st, a, f, u, ec, n, Bc, 0, nullptr, active);
+        launch_one<2, false>(st, a, f, u_in, u_out, ec, n, Bc, 0, nullptr, active);
     else
-        launch_one<1, false>(st, a, f, u, ec, n, Bc, 0, nullptr, active);
+        launch_one<1, false>(st, a, f, u_in, u_out, ec, n, Bc, 0, nullptr, active);
 }
 
 }  // namespace mlmc

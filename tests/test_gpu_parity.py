@@ -277,6 +277,26 @@ def test_full_size_bench_workload_sampled(oracle_mod):
                 assert abs(sg[r, q, l, 0] - math.fsum(d)) <= 1e-13 * math.fsum(np.abs(d))
 
 
+@pytest.mark.parametrize("B", [512, 2048])
+def test_tile_passes_race_free_at_256(oracle_mod, B):
+    """256^2 with many samples per launch (512: tile pre and post passes; 2048:
+    tile pre, row-streaming post).  Tiles read their neighbours' cells as
+    halo, so every pass writes an array the launch does not read; the result
+    is bitwise reproducible across calls and matches the oracle."""
+    dev = _dev()
+    w, ctx = _ctx("mlqmc_fp64_s100", max_batch=B)
+    P = _oracle_problem(oracle_mod, w)
+    k = w["num_levels"] - 1
+    pts = ctx.lattice(k, 0, B, 0, 1)
+    q1, _, _ = _solve(ctx, pts, k + 1)
+    q2, _, _ = _solve(ctx, pts, k + 1)
+    assert np.array_equal(q1, q2)
+    _, ys = _lattice_y(oracle_mod, w, k, [0], 0, 4)
+    for b in range(4):
+        qo = P.sample(k, ys[b], 0)[:, : ctx.nq]
+        assert _rel(q1[b], qo) <= 1e-11, b
+
+
 def _mixed_ctx(**over):
     w = synth.workload("mlqmc_mixed_s400")
     w.update(over)
