@@ -99,7 +99,11 @@ struct CoarseStage {
 // Per-cell stencil kept in registers.
 template <typename T>
 struct Cell {
-    int l;                        // LDS index li + S*lj, -1 if not owned / outside
+    // LDS index l = li + S*lj in the low 16 bits, distance to the region edge
+    // min(li, lj, S-1-li, S-1-lj) above; -1 if not owned / outside the grid
+    int lr;
+    __device__ int l() const { return lr & 0xFFFF; }
+    __device__ int ring() const { return lr >> 16; }
     T wE, wW, wN, wS, dw, inv, rhs;  // face weights (0 at a wall), wall term
                                      // 2 a_P per wall face, 1 / diagonal, h^2 f
 };
@@ -119,13 +123,13 @@ __device__ __forceinline__ void make_cell(Cell<T> &c, const T *a_s, int li, int 
     c.dw = dw;
     c.inv = frcp(d);
     c.rhs = rhs;
-    c.l = l;
+    c.lr = l | (min(min(li, lj), min(S - 1 - li, S - 1 - lj)) << 16);
 }
 
 template <int S, typename T>
 __device__ __forceinline__ void relax(const Cell<T> &c, T *u_s)
 {
-    const int l = c.l;
+    const int l = c.l();
     T num = c.rhs;
     num += c.wE * u_s[l + 1];
     num += c.wW * u_s[l - 1];
@@ -195,7 +199,7 @@ __device__ __forceinline__ void make_cells(Cell<T> *cs, const T *a_s, const T *f
 #pragma unroll
     for (int k = 0; k < Own::PER; ++k) {
         const int q = threadIdx.x + NT * k;
-        cs[k].l = -1;
+        cs[k].lr = -1;
         if (q < Own::COUNT) {
             int li, lj;
             Own::coords(q, li, lj);
@@ -207,15 +211,12 @@ __device__ __forceinline__ void make_cells(Cell<T> *cs, const T *a_s, const T *f
 }
 
 template <int S, int PER, typename T>
-__device__ __forceinline__ void sweep_ring(const Cell<T> *cs, T *u_s, int lo, int hi)
+__device__ __forceinline__ void sweep_ring(const Cell<T> *cs, T *u_s, int lo)
 {
+    // cells in the square ring [lo, S - lo)^2 of the region
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int l = cs[k].l;
-        if (l < 0) continue;
-        const int lj = l / S, li = l - lj * S;
-        if (li >= lo && li < hi && lj >= lo && lj < hi) relax<S>(cs[k], u_s);
-    }
+    for (int k = 0; k < PER; ++k)
+        if (cs[k].ring() >= lo) relax<S>(cs[k], u_s);
 }
 
 // ---------------------------------------------------------------------------
@@ -267,16 +268,15 @@ __global__ __launch_bounds__(NT) void k_pre_tile(const T *__restrict__ a, const 
     // half-sweep t (1-based) covers ring H - t around the tile
 #pragma unroll
     for (int t = 1; t <= 2 * MU; ++t) {
-        if (t & 1) sweep_ring<S, Red::PER>(red, u_s, t, S - t);
-        else sweep_ring<S, Blk::PER>(blk, u_s, t, S - t);
+        if (t & 1) sweep_ring<S, Red::PER>(red, u_s, t);
+        else sweep_ring<S, Blk::PER>(blk, u_s, t);
         __syncthreads();
     }
     // residual r = f - A u on the tile, into a_s (a is no longer read)
     const T inv_h2 = T(n) * T(n);
     auto resid = [&](const Cell<T> &c) {
-        const int l = c.l;
-        const int lj = l / S, li = l - lj * S;
-        if (li < H || li >= H + TILE || lj < H || lj >= H + TILE) return;
+        if (c.ring() < H) return;               // tile cells only (ring H of the region)
+        const int l = c.l();
         // h^-2 (h^2 f - net flux); the flux is summed face by face as
         // w (u_P - u_nbr) (0 at a wall, whose neighbour slot holds 0 and whose
         // weight is 0) plus the wall term; h^2, h^-2 are powers of two
@@ -290,10 +290,10 @@ __global__ __launch_bounds__(NT) void k_pre_tile(const T *__restrict__ a, const 
     };
 #pragma unroll
     for (int k = 0; k < Red::PER; ++k)
-        if (red[k].l >= 0) resid(red[k]);
+        resid(red[k]);
 #pragma unroll
     for (int k = 0; k < Blk::PER; ++k)
-        if (blk[k].l >= 0) resid(blk[k]);
+        resid(blk[k]);
     __syncthreads();
     // restriction (mean of the 4 children) and write-back of the tile
     constexpr int CT = TILE / 2;
@@ -351,8 +351,8 @@ __global__ __launch_bounds__(NT) void k_post_tile(const T *__restrict__ a, const
     make_cells<S, 2, 0>(red, a_s, fb, n, i0, j0, H, h2);
 #pragma unroll
     for (int t = 1; t <= 2 * MU; ++t) {
-        if (t & 1) sweep_ring<S, Blk::PER>(blk, u_s, t, S - t);
-        else sweep_ring<S, Red::PER>(red, u_s, t, S - t);
+        if (t & 1) sweep_ring<S, Blk::PER>(blk, u_s, t);
+        else sweep_ring<S, Red::PER>(red, u_s, t);
         __syncthreads();
     }
     for (int e = threadIdx.x; e < TILE * TILE; e += NT) {
