@@ -16,13 +16,6 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int FBM = 64, FBN = 128, FKB = 16;
 
-__device__ __forceinline__ int64_t level_major_index_f(int64_t m, int64_t b, int64_t Bc)
-{
-    int g = 0;
-    while (g < kMaxMgLevels - 1 && level_offset(g + 1) <= m) ++g;
-    const int64_t lo = level_offset(g);
-    return Bc * lo + b * level_cells(g) + (m - lo);
-}
 
 // mode 0: z to out[b*M + m]; mode 1: exp(z) into the level-major FP64 pool
 __global__ __launch_bounds__(256) void k_field_mfma64(const double *__restrict__ Y, int s,
@@ -41,28 +34,33 @@ __global__ __launch_bounds__(256) void k_field_mfma64(const double *__restrict__
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
+    // global loads of the next 16 modes are in flight while the matrix cores
+    // work on the current ones (register prefetch)
+    const int yr = t >> 2, yk = (t & 3) * 4;          // Y: sample row0 + yr, modes yk..yk+3
+    const int bk = t >> 4, bc = (t & 15) * 8;         // basis: mode bk, columns bc..bc+7
+    double yv[4], bv[8];
+    auto fetch = [&](int k0) {
+        const int64_t gr = row0 + yr;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gk = k0 + yk + q;
+            yv[q] = (gr < Bc && gk < s) ? Y[gr * s + gk] : 0.0;
+        }
+        const int gk = k0 + bk;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t gc = col0 + bc + q;
+            bv[q] = (gk < s && gc < M) ? basis[(int64_t)gk * ld + gc] : 0.0;
+        }
+    };
+    fetch(0);
     for (int k0 = 0; k0 < s; k0 += FKB) {
-        // Y: thread t reads 4 consecutive modes of sample row0 + t/4
-        {
-            const int r = t >> 2, kk = (t & 3) * 4;
-            const int64_t gr = row0 + r;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int gk = k0 + kk + q;
-                As[kk + q][r] = (gr < Bc && gk < s) ? Y[gr * s + gk] : 0.0;
-            }
-        }
-        // basis: thread t reads 8 consecutive columns of mode k0 + t/16
-        {
-            const int kk = t >> 4, c = (t & 15) * 8;
-            const int gk = k0 + kk;
+        for (int q = 0; q < 4; ++q) As[yk + q][yr] = yv[q];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int64_t gc = col0 + c + q;
-                Bs[kk][c + q] = (gk < s && gc < M) ? basis[(int64_t)gk * ld + gc] : 0.0;
-            }
-        }
+        for (int q = 0; q < 8; ++q) Bs[bk][bc + q] = bv[q];
         __syncthreads();
+        if (k0 + FKB < s) fetch(k0 + FKB);
 #pragma unroll
         for (int ks = 0; ks < FKB / 4; ++ks) {
             const int kr = 4 * ks + (lane >> 4);
@@ -84,14 +82,22 @@ __global__ __launch_bounds__(256) void k_field_mfma64(const double *__restrict__
     for (int j = 0; j < 4; ++j) {
         const int64_t m = col0 + 64 * wc + 16 * j + (lane & 15);
         if (m >= M) continue;
+        // column m of sample b: out[b*M + m], or level g of the level-major pool
+        int64_t base = m, stride = M;
+        if (mode != 0) {
+            int g = 0;
+            while (g < kMaxMgLevels - 1 && level_offset(g + 1) <= m) ++g;
+            const int64_t lo = level_offset(g);
+            base = Bc * lo + (m - lo);
+            stride = level_cells(g);
+        }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t b = row0 + 32 * wr + 16 * i + (lane >> 4) + 4 * e;
                 if (b >= Bc) continue;
-                if (mode == 0) out[b * M + m] = acc[i][j][e];
-                else out[level_major_index_f(m, b, Bc)] = exp(acc[i][j][e]);
+                out[base + b * stride] = mode == 0 ? acc[i][j][e] : exp(acc[i][j][e]);
             }
     }
 }
