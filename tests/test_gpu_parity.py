@@ -403,3 +403,24 @@ def test_refinement_high_contrast_matches_direct_solve(oracle_mod, precision):
     print(f"\n{precision}: max relative QoI error per level (mean, centre):\n{errs}")
     tol = 1e-9 if precision == "fp64" else 1e-8
     assert errs.max() <= tol, errs
+
+
+def test_adaptive_driver_on_gpu():
+    """Algorithm 1 (Section 3.4) driving the library on the s = 100 lattice
+    workload: reaches its tolerance, every call solves exactly the new lattice
+    points of all shifts, and estimates at two tolerances agree within their
+    error bounds."""
+    from paper_1806_05619_amd.driver import GpuSampler, mg_mlqmc
+    _dev()
+    w, ctx = _ctx("mlqmc_fp64_s100", max_batch=4096)
+    res = {}
+    for eps in (4e-3, 2e-3):
+        r = mg_mlqmc(GpuSampler(ctx), eps, max_level=w["num_levels"] - 1,
+                     max_points=1 << w["lattice_log2n"])
+        print(f"\neps {eps}: L {r['L']} N {r['N'].tolist()} q {r['q_bar']:.10f} "
+              f"sd {math.sqrt(r['var']):.2e} bias {r['bias']:.2e} alpha {r['alpha']:.2f}")
+        assert r["converged"], r
+        assert r["var"] <= eps * eps / 2 and r["bias"] <= eps / math.sqrt(2)
+        res[eps] = r
+    a, b = res[4e-3], res[2e-3]
+    assert abs(a["q_bar"] - b["q_bar"]) <= 3 * (4e-3 + 2e-3)
