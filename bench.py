@@ -134,6 +134,91 @@ def mixed_vs_fp64(m, torch, dev, max_batch=64, min_seconds=0.25):
     return out
 
 
+def serving(m, torch, w, seconds=3.0, rate=400.0, req_points=64, slots=4, slot_samples=4096):
+    """The serving loop (mlmc_server) on the s = 100 workload: requests of
+    `req_points` lattice points of one shift on level l, l drawn with
+    probability proportional to 2^-l (an MLQMC run asks for fewer samples on
+    finer levels).  Open loop: Poisson arrivals at `rate` requests/s for
+    `seconds`, latency percentiles from submit to QoIs on the host.
+    Saturated: 4000 such requests submitted at once, against the same
+    requests solved one call at a time on one context."""
+    import synth
+    L1 = w["num_levels"]
+    p = 2.0 ** -np.arange(L1)
+    p /= p.sum()
+    rng = np.random.default_rng(11)
+    kw = dict(n0=w["n0"], num_levels=L1, s=w["s"], corr_len=w["corr_len"], sigma2=w["sigma2"],
+              mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"], max_iters=w["max_iters"],
+              precision=m.MLMC_FP64, qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
+              genvec=synth.korobov_vector(w["seed"], w["s"]),
+              shifts=synth.shift_table(w["seed"], L1, w["num_shifts"], w["s"]))
+
+    def draw(n):
+        lv = rng.choice(L1, size=n, p=p)
+        r = rng.integers(0, w["num_shifts"], size=n)
+        n0 = rng.integers(0, 1 << 20, size=n)
+        return [(int(a), int(b), int(b) + req_points, int(c), int(c) + 1) for a, b, c in zip(lv, n0, r)]
+
+    out = dict(request=f"{req_points} lattice points of one shift, level l with probability "
+                       f"~2^-l over {w['n0']}^2..{w['n0'] << (L1 - 1)}^2",
+               slots=slots, slot_samples=slot_samples)
+
+    def drain(srv, lat):
+        while srv.pending():
+            lat += [r["latency_ms"] for r in srv.poll(wait_ms=50)]
+
+    with m.Server(**kw, num_slots=slots, slot_samples=slot_samples, device=0) as srv:
+        for r in draw(4 * slots):          # warm up every slot
+            srv.submit(*r)
+        drain(srv, [])
+        base = srv.stats()
+        lat = []
+        t0 = t_next = time.perf_counter()
+        while time.perf_counter() < t0 + seconds:
+            now = time.perf_counter()
+            while t_next <= now:
+                srv.submit(*draw(1)[0])
+                t_next += rng.exponential(1.0 / rate)
+            lat += [r["latency_ms"] for r in srv.poll(wait_ms=0)]
+            time.sleep(max(0.0, min(t_next - time.perf_counter(), 0.002)))
+        drain(srv, lat)
+        dt = time.perf_counter() - t0
+        st = srv.stats()
+        lat = np.array(lat)
+        out["open_loop"] = dict(rate_per_s=rate, seconds=seconds, requests=len(lat),
+                                samples_per_s=(st["samples"] - base["samples"]) / dt,
+                                batches=st["batches"] - base["batches"],
+                                p50_ms=float(np.percentile(lat, 50)),
+                                p99_ms=float(np.percentile(lat, 99)), max_ms=float(lat.max()))
+        reqs = draw(4000)
+        lat = []
+        t0 = time.perf_counter()
+        for r in reqs:
+            srv.submit(*r)
+        drain(srv, lat)
+        dt = time.perf_counter() - t0
+        out["saturated"] = dict(requests=len(reqs), samples_per_s=len(reqs) * req_points / dt,
+                                batches=srv.stats()["batches"] - st["batches"],
+                                p50_ms=float(np.percentile(lat, 50)),
+                                p99_ms=float(np.percentile(lat, 99)))
+    ctx = m.Context(**kw, max_batch=req_points, device=0)
+    q = torch.zeros((req_points, L1, 2), dtype=torch.float64, device="cuda:0")
+    t0 = time.perf_counter()
+    for r in reqs[:400]:
+        ctx.fmg_solve(ctx.lattice(*r), qoi=q)
+        q.cpu()
+    dt = time.perf_counter() - t0
+    out["one_call_per_request_samples_per_s"] = 400 * req_points / dt
+    out["saturated"]["speedup_over_one_call_per_request"] = (out["saturated"]["samples_per_s"] /
+                                                             out["one_call_per_request_samples_per_s"])
+    del ctx
+    log(f"[bench] serving: open loop {rate:.0f} req/s p50 {out['open_loop']['p50_ms']:.2f} ms "
+        f"p99 {out['open_loop']['p99_ms']:.2f} ms; saturated "
+        f"{out['saturated']['samples_per_s']:.0f} samples/s "
+        f"(x{out['saturated']['speedup_over_one_call_per_request']:.1f} over one call per request)")
+    return out
+
+
 def cpu_baseline(w, level, seconds):
     """The oracle (field by direct summation + CPU FMG + QoI) on the host's
     cores, over the first lattice points of shift 0 at the same level, run in
@@ -306,6 +391,7 @@ def main():
             lat[f"level{k}_n{nreq}"] = dict(p50_ms=float(np.percentile(times, 50)),
                                             p99_ms=float(np.percentile(times, 99)))
         out["latency"] = lat
+        out["serving"] = serving(m, torch, w)
         if not args.no_mixed:
             del ctx
             torch.cuda.empty_cache()

@@ -154,11 +154,12 @@ mlmc_status mlmc_points_gen(mlmc_ctx ctx, const mlmc_points *pts,
 /* Section 5, eq. truncatedKL: z(x) = sigma sum_{m<s} sqrt(theta_m) psi_m(x) y_m
  * at the cell centres of every MG level 0..G(level) of every sample, as one
  * dense product Y [B][s] x basis [s][M].  z_dev [B][M], M = mlmc_field_size
- * (sample-major, levels in order).  FP64 context: FP64 product.  MIXED
- * context: the product the MIXED solve uses, with Y and the basis each split
- * into three bf16 terms and six term products on the matrix cores (FP32
- * accumulation per 32 modes, FP64 across them); |error| stays within a few
- * units of 2^-24 times sum_m |y_m| |basis_m(x)|, returned as double. */
+ * (sample-major, levels in order).  FP64 context: FP64 product on the matrix
+ * cores.  MIXED context: the product the MIXED solve uses, with every sample
+ * row of Y and every cell column of the basis scaled by a power of two
+ * 2^E > max |entry| and written as four bf16 digits, ten digit products on the
+ * matrix cores summed exactly and folded into FP64; |error| <= 5 s
+ * 2^(E_y + E_b - 32) per cell, without rounding bias, returned as double. */
 mlmc_status mlmc_field(mlmc_ctx ctx, const mlmc_points *pts, double *z_dev,
                        void *hip_stream);
 
@@ -276,6 +277,64 @@ typedef struct {
 } mlmc_profile_result;
 mlmc_status mlmc_profile_begin(mlmc_ctx ctx, int32_t kernel_kind);
 mlmc_status mlmc_profile_end(mlmc_ctx ctx, mlmc_profile_result *out);
+
+/* ---- Serving loop: continuous batching of solve requests ----------------
+ * A server owns num_slots copies of one configuration, each with its own HIP
+ * stream, workspace for slot_samples samples and a host thread; the HBM
+ * footprint is fixed at create (E_NOMEM if the slots do not fit).  Requests
+ * (level, lattice-point range, shift range) join one FIFO queue.  A free slot
+ * takes the oldest request and packs behind it every queued request of the
+ * same level that still fits (continuous batching: requests arriving while
+ * other batches run are admitted as slots free up), generates their points,
+ * solves the batch (Algorithm 1's SampleAndSolve, all levels <= level) and
+ * copies the QoIs to the host.  Every sample's result is bitwise the same
+ * alone and in any batch. */
+typedef struct mlmc_server_s *mlmc_server;
+
+typedef struct {
+    int32_t level;                  /* finest MLMC level */
+    int32_t shift_begin, shift_end; /* shifts [shift_begin, shift_end) */
+    int64_t n_begin, n_end;         /* lattice points [n_begin, n_end) */
+    uint64_t tag;                   /* caller's label, returned with the result */
+    double *qoi_out;                /* host [B][level+1][nq], B = samples of the
+                                       request in lattice order (shift-major);
+                                       caller-owned, written before the result
+                                       is reported, kept valid until then */
+} mlmc_request;
+
+typedef struct {
+    uint64_t tag;
+    int32_t status;                 /* MLMC_OK, or the solve's error */
+    int32_t level;
+    int64_t samples;
+    int64_t batch_samples;          /* samples of the batch it was solved in */
+    double queued_ms;               /* submit -> its batch starts */
+    double latency_ms;              /* submit -> QoIs on the host */
+} mlmc_result;
+
+typedef struct {
+    int64_t requests, samples;      /* completed */
+    int64_t batches;
+    double p50_ms, p99_ms, max_ms;  /* latency of the completed requests */
+    double busy_s;                  /* first submit -> last completion */
+} mlmc_server_stats;
+
+/* cfg as for mlmc_create (cfg->max_batch is replaced by slot_samples; lattice
+ * points required).  E_INVAL for num_slots < 1, slot_samples < 1 or device < 0. */
+mlmc_status mlmc_server_create(const mlmc_config *cfg, int device, int32_t num_slots,
+                               int64_t slot_samples, mlmc_server *out);
+/* Finishes the queued and running requests, then frees everything. */
+mlmc_status mlmc_server_destroy(mlmc_server srv);
+/* Thread-safe, non-blocking.  E_INVAL (nothing queued) for a bad range, a
+ * level outside the configuration, more samples than a slot holds, or a NULL
+ * qoi_out. */
+mlmc_status mlmc_server_submit(mlmc_server srv, const mlmc_request *req);
+/* Up to max_results completed results, oldest first; waits up to wait_ms for
+ * the first one (0: no wait).  *count receives the number written. */
+mlmc_status mlmc_server_poll(mlmc_server srv, mlmc_result *out, int32_t max_results,
+                             int32_t wait_ms, int32_t *count);
+/* Counters and latency percentiles of everything completed so far. */
+mlmc_status mlmc_server_stats_get(mlmc_server srv, mlmc_server_stats *out);
 
 const char *mlmc_status_str(mlmc_status st);
 /* Text of the last error on ctx (empty string if none); NULL ctx gives the

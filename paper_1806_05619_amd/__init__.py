@@ -66,10 +66,30 @@ class mlmc_est_output(C.Structure):
                 ("q_shift", C.c_void_p), ("q_bar", C.c_void_p), ("var_q", C.c_void_p)]
 
 
+class mlmc_request(C.Structure):
+    _fields_ = [("level", C.c_int32), ("shift_begin", C.c_int32), ("shift_end", C.c_int32),
+                ("n_begin", C.c_int64), ("n_end", C.c_int64), ("tag", C.c_uint64),
+                ("qoi_out", C.c_void_p)]
+
+
+class mlmc_result(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("status", C.c_int32), ("level", C.c_int32),
+                ("samples", C.c_int64), ("batch_samples", C.c_int64),
+                ("queued_ms", C.c_double), ("latency_ms", C.c_double)]
+
+
+class mlmc_server_stats(C.Structure):
+    _fields_ = [("requests", C.c_int64), ("samples", C.c_int64), ("batches", C.c_int64),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("max_ms", C.c_double),
+                ("busy_s", C.c_double)]
+
+
 EXPORTS = [
     "mlmc_create", "mlmc_destroy", "mlmc_field_size", "mlmc_num_qoi", "mlmc_points_gen",
     "mlmc_field", "mlmc_fmg_solve", "mlmc_estimate", "mlmc_kl_modes", "mlmc_fmg_trace",
     "mlmc_status_str", "mlmc_last_error", "mlmc_profile_begin", "mlmc_profile_end",
+    "mlmc_server_create", "mlmc_server_destroy", "mlmc_server_submit", "mlmc_server_poll",
+    "mlmc_server_stats_get",
 ]
 
 _lib = None
@@ -104,6 +124,11 @@ def lib():
         "mlmc_fmg_trace": (i32, [vp, i32, vp, vp, i64, C.POINTER(i64)]),
         "mlmc_profile_begin": (i32, [vp, i32]),
         "mlmc_profile_end": (i32, [vp, C.POINTER(mlmc_profile_result)]),
+        "mlmc_server_create": (i32, [C.POINTER(mlmc_config), C.c_int, i32, i64, C.POINTER(vp)]),
+        "mlmc_server_destroy": (i32, [vp]),
+        "mlmc_server_submit": (i32, [vp, C.POINTER(mlmc_request)]),
+        "mlmc_server_poll": (i32, [vp, C.POINTER(mlmc_result), i32, i32, C.POINTER(i32)]),
+        "mlmc_server_stats_get": (i32, [vp, C.POINTER(mlmc_server_stats)]),
         "mlmc_status_str": (C.c_char_p, [i32]),
         "mlmc_last_error": (C.c_char_p, [vp]),
     }
@@ -149,21 +174,31 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _config(n0, num_levels, s, corr_len, sigma2, mu0, mu1, mu2, rtol, max_iters, precision,
+            qoi_mask, genvec, shifts, max_batch):
+    """mlmc_config plus the host arrays it points to (kept alive by the caller)."""
+    genvec = None if genvec is None else np.ascontiguousarray(genvec, dtype=np.uint32)
+    shifts = None if shifts is None else np.ascontiguousarray(shifts, dtype=np.uint64)
+    R = 0 if shifts is None else int(shifts.shape[1])
+    cfg = mlmc_config(int(n0), int(num_levels), int(s), float(corr_len), float(sigma2),
+                      int(mu0), int(mu1), int(mu2), float(rtol), int(max_iters),
+                      int(precision), int(qoi_mask), R,
+                      None if genvec is None else genvec.ctypes.data,
+                      None if shifts is None else shifts.ctypes.data,
+                      int(max_batch))
+    return cfg, genvec, shifts
+
+
 class Context:
     """An mlmc_ctx bound to one device; tensors must live on that device."""
 
     def __init__(self, n0, num_levels, s, corr_len, sigma2, mu0=2, mu1=2, mu2=2, rtol=0.0,
                  max_iters=0, precision=MLMC_FP64, qoi_mask=MLMC_QOI_MEAN, genvec=None,
                  shifts=None, max_batch=1024, device=0):
-        self._genvec = None if genvec is None else np.ascontiguousarray(genvec, dtype=np.uint32)
-        self._shifts = None if shifts is None else np.ascontiguousarray(shifts, dtype=np.uint64)
-        R = 0 if self._shifts is None else int(self._shifts.shape[1])
-        cfg = mlmc_config(int(n0), int(num_levels), int(s), float(corr_len), float(sigma2),
-                          int(mu0), int(mu1), int(mu2), float(rtol), int(max_iters),
-                          int(precision), int(qoi_mask), R,
-                          None if self._genvec is None else self._genvec.ctypes.data,
-                          None if self._shifts is None else self._shifts.ctypes.data,
-                          int(max_batch))
+        cfg, self._genvec, self._shifts = _config(n0, num_levels, s, corr_len, sigma2, mu0, mu1,
+                                                  mu2, rtol, max_iters, precision, qoi_mask,
+                                                  genvec, shifts, max_batch)
+        R = cfg.num_shifts
         h = C.c_void_p()
         _check(lib().mlmc_create(C.byref(cfg), int(device), C.byref(h)))
         self._h = h
@@ -254,3 +289,82 @@ class Context:
                                     C.byref(n)), self._h)
         n = min(n.value, cap)
         return lv[:n].tolist(), mk[:n].tolist()
+
+
+class Server:
+    """mlmc_server: slots of one configuration serving solve requests from a
+    FIFO with same-level batching.  QoIs come back in host arrays
+    [B][level+1][nq] owned by this object until the result is polled."""
+
+    def __init__(self, n0, num_levels, s, corr_len, sigma2, genvec, shifts, mu0=2, mu1=2, mu2=2,
+                 rtol=0.0, max_iters=0, precision=MLMC_FP64, qoi_mask=MLMC_QOI_MEAN,
+                 num_slots=2, slot_samples=1024, device=0):
+        cfg, self._genvec, self._shifts = _config(n0, num_levels, s, corr_len, sigma2, mu0, mu1,
+                                                  mu2, rtol, max_iters, precision, qoi_mask,
+                                                  genvec, shifts, slot_samples)
+        h = C.c_void_p()
+        _check(lib().mlmc_server_create(C.byref(cfg), int(device), int(num_slots),
+                                        int(slot_samples), C.byref(h)))
+        self._h = h
+        self.cfg = cfg
+        self.nq = bin(int(qoi_mask) & 3).count("1")
+        self.slot_samples = int(slot_samples)
+        self._pending = {}
+        self._next_tag = 0
+
+    def submit(self, level, n_begin, n_end, shift_begin=0, shift_end=1, tag=None):
+        """Queue lattice points [n_begin, n_end) of shifts [shift_begin,
+        shift_end) on finest level `level`; returns the request's tag."""
+        if tag is None:
+            tag = self._next_tag
+        tag = int(tag)
+        if tag in self._pending:
+            raise ValueError(f"tag {tag} is still pending")
+        self._next_tag = max(self._next_tag, tag + 1)
+        B = max(0, (int(n_end) - int(n_begin)) * (int(shift_end) - int(shift_begin)))
+        out = np.zeros((B, int(level) + 1, self.nq), dtype=np.float64)
+        req = mlmc_request(int(level), int(shift_begin), int(shift_end), int(n_begin), int(n_end),
+                           tag, out.ctypes.data if B else None)
+        _check(lib().mlmc_server_submit(self._h, C.byref(req)))
+        self._pending[tag] = out
+        return tag
+
+    def poll(self, max_results=256, wait_ms=0):
+        """Completed requests, oldest first: dicts with the result fields and
+        'qoi' (the request's array)."""
+        buf = (mlmc_result * max(1, int(max_results)))()
+        n = C.c_int32(0)
+        _check(lib().mlmc_server_poll(self._h, buf, int(max_results), int(wait_ms), C.byref(n)))
+        res = []
+        for r in buf[: n.value]:
+            res.append(dict(tag=int(r.tag), status=int(r.status), level=int(r.level),
+                            samples=int(r.samples), batch_samples=int(r.batch_samples),
+                            queued_ms=r.queued_ms, latency_ms=r.latency_ms,
+                            qoi=self._pending.pop(int(r.tag))))
+        return res
+
+    def pending(self):
+        return len(self._pending)
+
+    def stats(self):
+        st = mlmc_server_stats()
+        _check(lib().mlmc_server_stats_get(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in mlmc_server_stats._fields_}
+
+    def close(self):
+        """Finishes queued requests, then frees the slots."""
+        if getattr(self, "_h", None):
+            lib().mlmc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

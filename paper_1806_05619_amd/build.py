@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmlmc.so")
 SOURCES = ["host.hip", "kernels.hip", "kernels_fused.hip", "kernels_stream.hip", "kernels_mixed.hip",
-           "kernels_field.hip"]
+           "kernels_field.hip", "server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

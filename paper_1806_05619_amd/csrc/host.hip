@@ -394,11 +394,10 @@ mlmc_status run_fmg(mlmc_ctx c, hipStream_t st, const Hier &h, int k, double *qo
 // MLMC_LARGE_PASS=tile|stream forces one kind for both (tuning runs).
 int large_pass_override()
 {
-    static int mode = -2;
-    if (mode == -2) {
+    static const int mode = [] {
         const char *e = std::getenv("MLMC_LARGE_PASS");
-        mode = !e ? -1 : (std::strcmp(e, "tile") == 0 ? 0 : (std::strcmp(e, "stream") == 0 ? 1 : -1));
-    }
+        return !e ? -1 : (std::strcmp(e, "tile") == 0 ? 0 : (std::strcmp(e, "stream") == 0 ? 1 : -1));
+    }();
     return mode;
 }
 // The row-streaming pass runs one workgroup per sample, so it needs a batch

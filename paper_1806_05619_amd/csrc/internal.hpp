@@ -20,6 +20,18 @@ constexpr int kLdsMaxLevel = 4;    // grids up to 32^2 run LDS-resident (one wor
 __host__ __device__ inline int64_t level_offset(int g) { return 4 * (((int64_t)1 << (2 * g)) - 1) / 3; }
 __host__ __device__ inline int64_t level_cells(int g) { return (int64_t)4 << (2 * g); }
 
+// Bilinear prolongation of a cell-centred coarse correction (Section 4): the
+// fine cell gets (9 c + 3 x + 3 y + d) / 16 from its coarse parent c, the two
+// coarse neighbours x, y on its side and the diagonal one d.  The rounding
+// order is fixed by explicit fma, so every kernel that prolongates (LDS,
+// tile and row-streaming passes) produces the same bits and a sample's result
+// does not depend on which of them its batch size selects.
+template <typename T>
+__device__ __forceinline__ T prolong_9331(T c, T x, T y, T d)
+{
+    return (fma(T(3), y, fma(T(3), x, T(9) * c)) + d) * T(0.0625);
+}
+
 // Views of one chunk's multigrid hierarchy in the workspace pools.  Level g
 // holds Bc samples back to back: sample b, cell p at base_g + b*n_g^2 + p.
 struct Hier {

@@ -295,9 +295,8 @@ __global__ void k_prolong(const double *__restrict__ ec, double *__restrict__ u,
     const double *eb = ec + b * nc * nc;
     int I = i / 2, J = j / 2;
     int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1;
-    double v = (9.0 * coarse_odd(eb, nc, I, J) + 3.0 * coarse_odd(eb, nc, I + sx, J) +
-                3.0 * coarse_odd(eb, nc, I, J + sy) + coarse_odd(eb, nc, I + sx, J + sy)) /
-               16.0;
+    double v = prolong_9331(coarse_odd(eb, nc, I, J), coarse_odd(eb, nc, I + sx, J),
+                            coarse_odd(eb, nc, I, J + sy), coarse_odd(eb, nc, I + sx, J + sy));
     if (add)
         u[t] += v;
     else

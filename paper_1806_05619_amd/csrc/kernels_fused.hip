@@ -91,8 +91,7 @@ struct CoarseStage {
         const int I = (gi >> 1) - cI0, J = (gj >> 1) - cJ0;
         const int sx = (gi & 1) ? 1 : -1, sy = (gj & 1) ? CS : -CS;
         const int q = I + CS * J;
-        // times 1/16 (exact: a power of two)
-        return (T(9) * cs[q] + T(3) * cs[q + sx] + T(3) * cs[q + sy] + cs[q + sx + sy]) * T(0.0625);
+        return prolong_9331(cs[q], cs[q + sx], cs[q + sy], cs[q + sx + sy]);
     }
 };
 
@@ -112,6 +111,9 @@ template <int S, typename T>
 __device__ __forceinline__ void make_cell(Cell<T> &c, const T *a_s, int li, int lj, int gi, int gj,
                                           int n, T rhs)
 {
+    // no contraction: the diagonal is the plain sum of the rounded face
+    // weights, as in the row-streaming pass, whatever the compiler fuses
+#pragma clang fp contract(off)
     const int l = li + S * lj;
     const T ap = a_s[l];
     T d = T(0), dw = T(0);
@@ -130,11 +132,12 @@ template <int S, typename T>
 __device__ __forceinline__ void relax(const Cell<T> &c, T *u_s)
 {
     const int l = c.l();
-    T num = c.rhs;
-    num += c.wE * u_s[l + 1];
-    num += c.wW * u_s[l - 1];
-    num += c.wN * u_s[l + S];
-    num += c.wS * u_s[l - S];
+    // explicit fma, faces in the order E, W, N, S: the row-streaming pass
+    // rounds identically (a zero wall weight adds an exact zero)
+    T num = fma(c.wE, u_s[l + 1], c.rhs);
+    num = fma(c.wW, u_s[l - 1], num);
+    num = fma(c.wN, u_s[l + S], num);
+    num = fma(c.wS, u_s[l - S], num);
     u_s[l] = num * c.inv;
 }
 
@@ -494,8 +497,8 @@ __device__ void lds_prolong(const T *e, T *u, int n, bool add)
     for (int p = threadIdx.x; p < n * n; p += LT) {
         const int j = p >> __builtin_ctz(n), i = p & (n - 1);   // n is a power of two
         const int I = i >> 1, J = j >> 1, sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1;
-        const T v = (T(9) * codd(e, nc, I, J) + T(3) * codd(e, nc, I + sx, J) +
-                     T(3) * codd(e, nc, I, J + sy) + codd(e, nc, I + sx, J + sy)) * T(0.0625);
+        const T v = prolong_9331(codd(e, nc, I, J), codd(e, nc, I + sx, J), codd(e, nc, I, J + sy),
+                                 codd(e, nc, I + sx, J + sy));
         u[p] = add ? u[p] + v : v;
     }
     __syncthreads();

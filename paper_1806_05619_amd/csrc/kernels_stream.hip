@@ -96,8 +96,8 @@ __device__ __forceinline__ void load_coarse(Coarse6 &k, const double *__restrict
 // (9 e_IJ + 3 e_{I+sx,J} + 3 e_{I,J+sy} + e_{I+sx,J+sy}) / 16 for columns 2L (sx=-1), 2L+1 (sx=+1)
 __device__ __forceinline__ void prolong2(const Coarse6 &k, double &v0, double &v1)
 {
-    v0 = (9.0 * k.c0 + 3.0 * k.m0 + 3.0 * k.c1 + k.m1) / 16.0;
-    v1 = (9.0 * k.c0 + 3.0 * k.p0 + 3.0 * k.c1 + k.p1) / 16.0;
+    v0 = prolong_9331(k.c0, k.m0, k.c1, k.m1);
+    v1 = prolong_9331(k.c0, k.p0, k.c1, k.p1);
 }
 
 // PRE: init 0 = read u_in, 1 = zero, 2 = u = P uc.  POST: u = u_in + P ec.
@@ -191,6 +191,8 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
         });
         const int q = s - 1;
         if (q >= 0 && q < n && lane) {
+            // no contraction: weights and diagonal round as in the tile passes
+#pragma clang fp contract(off)
             const double *aq = a_ring + (q & 1) * n, *aq1 = a_ring + ((q + 1) & 1) * n;
             const double ap0 = aq[c0], ap1 = aq[c1];
             // faces of the two cells (zero weight at a wall, whose 2a_P goes to d)
@@ -241,11 +243,13 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
                 const double *dn = u_ring + ((rr - 1) & 7) * n;
                 // the red cell of row rr is column c0 when rr is even
                 const int c = red ? c0 + (rr & 1) : c1 - (rr & 1);
+                // explicit fma in the face order E, W, N, S of the tile passes,
+                // so that both kinds of pass give the same bits
                 double num = red ? r.rhs_r : r.rhs_b;
-                if (c + 1 < n) num += (red ? r.wE_r : r.wE_b) * row[c + 1];
-                if (c > 0) num += (red ? r.wW_r : r.wW_b) * row[c - 1];
-                if (rr + 1 < n) num += (red ? r.wN_r : r.wN_b) * up[c];
-                if (rr > 0) num += (red ? rs.wN_b : rs.wN_r) * dn[c];
+                if (c + 1 < n) num = fma(red ? r.wE_r : r.wE_b, row[c + 1], num);
+                if (c > 0) num = fma(red ? r.wW_r : r.wW_b, row[c - 1], num);
+                if (rr + 1 < n) num = fma(red ? r.wN_r : r.wN_b, up[c], num);
+                if (rr > 0) num = fma(red ? rs.wN_b : rs.wN_r, dn[c], num);
                 row[c] = num * (red ? r.inv_r : r.inv_b);
             }
             __syncthreads();
@@ -297,13 +301,14 @@ void launch_one(hipStream_t st, const double *a, const double *f, const double *
                 double *u_out, const double *ec, int n, int64_t Bc, int init, double *fc,
                 const int32_t *active)
 {
-    static bool attr_set = false;
-    const size_t lds = sizeof(double) * 10 * (size_t)n;
-    if (!attr_set) {
+    // once per instantiation; the static's initialisation is thread-safe
+    static const bool attr_set = [] {
         (void)hipFuncSetAttribute((const void *)k_stream<MU, PRE>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
-    }
+        return true;
+    }();
+    (void)attr_set;
+    const size_t lds = sizeof(double) * 10 * (size_t)n;
     const int threads = n / 2 < 64 ? 64 : n / 2;
     hipLaunchKernelGGL((k_stream<MU, PRE>), dim3((unsigned)Bc), dim3(threads), lds, st, a, f, u_in,
                        u_out, ec, n, Bc, init, fc, active);

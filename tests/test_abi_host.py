@@ -153,3 +153,41 @@ def test_estimate_matches_oracle(R, reuse):
 def test_estimate_rejects_bad_input():
     with pytest.raises(m.MlmcError):
         m.mlmc_estimate(np.array([-1, 2]), np.zeros((2, 2, 1, 2, 2)), 2, 1, True)
+
+
+def _server_cfg(**kw):
+    w = synth.workload("mlqmc_fp64_s100")
+    z = synth.korobov_vector(w["seed"], w["s"])
+    D = synth.shift_table(w["seed"], w["num_levels"], w["num_shifts"], w["s"])
+    base = dict(n0=w["n0"], num_levels=w["num_levels"], s=w["s"], corr_len=w["corr_len"],
+                sigma2=w["sigma2"], mu0=2, mu1=2, mu2=2, rtol=0.0, max_iters=0, precision=0,
+                qoi_mask=1, num_shifts=w["num_shifts"], genvec=z.ctypes.data,
+                shifts=D.ctypes.data, max_batch=16)
+    base.update(kw)
+    return m.mlmc_config(**base), (z, D)
+
+
+@pytest.mark.parametrize("dev,slots,samples,over", [
+    (-1, 1, 16, {}), (0, 0, 16, {}), (0, 2, 0, {}), (0, 1, 16, dict(genvec=None)),
+    (0, 1, 16, dict(shifts=None)), (0, 1, 16, dict(n0=3)), (0, 1, 16, dict(mu1=0, mu2=0)),
+])
+def test_server_create_rejects_invalid_arguments(dev, slots, samples, over):
+    """Argument errors are reported before any device work (no GPU here)."""
+    L = m.lib()
+    cfg, keep = _server_cfg(**over)
+    h = C.c_void_p(123)
+    assert L.mlmc_server_create(C.byref(cfg), dev, slots, samples, C.byref(h)) == m.MLMC_E_INVAL
+    assert not h.value
+    assert L.mlmc_server_create(C.byref(cfg), 0, 1, 16, None) == m.MLMC_E_INVAL
+
+
+def test_server_calls_reject_null_handles():
+    L = m.lib()
+    req = m.mlmc_request(0, 0, 1, 0, 1, 0, None)
+    res = (m.mlmc_result * 4)()
+    n = C.c_int32(-1)
+    st = m.mlmc_server_stats()
+    assert L.mlmc_server_destroy(None) == m.MLMC_OK
+    assert L.mlmc_server_submit(None, C.byref(req)) == m.MLMC_E_INVAL
+    assert L.mlmc_server_poll(None, res, 4, 0, C.byref(n)) == m.MLMC_E_INVAL
+    assert L.mlmc_server_stats_get(None, C.byref(st)) == m.MLMC_E_INVAL
