@@ -219,6 +219,73 @@ def serving(m, torch, w, seconds=3.0, rate=400.0, req_points=64, slots=4, slot_s
     return out
 
 
+def uneven(m, torch, slots=3, reps=2):
+    """Uneven levels: 4^2 .. 2048^2 with 2^(16-l) samples on level l (all 16
+    shifts), mixed path refined to 1e-10.  One context solving the levels one
+    call after another, against the serving loop with `slots` slots given the
+    whole mixed queue at once (one request per level and shift, finest levels
+    first), whose batches of different levels overlap on the device.  Every
+    sample's QoIs must be bitwise those of the one-context run."""
+    import synth
+    w = synth.workload("uneven_mixed_s400")
+    L1, R = w["num_levels"], w["num_shifts"]
+    counts = w["samples_per_level"]
+    finest = counts[-1]
+    kw = dict(n0=w["n0"], num_levels=L1, s=w["s"], corr_len=w["corr_len"], sigma2=w["sigma2"],
+              mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"], max_iters=w["max_iters"],
+              precision=m.MLMC_MIXED, qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
+              genvec=synth.korobov_vector(w["seed"], w["s"]),
+              shifts=synth.shift_table(w["seed"], L1, R, w["s"]))
+    dev = torch.device("cuda:0")
+    out = dict(workload="uneven_mixed_s400: levels 4^2..2048^2, 2^(16-l) samples on level l "
+                        f"({sum(counts)} in all, {R} shifts), s = 400, lambda 0.1, sigma^2 2, "
+                        "mixed path, every FMG stage refined to relative residual 1e-10",
+               slots=slots, levels={})
+    ctx = m.Context(**kw, max_batch=finest, device=0)
+    ref = {}
+    for rep in range(reps):           # the last repetition is timed
+        t_all = 0.0
+        for l in range(L1):
+            npts = counts[l] // R
+            q = torch.empty((npts * R, l + 1, 2), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = ctx.fmg_solve(ctx.lattice(l, 0, npts, 0, R), qoi=q, want_info=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            t_all += dt
+            ref[l] = q.cpu().numpy()
+            out["levels"][f"{w['n0'] << l}^2"] = dict(samples=counts[l], one_call_s=dt,
+                                                       samples_per_s=counts[l] / dt,
+                                                       not_converged=info["not_converged"],
+                                                       max_steps=info["max_iters_used"])
+        log(f"[bench] uneven, one context: {sum(counts) / t_all:.0f} samples/s ({t_all:.2f} s)")
+    out["one_context"] = dict(seconds=t_all, samples_per_s=sum(counts) / t_all)
+    del ctx
+    torch.cuda.empty_cache()
+    reqs = [(l, 0, counts[l] // R, r, r + 1) for l in reversed(range(L1)) for r in range(R)]
+    with m.Server(**kw, num_slots=slots, slot_samples=finest, device=0) as srv:
+        same = True
+        for rep in range(reps):
+            t0 = time.perf_counter()
+            tags = {srv.submit(*q): q for q in reqs}
+            done = []
+            while srv.pending():
+                done += srv.poll(wait_ms=50)
+            dt = time.perf_counter() - t0
+            for r in done:
+                l, n0, n1, r0, r1 = tags[r["tag"]]
+                same &= r["status"] == m.MLMC_OK and bool(
+                    np.array_equal(r["qoi"], ref[l][r0 * (n1 - n0):(r0 + 1) * (n1 - n0)]))
+        st = srv.stats()
+        log(f"[bench] uneven, server ({slots} slots): {sum(counts) / dt:.0f} samples/s "
+            f"({dt:.2f} s), bitwise equal to one context: {same}")
+    out["server"] = dict(seconds=dt, samples_per_s=sum(counts) / dt, batches=st["batches"] // reps,
+                         bitwise_equal_to_one_context=same,
+                         speedup=out["one_context"]["seconds"] / dt)
+    return out
+
+
 def cpu_baseline(w, level, seconds):
     """The oracle (field by direct summation + CPU FMG + QoI) on the host's
     cores, over the first lattice points of shift 0 at the same level, run in
@@ -260,6 +327,8 @@ def main():
                     help="skip the mixed-vs-FP64 comparison on the s = 400 workload")
     ap.add_argument("--only-mixed", action="store_true",
                     help="run only the mixed-vs-FP64 comparison (prints its JSON object)")
+    ap.add_argument("--only-uneven", action="store_true",
+                    help="run only the uneven-level comparison (prints its JSON object)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path "
@@ -275,6 +344,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.only_mixed:
         print(json.dumps(mixed_vs_fp64(m, torch, dev)), flush=True)
+        return
+    if args.only_uneven:
+        print(json.dumps(uneven(m, torch)), flush=True)
         return
     w = synth.workload("mlqmc_fp64_s100")
     k = w["num_levels"] - 1
@@ -394,6 +466,8 @@ def main():
         out["serving"] = serving(m, torch, w)
         if not args.no_mixed:
             del ctx
+            torch.cuda.empty_cache()
+            out["uneven"] = uneven(m, torch)
             torch.cuda.empty_cache()
             out["mixed"] = mixed_vs_fp64(m, torch, dev)
         log("[bench] extras done; CPU baseline ...")

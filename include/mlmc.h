@@ -54,7 +54,7 @@ typedef enum {
     MLMC_E_INVAL = -1,   /* invalid argument; nothing was written */
     MLMC_E_NOMEM = -2,   /* device memory (HBM) budget exceeded */
     MLMC_E_HIP = -3,     /* a HIP runtime call failed; see mlmc_last_error */
-    MLMC_E_NOCONV = -4,  /* refinement hit max_iters before rtol; outputs written */
+    MLMC_E_NOCONV = -4,  /* refinement stopped above rtol; outputs written */
     MLMC_E_STATE = -5    /* context unusable (e.g. earlier HIP failure) */
 } mlmc_status;
 
@@ -78,11 +78,16 @@ typedef struct {
     int32_t mu0;          /* V-cycles per FMG stage (fixed-cycle mode), >= 1 */
     int32_t mu1, mu2;     /* pre-/post-smoothing red-black sweeps, >= 0, sum >= 1 */
     double rtol;          /* 0: fixed mu0 cycles.  > 0: every stage iterates
-                             V-cycles on the residual until ||f-Au||_2/||f||_2 <= rtol */
+                             V-cycle-preconditioned flexible CG until
+                             ||f-Au||_2/||f||_2 <= rtol, max_iters steps, or
+                             three steps that do not halve the ratio (the
+                             FP64 rounding floor, about eps * condition) */
     int32_t max_iters;    /* refinement cap per stage when rtol > 0 (>= 1) */
-    int32_t precision;    /* MLMC_FP64, or MLMC_MIXED (bf16x3 matrix-core field
-                             stored as FP32, FP32 V-cycles inside FP64 residual
-                             refinement; needs rtol > 0) */
+    int32_t precision;    /* MLMC_FP64, or MLMC_MIXED (field from bf16 digit
+                             products on the matrix cores, see mlmc_field;
+                             a = exp(z) kept in FP32 for FP32 V-cycles and in
+                             FP64 for the residual of the FP64 refinement;
+                             needs rtol > 0) */
     uint32_t qoi_mask;    /* non-empty subset of MLMC_QOI_MEAN | MLMC_QOI_CENTER;
                              nq = number of bits, QoI q in increasing bit order */
     int32_t num_shifts;   /* R, number of random shifts (>= 1 if shifts given) */
@@ -122,7 +127,8 @@ typedef struct {
                                  stage of any sample; fixed mode: mu0 */
     double max_rel_residual;  /* rtol mode: largest final ||f-Au||/||f||;
                                  fixed mode: -1 */
-    int64_t not_converged;    /* rtol mode: samples with a stage at max_iters */
+    int64_t not_converged;    /* rtol mode: samples with a stage that stopped
+                                 above rtol (max_iters or stalled) */
 } mlmc_solve_info;
 
 /* Create a context on `device`: validates cfg, builds the KL mode table and
@@ -175,7 +181,7 @@ mlmc_status mlmc_field(mlmc_ctx ctx, const mlmc_points *pts, double *z_dev,
  *            square (F_{-1} = 0), compensated FP64 sums.
  *   info     host, optional; filling it synchronises the stream.
  * Returns MLMC_E_NOCONV (outputs still written) if info was requested and
- * some sample hit max_iters. */
+ * some sample has a stage that stopped above rtol. */
 mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts,
                            const double *z_dev, double *qoi_dev,
                            double *sums_dev, mlmc_solve_info *info,
@@ -287,7 +293,8 @@ mlmc_status mlmc_profile_end(mlmc_ctx ctx, mlmc_profile_result *out);
  * same level that still fits (continuous batching: requests arriving while
  * other batches run are admitted as slots free up), generates their points,
  * solves the batch (Algorithm 1's SampleAndSolve, all levels <= level) and
- * copies the QoIs to the host.  Every sample's result is bitwise the same
+ * copies the QoIs to the host; batches of different levels run concurrently
+ * on the slots' streams.  Every sample's result is bitwise the same
  * alone and in any batch. */
 typedef struct mlmc_server_s *mlmc_server;
 
@@ -320,19 +327,26 @@ typedef struct {
 } mlmc_server_stats;
 
 /* cfg as for mlmc_create (cfg->max_batch is replaced by slot_samples; lattice
- * points required).  E_INVAL for num_slots < 1, slot_samples < 1 or device < 0. */
+ * points required).  Each slot's workspace holds slot_samples samples of the
+ * finest level; a batch of a coarser level may hold more, as many as fit the
+ * same HBM footprint (mlmc_server_capacity).  The KL tables are held once and
+ * shared by the slots.  E_INVAL for num_slots < 1, slot_samples < 1 or
+ * device < 0. */
 mlmc_status mlmc_server_create(const mlmc_config *cfg, int device, int32_t num_slots,
                                int64_t slot_samples, mlmc_server *out);
 /* Finishes the queued and running requests, then frees everything. */
 mlmc_status mlmc_server_destroy(mlmc_server srv);
 /* Thread-safe, non-blocking.  E_INVAL (nothing queued) for a bad range, a
- * level outside the configuration, more samples than a slot holds, or a NULL
- * qoi_out. */
+ * level outside the configuration, more samples than a slot holds at that
+ * level, or a NULL qoi_out. */
 mlmc_status mlmc_server_submit(mlmc_server srv, const mlmc_request *req);
 /* Up to max_results completed results, oldest first; waits up to wait_ms for
  * the first one (0: no wait).  *count receives the number written. */
 mlmc_status mlmc_server_poll(mlmc_server srv, mlmc_result *out, int32_t max_results,
                              int32_t wait_ms, int32_t *count);
+/* Samples of finest level `level` that one batch (one slot's workspace)
+ * holds; 0 for a NULL server or a level outside the configuration. */
+int64_t mlmc_server_capacity(mlmc_server srv, int32_t level);
 /* Counters and latency percentiles of everything completed so far. */
 mlmc_status mlmc_server_stats_get(mlmc_server srv, mlmc_server_stats *out);
 

@@ -600,7 +600,9 @@ static double norm2(int64_t m, const double *v)
  * (Notay, SIAM J. Sci. Comput. 22 (2000): beta = (z, r - r_old) / (z_old,
  * r_old)), and the residual is recomputed from x at every step.  Returns the
  * number of preconditioner applications; *relres gets the final ratio;
- * *bad = 1 if max_iters was reached first. */
+ * *bad = 1 if the stage stopped above rtol: at max_iters, or because three
+ * steps did not halve the ratio (the accuracy a computed FP64 residual can
+ * show is bounded below by rounding; iterating on does not lower it). */
 static int stage_refine(fmg_state *S, int g, double *x, const double *ones, double *relres,
                         int *bad)
 {
@@ -615,9 +617,11 @@ static int stage_refine(fmg_state *S, int g, double *x, const double *ones, doub
     int it = 0;
     residual(n, S->a[g], ones, x, r);
     double rho = norm2(m, r) / nf;
+    double hist[4];                                    /* ratio after step k at k mod 4 */
+    hist[0] = rho;
     *bad = 0;
     while (rho > S->P->rtol) {
-        if (it >= S->P->max_iters) {
+        if (it >= S->P->max_iters || (it >= 3 && rho > 0.5 * hist[(it - 3) & 3])) {
             *bad = 1;
             break;
         }
@@ -636,6 +640,7 @@ static int stage_refine(fmg_state *S, int g, double *x, const double *ones, doub
         rho = norm2(m, r) / nf;
         rz_old = rz;
         ++it;
+        hist[it & 3] = rho;
     }
     *relres = rho;
     free(r);

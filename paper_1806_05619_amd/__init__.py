@@ -89,7 +89,7 @@ EXPORTS = [
     "mlmc_field", "mlmc_fmg_solve", "mlmc_estimate", "mlmc_kl_modes", "mlmc_fmg_trace",
     "mlmc_status_str", "mlmc_last_error", "mlmc_profile_begin", "mlmc_profile_end",
     "mlmc_server_create", "mlmc_server_destroy", "mlmc_server_submit", "mlmc_server_poll",
-    "mlmc_server_stats_get",
+    "mlmc_server_stats_get", "mlmc_server_capacity",
 ]
 
 _lib = None
@@ -129,6 +129,7 @@ def lib():
         "mlmc_server_submit": (i32, [vp, C.POINTER(mlmc_request)]),
         "mlmc_server_poll": (i32, [vp, C.POINTER(mlmc_result), i32, i32, C.POINTER(i32)]),
         "mlmc_server_stats_get": (i32, [vp, C.POINTER(mlmc_server_stats)]),
+        "mlmc_server_capacity": (i64, [vp, i32]),
         "mlmc_status_str": (C.c_char_p, [i32]),
         "mlmc_last_error": (C.c_char_p, [vp]),
     }
@@ -345,6 +346,10 @@ class Server:
 
     def pending(self):
         return len(self._pending)
+
+    def capacity(self, level):
+        """Samples of `level` one batch holds (requests may not exceed it)."""
+        return int(lib().mlmc_server_capacity(self._h, int(level)))
 
     def stats(self):
         st = mlmc_server_stats()

@@ -53,6 +53,7 @@ struct mlmc_ctx_s {
     double *d_state = nullptr;   // [max shifts][nq][num_levels][4]
     int64_t state_tuples = 0;
     double *d_rho = nullptr;
+    double *d_rho_hist = nullptr;    // [chunk_max][4]: rho after the last four CG steps
     int32_t *d_active = nullptr, *d_iters = nullptr;
     double *d_w = nullptr;           // refinement modes: FP64 stage solutions (pool elements)
     int32_t *d_st_iters = nullptr, *d_st_bad = nullptr;
@@ -184,6 +185,12 @@ int64_t chunk_capacity(mlmc_ctx c, int k)
         cap = std::min(cap, c->fcg_cells / level_cells(G));
     return std::max<int64_t>(1, std::min(cap, c->chunk_max));
 }
+
+}  // namespace
+
+int64_t mlmc::level_capacity(mlmc_ctx c, int k) { return chunk_capacity(c, k); }
+
+namespace {
 
 mlmc_status check_points(mlmc_ctx c, const mlmc_points *p, int64_t *B, int64_t *npts, int *nsh)
 {
@@ -573,6 +580,7 @@ mlmc_status run_fmg_refine(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k,
         v.part = c->d_part;
         v.fs = c->d_fs;
         v.rho = c->d_rho;
+        v.hist = c->d_rho_hist;
         v.active = c->d_active;
         v.iters = c->d_iters;
         const double vec = R.cells(n);   // cells of all samples of the chunk
@@ -581,8 +589,8 @@ mlmc_status run_fmg_refine(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k,
             ProfScope ps(c, st, MLMC_KERNEL_REFINE, vec * (16.0 + R.W), 0.0);
             launch_fcg_resid<T>(st, h.a64[g], h.w[g], n, Bc, h.f[g], c->d_part);
         }
-        launch_fcg_fin_rho(st, c->d_part, n, Bc, c->d_rho, c->d_active, c->d_iters, c->cfg.rtol,
-                           c->cfg.max_iters, 1);
+        launch_fcg_fin_rho(st, c->d_part, n, Bc, c->d_rho, c->d_rho_hist, c->d_active, c->d_iters,
+                           c->cfg.rtol, c->cfg.max_iters, 1);
         for (;;) {
             HIPCHK(c, hipMemcpyAsync(c->h_active, c->d_active, sizeof(int32_t) * Bc,
                                      hipMemcpyDeviceToHost, st));
@@ -652,7 +660,12 @@ const char *mlmc_last_error(mlmc_ctx ctx)
     return ctx->err.c_str();
 }
 
-mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
+}  // extern "C"
+
+// A context whose read-only tables (KL basis or its digits, generating vector,
+// shifts) are those of `parent` when parent is not NULL: same device and the
+// same field, level and lattice configuration; the parent must outlive it.
+mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent, mlmc_ctx *out)
 {
     g_create_error.clear();
     if (!out) { g_create_error = "out is NULL"; return MLMC_E_INVAL; }
@@ -681,6 +694,14 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     if (c.max_batch < 1) return bad("max_batch must be >= 1");
     bool lattice = c.genvec && c.shifts;
     if (lattice && c.num_shifts < 1) return bad("num_shifts must be >= 1 with shifts");
+    if (parent) {
+        const mlmc_config &q = parent->cfg;
+        if (parent->host_only || parent->device != device || q.n0 != c.n0 ||
+            q.num_levels != c.num_levels || q.s != c.s || q.corr_len != c.corr_len ||
+            q.sigma2 != c.sigma2 || q.precision != c.precision ||
+            parent->have_lattice != lattice || (lattice && q.num_shifts != c.num_shifts))
+            return bad("parent context has another field, level or lattice configuration");
+    }
 
     mlmc_ctx ctx = new (std::nothrow) mlmc_ctx_s();
     if (!ctx) { g_create_error = "host allocation failed"; return MLMC_E_NOMEM; }
@@ -780,10 +801,12 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     const int64_t yrows = mixed ? mixed_pad_rows(ctx->chunk_max) : 0;
     const int64_t a64 = mixed ? ctx->pool : 0;
     const bool tile_levels = fused_supported(c.mu1, c.mu2) && Gmax > kLdsMaxLevel;
+    const size_t own_tables = parent ? 0 : 1;
     size_t need = (size_t)ctx->elem * (tile_levels ? 4 : 3) * (size_t)ctx->pool +
-                  (8 * (size_t)ctx->sp + 4) * (size_t)(brows + yrows) + 8 * (size_t)a64 +
-                  sizeof(double) * ((size_t)s * ctx->Mmax + 4 * ctx->fcg_cells + parts + wcap +
-                                    (size_t)ctx->chunk_max * (s + c.num_levels * ctx->nq + 2) +
+                  (8 * (size_t)ctx->sp + 4) * (size_t)(own_tables * brows + yrows) +
+                  8 * (size_t)a64 +
+                  sizeof(double) * (own_tables * (size_t)s * ctx->Mmax + 4 * ctx->fcg_cells + parts + wcap +
+                                    (size_t)ctx->chunk_max * (s + c.num_levels * ctx->nq + 6) +
                                     4 * ctx->state_tuples) +
                   sizeof(int32_t) * 4 * ctx->chunk_max;
     size_t free_b = 0, total_b = 0;
@@ -794,7 +817,7 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
         ctx->err = msg;
         return fail(MLMC_E_NOMEM);
     }
-    CHK(dev_alloc(ctx, &ctx->d_basis, (int64_t)s * ctx->Mmax));
+    if (!parent) CHK(dev_alloc(ctx, &ctx->d_basis, (int64_t)s * ctx->Mmax));
     {
         char *pa = nullptr, *pu = nullptr, *pf = nullptr;
         CHK(dev_alloc(ctx, &pa, ctx->pool * ctx->elem));
@@ -805,10 +828,10 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
         ctx->d_f = (double *)pf;
     }
     for (int i = 0; i < 4 && mixed; ++i) {
-        CHK(dev_alloc(ctx, &ctx->d_bdig[i], brows * ctx->sp));
+        if (!parent) CHK(dev_alloc(ctx, &ctx->d_bdig[i], brows * ctx->sp));
         CHK(dev_alloc(ctx, &ctx->d_ydig[i], yrows * ctx->sp));
     }
-    CHK(dev_alloc(ctx, &ctx->d_bexp, brows));
+    if (!parent) CHK(dev_alloc(ctx, &ctx->d_bexp, brows));
     CHK(dev_alloc(ctx, &ctx->d_yexp, yrows));
     CHK(dev_alloc(ctx, &ctx->d_a64, a64));
     if (tile_levels) {
@@ -827,11 +850,21 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
     CHK(dev_alloc(ctx, &ctx->d_qoi, ctx->chunk_max * c.num_levels * ctx->nq));
     CHK(dev_alloc(ctx, &ctx->d_state, 4 * ctx->state_tuples));
     CHK(dev_alloc(ctx, &ctx->d_rho, ctx->chunk_max));
+    CHK(dev_alloc(ctx, &ctx->d_rho_hist, ctx->fcg_cells > 0 ? 4 * ctx->chunk_max : 0));
     CHK(dev_alloc(ctx, &ctx->d_active, ctx->chunk_max));
     CHK(dev_alloc(ctx, &ctx->d_iters, ctx->chunk_max));
     CHK(hipHostMalloc((void **)&ctx->h_active, sizeof(int32_t) * ctx->chunk_max, hipHostMallocDefault));
     CHK(hipHostMalloc((void **)&ctx->h_iters, sizeof(int32_t) * ctx->chunk_max, hipHostMallocDefault));
     CHK(hipHostMalloc((void **)&ctx->h_rho, sizeof(double) * ctx->chunk_max, hipHostMallocDefault));
+    if (parent) {
+        ctx->d_basis = parent->d_basis;
+        for (int i = 0; i < 4; ++i) ctx->d_bdig[i] = parent->d_bdig[i];
+        ctx->d_bexp = parent->d_bexp;
+        ctx->d_z = parent->d_z;
+        ctx->d_shifts = parent->d_shifts;
+        *out = ctx;
+        return MLMC_OK;
+    }
     if (lattice) {
         CHK(dev_alloc(ctx, &ctx->d_z, s));
         CHK(dev_alloc(ctx, &ctx->d_shifts, (int64_t)c.num_levels * c.num_shifts * s));
@@ -866,14 +899,27 @@ mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
         CHK(hipGetLastError());
     }
     CHK(hipDeviceSynchronize());
-    // the 1-D tables are no longer needed
-    for (void *p : {(void *)d_psi, (void *)d_coef, (void *)d_psi_off, (void *)d_mi, (void *)d_mj}) {
+    // the 1-D tables are no longer needed, nor, in the mixed mode, the FP64
+    // basis (the field is formed from its digits)
+    std::vector<void *> done{d_psi, d_coef, d_psi_off, d_mi, d_mj};
+    if (mixed) {
+        done.push_back(ctx->d_basis);
+        ctx->d_basis = nullptr;
+    }
+    for (void *p : done) {
         (void)hipFree(p);
         ctx->allocs.erase(std::find(ctx->allocs.begin(), ctx->allocs.end(), p));
     }
 #undef CHK
     *out = ctx;
     return MLMC_OK;
+}
+
+extern "C" {
+
+mlmc_status mlmc_create(const mlmc_config *cfg, int device, mlmc_ctx *out)
+{
+    return create_ctx(cfg, device, nullptr, out);
 }
 
 mlmc_status mlmc_destroy(mlmc_ctx ctx)

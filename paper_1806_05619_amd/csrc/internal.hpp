@@ -11,6 +11,12 @@
 
 namespace mlmc {
 
+// Host-side helpers shared by the C entry points (host.hip) and the serving
+// loop (server.hip).
+mlmc_status create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent, mlmc_ctx *out);
+// samples of finest MLMC level k that one pass over the workspace holds
+int64_t level_capacity(mlmc_ctx c, int k);
+
 constexpr int kMaxMgLevels = 12;   // n_g = 2^(g+1) <= 4096
 constexpr int kBlock = 256;
 constexpr int kLdsMaxLevel = 4;    // grids up to 32^2 run LDS-resident (one workgroup per sample)
@@ -136,15 +142,18 @@ struct FcgBufs {
     T *p0, *p1;             // search directions
     double *x0, *x1;        // iterates
     double *part, *fs, *rho;
+    double *hist;           // rho after each of the last four steps, 4 per sample
     int32_t *active, *iters;
 };
 // r = 1 - A x0 (every sample), f = T(r), partial ||r||^2
 template <typename T>
 void launch_fcg_resid(hipStream_t st, const double *a, const double *x, int n, int64_t Bc, T *f,
                       double *part);
-// rho = ||r||/||1||; active = rho > rtol && iters < max_iters; iters counts steps
+// rho = ||r||/||1||; active = rho > rtol && iters < max_iters and the last
+// three steps halved rho; iters counts steps
 void launch_fcg_fin_rho(hipStream_t st, const double *part, int n, int64_t Bc, double *rho,
-                        int32_t *active, int32_t *iters, double rtol, int max_iters, int first);
+                        double *hist, int32_t *active, int32_t *iters, double rtol, int max_iters,
+                        int first);
 // one step after z = B r: beta, p, alpha, x, new residual, convergence flags
 template <typename T>
 void launch_fcg_step(hipStream_t st, const FcgBufs<T> &v, int n, int64_t Bc, double rtol,

@@ -773,6 +773,7 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
         else lds_prolong<LT>(w_s + LdsHier<GS>::off(g - 1), xg, n, false);
         int it = 0;
         double rho, rz_old = 1.0;
+        double rh0 = 0.0, rh1 = 0.0, rh2 = 0.0;   // rho of the last three steps
         for (;;) {
             // r = 1 - A x, staged as the T right-hand side of the preconditioner
             double s = 0.0, c = 0.0;
@@ -789,7 +790,12 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
                 }
             }
             rho = sqrt(lds_reduce<LT>(s, c, red_s)) / (double)n;   // ||1||_2 = n
-            if (rho <= rtol || it >= max_iters || g == 0) break;
+            // attainable accuracy: stop once three steps have not halved rho
+            const bool stalled = it >= 3 && rho > 0.5 * rh2;
+            rh2 = rh1;
+            rh1 = rh0;
+            rh0 = rho;
+            if (rho <= rtol || it >= max_iters || g == 0 || stalled) break;
             V.run(g, fg);                                       // z = B r
             double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0;
 #pragma unroll
@@ -951,6 +957,7 @@ __global__ __launch_bounds__(256) void k_fcg_resid(const double *__restrict__ a,
 // and iters becomes the number of the step about to be taken.
 __global__ __launch_bounds__(256) void k_fcg_fin_rho(const double *__restrict__ part, int n,
                                                      int64_t Bc, double *__restrict__ rho,
+                                                     double *__restrict__ hist,
                                                      int32_t *__restrict__ active,
                                                      int32_t *__restrict__ iters, double rtol,
                                                      int max_iters, int first)
@@ -962,7 +969,11 @@ __global__ __launch_bounds__(256) void k_fcg_fin_rho(const double *__restrict__ 
     const double v = sqrt(fold_partials<1>(part, b, nch, 0)) / (double)n;
     if ((threadIdx.x & 63) == 0) {
         const int it = first ? 0 : iters[b];
-        const int go = v > rtol && it < max_iters;
+        // attainable accuracy: stop once three steps have not halved rho
+        // (hist[4b + k mod 4] holds rho after step k)
+        const bool stalled = it >= 3 && v > 0.5 * hist[4 * b + ((it - 3) & 3)];
+        const int go = v > rtol && it < max_iters && !stalled;
+        hist[4 * b + (it & 3)] = v;
         rho[b] = v;
         active[b] = go;
         iters[b] = it + go;
@@ -1228,10 +1239,11 @@ void launch_fcg_resid(hipStream_t st, const double *a, const double *x, int n, i
 }
 
 void launch_fcg_fin_rho(hipStream_t st, const double *part, int n, int64_t Bc, double *rho,
-                        int32_t *active, int32_t *iters, double rtol, int max_iters, int first)
+                        double *hist, int32_t *active, int32_t *iters, double rtol, int max_iters,
+                        int first)
 {
     hipLaunchKernelGGL(k_fcg_fin_rho, dim3(blocks_of(Bc, 4)), dim3(256), 0, st, part, n, Bc, rho,
-                       active, iters, rtol, max_iters, first);
+                       hist, active, iters, rtol, max_iters, first);
 }
 
 template <typename T>
@@ -1249,7 +1261,7 @@ void launch_fcg_step(hipStream_t st, const FcgBufs<T> &v, int n, int64_t Bc, dou
     hipLaunchKernelGGL(k_fcg_fin_alpha, dim3(ns), dim3(256), 0, st, v.part, n, Bc, v.fs, v.active);
     hipLaunchKernelGGL((k_fcg_x<T>), dim3(nb), dim3(256), 0, st, v.a64, v.x0, v.x1, v.p0, v.p1, v.f,
                        n, Bc, v.fs, v.part, v.active, v.iters);
-    hipLaunchKernelGGL(k_fcg_fin_rho, dim3(ns), dim3(256), 0, st, v.part, n, Bc, v.rho, v.active,
+    hipLaunchKernelGGL(k_fcg_fin_rho, dim3(ns), dim3(256), 0, st, v.part, n, Bc, v.rho, v.hist, v.active,
                        v.iters, rtol, max_iters, 0);
 }
 

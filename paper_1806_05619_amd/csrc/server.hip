@@ -1,10 +1,12 @@
 // Serving loop: a FIFO of (level, lattice range, shift range) solve requests,
 // served by a fixed set of slots.  Each slot is one context (its own
-// workspace, sized at create), one HIP stream and one host thread; a free slot
-// takes the oldest queued request and every queued request of the same level
-// that still fits, generates their points into one explicit batch, solves it
-// (the SampleAndSolve body of Algorithm 1) and hands the QoIs back.  Slots run
-// concurrently, so batches of different levels overlap on the device.
+// workspace, sized at create; the KL tables are the first slot's, held once),
+// one HIP stream and one host thread; a free slot takes the oldest queued
+// request and every queued request of the same level that still fits the
+// workspace at that level, generates their points into one explicit batch,
+// solves it (the SampleAndSolve body of Algorithm 1) and hands the QoIs back.
+// Slots run concurrently, so batches of different levels overlap on the
+// device.
 #include "internal.hpp"
 
 #include <algorithm>
@@ -47,6 +49,7 @@ struct mlmc_server_s {
     int device = 0;
     int nq = 1;
     int64_t slot_samples = 0;
+    std::vector<int64_t> cap;     // samples per batch at each level (HBM footprint)
     std::vector<Slot> slots;
 
     std::mutex mu;
@@ -106,7 +109,7 @@ void mlmc_server_s::work(int slot_index)
             if (queue.empty()) return;          // stopping and drained
             level = queue.front().req.level;
             for (auto it = queue.begin(); it != queue.end();) {
-                if (it->req.level == level && total + it->samples <= slot_samples) {
+                if (it->req.level == level && total + it->samples <= cap[level]) {
                     total += it->samples;
                     batch.push_back(*it);
                     it = queue.erase(it);
@@ -140,6 +143,23 @@ void mlmc_server_s::work(int slot_index)
     }
 }
 
+namespace {
+
+// slots in reverse order: the first slot's context owns the shared tables
+void free_slots(mlmc_server srv)
+{
+    for (auto it = srv->slots.rbegin(); it != srv->slots.rend(); ++it) {
+        if (it->q_host) (void)hipHostFree(it->q_host);
+        if (it->q_dev) (void)hipFree(it->q_dev);
+        if (it->y_dev) (void)hipFree(it->y_dev);
+        if (it->stream) (void)hipStreamDestroy(it->stream);
+        if (it->ctx) mlmc_destroy(it->ctx);
+    }
+    srv->slots.clear();
+}
+
+}  // namespace
+
 extern "C" {
 
 mlmc_status mlmc_server_create(const mlmc_config *cfg, int device, int32_t num_slots,
@@ -157,13 +177,20 @@ mlmc_status mlmc_server_create(const mlmc_config *cfg, int device, int32_t num_s
     srv->slot_samples = slot_samples;
     srv->slots.resize(num_slots);
     mlmc_status st = MLMC_OK;
+    int64_t cap_max = 1;
     for (auto &sl : srv->slots) {
-        st = mlmc_create(&srv->cfg, device, &sl.ctx);
+        st = mlmc::create_ctx(&srv->cfg, device, srv->slots[0].ctx, &sl.ctx);
         if (st) break;
-        srv->nq = mlmc_num_qoi(sl.ctx);
-        const size_t qsize = sizeof(double) * (size_t)slot_samples * cfg->num_levels * srv->nq;
+        if (srv->cap.empty()) {      // the same workspace in every slot
+            srv->nq = mlmc_num_qoi(sl.ctx);
+            for (int l = 0; l < cfg->num_levels; ++l) {
+                srv->cap.push_back(mlmc::level_capacity(sl.ctx, l));
+                cap_max = std::max(cap_max, srv->cap.back());
+            }
+        }
+        const size_t qsize = sizeof(double) * (size_t)cap_max * cfg->num_levels * srv->nq;
         if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&sl.stream) != hipSuccess ||
-            hipMalloc((void **)&sl.y_dev, sizeof(double) * (size_t)slot_samples * cfg->s) !=
+            hipMalloc((void **)&sl.y_dev, sizeof(double) * (size_t)cap_max * cfg->s) !=
                 hipSuccess ||
             hipMalloc((void **)&sl.q_dev, qsize) != hipSuccess ||
             hipHostMalloc((void **)&sl.q_host, qsize, hipHostMallocDefault) != hipSuccess) {
@@ -172,13 +199,7 @@ mlmc_status mlmc_server_create(const mlmc_config *cfg, int device, int32_t num_s
         }
     }
     if (st) {
-        for (auto &sl : srv->slots) {
-            if (sl.q_host) (void)hipHostFree(sl.q_host);
-            if (sl.q_dev) (void)hipFree(sl.q_dev);
-            if (sl.y_dev) (void)hipFree(sl.y_dev);
-            if (sl.stream) (void)hipStreamDestroy(sl.stream);
-            if (sl.ctx) mlmc_destroy(sl.ctx);
-        }
+        free_slots(srv);
         delete srv;
         return st;
     }
@@ -197,13 +218,7 @@ mlmc_status mlmc_server_destroy(mlmc_server srv)
     srv->cv_work.notify_all();
     for (auto &sl : srv->slots)
         if (sl.worker.joinable()) sl.worker.join();
-    for (auto &sl : srv->slots) {
-        (void)hipHostFree(sl.q_host);
-        (void)hipFree(sl.q_dev);
-        (void)hipFree(sl.y_dev);
-        (void)hipStreamDestroy(sl.stream);
-        mlmc_destroy(sl.ctx);
-    }
+    free_slots(srv);
     delete srv;
     return MLMC_OK;
 }
@@ -217,7 +232,7 @@ mlmc_status mlmc_server_submit(mlmc_server srv, const mlmc_request *req)
         req->shift_end <= req->shift_begin || req->shift_end > c.num_shifts)
         return MLMC_E_INVAL;
     const int64_t samples = (req->n_end - req->n_begin) * (req->shift_end - req->shift_begin);
-    if (samples > srv->slot_samples) return MLMC_E_INVAL;
+    if (samples > srv->cap[req->level]) return MLMC_E_INVAL;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         if (srv->stopping) return MLMC_E_STATE;
@@ -247,6 +262,12 @@ mlmc_status mlmc_server_poll(mlmc_server srv, mlmc_result *out, int32_t max_resu
     }
     *count = n;
     return MLMC_OK;
+}
+
+int64_t mlmc_server_capacity(mlmc_server srv, int32_t level)
+{
+    if (!srv || level < 0 || level >= srv->cfg.num_levels) return 0;
+    return srv->cap[level];
 }
 
 mlmc_status mlmc_server_stats_get(mlmc_server srv, mlmc_server_stats *out)

@@ -103,6 +103,22 @@ WORKLOADS = {
         qoi=("mean", "center"), sampling="lattice", lattice_log2n=12,
         num_shifts=16, seed=3,
     ),
+    # uneven levels: 4^2 .. 2048^2 with 2^(16-l) samples on level l (65536 ..
+    # 128, 130944 in all), the mixed path refined to 1e-10
+    "uneven_mixed_s400": dict(
+        n0=4, num_levels=10, s=400, corr_len=0.1, sigma2=2.0,
+        mu0=1, mu1=2, mu2=2, rtol=1e-10, max_iters=60, precision="mixed",
+        qoi=("mean", "center"), sampling="lattice", lattice_log2n=12,
+        num_shifts=16, seed=4, samples_per_level=tuple(1 << (16 - l) for l in range(10)),
+    ),
+    # serving: requests of an adaptive MLQMC driver, s = 1000, lambda 0.05,
+    # 4^2 .. 2048^2, FP64 with 2 V(2,2) cycles per FMG stage
+    "serving_fp64_s1000": dict(
+        n0=4, num_levels=10, s=1000, corr_len=0.05, sigma2=1.0,
+        mu0=2, mu1=2, mu2=2, rtol=0.0, max_iters=0, precision="fp64",
+        qoi=("mean", "center"), sampling="lattice", lattice_log2n=16,
+        num_shifts=16, seed=5,
+    ),
 }
 
 

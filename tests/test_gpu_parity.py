@@ -424,3 +424,37 @@ def test_adaptive_driver_on_gpu():
         res[eps] = r
     a, b = res[4e-3], res[2e-3]
     assert abs(a["q_bar"] - b["q_bar"]) <= 3 * (4e-3 + 2e-3)
+
+
+@pytest.mark.parametrize("precision", [m.MLMC_FP64, m.MLMC_MIXED])
+def test_unattainable_rtol_stops_at_rounding_floor(oracle_mod, precision):
+    """rtol below what an FP64 residual can show: every stage, in the
+    LDS-resident kernels (<= 32^2) and in the CG passes (64^2, 128^2), stops
+    once three steps fail to halve the residual ratio, long before max_iters;
+    the samples are reported as not converged and the QoIs are those of the
+    direct solve."""
+    dev = _dev()
+    w = synth.workload("mlqmc_fp64_s100")
+    L1 = 6
+    ctx = m.Context(w["n0"], L1, w["s"], w["corr_len"], w["sigma2"], mu0=1, mu1=2, mu2=2,
+                    rtol=1e-30, max_iters=200, precision=precision,
+                    qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
+                    genvec=synth.korobov_vector(w["seed"], w["s"]),
+                    shifts=synth.shift_table(w["seed"], L1, w["num_shifts"], w["s"]),
+                    max_batch=32, device=0)
+    P = _oracle_problem(oracle_mod, dict(w, num_levels=L1), mu0=1, rtol=1e-30, max_iters=200)
+    k = L1 - 1
+    B = 12
+    pts = ctx.lattice(k, 0, B, 2, 3)
+    q, _, info = _solve(ctx, pts, k + 1, info=True)
+    print(f"\nprecision {precision}: {info}", flush=True)
+    assert info["status"] == m.MLMC_E_NOCONV and info["not_converged"] == B
+    assert 4 <= info["max_iters_used"] < 60
+    assert info["max_rel_residual"] <= 1e-12
+    z = synth.korobov_vector(w["seed"], w["s"])
+    D = synth.shift_table(w["seed"], L1, w["num_shifts"], w["s"])
+    _, ys = oracle_mod.points(z, D[k, 2], 0, 3)
+    tol = 1e-11 if precision == m.MLMC_FP64 else 1e-8
+    for b in range(3):
+        qo = P.sample(k, ys[b], 1)[:, : ctx.nq]
+        assert _rel(q[b], qo) <= tol, b

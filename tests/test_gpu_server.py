@@ -97,8 +97,14 @@ def test_server_rejects_bad_requests_and_keeps_serving():
     w = synth.workload("mlqmc_fp64_s100")
     kw = _kw(w, m.MLMC_FP64)
     with m.Server(**kw, num_slots=1, slot_samples=32, device=0) as srv:
+        # footprint admission: the finest level holds slot_samples, coarser
+        # levels as many as fit the same workspace
+        caps = [srv.capacity(l) for l in range(w["num_levels"])]
+        assert caps[-1] == 32 and all(a >= b for a, b in zip(caps, caps[1:])) and caps[0] > 32
+        assert srv.capacity(7) == 0 and srv.capacity(-1) == 0
         for bad in [(7, 0, 1, 0, 1), (-1, 0, 1, 0, 1), (0, 5, 5, 0, 1), (0, 0, 1, 3, 3),
-                    (0, 0, 1, 15, 17), (0, 0, 33, 0, 1), (0, 0, 17, 0, 2)]:
+                    (0, 0, 1, 15, 17), (6, 0, 33, 0, 1), (6, 0, 17, 0, 2),
+                    (5, 0, caps[5] + 1, 0, 1)]:
             with pytest.raises(m.MlmcError):
                 srv.submit(*bad)
         tag = srv.submit(2, 0, 32, 1, 2)

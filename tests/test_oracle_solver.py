@@ -239,3 +239,20 @@ def test_vcycle_convergence_is_mesh_independent(oracle_mod):
     assert r["status"] == 0
     its = r["iters"][1:]
     assert np.all(its <= 13) and its.max() - its.min() <= 2, its
+
+
+def test_fmg_rtol_stops_at_rounding_floor(oracle_mod):
+    """An unattainable rtol: every stage stops once three CG steps fail to
+    halve the residual ratio, well before max_iters, flagged as not
+    converged; the iterate is then as accurate as FP64 allows (the band
+    Cholesky solve agrees to 1e-12)."""
+    P = oracle_mod.Problem(4, 5, 100, 0.3, 1.0, mu0=1, mu1=2, mu2=2, rtol=1e-30, max_iters=200)
+    k = 4
+    for z in _lognormal_fields(oracle_mod, P, k, 2, 31):
+        fm = P.sample_from_field(k, z, 0)
+        dr = P.sample_from_field(k, z, 1)
+        assert fm["status"] != 0
+        assert np.all(fm["iters"][1:] >= 4) and np.all(fm["iters"] < 60), fm["iters"]
+        assert np.all(fm["relres"][1:] <= 1e-13), fm["relres"]
+        rel = np.abs(fm["qoi"] - dr["qoi"]) / np.abs(dr["qoi"])
+        assert np.max(rel) <= 1e-12, rel
