@@ -134,87 +134,117 @@ def mixed_vs_fp64(m, torch, dev, max_batch=64, min_seconds=0.25):
     return out
 
 
-def serving(m, torch, w, seconds=3.0, rate=400.0, req_points=64, slots=4, slot_samples=4096):
-    """The serving loop (mlmc_server) on the s = 100 workload: requests of
-    `req_points` lattice points of one shift on level l, l drawn with
-    probability proportional to 2^-l (an MLQMC run asks for fewer samples on
-    finer levels).  Open loop: Poisson arrivals at `rate` requests/s for
-    `seconds`, latency percentiles from submit to QoIs on the host.
-    Saturated: 4000 such requests submitted at once, against the same
-    requests solved one call at a time on one context."""
+def serving(m, torch, seconds=4.0, rate=500.0, clients=4, slots=4, slot_samples=64,
+            eps=1e-4):
+    """The serving loop (mlmc_server) on the s = 1000 workload (lambda 0.05,
+    4^2 .. 2048^2, FP64, 2 V(2,2) per FMG stage).  Open loop: jobs arrive as a
+    Poisson process, each an adaptive MLQMC estimate (Algorithm 1) to RMSE
+    `eps` on its own group of 16 random shifts, whose (level, lattice range,
+    shift) requests go through the server while other jobs run; the job rate
+    is set so that requests arrive at `rate` per second on average.  Reported:
+    request latency p50/p99 (submit to QoIs on the host), job latency,
+    samples/s.  Saturated: 4000 single-shift requests of 64 points (level l
+    with probability ~2^-l) submitted at once, against the same requests
+    solved one call at a time on one context."""
+    import threading
     import synth
-    L1 = w["num_levels"]
-    p = 2.0 ** -np.arange(L1)
-    p /= p.sum()
-    rng = np.random.default_rng(11)
+    from paper_1806_05619_amd.driver import ServerSampler, mg_mlqmc
+    w = synth.workload("serving_fp64_s1000")
+    L1, R = w["num_levels"], w["num_shifts"]
     kw = dict(n0=w["n0"], num_levels=L1, s=w["s"], corr_len=w["corr_len"], sigma2=w["sigma2"],
               mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"], max_iters=w["max_iters"],
               precision=m.MLMC_FP64, qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
               genvec=synth.korobov_vector(w["seed"], w["s"]),
-              shifts=synth.shift_table(w["seed"], L1, w["num_shifts"], w["s"]))
-
-    def draw(n):
-        lv = rng.choice(L1, size=n, p=p)
-        r = rng.integers(0, w["num_shifts"], size=n)
-        n0 = rng.integers(0, 1 << 20, size=n)
-        return [(int(a), int(b), int(b) + req_points, int(c), int(c) + 1) for a, b, c in zip(lv, n0, r)]
-
-    out = dict(request=f"{req_points} lattice points of one shift, level l with probability "
-                       f"~2^-l over {w['n0']}^2..{w['n0'] << (L1 - 1)}^2",
-               slots=slots, slot_samples=slot_samples)
-
-    def drain(srv, lat):
-        while srv.pending():
-            lat += [r["latency_ms"] for r in srv.poll(wait_ms=50)]
-
+              shifts=synth.shift_table(w["seed"], L1, R * clients, w["s"]))
+    rng = np.random.default_rng(11)
+    out = dict(workload="serving_fp64_s1000: s = 1000, lambda 0.05, sigma^2 1, levels 4^2..2048^2, "
+                        "FP64, 2 V(2,2) cycles per FMG stage",
+               slots=slots, slot_samples=slot_samples, eps=eps)
     with m.Server(**kw, num_slots=slots, slot_samples=slot_samples, device=0) as srv:
-        for r in draw(4 * slots):          # warm up every slot
-            srv.submit(*r)
-        drain(srv, [])
+        def job(c):
+            t0 = time.perf_counter()
+            r = mg_mlqmc(ServerSampler(srv, R, first_shift=R * (c % clients)), eps,
+                         max_level=L1 - 1, max_points=1 << w["lattice_log2n"])
+            return time.perf_counter() - t0, r
+
+        job(0)                                   # warm-up; calibrates requests per job
+        s0 = srv.stats()
+        job(1)
+        per_job = srv.stats()["requests"] - s0["requests"]
+        job_rate = rate / max(per_job, 1)
         base = srv.stats()
-        lat = []
-        t0 = t_next = time.perf_counter()
-        while time.perf_counter() < t0 + seconds:
-            now = time.perf_counter()
-            while t_next <= now:
-                srv.submit(*draw(1)[0])
-                t_next += rng.exponential(1.0 / rate)
-            lat += [r["latency_ms"] for r in srv.poll(wait_ms=0)]
-            time.sleep(max(0.0, min(t_next - time.perf_counter(), 0.002)))
-        drain(srv, lat)
-        dt = time.perf_counter() - t0
-        st = srv.stats()
-        lat = np.array(lat)
-        out["open_loop"] = dict(rate_per_s=rate, seconds=seconds, requests=len(lat),
-                                samples_per_s=(st["samples"] - base["samples"]) / dt,
-                                batches=st["batches"] - base["batches"],
-                                p50_ms=float(np.percentile(lat, 50)),
-                                p99_ms=float(np.percentile(lat, 99)), max_ms=float(lat.max()))
-        reqs = draw(4000)
-        lat = []
+        srv.take_latencies()
+        results, threads = [], []
+        lock = threading.Lock()
+
+        def run(c):
+            res = job(c)
+            with lock:
+                results.append(res)
+
         t0 = time.perf_counter()
-        for r in reqs:
-            srv.submit(*r)
-        drain(srv, lat)
+        t_next, c = t0, 0
+        while t_next < t0 + seconds:
+            time.sleep(max(0.0, t_next - time.perf_counter()))
+            th = threading.Thread(target=run, args=(c,))
+            th.start()
+            threads.append(th)
+            c += 1
+            t_next += rng.exponential(1.0 / job_rate)
+        for th in threads:
+            th.join()
+        dt = max(time.perf_counter() - t0, seconds)   # arrival window, or longer if a job ran on
+        st = srv.stats()
+        rl = np.array(srv.take_latencies())
+        jl = np.array([r[0] for r in results]) * 1e3
+        q = np.array([r[1]["q_bar"] for r in results])
+        out["open_loop"] = dict(
+            request_rate_per_s=(st["requests"] - base["requests"]) / dt, jobs=len(results),
+            requests_per_job=per_job, seconds=dt,
+            samples_per_s=(st["samples"] - base["samples"]) / dt,
+            batches=st["batches"] - base["batches"],
+            request_p50_ms=float(np.percentile(rl, 50)), request_p99_ms=float(np.percentile(rl, 99)),
+            request_max_ms=float(rl.max()),
+            job_p50_ms=float(np.percentile(jl, 50)), job_p99_ms=float(np.percentile(jl, 99)),
+            all_converged=all(r[1]["converged"] for r in results),
+            finest_level=max(r[1]["L"] for r in results),
+            estimate_mean=float(q.mean()), estimate_spread=float(q.std()),
+            estimate_sd_predicted=float(np.mean([np.sqrt(r[1]["var"]) for r in results])))
+        log(f"[bench] serving (s = 1000): {len(results)} jobs, "
+            f"{out['open_loop']['request_rate_per_s']:.0f} req/s, request p50 "
+            f"{np.percentile(rl, 50):.2f} ms p99 {np.percentile(rl, 99):.2f} ms, job p50 "
+            f"{out['open_loop']['job_p50_ms']:.0f} ms")
+
+        def draw(n):
+            p = 2.0 ** -np.arange(L1)
+            lv = rng.choice(L1, size=n, p=p / p.sum())
+            r = rng.integers(0, R, size=n)
+            n0 = rng.integers(0, 1 << 20, size=n)
+            return [(int(a), int(b), int(b) + 64, int(c), int(c) + 1) for a, b, c in zip(lv, n0, r)]
+
+        reqs = draw(4000)
+        s1 = srv.stats()
+        t0 = time.perf_counter()
+        tags = [srv.submit(*q) for q in reqs]
+        res = srv.collect(tags)
         dt = time.perf_counter() - t0
-        out["saturated"] = dict(requests=len(reqs), samples_per_s=len(reqs) * req_points / dt,
-                                batches=srv.stats()["batches"] - st["batches"],
+        lat = np.array([r["latency_ms"] for r in res])
+        out["saturated"] = dict(requests=len(reqs), samples_per_s=len(reqs) * 64 / dt,
+                                batches=srv.stats()["batches"] - s1["batches"],
                                 p50_ms=float(np.percentile(lat, 50)),
                                 p99_ms=float(np.percentile(lat, 99)))
-    ctx = m.Context(**kw, max_batch=req_points, device=0)
-    q = torch.zeros((req_points, L1, 2), dtype=torch.float64, device="cuda:0")
+    ctx = m.Context(**kw, max_batch=64, device=0)
+    qd = torch.zeros((64, L1, 2), dtype=torch.float64, device="cuda:0")
     t0 = time.perf_counter()
     for r in reqs[:400]:
-        ctx.fmg_solve(ctx.lattice(*r), qoi=q)
-        q.cpu()
+        ctx.fmg_solve(ctx.lattice(*r), qoi=qd)
+        qd.cpu()
     dt = time.perf_counter() - t0
-    out["one_call_per_request_samples_per_s"] = 400 * req_points / dt
+    del ctx
+    out["one_call_per_request_samples_per_s"] = 400 * 64 / dt
     out["saturated"]["speedup_over_one_call_per_request"] = (out["saturated"]["samples_per_s"] /
                                                              out["one_call_per_request_samples_per_s"])
-    del ctx
-    log(f"[bench] serving: open loop {rate:.0f} req/s p50 {out['open_loop']['p50_ms']:.2f} ms "
-        f"p99 {out['open_loop']['p99_ms']:.2f} ms; saturated "
-        f"{out['saturated']['samples_per_s']:.0f} samples/s "
+    log(f"[bench] serving saturated: {out['saturated']['samples_per_s']:.0f} samples/s "
         f"(x{out['saturated']['speedup_over_one_call_per_request']:.1f} over one call per request)")
     return out
 
@@ -327,6 +357,8 @@ def main():
                     help="skip the mixed-vs-FP64 comparison on the s = 400 workload")
     ap.add_argument("--only-mixed", action="store_true",
                     help="run only the mixed-vs-FP64 comparison (prints its JSON object)")
+    ap.add_argument("--only-serving", action="store_true",
+                    help="run only the serving-loop measurement (prints its JSON object)")
     ap.add_argument("--only-uneven", action="store_true",
                     help="run only the uneven-level comparison (prints its JSON object)")
     args = ap.parse_args()
@@ -347,6 +379,9 @@ def main():
         return
     if args.only_uneven:
         print(json.dumps(uneven(m, torch)), flush=True)
+        return
+    if args.only_serving:
+        print(json.dumps(serving(m, torch)), flush=True)
         return
     w = synth.workload("mlqmc_fp64_s100")
     k = w["num_levels"] - 1
@@ -463,7 +498,7 @@ def main():
             lat[f"level{k}_n{nreq}"] = dict(p50_ms=float(np.percentile(times, 50)),
                                             p99_ms=float(np.percentile(times, 99)))
         out["latency"] = lat
-        out["serving"] = serving(m, torch, w)
+        out["serving"] = serving(m, torch)
         if not args.no_mixed:
             del ctx
             torch.cuda.empty_cache()

@@ -15,6 +15,8 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import threading
+import time
 
 import numpy as np
 
@@ -311,24 +313,28 @@ class Server:
         self.nq = bin(int(qoi_mask) & 3).count("1")
         self.slot_samples = int(slot_samples)
         self._pending = {}
+        self._done = {}
+        self._lat = []
         self._next_tag = 0
+        self._lock = threading.RLock()
 
     def submit(self, level, n_begin, n_end, shift_begin=0, shift_end=1, tag=None):
         """Queue lattice points [n_begin, n_end) of shifts [shift_begin,
         shift_end) on finest level `level`; returns the request's tag."""
-        if tag is None:
-            tag = self._next_tag
-        tag = int(tag)
-        if tag in self._pending:
-            raise ValueError(f"tag {tag} is still pending")
-        self._next_tag = max(self._next_tag, tag + 1)
-        B = max(0, (int(n_end) - int(n_begin)) * (int(shift_end) - int(shift_begin)))
-        out = np.zeros((B, int(level) + 1, self.nq), dtype=np.float64)
-        req = mlmc_request(int(level), int(shift_begin), int(shift_end), int(n_begin), int(n_end),
-                           tag, out.ctypes.data if B else None)
-        _check(lib().mlmc_server_submit(self._h, C.byref(req)))
-        self._pending[tag] = out
-        return tag
+        with self._lock:
+            if tag is None:
+                tag = self._next_tag
+            tag = int(tag)
+            if tag in self._pending or tag in self._done:
+                raise ValueError(f"tag {tag} is still pending")
+            self._next_tag = max(self._next_tag, tag + 1)
+            B = max(0, (int(n_end) - int(n_begin)) * (int(shift_end) - int(shift_begin)))
+            out = np.zeros((B, int(level) + 1, self.nq), dtype=np.float64)
+            req = mlmc_request(int(level), int(shift_begin), int(shift_end), int(n_begin),
+                               int(n_end), tag, out.ctypes.data if B else None)
+            _check(lib().mlmc_server_submit(self._h, C.byref(req)))
+            self._pending[tag] = out
+            return tag
 
     def poll(self, max_results=256, wait_ms=0):
         """Completed requests, oldest first: dicts with the result fields and
@@ -337,15 +343,38 @@ class Server:
         n = C.c_int32(0)
         _check(lib().mlmc_server_poll(self._h, buf, int(max_results), int(wait_ms), C.byref(n)))
         res = []
-        for r in buf[: n.value]:
-            res.append(dict(tag=int(r.tag), status=int(r.status), level=int(r.level),
-                            samples=int(r.samples), batch_samples=int(r.batch_samples),
-                            queued_ms=r.queued_ms, latency_ms=r.latency_ms,
-                            qoi=self._pending.pop(int(r.tag))))
+        with self._lock:
+            for r in buf[: n.value]:
+                res.append(dict(tag=int(r.tag), status=int(r.status), level=int(r.level),
+                                samples=int(r.samples), batch_samples=int(r.batch_samples),
+                                queued_ms=r.queued_ms, latency_ms=r.latency_ms,
+                                qoi=self._pending.pop(int(r.tag))))
+                self._lat.append(r.latency_ms)
         return res
 
+    def take_latencies(self):
+        """Latencies (ms) of the requests polled since the last call."""
+        with self._lock:
+            lat, self._lat = self._lat, []
+        return lat
+
+    def collect(self, tags, timeout_s=600.0):
+        """Wait for the results of `tags` (safe from several threads: results
+        polled for other callers are kept for them); returns them in order."""
+        t0 = time.monotonic()
+        while True:
+            with self._lock:
+                for r in self.poll(max_results=1024, wait_ms=0):
+                    self._done[r["tag"]] = r
+                if all(t in self._done for t in tags):
+                    return [self._done.pop(t) for t in tags]
+            if time.monotonic() - t0 > timeout_s:
+                raise TimeoutError(f"{len(tags)} requests not completed in {timeout_s} s")
+            time.sleep(2e-4)
+
     def pending(self):
-        return len(self._pending)
+        with self._lock:
+            return len(self._pending)
 
     def capacity(self, level):
         """Samples of `level` one batch holds (requests may not exceed it)."""

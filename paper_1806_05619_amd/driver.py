@@ -46,6 +46,36 @@ class GpuSampler:
         return s.cpu().numpy()          # synchronising copy: the timer sees the solve
 
 
+class ServerSampler:
+    """SampleAndSolve through the serving loop (mlmc_server): the new lattice
+    points of every shift become requests (split to the server's capacity at
+    the level), which the server batches with whatever else is queued; the
+    level-difference sums are formed on the host from the returned QoIs."""
+
+    def __init__(self, server, num_shifts, first_shift=0):
+        self.srv = server
+        self.R = int(num_shifts)
+        self.r0 = int(first_shift)      # shifts r0 .. r0+R-1 of the server's table
+        self.nq = server.nq
+
+    def sample(self, level, n_begin, n_end):
+        cap = self.srv.capacity(level)
+        reqs = [(level, a, min(a + cap, n_end), self.r0 + r, self.r0 + r + 1)
+                for r in range(self.R) for a in range(n_begin, n_end, cap)]
+        tags = [self.srv.submit(*q) for q in reqs]
+        sums = np.zeros((self.R, self.nq, level + 1, 2))
+        for q, res in zip(reqs, self.srv.collect(tags)):
+            if res["status"] != 0:
+                raise RuntimeError(f"request {q} failed with status {res['status']}")
+            F = res["qoi"]                                   # [B][level+1][nq]
+            d = F.copy()
+            d[:, 1:, :] -= F[:, :-1, :]                      # F_l - F_(l-1), F_(-1) = 0
+            r = q[3] - self.r0
+            sums[r, :, :, 0] += d.sum(axis=0).T
+            sums[r, :, :, 1] += (d * d).sum(axis=0).T
+        return sums
+
+
 def _alpha_fit(ubar):
     """Least-squares slope of -log2 |Upsilon-bar_l| over l = 1..L (at least 0.5)."""
     lv = np.arange(1, len(ubar))
