@@ -72,3 +72,47 @@ def test_stops_when_levels_or_points_run_out():
     assert not r["converged"] and r["L"] == 3
     r = mg_mlqmc(SyntheticSampler(), 1e-9, max_level=12, max_points=64)
     assert not r["converged"] and r["N"].max() <= 64
+
+
+class FakeServer:
+    """Stands in for mlmc_server: capacity 5 samples per batch, QoIs
+    F_l(n, r) = (n + 1) * 10^-l + r (two QoIs: that and its double)."""
+
+    nq = 2
+
+    def __init__(self):
+        self.reqs = {}
+
+    def capacity(self, level):
+        return 5
+
+    def submit(self, level, n0, n1, r0, r1):
+        assert n1 - n0 <= 5 and r1 - r0 == 1
+        tag = len(self.reqs)
+        self.reqs[tag] = (level, n0, n1, r0)
+        return tag
+
+    def collect(self, tags):
+        out = []
+        for t in tags:
+            level, n0, n1, r = self.reqs[t]
+            n = np.arange(n0, n1, dtype=np.float64)[:, None]
+            F = (n + 1.0) * 10.0 ** -np.arange(level + 1)[None, :] + r
+            out.append(dict(status=0, qoi=np.stack([F, 2.0 * F], axis=-1)))
+        return out
+
+
+def test_server_sampler_splits_requests_and_forms_level_sums():
+    from paper_1806_05619_amd.driver import ServerSampler
+    srv = FakeServer()
+    s = ServerSampler(srv, num_shifts=3, first_shift=4).sample(2, 3, 15)
+    # 12 points per shift in requests of at most 5, shifts 4..6 of the table
+    assert len(srv.reqs) == 3 * 3
+    assert sorted({q[3] for q in srv.reqs.values()}) == [4, 5, 6]
+    for r in range(3):
+        for q in range(2):
+            n = np.arange(3, 15, dtype=np.float64)
+            F = np.stack([(n + 1.0) * 10.0 ** -l + (r + 4) for l in range(3)], axis=1) * (q + 1)
+            d = np.diff(np.concatenate([np.zeros((12, 1)), F], axis=1), axis=1)
+            assert np.allclose(s[r, q, :, 0], d.sum(axis=0), rtol=1e-14, atol=0)
+            assert np.allclose(s[r, q, :, 1], (d * d).sum(axis=0), rtol=1e-14, atol=0)
