@@ -54,6 +54,7 @@ struct mlmc_ctx_s {
     int64_t state_tuples = 0;
     double *d_rho = nullptr;
     double *d_rho_hist = nullptr;    // [chunk_max][4]: rho after the last four CG steps
+    double *d_qpart = nullptr;       // chunk sums of the QoI mean on grids >= 128^2
     int32_t *d_active = nullptr, *d_iters = nullptr;
     double *d_w = nullptr;           // refinement modes: FP64 stage solutions (pool elements)
     int32_t *d_st_iters = nullptr, *d_st_bad = nullptr;
@@ -375,7 +376,7 @@ mlmc_status run_fmg(mlmc_ctx c, hipStream_t st, const Hier &h, int k, double *qo
     if (tr) tr->record();
     if (!tr && g0 == 0) {
         ProfScope ps(c, st, MLMC_KERNEL_QOI, 8.0 * h.Bc * 4, 0.0);
-        launch_qoi(st, h.u[0], 2, h.Bc, qoi, nlev, 0, c->cfg.qoi_mask);
+        launch_qoi(st, h.u[0], 2, h.Bc, qoi, nlev, 0, c->cfg.qoi_mask, c->d_qpart);
     }
     for (int g = 1; g <= G; ++g) {
         const int n = 2 << g;
@@ -388,7 +389,7 @@ mlmc_status run_fmg(mlmc_ctx c, hipStream_t st, const Hier &h, int k, double *qo
         if (tr) tr->record();
         if (!tr && g >= g0) {
             ProfScope ps(c, st, MLMC_KERNEL_QOI, 8.0 * R.cells(n), 0.0);
-            launch_qoi(st, h.u[g], n, h.Bc, qoi, nlev, g - g0, c->cfg.qoi_mask);
+            launch_qoi(st, h.u[g], n, h.Bc, qoi, nlev, g - g0, c->cfg.qoi_mask, c->d_qpart);
         }
     }
     if (stats)
@@ -532,7 +533,7 @@ mlmc_status run_fmg_fixed(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k, 
             R.vcycle(g, R.h.u[g], cyc == 0 ? 2 : 0, nullptr, nullptr);
         if (g >= c->g0) {
             ProfScope ps(c, st, MLMC_KERNEL_QOI, 8.0 * R.cells(n), 0.0);
-            launch_qoi(st, R.h.u[g], n, Bc, qoi, nlev, g - c->g0, c->cfg.qoi_mask);
+            launch_qoi(st, R.h.u[g], n, Bc, qoi, nlev, g - c->g0, c->cfg.qoi_mask, c->d_qpart);
         }
     }
     if (stats) stats->max_iters = std::max(stats->max_iters, c->cfg.mu0);
@@ -611,7 +612,7 @@ mlmc_status run_fmg_refine(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k,
                             c->d_st_bad);
         if (g >= c->g0) {
             ProfScope ps(c, st, MLMC_KERNEL_QOI, 8.0 * R.cells(n), 0.0);
-            launch_qoi(st, h.w[g], n, Bc, qoi, nlev, g - c->g0, c->cfg.qoi_mask);
+            launch_qoi(st, h.w[g], n, Bc, qoi, nlev, g - c->g0, c->cfg.qoi_mask, c->d_qpart);
         }
     }
     if (stats) {
@@ -807,6 +808,7 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
                   8 * (size_t)a64 +
                   sizeof(double) * (own_tables * (size_t)s * ctx->Mmax + 4 * ctx->fcg_cells + parts + wcap +
                                     (size_t)ctx->chunk_max * (s + c.num_levels * ctx->nq + 6) +
+                                    qoi_partials(ctx->pool) +
                                     4 * ctx->state_tuples) +
                   sizeof(int32_t) * 4 * ctx->chunk_max;
     size_t free_b = 0, total_b = 0;
@@ -851,6 +853,7 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
     CHK(dev_alloc(ctx, &ctx->d_state, 4 * ctx->state_tuples));
     CHK(dev_alloc(ctx, &ctx->d_rho, ctx->chunk_max));
     CHK(dev_alloc(ctx, &ctx->d_rho_hist, ctx->fcg_cells > 0 ? 4 * ctx->chunk_max : 0));
+    CHK(dev_alloc(ctx, &ctx->d_qpart, qoi_partials(ctx->pool)));
     CHK(dev_alloc(ctx, &ctx->d_active, ctx->chunk_max));
     CHK(dev_alloc(ctx, &ctx->d_iters, ctx->chunk_max));
     CHK(hipHostMalloc((void **)&ctx->h_active, sizeof(int32_t) * ctx->chunk_max, hipHostMallocDefault));

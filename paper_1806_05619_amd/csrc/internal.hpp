@@ -91,8 +91,11 @@ void launch_resid_restrict(hipStream_t st, const double *a, const double *f, con
                            int n, int64_t Bc, double *fc, double *uc, const int32_t *active);
 void launch_prolong(hipStream_t st, const double *ec, double *u, int n, int64_t Bc, int add,
                     const int32_t *active);
+// QoI of level l for Bc samples; grids of 128^2 cells or more need `part`,
+// qoi_partials(cells of all samples) doubles of scratch
 void launch_qoi(hipStream_t st, const double *u, int n, int64_t Bc, double *qoi, int nlev,
-                int l, uint32_t mask);
+                int l, uint32_t mask, double *part);
+int64_t qoi_partials(int64_t pool_cells);
 void launch_fill(hipStream_t st, double *p, int64_t count, double v);
 void launch_fill_i32(hipStream_t st, int32_t *p, int64_t count, int32_t v);
 void launch_sums(hipStream_t st, const double *qoi, int nlev, int nq, int64_t b0, int64_t Bc,

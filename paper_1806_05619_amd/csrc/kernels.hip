@@ -332,6 +332,77 @@ __global__ __launch_bounds__(256) void k_qoi(const double *__restrict__ u, int n
     }
 }
 
+// Grids of QCH cells or more: the mean is summed in chunks of QCH cells, one
+// block per chunk (a single wavefront per sample leaves most of the chip idle
+// when a batch of a fine level has few samples), then the chunk sums of a
+// sample are folded in chunk order.  The order depends on n only, so a
+// sample's QoI does not depend on its batch.
+constexpr int QCH = 16384;
+
+__global__ __launch_bounds__(256) void k_qoi_part(const double *__restrict__ u, int n, int64_t Bc,
+                                                  double *__restrict__ part)
+{
+    const int64_t cells = (int64_t)n * n;
+    const int P = (int)(cells / QCH);
+    const int64_t blk = blockIdx.x;
+    const int64_t b = blk / P;
+    if (b >= Bc)
+        return;
+    const double *src = u + b * cells + (blk - b * P) * QCH;
+    Comp k{0.0, 0.0};
+    for (int q = threadIdx.x; q < QCH; q += 256)
+        comp_add(k, src[q]);
+    k = wave_reduce(k);
+    __shared__ double ws[4][2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        ws[w][0] = k.s;
+        ws[w][1] = k.c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Comp t{0.0, 0.0};
+        for (int i = 0; i < 4; ++i) {
+            comp_add(t, ws[i][0]);
+            comp_add(t, ws[i][1]);
+        }
+        part[2 * blk] = t.s;
+        part[2 * blk + 1] = t.c;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_qoi_fin(const double *__restrict__ u,
+                                                 const double *__restrict__ part, int n,
+                                                 int64_t Bc, double *__restrict__ qoi, int nlev,
+                                                 int l, uint32_t mask)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    if (b >= Bc)
+        return;
+    const int64_t cells = (int64_t)n * n;
+    const int P = (int)(cells / QCH);
+    Comp k{0.0, 0.0};
+    for (int p = lane; p < P; p += 64) {
+        comp_add(k, part[2 * (b * P + p)]);
+        comp_add(k, part[2 * (b * P + p) + 1]);
+    }
+    k = wave_reduce(k);
+    if (lane == 0) {
+        const double *ub = u + b * cells;
+        const int nq = (mask & 1u ? 1 : 0) + (mask & 2u ? 1 : 0);
+        double *qb = qoi + (b * nlev + l) * nq;
+        int q = 0;
+        if (mask & 1u)
+            qb[q++] = (k.s + k.c) / (double)cells;
+        if (mask & 2u) {
+            int c = n / 2;
+            qb[q] = 0.25 * (ub[(c - 1) + n * (c - 1)] + ub[c + n * (c - 1)] +
+                            ub[(c - 1) + n * c] + ub[c + n * c]);
+        }
+    }
+}
+
 __global__ void k_fill(double *p, int64_t count, double v)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -456,11 +527,20 @@ void launch_prolong(hipStream_t st, const double *ec, double *u, int n, int64_t 
 }
 
 void launch_qoi(hipStream_t st, const double *u, int n, int64_t Bc, double *qoi, int nlev, int l,
-                uint32_t mask)
+                uint32_t mask, double *part)
 {
+    if ((int64_t)n * n >= QCH) {
+        const int64_t P = (int64_t)n * n / QCH;
+        hipLaunchKernelGGL(k_qoi_part, dim3((unsigned)(Bc * P)), dim3(256), 0, st, u, n, Bc, part);
+        hipLaunchKernelGGL(k_qoi_fin, dim3(blocks_for(Bc, kBlock / 64)), dim3(kBlock), 0, st, u,
+                           part, n, Bc, qoi, nlev, l, mask);
+        return;
+    }
     hipLaunchKernelGGL(k_qoi, dim3(blocks_for(Bc, kBlock / 64)), dim3(kBlock), 0, st, u, n, Bc,
                        qoi, nlev, l, mask);
 }
+
+int64_t qoi_partials(int64_t pool_cells) { return 2 * (pool_cells / QCH) + 2; }
 
 void launch_fill(hipStream_t st, double *p, int64_t count, double v)
 {
