@@ -233,6 +233,7 @@ def serving(m, torch, seconds=4.0, rate=500.0, clients=4, slots=4, slot_samples=
                                 batches=srv.stats()["batches"] - s1["batches"],
                                 p50_ms=float(np.percentile(lat, 50)),
                                 p99_ms=float(np.percentile(lat, 99)))
+    kw["shifts"] = synth.shift_table(w["seed"], L1, R, w["s"])
     ctx = m.Context(**kw, max_batch=64, device=0)
     qd = torch.zeros((64, L1, 2), dtype=torch.float64, device="cuda:0")
     t0 = time.perf_counter()
@@ -240,6 +241,14 @@ def serving(m, torch, seconds=4.0, rate=500.0, clients=4, slots=4, slot_samples=
         ctx.fmg_solve(ctx.lattice(*r), qoi=qd)
         qd.cpu()
     dt = time.perf_counter() - t0
+    # one adaptive run on this context alone: recycled fractions against
+    # Proposition 1 for the rates fitted to its costs and variances
+    from paper_1806_05619_amd.driver import GpuSampler, recycling_report
+    mg_mlqmc(GpuSampler(ctx), eps, max_level=L1 - 1, max_points=1 << w["lattice_log2n"])
+    r1 = mg_mlqmc(GpuSampler(ctx), eps, max_level=L1 - 1, max_points=1 << w["lattice_log2n"])
+    rep = recycling_report(r1["N"], r1["cost"], r1["estimate"]["var_level"][0][: r1["L"] + 1])
+    out["recycling"] = dict(N=r1["N"].tolist(), cost_us=(r1["cost"] * 1e6).tolist(), **rep,
+                            note="beta fitted to var_l * N_l (Monte Carlo rate), lam = 1")
     del ctx
     out["one_call_per_request_samples_per_s"] = 400 * 64 / dt
     out["saturated"]["speedup_over_one_call_per_request"] = (out["saturated"]["samples_per_s"] /

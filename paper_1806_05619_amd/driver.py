@@ -146,3 +146,46 @@ def mg_mlqmc(sampler, eps, max_level, qoi=0, rho=2.0, reuse=True, max_points=Non
     return dict(q_bar=float(est["q_bar"][qoi]), var=float(np.sum(V[: L + 1])), bias=b,
                 alpha=alpha, L=L, N=N[: L + 1].copy(), cost=C[: L + 1].copy(),
                 converged=converged, history=history, estimate=est)
+
+
+def _rate(values, rho):
+    """Least-squares slope of log_rho |values_l| over l = 1..L (None if < 2 levels)."""
+    v = np.abs(np.asarray(values, dtype=np.float64))
+    lv = np.arange(1, len(v))
+    if len(lv) < 2 or np.any(v[1:] <= 0):
+        return None
+    return float(np.polyfit(lv, np.log(v[1:]) / np.log(rho), 1)[0])
+
+
+def prop1_reduction(beta, gamma, lam=1.0, rho=2.0):
+    """Proposition 1: with geometric refinement h_l = rho h_(l+1) and the
+    sample numbers of eq. nopt2, recycling leaves a fraction
+    1 - rho^(-(beta+gamma) lam/(lam+1)) of the samples of every level
+    (but the finest) to be computed; lam = 1 for Monte Carlo."""
+    return 1.0 - rho ** (-(beta + gamma) * lam / (lam + 1.0))
+
+
+def recycling_report(N, cost, var=None, rho=2.0, lam=1.0):
+    """Recycled fractions of a run (Section 3.3, Proposition 1).  N[l]:
+    samples whose finest level is l (the new ones, N'_l); the samples
+    available on level l are sum_(k >= l) N[k].  Returns the new fraction
+    N'_l / N_l per level, the cost ratio with and without recycling for the
+    measured cost per sample, the cost rate gamma fitted to `cost`, and, if
+    per-level variances `var` of the level estimators are given, beta fitted
+    to var[l] * N_l (the per-sample variance under a Monte Carlo rate) and
+    Proposition 1's prediction for those rates."""
+    N = np.asarray(N, dtype=np.float64)
+    cost = np.asarray(cost, dtype=np.float64)
+    total = np.cumsum(N[::-1])[::-1]
+    frac = np.where(total > 0, N / np.where(total > 0, total, 1.0), np.nan)
+    out = dict(new_fraction=frac.tolist(), available=total.tolist(),
+               cost_ratio=float(np.sum(N * cost) / np.sum(total * cost)))
+    gamma = _rate(cost, rho)
+    out["gamma"] = gamma
+    if var is not None:
+        v = np.asarray(var, dtype=np.float64) * total
+        b = _rate(v, rho)
+        out["beta"] = None if b is None else -b
+        if b is not None and gamma is not None:
+            out["predicted_fraction"] = prop1_reduction(-b, gamma, lam, rho)
+    return out

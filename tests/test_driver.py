@@ -116,3 +116,26 @@ def test_server_sampler_splits_requests_and_forms_level_sums():
             d = np.diff(np.concatenate([np.zeros((12, 1)), F], axis=1), axis=1)
             assert np.allclose(s[r, q, :, 0], d.sum(axis=0), rtol=1e-14, atol=0)
             assert np.allclose(s[r, q, :, 1], (d * d).sum(axis=0), rtol=1e-14, atol=0)
+
+
+def test_prop1_on_the_optimal_sample_numbers():
+    """Sample numbers of eq. nopt2, N_l ~ h_l^((beta+gamma) lam/(lam+1)),
+    make the new fraction of every level but the finest exactly
+    1 - rho^(-(beta+gamma) lam/(lam+1)) (Proposition 1); the report fits
+    gamma and beta back from costs and variances built with those rates."""
+    from paper_1806_05619_amd.driver import prop1_reduction, recycling_report
+    rho, beta, gamma, L = 2.0, 4.0, 2.0, 12
+    for lam in (1.0, 0.5):
+        x = (beta + gamma) * lam / (lam + 1.0)
+        total = rho ** (-x * np.arange(L + 1)) * 1e9       # N_l with recycling
+        new = total - np.append(total[1:], 0.0)              # N'_l
+        cost = rho ** (gamma * np.arange(L + 1))
+        var = rho ** (-beta * np.arange(L + 1)) / total      # estimator variance, MC rate
+        rep = recycling_report(new, cost, var, rho=rho, lam=lam)
+        want = prop1_reduction(beta, gamma, lam, rho)
+        assert np.allclose(rep["new_fraction"][:-1], want, rtol=1e-12)
+        assert rep["new_fraction"][-1] == 1.0
+        assert abs(rep["gamma"] - gamma) < 1e-9 and abs(rep["beta"] - beta) < 1e-9
+        assert abs(rep["predicted_fraction"] - want) < 1e-9
+    # Monte Carlo, beta = 2, gamma = 2, rho = 2: 1 - 2^-2 of every level is new
+    assert abs(prop1_reduction(2.0, 2.0, 1.0, 2.0) - 0.75) < 1e-15
