@@ -258,6 +258,47 @@ def serving(m, torch, seconds=4.0, rate=500.0, clients=4, slots=4, slot_samples=
     return out
 
 
+def methods(m, torch, eps_list=(2e-3, 1e-3, 5e-4, 2.5e-4)):
+    """The four estimators of the paper on the s = 100 workload (4^2 ..
+    256^2, FP64, 2 V(2,2) per FMG stage), each driven by Algorithm 1 to RMSE
+    eps: MLMC and MG-MLMC (Monte Carlo points, 16 independent replicas),
+    MLQMC and MG-MLQMC (Korobov lattice sequence, 16 random shifts); MG-
+    means the coarse FMG solutions are recycled (eq. Upsilon-reuse).  Wall
+    time on the GPU, points per level, finest level and the estimate."""
+    import synth
+    from paper_1806_05619_amd.driver import GpuMcSampler, GpuSampler, mg_mlqmc
+    w = synth.workload("mlqmc_fp64_s100")
+    L1, R = w["num_levels"], w["num_shifts"]
+    ctx = make_context(m, w, max_batch=4096)
+    seed = w["seed"]
+
+    def normals(level, r, n0, n1):
+        return synth.mc_normals(seed, level, n1, w["s"], replica=r)[n0:n1]
+
+    samplers = dict(MLMC=(lambda: GpuMcSampler(ctx, normals, R), False),
+                    MG_MLMC=(lambda: GpuMcSampler(ctx, normals, R), True),
+                    MLQMC=(lambda: GpuSampler(ctx), False),
+                    MG_MLQMC=(lambda: GpuSampler(ctx), True))
+    out = dict(workload="mlqmc_fp64_s100 (s = 100, lambda 0.3, sigma 1, 4^2..256^2, FP64, "
+                        "2 V(2,2) per FMG stage), QoI mean(u), 16 shifts / replicas",
+               runs=[])
+    mg_mlqmc(GpuSampler(ctx), eps_list[0], max_level=L1 - 1)      # warm-up
+    for eps in eps_list:
+        for name, (mk, reuse) in samplers.items():
+            t0 = time.perf_counter()
+            r = mg_mlqmc(mk(), eps, max_level=L1 - 1, reuse=reuse, max_points=1 << 16)
+            dt = time.perf_counter() - t0
+            out["runs"].append(dict(method=name, eps=eps, seconds=dt, L=r["L"],
+                                    N=r["N"].tolist(), q_bar=r["q_bar"],
+                                    sd=float(np.sqrt(r["var"])), bias=r["bias"],
+                                    converged=r["converged"],
+                                    samples=int(np.sum(r["N"]) * R)))
+        row = {x["method"]: x["seconds"] for x in out["runs"] if x["eps"] == eps}
+        log(f"[bench] methods eps {eps:g}: " + ", ".join(f"{k} {v:.3f} s" for k, v in row.items()))
+    del ctx
+    return out
+
+
 def uneven(m, torch, slots=3, reps=2):
     """Uneven levels: 4^2 .. 2048^2 with 2^(16-l) samples on level l (all 16
     shifts), mixed path refined to 1e-10.  One context solving the levels one
@@ -366,6 +407,8 @@ def main():
                     help="skip the mixed-vs-FP64 comparison on the s = 400 workload")
     ap.add_argument("--only-mixed", action="store_true",
                     help="run only the mixed-vs-FP64 comparison (prints its JSON object)")
+    ap.add_argument("--only-methods", action="store_true",
+                    help="run only the MLMC / MLQMC / recycling comparison (prints its JSON object)")
     ap.add_argument("--only-serving", action="store_true",
                     help="run only the serving-loop measurement (prints its JSON object)")
     ap.add_argument("--only-uneven", action="store_true",
@@ -391,6 +434,9 @@ def main():
         return
     if args.only_serving:
         print(json.dumps(serving(m, torch)), flush=True)
+        return
+    if args.only_methods:
+        print(json.dumps(methods(m, torch)), flush=True)
         return
     w = synth.workload("mlqmc_fp64_s100")
     k = w["num_levels"] - 1
@@ -508,6 +554,7 @@ def main():
                                             p99_ms=float(np.percentile(times, 99)))
         out["latency"] = lat
         out["serving"] = serving(m, torch)
+        out["methods"] = methods(m, torch)
         if not args.no_mixed:
             del ctx
             torch.cuda.empty_cache()

@@ -46,6 +46,32 @@ class GpuSampler:
         return s.cpu().numpy()          # synchronising copy: the timer sees the solve
 
 
+class GpuMcSampler:
+    """SampleAndSolve with Monte Carlo points (plain MLMC, Section 2): R
+    independent replicas of i.i.d. standard normal vectors play the role of
+    the R random shifts, so the same estimators (eq. MLQMC, eq. varovershifts
+    and their recycling forms) apply.  normals(level, replica, n_begin, n_end)
+    returns the [n_end - n_begin][s] normals of that replica, drawn once per
+    (level, replica) stream; each replica is one explicit-points solve."""
+
+    def __init__(self, ctx, normals, num_replicas):
+        import torch
+        self.ctx = ctx
+        self.R = int(num_replicas)
+        self.nq = ctx.nq
+        self.normals = normals
+        self._torch = torch
+
+    def sample(self, level, n_begin, n_end):
+        torch = self._torch
+        dev = torch.device("cuda", self.ctx.device)
+        out = torch.zeros((self.R, self.nq, level + 1, 2), dtype=torch.float64, device=dev)
+        for r in range(self.R):
+            y = torch.as_tensor(self.normals(level, r, n_begin, n_end), dtype=torch.float64)
+            self.ctx.fmg_solve(self.ctx.explicit(level, y.to(dev).contiguous()), sums=out[r:r + 1])
+        return out.cpu().numpy()
+
+
 class ServerSampler:
     """SampleAndSolve through the serving loop (mlmc_server): the new lattice
     points of every shift become requests (split to the server's capacity at

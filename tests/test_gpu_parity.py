@@ -458,3 +458,35 @@ def test_unattainable_rtol_stops_at_rounding_floor(oracle_mod, precision):
     for b in range(3):
         qo = P.sample(k, ys[b], 1)[:, : ctx.nq]
         assert _rel(q[b], qo) <= tol, b
+
+
+def test_monte_carlo_sampler_and_mlmc_driver():
+    """Plain MLMC through the same driver: R replicas of i.i.d. normals stand
+    in for the shifts.  The sampler's level sums equal exactly rounded sums of
+    the per-sample QoIs of the same explicit points, and MLMC agrees with
+    MG-MLQMC within the two error bounds."""
+    from paper_1806_05619_amd.driver import GpuMcSampler, GpuSampler, mg_mlqmc
+    dev = _dev()
+    w, ctx = _ctx("mlqmc_fp64_s100", max_batch=4096)
+
+    def normals(level, r, n0, n1):
+        return synth.mc_normals(w["seed"], level, n1, w["s"], replica=r)[n0:n1]
+
+    S = GpuMcSampler(ctx, normals, 3)
+    k = 3
+    sums = S.sample(k, 5, 42)
+    for r in range(3):
+        y = torch.tensor(normals(k, r, 5, 42), device=dev)
+        q, _, _ = _solve(ctx, ctx.explicit(k, y), k + 1)
+        for qi in range(ctx.nq):
+            d = np.diff(np.concatenate([np.zeros((37, 1)), q[:, :, qi]], axis=1), axis=1)
+            for l in range(k + 1):
+                assert abs(sums[r, qi, l, 0] - math.fsum(d[:, l])) <= 1e-13 * math.fsum(np.abs(d[:, l]))
+                assert abs(sums[r, qi, l, 1] - math.fsum(d[:, l] ** 2)) <= 1e-13 * math.fsum(d[:, l] ** 2)
+    eps = 2e-3
+    a = mg_mlqmc(GpuMcSampler(ctx, normals, 16), eps, max_level=w["num_levels"] - 1, reuse=False)
+    b = mg_mlqmc(GpuSampler(ctx), eps, max_level=w["num_levels"] - 1, reuse=True)
+    print(f"\nMLMC {a['q_bar']:.6f} (L {a['L']}, N {a['N'].tolist()}), "
+          f"MG-MLQMC {b['q_bar']:.6f} (L {b['L']}, N {b['N'].tolist()})")
+    assert a["converged"] and b["converged"]
+    assert abs(a["q_bar"] - b["q_bar"]) <= 3 * eps
