@@ -80,8 +80,9 @@ typedef struct {
     double rtol;          /* 0: fixed mu0 cycles.  > 0: every stage iterates
                              V-cycle-preconditioned flexible CG until
                              ||f-Au||_2/||f||_2 <= rtol, max_iters steps, or
-                             three steps that do not halve the ratio (the
-                             FP64 rounding floor, about eps * condition) */
+                             four steps in a row that do not bring the ratio
+                             10% below its best value (the FP64 rounding
+                             floor, about eps * condition) */
     int32_t max_iters;    /* refinement cap per stage when rtol > 0 (>= 1) */
     int32_t precision;    /* MLMC_FP64, or MLMC_MIXED (field from bf16 digit
                              products on the matrix cores, see mlmc_field;

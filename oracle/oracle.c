@@ -600,9 +600,10 @@ static double norm2(int64_t m, const double *v)
  * (Notay, SIAM J. Sci. Comput. 22 (2000): beta = (z, r - r_old) / (z_old,
  * r_old)), and the residual is recomputed from x at every step.  Returns the
  * number of preconditioner applications; *relres gets the final ratio;
- * *bad = 1 if the stage stopped above rtol: at max_iters, or because three
- * steps did not halve the ratio (the accuracy a computed FP64 residual can
- * show is bounded below by rounding; iterating on does not lower it). */
+ * *bad = 1 if the stage stopped above rtol: at max_iters, or because four
+ * steps in a row did not bring the ratio 10% below its best value so far
+ * (the accuracy a computed FP64 residual can show is bounded below by
+ * rounding; iterating on does not lower it). */
 static int stage_refine(fmg_state *S, int g, double *x, const double *ones, double *relres,
                         int *bad)
 {
@@ -617,11 +618,11 @@ static int stage_refine(fmg_state *S, int g, double *x, const double *ones, doub
     int it = 0;
     residual(n, S->a[g], ones, x, r);
     double rho = norm2(m, r) / nf;
-    double hist[4];                                    /* ratio after step k at k mod 4 */
-    hist[0] = rho;
+    double best = rho;                                 /* last 10% improvement */
+    int since = 0;                                     /* steps since then */
     *bad = 0;
     while (rho > S->P->rtol) {
-        if (it >= S->P->max_iters || (it >= 3 && rho > 0.5 * hist[(it - 3) & 3])) {
+        if (it >= S->P->max_iters || since >= 4) {
             *bad = 1;
             break;
         }
@@ -640,7 +641,12 @@ static int stage_refine(fmg_state *S, int g, double *x, const double *ones, doub
         rho = norm2(m, r) / nf;
         rz_old = rz;
         ++it;
-        hist[it & 3] = rho;
+        if (rho < 0.9 * best) {
+            best = rho;
+            since = 0;
+        } else {
+            ++since;
+        }
     }
     *relres = rho;
     free(r);

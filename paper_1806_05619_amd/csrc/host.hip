@@ -53,7 +53,7 @@ struct mlmc_ctx_s {
     double *d_state = nullptr;   // [max shifts][nq][num_levels][4]
     int64_t state_tuples = 0;
     double *d_rho = nullptr;
-    double *d_rho_hist = nullptr;    // [chunk_max][4]: rho after the last four CG steps
+    double *d_rho_hist = nullptr;    // [chunk_max][4]: CG stagnation state (best rho, steps since)
     double *d_qpart = nullptr;       // chunk sums of the QoI mean on grids >= 128^2
     int32_t *d_active = nullptr, *d_iters = nullptr;
     double *d_w = nullptr;           // refinement modes: FP64 stage solutions (pool elements)

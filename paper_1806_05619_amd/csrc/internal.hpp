@@ -145,15 +145,15 @@ struct FcgBufs {
     T *p0, *p1;             // search directions
     double *x0, *x1;        // iterates
     double *part, *fs, *rho;
-    double *hist;           // rho after each of the last four steps, 4 per sample
+    double *hist;           // stagnation state, 4 doubles per sample
     int32_t *active, *iters;
 };
 // r = 1 - A x0 (every sample), f = T(r), partial ||r||^2
 template <typename T>
 void launch_fcg_resid(hipStream_t st, const double *a, const double *x, int n, int64_t Bc, T *f,
                       double *part);
-// rho = ||r||/||1||; active = rho > rtol && iters < max_iters and the last
-// three steps halved rho; iters counts steps
+// rho = ||r||/||1||; active = rho > rtol && iters < max_iters and rho came
+// 10% below its best value within the last four steps; iters counts steps
 void launch_fcg_fin_rho(hipStream_t st, const double *part, int n, int64_t Bc, double *rho,
                         double *hist, int32_t *active, int32_t *iters, double rtol, int max_iters,
                         int first);

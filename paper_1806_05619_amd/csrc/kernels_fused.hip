@@ -773,7 +773,8 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
         else lds_prolong<LT>(w_s + LdsHier<GS>::off(g - 1), xg, n, false);
         int it = 0;
         double rho, rz_old = 1.0;
-        double rh0 = 0.0, rh1 = 0.0, rh2 = 0.0;   // rho of the last three steps
+        double best = 0.0;                        // smallest rho of a 10% improvement
+        int since = 0;                            // steps since then
         for (;;) {
             // r = 1 - A x, staged as the T right-hand side of the preconditioner
             double s = 0.0, c = 0.0;
@@ -790,11 +791,15 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
                 }
             }
             rho = sqrt(lds_reduce<LT>(s, c, red_s)) / (double)n;   // ||1||_2 = n
-            // attainable accuracy: stop once three steps have not halved rho
-            const bool stalled = it >= 3 && rho > 0.5 * rh2;
-            rh2 = rh1;
-            rh1 = rh0;
-            rh0 = rho;
+            // attainable accuracy: stop once four steps in a row have not
+            // brought rho 10% below the best value so far
+            if (it == 0 || rho < 0.9 * best) {
+                best = rho;
+                since = 0;
+            } else {
+                ++since;
+            }
+            const bool stalled = since >= 4;
             if (rho <= rtol || it >= max_iters || g == 0 || stalled) break;
             V.run(g, fg);                                       // z = B r
             double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0;
@@ -969,11 +974,19 @@ __global__ __launch_bounds__(256) void k_fcg_fin_rho(const double *__restrict__ 
     const double v = sqrt(fold_partials<1>(part, b, nch, 0)) / (double)n;
     if ((threadIdx.x & 63) == 0) {
         const int it = first ? 0 : iters[b];
-        // attainable accuracy: stop once three steps have not halved rho
-        // (hist[4b + k mod 4] holds rho after step k)
-        const bool stalled = it >= 3 && v > 0.5 * hist[4 * b + ((it - 3) & 3)];
-        const int go = v > rtol && it < max_iters && !stalled;
-        hist[4 * b + (it & 3)] = v;
+        // attainable accuracy: stop once four steps in a row have not brought
+        // rho 10% below the best value so far (hist[4b]: that value,
+        // hist[4b + 1]: steps since it was reached)
+        double best = hist[4 * b], since = hist[4 * b + 1];
+        if (it == 0 || v < 0.9 * best) {
+            best = v;
+            since = 0.0;
+        } else {
+            since += 1.0;
+        }
+        hist[4 * b] = best;
+        hist[4 * b + 1] = since;
+        const int go = v > rtol && it < max_iters && since < 4.0;
         rho[b] = v;
         active[b] = go;
         iters[b] = it + go;

@@ -430,7 +430,8 @@ def test_adaptive_driver_on_gpu():
 def test_unattainable_rtol_stops_at_rounding_floor(oracle_mod, precision):
     """rtol below what an FP64 residual can show: every stage, in the
     LDS-resident kernels (<= 32^2) and in the CG passes (64^2, 128^2), stops
-    once three steps fail to halve the residual ratio, long before max_iters;
+    once four steps in a row fail to bring the residual ratio 10% below its
+    best value, long before max_iters;
     the samples are reported as not converged and the QoIs are those of the
     direct solve."""
     dev = _dev()

@@ -242,10 +242,10 @@ def test_vcycle_convergence_is_mesh_independent(oracle_mod):
 
 
 def test_fmg_rtol_stops_at_rounding_floor(oracle_mod):
-    """An unattainable rtol: every stage stops once three CG steps fail to
-    halve the residual ratio, well before max_iters, flagged as not
-    converged; the iterate is then as accurate as FP64 allows (the band
-    Cholesky solve agrees to 1e-12)."""
+    """An unattainable rtol: every stage stops once four CG steps in a row
+    fail to bring the residual ratio 10% below its best value, well before
+    max_iters, flagged as not converged; the iterate is then as accurate as
+    FP64 allows (the band Cholesky solve agrees to 1e-12)."""
     P = oracle_mod.Problem(4, 5, 100, 0.3, 1.0, mu0=1, mu1=2, mu2=2, rtol=1e-30, max_iters=200)
     k = 4
     for z in _lognormal_fields(oracle_mod, P, k, 2, 31):
