@@ -103,8 +103,8 @@ struct Cell {
     int lr;
     __device__ int l() const { return lr & 0xFFFF; }
     __device__ int ring() const { return lr >> 16; }
-    T wE, wW, wN, wS, dw, inv, rhs;  // face weights (0 at a wall), wall term
-                                     // 2 a_P per wall face, 1 / diagonal, h^2 f
+    T wE, wW, wN, wS, inv, rhs;  // face weights (2 a_P at a wall, whose
+                                 // neighbour slot holds 0), 1 / diagonal, h^2 f
 };
 
 template <int S, typename T>
@@ -116,13 +116,16 @@ __device__ __forceinline__ void make_cell(Cell<T> &c, const T *a_s, int li, int 
 #pragma clang fp contract(off)
     const int l = li + S * lj;
     const T ap = a_s[l];
-    T d = T(0), dw = T(0);
-    c.wE = c.wW = c.wN = c.wS = T(0);
-    if (gi + 1 < n) { c.wE = hm(ap, a_s[l + 1]); d += c.wE; } else { d += T(2) * ap; dw += T(2) * ap; }
-    if (gi > 0)     { c.wW = hm(ap, a_s[l - 1]); d += c.wW; } else { d += T(2) * ap; dw += T(2) * ap; }
-    if (gj + 1 < n) { c.wN = hm(ap, a_s[l + S]); d += c.wN; } else { d += T(2) * ap; dw += T(2) * ap; }
-    if (gj > 0)     { c.wS = hm(ap, a_s[l - S]); d += c.wS; } else { d += T(2) * ap; dw += T(2) * ap; }
-    c.dw = dw;
+    const T wall = T(2) * ap;
+    c.wE = gi + 1 < n ? hm(ap, a_s[l + 1]) : wall;
+    c.wW = gi > 0 ? hm(ap, a_s[l - 1]) : wall;
+    c.wN = gj + 1 < n ? hm(ap, a_s[l + S]) : wall;
+    c.wS = gj > 0 ? hm(ap, a_s[l - S]) : wall;
+    T d = T(0);
+    d += c.wE;
+    d += c.wW;
+    d += c.wN;
+    d += c.wS;
     c.inv = frcp(d);
     c.rhs = rhs;
     c.lr = l | (min(min(li, lj), min(S - 1 - li, S - 1 - lj)) << 16);
@@ -133,7 +136,7 @@ __device__ __forceinline__ void relax(const Cell<T> &c, T *u_s)
 {
     const int l = c.l();
     // explicit fma, faces in the order E, W, N, S: the row-streaming pass
-    // rounds identically (a zero wall weight adds an exact zero)
+    // rounds identically (a wall face multiplies a neighbour slot holding 0)
     T num = fma(c.wE, u_s[l + 1], c.rhs);
     num = fma(c.wW, u_s[l - 1], num);
     num = fma(c.wN, u_s[l + S], num);
@@ -281,11 +284,10 @@ __global__ __launch_bounds__(NT) void k_pre_tile(const T *__restrict__ a, const 
         if (c.ring() < H) return;               // tile cells only (ring H of the region)
         const int l = c.l();
         // h^-2 (h^2 f - net flux); the flux is summed face by face as
-        // w (u_P - u_nbr) (0 at a wall, whose neighbour slot holds 0 and whose
-        // weight is 0) plus the wall term; h^2, h^-2 are powers of two
+        // w (u_P - u_nbr), a wall face giving 2 a_P u_P (its neighbour slot
+        // holds 0); h^2, h^-2 are powers of two
         const T up = u_s[l];
-        T v = c.dw * up;
-        v += c.wE * (up - u_s[l + 1]);
+        T v = c.wE * (up - u_s[l + 1]);
         v += c.wW * (up - u_s[l - 1]);
         v += c.wN * (up - u_s[l + S]);
         v += c.wS * (up - u_s[l - S]);
