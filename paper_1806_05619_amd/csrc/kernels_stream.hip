@@ -102,7 +102,9 @@ __device__ __forceinline__ void prolong2(const Coarse6 &k, double &v0, double &v
 
 // PRE: init 0 = read u_in, 1 = zero, 2 = u = P uc.  POST: u = u_in + P ec.
 // The result goes to u_out (may equal u_in: rows are read before written).
-template <int MU, bool PRE>
+// F1: f = 1 (the top level of a stage), so every rhs is h^2 and no row of
+// the register window carries one.
+template <int MU, bool PRE, bool F1>
 __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
                                                  const double *__restrict__ f,
                                                  const double *u_in, double *u_out,
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
                 const int c = red ? c0 + (rr & 1) : c1 - (rr & 1);
                 // explicit fma in the face order E, W, N, S of the tile passes,
                 // so that both kinds of pass give the same bits
-                double num = red ? r.rhs_r : r.rhs_b;
+                double num = F1 ? h2 : (red ? r.rhs_r : r.rhs_b);
                 if (c + 1 < n) num = fma(red ? r.wE_r : r.wE_b, row[c + 1], num);
                 if (c > 0) num = fma(red ? r.wW_r : r.wW_b, row[c - 1], num);
                 if (rr + 1 < n) num = fma(red ? r.wN_r : r.wN_b, up[c], num);
@@ -273,8 +275,8 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
                 if (cb > 0) fbk += r.wW_b * (ubk - row[cb - 1]);
                 if (rr + 1 < n) { fr += r.wN_r * (ur - up[cr]); fbk += r.wN_b * (ubk - up[cb]); }
                 if (rr > 0) { fr += rs.wN_b * (ur - dn[cr]); fbk += rs.wN_r * (ubk - dn[cb]); }
-                const double resr = inv_h2 * (r.rhs_r - fr);
-                const double resb = inv_h2 * (r.rhs_b - fbk);
+                const double resr = inv_h2 * ((F1 ? h2 : r.rhs_r) - fr);
+                const double resb = inv_h2 * ((F1 ? h2 : r.rhs_b) - fbk);
                 const bool odd = rr & 1;
                 const double u0 = odd ? ubk : ur, u1 = odd ? ur : ubk;
                 const double res0 = odd ? resb : resr, res1 = odd ? resr : resb;
@@ -296,21 +298,21 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
     }
 }
 
-template <int MU, bool PRE>
+template <int MU, bool PRE, bool F1>
 void launch_one(hipStream_t st, const double *a, const double *f, const double *u_in,
                 double *u_out, const double *ec, int n, int64_t Bc, int init, double *fc,
                 const int32_t *active)
 {
     // once per instantiation; the static's initialisation is thread-safe
     static const bool attr_set = [] {
-        (void)hipFuncSetAttribute((const void *)k_stream<MU, PRE>,
+        (void)hipFuncSetAttribute((const void *)k_stream<MU, PRE, F1>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         return true;
     }();
     (void)attr_set;
     const size_t lds = sizeof(double) * 10 * (size_t)n;
     const int threads = n / 2 < 64 ? 64 : n / 2;
-    hipLaunchKernelGGL((k_stream<MU, PRE>), dim3((unsigned)Bc), dim3(threads), lds, st, a, f, u_in,
+    hipLaunchKernelGGL((k_stream<MU, PRE, F1>), dim3((unsigned)Bc), dim3(threads), lds, st, a, f, u_in,
                        u_out, ec, n, Bc, init, fc, active);
 }
 
@@ -323,9 +325,11 @@ void launch_pre_stream(hipStream_t st, int mu1, const double *a, const double *f
                        int init, double *fc, const int32_t *active)
 {
     if (mu1 == 2)
-        launch_one<2, true>(st, a, f, u_in, u_out, uc, n, Bc, init, fc, active);
+        f ? launch_one<2, true, false>(st, a, f, u_in, u_out, uc, n, Bc, init, fc, active)
+          : launch_one<2, true, true>(st, a, f, u_in, u_out, uc, n, Bc, init, fc, active);
     else
-        launch_one<1, true>(st, a, f, u_in, u_out, uc, n, Bc, init, fc, active);
+        f ? launch_one<1, true, false>(st, a, f, u_in, u_out, uc, n, Bc, init, fc, active)
+          : launch_one<1, true, true>(st, a, f, u_in, u_out, uc, n, Bc, init, fc, active);
 }
 
 void launch_post_stream(hipStream_t st, int mu2, const double *a, const double *f,
@@ -333,9 +337,11 @@ void launch_post_stream(hipStream_t st, int mu2, const double *a, const double *
                         const int32_t *active)
 {
     if (mu2 == 2)
-        launch_one<2, false>(st, a, f, u_in, u_out, ec, n, Bc, 0, nullptr, active);
+        f ? launch_one<2, false, false>(st, a, f, u_in, u_out, ec, n, Bc, 0, nullptr, active)
+          : launch_one<2, false, true>(st, a, f, u_in, u_out, ec, n, Bc, 0, nullptr, active);
     else
-        launch_one<1, false>(st, a, f, u_in, u_out, ec, n, Bc, 0, nullptr, active);
+        f ? launch_one<1, false, false>(st, a, f, u_in, u_out, ec, n, Bc, 0, nullptr, active)
+          : launch_one<1, false, true>(st, a, f, u_in, u_out, ec, n, Bc, 0, nullptr, active);
 }
 
 }  // namespace mlmc
