@@ -491,3 +491,28 @@ def test_monte_carlo_sampler_and_mlmc_driver():
           f"MG-MLQMC {b['q_bar']:.6f} (L {b['L']}, N {b['N'].tolist()})")
     assert a["converged"] and b["converged"]
     assert abs(a["q_bar"] - b["q_bar"]) <= 3 * eps
+
+
+def test_uneven_workload_finest_level_sampled(oracle_mod):
+    """The finest level of the uneven workload at its own launch
+    configuration: 8 lattice points x 16 shifts at 2048^2 in one mixed-path
+    call (s = 400, refinement to 1e-10 with the rounding-floor stop).  Two
+    samples against the oracle's FMG in FP64 with the same stopping rule."""
+    dev = _dev()
+    w = synth.workload("uneven_mixed_s400")
+    L1, R = w["num_levels"], w["num_shifts"]
+    ctx = m.Context(w["n0"], L1, w["s"], w["corr_len"], w["sigma2"], mu0=w["mu0"], mu1=w["mu1"],
+                    mu2=w["mu2"], rtol=w["rtol"], max_iters=w["max_iters"],
+                    precision=m.MLMC_MIXED, qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
+                    genvec=synth.korobov_vector(w["seed"], w["s"]),
+                    shifts=synth.shift_table(w["seed"], L1, R, w["s"]), max_batch=128, device=0)
+    k = L1 - 1
+    print(f"\nuneven finest level {w['n0'] << k}^2, 128 samples", flush=True)
+    q, _, info = _solve(ctx, ctx.lattice(k, 0, 8, 0, R), k + 1, info=True)
+    assert np.all(np.isfinite(q))
+    assert info["max_rel_residual"] <= 1e-9, info
+    P = _oracle_problem(oracle_mod, w)
+    _, ys = _lattice_y(oracle_mod, w, k, [0], 0, 2)
+    qo, _ = P.batch(k, ys, 0, nthreads=2)
+    for b in range(2):
+        assert _rel(q[b], qo[b][:, : ctx.nq]) <= 1e-8, b
