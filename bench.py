@@ -378,19 +378,24 @@ def cpu_baseline(w, level, seconds):
                        mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"])
     z = synth.korobov_vector(w["seed"], w["s"])
     D = synth.shift_table(w["seed"], w["num_levels"], w["num_shifts"], w["s"])
-    done, n0 = 0, 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        nb = 2 * threads
-        _, y = oracle.points(z, D[level, 0], n0, n0 + nb)
-        P.batch(level, y, 0, nthreads=threads)
-        done += nb
-        n0 += nb
-    dt = time.perf_counter() - t0
+    def run(nthreads, secs, n0):
+        done = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < secs:
+            nb = 2 * nthreads
+            _, y = oracle.points(z, D[level, 0], n0 + done, n0 + done + nb)
+            P.batch(level, y, 0, nthreads=nthreads)
+            done += nb
+        return done, time.perf_counter() - t0
+
+    done, dt = run(threads, seconds, 0)
+    done1, dt1 = run(1, max(1.0, seconds / 4), done)
     return dict(value=done / dt, unit="samples/s", cores=threads, kind="oracle",
                 sample=f"{done} lattice samples (shift 0, points 0..{done - 1}) at level "
                        f"{level} ({w['n0'] << level}^2): direct-sum KL field + CPU FMG + QoI, "
-                       f"{dt:.1f} s wall")
+                       f"{dt:.1f} s wall",
+                single_thread_value=done1 / dt1,
+                single_thread_sample=f"{done1} further samples on one thread, {dt1:.1f} s wall")
 
 
 def main():
@@ -537,21 +542,28 @@ def main():
             torch.cuda.synchronize()
             per_level[f"{w['n0'] << lev}^2"] = B * reps / (time.perf_counter() - ta)
         out["samples_per_s_per_level"] = per_level
-        # request latency: (level, lattice range, shift) calls, host-visible sums
+        # request latency: one (level, lattice range, shift) call, from the ABI
+        # call to host-visible sums, per level and request size
         lat = {}
-        for nreq in (1, 64, 1024):
-            p = ctx.lattice(k, 0, nreq, 3, 4)
-            s3 = torch.zeros((1, nq, k + 1, 2), dtype=torch.float64, device=dev)
-            times = []
-            for i in range(40 if nreq < 1024 else 15):
-                torch.cuda.synchronize()
-                ta = time.perf_counter()
-                ctx.fmg_solve(p, sums=s3)
-                s3.cpu()
-                times.append((time.perf_counter() - ta) * 1e3)
-            times = np.array(times[3:])
-            lat[f"level{k}_n{nreq}"] = dict(p50_ms=float(np.percentile(times, 50)),
-                                            p99_ms=float(np.percentile(times, 99)))
+        for lev in range(k + 1):
+            for nreq in (1, 64, 1024):
+                p = ctx.lattice(lev, 0, nreq, 3, 4)
+                s3 = torch.zeros((1, nq, lev + 1, 2), dtype=torch.float64, device=dev)
+                reps = 1000 if nreq * 4 ** lev <= 64 * 4 ** 6 else 200
+                times = []
+                for i in range(reps + 10):
+                    torch.cuda.synchronize()
+                    ta = time.perf_counter()
+                    ctx.fmg_solve(p, sums=s3)
+                    s3.cpu()
+                    times.append((time.perf_counter() - ta) * 1e3)
+                times = np.array(times[10:])
+                lat[f"level{lev}_{w['n0'] << lev}^2_n{nreq}"] = dict(
+                    p50_ms=float(np.percentile(times, 50)), p99_ms=float(np.percentile(times, 99)),
+                    repeats=reps)
+        log("[bench] latency 256^2: " + ", ".join(
+            f"n{q} {lat[f'level{k}_256^2_n{q}']['p50_ms']:.2f}/{lat[f'level{k}_256^2_n{q}']['p99_ms']:.2f} ms"
+            for q in (1, 64, 1024)))
         out["latency"] = lat
         out["serving"] = serving(m, torch)
         out["methods"] = methods(m, torch)
