@@ -2,7 +2,7 @@
 // truncatedKL): z = Y basis with v_mfma_f64_16x16x4f64, a = exp(z) in the
 // epilogue.
 //
-// Block tile 64 samples x 128 field columns, 4 wavefronts of 32 x 64 (2 x 4
+// Block tile 128 samples x 128 field columns, 8 wavefronts of 32 x 64 (2 x 4
 // MFMA tiles, 32 FP64 accumulators per lane), K staged through LDS 16 modes at
 // a time.  MFMA lane layout (16x16x4 f64, checked on the device): A row l%16 and
 // B column l%16 take mode l/16; lane l holds D rows l/16 + 4 i (i = 0..3) of
@@ -14,11 +14,11 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int FBM = 64, FBN = 128, FKB = 16;
+constexpr int FBM = 128, FBN = 128, FKB = 16, FNT = 512;
 
 
 // mode 0: z to out[b*M + m]; mode 1: exp(z) into the level-major FP64 pool
-__global__ __launch_bounds__(256) void k_field_mfma64(const double *__restrict__ Y, int s,
+__global__ __launch_bounds__(FNT) void k_field_mfma64(const double *__restrict__ Y, int s,
                                                       const double *__restrict__ basis, int64_t ld,
                                                       int64_t M, int64_t Bc,
                                                       double *__restrict__ out, int mode)
@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_field_mfma64(const double *__restrict__
     __shared__ double Bs[FKB][FBN];      // basis tile
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t row0 = (int64_t)blockIdx.y * FBM, col0 = (int64_t)blockIdx.x * FBN;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave >> 1, wc = wave & 1;      // 4 x 2 waves
     d4 acc[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -37,8 +37,8 @@ __global__ __launch_bounds__(256) void k_field_mfma64(const double *__restrict__
     // global loads of the next 16 modes are in flight while the matrix cores
     // work on the current ones (register prefetch)
     const int yr = t >> 2, yk = (t & 3) * 4;          // Y: sample row0 + yr, modes yk..yk+3
-    const int bk = t >> 4, bc = (t & 15) * 8;         // basis: mode bk, columns bc..bc+7
-    double yv[4], bv[8];
+    const int bk = t >> 5, bc = (t & 31) * 4;         // basis: mode bk, columns bc..bc+3
+    double yv[4], bv[4];
     auto fetch = [&](int k0) {
         const int64_t gr = row0 + yr;
 #pragma unroll
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_field_mfma64(const double *__restrict__
         }
         const int gk = k0 + bk;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < 4; ++q) {
             const int64_t gc = col0 + bc + q;
             bv[q] = (gk < s && gc < M) ? basis[(int64_t)gk * ld + gc] : 0.0;
         }
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void k_field_mfma64(const double *__restrict__
 #pragma unroll
         for (int q = 0; q < 4; ++q) As[yk + q][yr] = yv[q];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) Bs[bk][bc + q] = bv[q];
+        for (int q = 0; q < 4; ++q) Bs[bk][bc + q] = bv[q];
         __syncthreads();
         if (k0 + FKB < s) fetch(k0 + FKB);
 #pragma unroll
@@ -108,7 +108,7 @@ void launch_field_gemm(hipStream_t st, const double *Y, int s, const double *bas
                        int64_t M, int64_t Bc, void *out, int mode)
 {
     dim3 grid((unsigned)((M + FBN - 1) / FBN), (unsigned)((Bc + FBM - 1) / FBM));
-    hipLaunchKernelGGL(k_field_mfma64, grid, dim3(256), 0, st, Y, s, basis, ld, M, Bc,
+    hipLaunchKernelGGL(k_field_mfma64, grid, dim3(FNT), 0, st, Y, s, basis, ld, M, Bc,
                        (double *)out, mode);
 }
 
