@@ -134,7 +134,7 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
 
 // out mode 0: z (double) at out[b*M + m]; mode 2: exp(z) as float into the
 // level-major pool `out` and as double into `out64`.
-__global__ __launch_bounds__(256) void k_field_digits(
+__global__ __launch_bounds__(256, 2) void k_field_digits(
     const uint16_t *__restrict__ Y0, const uint16_t *__restrict__ Y1,
     const uint16_t *__restrict__ Y2, const uint16_t *__restrict__ Y3,
     const int32_t *__restrict__ EY, const uint16_t *__restrict__ B0,
@@ -142,9 +142,20 @@ __global__ __launch_bounds__(256) void k_field_digits(
     const uint16_t *__restrict__ B3, const int32_t *__restrict__ EB, int sp, int64_t M, int64_t Bc,
     void *__restrict__ out, double *__restrict__ out64, int mode)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t row0 = (int64_t)blockIdx.y * BM + (wave >> 1) * WM;    // sample rows
-    const int64_t col0 = (int64_t)blockIdx.x * BN + (wave & 1) * WN;     // field columns
+    // The block's 64 x 32 digit panels of Y and of the basis are staged in
+    // LDS, double-buffered: every 16-byte chunk is fetched from global memory
+    // once per block (not once per wavefront that uses it), and the chunks of
+    // the next 32 modes are in flight while the matrix cores work on the
+    // current ones.  Rows are padded to KP bf16 so that the 16 rows a
+    // quarter-wavefront reads fall into distinct LDS banks.
+    constexpr int KP = 40;
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][4][BM * KP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][4][BN * KP];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t brow0 = (int64_t)blockIdx.y * BM, bcol0 = (int64_t)blockIdx.x * BN;
+    const int64_t row0 = brow0 + (wave >> 1) * WM;    // sample rows of this wave
+    const int64_t col0 = bcol0 + (wave & 1) * WN;     // field columns of this wave
+    const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
     const int lr = lane & 15, kg = 8 * (lane >> 4);
     const uint16_t *Yd[4] = {Y0, Y1, Y2, Y3};
     const uint16_t *Bd[4] = {B0, B1, B2, B3};
@@ -159,37 +170,56 @@ __global__ __launch_bounds__(256) void k_field_digits(
 #pragma unroll
             for (int g = 0; g < 4; ++g) G[g][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
+    // staging: 4 digits x 64 rows x 4 chunks of 8 modes per operand = 1024
+    // chunks, four per thread: chunk c = t + 256 q has digit q, row t / 4 and
+    // modes 8 (t % 4) .. +7 (rows and columns are padded, all in range)
+    const int sr = t >> 2, sk = (t & 3) * 8;
+    bf16x8 ya[4], yb[4];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ya[q] = *(const bf16x8 *)(Yd[q] + (brow0 + sr) * sp + k0 + sk);
+            yb[q] = *(const bf16x8 *)(Bd[q] + (bcol0 + sr) * sp + k0 + sk);
+        }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            *(bf16x8 *)(&As[buf][q][sr * KP + sk]) = ya[q];
+            *(bf16x8 *)(&Bs[buf][q][sr * KP + sk]) = yb[q];
+        }
+    };
     const int nk = sp / 32;
+    fetch(0);
+    stage(0);
+    __syncthreads();
     for (int ks = 0; ks < nk; ++ks) {
-        const int k0 = 32 * ks;
+        const int buf = ks & 1;
+        if (ks + 1 < nk) fetch(32 * (ks + 1));
         bf16x8 a[2][4], b[2][4];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int64_t o = (row0 + 16 * i + lr) * sp + k0 + kg;
-#pragma unroll
-            for (int d = 0; d < 4; ++d) a[i][d] = *(const bf16x8 *)(Yd[d] + o);
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int64_t o = (col0 + 16 * j + lr) * sp + k0 + kg;
-#pragma unroll
-            for (int d = 0; d < 4; ++d) b[j][d] = *(const bf16x8 *)(Bd[d] + o);
-        }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                G[0][i][j] = mfma(a[i][0], b[j][0], G[0][i][j]);
-                G[1][i][j] = mfma(a[i][0], b[j][1], G[1][i][j]);
-                G[1][i][j] = mfma(a[i][1], b[j][0], G[1][i][j]);
-                G[2][i][j] = mfma(a[i][0], b[j][2], G[2][i][j]);
-                G[2][i][j] = mfma(a[i][2], b[j][0], G[2][i][j]);
-                G[2][i][j] = mfma(a[i][1], b[j][1], G[2][i][j]);
-                G[3][i][j] = mfma(a[i][0], b[j][3], G[3][i][j]);
-                G[3][i][j] = mfma(a[i][3], b[j][0], G[3][i][j]);
-                G[3][i][j] = mfma(a[i][1], b[j][2], G[3][i][j]);
-                G[3][i][j] = mfma(a[i][2], b[j][1], G[3][i][j]);
-            }
+            for (int d = 0; d < 4; ++d)
+                a[i][d] = *(const bf16x8 *)(&As[buf][d][(wr + 16 * i + lr) * KP + kg]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                b[j][d] = *(const bf16x8 *)(&Bs[buf][d][(wc + 16 * j + lr) * KP + kg]);
+        // the ten digit products (digit of Y, digit of the basis, group), each
+        // over the four 16 x 16 tiles in turn, so that consecutive MFMAs write
+        // different accumulators
+        constexpr int PA[10] = {0, 0, 1, 0, 2, 1, 0, 3, 1, 2};
+        constexpr int PB[10] = {0, 1, 0, 2, 0, 1, 3, 0, 2, 1};
+        constexpr int PG[10] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3};
+#pragma unroll
+        for (int p = 0; p < 10; ++p)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    G[PG[p]][i][j] = mfma(a[i][PA[p]], b[j][PB[p]], G[PG[p]][i][j]);
         if ((ks + 1) % KFOLD == 0 || ks + 1 == nk) {
             // exact: the groups are integers below 2^24 and span < 53 bits
 #pragma unroll
@@ -204,6 +234,10 @@ __global__ __launch_bounds__(256) void k_field_digits(
 #pragma unroll
                     for (int g = 0; g < 4; ++g) G[g][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
+        }
+        if (ks + 1 < nk) {
+            stage(buf ^ 1);      // its last readers finished before the previous barrier
+            __syncthreads();
         }
     }
 #pragma unroll
