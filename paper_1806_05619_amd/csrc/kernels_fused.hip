@@ -422,16 +422,16 @@ __device__ void lds_sweep(const T *a, const T *f, T *u, int n, int colour)
 // r = f - A u at one cell, in the arithmetic of TU (coefficients TA promoted)
 // net flux out of cell (i, j) times h^2, face by face: w (u_P - u_nbr) for an
 // interior face, 2 a_P u_P for a wall face
-template <typename TU, typename TA>
-__device__ __forceinline__ TU lds_flux(const TA *a, const TU *u, int n, int i, int j)
+template <typename TU, typename TA, typename TV>
+__device__ __forceinline__ TU lds_flux(const TA *a, const TV *u, int n, int i, int j)
 {
     const int p = i + n * j;
-    const TU ap = TU(a[p]), up = u[p];
+    const TU ap = TU(a[p]), up = TU(u[p]);
     TU v = TU(0);
-    v += (i + 1 < n) ? hm(ap, TU(a[p + 1])) * (up - u[p + 1]) : TU(2) * ap * up;
-    v += (i > 0) ? hm(ap, TU(a[p - 1])) * (up - u[p - 1]) : TU(2) * ap * up;
-    v += (j + 1 < n) ? hm(ap, TU(a[p + n])) * (up - u[p + n]) : TU(2) * ap * up;
-    v += (j > 0) ? hm(ap, TU(a[p - n])) * (up - u[p - n]) : TU(2) * ap * up;
+    v += (i + 1 < n) ? hm(ap, TU(a[p + 1])) * (up - TU(u[p + 1])) : TU(2) * ap * up;
+    v += (i > 0) ? hm(ap, TU(a[p - 1])) * (up - TU(u[p - 1])) : TU(2) * ap * up;
+    v += (j + 1 < n) ? hm(ap, TU(a[p + n])) * (up - TU(u[p + n])) : TU(2) * ap * up;
+    v += (j > 0) ? hm(ap, TU(a[p - n])) * (up - TU(u[p - n])) : TU(2) * ap * up;
     return v;
 }
 
@@ -716,8 +716,8 @@ __device__ __forceinline__ void lds_reduce2(double s0, double c0, double s1, dou
 }
 
 // (A u)_P in FP64 at cell (i, j) of the n x n grid, coefficients TA promoted
-template <typename TA>
-__device__ __forceinline__ double lds_apply(const TA *a, const double *u, int n, int i, int j)
+template <typename TA, typename TV>
+__device__ __forceinline__ double lds_apply(const TA *a, const TV *u, int n, int i, int j)
 {
     return double(n) * double(n) * lds_flux<double>(a, u, n, i, j);
 }
@@ -743,9 +743,11 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
     constexpr bool F64 = sizeof(T) == sizeof(double);
     constexpr int RPT = (TOP + LT - 1) / LT;   // top-level cells per thread
     __shared__ T a_s[TOT], u_s[TOT], f_s[TOT], chol_s[10];
-    __shared__ double a64_s[F64 ? 1 : TOT];   // FP64 coefficients of the CG operator
+    // FP64 coefficients of the current stage's CG operator (the FP64 context
+    // uses a_s itself)
+    __shared__ double a64_s[F64 ? 1 : TOP];
     __shared__ double w_s[TOT];          // FP64 stage solutions x
-    __shared__ double p_s[TOP];          // search direction
+    __shared__ T p_s[TOP];               // search direction, in the V-cycle type
     __shared__ double red_s[4 * (LT / 64)], chol64_s[10];
     double r_v[RPT], ro_v[RPT];          // r and r_old of this thread's cells p = tid + LT q
     const int64_t b = blockIdx.x;
@@ -753,15 +755,12 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
     for (int g = 0; g <= G; ++g) {
         const int cnt = 4 << (2 * g);
         const int64_t o = Bc * level_offset(g) + b * (int64_t)cnt;
-        for (int p = threadIdx.x; p < cnt; p += LT) {
-            a_s[LdsHier<GS>::off(g) + p] = a_pool[o + p];
-            if (!F64) a64_s[LdsHier<GS>::off(g) + p] = a64_pool[o + p];
-        }
+        for (int p = threadIdx.x; p < cnt; p += LT) a_s[LdsHier<GS>::off(g) + p] = a_pool[o + p];
     }
+    if (!F64 && threadIdx.x < 4) a64_s[threadIdx.x] = a64_pool[b * 4 + threadIdx.x];
     __syncthreads();
-    const double *a64 = F64 ? (const double *)a_s : a64_s;
     lds_chol4<T>(a_s, chol_s);
-    lds_chol4<double>(a64, chol64_s);
+    lds_chol4<double>(F64 ? (const double *)a_s : a64_s, chol64_s);
     __syncthreads();
     LdsVcycle<GS, T, LT> V{a_s, u_s, f_s, chol_s, mu1, mu2};
     int it_max = 0, bad = 0;
@@ -770,7 +769,12 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
         const int n = 2 << g, cells = n * n;
         double *xg = w_s + LdsHier<GS>::off(g);
         T *zg = u_s + LdsHier<GS>::off(g), *fg = f_s + LdsHier<GS>::off(g);
-        const double *ag = a64 + LdsHier<GS>::off(g);
+        if (!F64 && g > 0) {
+            const int64_t o = Bc * level_offset(g) + b * (int64_t)cells;
+            __syncthreads();             // the previous stage's operator is no longer read
+            for (int p = threadIdx.x; p < cells; p += LT) a64_s[p] = a64_pool[o + p];
+        }
+        const double *ag = F64 ? (const double *)a_s + LdsHier<GS>::off(g) : a64_s;
         if (g == 0) lds_coarse_solve<double>(chol64_s, (const double *)nullptr, xg);
         else lds_prolong<LT>(w_s + LdsHier<GS>::off(g - 1), xg, n, false);
         int it = 0;
@@ -819,16 +823,16 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_refine(
             lds_reduce2<LT>(s0, c0, s1, c1, red_s, rz, rzo);
             const double beta = it == 0 ? 0.0 : (rz - rzo) / rz_old;
             for (int p = threadIdx.x; p < cells; p += LT)
-                p_s[p] = it == 0 ? double(zg[p]) : double(zg[p]) + beta * p_s[p];
+                p_s[p] = T(it == 0 ? double(zg[p]) : double(zg[p]) + beta * double(p_s[p]));
             __syncthreads();
             s = 0.0;
             c = 0.0;
             for (int p = threadIdx.x; p < cells; p += LT) {
                 const int j = p >> __builtin_ctz(n), i = p & (n - 1);
-                neumaier(s, c, p_s[p] * lds_apply(ag, p_s, n, i, j));
+                neumaier(s, c, double(p_s[p]) * lds_apply(ag, p_s, n, i, j));
             }
             const double alpha = rz / lds_reduce<LT>(s, c, red_s);
-            for (int p = threadIdx.x; p < cells; p += LT) xg[p] += alpha * p_s[p];
+            for (int p = threadIdx.x; p < cells; p += LT) xg[p] += alpha * double(p_s[p]);
             __syncthreads();
             rz_old = rz;
             ++it;
