@@ -732,7 +732,7 @@ __device__ __forceinline__ double lds_apply(const TA *a, const TV *u, int n, int
 // largest step count, the largest final relative residual and whether a stage
 // stopped at max_iters.
 template <int GS, typename T, int LT>
-__global__ __launch_bounds__(LT) void k_lds_fmg_refine(
+__global__ __launch_bounds__(LT, LT == 64 ? 4 : 1) void k_lds_fmg_refine(
     const T *__restrict__ a_pool, const double *__restrict__ a64_pool,
     double *__restrict__ u64_pool, int64_t Bc, int G, int mu1, int mu2, double rtol, int max_iters,
     int g0, double *__restrict__ qoi, int nlev, uint32_t mask, int32_t *__restrict__ st_iters,
