@@ -125,3 +125,36 @@ def test_large_batch_passes_equal_small_batch_passes():
     big = _direct(ctx, k, 0, 1100, 3, 4)
     for n in (0, 517, 1099):
         assert np.array_equal(_direct(ctx, k, n, n + 1, 3, 4)[0], big[n]), n
+
+
+def test_server_concurrent_clients_collect_their_own_results():
+    """Four host threads submit interleaved requests to one server and collect
+    their own tags (results polled by one client are kept for the others);
+    every result is bitwise the direct solve of its points."""
+    import threading
+    _dev()
+    w = synth.workload("mlqmc_fp64_s100")
+    kw = _kw(w, m.MLMC_FP64)
+    got, errors = {}, []
+    with m.Server(**kw, num_slots=2, slot_samples=64, device=0) as srv:
+        def client(c):
+            try:
+                rng = np.random.default_rng(100 + c)
+                reqs = _requests(rng, w["num_levels"], 15, 64)
+                tags = [srv.submit(*r) for r in reqs]
+                for r, res in zip(reqs, srv.collect(tags, timeout_s=120)):
+                    got[(c, res["tag"])] = (r, res)
+            except Exception as e:          # reported below, on the main thread
+                errors.append(e)
+        th = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        assert srv.pending() == 0
+    assert not errors, errors
+    assert len(got) == 60
+    ctx = m.Context(**kw, max_batch=64, device=0)
+    for (c, tag), (r, res) in got.items():
+        assert res["status"] == m.MLMC_OK and res["tag"] == tag
+        assert np.array_equal(res["qoi"], _direct(ctx, *r)), (c, tag, r)
