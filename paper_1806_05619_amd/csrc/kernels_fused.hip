@@ -1061,21 +1061,25 @@ __global__ __launch_bounds__(256) void k_fcg_p(const T *__restrict__ a, const T 
     const T *ab = a + base, *zb = z + base;
     const T *pold = ((k - 1) & 1 ? P1 : P0) + base;
     T *pnew = (k & 1 ? P1 : P0) + base;
-    auto pk = [&](int64_t q) { return k == 1 ? double(zb[q]) : double(zb[q]) + beta * double(pold[q]); };
+    // p = z + beta p_old and A p in the V-cycle type T (p is stored in T; the
+    // step length only scales the update of the FP64 iterate, whose residual
+    // is recomputed in FP64), the products (p, A p) summed in FP64
+    const T bt = T(beta);
+    auto pk = [&](int64_t q) { return k == 1 ? zb[q] : T(zb[q] + bt * pold[q]); };
     double s[1] = {0.0}, c[1] = {0.0};
 #pragma unroll
     for (int qq = 0; qq < FCH / 256; ++qq) {
         const int64_t p = m.c0 + threadIdx.x + 256 * qq;
         if (p < cells) {
             const int j = (int)p >> __builtin_ctz(n), i = (int)p & (n - 1);
-            const double ap = double(ab[p]), pp = pk(p);
-            double v = 0.0;   // net flux of p, face by face
-            v += (i + 1 < n) ? hm(ap, double(ab[p + 1])) * (pp - pk(p + 1)) : 2.0 * ap * pp;
-            v += (i > 0) ? hm(ap, double(ab[p - 1])) * (pp - pk(p - 1)) : 2.0 * ap * pp;
-            v += (j + 1 < n) ? hm(ap, double(ab[p + n])) * (pp - pk(p + n)) : 2.0 * ap * pp;
-            v += (j > 0) ? hm(ap, double(ab[p - n])) * (pp - pk(p - n)) : 2.0 * ap * pp;
-            pnew[p] = T(pp);
-            neumaier(s[0], c[0], pp * double(n) * double(n) * v);
+            const T ap = ab[p], pp = pk(p);
+            T v = T(0);   // net flux of p, face by face
+            v += (i + 1 < n) ? hm(ap, ab[p + 1]) * (pp - pk(p + 1)) : T(2) * ap * pp;
+            v += (i > 0) ? hm(ap, ab[p - 1]) * (pp - pk(p - 1)) : T(2) * ap * pp;
+            v += (j + 1 < n) ? hm(ap, ab[p + n]) * (pp - pk(p + n)) : T(2) * ap * pp;
+            v += (j > 0) ? hm(ap, ab[p - n]) * (pp - pk(p - n)) : T(2) * ap * pp;
+            pnew[p] = pp;
+            neumaier(s[0], c[0], double(pp) * double(n) * double(n) * double(v));
         }
     }
     block_partials<1>(s, c, part + (m.b * m.nch + m.c0 / FCH) * 2);
