@@ -520,7 +520,7 @@ mlmc_status run_fmg_fixed(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k, 
                           StageStats *stats)
 {
     const int nlev = k + 1;
-    FusedRunner<double> R{c, st, make_hier_t<double>(c, G, Bc), std::min(G, kLdsMaxLevel)};
+    FusedRunner<double> R{c, st, make_hier_t<double>(c, G, Bc), std::min(G, kLdsMaxLevelFixed)};
     {
         const int n = 2 << R.Gs;
         ProfScope ps(c, st, MLMC_KERNEL_LDS, 8.0 * Bc * level_offset(R.Gs + 1) + 8.0 * R.cells(n), 0.0);
@@ -801,7 +801,8 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
     const int64_t brows = mixed ? mixed_pad_cols(ctx->Mmax) : 0;
     const int64_t yrows = mixed ? mixed_pad_rows(ctx->chunk_max) : 0;
     const int64_t a64 = mixed ? ctx->pool : 0;
-    const bool tile_levels = fused_supported(c.mu1, c.mu2) && Gmax > kLdsMaxLevel;
+    const bool tile_levels = fused_supported(c.mu1, c.mu2) &&
+                             Gmax > (c.rtol > 0.0 ? kLdsMaxLevel : kLdsMaxLevelFixed);
     const size_t own_tables = parent ? 0 : 1;
     size_t need = (size_t)ctx->elem * (tile_levels ? 4 : 3) * (size_t)ctx->pool +
                   (8 * (size_t)ctx->sp + 4) * (size_t)(own_tables * brows + yrows) +

@@ -20,6 +20,7 @@ int64_t level_capacity(mlmc_ctx c, int k);
 constexpr int kMaxMgLevels = 12;   // n_g = 2^(g+1) <= 4096
 constexpr int kBlock = 256;
 constexpr int kLdsMaxLevel = 4;    // grids up to 32^2 run LDS-resident (one workgroup per sample)
+constexpr int kLdsMaxLevelFixed = 3;   // fixed-cycle mode: up to 16^2; 32^2 runs the tile passes
 
 // Offset (in cells) of multigrid level g inside a level-major per-sample
 // field: sum_{g' < g} 4^(g'+1) = 4 (4^g - 1) / 3.
