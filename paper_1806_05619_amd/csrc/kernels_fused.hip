@@ -186,6 +186,7 @@ __device__ __forceinline__ void load_region(T *a_s, T *u_s, const T *c_s, const 
             else if (mode == 3) uv[k] = ub[p] + CSt::at(c_s, cI0, cJ0, gi, gj);
         }
     }
+    if (mode >= 2) __syncthreads();      // c_s may share storage with a_s
 #pragma unroll
     for (int k = 0; k < PERT; ++k) {
         const int e = threadIdx.x + NT * k;
@@ -244,7 +245,9 @@ __global__ __launch_bounds__(NT) void k_pre_tile(const T *__restrict__ a, const 
     using CSt = CoarseStage<S, T>;
     __shared__ T u_s[S * S];
     __shared__ T a_s[S * S];
-    __shared__ T c_s[CSt::CS * CSt::CS];
+    // the coarse values for the interpolation are read before a_s is written
+    static_assert(CSt::CS * CSt::CS <= S * S, "coarse stage fits in a_s");
+    T *const c_s = a_s;
 
     const int tiles_side = n / TILE;
     const int tps = tiles_side * tiles_side;
@@ -329,7 +332,9 @@ __global__ __launch_bounds__(NT) void k_post_tile(const T *__restrict__ a, const
     using CSt = CoarseStage<S, T>;
     __shared__ T u_s[S * S];
     __shared__ T a_s[S * S];
-    __shared__ T c_s[CSt::CS * CSt::CS];
+    // the coarse correction is read before a_s is written
+    static_assert(CSt::CS * CSt::CS <= S * S, "coarse stage fits in a_s");
+    T *const c_s = a_s;
 
     const int tiles_side = n / TILE;
     const int tps = tiles_side * tiles_side;
