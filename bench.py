@@ -36,11 +36,11 @@ FP64_PEAK_TFLOPS = 78.6
 KINDS = ("points", "field", "smooth", "restrict", "prolong", "coarse", "qoi", "sums", "pre", "post",
          "lds", "refine")
 KERNEL_NAMES = dict(
-    points="k_points", field="k_field_gemm", smooth="k_rbgs (one colour)",
+    points="k_points", field="k_field_mfma64", smooth="k_rbgs (one colour)",
     restrict="k_resid_restrict", prolong="k_prolong", coarse="k_coarse_solve", qoi="k_qoi",
-    sums="k_sums", pre="k_pre_tile<2> (2 red-black sweeps + residual + restriction, 64^2..256^2)",
-    post="k_post_tile<2> (prolongation + correction + 2 sweeps, 64^2..256^2)",
-    lds="k_lds_mg<4> (LDS-resident grids <= 32^2)",
+    sums="k_sums", pre="k_pre_tile<2> (2 red-black sweeps + residual + restriction, 32^2..256^2)",
+    post="k_stream<2> / k_post_tile<2> (prolongation + correction + 2 sweeps, 32^2..256^2)",
+    lds="k_lds_fmg_fixed, k_lds_vcycle (LDS-resident grids <= 16^2)",
     refine="k_fcg_* (flexible-CG vector passes, grids >= 64^2)")
 
 

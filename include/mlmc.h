@@ -266,7 +266,8 @@ enum {
     MLMC_KERNEL_POST = 9,  /* fused tile pass: prolongation + correction + mu2
                               sweeps; bytes e_c (n^2/4), a, u, f (unless 1) read,
                               u written */
-    MLMC_KERNEL_LDS = 10,  /* LDS-resident hierarchy <= 32^2: a of all its grids
+    MLMC_KERNEL_LDS = 10,  /* LDS-resident hierarchy (up to 16^2 with fixed
+                              cycles, 32^2 with rtol): a of all its grids
                               read, f of its top grid read (V-cycle mode), u of
                               its top grid written */
     MLMC_KERNEL_REFINE = 11 /* rtol mode on grids >= 64^2, the flexible-CG passes

@@ -418,7 +418,7 @@ bool post_uses_stream(int n, int64_t Bc)
     return stream_supported(n) && (o == 1 || (o == -1 && Bc >= kStreamMinBatch));
 }
 
-// ---- fused schedule: LDS-resident grids <= 32^2, tile passes above --------
+// ---- fused schedule: LDS-resident grids (<= 16^2 fixed, <= 32^2 rtol), tile passes above
 // Typed views of one chunk's pools: a, u, f in the V-cycle type T; w holds the
 // FP64 stage solutions of the refinement modes.
 template <typename T>

@@ -114,7 +114,8 @@ void launch_pre_tile(hipStream_t st, int mu1, const T *a, const T *f, const T *u
 template <typename T>
 void launch_post_tile(hipStream_t st, int mu2, const T *a, const T *f, const T *u_in, T *u_out,
                       const T *ec, int n, int64_t Bc, const int32_t *active);
-// LDS-resident hierarchy <= 32^2, one workgroup per sample:
+// LDS-resident hierarchy (up to 32^2; 16^2 in the fixed-cycle schedule), one
+// workgroup per sample:
 // FP64 FMG stages 0..G with fixed cycles and QoI, final u of level G to the pool
 void launch_lds_fmg_fixed(hipStream_t st, const double *a_pool, double *u_pool, int64_t Bc, int G,
                           int mu0, int mu1, int mu2, int g0, double *qoi, int nlev, uint32_t mask);

@@ -13,13 +13,15 @@
 // order exactly.  Face weights and the inverse diagonal of every cell a thread
 // updates are computed once and kept in registers for all half-sweeps.
 //
-// Small grids (n <= 32): one workgroup per sample keeps the whole hierarchy
-// 2^2 .. n^2 in LDS and runs the FMG stages (fixed cycles, or refinement to a
-// residual tolerance with an FP64 residual), or one V-cycle.
+// Small grids (up to 32^2; the fixed-cycle schedule uses them up to 16^2):
+// one workgroup per sample keeps the whole hierarchy 2^2 .. n^2 in LDS and
+// runs the FMG stages (fixed cycles, or refinement to a residual tolerance by
+// flexible CG with an FP64 residual), or one V-cycle.
 //
-// Refinement kernels: FP64 residual of the top grid from the stored
-// coefficient (T) and the FP64 iterate, with per-sample norms and the
-// convergence flags of the loop; u64 += e.
+// Flexible-CG passes for larger grids: FP64 residual of the top grid from the
+// FP64 coefficients and the FP64 iterate, search directions in the V-cycle
+// type, per-sample reproducible two-stage reductions and the convergence flags
+// of the host-driven loop.
 //
 // Block ids of tile passes are remapped so that consecutive tiles of a sample
 // run on the same XCD (blocks are dealt round-robin over the 8 XCDs), which
