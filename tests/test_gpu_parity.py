@@ -516,3 +516,29 @@ def test_uneven_workload_finest_level_sampled(oracle_mod):
     qo, _ = P.batch(k, ys, 0, nthreads=2)
     for b in range(2):
         assert _rel(q[b], qo[b][:, : ctx.nq]) <= 1e-8, b
+
+
+@pytest.mark.parametrize("precision", [m.MLMC_FP64, m.MLMC_MIXED])
+def test_mixed_workload_finest_level_sampled(oracle_mod, precision):
+    """The s = 400 workload's finest level (1024^2) at the launch configuration
+    of the mixed-vs-FP64 measurement: 64 lattice points of shift 0 in one
+    call.  Two samples against the oracle's FP64 FMG with the same stopping
+    rule, both precisions."""
+    dev = _dev()
+    w = synth.workload("mlqmc_mixed_s400")
+    L1, R = w["num_levels"], w["num_shifts"]
+    ctx = m.Context(w["n0"], L1, w["s"], w["corr_len"], w["sigma2"], mu0=w["mu0"], mu1=w["mu1"],
+                    mu2=w["mu2"], rtol=w["rtol"], max_iters=w["max_iters"], precision=precision,
+                    qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
+                    genvec=synth.korobov_vector(w["seed"], w["s"]),
+                    shifts=synth.shift_table(w["seed"], L1, R, w["s"]), max_batch=64, device=0)
+    k = L1 - 1
+    print(f"\nmixed workload finest level {w['n0'] << k}^2, 64 samples, precision {precision}",
+          flush=True)
+    q, _, info = _solve(ctx, ctx.lattice(k, 0, 64, 0, 1), k + 1, info=True)
+    assert np.all(np.isfinite(q)) and info["max_rel_residual"] <= 1e-9, info
+    P = _oracle_problem(oracle_mod, w)
+    _, ys = _lattice_y(oracle_mod, w, k, [0], 0, 2)
+    qo, _ = P.batch(k, ys, 0, nthreads=2)
+    for b in range(2):
+        assert _rel(q[b], qo[b][:, : ctx.nq]) <= 1e-8, b
