@@ -31,6 +31,7 @@ if ROOT not in sys.path:
 METRIC = ("samples/s per level (KL+FMG) mixed vs FP64 at equal QoI error; p50/p99 latency")
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
 
 
 KINDS = ("points", "field", "smooth", "restrict", "prolong", "coarse", "qoi", "sums", "pre", "post",
@@ -86,7 +87,9 @@ def mixed_vs_fp64(m, torch, dev, max_batch=64, min_seconds=0.25):
     FP64 CG with FP32 V-cycles and the bf16 digit-product field.  Per level:
     samples/s of each (lattice points of shift 0, 2^26 / n^2 of them, at most
     65536), their ratio, the largest relative QoI difference between the two,
-    step counts and unconverged samples."""
+    step counts and unconverged samples; the field product's time and
+    TFLOP/s (issued digit-product flops in the mixed path, 20 s M per sample,
+    against the bf16 matrix-core peak; 2 s M in FP64)."""
     import synth
     w = synth.workload("mlqmc_mixed_s400")
     out = dict(workload="mlqmc_mixed_s400: lambda 0.1, sigma^2 2, s = 400, levels 4^2..1024^2, "
@@ -120,6 +123,11 @@ def mixed_vs_fp64(m, torch, dev, max_batch=64, min_seconds=0.25):
                 if time.perf_counter() - t0 >= min_seconds:
                     break
             dt = (time.perf_counter() - t0) / reps
+            c.profile_begin("field")
+            c.fmg_solve(p, qoi=qq)
+            fr = c.profile_end()
+            row[f"{name}_field_ms"] = fr["total_ms"]
+            row[f"{name}_field_tflops"] = fr["flops"] / (fr["total_ms"] * 1e-3) / 1e12
             row[f"{name}_samples_per_s"] = npts / dt
             row[f"{name}_max_steps"] = info["max_iters_used"]
             row[f"{name}_not_converged"] = info["not_converged"]
@@ -127,6 +135,7 @@ def mixed_vs_fp64(m, torch, dev, max_batch=64, min_seconds=0.25):
         row["ratio_mixed_over_fp64"] = row["mixed_samples_per_s"] / row["fp64_samples_per_s"]
         row["max_rel_qoi_diff"] = float(np.max(np.abs(q["mixed"] - q["fp64"]) / np.abs(q["fp64"])))
         out["levels"][f"{n}^2"] = row
+        row["field_digits_frac_of_bf16_peak"] = row["mixed_field_tflops"] / BF16_PEAK_TFLOPS
         log(f"[bench] mixed vs fp64 {n}^2: {row['mixed_samples_per_s']:.0f} vs "
             f"{row['fp64_samples_per_s']:.0f} samples/s (x{row['ratio_mixed_over_fp64']:.2f}), "
             f"max rel diff {row['max_rel_qoi_diff']:.1e}")
