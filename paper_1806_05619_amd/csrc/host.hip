@@ -1080,7 +1080,7 @@ mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts, const double *z
         info->max_rel_residual = ctx->cfg.rtol > 0.0 ? stats.max_rho : -1.0;
         info->not_converged = stats.noconv;
         if (stats.noconv > 0) {
-            ctx->err = "refinement reached max_iters before rtol";
+            ctx->err = "refinement stopped above rtol (max_iters or the rounding floor)";
             return MLMC_E_NOCONV;
         }
     }
