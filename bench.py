@@ -36,11 +36,14 @@ BF16_PEAK_TFLOPS = 2500.0
 
 KINDS = ("points", "field", "smooth", "restrict", "prolong", "coarse", "qoi", "sums", "pre", "post",
          "lds", "refine")
+KIND_NAMES = {0: "tile32", 1: "tile16", 2: "stream"}
 KERNEL_NAMES = dict(
     points="k_points", field="k_field_mfma64", smooth="k_rbgs (one colour)",
     restrict="k_resid_restrict", prolong="k_prolong", coarse="k_coarse_solve", qoi="k_qoi",
-    sums="k_sums", pre="k_pre_tile<2> (2 red-black sweeps + residual + restriction, 32^2..256^2)",
-    post="k_stream<2> / k_post_tile<2> (prolongation + correction + 2 sweeps, 32^2..256^2)",
+    sums="k_sums",
+    pre="k_pre_tile<32,256,2,double> (2 red-black sweeps + residual + restriction, 32^2..256^2)",
+    post="k_stream<2,post> / k_post_tile<32,256,2,double> (prolongation + correction + 2 sweeps, "
+         "32^2..256^2)",
     lds="k_lds_fmg_fixed, k_lds_vcycle (LDS-resident grids <= 16^2)",
     refine="k_fcg_* (flexible-CG vector passes, grids >= 64^2)")
 
@@ -412,6 +415,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default pass kinds instead of measuring them first")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip per-level, latency and CPU-baseline measurements")
@@ -478,6 +483,16 @@ def main():
         torch.cuda.synchronize()
         log("[bench] copy calibration: 1 GiB read + 1 GiB written")
         del src, dst
+    tune = None
+    if not args.no_autotune:
+        # pass kinds of the tile grids measured on this device (setup, untimed)
+        ta = time.perf_counter()
+        table = ctx.autotune(k)
+        tune = dict(seconds=time.perf_counter() - ta,
+                    measured=[[e["n"], e["batch_class"], KIND_NAMES[e["pre"]], KIND_NAMES[e["post"]],
+                               round(e["pre_ms"], 4), round(e["post_ms"], 4)]
+                              for e in table if e["pre_ms"] > 0])
+        log(f"[bench] autotune {tune['seconds']:.2f} s")
     log(f"[bench] workload mlqmc_fp64_s100 level {k}: {B} samples, warmup {args.warmup}")
     for _ in range(args.warmup):
         step()
@@ -535,6 +550,7 @@ def main():
                estimate=dict(q_bar=float(est["q_bar"][0]), std=float(np.sqrt(est["var_q"][0]))))
 
     out["kernel_breakdown_one_step"] = breakdown
+    out["autotune"] = tune
     if not args.no_extras:
         # samples/s per level, same batch size (16384 samples finest at each level)
         per_level = {}

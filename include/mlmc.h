@@ -286,6 +286,49 @@ typedef struct {
 mlmc_status mlmc_profile_begin(mlmc_ctx ctx, int32_t kernel_kind);
 mlmc_status mlmc_profile_end(mlmc_ctx ctx, mlmc_profile_result *out);
 
+/* ---- Pass kinds of the large grids and their autotuner -------------------
+ * Every V-cycle level above the LDS-resident grids runs one pre pass (mu1
+ * red-black sweeps, residual, restriction) and one post pass (prolongation,
+ * correction, mu2 sweeps) per cycle, each in one of these kinds:
+ *   MLMC_PASS_TILE32  32 x 32 cells and a halo per 256-thread workgroup
+ *   MLMC_PASS_TILE16  16 x 16 cells per 128-thread workgroup (four times the
+ *                     workgroups: for batches too small to fill the chip)
+ *   MLMC_PASS_STREAM  one workgroup per sample streaming rows through LDS
+ *                     (FP64 V-cycles, 64 <= n <= 512 only)
+ * All kinds give the bits of the same global sweep order, so the choice
+ * changes only the time.  The choice is kept per context for each grid side
+ * n and batch class c: chunks of Bc samples with 4^(c-1) < Bc <= 4^c (c = 0
+ * for one sample), c < MLMC_BATCH_CLASSES (the last class takes every larger
+ * chunk).  A new context starts from defaults measured on MI355X, a rule in
+ * the number of 32 x 32 tiles of the pass, t = 4^c (n/32)^2: TILE16 for
+ * t <= 256; STREAM for the post pass when t >= 65536 and n >= 128 (FP64);
+ * TILE32 otherwise.  A server's slots take the first slot's table. */
+enum { MLMC_PASS_TILE32 = 0, MLMC_PASS_TILE16 = 1, MLMC_PASS_STREAM = 2 };
+enum { MLMC_BATCH_CLASSES = 10 };
+typedef struct {
+    int32_t n;             /* grid side of the pass (cells per side) */
+    int32_t batch_class;   /* c above */
+    int32_t pre, post;     /* MLMC_PASS_* */
+    double pre_ms, post_ms;  /* one launch as measured by mlmc_autotune (at
+                                min(4^c, capacity) samples); 0 if not measured */
+} mlmc_tune_entry;
+/* Measures every allowed kind of both passes on every tile grid of levels
+ * <= level, for every batch class up to the level's chunk capacity, on the
+ * context's own workspace (its contents are overwritten; stream-ordered on
+ * hip_stream, synchronous on return), and installs the fastest.  Solves
+ * already enqueued on other streams must have finished.  E_INVAL for a level
+ * out of range, E_STATE for a host-only context. */
+mlmc_status mlmc_autotune(mlmc_ctx ctx, int32_t level, void *hip_stream);
+/* The context's table: one entry per tile grid (coarsest first) and batch
+ * class; writes at most max_entries and the full count to *count (host). */
+mlmc_status mlmc_tuning_get(mlmc_ctx ctx, mlmc_tune_entry *out, int32_t max_entries,
+                            int32_t *count);
+/* Installs the kinds of `count` entries (a saved table, or a forced choice);
+ * E_INVAL, before any change, if an entry names a grid that is not a tile
+ * grid of the context, a class out of range or a kind the grid does not
+ * support. */
+mlmc_status mlmc_tuning_set(mlmc_ctx ctx, const mlmc_tune_entry *in, int32_t count);
+
 /* ---- Serving loop: continuous batching of solve requests ----------------
  * A server owns num_slots copies of one configuration, each with its own HIP
  * stream, workspace for slot_samples samples and a host thread; the HBM

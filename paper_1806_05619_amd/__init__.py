@@ -27,6 +27,8 @@ MLMC_OK, MLMC_E_INVAL, MLMC_E_NOMEM, MLMC_E_HIP, MLMC_E_NOCONV, MLMC_E_STATE = 0
 MLMC_FP64, MLMC_MIXED = 0, 1
 MLMC_QOI_MEAN, MLMC_QOI_CENTER = 1, 2
 MLMC_POINTS_LATTICE, MLMC_POINTS_EXPLICIT = 0, 1
+MLMC_PASS_TILE32, MLMC_PASS_TILE16, MLMC_PASS_STREAM = 0, 1, 2
+MLMC_BATCH_CLASSES = 10
 
 
 class mlmc_config(C.Structure):
@@ -52,6 +54,11 @@ class mlmc_solve_info(C.Structure):
 class mlmc_profile_result(C.Structure):
     _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("bytes", C.c_double),
                 ("flops", C.c_double)]
+
+
+class mlmc_tune_entry(C.Structure):
+    _fields_ = [("n", C.c_int32), ("batch_class", C.c_int32), ("pre", C.c_int32),
+                ("post", C.c_int32), ("pre_ms", C.c_double), ("post_ms", C.c_double)]
 
 
 MLMC_KERNEL = dict(points=0, field=1, smooth=2, restrict=3, prolong=4, coarse=5, qoi=6, sums=7,
@@ -91,7 +98,8 @@ EXPORTS = [
     "mlmc_field", "mlmc_fmg_solve", "mlmc_estimate", "mlmc_kl_modes", "mlmc_fmg_trace",
     "mlmc_status_str", "mlmc_last_error", "mlmc_profile_begin", "mlmc_profile_end",
     "mlmc_server_create", "mlmc_server_destroy", "mlmc_server_submit", "mlmc_server_poll",
-    "mlmc_server_stats_get", "mlmc_server_capacity",
+    "mlmc_server_stats_get", "mlmc_server_capacity", "mlmc_autotune", "mlmc_tuning_get",
+    "mlmc_tuning_set",
 ]
 
 _lib = None
@@ -132,6 +140,9 @@ def lib():
         "mlmc_server_poll": (i32, [vp, C.POINTER(mlmc_result), i32, i32, C.POINTER(i32)]),
         "mlmc_server_stats_get": (i32, [vp, C.POINTER(mlmc_server_stats)]),
         "mlmc_server_capacity": (i64, [vp, i32]),
+        "mlmc_autotune": (i32, [vp, i32, vp]),
+        "mlmc_tuning_get": (i32, [vp, C.POINTER(mlmc_tune_entry), i32, C.POINTER(i32)]),
+        "mlmc_tuning_set": (i32, [vp, C.POINTER(mlmc_tune_entry), i32]),
         "mlmc_status_str": (C.c_char_p, [i32]),
         "mlmc_last_error": (C.c_char_p, [vp]),
     }
@@ -275,6 +286,32 @@ class Context:
         r = mlmc_profile_result()
         _check(lib().mlmc_profile_end(self._h, C.byref(r)), self._h)
         return dict(launches=r.launches, total_ms=r.total_ms, bytes=r.bytes, flops=r.flops)
+
+    def autotune(self, level=None):
+        """Measure the pass kinds of every tile grid up to `level` (default:
+        the finest) and batch class on this context's stream; install the
+        fastest.  Returns the table (see tuning())."""
+        lev = self.cfg.num_levels - 1 if level is None else int(level)
+        _check(lib().mlmc_autotune(self._h, lev, self._stream()), self._h)
+        return self.tuning()
+
+    def tuning(self):
+        """The pass-kind table: dicts n, batch_class, pre, post, pre_ms, post_ms."""
+        cnt = C.c_int32(0)
+        _check(lib().mlmc_tuning_get(self._h, None, 0, C.byref(cnt)), self._h)
+        arr = (mlmc_tune_entry * max(cnt.value, 1))()
+        _check(lib().mlmc_tuning_get(self._h, arr, cnt.value, C.byref(cnt)), self._h)
+        return [dict(n=e.n, batch_class=e.batch_class, pre=e.pre, post=e.post, pre_ms=e.pre_ms,
+                     post_ms=e.post_ms) for e in arr[:cnt.value]]
+
+    def set_tuning(self, entries):
+        """Install pass kinds: an iterable of dicts with n, batch_class, pre, post."""
+        entries = list(entries)
+        arr = (mlmc_tune_entry * max(len(entries), 1))()
+        for k, e in enumerate(entries):
+            arr[k] = mlmc_tune_entry(int(e["n"]), int(e["batch_class"]), int(e["pre"]),
+                                     int(e["post"]), 0.0, 0.0)
+        _check(lib().mlmc_tuning_set(self._h, arr, len(entries)), self._h)
 
     def kl_modes(self):
         s = self.cfg.s

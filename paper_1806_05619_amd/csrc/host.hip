@@ -60,6 +60,12 @@ struct mlmc_ctx_s {
     int32_t *d_st_iters = nullptr, *d_st_bad = nullptr;
     double *d_st_rho = nullptr;      // per-sample refinement statistics of a chunk
     int elem = 8;                    // bytes per pool element (4 in the mixed mode)
+    // pass kinds of the tile grids: [MG level g][batch class], with the
+    // durations mlmc_autotune measured for them (0: not measured)
+    int8_t pre_kind[kMaxMgLevels][MLMC_BATCH_CLASSES] = {};
+    int8_t post_kind[kMaxMgLevels][MLMC_BATCH_CLASSES] = {};
+    double pre_ms[kMaxMgLevels][MLMC_BATCH_CLASSES] = {};
+    double post_ms[kMaxMgLevels][MLMC_BATCH_CLASSES] = {};
     int32_t *h_active = nullptr, *h_iters = nullptr;
     double *h_rho = nullptr;
     std::vector<void *> allocs;
@@ -397,25 +403,40 @@ mlmc_status run_fmg(mlmc_ctx c, hipStream_t st, const Hier &h, int k, double *qo
     return MLMC_OK;
 }
 
-// Large-grid pass kind per pass, chosen by measurement on MI355X (256^2 FP64,
-// 16384 samples): LDS tiles for the pre pass, row streaming for the post pass.
-// MLMC_LARGE_PASS=tile|stream forces one kind for both (tuning runs).
-int large_pass_override()
+// ---- pass kinds of the tile grids (mlmc_autotune) --------------------------
+// batch class of a chunk of Bc samples: 4^(c-1) < Bc <= 4^c, c = 0 for one
+int batch_class(int64_t Bc)
 {
-    static const int mode = [] {
-        const char *e = std::getenv("MLMC_LARGE_PASS");
-        return !e ? -1 : (std::strcmp(e, "tile") == 0 ? 0 : (std::strcmp(e, "stream") == 0 ? 1 : -1));
-    }();
-    return mode;
+    int c = 0;
+    while (c + 1 < MLMC_BATCH_CLASSES && ((int64_t)1 << (2 * c)) < Bc) ++c;
+    return c;
 }
-// The row-streaming pass runs one workgroup per sample, so it needs a batch
-// that fills the chip (a few workgroups per CU) before it beats the tiles.
-constexpr int64_t kStreamMinBatch = 1024;
-bool pre_uses_stream(int n) { return large_pass_override() == 1 && stream_supported(n); }
-bool post_uses_stream(int n, int64_t Bc)
+// top MG level of the LDS-resident grids; the tile grids lie above it
+int lds_top(mlmc_ctx c) { return c->cfg.rtol > 0.0 ? kLdsMaxLevel : kLdsMaxLevelFixed; }
+bool kind_allowed(mlmc_ctx c, int g, int kind)
 {
-    const int o = large_pass_override();
-    return stream_supported(n) && (o == 1 || (o == -1 && Bc >= kStreamMinBatch));
+    if (kind == kTile32 || kind == kTile16) return true;
+    // the row-streaming passes exist for FP64 V-cycles
+    return kind == kStream && c->cfg.precision == MLMC_FP64 && stream_supported(2 << g);
+}
+// Defaults: the choices mlmc_autotune made on MI355X for the s = 100 FP64
+// workload (grids 32^2 .. 256^2, batch classes up to 16384 samples), as a
+// rule in the number of 32 x 32 tiles a pass covers, 4^c (n/32)^2: up to 256
+// (one per CU or fewer) 16 x 16 tiles, which give four times the workgroups;
+// from 65536 on row streaming for the post pass where it exists; 32 x 32
+// tiles otherwise.
+void default_tuning(mlmc_ctx c)
+{
+    for (int g = 0; g < kMaxMgLevels; ++g) {
+        const int64_t side = std::max(1, (2 << g) / 32);
+        for (int cl = 0; cl < MLMC_BATCH_CLASSES; ++cl) {
+            const int64_t tiles = ((int64_t)1 << (2 * cl)) * side * side;
+            const int8_t tile = tiles <= 256 ? kTile16 : kTile32;
+            c->pre_kind[g][cl] = tile;
+            c->post_kind[g][cl] =
+                tiles >= 65536 && (2 << g) >= 128 && kind_allowed(c, g, kStream) ? kStream : tile;
+        }
+    }
 }
 
 // ---- fused schedule: LDS-resident grids (<= 16^2 fixed, <= 32^2 rtol), tile passes above
@@ -476,6 +497,7 @@ struct FusedRunner {
     // u (top_u on the top level), so no pass reads the array it writes.
     void vcycle(int g, T *top_u, int init_top, const T *top_f, const int32_t *active)
     {
+        const int cls = batch_class(h.Bc);
         for (int l = g; l > Gs; --l) {
             const int n = 2 << l;
             const int init = (l == g) ? init_top : 1;
@@ -484,15 +506,16 @@ struct FusedRunner {
             double words = 1.0 + (init == 0 ? 1.0 : 0.0) + (f ? 1.0 : 0.0) + 1.0 + 0.25 +
                            (init == 2 ? 0.25 : 0.0);
             ProfScope ps(c, st, MLMC_KERNEL_PRE, W * cells(n) * words, 0.0);
+            const int kind = c->pre_kind[l][cls];
             if constexpr (std::is_same<T, double>::value) {
-                if (pre_uses_stream(n)) {
+                if (kind == kStream) {
                     launch_pre_stream(st, c->cfg.mu1, h.a[l], f, u, h.ua[l], h.u[l - 1], n, h.Bc,
                                       init, h.f[l - 1], active);
                     continue;
                 }
             }
-            launch_pre_tile<T>(st, c->cfg.mu1, h.a[l], f, u, h.ua[l], h.u[l - 1], n, h.Bc, init,
-                               h.f[l - 1], active);
+            launch_pre_tile<T>(st, kind, c->cfg.mu1, h.a[l], f, u, h.ua[l], h.u[l - 1], n, h.Bc,
+                               init, h.f[l - 1], active);
         }
         lds_vcycle(active);
         for (int l = Gs + 1; l <= g; ++l) {
@@ -500,14 +523,15 @@ struct FusedRunner {
             const T *f = (l == g) ? top_f : h.f[l];
             T *u = (l == g) ? top_u : h.u[l];
             ProfScope ps(c, st, MLMC_KERNEL_POST, W * cells(n) * (3.25 + (f ? 1.0 : 0.0)), 0.0);
+            const int kind = c->post_kind[l][cls];
             if constexpr (std::is_same<T, double>::value) {
-                if (post_uses_stream(n, h.Bc)) {
+                if (kind == kStream) {
                     launch_post_stream(st, c->cfg.mu2, h.a[l], f, h.ua[l], u, h.u[l - 1], n, h.Bc,
                                        active);
                     continue;
                 }
             }
-            launch_post_tile<T>(st, c->cfg.mu2, h.a[l], f, h.ua[l], u, h.u[l - 1], n, h.Bc,
+            launch_post_tile<T>(st, kind, c->cfg.mu2, h.a[l], f, h.ua[l], u, h.u[l - 1], n, h.Bc,
                                 active);
         }
     }
@@ -780,6 +804,7 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
     }
 
     ctx->Mmax = field_size_g(Gmax);
+    default_tuning(ctx);
     if (ctx->host_only) {
         *out = ctx;
         return MLMC_OK;
@@ -861,6 +886,14 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
     CHK(hipHostMalloc((void **)&ctx->h_iters, sizeof(int32_t) * ctx->chunk_max, hipHostMallocDefault));
     CHK(hipHostMalloc((void **)&ctx->h_rho, sizeof(double) * ctx->chunk_max, hipHostMallocDefault));
     if (parent) {
+        const mlmc_config &q = parent->cfg;
+        if (q.precision == c.precision && (q.rtol > 0.0) == (c.rtol > 0.0) && q.mu1 == c.mu1 &&
+            q.mu2 == c.mu2) {
+            std::memcpy(ctx->pre_kind, parent->pre_kind, sizeof(ctx->pre_kind));
+            std::memcpy(ctx->post_kind, parent->post_kind, sizeof(ctx->post_kind));
+            std::memcpy(ctx->pre_ms, parent->pre_ms, sizeof(ctx->pre_ms));
+            std::memcpy(ctx->post_ms, parent->post_ms, sizeof(ctx->post_ms));
+        }
         ctx->d_basis = parent->d_basis;
         for (int i = 0; i < 4; ++i) ctx->d_bdig[i] = parent->d_bdig[i];
         ctx->d_bexp = parent->d_bexp;
@@ -918,6 +951,184 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
     *out = ctx;
     return MLMC_OK;
 }
+
+namespace {
+
+// Durations of one pre and one post pass of every allowed kind on tile grid g
+// for Bc samples, on the workspace (a = f = 1, u = 0: the time does not depend
+// on the values).  Each: one warm-up launch, then the best of two runs of
+// `reps` launches between events.
+template <typename T>
+mlmc_status tune_grid(mlmc_ctx c, hipStream_t st, int g, int64_t Bc, int cls, hipEvent_t e0,
+                      hipEvent_t e1)
+{
+    HierT<T> h = make_hier_t<T>(c, g, Bc);
+    const int n = 2 << g;
+    const int64_t cells = Bc * (int64_t)n * n;
+    const int64_t coarse = cells / 4;
+    if constexpr (std::is_same<T, double>::value) {
+        launch_fill(st, h.a[g], cells, 1.0);
+        launch_fill(st, h.f[g], cells, 1.0);
+        launch_fill(st, h.u[g], cells, 0.0);
+        launch_fill(st, h.u[g - 1], coarse, 0.0);
+    } else {
+        launch_fill_f32(st, h.a[g], cells, 1.0f);
+        launch_fill_f32(st, h.f[g], cells, 1.0f);
+        launch_fill_f32(st, h.u[g], cells, 0.0f);
+        launch_fill_f32(st, h.u[g - 1], coarse, 0.0f);
+    }
+    const int reps = cells >= ((int64_t)1 << 22) ? 3 : 10;
+    double ms_best = 0.0;
+    auto time_it = [&](auto launch) -> hipError_t {
+        launch();
+        ms_best = 1e300;
+        for (int r = 0; r < 2; ++r) {
+            hipError_t e = hipEventRecord(e0, st);
+            for (int i = 0; i < reps && e == hipSuccess; ++i) launch();
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess) e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            ms_best = std::min(ms_best, (double)ms / reps);
+        }
+        return hipSuccess;
+    };
+    const int kinds[] = {kTile32, kTile16, kStream};
+    double best_pre = 1e300, best_post = 1e300;
+    for (int kind : kinds) {
+        if (!kind_allowed(c, g, kind)) continue;
+        auto pre = [&] {
+            if constexpr (std::is_same<T, double>::value) {
+                if (kind == kStream) {
+                    launch_pre_stream(st, c->cfg.mu1, h.a[g], h.f[g], h.u[g], h.ua[g], h.u[g - 1],
+                                      n, Bc, 1, h.f[g - 1], nullptr);
+                    return;
+                }
+            }
+            launch_pre_tile<T>(st, kind, c->cfg.mu1, h.a[g], h.f[g], h.u[g], h.ua[g], h.u[g - 1], n,
+                               Bc, 1, h.f[g - 1], nullptr);
+        };
+        auto post = [&] {
+            if constexpr (std::is_same<T, double>::value) {
+                if (kind == kStream) {
+                    launch_post_stream(st, c->cfg.mu2, h.a[g], h.f[g], h.ua[g], h.u[g], h.u[g - 1],
+                                       n, Bc, nullptr);
+                    return;
+                }
+            }
+            launch_post_tile<T>(st, kind, c->cfg.mu2, h.a[g], h.f[g], h.ua[g], h.u[g], h.u[g - 1],
+                                n, Bc, nullptr);
+        };
+        HIPCHK(c, time_it(pre));
+        if (ms_best < best_pre) {
+            best_pre = ms_best;
+            c->pre_kind[g][cls] = (int8_t)kind;
+        }
+        HIPCHK(c, time_it(post));
+        if (ms_best < best_post) {
+            best_post = ms_best;
+            c->post_kind[g][cls] = (int8_t)kind;
+        }
+    }
+    c->pre_ms[g][cls] = best_pre;
+    c->post_ms[g][cls] = best_post;
+    return MLMC_OK;
+}
+
+// tile grids of a context: MG levels lds_top < g <= Gmax (none without the
+// fused passes)
+int first_tile_grid(mlmc_ctx c) { return lds_top(c) + 1; }
+int tile_grid_count(mlmc_ctx c)
+{
+    return use_fused(c) ? std::max(0, c->Gmax - lds_top(c)) : 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+mlmc_status mlmc_autotune(mlmc_ctx ctx, int32_t level, void *hip_stream)
+{
+    if (!ctx) return MLMC_E_INVAL;
+    if (ctx->broken || ctx->host_only) return MLMC_E_STATE;
+    if (level < 0 || level >= ctx->cfg.num_levels) return inval(ctx, "level out of range");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if (tile_grid_count(ctx) == 0) return MLMC_OK;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        ctx->err = "hipEventCreate failed";
+        ctx->broken = true;
+        return MLMC_E_HIP;
+    }
+    mlmc_status r = MLMC_OK;
+    for (int g = first_tile_grid(ctx); g <= ctx->g0 + level && r == MLMC_OK; ++g) {
+        const int64_t cap = chunk_capacity(ctx, std::max(0, g - ctx->g0));
+        for (int cl = 0; cl < MLMC_BATCH_CLASSES && r == MLMC_OK; ++cl) {
+            const int64_t lo = cl == 0 ? 1 : ((int64_t)1 << (2 * (cl - 1))) + 1;
+            if (lo > cap) break;
+            const int64_t Bc = cl + 1 == MLMC_BATCH_CLASSES
+                                   ? cap
+                                   : std::min<int64_t>((int64_t)1 << (2 * cl), cap);
+            r = ctx->cfg.precision == MLMC_MIXED ? tune_grid<float>(ctx, st, g, Bc, cl, e0, e1)
+                                                 : tune_grid<double>(ctx, st, g, Bc, cl, e0, e1);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return r;
+}
+
+mlmc_status mlmc_tuning_get(mlmc_ctx ctx, mlmc_tune_entry *out, int32_t max_entries,
+                            int32_t *count)
+{
+    if (!ctx || !count || max_entries < 0 || (max_entries > 0 && !out)) return MLMC_E_INVAL;
+    int32_t k = 0;
+    const int g1 = first_tile_grid(ctx);
+    for (int g = g1; g < g1 + tile_grid_count(ctx); ++g)
+        for (int cl = 0; cl < MLMC_BATCH_CLASSES; ++cl, ++k) {
+            if (k >= max_entries) continue;
+            mlmc_tune_entry &e = out[k];
+            e.n = 2 << g;
+            e.batch_class = cl;
+            e.pre = ctx->pre_kind[g][cl];
+            e.post = ctx->post_kind[g][cl];
+            e.pre_ms = ctx->pre_ms[g][cl];
+            e.post_ms = ctx->post_ms[g][cl];
+        }
+    *count = k;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_tuning_set(mlmc_ctx ctx, const mlmc_tune_entry *in, int32_t count)
+{
+    if (!ctx || count < 0 || (count > 0 && !in)) return MLMC_E_INVAL;
+    const int g1 = first_tile_grid(ctx), g2 = g1 + tile_grid_count(ctx);
+    for (int32_t i = 0; i < count; ++i) {
+        const mlmc_tune_entry &e = in[i];
+        const int g = ilog2_exact(e.n) - 1;
+        if (g < g1 || g >= g2) return inval(ctx, "tuning entry: n is not a tile grid of this context");
+        if (e.batch_class < 0 || e.batch_class >= MLMC_BATCH_CLASSES)
+            return inval(ctx, "tuning entry: batch class out of range");
+        if (!kind_allowed(ctx, g, e.pre) || !kind_allowed(ctx, g, e.post))
+            return inval(ctx, "tuning entry: pass kind not available on this grid");
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        const mlmc_tune_entry &e = in[i];
+        const int g = ilog2_exact(e.n) - 1;
+        ctx->pre_kind[g][e.batch_class] = (int8_t)e.pre;
+        ctx->post_kind[g][e.batch_class] = (int8_t)e.post;
+        ctx->pre_ms[g][e.batch_class] = 0.0;
+        ctx->post_ms[g][e.batch_class] = 0.0;
+    }
+    return MLMC_OK;
+}
+
+}  // extern "C"
 
 extern "C" {
 

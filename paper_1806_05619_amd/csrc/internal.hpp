@@ -98,6 +98,7 @@ void launch_qoi(hipStream_t st, const double *u, int n, int64_t Bc, double *qoi,
                 int l, uint32_t mask, double *part);
 int64_t qoi_partials(int64_t pool_cells);
 void launch_fill(hipStream_t st, double *p, int64_t count, double v);
+void launch_fill_f32(hipStream_t st, float *p, int64_t count, float v);
 void launch_fill_i32(hipStream_t st, int32_t *p, int64_t count, int32_t v);
 void launch_sums(hipStream_t st, const double *qoi, int nlev, int nq, int64_t b0, int64_t Bc,
                  int64_t npts, int nshift, double *state);
@@ -105,15 +106,19 @@ void launch_sums_final(hipStream_t st, const double *state, int64_t count, doubl
 
 // ---- fused kernels (kernels_fused.hip), T = double or float ----
 bool fused_supported(int mu1, int mu2);
-// pre pass on level n: init 0 read u_in, 1 zero guess, 2 u = P uc; writes u_out
-// (never u_in: tiles read their neighbours' cells) and fc
+// pass kinds of the tile grids (the MLMC_PASS_* values)
+constexpr int kTile32 = MLMC_PASS_TILE32, kTile16 = MLMC_PASS_TILE16, kStream = MLMC_PASS_STREAM;
+// pre pass on level n with tile shape kTile32 or kTile16: init 0 read u_in, 1
+// zero guess, 2 u = P uc; writes u_out (never u_in: tiles read their
+// neighbours' cells) and fc
 template <typename T>
-void launch_pre_tile(hipStream_t st, int mu1, const T *a, const T *f, const T *u_in, T *u_out,
-                     const T *uc, int n, int64_t Bc, int init, T *fc, const int32_t *active);
+void launch_pre_tile(hipStream_t st, int shape, int mu1, const T *a, const T *f, const T *u_in,
+                     T *u_out, const T *uc, int n, int64_t Bc, int init, T *fc,
+                     const int32_t *active);
 // post pass on level n: u = u_in + P ec, then mu2 sweeps, into u_out (!= u_in)
 template <typename T>
-void launch_post_tile(hipStream_t st, int mu2, const T *a, const T *f, const T *u_in, T *u_out,
-                      const T *ec, int n, int64_t Bc, const int32_t *active);
+void launch_post_tile(hipStream_t st, int shape, int mu2, const T *a, const T *f, const T *u_in,
+                      T *u_out, const T *ec, int n, int64_t Bc, const int32_t *active);
 // LDS-resident hierarchy (up to 32^2; 16^2 in the fixed-cycle schedule), one
 // workgroup per sample:
 // FP64 FMG stages 0..G with fixed cycles and QoI, final u of level G to the pool

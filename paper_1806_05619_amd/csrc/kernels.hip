@@ -410,6 +410,13 @@ __global__ void k_fill(double *p, int64_t count, double v)
         p[t] = v;
 }
 
+__global__ void k_fill_f32(float *p, int64_t count, float v)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count)
+        p[t] = v;
+}
+
 __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t v)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -547,6 +554,13 @@ void launch_fill(hipStream_t st, double *p, int64_t count, double v)
     if (count <= 0)
         return;
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(count)), dim3(kBlock), 0, st, p, count, v);
+}
+
+void launch_fill_f32(hipStream_t st, float *p, int64_t count, float v)
+{
+    if (count <= 0)
+        return;
+    hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(count)), dim3(kBlock), 0, st, p, count, v);
 }
 
 void launch_fill_i32(hipStream_t st, int32_t *p, int64_t count, int32_t v)

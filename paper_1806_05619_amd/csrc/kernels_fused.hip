@@ -3,7 +3,9 @@
 // the FP64 path, float for the FP32 V-cycles of the mixed-precision path).
 //
 // Large grids (n >= 64): temporally blocked tile passes.  One workgroup owns a
-// 32 x 32 tile of one sample and stages the tile plus a halo of u and a in LDS:
+// 32 x 32 tile of one sample (256 threads; or a 16 x 16 tile with 128 threads,
+// four times the workgroups for small batches) and stages the tile plus a halo
+// of u and a in LDS:
 //   pre pass  : mu1 red-black sweeps (red first), residual, 4-cell restriction
 //               -> writes u (tile) and the coarse right-hand side;
 //   post pass : bilinear prolongation of the coarse correction, mu2 sweeps
@@ -31,8 +33,6 @@
 namespace mlmc {
 namespace {
 
-constexpr int TILE = 32;
-constexpr int NT = 256;                 // threads per tile workgroup
 
 // 1/x for the well-scaled positive values of this path (coefficients within
 // e^+-15 and sums of them): hardware reciprocal estimate refined by Newton
@@ -76,7 +76,7 @@ __device__ __forceinline__ T codd(const T *__restrict__ e, int nc, int I, int J)
 
 // Coarse values needed to prolongate onto a fine region [fi0, fi0+S)^2, staged
 // in LDS with the odd wall reflection already applied (indices -1 and nc).
-template <int S, typename T>
+template <int S, int NT, typename T>
 struct CoarseStage {
     static constexpr int CS = S / 2 + 3;
     __device__ static void load(T *cs, const T *__restrict__ e, int nc, int cI0, int cJ0)
@@ -123,8 +123,7 @@ __device__ __forceinline__ void make_cell(Cell<T> &c, const T *a_s, int li, int 
     c.wW = gi > 0 ? hm(ap, a_s[l - 1]) : wall;
     c.wN = gj + 1 < n ? hm(ap, a_s[l + S]) : wall;
     c.wS = gj > 0 ? hm(ap, a_s[l - S]) : wall;
-    T d = T(0);
-    d += c.wE;
+    T d = c.wE;
     d += c.wW;
     d += c.wN;
     d += c.wS;
@@ -148,7 +147,7 @@ __device__ __forceinline__ void relax(const Cell<T> &c, T *u_s)
 
 // Owned cells of one colour inside the square ring [lo, S-lo)^2 of the region.
 // q-th cell: row r = q / half, column 2*(q % half) + parity.
-template <int S, int LO, int COLOUR>
+template <int S, int NT, int LO, int COLOUR>
 struct OwnSet {
     static constexpr int SIDE = S - 2 * LO;
     static constexpr int COUNT = SIDE * SIDE / 2;
@@ -166,11 +165,11 @@ struct OwnSet {
 
 // Region loads: all global loads first (memory-level parallelism), then LDS.
 // mode 0: u = u; 1: u = 0; 2: u = P(coarse); 3: u = u + P(coarse)
-template <int S, int H, typename T>
+template <int S, int NT, int H, typename T>
 __device__ __forceinline__ void load_region(T *a_s, T *u_s, const T *c_s, const T *ab, const T *ub,
                                             int n, int i0, int j0, int cI0, int cJ0, int mode)
 {
-    using CSt = CoarseStage<S, T>;
+    using CSt = CoarseStage<S, NT, T>;
     constexpr int PERT = (S * S + NT - 1) / NT;
     T av[PERT], uv[PERT];
 #pragma unroll
@@ -200,11 +199,11 @@ __device__ __forceinline__ void load_region(T *a_s, T *u_s, const T *c_s, const 
     __syncthreads();
 }
 
-template <int S, int LO, int COLOUR, typename T>
+template <int S, int NT, int LO, int COLOUR, typename T>
 __device__ __forceinline__ void make_cells(Cell<T> *cs, const T *a_s, const T *fb, int n, int i0,
                                            int j0, int H, T h2)
 {
-    using Own = OwnSet<S, LO, COLOUR>;
+    using Own = OwnSet<S, NT, LO, COLOUR>;
 #pragma unroll
     for (int k = 0; k < Own::PER; ++k) {
         const int q = threadIdx.x + NT * k;
@@ -233,7 +232,7 @@ __device__ __forceinline__ void sweep_ring(const Cell<T> *cs, T *u_s, int lo)
 // init: 0 = read u_in, 1 = zero initial guess, 2 = FMG interpolation from uc.
 // The result goes to u_out, which no block of the launch reads: a tile reads
 // its neighbours' cells as halo, so an in-place write would race with them.
-template <int MU, typename T>
+template <int TILE, int NT, int MU, typename T>
 __global__ __launch_bounds__(NT) void k_pre_tile(const T *__restrict__ a, const T *__restrict__ f,
                                                  const T *__restrict__ u_in, T *__restrict__ u_out,
                                                  const T *__restrict__ uc, int n,
@@ -242,9 +241,9 @@ __global__ __launch_bounds__(NT) void k_pre_tile(const T *__restrict__ a, const 
 {
     constexpr int H = 2 * MU + 1;
     constexpr int S = TILE + 2 * H;
-    using Red = OwnSet<S, 1, 0>;              // red cells are updated within ring H-1
-    using Blk = OwnSet<S, 2, 1>;              // black cells within ring H-2
-    using CSt = CoarseStage<S, T>;
+    using Red = OwnSet<S, NT, 1, 0>;          // red cells are updated within ring H-1
+    using Blk = OwnSet<S, NT, 2, 1>;          // black cells within ring H-2
+    using CSt = CoarseStage<S, NT, T>;
     __shared__ T u_s[S * S];
     __shared__ T a_s[S * S];
     // the coarse values for the interpolation are read before a_s is written
@@ -271,11 +270,11 @@ __global__ __launch_bounds__(NT) void k_pre_tile(const T *__restrict__ a, const 
         CSt::load(c_s, uc + b * (int64_t)nc * nc, nc, cI0, cJ0);
         __syncthreads();
     }
-    load_region<S, H>(a_s, u_s, c_s, ab, ub, n, i0, j0, cI0, cJ0, init);
+    load_region<S, NT, H>(a_s, u_s, c_s, ab, ub, n, i0, j0, cI0, cJ0, init);
 
     Cell<T> red[Red::PER], blk[Blk::PER];
-    make_cells<S, 1, 0>(red, a_s, fb, n, i0, j0, H, h2);
-    make_cells<S, 2, 1>(blk, a_s, fb, n, i0, j0, H, h2);
+    make_cells<S, NT, 1, 0>(red, a_s, fb, n, i0, j0, H, h2);
+    make_cells<S, NT, 2, 1>(blk, a_s, fb, n, i0, j0, H, h2);
     // half-sweep t (1-based) covers ring H - t around the tile
 #pragma unroll
     for (int t = 1; t <= 2 * MU; ++t) {
@@ -291,11 +290,13 @@ __global__ __launch_bounds__(NT) void k_pre_tile(const T *__restrict__ a, const 
         // h^-2 (h^2 f - net flux); the flux is summed face by face as
         // w (u_P - u_nbr), a wall face giving 2 a_P u_P (its neighbour slot
         // holds 0); h^2, h^-2 are powers of two
+        // explicit fma in the face order E, W, N, S: the row-streaming pre
+        // pass rounds identically
         const T up = u_s[l];
         T v = c.wE * (up - u_s[l + 1]);
-        v += c.wW * (up - u_s[l - 1]);
-        v += c.wN * (up - u_s[l + S]);
-        v += c.wS * (up - u_s[l - S]);
+        v = fma(c.wW, up - u_s[l - 1], v);
+        v = fma(c.wN, up - u_s[l + S], v);
+        v = fma(c.wS, up - u_s[l - S], v);
         a_s[l] = inv_h2 * (c.rhs - v);
     };
 #pragma unroll
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(NT) void k_pre_tile(const T *__restrict__ a, const 
 
 // Post pass: u = u_in + P ec on the tile and its halo, then mu2 sweeps black
 // first; the result goes to u_out (not read by the launch).
-template <int MU, typename T>
+template <int TILE, int NT, int MU, typename T>
 __global__ __launch_bounds__(NT) void k_post_tile(const T *__restrict__ a, const T *__restrict__ f,
                                                   const T *__restrict__ u_in, T *__restrict__ u_out,
                                                   const T *__restrict__ ec, int n,
@@ -329,9 +330,9 @@ __global__ __launch_bounds__(NT) void k_post_tile(const T *__restrict__ a, const
 {
     constexpr int H = 2 * MU;
     constexpr int S = TILE + 2 * H;
-    using Blk = OwnSet<S, 1, 1>;              // first half-sweep (black): ring H-1
-    using Red = OwnSet<S, 2, 0>;              // second (red): ring H-2
-    using CSt = CoarseStage<S, T>;
+    using Blk = OwnSet<S, NT, 1, 1>;          // first half-sweep (black): ring H-1
+    using Red = OwnSet<S, NT, 2, 0>;          // second (red): ring H-2
+    using CSt = CoarseStage<S, NT, T>;
     __shared__ T u_s[S * S];
     __shared__ T a_s[S * S];
     // the coarse correction is read before a_s is written
@@ -356,11 +357,11 @@ __global__ __launch_bounds__(NT) void k_post_tile(const T *__restrict__ a, const
     const int cI0 = i0 / 2 - (H + 1) / 2 - 1, cJ0 = j0 / 2 - (H + 1) / 2 - 1;
     CSt::load(c_s, ec + b * (int64_t)nc * nc, nc, cI0, cJ0);
     __syncthreads();
-    load_region<S, H>(a_s, u_s, c_s, ab, ub, n, i0, j0, cI0, cJ0, 3);
+    load_region<S, NT, H>(a_s, u_s, c_s, ab, ub, n, i0, j0, cI0, cJ0, 3);
 
     Cell<T> blk[Blk::PER], red[Red::PER];
-    make_cells<S, 1, 1>(blk, a_s, fb, n, i0, j0, H, h2);
-    make_cells<S, 2, 0>(red, a_s, fb, n, i0, j0, H, h2);
+    make_cells<S, NT, 1, 1>(blk, a_s, fb, n, i0, j0, H, h2);
+    make_cells<S, NT, 2, 0>(red, a_s, fb, n, i0, j0, H, h2);
 #pragma unroll
     for (int t = 1; t <= 2 * MU; ++t) {
         if (t & 1) sweep_ring<S, Blk::PER>(blk, u_s, t);
@@ -1185,30 +1186,43 @@ inline unsigned blocks_of(int64_t n, int per) { return nblocks((n + per - 1) / p
 // ---------------------------------------------------------------------------
 bool fused_supported(int mu1, int mu2) { return mu1 >= 1 && mu1 <= 2 && mu2 >= 1 && mu2 <= 2; }
 
+// Tile shapes: 32 x 32 cells per 256-thread workgroup, or 16 x 16 per 128
+// threads; every shape gives the bits of the global sweep order.
+int tile_side(int shape) { return shape == kTile16 ? 16 : 32; }
+
 template <typename T>
-void launch_pre_tile(hipStream_t st, int mu1, const T *a, const T *f, const T *u_in, T *u_out,
-                     const T *uc, int n, int64_t Bc, int init, T *fc, const int32_t *active)
+void launch_pre_tile(hipStream_t st, int shape, int mu1, const T *a, const T *f, const T *u_in,
+                     T *u_out, const T *uc, int n, int64_t Bc, int init, T *fc,
+                     const int32_t *active)
 {
-    const int64_t blocks = Bc * (int64_t)(n / TILE) * (n / TILE);
-    if (mu1 == 2)
-        hipLaunchKernelGGL((k_pre_tile<2, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u_in,
-                           u_out, uc, n, Bc, init, fc, active);
-    else
-        hipLaunchKernelGGL((k_pre_tile<1, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u_in,
-                           u_out, uc, n, Bc, init, fc, active);
+    const int ts = tile_side(shape);
+    const unsigned blocks = nblocks(Bc * (int64_t)(n / ts) * (n / ts));
+#define L(TL, NTH, MU)                                                                             \
+    hipLaunchKernelGGL((k_pre_tile<TL, NTH, MU, T>), dim3(blocks), dim3(NTH), 0, st, a, f, u_in,  \
+                       u_out, uc, n, Bc, init, fc, active)
+    if (ts == 16) {
+        if (mu1 == 2) L(16, 128, 2); else L(16, 128, 1);
+    } else {
+        if (mu1 == 2) L(32, 256, 2); else L(32, 256, 1);
+    }
+#undef L
 }
 
 template <typename T>
-void launch_post_tile(hipStream_t st, int mu2, const T *a, const T *f, const T *u_in, T *u_out,
-                      const T *ec, int n, int64_t Bc, const int32_t *active)
+void launch_post_tile(hipStream_t st, int shape, int mu2, const T *a, const T *f, const T *u_in,
+                      T *u_out, const T *ec, int n, int64_t Bc, const int32_t *active)
 {
-    const int64_t blocks = Bc * (int64_t)(n / TILE) * (n / TILE);
-    if (mu2 == 2)
-        hipLaunchKernelGGL((k_post_tile<2, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u_in,
-                           u_out, ec, n, Bc, active);
-    else
-        hipLaunchKernelGGL((k_post_tile<1, T>), dim3(nblocks(blocks)), dim3(NT), 0, st, a, f, u_in,
-                           u_out, ec, n, Bc, active);
+    const int ts = tile_side(shape);
+    const unsigned blocks = nblocks(Bc * (int64_t)(n / ts) * (n / ts));
+#define L(TL, NTH, MU)                                                                             \
+    hipLaunchKernelGGL((k_post_tile<TL, NTH, MU, T>), dim3(blocks), dim3(NTH), 0, st, a, f, u_in, \
+                       u_out, ec, n, Bc, active)
+    if (ts == 16) {
+        if (mu2 == 2) L(16, 128, 2); else L(16, 128, 1);
+    } else {
+        if (mu2 == 2) L(32, 256, 2); else L(32, 256, 1);
+    }
+#undef L
 }
 
 // Workgroups sized to the top LDS grid: LDS for exactly levels 0..G, one
@@ -1310,9 +1324,9 @@ void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho
 }
 
 #define MLMC_INSTANTIATE(T)                                                                        \
-    template void launch_pre_tile<T>(hipStream_t, int, const T *, const T *, const T *, T *,      \
+    template void launch_pre_tile<T>(hipStream_t, int, int, const T *, const T *, const T *, T *, \
                                      const T *, int, int64_t, int, T *, const int32_t *);          \
-    template void launch_post_tile<T>(hipStream_t, int, const T *, const T *, const T *, T *,     \
+    template void launch_post_tile<T>(hipStream_t, int, int, const T *, const T *, const T *, T *,\
                                       const T *, int, int64_t, const int32_t *);                   \
     template void launch_lds_vcycle<T>(hipStream_t, const T *, const T *, T *, int64_t, int, int, \
                                        int, const int32_t *);                                      \

@@ -267,14 +267,22 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
                 const double *up = u_ring + ((rr + 1) & 7) * n, *dn = u_ring + ((rr - 1) & 7) * n;
                 const int cr = c0 + (rr & 1), cb = c1 - (rr & 1);
                 const double ur = row[cr], ubk = row[cb];
-                // net flux face by face: w (u_P - u_nbr), plus the wall term
-                double fr = r.dw_r * ur, fbk = r.dw_b * ubk;
-                if (cr + 1 < n) fr += r.wE_r * (ur - row[cr + 1]);
-                if (cr > 0) fr += r.wW_r * (ur - row[cr - 1]);
-                if (cb + 1 < n) fbk += r.wE_b * (ubk - row[cb + 1]);
-                if (cb > 0) fbk += r.wW_b * (ubk - row[cb - 1]);
-                if (rr + 1 < n) { fr += r.wN_r * (ur - up[cr]); fbk += r.wN_b * (ubk - up[cb]); }
-                if (rr > 0) { fr += rs.wN_b * (ur - dn[cr]); fbk += rs.wN_r * (ubk - dn[cb]); }
+                // net flux face by face, w (u_P - u_nbr) in the order E, W, N,
+                // S with explicit fma, a wall face as 2 a_P (u_P - 0): the
+                // rounding of the tile passes.  2 a_P is the wall term, halved
+                // (exactly) at a corner, whose two wall faces it sums.
+                auto flux = [&](double u, int c, double wE, double wW, double wN, double wS,
+                                double dw) {
+                    const int walls = (c == 0) + (c + 1 == n) + (rr == 0) + (rr + 1 == n);
+                    const double ww = walls == 2 ? 0.5 * dw : dw;
+                    double v = (c + 1 < n ? wE : ww) * (u - (c + 1 < n ? row[c + 1] : 0.0));
+                    v = fma(c > 0 ? wW : ww, u - (c > 0 ? row[c - 1] : 0.0), v);
+                    v = fma(rr + 1 < n ? wN : ww, u - (rr + 1 < n ? up[c] : 0.0), v);
+                    v = fma(rr > 0 ? wS : ww, u - (rr > 0 ? dn[c] : 0.0), v);
+                    return v;
+                };
+                const double fr = flux(ur, cr, r.wE_r, r.wW_r, r.wN_r, rs.wN_b, r.dw_r);
+                const double fbk = flux(ubk, cb, r.wE_b, r.wW_b, r.wN_b, rs.wN_r, r.dw_b);
                 const double resr = inv_h2 * ((F1 ? h2 : r.rhs_r) - fr);
                 const double resb = inv_h2 * ((F1 ? h2 : r.rhs_b) - fbk);
                 const bool odd = rr & 1;

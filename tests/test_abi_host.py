@@ -191,3 +191,52 @@ def test_server_calls_reject_null_handles():
     assert L.mlmc_server_submit(None, C.byref(req)) == m.MLMC_E_INVAL
     assert L.mlmc_server_poll(None, res, 4, 0, C.byref(n)) == m.MLMC_E_INVAL
     assert L.mlmc_server_stats_get(None, C.byref(st)) == m.MLMC_E_INVAL
+
+
+def test_tuning_table_defaults_and_validation():
+    """Pass-kind table of a context (host-only: no measurement): one entry per
+    tile grid and batch class with the documented defaults; mlmc_tuning_set
+    checks every entry before changing any."""
+    ctx = _host_ctx(n0=4, num_levels=7)             # tile grids 32^2 .. 256^2
+    t = ctx.tuning()
+    assert [(e["n"], e["batch_class"]) for e in t] == [
+        (n, c) for n in (32, 64, 128, 256) for c in range(m.MLMC_BATCH_CLASSES)]
+    for e in t:
+        tiles = 4 ** e["batch_class"] * (e["n"] // 32) ** 2
+        tile = m.MLMC_PASS_TILE16 if tiles <= 256 else m.MLMC_PASS_TILE32
+        assert e["pre"] == tile and e["pre_ms"] == 0.0, e
+        stream = tiles >= 65536 and e["n"] >= 128
+        assert e["post"] == (m.MLMC_PASS_STREAM if stream else tile), e
+    kinds = {(e["n"], e["batch_class"]): (e["pre"], e["post"]) for e in t}
+    assert kinds[(256, 1)] == (m.MLMC_PASS_TILE16,) * 2            # 4 samples: 256 tiles
+    assert kinds[(256, 7)] == (m.MLMC_PASS_TILE32, m.MLMC_PASS_STREAM)   # 16384 samples
+    with pytest.raises(m.MlmcError):
+        ctx.autotune()                              # host-only: no device to measure on
+    L = m.lib()
+    assert L.mlmc_autotune(None, 0, None) == m.MLMC_E_INVAL
+    cnt = C.c_int32(-1)
+    assert L.mlmc_tuning_get(None, None, 0, C.byref(cnt)) == m.MLMC_E_INVAL
+    T16, ST, T32 = m.MLMC_PASS_TILE16, m.MLMC_PASS_STREAM, m.MLMC_PASS_TILE32
+    for bad in [dict(n=16, batch_class=0, pre=T32, post=T32),      # LDS-resident grid
+                dict(n=48, batch_class=0, pre=T32, post=T32),
+                dict(n=512, batch_class=0, pre=T32, post=T32),     # beyond the finest level
+                dict(n=64, batch_class=10, pre=T32, post=T32),
+                dict(n=64, batch_class=-1, pre=T32, post=T32),
+                dict(n=32, batch_class=0, pre=ST, post=T32),       # no streaming pass at 32^2
+                dict(n=64, batch_class=0, pre=T32, post=3)]:
+        with pytest.raises(m.MlmcError):
+            ctx.set_tuning([dict(n=128, batch_class=2, pre=T16, post=T16), bad])
+        assert ctx.tuning() == t                    # nothing changed
+    ctx.set_tuning([dict(n=128, batch_class=2, pre=T16, post=ST), dict(n=32, batch_class=9, pre=T16, post=T16)])
+    t2 = {(e["n"], e["batch_class"]): (e["pre"], e["post"]) for e in ctx.tuning()}
+    assert t2[(128, 2)] == (T16, ST) and t2[(32, 9)] == (T16, T16)
+    assert sum(t2[k] != (e["pre"], e["post"]) for e in t for k in [(e["n"], e["batch_class"])]) == 2
+    # mixed precision: FP32 V-cycles have no streaming passes; rtol mode keeps
+    # 32^2 LDS-resident
+    mx = _host_ctx(n0=4, num_levels=7, precision=1, rtol=1e-10, max_iters=50)
+    tm = mx.tuning()
+    assert [e["n"] for e in tm[::m.MLMC_BATCH_CLASSES]] == [64, 128, 256]
+    assert all(e["pre"] == e["post"] != ST for e in tm)
+    with pytest.raises(m.MlmcError):
+        mx.set_tuning([dict(n=256, batch_class=7, pre=T32, post=ST)])
+    assert _host_ctx(n0=4, num_levels=3).tuning() == []          # all grids LDS-resident

@@ -1,0 +1,91 @@
+"""GPU tests of the large-grid pass kinds and their autotuner: every kind
+(32x32 tiles, 16x16 tiles, row streaming) of the pre and post passes gives
+bitwise the QoIs of the default choice, for both V-cycle precisions, and a
+measured table installs only kinds that keep those bits."""
+import itertools
+
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1806_05619_amd as m  # noqa: E402
+
+T32, T16, ST = m.MLMC_PASS_TILE32, m.MLMC_PASS_TILE16, m.MLMC_PASS_STREAM
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _ctx(name, precision, max_batch):
+    w = synth.workload(name)
+    return w, m.Context(n0=w["n0"], num_levels=w["num_levels"], s=w["s"], corr_len=w["corr_len"],
+                        sigma2=w["sigma2"], mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"],
+                        rtol=w["rtol"], max_iters=w["max_iters"], precision=precision,
+                        qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
+                        genvec=synth.korobov_vector(w["seed"], w["s"]),
+                        shifts=synth.shift_table(w["seed"], w["num_levels"], w["num_shifts"], w["s"]),
+                        max_batch=max_batch, device=0)
+
+
+def _solve(ctx, level, n0, n1, r0, r1):
+    pts = ctx.lattice(level, n0, n1, r0, r1)
+    q = torch.full((ctx.count(pts), level + 1, ctx.nq), float("nan"), dtype=torch.float64,
+                   device="cuda:0")
+    ctx.fmg_solve(pts, qoi=q)
+    torch.cuda.synchronize()
+    return q.cpu().numpy()
+
+
+def _force(ctx, pre, post):
+    ctx.set_tuning(dict(e, pre=pre, post=post) for e in ctx.tuning())
+
+
+@pytest.mark.parametrize("name,precision,level,sizes", [
+    ("mlqmc_fp64_s100", m.MLMC_FP64, 6, ((0, 3, 5, 6), (7, 47, 0, 1))),     # 32^2 .. 256^2
+    ("mlqmc_mixed_s400", m.MLMC_FP64, 5, ((0, 2, 1, 3), (9, 29, 4, 5))),    # rtol, FP64 V-cycles
+    ("mlqmc_mixed_s400", m.MLMC_MIXED, 5, ((0, 2, 1, 3), (9, 29, 4, 5))),   # FP32 V-cycles
+])
+def test_every_pass_kind_gives_the_same_bits(name, precision, level, sizes):
+    _dev()
+    w, ctx = _ctx(name, precision, max_batch=64)
+    want = [_solve(ctx, level, *r) for r in sizes]
+    kinds = [T32, T16] + ([ST] if precision == m.MLMC_FP64 else [])
+    for pre, post in itertools.product(kinds, kinds):
+        ok = [e for e in ctx.tuning() if (ST not in (pre, post)) or 64 <= e["n"] <= 512]
+        ctx.set_tuning(dict(e, pre=pre, post=post) for e in ok)
+        print(f"{name} precision {precision}: pre {pre} post {post}", flush=True)
+        for r, q0 in zip(sizes, want):
+            assert np.array_equal(_solve(ctx, level, *r), q0), (pre, post, r)
+
+
+def test_autotune_installs_measured_kinds_and_keeps_results():
+    _dev()
+    w, ctx = _ctx("mlqmc_fp64_s100", m.MLMC_FP64, max_batch=256)
+    before = [_solve(ctx, 6, 0, 5, 2, 3), _solve(ctx, 6, 3, 131, 7, 9)]
+    table = ctx.autotune()
+    assert [e["n"] for e in table[::m.MLMC_BATCH_CLASSES]] == [32, 64, 128, 256]
+    # the workspace holds 256 samples of the 256^2 hierarchy, so a chunk
+    # whose finest grid is n holds 256 M(256)/M(n) samples (M: cells of the
+    # hierarchy up to n): measured classes 0..4 at 256^2, ..5 at 128^2, ..6
+    # at 64^2, ..8 at 32^2 (16399 samples)
+    top_class = {256: 4, 128: 5, 64: 6, 32: 8}
+    for e in table:
+        measured = e["batch_class"] <= top_class[e["n"]]
+        assert (e["pre_ms"] > 0 and e["post_ms"] > 0) == measured, e
+        assert e["pre"] in (T32, T16, ST) and e["post"] in (T32, T16, ST)
+        if e["n"] == 32:
+            assert ST not in (e["pre"], e["post"])
+    print("tuned:", [(e["n"], e["batch_class"], e["pre"], e["post"]) for e in table
+                     if e["pre_ms"] > 0], flush=True)
+    after = [_solve(ctx, 6, 0, 5, 2, 3), _solve(ctx, 6, 3, 131, 7, 9)]
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+    with pytest.raises(m.MlmcError):
+        ctx.autotune(level=7)
