@@ -385,19 +385,27 @@ struct LdsHier {
     static __device__ constexpr int off(int g) { return (int)(4 * ((1LL << (2 * g)) - 1) / 3); }
 };
 
-// stencil of cell (i, j) from coefficients of type TA, weights in type TW
+// Stencil of cell (i, j) from coefficients of type TA, weights in type TW,
+// rounded as in the tile passes (make_cell): a wall face carries 2 a_P (its
+// neighbour reads as 0), the diagonal is the plain sum E + W + N + S.  The
+// LDS-resident and the tile kernels then give the same bits on a grid that
+// either may run, whichever the batch size selects.
 template <typename TW, typename TA>
 __device__ __forceinline__ void lds_stencil(const TA *a, int n, int i, int j, TW &wE, TW &wW,
                                             TW &wN, TW &wS, TW &d)
 {
+#pragma clang fp contract(off)
     const int p = i + n * j;
     const TW ap = TW(a[p]);
-    d = TW(0);
-    wE = wW = wN = wS = TW(0);
-    if (i + 1 < n) { wE = hm(ap, TW(a[p + 1])); d += wE; } else d += TW(2) * ap;
-    if (i > 0)     { wW = hm(ap, TW(a[p - 1])); d += wW; } else d += TW(2) * ap;
-    if (j + 1 < n) { wN = hm(ap, TW(a[p + n])); d += wN; } else d += TW(2) * ap;
-    if (j > 0)     { wS = hm(ap, TW(a[p - n])); d += wS; } else d += TW(2) * ap;
+    const TW wall = TW(2) * ap;
+    wE = i + 1 < n ? hm(ap, TW(a[p + 1])) : wall;
+    wW = i > 0 ? hm(ap, TW(a[p - 1])) : wall;
+    wN = j + 1 < n ? hm(ap, TW(a[p + n])) : wall;
+    wS = j > 0 ? hm(ap, TW(a[p - n])) : wall;
+    d = wE;
+    d += wW;
+    d += wN;
+    d += wS;
 }
 
 template <typename T>
@@ -406,7 +414,8 @@ __device__ __forceinline__ T lds_nb(const T *u, int n, int i, int j)
     return (i < 0 || j < 0 || i >= n || j >= n) ? T(0) : u[i + n * j];
 }
 
-// one colour; f == nullptr means f = 1
+// one colour; f == nullptr means f = 1.  Explicit fma in the face order E, W,
+// N, S, as in the tile passes.
 template <int LT, typename T>
 __device__ void lds_sweep(const T *a, const T *f, T *u, int n, int colour)
 {
@@ -418,28 +427,31 @@ __device__ void lds_sweep(const T *a, const T *f, T *u, int n, int colour)
         T wE, wW, wN, wS, d;
         lds_stencil<T>(a, n, i, j, wE, wW, wN, wS, d);
         T num = h2 * (f ? f[i + n * j] : T(1));
-        num += wE * lds_nb(u, n, i + 1, j);
-        num += wW * lds_nb(u, n, i - 1, j);
-        num += wN * lds_nb(u, n, i, j + 1);
-        num += wS * lds_nb(u, n, i, j - 1);
+        num = fma(wE, lds_nb(u, n, i + 1, j), num);
+        num = fma(wW, lds_nb(u, n, i - 1, j), num);
+        num = fma(wN, lds_nb(u, n, i, j + 1), num);
+        num = fma(wS, lds_nb(u, n, i, j - 1), num);
         u[i + n * j] = num * frcp(d);
     }
     __syncthreads();
 }
 
 // r = f - A u at one cell, in the arithmetic of TU (coefficients TA promoted)
-// net flux out of cell (i, j) times h^2, face by face: w (u_P - u_nbr) for an
-// interior face, 2 a_P u_P for a wall face
+// net flux out of cell (i, j) times h^2, face by face w (u_P - u_nbr) in the
+// order E, W, N, S with explicit fma, a wall face as 2 a_P (u_P - 0): the
+// rounding of the tile passes.  (Their residual h^-2 (h^2 f - flux) equals
+// f - h^-2 flux bit for bit: both scalings are by powers of two.)
 template <typename TU, typename TA, typename TV>
 __device__ __forceinline__ TU lds_flux(const TA *a, const TV *u, int n, int i, int j)
 {
+    // each face weight as in lds_stencil, formed where it is used; a wall
+    // face's 2 a_P (u_P - 0) written as 2 a_P u_P
     const int p = i + n * j;
-    const TU ap = TU(a[p]), up = TU(u[p]);
-    TU v = TU(0);
-    v += (i + 1 < n) ? hm(ap, TU(a[p + 1])) * (up - TU(u[p + 1])) : TU(2) * ap * up;
-    v += (i > 0) ? hm(ap, TU(a[p - 1])) * (up - TU(u[p - 1])) : TU(2) * ap * up;
-    v += (j + 1 < n) ? hm(ap, TU(a[p + n])) * (up - TU(u[p + n])) : TU(2) * ap * up;
-    v += (j > 0) ? hm(ap, TU(a[p - n])) * (up - TU(u[p - n])) : TU(2) * ap * up;
+    const TU ap = TU(a[p]), up = TU(u[p]), wall = TU(2) * ap;
+    TU v = (i + 1 < n) ? hm(ap, TU(a[p + 1])) * (up - TU(u[p + 1])) : wall * up;
+    v = (i > 0) ? fma(hm(ap, TU(a[p - 1])), up - TU(u[p - 1]), v) : fma(wall, up, v);
+    v = (j + 1 < n) ? fma(hm(ap, TU(a[p + n])), up - TU(u[p + n]), v) : fma(wall, up, v);
+    v = (j > 0) ? fma(hm(ap, TU(a[p - n])), up - TU(u[p - n]), v) : fma(wall, up, v);
     return v;
 }
 
@@ -617,27 +629,37 @@ __device__ __forceinline__ double lds_reduce(double s, double c, double *scratch
     return v;
 }
 
+// QoI of one sample's grid ug in LDS, summed in the order of the QoI kernel
+// of the larger grids (k_qoi: lane k of one wavefront adds cells k, k + 64,
+// ... compensated, then a butterfly), so a grid gives the same bits in either
+// kernel.  Ends with a barrier: the grid may be overwritten next.
 template <int LT>
 __device__ void lds_write_qoi(const double *ug, int n, double *qoi, int64_t b, int nlev, int l,
-                              uint32_t mask, double *scratch)
+                              uint32_t mask)
 {
-    const int nq = (mask & 1u ? 1 : 0) + (mask & 2u ? 1 : 0);
-    double qm = 0.0;
-    if (mask & 1u) {
-        double s = 0.0, c = 0.0;
-        for (int p = threadIdx.x; p < n * n; p += LT) neumaier(s, c, ug[p]);
-        qm = lds_reduce<LT>(s, c, scratch) / ((double)n * n);
-    }
-    if (threadIdx.x == 0) {
-        double *qb = qoi + (b * nlev + l) * nq;
-        int q = 0;
-        if (mask & 1u) qb[q++] = qm;
-        if (mask & 2u) {
-            const int c = n / 2;
-            qb[q] = 0.25 * (ug[(c - 1) + n * (c - 1)] + ug[c + n * (c - 1)] + ug[(c - 1) + n * c] +
-                            ug[c + n * c]);
+    if (threadIdx.x < 64) {
+        const int nq = (mask & 1u ? 1 : 0) + (mask & 2u ? 1 : 0);
+        double qm = 0.0;
+        if (mask & 1u) {
+            double s = 0.0, c = 0.0;
+            for (int p = threadIdx.x; p < n * n; p += 64) neumaier(s, c, ug[p]);
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1)
+                two_sum_fold(s, c, __shfl_xor(s, m, 64), __shfl_xor(c, m, 64));
+            qm = (s + c) / ((double)n * n);
+        }
+        if (threadIdx.x == 0) {
+            double *qb = qoi + (b * nlev + l) * nq;
+            int q = 0;
+            if (mask & 1u) qb[q++] = qm;
+            if (mask & 2u) {
+                const int c = n / 2;
+                qb[q] = 0.25 * (ug[(c - 1) + n * (c - 1)] + ug[c + n * (c - 1)] +
+                                ug[(c - 1) + n * c] + ug[c + n * c]);
+            }
         }
     }
+    __syncthreads();
 }
 
 // FMG stages 0..G (G <= GS) with fixed mu0 cycles, FP64; QoI of stages g >= g0;
@@ -651,7 +673,7 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_fixed(const double *__restrict__
 {
     constexpr int TOT = LdsHier<GS>::TOTAL;
     __shared__ double a_s[TOT], u_s[TOT], f_s[TOT];
-    __shared__ double red_s[4 * (LT / 64)], chol_s[10];
+    __shared__ double chol_s[10];
     const int64_t b = blockIdx.x;
     if (b >= Bc) return;
     for (int g = 0; g <= G; ++g) {
@@ -672,7 +694,7 @@ __global__ __launch_bounds__(LT) void k_lds_fmg_fixed(const double *__restrict__
             lds_prolong<LT>(u_s + LdsHier<GS>::off(g - 1), ug, n, false);
             for (int c = 0; c < mu0; ++c) V.run(g, nullptr);
         }
-        if (g >= g0) lds_write_qoi<LT>(ug, n, qoi, b, nlev, g - g0, mask, red_s);
+        if (g >= g0) lds_write_qoi<LT>(ug, n, qoi, b, nlev, g - g0, mask);
     }
     const int cntG = 4 << (2 * G);
     double *dst = u_pool + Bc * level_offset(G) + b * (int64_t)cntG;
@@ -848,7 +870,7 @@ __global__ __launch_bounds__(LT, LT == 64 ? 4 : 1) void k_lds_fmg_refine(
         if (g > 0 && rho > rtol) bad = 1;
         it_max = it > it_max ? it : it_max;
         rho_max = rho > rho_max ? rho : rho_max;
-        if (g >= g0) lds_write_qoi<LT>(xg, n, qoi, b, nlev, g - g0, mask, red_s);
+        if (g >= g0) lds_write_qoi<LT>(xg, n, qoi, b, nlev, g - g0, mask);
     }
     const int cntG = 4 << (2 * G);
     double *dst = u64_pool + Bc * level_offset(G) + b * (int64_t)cntG;

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_1806_05619_amd as m  # noqa: E402
 
-T32, T16, ST = m.MLMC_PASS_TILE32, m.MLMC_PASS_TILE16, m.MLMC_PASS_STREAM
+T32, T16, ST, LDS = m.MLMC_PASS_TILE32, m.MLMC_PASS_TILE16, m.MLMC_PASS_STREAM, m.MLMC_PASS_LDS
 
 
 def _dev():
@@ -53,16 +53,28 @@ def _force(ctx, pre, post):
     ("mlqmc_mixed_s400", m.MLMC_MIXED, 5, ((0, 2, 1, 3), (9, 29, 4, 5))),   # FP32 V-cycles
 ])
 def test_every_pass_kind_gives_the_same_bits(name, precision, level, sizes):
+    """Every combination of kinds on the 32^2 grid (tiles, or LDS-resident in
+    the fixed-cycle mode) and on the larger grids gives the QoIs of the
+    default choice, on every level of the solve."""
     _dev()
     w, ctx = _ctx(name, precision, max_batch=64)
-    want = [_solve(ctx, level, *r) for r in sizes]
-    kinds = [T32, T16] + ([ST] if precision == m.MLMC_FP64 else [])
-    for pre, post in itertools.product(kinds, kinds):
-        ok = [e for e in ctx.tuning() if (ST not in (pre, post)) or 64 <= e["n"] <= 512]
-        ctx.set_tuning(dict(e, pre=pre, post=post) for e in ok)
-        print(f"{name} precision {precision}: pre {pre} post {post}", flush=True)
-        for r, q0 in zip(sizes, want):
-            assert np.array_equal(_solve(ctx, level, *r), q0), (pre, post, r)
+    fixed = w["rtol"] <= 0
+    levels = (level, 3) if fixed else (level,)
+    want = {(lv, r): _solve(ctx, lv, *r) for lv in levels for r in sizes}
+    small = [T32, T16, LDS] if fixed else []
+    large = [T32, T16] + ([ST] if precision == m.MLMC_FP64 else [])
+    for k32 in small or [None]:
+        for pre, post in itertools.product(large, large):
+            ent = []
+            for e in ctx.tuning():
+                if e["n"] == 32 and fixed:
+                    ent.append(dict(e, pre=k32, post=k32))
+                elif ST not in (pre, post) or 64 <= e["n"] <= 512:
+                    ent.append(dict(e, pre=pre, post=post))
+            ctx.set_tuning(ent)
+            print(f"{name} precision {precision}: 32^2 {k32} pre {pre} post {post}", flush=True)
+            for (lv, r), q0 in want.items():
+                assert np.array_equal(_solve(ctx, lv, *r), q0), (k32, pre, post, lv, r)
 
 
 def test_autotune_installs_measured_kinds_and_keeps_results():
@@ -79,9 +91,12 @@ def test_autotune_installs_measured_kinds_and_keeps_results():
     for e in table:
         measured = e["batch_class"] <= top_class[e["n"]]
         assert (e["pre_ms"] > 0 and e["post_ms"] > 0) == measured, e
-        assert e["pre"] in (T32, T16, ST) and e["post"] in (T32, T16, ST)
+        assert e["pre"] in (T32, T16, ST, LDS) and e["post"] in (T32, T16, ST, LDS)
+        assert (e["pre"] == LDS) == (e["post"] == LDS), e
         if e["n"] == 32:
             assert ST not in (e["pre"], e["post"])
+        else:
+            assert LDS not in (e["pre"], e["post"])
     print("tuned:", [(e["n"], e["batch_class"], e["pre"], e["post"]) for e in table
                      if e["pre_ms"] > 0], flush=True)
     after = [_solve(ctx, 6, 0, 5, 2, 3), _solve(ctx, 6, 3, 131, 7, 9)]
