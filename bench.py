@@ -36,7 +36,7 @@ BF16_PEAK_TFLOPS = 2500.0
 
 KINDS = ("points", "field", "smooth", "restrict", "prolong", "coarse", "qoi", "sums", "pre", "post",
          "lds", "refine")
-KIND_NAMES = {0: "tile32", 1: "tile16", 2: "stream", 3: "lds"}
+KIND_NAMES = {0: "tile32", 1: "tile16", 2: "stream"}
 KERNEL_NAMES = dict(
     points="k_points", field="k_field_mfma64", smooth="k_rbgs (one colour)",
     restrict="k_resid_restrict", prolong="k_prolong", coarse="k_coarse_solve", qoi="k_qoi",

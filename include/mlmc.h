@@ -295,29 +295,22 @@ mlmc_status mlmc_profile_end(mlmc_ctx ctx, mlmc_profile_result *out);
  *                     workgroups: for batches too small to fill the chip)
  *   MLMC_PASS_STREAM  one workgroup per sample streaming rows through LDS
  *                     (FP64 V-cycles, 64 <= n <= 512 only)
- *   MLMC_PASS_LDS     no pass: the grid joins the LDS-resident hierarchy below
- *                     it, one workgroup per sample for the whole V-cycle (and
- *                     the FMG stages up to it); fixed-cycle mode, n = 32
- *                     only, for the pre and the post pass together
  * All kinds give the bits of the same global sweep order, so the choice
- * changes only the time (and, with LDS, the number of launches).  The choice is kept per context for each grid side
+ * changes only the time.  The choice is kept per context for each grid side
  * n and batch class c: chunks of Bc samples with 4^(c-1) < Bc <= 4^c (c = 0
  * for one sample), c < MLMC_BATCH_CLASSES (the last class takes every larger
  * chunk).  A new context starts from defaults measured on MI355X, a rule in
  * the number of 32 x 32 tiles of the pass, t = 4^c (n/32)^2: TILE16 for
  * t <= 256; STREAM for the post pass when t >= 65536 and n >= 128 (FP64);
- * TILE32 otherwise; LDS at n = 32 (fixed cycles) for classes 4 and 5.  A
- * server's slots take the first slot's table. */
-enum { MLMC_PASS_TILE32 = 0, MLMC_PASS_TILE16 = 1, MLMC_PASS_STREAM = 2, MLMC_PASS_LDS = 3 };
+ * TILE32 otherwise.  A server's slots take the first slot's table. */
+enum { MLMC_PASS_TILE32 = 0, MLMC_PASS_TILE16 = 1, MLMC_PASS_STREAM = 2 };
 enum { MLMC_BATCH_CLASSES = 10 };
 typedef struct {
     int32_t n;             /* grid side of the pass (cells per side) */
     int32_t batch_class;   /* c above */
     int32_t pre, post;     /* MLMC_PASS_* */
     double pre_ms, post_ms;  /* one launch as measured by mlmc_autotune (at
-                                min(4^c, capacity) samples); for LDS each holds
-                                half of the LDS-resident V-cycle launch that
-                                covers the grid; 0 if not measured */
+                                min(4^c, capacity) samples); 0 if not measured */
 } mlmc_tune_entry;
 /* Measures every allowed kind of both passes on every tile grid of levels
  * <= level, for every batch class up to the level's chunk capacity, on the
@@ -332,8 +325,8 @@ mlmc_status mlmc_tuning_get(mlmc_ctx ctx, mlmc_tune_entry *out, int32_t max_entr
                             int32_t *count);
 /* Installs the kinds of `count` entries (a saved table, or a forced choice);
  * E_INVAL, before any change, if an entry names a grid that is not a tile
- * grid of the context, a class out of range, a kind the grid does not
- * support or LDS for only one of the two passes. */
+ * grid of the context, a class out of range or a kind the grid does not
+ * support. */
 mlmc_status mlmc_tuning_set(mlmc_ctx ctx, const mlmc_tune_entry *in, int32_t count);
 
 /* ---- Serving loop: continuous batching of solve requests ----------------

@@ -27,7 +27,7 @@ MLMC_OK, MLMC_E_INVAL, MLMC_E_NOMEM, MLMC_E_HIP, MLMC_E_NOCONV, MLMC_E_STATE = 0
 MLMC_FP64, MLMC_MIXED = 0, 1
 MLMC_QOI_MEAN, MLMC_QOI_CENTER = 1, 2
 MLMC_POINTS_LATTICE, MLMC_POINTS_EXPLICIT = 0, 1
-MLMC_PASS_TILE32, MLMC_PASS_TILE16, MLMC_PASS_STREAM, MLMC_PASS_LDS = 0, 1, 2, 3
+MLMC_PASS_TILE32, MLMC_PASS_TILE16, MLMC_PASS_STREAM = 0, 1, 2
 MLMC_BATCH_CLASSES = 10
 
 

@@ -416,24 +416,16 @@ int lds_top(mlmc_ctx c) { return c->cfg.rtol > 0.0 ? kLdsMaxLevel : kLdsMaxLevel
 bool kind_allowed(mlmc_ctx c, int g, int kind)
 {
     if (kind == kTile32 || kind == kTile16) return true;
-    // the 32^2 grid may join the LDS-resident hierarchy of the fixed-cycle mode
-    if (kind == kLdsKind) return c->cfg.rtol <= 0.0 && g == kLdsMaxLevelFixed + 1;
     // the row-streaming passes exist for FP64 V-cycles
     return kind == kStream && c->cfg.precision == MLMC_FP64 && stream_supported(2 << g);
 }
-// top MG level of the LDS-resident grids of a fixed-cycle chunk of Bc samples
-int lds_top_fixed(mlmc_ctx c, int64_t Bc)
-{
-    return c->pre_kind[kLdsMaxLevelFixed + 1][batch_class(Bc)] == kLdsKind ? kLdsMaxLevelFixed + 1
-                                                                           : kLdsMaxLevelFixed;
-}
+
 // Defaults: the choices mlmc_autotune made on MI355X for the s = 100 FP64
 // workload (grids 32^2 .. 256^2, batch classes up to 16384 samples), as a
 // rule in the number of 32 x 32 tiles a pass covers, 4^c (n/32)^2: up to 256
 // (one per CU or fewer) 16 x 16 tiles, which give four times the workgroups;
 // from 65536 on row streaming for the post pass where it exists; 32 x 32
-// tiles otherwise; and in the fixed-cycle mode the 32^2 grid LDS-resident for
-// chunks of 65 .. 1024 samples (classes 4 and 5).
+// tiles otherwise.
 void default_tuning(mlmc_ctx c)
 {
     for (int g = 0; g < kMaxMgLevels; ++g) {
@@ -444,8 +436,6 @@ void default_tuning(mlmc_ctx c)
             c->pre_kind[g][cl] = tile;
             c->post_kind[g][cl] =
                 tiles >= 65536 && (2 << g) >= 128 && kind_allowed(c, g, kStream) ? kStream : tile;
-            if ((cl == 4 || cl == 5) && kind_allowed(c, g, kLdsKind))
-                c->pre_kind[g][cl] = c->post_kind[g][cl] = kLdsKind;
         }
     }
 }
@@ -555,7 +545,7 @@ mlmc_status run_fmg_fixed(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k, 
                           StageStats *stats)
 {
     const int nlev = k + 1;
-    FusedRunner<double> R{c, st, make_hier_t<double>(c, G, Bc), std::min(G, lds_top_fixed(c, Bc))};
+    FusedRunner<double> R{c, st, make_hier_t<double>(c, G, Bc), std::min(G, kLdsMaxLevelFixed)};
     {
         const int n = 2 << R.Gs;
         ProfScope ps(c, st, MLMC_KERNEL_LDS, 8.0 * Bc * level_offset(R.Gs + 1) + 8.0 * R.cells(n), 0.0);
@@ -1007,7 +997,7 @@ mlmc_status tune_grid(mlmc_ctx c, hipStream_t st, int g, int64_t Bc, int cls, hi
     const int kinds[] = {kTile32, kTile16, kStream};
     double best_pre = 1e300, best_post = 1e300;
     for (int kind : kinds) {
-        if (!kind_allowed(c, g, kind)) continue;   // (LDS is not a pass: below)
+        if (!kind_allowed(c, g, kind)) continue;
         auto pre = [&] {
             if constexpr (std::is_same<T, double>::value) {
                 if (kind == kStream) {
@@ -1043,24 +1033,6 @@ mlmc_status tune_grid(mlmc_ctx c, hipStream_t st, int g, int64_t Bc, int cls, hi
     }
     c->pre_ms[g][cls] = best_pre;
     c->post_ms[g][cls] = best_post;
-    if (kind_allowed(c, g, kLdsKind)) {
-        // the V-cycle at grid g with the grid LDS-resident (one launch)
-        // against its two passes around the LDS-resident V-cycle below it
-        double t_lds = 0.0, t_below = 0.0;
-        HIPCHK(c, time_it([&] {
-            launch_lds_vcycle<T>(st, h.a[0], h.f[0], h.u[0], Bc, g, c->cfg.mu1, c->cfg.mu2, nullptr);
-        }));
-        t_lds = ms_best;
-        HIPCHK(c, time_it([&] {
-            launch_lds_vcycle<T>(st, h.a[0], h.f[0], h.u[0], Bc, g - 1, c->cfg.mu1, c->cfg.mu2,
-                                 nullptr);
-        }));
-        t_below = ms_best;
-        if (t_lds < best_pre + t_below + best_post) {
-            c->pre_kind[g][cls] = c->post_kind[g][cls] = kLdsKind;
-            c->pre_ms[g][cls] = c->post_ms[g][cls] = 0.5 * t_lds;
-        }
-    }
     return MLMC_OK;
 }
 
@@ -1143,8 +1115,6 @@ mlmc_status mlmc_tuning_set(mlmc_ctx ctx, const mlmc_tune_entry *in, int32_t cou
             return inval(ctx, "tuning entry: batch class out of range");
         if (!kind_allowed(ctx, g, e.pre) || !kind_allowed(ctx, g, e.post))
             return inval(ctx, "tuning entry: pass kind not available on this grid");
-        if ((e.pre == kLdsKind) != (e.post == kLdsKind))
-            return inval(ctx, "tuning entry: LDS-resident for one pass only");
     }
     for (int32_t i = 0; i < count; ++i) {
         const mlmc_tune_entry &e = in[i];

@@ -20,8 +20,7 @@ int64_t level_capacity(mlmc_ctx c, int k);
 constexpr int kMaxMgLevels = 12;   // n_g = 2^(g+1) <= 4096
 constexpr int kBlock = 256;
 constexpr int kLdsMaxLevel = 4;    // grids up to 32^2 run LDS-resident (one workgroup per sample)
-constexpr int kLdsMaxLevelFixed = 3;   // fixed-cycle mode: up to 16^2, and 32^2 where the
-                                       // tuning table says so; tile passes above
+constexpr int kLdsMaxLevelFixed = 3;   // fixed-cycle mode: up to 16^2; 32^2 runs the tile passes
 
 // Offset (in cells) of multigrid level g inside a level-major per-sample
 // field: sum_{g' < g} 4^(g'+1) = 4 (4^g - 1) / 3.
@@ -108,8 +107,7 @@ void launch_sums_final(hipStream_t st, const double *state, int64_t count, doubl
 // ---- fused kernels (kernels_fused.hip), T = double or float ----
 bool fused_supported(int mu1, int mu2);
 // pass kinds of the tile grids (the MLMC_PASS_* values)
-constexpr int kTile32 = MLMC_PASS_TILE32, kTile16 = MLMC_PASS_TILE16, kStream = MLMC_PASS_STREAM,
-              kLdsKind = MLMC_PASS_LDS;
+constexpr int kTile32 = MLMC_PASS_TILE32, kTile16 = MLMC_PASS_TILE16, kStream = MLMC_PASS_STREAM;
 // pre pass on level n with tile shape kTile32 or kTile16: init 0 read u_in, 1
 // zero guess, 2 u = P uc; writes u_out (never u_in: tiles read their
 // neighbours' cells) and fc

@@ -205,8 +205,6 @@ def test_tuning_table_defaults_and_validation():
         tiles = 4 ** e["batch_class"] * (e["n"] // 32) ** 2
         tile = m.MLMC_PASS_TILE16 if tiles <= 256 else m.MLMC_PASS_TILE32
         stream = tiles >= 65536 and e["n"] >= 128
-        if e["n"] == 32 and e["batch_class"] in (4, 5):
-            tile = m.MLMC_PASS_LDS
         assert e["pre"] == tile and e["pre_ms"] == 0.0, e
         assert e["post"] == (m.MLMC_PASS_STREAM if stream else tile), e
     kinds = {(e["n"], e["batch_class"]): (e["pre"], e["post"]) for e in t}
@@ -218,24 +216,21 @@ def test_tuning_table_defaults_and_validation():
     assert L.mlmc_autotune(None, 0, None) == m.MLMC_E_INVAL
     cnt = C.c_int32(-1)
     assert L.mlmc_tuning_get(None, None, 0, C.byref(cnt)) == m.MLMC_E_INVAL
-    T16, ST, T32, LDS = m.MLMC_PASS_TILE16, m.MLMC_PASS_STREAM, m.MLMC_PASS_TILE32, m.MLMC_PASS_LDS
+    T16, ST, T32 = m.MLMC_PASS_TILE16, m.MLMC_PASS_STREAM, m.MLMC_PASS_TILE32
     for bad in [dict(n=16, batch_class=0, pre=T32, post=T32),      # LDS-resident grid
                 dict(n=48, batch_class=0, pre=T32, post=T32),
                 dict(n=512, batch_class=0, pre=T32, post=T32),     # beyond the finest level
                 dict(n=64, batch_class=10, pre=T32, post=T32),
                 dict(n=64, batch_class=-1, pre=T32, post=T32),
                 dict(n=32, batch_class=0, pre=ST, post=T32),       # no streaming pass at 32^2
-                dict(n=32, batch_class=0, pre=LDS, post=T32),      # LDS-resident: both or neither
-                dict(n=64, batch_class=0, pre=LDS, post=LDS),      # LDS-resident up to 32^2 only
-                dict(n=64, batch_class=0, pre=T32, post=4)]:
+                dict(n=64, batch_class=0, pre=T32, post=3)]:
         with pytest.raises(m.MlmcError):
             ctx.set_tuning([dict(n=128, batch_class=2, pre=T16, post=T16), bad])
         assert ctx.tuning() == t                    # nothing changed
-    ctx.set_tuning([dict(n=128, batch_class=2, pre=T16, post=ST), dict(n=32, batch_class=9, pre=T16, post=T16),
-                    dict(n=32, batch_class=3, pre=LDS, post=LDS), dict(n=32, batch_class=4, pre=LDS, post=LDS)])
+    ctx.set_tuning([dict(n=128, batch_class=2, pre=T16, post=ST), dict(n=32, batch_class=9, pre=T16, post=T16)])
     t2 = {(e["n"], e["batch_class"]): (e["pre"], e["post"]) for e in ctx.tuning()}
-    assert t2[(128, 2)] == (T16, ST) and t2[(32, 9)] == (T16, T16) and t2[(32, 3)] == (LDS, LDS)
-    assert sum(t2[k] != (e["pre"], e["post"]) for e in t for k in [(e["n"], e["batch_class"])]) == 3
+    assert t2[(128, 2)] == (T16, ST) and t2[(32, 9)] == (T16, T16)
+    assert sum(t2[k] != (e["pre"], e["post"]) for e in t for k in [(e["n"], e["batch_class"])]) == 2
     # mixed precision: FP32 V-cycles have no streaming passes; rtol mode keeps
     # 32^2 LDS-resident
     mx = _host_ctx(n0=4, num_levels=7, precision=1, rtol=1e-10, max_iters=50)
@@ -244,6 +239,6 @@ def test_tuning_table_defaults_and_validation():
     assert all(e["pre"] == e["post"] != ST for e in tm)
     with pytest.raises(m.MlmcError):
         mx.set_tuning([dict(n=256, batch_class=7, pre=T32, post=ST)])
-    with pytest.raises(m.MlmcError):                 # rtol mode: 32^2 is always LDS-resident
-        mx.set_tuning([dict(n=64, batch_class=0, pre=LDS, post=LDS)])
+    with pytest.raises(m.MlmcError):                 # rtol mode: 32^2 is LDS-resident
+        mx.set_tuning([dict(n=32, batch_class=0, pre=T32, post=T32)])
     assert _host_ctx(n0=4, num_levels=3).tuning() == []          # all grids LDS-resident

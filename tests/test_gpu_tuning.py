@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_1806_05619_amd as m  # noqa: E402
 
-T32, T16, ST, LDS = m.MLMC_PASS_TILE32, m.MLMC_PASS_TILE16, m.MLMC_PASS_STREAM, m.MLMC_PASS_LDS
+T32, T16, ST = m.MLMC_PASS_TILE32, m.MLMC_PASS_TILE16, m.MLMC_PASS_STREAM
 
 
 def _dev():
@@ -53,15 +53,15 @@ def _force(ctx, pre, post):
     ("mlqmc_mixed_s400", m.MLMC_MIXED, 5, ((0, 2, 1, 3), (9, 29, 4, 5))),   # FP32 V-cycles
 ])
 def test_every_pass_kind_gives_the_same_bits(name, precision, level, sizes):
-    """Every combination of kinds on the 32^2 grid (tiles, or LDS-resident in
-    the fixed-cycle mode) and on the larger grids gives the QoIs of the
-    default choice, on every level of the solve."""
+    """Every combination of kinds on the 32^2 grid (fixed-cycle mode) and on
+    the larger grids gives the QoIs of the default choice, on every level of
+    the solve."""
     _dev()
     w, ctx = _ctx(name, precision, max_batch=64)
     fixed = w["rtol"] <= 0
     levels = (level, 3) if fixed else (level,)
     want = {(lv, r): _solve(ctx, lv, *r) for lv in levels for r in sizes}
-    small = [T32, T16, LDS] if fixed else []
+    small = [T32, T16] if fixed else []
     large = [T32, T16] + ([ST] if precision == m.MLMC_FP64 else [])
     for k32 in small or [None]:
         for pre, post in itertools.product(large, large):
@@ -91,12 +91,9 @@ def test_autotune_installs_measured_kinds_and_keeps_results():
     for e in table:
         measured = e["batch_class"] <= top_class[e["n"]]
         assert (e["pre_ms"] > 0 and e["post_ms"] > 0) == measured, e
-        assert e["pre"] in (T32, T16, ST, LDS) and e["post"] in (T32, T16, ST, LDS)
-        assert (e["pre"] == LDS) == (e["post"] == LDS), e
+        assert e["pre"] in (T32, T16, ST) and e["post"] in (T32, T16, ST)
         if e["n"] == 32:
             assert ST not in (e["pre"], e["post"])
-        else:
-            assert LDS not in (e["pre"], e["post"])
     print("tuned:", [(e["n"], e["batch_class"], e["pre"], e["post"]) for e in table
                      if e["pre_ms"] > 0], flush=True)
     after = [_solve(ctx, 6, 0, 5, 2, 3), _solve(ctx, 6, 3, 131, 7, 9)]
