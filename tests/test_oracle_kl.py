@@ -74,7 +74,7 @@ def test_mercer_covariance(oracle_mod):
 
 
 def test_first_eigenvalues_lambda_03(oracle_mod):
-    # independent bisection values computed when the workloads were surveyed
+    # eigenvalues from an independent bisection on the characteristic equation
     th = [oracle_mod.kl_theta(0.3, oracle_mod.kl_root(0.3, k)) for k in (1, 2)]
     assert abs(th[0] - 0.436249) < 1e-6 and abs(th[1] - 0.216812) < 1e-6
 
