@@ -67,6 +67,15 @@ enum { MLMC_QOI_MEAN = 1u, MLMC_QOI_CENTER = 2u };
 
 enum { MLMC_POINTS_LATTICE = 0, MLMC_POINTS_EXPLICIT = 1 };
 
+/* Covariance of the Gaussian field z (Section 5):
+ * SEPARABLE_EXP  exp(-|x1-x1'|/lambda - |x2-x2'|/lambda), KL eigenpairs from
+ *                the 1-D characteristic equation (products of 1-D modes);
+ * MATERN         isotropic Matern, eq. matern, smoothness nu, rho = |x-x'|/lambda;
+ *                KL eigenpairs by the Nystrom method on the nystrom_q^2
+ *                midpoint nodes of the unit square, eigenfunctions at the cell
+ *                centres by the Nystrom interpolation formula. */
+enum { MLMC_FIELD_SEPARABLE_EXP = 0, MLMC_FIELD_MATERN = 1 };
+
 typedef struct mlmc_ctx_s *mlmc_ctx;
 
 typedef struct {
@@ -100,6 +109,10 @@ typedef struct {
                                 NULL disables lattice points.  Copied at create. */
     int64_t max_batch;    /* samples of the finest level solved at once; sizes
                              the workspace (coarser levels run larger chunks) */
+    int32_t field_kind;   /* MLMC_FIELD_* */
+    double nu;            /* MATERN: smoothness, 0 < nu <= 8 */
+    int32_t nystrom_q;    /* MATERN: quadrature nodes per side, 4..96 (0: 32);
+                             s <= nystrom_q^2 */
 } mlmc_config;
 
 /* A set of samples, all with finest MLMC level `level` (Algorithm 1,
@@ -133,7 +146,11 @@ typedef struct {
 } mlmc_solve_info;
 
 /* Create a context on `device`: validates cfg, builds the KL mode table and
- * basis (analytic 1-D eigenpairs, Section 5 with the exponential kernel),
+ * basis (analytic 1-D eigenpairs, Section 5 with the exponential kernel; or,
+ * for MATERN, the Nystrom eigenpairs: the weighted covariance matrix of the
+ * nodes formed on the device, its symmetric eigendecomposition by rocSOLVER,
+ * the interpolation formula evaluated at every cell centre of every level as
+ * one FP64 matrix-core product), MATERN needs device >= 0;
  * uploads generating vector and shifts, allocates the workspace for
  * max_batch finest-level samples.  E_NOMEM if it does not fit in free HBM.
  * Synchronous.  device < 0 creates a host-only context that makes no HIP
@@ -227,7 +244,8 @@ mlmc_status mlmc_estimate(const mlmc_est_input *in, mlmc_est_output *out);
 
 /* The ordered 2-D KL mode table (descending theta_i theta_j, ties by i
  * ascending): i_out, j_out [s] 1-based 1-D indices, theta_out [s] products.
- * Any output may be NULL.  Host-only. */
+ * MATERN: i_out = j_out = 0, theta_out the s largest Nystrom eigenvalues,
+ * descending.  Any output may be NULL.  Host-only. */
 mlmc_status mlmc_kl_modes(mlmc_ctx ctx, int32_t *i_out, int32_t *j_out,
                           double *theta_out);
 

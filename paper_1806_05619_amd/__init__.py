@@ -28,6 +28,7 @@ MLMC_FP64, MLMC_MIXED = 0, 1
 MLMC_QOI_MEAN, MLMC_QOI_CENTER = 1, 2
 MLMC_POINTS_LATTICE, MLMC_POINTS_EXPLICIT = 0, 1
 MLMC_PASS_TILE32, MLMC_PASS_TILE16, MLMC_PASS_STREAM = 0, 1, 2
+MLMC_FIELD_SEPARABLE_EXP, MLMC_FIELD_MATERN = 0, 1
 MLMC_BATCH_CLASSES = 10
 
 
@@ -37,7 +38,8 @@ class mlmc_config(C.Structure):
                 ("mu0", C.c_int32), ("mu1", C.c_int32), ("mu2", C.c_int32),
                 ("rtol", C.c_double), ("max_iters", C.c_int32), ("precision", C.c_int32),
                 ("qoi_mask", C.c_uint32), ("num_shifts", C.c_int32),
-                ("genvec", C.c_void_p), ("shifts", C.c_void_p), ("max_batch", C.c_int64)]
+                ("genvec", C.c_void_p), ("shifts", C.c_void_p), ("max_batch", C.c_int64),
+                ("field_kind", C.c_int32), ("nu", C.c_double), ("nystrom_q", C.c_int32)]
 
 
 class mlmc_points(C.Structure):
@@ -189,7 +191,8 @@ def _stream():
 
 
 def _config(n0, num_levels, s, corr_len, sigma2, mu0, mu1, mu2, rtol, max_iters, precision,
-            qoi_mask, genvec, shifts, max_batch):
+            qoi_mask, genvec, shifts, max_batch, field_kind=MLMC_FIELD_SEPARABLE_EXP, nu=0.5,
+            nystrom_q=0):
     """mlmc_config plus the host arrays it points to (kept alive by the caller)."""
     genvec = None if genvec is None else np.ascontiguousarray(genvec, dtype=np.uint32)
     shifts = None if shifts is None else np.ascontiguousarray(shifts, dtype=np.uint64)
@@ -199,7 +202,7 @@ def _config(n0, num_levels, s, corr_len, sigma2, mu0, mu1, mu2, rtol, max_iters,
                       int(precision), int(qoi_mask), R,
                       None if genvec is None else genvec.ctypes.data,
                       None if shifts is None else shifts.ctypes.data,
-                      int(max_batch))
+                      int(max_batch), int(field_kind), float(nu), int(nystrom_q))
     return cfg, genvec, shifts
 
 
@@ -208,10 +211,12 @@ class Context:
 
     def __init__(self, n0, num_levels, s, corr_len, sigma2, mu0=2, mu1=2, mu2=2, rtol=0.0,
                  max_iters=0, precision=MLMC_FP64, qoi_mask=MLMC_QOI_MEAN, genvec=None,
-                 shifts=None, max_batch=1024, device=0):
+                 shifts=None, max_batch=1024, device=0, field_kind=MLMC_FIELD_SEPARABLE_EXP,
+                 nu=0.5, nystrom_q=0):
         cfg, self._genvec, self._shifts = _config(n0, num_levels, s, corr_len, sigma2, mu0, mu1,
                                                   mu2, rtol, max_iters, precision, qoi_mask,
-                                                  genvec, shifts, max_batch)
+                                                  genvec, shifts, max_batch, field_kind, nu,
+                                                  nystrom_q)
         R = cfg.num_shifts
         h = C.c_void_p()
         _check(lib().mlmc_create(C.byref(cfg), int(device), C.byref(h)))
@@ -338,10 +343,12 @@ class Server:
 
     def __init__(self, n0, num_levels, s, corr_len, sigma2, genvec, shifts, mu0=2, mu1=2, mu2=2,
                  rtol=0.0, max_iters=0, precision=MLMC_FP64, qoi_mask=MLMC_QOI_MEAN,
-                 num_slots=2, slot_samples=1024, device=0):
+                 num_slots=2, slot_samples=1024, device=0, field_kind=MLMC_FIELD_SEPARABLE_EXP,
+                 nu=0.5, nystrom_q=0):
         cfg, self._genvec, self._shifts = _config(n0, num_levels, s, corr_len, sigma2, mu0, mu1,
                                                   mu2, rtol, max_iters, precision, qoi_mask,
-                                                  genvec, shifts, slot_samples)
+                                                  genvec, shifts, slot_samples, field_kind, nu,
+                                                  nystrom_q)
         h = C.c_void_p()
         _check(lib().mlmc_server_create(C.byref(cfg), int(device), int(num_slots),
                                         int(slot_samples), C.byref(h)))

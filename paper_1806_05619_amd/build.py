@@ -10,7 +10,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmlmc.so")
 SOURCES = ["host.hip", "kernels.hip", "kernels_fused.hip", "kernels_stream.hip", "kernels_mixed.hip",
-           "kernels_field.hip", "server.hip"]
+           "kernels_field.hip", "matern.hip", "server.hip"]
+# rocSOLVER (and the rocBLAS handle it runs on): the symmetric eigensolve of
+# the Nystrom matrix at context set-up
+LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -44,7 +47,8 @@ def build(jobs: int = 4) -> str:
     if failed:
         raise RuntimeError("hipcc failed for " + ", ".join(failed))
     tmp = LIB + ".tmp"
-    subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], check=True)
+    subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, *LIBS, "-o", tmp],
+                   check=True)
     os.replace(tmp, LIB)
     return LIB
 

@@ -720,11 +720,22 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
     if (c.max_batch < 1) return bad("max_batch must be >= 1");
     bool lattice = c.genvec && c.shifts;
     if (lattice && c.num_shifts < 1) return bad("num_shifts must be >= 1 with shifts");
+    if (c.field_kind != MLMC_FIELD_SEPARABLE_EXP && c.field_kind != MLMC_FIELD_MATERN)
+        return bad("unknown field_kind");
+    const bool matern = c.field_kind == MLMC_FIELD_MATERN;
+    const int nq_nodes = c.nystrom_q == 0 ? 32 : c.nystrom_q;
+    if (matern) {
+        if (!(c.nu > 0.0 && c.nu <= 8.0)) return bad("Matern nu must be in (0, 8]");
+        if (nq_nodes < 4 || nq_nodes > 96) return bad("nystrom_q must be 0 or in 4..96");
+        if (c.s > nq_nodes * nq_nodes) return bad("s exceeds nystrom_q^2 Nystrom eigenpairs");
+        if (device < 0) return bad("the Matern field's Nystrom eigensolve needs a device");
+    }
     if (parent) {
         const mlmc_config &q = parent->cfg;
         if (parent->host_only || parent->device != device || q.n0 != c.n0 ||
             q.num_levels != c.num_levels || q.s != c.s || q.corr_len != c.corr_len ||
-            q.sigma2 != c.sigma2 || q.precision != c.precision ||
+            q.sigma2 != c.sigma2 || q.precision != c.precision || q.field_kind != c.field_kind ||
+            (matern && (q.nu != c.nu || q.nystrom_q != c.nystrom_q)) ||
             parent->have_lattice != lattice || (lattice && q.num_shifts != c.num_shifts))
             return bad("parent context has another field, level or lattice configuration");
     }
@@ -732,6 +743,7 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
     mlmc_ctx ctx = new (std::nothrow) mlmc_ctx_s();
     if (!ctx) { g_create_error = "host allocation failed"; return MLMC_E_NOMEM; }
     ctx->cfg = c;
+    if (matern) ctx->cfg.nystrom_q = nq_nodes;
     ctx->cfg.genvec = nullptr;
     ctx->cfg.shifts = nullptr;
     if (!lattice) ctx->cfg.num_shifts = std::max(ctx->cfg.num_shifts, 1);
@@ -760,29 +772,31 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
     if (!ctx->host_only) CHK(hipSetDevice(device));
 
     // KL mode table: the s largest products theta_i theta_j (i, j <= s),
-    // descending, exact ties ordered by i ascending.
+    // descending, exact ties ordered by i ascending (separable kernel; the
+    // Matern eigenvalues come from the Nystrom eigensolve below).
     const int s = c.s;
     const double lam = c.corr_len;
-    std::vector<double> w(s), th(s);
-    for (int k = 1; k <= s; ++k) {
+    const int s1 = matern ? 0 : s;          // 1-D eigenpairs needed
+    std::vector<double> w(s1), th(s1);
+    for (int k = 1; k <= s1; ++k) {
         w[k - 1] = kl_root(lam, k);
         th[k - 1] = kl_eigenvalue(lam, w[k - 1]);
     }
     struct Pair { double t; int32_t i, j; };
     std::vector<Pair> pairs;
-    pairs.reserve((size_t)s * s);
-    for (int i = 1; i <= s; ++i)
-        for (int j = 1; j <= s; ++j) pairs.push_back({th[i - 1] * th[j - 1], i, j});
-    std::partial_sort(pairs.begin(), pairs.begin() + s, pairs.end(), [](const Pair &a, const Pair &b) {
+    pairs.reserve((size_t)s1 * s1);
+    for (int i = 1; i <= s1; ++i)
+        for (int j = 1; j <= s1; ++j) pairs.push_back({th[i - 1] * th[j - 1], i, j});
+    std::partial_sort(pairs.begin(), pairs.begin() + s1, pairs.end(), [](const Pair &a, const Pair &b) {
         if (a.t != b.t) return a.t > b.t;
         if (a.i != b.i) return a.i < b.i;
         return a.j < b.j;
     });
-    ctx->mi.resize(s);
-    ctx->mj.resize(s);
-    ctx->theta2.resize(s);
+    ctx->mi.assign(s, 0);
+    ctx->mj.assign(s, 0);
+    ctx->theta2.assign(s, 0.0);
     int pmax = 1;
-    for (int m = 0; m < s; ++m) {
+    for (int m = 0; m < s1; ++m) {
         ctx->mi[m] = pairs[m].i;
         ctx->mj[m] = pairs[m].j;
         ctx->theta2[m] = pairs[m].t;
@@ -790,13 +804,13 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
     }
     std::vector<Pair>().swap(pairs);
     const double sigma = std::sqrt(c.sigma2);
-    std::vector<double> coef(s);
-    for (int m = 0; m < s; ++m)
+    std::vector<double> coef(s1);
+    for (int m = 0; m < s1; ++m)
         coef[m] = sigma * std::sqrt(th[ctx->mi[m] - 1]) * std::sqrt(th[ctx->mj[m] - 1]);
     // 1-D eigenfunctions at the cell centres of every level
     std::vector<int64_t> psi_off(Gmax + 2);
     std::vector<double> psi;
-    for (int g = 0; g <= Gmax; ++g) {
+    for (int g = 0; g <= Gmax && !matern; ++g) {
         int n = 2 << g;
         psi_off[g] = (int64_t)psi.size();
         for (int k = 0; k < pmax; ++k)
@@ -909,6 +923,26 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
         CHK(hipMemcpy(ctx->d_z, c.genvec, sizeof(uint32_t) * s, hipMemcpyHostToDevice));
         CHK(hipMemcpy(ctx->d_shifts, c.shifts, sizeof(uint64_t) * (size_t)c.num_levels * c.num_shifts * s,
                       hipMemcpyHostToDevice));
+    }
+    if (matern) {
+        const std::string merr = matern_basis(nq_nodes, c.nu, lam, sigma, s, Gmax, ctx->d_basis,
+                                              ctx->Mmax, ctx->theta2);
+        if (!merr.empty()) {
+            ctx->err = merr;
+            return fail(merr.find("out of memory") != std::string::npos ? MLMC_E_NOMEM : MLMC_E_HIP);
+        }
+        if (mixed) {
+            launch_digits_cols(nullptr, ctx->d_basis, ctx->Mmax, s, ctx->Mmax, brows, ctx->sp,
+                               ctx->d_bdig, ctx->d_bexp);
+            CHK(hipGetLastError());
+            CHK(hipDeviceSynchronize());
+            void *fb = ctx->d_basis;
+            ctx->d_basis = nullptr;
+            (void)hipFree(fb);
+            ctx->allocs.erase(std::find(ctx->allocs.begin(), ctx->allocs.end(), fb));
+        }
+        *out = ctx;
+        return MLMC_OK;
     }
     // build the dense basis on the device from the 1-D tables
     double *d_psi = nullptr, *d_coef = nullptr;

@@ -174,6 +174,14 @@ void launch_fcg_copyback(hipStream_t st, double *x0, const double *x1, int n, in
 void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho, int64_t Bc,
                          double rtol, int32_t *st_iters, double *st_rho, int32_t *st_bad);
 
+// ---- Matern field by the Nystrom method (matern.hip) ----
+// KL basis sigma sqrt(theta_m) psi_m of the isotropic Matern covariance on
+// the cell centres of MG levels 0..G: basis [s][ld] (device), theta [s]
+// (host, descending).  Q x Q midpoint quadrature nodes.  Null stream,
+// synchronous.  Returns "" on success, else the error.
+std::string matern_basis(int Q, double nu, double lam, double sigma, int s, int G, double *basis,
+                         int64_t ld, std::vector<double> &theta);
+
 // ---- row-streaming passes (kernels_stream.hip), one workgroup per sample ----
 bool stream_supported(int n);
 void launch_pre_stream(hipStream_t st, int mu1, const double *a, const double *f,

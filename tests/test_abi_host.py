@@ -51,6 +51,9 @@ def _cfg(**kw):
     dict(rtol=1e-8, max_iters=0), dict(rtol=1e-8, max_iters=5, mu1=3),
     dict(rtol=1e-8, max_iters=5, mu2=0), dict(precision=1), dict(precision=7),
     dict(qoi_mask=0), dict(qoi_mask=4), dict(max_batch=0),
+    dict(field_kind=2), dict(field_kind=1, nu=0.0), dict(field_kind=1, nu=9.0),
+    dict(field_kind=1, nu=1.0, nystrom_q=3), dict(field_kind=1, nu=1.0, nystrom_q=97),
+    dict(field_kind=1, nu=1.0, nystrom_q=4, s=17),
 ])
 def test_create_rejects_invalid_config(bad):
     L = m.lib()
@@ -65,6 +68,12 @@ def _host_ctx(**kw):
     cfg = dict(n0=4, num_levels=3, s=10, corr_len=0.3, sigma2=1.0)
     cfg.update(kw)
     return m.Context(**cfg, device=-1)
+
+
+def test_matern_field_needs_a_device():
+    # the Nystrom eigensolve runs on the GPU: no host-only Matern context
+    with pytest.raises(m.MlmcError):
+        _host_ctx(field_kind=m.MLMC_FIELD_MATERN, nu=1.0)
 
 
 def test_host_only_context_refuses_gpu_calls():

@@ -1,0 +1,116 @@
+"""GPU tests of the Matern field (Section 5, eq. matern, Nystrom method)
+against the oracle's independent Nystrom basis (scipy Bessel function, LAPACK
+eigensolver).
+
+The eigenfunctions of an isotropic covariance on the square come in
+degenerate pairs, inside which any rotation is an equally valid basis, so the
+comparison is on what is unique: the eigenvalues, each basis function whose
+eigenvalue is isolated (up to sign), and the covariance of the truncated
+field sum_m b_m(x) b_m(x'), with s chosen at a gap of the spectrum so that no
+eigenspace is cut."""
+import numpy as np
+import pytest
+
+from oracle import matern as om
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1806_05619_amd as m  # noqa: E402
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _gap_s(theta, s_max):
+    """Largest s <= s_max with theta_s clearly above theta_{s+1}."""
+    for s in range(s_max, 1, -1):
+        if theta[s - 1] > theta[s] * (1 + 1e-6):
+            return s
+    return 1
+
+
+def _ctx(nu, lam, s, Q, precision=m.MLMC_FP64, num_levels=2, sigma2=1.0, **kw):
+    if precision == m.MLMC_MIXED:
+        kw.setdefault("rtol", 1e-10)
+        kw.setdefault("max_iters", 60)
+    return m.Context(n0=4, num_levels=num_levels, s=s, corr_len=lam, sigma2=sigma2,
+                     field_kind=m.MLMC_FIELD_MATERN, nu=nu, nystrom_q=Q, precision=precision,
+                     qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER, max_batch=64, device=0, **kw)
+
+
+def _gpu_basis(ctx, level=None):
+    """The basis rows b_m on every cell of the hierarchy: the field of the unit
+    vectors y = e_m."""
+    lev = ctx.cfg.num_levels - 1 if level is None else level
+    s = ctx.cfg.s
+    y = torch.eye(s, dtype=torch.float64, device="cuda:0")
+    z = torch.empty((s, ctx.field_size(lev)), dtype=torch.float64, device="cuda:0")
+    ctx.field(ctx.explicit(lev, y), z)
+    torch.cuda.synchronize()
+    return z.cpu().numpy()
+
+
+@pytest.mark.parametrize("nu,lam,Q", [(0.5, 0.3, 16), (1.0, 0.1, 16), (2.0, 0.5, 12), (1.5, 0.3, 20)])
+def test_nystrom_eigenvalues_and_basis_match_oracle(nu, lam, Q):
+    _dev()
+    th_o, _ = om.nystrom(Q, nu, lam)
+    s = _gap_s(th_o, 30)
+    sigma2 = 1.7
+    ctx = _ctx(nu, lam, s, Q, sigma2=sigma2)
+    i, j, th = ctx.kl_modes()
+    assert np.all(i == 0) and np.all(j == 0)
+    assert np.max(np.abs(th - th_o[:s])) < 1e-12, (th[:4], th_o[:4])
+    G = 2                                   # MG levels 0..2: 2^2, 4^2, 8^2 cells
+    _, b_o = om.hierarchy_basis(Q, nu, lam, sigma2, s, G)
+    b = _gpu_basis(ctx)
+    assert b.shape == b_o.shape
+    scale = np.max(np.abs(b_o))
+    K, K_o = b.T @ b, b_o.T @ b_o
+    assert np.max(np.abs(K - K_o)) < 1e-11 * np.max(np.abs(K_o))
+    isolated = [k for k in range(s)
+                if (k == 0 or th_o[k - 1] > th_o[k] * (1 + 1e-6)) and th_o[k] > th_o[k + 1] * (1 + 1e-6)]
+    assert len(isolated) >= 2
+    for k in isolated:
+        sg = np.sign(b[k] @ b_o[k])
+        assert np.max(np.abs(sg * b[k] - b_o[k])) < 1e-10 * scale, k
+
+
+def test_matern_full_path_and_mixed_digits():
+    """Fixed-cycle solves on the Matern field: the QoIs of lattice-free
+    explicit points equal those of the same solve fed the library's own field
+    z; the mixed context's digit-product field is within its stated bound of
+    the FP64 one."""
+    dev = _dev()
+    nu, lam, Q = 1.0, 0.3, 16
+    th_o, _ = om.nystrom(Q, nu, lam)
+    s = _gap_s(th_o, 40)
+    ctx = _ctx(nu, lam, s, Q, num_levels=3)
+    y = torch.tensor(np.random.default_rng(3).standard_normal((20, s)), device=dev)
+    pts = ctx.explicit(2, y)
+    q1 = torch.full((20, 3, 2), float("nan"), dtype=torch.float64, device=dev)
+    ctx.fmg_solve(pts, qoi=q1)
+    z = torch.empty((20, ctx.field_size(2)), dtype=torch.float64, device=dev)
+    ctx.field(pts, z)
+    q2 = torch.full_like(q1, float("nan"))
+    ctx.fmg_solve(pts, z=z, qoi=q2)
+    torch.cuda.synchronize()
+    q1, q2 = q1.cpu().numpy(), q2.cpu().numpy()
+    assert np.all(np.isfinite(q1)) and np.all(q1 > 0)
+    assert np.array_equal(q1, q2)
+    # the field equals y . basis with the oracle's covariance: var of z at a
+    # cell = sum_m b_m^2 (up to the basis rotation, which the sum ignores)
+    _, b_o = om.hierarchy_basis(Q, nu, lam, 1.0, s, 3)
+    zz = z.cpu().numpy()
+    assert np.max(np.abs(zz - y.cpu().numpy() @ _gpu_basis(ctx, 2))) < 1e-12
+    var_gpu = (_gpu_basis(ctx, 2) ** 2).sum(0)
+    assert np.max(np.abs(var_gpu - (b_o ** 2).sum(0))) < 1e-11
+    mx = _ctx(nu, lam, s, Q, precision=m.MLMC_MIXED, num_levels=3)
+    zm = torch.empty_like(z)
+    mx.field(mx.explicit(2, y), zm)
+    torch.cuda.synchronize()
+    # |error| <= 5 s 2^(E_y + E_b - 32): with |y| < 8 and |b| < 2, E_y + E_b <= 4
+    assert np.max(np.abs(zm.cpu().numpy() - zz)) <= 5 * s * 2.0 ** (4 - 32)
