@@ -311,6 +311,52 @@ def methods(m, torch, eps_list=(2e-3, 1e-3, 5e-4, 2.5e-4)):
     return out
 
 
+def matern_fields(m, torch, Q=64, samples=1024, reps=3):
+    """The paper's field families (Section 6): isotropic Matern covariance with
+    lambda_c in {0.1, 0.3, 0.5} and nu in {0.5, 1, 2}, KL eigenpairs by the
+    Nystrom method on Q x Q nodes, s the smallest number of terms that keeps
+    99.8% of the variance (the eigenvalues of the Nystrom matrix sum to the
+    area of the domain, 1), at most Q^2.  Per field: set-up time of the
+    context (eigensolve and basis), and FP64 samples/s on the benchmark's
+    grids (4^2 .. 256^2, 2 V(2,2) per FMG stage) for N(0,1) points."""
+    out = {}
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(11)
+    base = dict(n0=4, sigma2=1.0, mu0=2, mu1=2, mu2=2, field_kind=m.MLMC_FIELD_MATERN,
+                nystrom_q=Q, qoi_mask=m.MLMC_QOI_MEAN, device=0)
+    for lam in (0.1, 0.3, 0.5):
+        for nu in (0.5, 1.0, 2.0):
+            # all Q^2 eigenvalues from a context on the 2^2 .. 4^2 grids only
+            probe = m.Context(**base, num_levels=1, s=Q * Q, corr_len=lam, nu=nu, max_batch=1)
+            th = probe.kl_modes()[2]
+            probe.close()
+            s = int(min(Q * Q, np.searchsorted(np.cumsum(th), 0.998) + 1))
+            t0 = time.perf_counter()
+            ctx = m.Context(**base, num_levels=7, s=s, corr_len=lam, nu=nu, max_batch=samples)
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
+            y = torch.tensor(rng.standard_normal((samples, s)), device=dev)
+            pts = ctx.explicit(6, y)
+            q = torch.zeros((samples, 7, 1), dtype=torch.float64, device=dev)
+            ctx.fmg_solve(pts, qoi=q)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.fmg_solve(pts, qoi=q)
+            torch.cuda.synchronize()
+            rate = samples * reps / (time.perf_counter() - t0)
+            key = f"lambda {lam} nu {nu}"
+            out[key] = dict(s=s, variance_kept=float(np.sum(th[:s])), setup_s=t_setup,
+                            samples_per_s=rate, mean_qoi_256=float(q[:, 6, 0].mean()))
+            log(f"[bench] matern {key}: s {s} ({np.sum(th[:s]):.4f} of the variance), "
+                f"set-up {t_setup:.2f} s, {rate:.0f} samples/s at 256^2")
+            del ctx, y, q
+            torch.cuda.empty_cache()
+    return dict(workload=f"isotropic Matern fields, Nystrom on {Q}x{Q} nodes, sigma^2 1, FP64, "
+                         f"4^2..256^2, 2 V(2,2) per stage, {samples} N(0,1) samples",
+                fields=out)
+
+
 def uneven(m, torch, slots=3, reps=2):
     """Uneven levels: 4^2 .. 2048^2 with 2^(16-l) samples on level l (all 16
     shifts), mixed path refined to 1e-10.  One context solving the levels one
@@ -426,6 +472,8 @@ def main():
                     help="skip the mixed-vs-FP64 comparison on the s = 400 workload")
     ap.add_argument("--only-mixed", action="store_true",
                     help="run only the mixed-vs-FP64 comparison (prints its JSON object)")
+    ap.add_argument("--only-matern", action="store_true",
+                    help="only the Matern field families (Nystrom basis, 9 fields)")
     ap.add_argument("--only-methods", action="store_true",
                     help="run only the MLMC / MLQMC / recycling comparison (prints its JSON object)")
     ap.add_argument("--only-serving", action="store_true",
@@ -456,6 +504,9 @@ def main():
         return
     if args.only_methods:
         print(json.dumps(methods(m, torch)), flush=True)
+        return
+    if args.only_matern:
+        print(json.dumps(matern_fields(m, torch)), flush=True)
         return
     w = synth.workload("mlqmc_fp64_s100")
     k = w["num_levels"] - 1
@@ -592,6 +643,7 @@ def main():
         out["latency"] = lat
         out["serving"] = serving(m, torch)
         out["methods"] = methods(m, torch)
+        out["matern"] = matern_fields(m, torch)
         if not args.no_mixed:
             del ctx
             torch.cuda.empty_cache()
