@@ -357,6 +357,62 @@ def matern_fields(m, torch, Q=64, samples=1024, reps=3):
                 fields=out)
 
 
+def recycling_by_smoothness(m, torch, lam=0.3, nus=(0.5, 1.0, 2.0), eps_list=(2e-4, 1e-4, 5e-5),
+                            Q=64):
+    """Section 6's finding on this implementation: recycling the coarse FMG
+    solutions pays more for rougher fields.  For Matern fields of correlation
+    length lam and smoothness nu (s by the 99.8% rule on Q x Q Nystrom
+    nodes), Algorithm 1 with lattice points (16 shifts) runs to RMSE eps
+    without (MLQMC) and with (MG-MLQMC) recycling.  Per run: GPU wall time,
+    points per level, finest level; for MG-MLQMC the recycled fractions and
+    the cost of its own sample counts with recycling over without
+    (Proposition 1's quantity, independent of timing noise)."""
+    import synth
+    from paper_1806_05619_amd.driver import GpuSampler, mg_mlqmc, recycling_report
+    out = dict(workload=f"isotropic Matern, lambda_c {lam}, sigma^2 1, Nystrom {Q}x{Q}, "
+                        "4^2..256^2, FP64, 2 V(2,2) per stage, QoI mean(u), 16 shifts",
+               fields={})
+    seed, L1, R = 5, 7, 16
+    for nu in nus:
+        probe = m.Context(n0=4, num_levels=1, s=Q * Q, corr_len=lam, sigma2=1.0,
+                          field_kind=m.MLMC_FIELD_MATERN, nu=nu, nystrom_q=Q, max_batch=1,
+                          device=0)
+        th = probe.kl_modes()[2]
+        probe.close()
+        s = int(min(Q * Q, np.searchsorted(np.cumsum(th), 0.998) + 1))
+        ctx = m.Context(n0=4, num_levels=L1, s=s, corr_len=lam, sigma2=1.0, mu0=2, mu1=2, mu2=2,
+                        field_kind=m.MLMC_FIELD_MATERN, nu=nu, nystrom_q=Q,
+                        qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
+                        genvec=synth.korobov_vector(seed, s),
+                        shifts=synth.shift_table(seed, L1, R, s), max_batch=4096, device=0)
+        mg_mlqmc(GpuSampler(ctx), eps_list[0], max_level=L1 - 1)      # warm-up
+        runs = []
+        for eps in eps_list:
+            row = {}
+            for name, reuse in (("MLQMC", False), ("MG_MLQMC", True)):
+                t0 = time.perf_counter()
+                r = mg_mlqmc(GpuSampler(ctx), eps, max_level=L1 - 1, reuse=reuse,
+                             max_points=1 << 20)
+                dt = time.perf_counter() - t0
+                run = dict(method=name, eps=eps, seconds=dt, L=r["L"], N=r["N"].tolist(),
+                           q_bar=r["q_bar"], converged=r["converged"])
+                if reuse:
+                    rep = recycling_report(r["N"], r["cost"])
+                    run["new_fraction"] = rep["new_fraction"]
+                    run["cost_with_over_without"] = rep["cost_ratio"]
+                runs.append(run)
+                row[name] = run
+            log(f"[bench] recycling nu {nu} (s {s}) eps {eps:g}: MLQMC {row['MLQMC']['seconds']:.3f} s "
+                f"(L {row['MLQMC']['L']}), MG-MLQMC {row['MG_MLQMC']['seconds']:.3f} s "
+                f"(L {row['MG_MLQMC']['L']}), its cost with/without recycling "
+                f"{row['MG_MLQMC']['cost_with_over_without']:.2f}, converged "
+                f"{row['MLQMC']['converged'] and row['MG_MLQMC']['converged']}")
+        out["fields"][f"nu {nu}"] = dict(s=s, runs=runs)
+        del ctx
+        torch.cuda.empty_cache()
+    return out
+
+
 def uneven(m, torch, slots=3, reps=2):
     """Uneven levels: 4^2 .. 2048^2 with 2^(16-l) samples on level l (all 16
     shifts), mixed path refined to 1e-10.  One context solving the levels one
@@ -473,7 +529,7 @@ def main():
     ap.add_argument("--only-mixed", action="store_true",
                     help="run only the mixed-vs-FP64 comparison (prints its JSON object)")
     ap.add_argument("--only-matern", action="store_true",
-                    help="only the Matern field families (Nystrom basis, 9 fields)")
+                    help="only the Matern field families and recycling against smoothness")
     ap.add_argument("--only-methods", action="store_true",
                     help="run only the MLMC / MLQMC / recycling comparison (prints its JSON object)")
     ap.add_argument("--only-serving", action="store_true",
@@ -506,7 +562,8 @@ def main():
         print(json.dumps(methods(m, torch)), flush=True)
         return
     if args.only_matern:
-        print(json.dumps(matern_fields(m, torch)), flush=True)
+        print(json.dumps(dict(matern=matern_fields(m, torch),
+                              recycling=recycling_by_smoothness(m, torch))), flush=True)
         return
     w = synth.workload("mlqmc_fp64_s100")
     k = w["num_levels"] - 1
@@ -644,6 +701,7 @@ def main():
         out["serving"] = serving(m, torch)
         out["methods"] = methods(m, torch)
         out["matern"] = matern_fields(m, torch)
+        out["recycling_by_smoothness"] = recycling_by_smoothness(m, torch)
         if not args.no_mixed:
             del ctx
             torch.cuda.empty_cache()
