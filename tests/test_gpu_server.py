@@ -158,3 +158,24 @@ def test_server_concurrent_clients_collect_their_own_results():
     for (c, tag), (r, res) in got.items():
         assert res["status"] == m.MLMC_OK and res["tag"] == tag
         assert np.array_equal(res["qoi"], _direct(ctx, *r)), (c, tag, r)
+
+
+def test_server_on_matern_field_equals_direct_solves():
+    """Slots of a Matern configuration share the first slot's Nystrom basis;
+    every served result is bitwise the direct solve of its points."""
+    _dev()
+    w = synth.workload("mlqmc_fp64_s100")
+    s = 60
+    kw = dict(n0=4, num_levels=5, s=s, corr_len=0.3, sigma2=1.0, mu0=2, mu1=2, mu2=2,
+              qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER, field_kind=m.MLMC_FIELD_MATERN,
+              nu=1.0, nystrom_q=16, genvec=synth.korobov_vector(w["seed"], s),
+              shifts=synth.shift_table(w["seed"], 5, 16, s))
+    rng = np.random.default_rng(21)
+    reqs = _requests(rng, 5, 24, 48)
+    with m.Server(**kw, num_slots=2, slot_samples=48, device=0) as srv:
+        tags = [srv.submit(*r) for r in reqs]
+        res = srv.collect(tags, timeout_s=120)
+    ctx = m.Context(**kw, max_batch=48, device=0)
+    for r, out in zip(reqs, res):
+        assert out["status"] == m.MLMC_OK
+        assert np.array_equal(out["qoi"], _direct(ctx, *r)), r
