@@ -41,9 +41,10 @@ KERNEL_NAMES = dict(
     points="k_points", field="k_field_mfma64", smooth="k_rbgs (one colour)",
     restrict="k_resid_restrict", prolong="k_prolong", coarse="k_coarse_solve", qoi="k_qoi",
     sums="k_sums",
-    pre="k_pre_tile<32,256,2,double> (2 red-black sweeps + residual + restriction, 32^2..256^2)",
-    post="k_stream<2,post> / k_post_tile<32,256,2,double> (prolongation + correction + 2 sweeps, "
-         "32^2..256^2)",
+    pre="pre pass (2 red-black sweeps + residual + restriction): k_stream<2,pre> on 128^2 and "
+        "256^2, k_pre_tile<32,256,2,double> on 32^2 and 64^2",
+    post="post pass (prolongation + correction + 2 sweeps): k_stream<2,post> on 64^2..256^2, "
+         "k_post_tile<32,256,2,double> on 32^2",
     lds="k_lds_fmg_fixed, k_lds_vcycle (LDS-resident grids <= 16^2)",
     refine="k_fcg_* (flexible-CG vector passes, grids >= 64^2)")
 
@@ -55,7 +56,8 @@ def log(*a):
 # HBM bytes per launch of a kernel from two rocprofv3 --pmc passes (FETCH_SIZE,
 # WRITE_SIZE), scaled by the same counters on a 1 GiB copy; valid only while
 # the kernel source is the one the counters were taken on.
-TRAFFIC_RECORDS = dict(pre="profiles/pre_tile_mlqmc_fp64_s100_256_traffic.txt")
+TRAFFIC_RECORDS = dict(pre="profiles/pre_pass_mlqmc_fp64_s100_256_traffic.txt",
+                       post="profiles/post_pass_mlqmc_fp64_s100_256_traffic.txt")
 
 
 def measured_traffic(kind):
@@ -65,9 +67,11 @@ def measured_traffic(kind):
         return None, "no counter record"
     with open(os.path.join(ROOT, rec)) as fh:
         r = json.load(fh)
-    with open(os.path.join(ROOT, r["source"]), "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()
-    if sha != r["source_sha256"]:
+    h = hashlib.sha256()
+    for src in r["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != r["sources_sha256"]:
         return None, f"{rec}: kernel source changed since the counters were taken"
     return r["hbm_bytes_per_launch"], rec
 

@@ -318,9 +318,11 @@ mlmc_status mlmc_profile_end(mlmc_ctx ctx, mlmc_profile_result *out);
  * n and batch class c: chunks of Bc samples with 4^(c-1) < Bc <= 4^c (c = 0
  * for one sample), c < MLMC_BATCH_CLASSES (the last class takes every larger
  * chunk).  A new context starts from defaults measured on MI355X, a rule in
- * the number of 32 x 32 tiles of the pass, t = 4^c (n/32)^2: TILE16 for
- * t <= 256; STREAM for the post pass when t >= 65536 and n >= 128 (FP64);
- * TILE32 otherwise.  A server's slots take the first slot's table. */
+ * c and the number of 32 x 32 tiles of the pass, t = 4^c (n/32)^2: TILE16
+ * for t <= 256, TILE32 otherwise; where STREAM exists (FP64, 64 <= n <= 512)
+ * it takes the post pass for c >= 6 (c >= 5 when n >= 256) and the pre pass
+ * for t >= 262144 when n >= 128.  A server's slots take the first slot's
+ * table. */
 enum { MLMC_PASS_TILE32 = 0, MLMC_PASS_TILE16 = 1, MLMC_PASS_STREAM = 2 };
 enum { MLMC_BATCH_CLASSES = 10 };
 typedef struct {

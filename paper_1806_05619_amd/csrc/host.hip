@@ -422,20 +422,23 @@ bool kind_allowed(mlmc_ctx c, int g, int kind)
 
 // Defaults: the choices mlmc_autotune made on MI355X for the s = 100 FP64
 // workload (grids 32^2 .. 256^2, batch classes up to 16384 samples), as a
-// rule in the number of 32 x 32 tiles a pass covers, 4^c (n/32)^2: up to 256
-// (one per CU or fewer) 16 x 16 tiles, which give four times the workgroups;
-// from 65536 on row streaming for the post pass where it exists; 32 x 32
-// tiles otherwise.
+// rule in the batch class c and the number of 32 x 32 tiles a pass covers,
+// t = 4^c (n/32)^2: up to 256 tiles (one per CU or fewer) 16 x 16 tiles,
+// which give four times the workgroups; 32 x 32 tiles otherwise; where the
+// FP64 row-streaming passes exist (64^2 .. 512^2), they take the post pass
+// from c = 6 on (more than 1024 samples; from c = 5 on grids of 256^2 and
+// more) and the pre pass from t = 262144 on grids of 128^2 and more.
 void default_tuning(mlmc_ctx c)
 {
     for (int g = 0; g < kMaxMgLevels; ++g) {
-        const int64_t side = std::max(1, (2 << g) / 32);
+        const int n = 2 << g;
+        const int64_t side = std::max(1, n / 32);
+        const bool stream = kind_allowed(c, g, kStream);
         for (int cl = 0; cl < MLMC_BATCH_CLASSES; ++cl) {
             const int64_t tiles = ((int64_t)1 << (2 * cl)) * side * side;
             const int8_t tile = tiles <= 256 ? kTile16 : kTile32;
-            c->pre_kind[g][cl] = tile;
-            c->post_kind[g][cl] =
-                tiles >= 65536 && (2 << g) >= 128 && kind_allowed(c, g, kStream) ? kStream : tile;
+            c->pre_kind[g][cl] = stream && n >= 128 && tiles >= 262144 ? kStream : tile;
+            c->post_kind[g][cl] = stream && (cl >= 6 || (n >= 256 && cl >= 5)) ? kStream : tile;
         }
     }
 }

@@ -52,27 +52,33 @@ __device__ __forceinline__ void static_for(F &&f)
     }
 }
 
-// Stencil of the lane's two cells of one row, stored by colour (red cell
-// first): sweeps of a known colour then read fixed fields, so the window stays
-// in registers.  wS of a cell is wN of the cell below, which has the other
-// colour in the row below.
+// Face weights of the lane's two cells (columns c0 = 2L, c1 = 2L+1) of one
+// row, by column: the face between them is stored once, a wall face holds
+// 2 a_P as in the tile passes, and the south faces of a row are the north
+// faces of the row below (row -1 holds the south wall of row 0).  The
+// diagonal and its reciprocal are formed again at each use from the same
+// rounded weights in the same order, so they carry the same bits as a
+// stored copy would, and the window needs 5 doubles a row (7 with f).
+template <bool F1>
 struct RowW {
-    double wE_r, wW_r, wN_r, dw_r, inv_r, rhs_r;   // dw: wall term, 2 a_P per wall face
-    double wE_b, wW_b, wN_b, dw_b, inv_b, rhs_b;
+    double wW0, wC, wE1, wN0, wN1;   // W face of c0, c0|c1, E face of c1, N faces
+    double rhs0, rhs1;                // h^2 f (unused when f = 1)
 };
 
 // field-wise copy (a struct copy becomes a memcpy that keeps the window in
 // scratch memory)
-__device__ __forceinline__ void copy_row(RowW &d, const RowW &s)
+template <bool F1>
+__device__ __forceinline__ void copy_row(RowW<F1> &d, const RowW<F1> &s)
 {
-    d.wE_r = s.wE_r; d.wW_r = s.wW_r; d.wN_r = s.wN_r; d.dw_r = s.dw_r; d.inv_r = s.inv_r; d.rhs_r = s.rhs_r;
-    d.wE_b = s.wE_b; d.wW_b = s.wW_b; d.wN_b = s.wN_b; d.dw_b = s.dw_b; d.inv_b = s.inv_b; d.rhs_b = s.rhs_b;
+    d.wW0 = s.wW0; d.wC = s.wC; d.wE1 = s.wE1; d.wN0 = s.wN0; d.wN1 = s.wN1;
+    if constexpr (!F1) { d.rhs0 = s.rhs0; d.rhs1 = s.rhs1; }
 }
 
-__device__ __forceinline__ void zero_row(RowW &d)
+template <bool F1>
+__device__ __forceinline__ void zero_row(RowW<F1> &d)
 {
-    d.wE_r = d.wW_r = d.wN_r = d.dw_r = d.inv_r = d.rhs_r = 0.0;
-    d.wE_b = d.wW_b = d.wN_b = d.dw_b = d.inv_b = d.rhs_b = 0.0;
+    d.wW0 = d.wC = d.wE1 = d.wN0 = d.wN1 = 0.0;
+    d.rhs0 = d.rhs1 = 0.0;
 }
 
 // coarse values of row R's prolongation for lane L: columns L-1, L, L+1 of
@@ -99,6 +105,30 @@ __device__ __forceinline__ void prolong2(const Coarse6 &k, double &v0, double &v
     v0 = prolong_9331(k.c0, k.m0, k.c1, k.m1);
     v1 = prolong_9331(k.c0, k.p0, k.c1, k.p1);
 }
+
+// Faces of the lane's cell in column K (0: c0, 1: c1) of a row: r the row,
+// rs the row below.
+template <int K, bool F1>
+struct Faces {
+    double e, w, nn, s;
+    __device__ __forceinline__ Faces(const RowW<F1> &r, const RowW<F1> &rs)
+    {
+        e = K == 0 ? r.wC : r.wE1;
+        w = K == 0 ? r.wW0 : r.wC;
+        nn = K == 0 ? r.wN0 : r.wN1;
+        s = K == 0 ? rs.wN0 : rs.wN1;
+    }
+    // the diagonal as the tile passes form it: E + W + N + S, no contraction
+    __device__ __forceinline__ double diag() const
+    {
+#pragma clang fp contract(off)
+        double d = e;
+        d += w;
+        d += nn;
+        d += s;
+        return d;
+    }
+};
 
 // PRE: init 0 = read u_in, 1 = zero, 2 = u = P uc.  POST: u = u_in + P ec.
 // The result goes to u_out (may equal u_in: rows are read before written).
@@ -146,7 +176,7 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
         const int64_t o = (int64_t)R * n;
         pa0 = ab[o + c0];
         pa1 = ab[o + c1];
-        if (fb) {
+        if (!F1) {
             pf0 = fb[o + c0];
             pf1 = fb[o + c1];
         }
@@ -159,14 +189,17 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
     fetch(0);
     __syncthreads();
 
-    RowW w[NS];
+    RowW<F1> w[NS];
     static_for<0, NS>([&](auto K) __attribute__((always_inline)) { zero_row(w[K.value]); });
     double rhs_cur0 = 0, rhs_cur1 = 0, rkeep0 = 0, rkeep1 = 0;
     const int s_end = PRE ? n + D : n + D - 1;
 
-    for (int s = 0; s <= s_end; ++s) {
+    // One pipeline step for row s entering; P = s & 1, so that every row
+    // parity below is known at compile time.
+    auto step = [&](int s, auto Pc) __attribute__((always_inline)) {
+        constexpr int P = decltype(Pc)::value;
         // (A) row s enters the rings; fetch row s + 1
-        double rhs_prev0 = rhs_cur0, rhs_prev1 = rhs_cur1;
+        const double rhs_prev0 = rhs_cur0, rhs_prev1 = rhs_cur1;
         if (s < n && lane) {
             double u0 = pu0, u1 = pu1;
             if (need_coarse) {
@@ -181,55 +214,36 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
             u_ring[(s & 7) * n + c1] = u1;
             a_ring[(s & 1) * n + c0] = pa0;
             a_ring[(s & 1) * n + c1] = pa1;
-            rhs_cur0 = h2 * pf0;
-            rhs_cur1 = h2 * pf1;
+            if (!F1) {
+                rhs_cur0 = h2 * pf0;
+                rhs_cur1 = h2 * pf1;
+            }
             fetch(s + 1);
         }
         __syncthreads();
 
-        // (B) stencil of row q = s - 1 (its upper neighbour row s is now present)
+        // (B) faces of row q = s - 1 (its upper neighbour row s is now present)
         static_for<0, NS - 1>([&](auto K) __attribute__((always_inline)) {
             copy_row(w[NS - 1 - K.value], w[NS - 2 - K.value]);
         });
         const int q = s - 1;
         if (q >= 0 && q < n && lane) {
-            // no contraction: weights and diagonal round as in the tile passes
-#pragma clang fp contract(off)
             const double *aq = a_ring + (q & 1) * n, *aq1 = a_ring + ((q + 1) & 1) * n;
             const double ap0 = aq[c0], ap1 = aq[c1];
-            // faces of the two cells (zero weight at a wall, whose 2a_P goes to d)
-            const double wE0 = hmean(ap0, ap1);                       // c0|c1
-            const double wE1 = (c1 + 1 < n) ? hmean(ap1, aq[c1 + 1]) : 0.0;
-            const double wW0 = (c0 > 0) ? hmean(ap0, aq[c0 - 1]) : 0.0;
-            const double wN0 = (q + 1 < n) ? hmean(ap0, aq1[c0]) : 0.0;
-            const double wN1 = (q + 1 < n) ? hmean(ap1, aq1[c1]) : 0.0;
-            // south faces: wN of the cell below, stored by that row's colours
-            // (row q-1 has the opposite parity: c0 there is black if c0 here is red)
-            const bool odd = q & 1;                // c0 is red iff q is even
-            const double wS0 = (q > 0) ? (odd ? w[1].wN_r : w[1].wN_b) : 0.0;
-            const double wS1 = (q > 0) ? (odd ? w[1].wN_b : w[1].wN_r) : 0.0;
-            double d0 = 0.0, d1 = 0.0;             // E, W, N, S in this order
-            d0 += wE0;
-            d0 += (c0 > 0) ? wW0 : 2.0 * ap0;
-            d0 += (q + 1 < n) ? wN0 : 2.0 * ap0;
-            d0 += (q > 0) ? wS0 : 2.0 * ap0;
-            d1 += (c1 + 1 < n) ? wE1 : 2.0 * ap1;
-            d1 += wE0;
-            d1 += (q + 1 < n) ? wN1 : 2.0 * ap1;
-            d1 += (q > 0) ? wS1 : 2.0 * ap1;
-            const double dw0 = ((c0 > 0) ? 0.0 : 2.0 * ap0) + ((q + 1 < n) ? 0.0 : 2.0 * ap0) +
-                               ((q > 0) ? 0.0 : 2.0 * ap0);
-            const double dw1 = ((c1 + 1 < n) ? 0.0 : 2.0 * ap1) + ((q + 1 < n) ? 0.0 : 2.0 * ap1) +
-                               ((q > 0) ? 0.0 : 2.0 * ap1);
-            const double i0 = frcp_s(d0), i1 = frcp_s(d1);
-            RowW &r = w[0];
-            r.wE_r = odd ? wE1 : wE0;   r.wE_b = odd ? wE0 : wE1;
-            r.wW_r = odd ? wE0 : wW0;   r.wW_b = odd ? wW0 : wE0;
-            r.wN_r = odd ? wN1 : wN0;   r.wN_b = odd ? wN0 : wN1;
-            r.dw_r = odd ? dw1 : dw0;   r.dw_b = odd ? dw0 : dw1;
-            r.inv_r = odd ? i1 : i0;    r.inv_b = odd ? i0 : i1;
-            r.rhs_r = odd ? rhs_prev1 : rhs_prev0;
-            r.rhs_b = odd ? rhs_prev0 : rhs_prev1;
+            RowW<F1> &r = w[0];
+            r.wC = hmean(ap0, ap1);
+            r.wW0 = c0 > 0 ? hmean(ap0, aq[c0 - 1]) : 2.0 * ap0;
+            r.wE1 = c1 + 1 < n ? hmean(ap1, aq[c1 + 1]) : 2.0 * ap1;
+            r.wN0 = q + 1 < n ? hmean(ap0, aq1[c0]) : 2.0 * ap0;
+            r.wN1 = q + 1 < n ? hmean(ap1, aq1[c1]) : 2.0 * ap1;
+            if constexpr (!F1) {
+                r.rhs0 = rhs_prev0;
+                r.rhs1 = rhs_prev1;
+            }
+            if (q == 0) {          // south wall of row 0, in the slot of row -1
+                w[1].wN0 = 2.0 * ap0;
+                w[1].wN1 = 2.0 * ap1;
+            }
         }
 
         // (C) half-sweep t on row s - t (register slot t - 1)
@@ -238,60 +252,54 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
             const int rr = s - t;
             if (rr >= 0 && rr < n && lane) {
                 constexpr bool red = PRE ? (t & 1) : !(t & 1);
-                const RowW &r = w[t - 1];
-                const RowW &rs = w[t];
+                // the red cell of row rr is column c0 when rr is even
+                constexpr int K = red ? ((P - t) & 1) : 1 - ((P - t) & 1);
+                const Faces<K, F1> fw(w[t - 1], w[t]);
                 double *row = u_ring + (rr & 7) * n;
                 const double *up = u_ring + ((rr + 1) & 7) * n;
                 const double *dn = u_ring + ((rr - 1) & 7) * n;
-                // the red cell of row rr is column c0 when rr is even
-                const int c = red ? c0 + (rr & 1) : c1 - (rr & 1);
-                // explicit fma in the face order E, W, N, S of the tile passes,
-                // so that both kinds of pass give the same bits
-                double num = F1 ? h2 : (red ? r.rhs_r : r.rhs_b);
-                if (c + 1 < n) num = fma(red ? r.wE_r : r.wE_b, row[c + 1], num);
-                if (c > 0) num = fma(red ? r.wW_r : r.wW_b, row[c - 1], num);
-                if (rr + 1 < n) num = fma(red ? r.wN_r : r.wN_b, up[c], num);
-                if (rr > 0) num = fma(red ? rs.wN_b : rs.wN_r, dn[c], num);
-                row[c] = num * (red ? r.inv_r : r.inv_b);
+                const int c = K == 0 ? c0 : c1;
+                // explicit fma in the face order E, W, N, S of the tile passes
+                // (a wall face meets a neighbour of value 0 there: skipped)
+                double num = F1 ? h2 : (K == 0 ? w[t - 1].rhs0 : w[t - 1].rhs1);
+                if (c + 1 < n) num = fma(fw.e, row[c + 1], num);
+                if (c > 0) num = fma(fw.w, row[c - 1], num);
+                if (rr + 1 < n) num = fma(fw.nn, up[c], num);
+                if (rr > 0) num = fma(fw.s, dn[c], num);
+                row[c] = num * frcp_s(fw.diag());
             }
             __syncthreads();
         });
 
         // (D) leave the pipeline
-        if (PRE) {
+        if constexpr (PRE) {
             const int rr = s - D - 1;
             if (rr >= 0 && rr < n && lane) {
-                const RowW &r = w[D];
-                const RowW &rs = w[D + 1];
                 const double *row = u_ring + (rr & 7) * n;
                 const double *up = u_ring + ((rr + 1) & 7) * n, *dn = u_ring + ((rr - 1) & 7) * n;
-                const int cr = c0 + (rr & 1), cb = c1 - (rr & 1);
-                const double ur = row[cr], ubk = row[cb];
                 // net flux face by face, w (u_P - u_nbr) in the order E, W, N,
                 // S with explicit fma, a wall face as 2 a_P (u_P - 0): the
-                // rounding of the tile passes.  2 a_P is the wall term, halved
-                // (exactly) at a corner, whose two wall faces it sums.
-                auto flux = [&](double u, int c, double wE, double wW, double wN, double wS,
-                                double dw) {
-                    const int walls = (c == 0) + (c + 1 == n) + (rr == 0) + (rr + 1 == n);
-                    const double ww = walls == 2 ? 0.5 * dw : dw;
-                    double v = (c + 1 < n ? wE : ww) * (u - (c + 1 < n ? row[c + 1] : 0.0));
-                    v = fma(c > 0 ? wW : ww, u - (c > 0 ? row[c - 1] : 0.0), v);
-                    v = fma(rr + 1 < n ? wN : ww, u - (rr + 1 < n ? up[c] : 0.0), v);
-                    v = fma(rr > 0 ? wS : ww, u - (rr > 0 ? dn[c] : 0.0), v);
+                // rounding of the tile passes
+                auto flux = [&](auto Kc) __attribute__((always_inline)) {
+                    constexpr int K = decltype(Kc)::value;
+                    const Faces<K, F1> fw(w[D], w[D + 1]);
+                    const int c = K == 0 ? c0 : c1;
+                    const double u = row[c];
+                    double v = fw.e * (u - (c + 1 < n ? row[c + 1] : 0.0));
+                    v = fma(fw.w, u - (c > 0 ? row[c - 1] : 0.0), v);
+                    v = fma(fw.nn, u - (rr + 1 < n ? up[c] : 0.0), v);
+                    v = fma(fw.s, u - (rr > 0 ? dn[c] : 0.0), v);
                     return v;
                 };
-                const double fr = flux(ur, cr, r.wE_r, r.wW_r, r.wN_r, rs.wN_b, r.dw_r);
-                const double fbk = flux(ubk, cb, r.wE_b, r.wW_b, r.wN_b, rs.wN_r, r.dw_b);
-                const double resr = inv_h2 * ((F1 ? h2 : r.rhs_r) - fr);
-                const double resb = inv_h2 * ((F1 ? h2 : r.rhs_b) - fbk);
-                const bool odd = rr & 1;
-                const double u0 = odd ? ubk : ur, u1 = odd ? ur : ubk;
-                const double res0 = odd ? resb : resr, res1 = odd ? resr : resb;
+                const double res0 =
+                    inv_h2 * ((F1 ? h2 : w[D].rhs0) - flux(std::integral_constant<int, 0>{}));
+                const double res1 =
+                    inv_h2 * ((F1 ? h2 : w[D].rhs1) - flux(std::integral_constant<int, 1>{}));
                 const int64_t o = (int64_t)rr * n;
-                ob[o + c0] = u0;
-                ob[o + c1] = u1;
-                if (rr & 1) fcb[L + (int64_t)nc * (rr >> 1)] = 0.25 * (rkeep0 + rkeep1 + res0 + res1);
+                ob[o + c0] = row[c0];
+                ob[o + c1] = row[c1];
+                constexpr bool odd = ((P - D - 1) & 1) != 0;
+                if constexpr (odd) fcb[L + (int64_t)nc * (rr >> 1)] = 0.25 * (rkeep0 + rkeep1 + res0 + res1);
                 else { rkeep0 = res0; rkeep1 = res1; }
             }
         } else {
@@ -303,6 +311,10 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
                 ob[o + c1] = row[c1];
             }
         }
+    };
+    for (int s = 0; s <= s_end; s += 2) {
+        step(s, std::integral_constant<int, 0>{});
+        if (s + 1 <= s_end) step(s + 1, std::integral_constant<int, 1>{});
     }
 }
 

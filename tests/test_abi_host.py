@@ -211,14 +211,18 @@ def test_tuning_table_defaults_and_validation():
     assert [(e["n"], e["batch_class"]) for e in t] == [
         (n, c) for n in (32, 64, 128, 256) for c in range(m.MLMC_BATCH_CLASSES)]
     for e in t:
-        tiles = 4 ** e["batch_class"] * (e["n"] // 32) ** 2
+        c, n = e["batch_class"], e["n"]
+        tiles = 4 ** c * (n // 32) ** 2
         tile = m.MLMC_PASS_TILE16 if tiles <= 256 else m.MLMC_PASS_TILE32
-        stream = tiles >= 65536 and e["n"] >= 128
-        assert e["pre"] == tile and e["pre_ms"] == 0.0, e
-        assert e["post"] == (m.MLMC_PASS_STREAM if stream else tile), e
+        has_stream = 64 <= n <= 512
+        pre = m.MLMC_PASS_STREAM if has_stream and n >= 128 and tiles >= 262144 else tile
+        post = m.MLMC_PASS_STREAM if has_stream and (c >= 6 or (n >= 256 and c >= 5)) else tile
+        assert e["pre"] == pre and e["pre_ms"] == 0.0, e
+        assert e["post"] == post, e
     kinds = {(e["n"], e["batch_class"]): (e["pre"], e["post"]) for e in t}
     assert kinds[(256, 1)] == (m.MLMC_PASS_TILE16,) * 2            # 4 samples: 256 tiles
-    assert kinds[(256, 7)] == (m.MLMC_PASS_TILE32, m.MLMC_PASS_STREAM)   # 16384 samples
+    assert kinds[(256, 7)] == (m.MLMC_PASS_STREAM,) * 2            # 16384 samples
+    assert kinds[(32, 7)] == (m.MLMC_PASS_TILE32,) * 2
     with pytest.raises(m.MlmcError):
         ctx.autotune()                              # host-only: no device to measure on
     L = m.lib()
