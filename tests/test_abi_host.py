@@ -255,3 +255,12 @@ def test_tuning_table_defaults_and_validation():
     with pytest.raises(m.MlmcError):                 # rtol mode: 32^2 is LDS-resident
         mx.set_tuning([dict(n=32, batch_class=0, pre=T32, post=T32)])
     assert _host_ctx(n0=4, num_levels=3).tuning() == []          # all grids LDS-resident
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)

@@ -101,3 +101,23 @@ def test_autotune_installs_measured_kinds_and_keeps_results():
         assert np.array_equal(a, b)
     with pytest.raises(m.MlmcError):
         ctx.autotune(level=7)
+
+
+@pytest.mark.parametrize("precision", [m.MLMC_FP64, m.MLMC_MIXED])
+def test_autotune_refinement_contexts(precision):
+    """rtol contexts: 64^2 and up are tile grids (32^2 is LDS-resident); the
+    mixed context's FP32 V-cycles may only take tiles.  The tuned table keeps
+    every result bitwise."""
+    _dev()
+    w, ctx = _ctx("mlqmc_mixed_s400", precision, max_batch=32)
+    before = _solve(ctx, 5, 0, 3, 2, 4)
+    table = ctx.autotune(5)
+    assert [e["n"] for e in table[::m.MLMC_BATCH_CLASSES]][:3] == [64, 128, 256]
+    for e in table:
+        if precision == m.MLMC_MIXED:
+            assert e["pre"] in (T32, T16) and e["post"] in (T32, T16), e
+        if e["n"] <= 128 and e["batch_class"] == 0:      # tuned: levels <= 5 reach 128^2
+            assert e["pre_ms"] > 0 and e["post_ms"] > 0, e
+        if e["n"] > 128:
+            assert e["pre_ms"] == 0, e
+    assert np.array_equal(_solve(ctx, 5, 0, 3, 2, 4), before)
