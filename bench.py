@@ -43,8 +43,8 @@ KERNEL_NAMES = dict(
     sums="k_sums",
     pre="pre pass (2 red-black sweeps + residual + restriction): k_stream<2,pre> on 128^2 and "
         "256^2, k_pre_tile<32,256,2,double> on 32^2 and 64^2",
-    post="post pass (prolongation + correction + 2 sweeps): k_stream<2,post> on 64^2..256^2, "
-         "k_post_tile<32,256,2,double> on 32^2",
+    post="post pass (prolongation + correction + 2 sweeps): k_stream<2,post> on 32^2..256^2 "
+         "(2 and 4 samples per workgroup on 64^2 and 32^2)",
     lds="k_lds_fmg_fixed, k_lds_vcycle (LDS-resident grids <= 16^2)",
     refine="k_fcg_* (flexible-CG vector passes, grids >= 64^2)")
 

@@ -311,17 +311,18 @@ mlmc_status mlmc_profile_end(mlmc_ctx ctx, mlmc_profile_result *out);
  *   MLMC_PASS_TILE32  32 x 32 cells and a halo per 256-thread workgroup
  *   MLMC_PASS_TILE16  16 x 16 cells per 128-thread workgroup (four times the
  *                     workgroups: for batches too small to fill the chip)
- *   MLMC_PASS_STREAM  one workgroup per sample streaming rows through LDS
- *                     (FP64 V-cycles, 64 <= n <= 512 only)
+ *   MLMC_PASS_STREAM  rows streamed through LDS, one sample per workgroup
+ *                     (2 or 4 per workgroup on 64^2 and 32^2, so that they
+ *                     fill a wavefront); FP64 V-cycles, 32 <= n <= 512 only
  * All kinds give the bits of the same global sweep order, so the choice
  * changes only the time.  The choice is kept per context for each grid side
  * n and batch class c: chunks of Bc samples with 4^(c-1) < Bc <= 4^c (c = 0
  * for one sample), c < MLMC_BATCH_CLASSES (the last class takes every larger
  * chunk).  A new context starts from defaults measured on MI355X, a rule in
  * c and the number of 32 x 32 tiles of the pass, t = 4^c (n/32)^2: TILE16
- * for t <= 256, TILE32 otherwise; where STREAM exists (FP64, 64 <= n <= 512)
- * it takes the post pass for c >= 6 (c >= 5 when n >= 256) and the pre pass
- * for t >= 262144 when n >= 128.  A server's slots take the first slot's
+ * for t <= 256, TILE32 otherwise; where STREAM exists (FP64) it takes the
+ * post pass for t >= 65536 (t >= 16384 when n <= 64) and the pre pass for
+ * t >= 262144 when n >= 128.  A server's slots take the first slot's
  * table. */
 enum { MLMC_PASS_TILE32 = 0, MLMC_PASS_TILE16 = 1, MLMC_PASS_STREAM = 2 };
 enum { MLMC_BATCH_CLASSES = 10 };

@@ -425,9 +425,10 @@ bool kind_allowed(mlmc_ctx c, int g, int kind)
 // rule in the batch class c and the number of 32 x 32 tiles a pass covers,
 // t = 4^c (n/32)^2: up to 256 tiles (one per CU or fewer) 16 x 16 tiles,
 // which give four times the workgroups; 32 x 32 tiles otherwise; where the
-// FP64 row-streaming passes exist (64^2 .. 512^2), they take the post pass
-// from c = 6 on (more than 1024 samples; from c = 5 on grids of 256^2 and
-// more) and the pre pass from t = 262144 on grids of 128^2 and more.
+// FP64 row-streaming passes exist (32^2 .. 512^2), they take the post pass
+// from t = 65536 on (from t = 16384 on 32^2 and 64^2, where a workgroup
+// packs 4 or 2 samples) and the pre pass from t = 262144 on grids of 128^2
+// and more.
 void default_tuning(mlmc_ctx c)
 {
     for (int g = 0; g < kMaxMgLevels; ++g) {
@@ -438,7 +439,8 @@ void default_tuning(mlmc_ctx c)
             const int64_t tiles = ((int64_t)1 << (2 * cl)) * side * side;
             const int8_t tile = tiles <= 256 ? kTile16 : kTile32;
             c->pre_kind[g][cl] = stream && n >= 128 && tiles >= 262144 ? kStream : tile;
-            c->post_kind[g][cl] = stream && (cl >= 6 || (n >= 256 && cl >= 5)) ? kStream : tile;
+            c->post_kind[g][cl] =
+                stream && (tiles >= 65536 || (n <= 64 && tiles >= 16384)) ? kStream : tile;
         }
     }
 }

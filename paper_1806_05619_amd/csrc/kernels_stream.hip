@@ -1,9 +1,10 @@
 // Row-streaming multigrid passes for gfx950 (Section 4), FP64.
 //
-// One workgroup solves one sample's grid of n x n cells (64 <= n <= 512).
-// Lane L owns the two columns 2L and 2L+1, so every row gives each lane one
-// red and one black cell, and the workgroup spans the full width: no halo is
-// recomputed.  Rows stream bottom to top through a ring of 8 rows of u and 2
+// One workgroup solves the grids of SPB samples of n x n cells (32 <= n <=
+// 512; SPB = 64 / (n/2) samples on grids narrower than a wavefront, so that no
+// lane idles, else 1).  Lane L of a sample owns the two columns 2L and 2L+1,
+// so every row gives each lane one red and one black cell, and the lanes of a
+// sample span the full width: no halo is recomputed.  Rows stream bottom to top through a ring of 8 rows of u and 2
 // rows of a in LDS; the 2*mu red-black half-sweeps run as a pipeline one row
 // apart (half-sweep t works on row s - t while row s + 1 is being fetched),
 // which reproduces the global sweep order exactly:
@@ -134,7 +135,7 @@ struct Faces {
 // The result goes to u_out (may equal u_in: rows are read before written).
 // F1: f = 1 (the top level of a stage), so every rhs is h^2 and no row of
 // the register window carries one.
-template <int MU, bool PRE, bool F1>
+template <int MU, bool PRE, bool F1, int SPB>
 __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
                                                  const double *__restrict__ f,
                                                  const double *u_in, double *u_out,
@@ -145,16 +146,22 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
     constexpr int D = 2 * MU;                  // half-sweeps in the pass
     constexpr int NS = PRE ? D + 2 : D + 1;    // rows s-1 .. s-NS in the register window
     extern __shared__ double smem[];
-    double *u_ring = smem;                     // [8][n]
-    double *a_ring = smem + 8 * n;             // [2][n]
-
-    const int64_t b = blockIdx.x;
-    if (b >= Bc) return;
-    if (active && !active[b]) return;
-    const int L = threadIdx.x;
-    const bool lane = L < n / 2;
-    const int c0 = 2 * L, c1 = 2 * L + 1;
     const int nc = n / 2;
+    // sample `sub` of the block: lanes sub * n/2 .. (sub+1) * n/2 - 1; a
+    // sample past the batch or inactive keeps its lanes idle but passes every
+    // barrier with the others
+    const int sub = SPB == 1 ? 0 : threadIdx.x / nc;
+    const int L = threadIdx.x - sub * nc;
+    const int64_t bs = (int64_t)blockIdx.x * SPB + sub;
+    if constexpr (SPB == 1) {           // the whole workgroup is one sample
+        if (bs >= Bc) return;
+        if (active && !active[bs]) return;
+    }
+    const bool lane = SPB == 1 ? L < nc : (sub < SPB && bs < Bc && (!active || active[bs]));
+    const int64_t b = (SPB == 1 || lane) ? bs : 0;
+    double *u_ring = smem + (SPB == 1 || !lane ? 0 : sub) * 10 * n;   // [8][n]
+    double *a_ring = u_ring + 8 * n;                                  // [2][n]
+    const int c0 = 2 * L, c1 = 2 * L + 1;
     const int64_t cells = (int64_t)n * n;
     const double *ab = a + b * cells;
     const double *fb = f ? f + b * cells : nullptr;
@@ -166,7 +173,7 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
     const double inv_h2 = (double)n * (double)n;
     const bool need_coarse = PRE ? (init == 2) : true;
 
-    for (int q = threadIdx.x; q < 10 * n; q += blockDim.x) smem[q] = 0.0;
+    for (int q = threadIdx.x; q < SPB * 10 * n; q += blockDim.x) smem[q] = 0.0;
 
     // prefetch registers for the next row
     double pa0 = 0, pa1 = 0, pu0 = 0, pu1 = 0, pf0 = 1.0, pf1 = 1.0;
@@ -318,27 +325,39 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
     }
 }
 
-template <int MU, bool PRE, bool F1>
-void launch_one(hipStream_t st, const double *a, const double *f, const double *u_in,
+template <int MU, bool PRE, bool F1, int SPB>
+void launch_spb(hipStream_t st, const double *a, const double *f, const double *u_in,
                 double *u_out, const double *ec, int n, int64_t Bc, int init, double *fc,
                 const int32_t *active)
 {
     // once per instantiation; the static's initialisation is thread-safe
     static const bool attr_set = [] {
-        (void)hipFuncSetAttribute((const void *)k_stream<MU, PRE, F1>,
+        (void)hipFuncSetAttribute((const void *)k_stream<MU, PRE, F1, SPB>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         return true;
     }();
     (void)attr_set;
-    const size_t lds = sizeof(double) * 10 * (size_t)n;
-    const int threads = n / 2 < 64 ? 64 : n / 2;
-    hipLaunchKernelGGL((k_stream<MU, PRE, F1>), dim3((unsigned)Bc), dim3(threads), lds, st, a, f, u_in,
-                       u_out, ec, n, Bc, init, fc, active);
+    const size_t lds = sizeof(double) * 10 * (size_t)n * SPB;
+    const int threads = SPB * (n / 2) < 64 ? 64 : SPB * (n / 2);
+    const unsigned blocks = (unsigned)((Bc + SPB - 1) / SPB);
+    hipLaunchKernelGGL((k_stream<MU, PRE, F1, SPB>), dim3(blocks), dim3(threads), lds, st, a, f,
+                       u_in, u_out, ec, n, Bc, init, fc, active);
+}
+
+template <int MU, bool PRE, bool F1>
+void launch_one(hipStream_t st, const double *a, const double *f, const double *u_in,
+                double *u_out, const double *ec, int n, int64_t Bc, int init, double *fc,
+                const int32_t *active)
+{
+    // as many samples per workgroup as fill one wavefront
+    if (n >= 128) launch_spb<MU, PRE, F1, 1>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
+    else if (n == 64) launch_spb<MU, PRE, F1, 2>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
+    else launch_spb<MU, PRE, F1, 4>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
 }
 
 }  // namespace
 
-bool stream_supported(int n) { return n >= 64 && n <= 512; }
+bool stream_supported(int n) { return n >= 32 && n <= 512; }
 
 void launch_pre_stream(hipStream_t st, int mu1, const double *a, const double *f,
                        const double *u_in, double *u_out, const double *uc, int n, int64_t Bc,

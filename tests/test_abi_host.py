@@ -214,15 +214,17 @@ def test_tuning_table_defaults_and_validation():
         c, n = e["batch_class"], e["n"]
         tiles = 4 ** c * (n // 32) ** 2
         tile = m.MLMC_PASS_TILE16 if tiles <= 256 else m.MLMC_PASS_TILE32
-        has_stream = 64 <= n <= 512
+        has_stream = 32 <= n <= 512
         pre = m.MLMC_PASS_STREAM if has_stream and n >= 128 and tiles >= 262144 else tile
-        post = m.MLMC_PASS_STREAM if has_stream and (c >= 6 or (n >= 256 and c >= 5)) else tile
+        post = (m.MLMC_PASS_STREAM if has_stream and (tiles >= 65536 or (n <= 64 and tiles >= 16384))
+                else tile)
         assert e["pre"] == pre and e["pre_ms"] == 0.0, e
         assert e["post"] == post, e
     kinds = {(e["n"], e["batch_class"]): (e["pre"], e["post"]) for e in t}
     assert kinds[(256, 1)] == (m.MLMC_PASS_TILE16,) * 2            # 4 samples: 256 tiles
     assert kinds[(256, 7)] == (m.MLMC_PASS_STREAM,) * 2            # 16384 samples
-    assert kinds[(32, 7)] == (m.MLMC_PASS_TILE32,) * 2
+    assert kinds[(32, 7)] == (m.MLMC_PASS_TILE32, m.MLMC_PASS_STREAM)
+    assert kinds[(32, 6)] == (m.MLMC_PASS_TILE32,) * 2
     with pytest.raises(m.MlmcError):
         ctx.autotune()                              # host-only: no device to measure on
     L = m.lib()
@@ -235,7 +237,6 @@ def test_tuning_table_defaults_and_validation():
                 dict(n=512, batch_class=0, pre=T32, post=T32),     # beyond the finest level
                 dict(n=64, batch_class=10, pre=T32, post=T32),
                 dict(n=64, batch_class=-1, pre=T32, post=T32),
-                dict(n=32, batch_class=0, pre=ST, post=T32),       # no streaming pass at 32^2
                 dict(n=64, batch_class=0, pre=T32, post=3)]:
         with pytest.raises(m.MlmcError):
             ctx.set_tuning([dict(n=128, batch_class=2, pre=T16, post=T16), bad])
