@@ -427,7 +427,7 @@ bool kind_allowed(mlmc_ctx c, int g, int kind)
 // which give four times the workgroups; 32 x 32 tiles otherwise; where the
 // FP64 row-streaming passes exist (32^2 .. 512^2), they take the post pass
 // from t = 65536 on (from t = 16384 on 32^2 and 64^2, where a workgroup
-// packs 4 or 2 samples) and the pre pass from t = 262144 on grids of 128^2
+// packs 4 or 2 samples), and the pre pass by the same rule on grids of 64^2
 // and more.
 void default_tuning(mlmc_ctx c)
 {
@@ -438,9 +438,9 @@ void default_tuning(mlmc_ctx c)
         for (int cl = 0; cl < MLMC_BATCH_CLASSES; ++cl) {
             const int64_t tiles = ((int64_t)1 << (2 * cl)) * side * side;
             const int8_t tile = tiles <= 256 ? kTile16 : kTile32;
-            c->pre_kind[g][cl] = stream && n >= 128 && tiles >= 262144 ? kStream : tile;
-            c->post_kind[g][cl] =
-                stream && (tiles >= 65536 || (n <= 64 && tiles >= 16384)) ? kStream : tile;
+            const bool big = tiles >= 65536 || (n <= 64 && tiles >= 16384);
+            c->pre_kind[g][cl] = stream && n >= 64 && big ? kStream : tile;
+            c->post_kind[g][cl] = stream && big ? kStream : tile;
         }
     }
 }

@@ -4,16 +4,20 @@
 // 512; SPB = 64 / (n/2) samples on grids narrower than a wavefront, so that no
 // lane idles, else 1).  Lane L of a sample owns the two columns 2L and 2L+1,
 // so every row gives each lane one red and one black cell, and the lanes of a
-// sample span the full width: no halo is recomputed.  Rows stream bottom to top through a ring of 8 rows of u and 2
-// rows of a in LDS; the 2*mu red-black half-sweeps run as a pipeline one row
-// apart (half-sweep t works on row s - t while row s + 1 is being fetched),
-// which reproduces the global sweep order exactly:
+// sample span the full width: no halo is recomputed.  Rows stream bottom to
+// top through a ring of 8 rows of u and 2 rows of a in LDS; the 2*mu
+// red-black half-sweeps run as a pipeline one row apart (half-sweep t works
+// on row s - t while row s + 1 is being fetched), which reproduces the global
+// sweep order exactly:
 //   pre  pass: half-sweeps red, black, ... then the residual of row s-2mu-1
 //              and, for every odd row, the 4-cell restriction -> coarse f;
 //   post pass: rows arrive as u + P e_c (bilinear, odd reflection), half-sweeps
 //              black, red, ...; row s-2mu is final.
 // Face weights, diagonal and right-hand side of a row are computed once when
-// the row above has arrived and then travel down a register window.
+// the row above has arrived and then stay in a register window.  A row step
+// needs one workgroup barrier (lanes exchange only values of earlier steps),
+// and the row loop is unrolled by 8 so that window slots and ring rows are
+// compile-time indices.
 #include <type_traits>
 
 #include "internal.hpp"
@@ -32,15 +36,6 @@ __device__ __forceinline__ double frcp_s(double x)
 
 __device__ __forceinline__ double hmean(double ap, double an) { return 2.0 * ap * an * frcp_s(ap + an); }
 
-__device__ __forceinline__ double codd_s(const double *__restrict__ e, int nc, int I, int J)
-{
-    double sg = 1.0;
-    if (I < 0) { I = 0; sg = -sg; }
-    if (I >= nc) { I = nc - 1; sg = -sg; }
-    if (J < 0) { J = 0; sg = -sg; }
-    if (J >= nc) { J = nc - 1; sg = -sg; }
-    return sg * e[I + nc * J];
-}
 
 // compile-time loop: f(integral_constant<int, I>) for I = B .. E-1, so that
 // register-window slots are always addressed with constant indices
@@ -66,15 +61,6 @@ struct RowW {
     double rhs0, rhs1;                // h^2 f (unused when f = 1)
 };
 
-// field-wise copy (a struct copy becomes a memcpy that keeps the window in
-// scratch memory)
-template <bool F1>
-__device__ __forceinline__ void copy_row(RowW<F1> &d, const RowW<F1> &s)
-{
-    d.wW0 = s.wW0; d.wC = s.wC; d.wE1 = s.wE1; d.wN0 = s.wN0; d.wN1 = s.wN1;
-    if constexpr (!F1) { d.rhs0 = s.rhs0; d.rhs1 = s.rhs1; }
-}
-
 template <bool F1>
 __device__ __forceinline__ void zero_row(RowW<F1> &d)
 {
@@ -83,21 +69,37 @@ __device__ __forceinline__ void zero_row(RowW<F1> &d)
 }
 
 // coarse values of row R's prolongation for lane L: columns L-1, L, L+1 of
-// coarse rows J = R/2 and J + sy
+// coarse rows J = R/2 and J + sy.  Outside the coarse grid the correction is
+// continued oddly (reflected, sign flipped).  The loads take the clamped
+// indices only and the signs are applied when the row is used, so that the
+// loads of the next row stay in flight through a whole row step.
 struct Coarse6 {
     double m0, c0, p0, m1, c1, p1;
 };
 
-__device__ __forceinline__ void load_coarse(Coarse6 &k, const double *__restrict__ e, int nc, int L,
-                                            int R)
+__device__ __forceinline__ void load_coarse_raw(Coarse6 &k, const double *__restrict__ e, int nc,
+                                                int L, int R)
 {
-    const int J = R >> 1, J2 = J + ((R & 1) ? 1 : -1);
-    k.m0 = codd_s(e, nc, L - 1, J);
-    k.c0 = codd_s(e, nc, L, J);
-    k.p0 = codd_s(e, nc, L + 1, J);
-    k.m1 = codd_s(e, nc, L - 1, J2);
-    k.c1 = codd_s(e, nc, L, J2);
-    k.p1 = codd_s(e, nc, L + 1, J2);
+    const int J = R >> 1;
+    int J2 = J + ((R & 1) ? 1 : -1);
+    J2 = J2 < 0 ? 0 : (J2 >= nc ? nc - 1 : J2);
+    const int Im = L > 0 ? L - 1 : 0, Ip = L + 1 < nc ? L + 1 : nc - 1;
+    const double *r0 = e + (int64_t)nc * J, *r1 = e + (int64_t)nc * J2;
+    k.m0 = r0[Im];
+    k.c0 = r0[L];
+    k.p0 = r0[Ip];
+    k.m1 = r1[Im];
+    k.c1 = r1[L];
+    k.p1 = r1[Ip];
+}
+
+// the reflection signs of load_coarse_raw's values (products of exact -1
+// factors: the bits of the reflected values themselves)
+__device__ __forceinline__ void sign_coarse(Coarse6 &k, int nc, int L, int R, int n)
+{
+    if (L == 0) { k.m0 = -k.m0; k.m1 = -k.m1; }
+    if (L == nc - 1) { k.p0 = -k.p0; k.p1 = -k.p1; }
+    if (R == 0 || R == n - 1) { k.m1 = -k.m1; k.c1 = -k.c1; k.p1 = -k.p1; }
 }
 
 // (9 e_IJ + 3 e_{I+sx,J} + 3 e_{I,J+sy} + e_{I+sx,J+sy}) / 16 for columns 2L (sx=-1), 2L+1 (sx=+1)
@@ -135,8 +137,10 @@ struct Faces {
 // The result goes to u_out (may equal u_in: rows are read before written).
 // F1: f = 1 (the top level of a stage), so every rhs is h^2 and no row of
 // the register window carries one.
+// Register budget: 128 (4 waves per SIMD) with f = 1, whose window carries
+// no right-hand side, else 168 (3 waves); both measured against the other.
 template <int MU, bool PRE, bool F1, int SPB>
-__global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3))) void k_stream(const double *__restrict__ a,
                                                  const double *__restrict__ f,
                                                  const double *u_in, double *u_out,
                                                  const double *__restrict__ ec, int n, int64_t Bc,
@@ -145,6 +149,8 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
 {
     constexpr int D = 2 * MU;                  // half-sweeps in the pass
     constexpr int NS = PRE ? D + 2 : D + 1;    // rows s-1 .. s-NS in the register window
+    // rows fetched ahead (two, in the post pass with f = 1, measured slower)
+    constexpr int PD = 1;
     extern __shared__ double smem[];
     const int nc = n / 2;
     // sample `sub` of the block: lanes sub * n/2 .. (sub+1) * n/2 - 1; a
@@ -175,69 +181,106 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
 
     for (int q = threadIdx.x; q < SPB * 10 * n; q += blockDim.x) smem[q] = 0.0;
 
-    // prefetch registers for the next row
-    double pa0 = 0, pa1 = 0, pu0 = 0, pu1 = 0, pf0 = 1.0, pf1 = 1.0;
-    Coarse6 pk{};
-    auto fetch = [&](int R) __attribute__((always_inline)) {
-        if (!lane || R >= n) return;
-        const int64_t o = (int64_t)R * n;
-        pa0 = ab[o + c0];
-        pa1 = ab[o + c1];
-        if (!F1) {
-            pf0 = fb[o + c0];
-            pf1 = fb[o + c1];
+    // prefetch registers: row R is fetched PD row steps before it enters,
+    // into set R % PD
+    struct Prefetch {
+        double a0 = 0, a1 = 0, u0 = 0, u1 = 0, f0 = 1.0, f1 = 1.0;
+        Coarse6 k{};
+    };
+    Prefetch pre[PD];
+    // In the post pass unconditional, so that no register keeps an older
+    // value beside the new one: past the last row the last row is fetched
+    // again, and an idle lane (b = 0) fetches sample 0; neither is used.
+    // (Measured the other way round in the pre pass, whose register budget
+    // it overflows.)
+    auto fetch = [&](int R, Prefetch &pp) __attribute__((always_inline)) {
+        if constexpr (PRE) {
+            if (!lane || R >= n) return;
+        } else {
+            R = R < n ? R : n - 1;
         }
-        if (need_coarse) load_coarse(pk, eb, nc, L, R);
+        const int64_t o = (int64_t)R * n;
+        pp.a0 = ab[o + c0];
+        pp.a1 = ab[o + c1];
+        if (!F1) {
+            pp.f0 = fb[o + c0];
+            pp.f1 = fb[o + c1];
+        }
+        if (need_coarse) load_coarse_raw(pp.k, eb, nc, L, R);
         if (!PRE || init == 0) {
-            pu0 = ub[o + c0];
-            pu1 = ub[o + c1];
+            pp.u0 = ub[o + c0];
+            pp.u1 = ub[o + c1];
         }
     };
-    fetch(0);
-    __syncthreads();
+    static_for<0, PD>([&](auto K) __attribute__((always_inline)) { fetch(K.value, pre[K.value]); });
 
-    RowW<F1> w[NS];
-    static_for<0, NS>([&](auto K) __attribute__((always_inline)) { zero_row(w[K.value]); });
+    // The register window and the u ring are indexed by row mod 8, and the
+    // row loop is unrolled by 8, so that every slot is a compile-time index:
+    // the window needs no moves and the ring rows sit at fixed offsets.  At
+    // most NS <= 8 window slots are live.
+    static_assert(NS <= 8 && D + 2 <= 8, "window and ring hold 8 rows");
+    RowW<F1> w[8];
+    static_for<0, 8>([&](auto K) __attribute__((always_inline)) { zero_row(w[K.value]); });
     double rhs_cur0 = 0, rhs_cur1 = 0, rkeep0 = 0, rkeep1 = 0;
     const int s_end = PRE ? n + D : n + D - 1;
 
-    // One pipeline step for row s entering; P = s & 1, so that every row
-    // parity below is known at compile time.
-    auto step = [&](int s, auto Pc) __attribute__((always_inline)) {
-        constexpr int P = decltype(Pc)::value;
+    // One pipeline step for row s entering; J = s & 8 - 1 and P = s & 1 are
+    // compile-time constants.
+    auto step = [&](int s_in, auto Jc) __attribute__((always_inline)) {
+        constexpr int J = decltype(Jc)::value;
+        constexpr int P = J & 1;
+        // the row index as an opaque scalar: without this the unrolled steps'
+        // row addresses become separate pointer induction variables, more
+        // than the registers hold (an empty asm: no instruction is emitted)
+        int s = s_in;
+        asm volatile("" : "+s"(s));
+        // The one barrier of a row step.  A lane shares nothing with another
+        // lane inside a step: every value it reads from another lane's columns
+        // (the E/W neighbours of a half-sweep or of the residual, the a of
+        // row s-1 beside its own) was written in an earlier step, and every
+        // ring slot it writes was last read by another lane in an earlier
+        // step (the u slot of row s-8, the a slot of row s-2, cells of the
+        // colour that the previous step's next half-sweep read as E/W
+        // neighbours).  What a lane reads of its own columns it wrote itself.
+        __syncthreads();
         // (A) row s enters the rings; fetch row s + 1
         const double rhs_prev0 = rhs_cur0, rhs_prev1 = rhs_cur1;
+        Prefetch &pp = pre[P % PD];
         if (s < n && lane) {
-            double u0 = pu0, u1 = pu1;
+            double u0 = pp.u0, u1 = pp.u1;
             if (need_coarse) {
+                Coarse6 k = pp.k;
+                sign_coarse(k, nc, L, s, n);
                 double v0, v1;
-                prolong2(pk, v0, v1);
+                prolong2(k, v0, v1);
                 if (PRE) { u0 = v0; u1 = v1; }
                 else { u0 += v0; u1 += v1; }
             } else if (PRE && init == 1) {
                 u0 = u1 = 0.0;
             }
-            u_ring[(s & 7) * n + c0] = u0;
-            u_ring[(s & 7) * n + c1] = u1;
-            a_ring[(s & 1) * n + c0] = pa0;
-            a_ring[(s & 1) * n + c1] = pa1;
-            if (!F1) {
-                rhs_cur0 = h2 * pf0;
-                rhs_cur1 = h2 * pf1;
-            }
-            fetch(s + 1);
+            u_ring[J * n + c0] = u0;
+            u_ring[J * n + c1] = u1;
+            a_ring[P * n + c0] = pp.a0;
+            a_ring[P * n + c1] = pp.a1;
         }
-        __syncthreads();
+        if (!F1) {
+            rhs_cur0 = h2 * pp.f0;
+            rhs_cur1 = h2 * pp.f1;
+        }
+        if (!PRE || (s < n && lane)) fetch(s + PD, pp);
 
-        // (B) faces of row q = s - 1 (its upper neighbour row s is now present)
-        static_for<0, NS - 1>([&](auto K) __attribute__((always_inline)) {
-            copy_row(w[NS - 1 - K.value], w[NS - 2 - K.value]);
-        });
+        // window slot of row s - k
+        auto slot = [](int k) constexpr { return (J - k) & 7; };
+        // (B) faces of row q = s - 1 (its upper neighbour row s is now
+        // present).  Formed whether or not q is a row of the grid, so that a
+        // slot's previous row is dead once the step begins: a slot filled
+        // outside the grid is never read, and every LDS read stays inside
+        // the workgroup's rings.
         const int q = s - 1;
-        if (q >= 0 && q < n && lane) {
-            const double *aq = a_ring + (q & 1) * n, *aq1 = a_ring + ((q + 1) & 1) * n;
+        {
+            const double *aq = a_ring + (1 - P) * n, *aq1 = a_ring + P * n;
             const double ap0 = aq[c0], ap1 = aq[c1];
-            RowW<F1> &r = w[0];
+            RowW<F1> &r = w[slot(1)];
             r.wC = hmean(ap0, ap1);
             r.wW0 = c0 > 0 ? hmean(ap0, aq[c0 - 1]) : 2.0 * ap0;
             r.wE1 = c1 + 1 < n ? hmean(ap1, aq[c1 + 1]) : 2.0 * ap1;
@@ -248,12 +291,12 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
                 r.rhs1 = rhs_prev1;
             }
             if (q == 0) {          // south wall of row 0, in the slot of row -1
-                w[1].wN0 = 2.0 * ap0;
-                w[1].wN1 = 2.0 * ap1;
+                w[slot(2)].wN0 = 2.0 * ap0;
+                w[slot(2)].wN1 = 2.0 * ap1;
             }
         }
 
-        // (C) half-sweep t on row s - t (register slot t - 1)
+        // (C) half-sweep t on row s - t
         static_for<1, D + 1>([&](auto T) __attribute__((always_inline)) {
             constexpr int t = T.value;
             const int rr = s - t;
@@ -261,35 +304,34 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
                 constexpr bool red = PRE ? (t & 1) : !(t & 1);
                 // the red cell of row rr is column c0 when rr is even
                 constexpr int K = red ? ((P - t) & 1) : 1 - ((P - t) & 1);
-                const Faces<K, F1> fw(w[t - 1], w[t]);
-                double *row = u_ring + (rr & 7) * n;
-                const double *up = u_ring + ((rr + 1) & 7) * n;
-                const double *dn = u_ring + ((rr - 1) & 7) * n;
+                const Faces<K, F1> fw(w[slot(t)], w[slot(t + 1)]);
+                double *row = u_ring + slot(t) * n;
+                const double *up = u_ring + slot(t - 1) * n;
+                const double *dn = u_ring + slot(t + 1) * n;
                 const int c = K == 0 ? c0 : c1;
                 // explicit fma in the face order E, W, N, S of the tile passes
                 // (a wall face meets a neighbour of value 0 there: skipped)
-                double num = F1 ? h2 : (K == 0 ? w[t - 1].rhs0 : w[t - 1].rhs1);
+                double num = F1 ? h2 : (K == 0 ? w[slot(t)].rhs0 : w[slot(t)].rhs1);
                 if (c + 1 < n) num = fma(fw.e, row[c + 1], num);
                 if (c > 0) num = fma(fw.w, row[c - 1], num);
                 if (rr + 1 < n) num = fma(fw.nn, up[c], num);
                 if (rr > 0) num = fma(fw.s, dn[c], num);
                 row[c] = num * frcp_s(fw.diag());
             }
-            __syncthreads();
         });
 
         // (D) leave the pipeline
         if constexpr (PRE) {
             const int rr = s - D - 1;
             if (rr >= 0 && rr < n && lane) {
-                const double *row = u_ring + (rr & 7) * n;
-                const double *up = u_ring + ((rr + 1) & 7) * n, *dn = u_ring + ((rr - 1) & 7) * n;
+                const double *row = u_ring + slot(D + 1) * n;
+                const double *up = u_ring + slot(D) * n, *dn = u_ring + slot(D + 2) * n;
                 // net flux face by face, w (u_P - u_nbr) in the order E, W, N,
                 // S with explicit fma, a wall face as 2 a_P (u_P - 0): the
                 // rounding of the tile passes
                 auto flux = [&](auto Kc) __attribute__((always_inline)) {
                     constexpr int K = decltype(Kc)::value;
-                    const Faces<K, F1> fw(w[D], w[D + 1]);
+                    const Faces<K, F1> fw(w[slot(D + 1)], w[slot(D + 2)]);
                     const int c = K == 0 ? c0 : c1;
                     const double u = row[c];
                     double v = fw.e * (u - (c + 1 < n ? row[c + 1] : 0.0));
@@ -299,9 +341,9 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
                     return v;
                 };
                 const double res0 =
-                    inv_h2 * ((F1 ? h2 : w[D].rhs0) - flux(std::integral_constant<int, 0>{}));
+                    inv_h2 * ((F1 ? h2 : w[slot(D + 1)].rhs0) - flux(std::integral_constant<int, 0>{}));
                 const double res1 =
-                    inv_h2 * ((F1 ? h2 : w[D].rhs1) - flux(std::integral_constant<int, 1>{}));
+                    inv_h2 * ((F1 ? h2 : w[slot(D + 1)].rhs1) - flux(std::integral_constant<int, 1>{}));
                 const int64_t o = (int64_t)rr * n;
                 ob[o + c0] = row[c0];
                 ob[o + c1] = row[c1];
@@ -312,17 +354,17 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ a,
         } else {
             const int rr = s - D;
             if (rr >= 0 && rr < n && lane) {
-                const double *row = u_ring + (rr & 7) * n;
+                const double *row = u_ring + slot(D) * n;
                 const int64_t o = (int64_t)rr * n;
                 ob[o + c0] = row[c0];
                 ob[o + c1] = row[c1];
             }
         }
     };
-    for (int s = 0; s <= s_end; s += 2) {
-        step(s, std::integral_constant<int, 0>{});
-        if (s + 1 <= s_end) step(s + 1, std::integral_constant<int, 1>{});
-    }
+    // steps past s_end (at most 7) find no row in range and only pass the
+    // barrier, which every lane of the workgroup reaches alike
+    for (int s0 = 0; s0 <= s_end; s0 += 8)
+        static_for<0, 8>([&](auto Jc) __attribute__((always_inline)) { step(s0 + Jc.value, Jc); });
 }
 
 template <int MU, bool PRE, bool F1, int SPB>
