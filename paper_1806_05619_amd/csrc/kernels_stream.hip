@@ -133,18 +133,20 @@ struct Faces {
     }
 };
 
-// PRE: init 0 = read u_in, 1 = zero, 2 = u = P uc.  POST: u = u_in + P ec.
+// PRE: INIT 0 = read u_in, 1 = zero, 2 = u = P uc (a template parameter, so
+// that a launch holds registers only for the loads it makes).  POST (INIT 0):
+// u = u_in + P ec.
 // The result goes to u_out (may equal u_in: rows are read before written).
 // F1: f = 1 (the top level of a stage), so every rhs is h^2 and no row of
 // the register window carries one.
 // Register budget: 128 (4 waves per SIMD) with f = 1, whose window carries
 // no right-hand side, else 168 (3 waves); both measured against the other.
-template <int MU, bool PRE, bool F1, int SPB>
+template <int MU, bool PRE, bool F1, int SPB, int INIT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3))) void k_stream(const double *__restrict__ a,
                                                  const double *__restrict__ f,
                                                  const double *u_in, double *u_out,
                                                  const double *__restrict__ ec, int n, int64_t Bc,
-                                                 int init, double *__restrict__ fc,
+                                                 double *__restrict__ fc,
                                                  const int32_t *__restrict__ active)
 {
     constexpr int D = 2 * MU;                  // half-sweeps in the pass
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3)
     double *fcb = PRE ? fc + b * (int64_t)nc * nc : nullptr;
     const double h2 = 1.0 / ((double)n * (double)n);
     const double inv_h2 = (double)n * (double)n;
-    const bool need_coarse = PRE ? (init == 2) : true;
+    constexpr bool need_coarse = PRE ? INIT == 2 : true;
 
     for (int q = threadIdx.x; q < SPB * 10 * n; q += blockDim.x) smem[q] = 0.0;
 
@@ -206,8 +208,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3)
             pp.f0 = fb[o + c0];
             pp.f1 = fb[o + c1];
         }
-        if (need_coarse) load_coarse_raw(pp.k, eb, nc, L, R);
-        if (!PRE || init == 0) {
+        if constexpr (need_coarse) load_coarse_raw(pp.k, eb, nc, L, R);
+        if constexpr (!PRE || INIT == 0) {
             pp.u0 = ub[o + c0];
             pp.u1 = ub[o + c1];
         }
@@ -248,14 +250,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3)
         Prefetch &pp = pre[P % PD];
         if (s < n && lane) {
             double u0 = pp.u0, u1 = pp.u1;
-            if (need_coarse) {
+            if constexpr (need_coarse) {
                 Coarse6 k = pp.k;
                 sign_coarse(k, nc, L, s, n);
                 double v0, v1;
                 prolong2(k, v0, v1);
                 if (PRE) { u0 = v0; u1 = v1; }
                 else { u0 += v0; u1 += v1; }
-            } else if (PRE && init == 1) {
+            } else if (PRE && INIT == 1) {
                 u0 = u1 = 0.0;
             }
             u_ring[J * n + c0] = u0;
@@ -367,14 +369,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3)
         static_for<0, 8>([&](auto Jc) __attribute__((always_inline)) { step(s0 + Jc.value, Jc); });
 }
 
-template <int MU, bool PRE, bool F1, int SPB>
+template <int MU, bool PRE, bool F1, int SPB, int INIT>
 void launch_spb(hipStream_t st, const double *a, const double *f, const double *u_in,
-                double *u_out, const double *ec, int n, int64_t Bc, int init, double *fc,
+                double *u_out, const double *ec, int n, int64_t Bc, double *fc,
                 const int32_t *active)
 {
     // once per instantiation; the static's initialisation is thread-safe
     static const bool attr_set = [] {
-        (void)hipFuncSetAttribute((const void *)k_stream<MU, PRE, F1, SPB>,
+        (void)hipFuncSetAttribute((const void *)k_stream<MU, PRE, F1, SPB, INIT>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         return true;
     }();
@@ -382,8 +384,26 @@ void launch_spb(hipStream_t st, const double *a, const double *f, const double *
     const size_t lds = sizeof(double) * 10 * (size_t)n * SPB;
     const int threads = SPB * (n / 2) < 64 ? 64 : SPB * (n / 2);
     const unsigned blocks = (unsigned)((Bc + SPB - 1) / SPB);
-    hipLaunchKernelGGL((k_stream<MU, PRE, F1, SPB>), dim3(blocks), dim3(threads), lds, st, a, f,
-                       u_in, u_out, ec, n, Bc, init, fc, active);
+    hipLaunchKernelGGL((k_stream<MU, PRE, F1, SPB, INIT>), dim3(blocks), dim3(threads), lds, st, a,
+                       f, u_in, u_out, ec, n, Bc, fc, active);
+}
+
+template <int MU, bool PRE, bool F1, int SPB>
+void launch_init(hipStream_t st, const double *a, const double *f, const double *u_in,
+                 double *u_out, const double *ec, int n, int64_t Bc, int init, double *fc,
+                 const int32_t *active)
+{
+    if constexpr (PRE) {
+        if (init == 1) {
+            launch_spb<MU, PRE, F1, SPB, 1>(st, a, f, u_in, u_out, ec, n, Bc, fc, active);
+            return;
+        }
+        if (init == 2) {
+            launch_spb<MU, PRE, F1, SPB, 2>(st, a, f, u_in, u_out, ec, n, Bc, fc, active);
+            return;
+        }
+    }
+    launch_spb<MU, PRE, F1, SPB, 0>(st, a, f, u_in, u_out, ec, n, Bc, fc, active);
 }
 
 template <int MU, bool PRE, bool F1>
@@ -392,9 +412,9 @@ void launch_one(hipStream_t st, const double *a, const double *f, const double *
                 const int32_t *active)
 {
     // as many samples per workgroup as fill one wavefront
-    if (n >= 128) launch_spb<MU, PRE, F1, 1>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
-    else if (n == 64) launch_spb<MU, PRE, F1, 2>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
-    else launch_spb<MU, PRE, F1, 4>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
+    if (n >= 128) launch_init<MU, PRE, F1, 1>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
+    else if (n == 64) launch_init<MU, PRE, F1, 2>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
+    else launch_init<MU, PRE, F1, 4>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
 }
 
 }  // namespace
