@@ -224,6 +224,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3)
     RowW<F1> w[8];
     static_for<0, 8>([&](auto K) __attribute__((always_inline)) { zero_row(w[K.value]); });
     double rhs_cur0 = 0, rhs_cur1 = 0, rkeep0 = 0, rkeep1 = 0;
+    // With mu = 2, half-sweeps t and t + 2 update the same cell of a row, two
+    // steps apart: the reciprocal of its diagonal is formed at the first and
+    // kept for the second (the same bits), by row mod 4, for the colour of
+    // half-sweeps 1 and 3 (rdA) and of 2 and 4 (rdB).
+    double rdA[4] = {}, rdB[4] = {};
     const int s_end = PRE ? n + D : n + D - 1;
 
     // One pipeline step for row s entering; J = s & 8 - 1 and P = s & 1 are
@@ -302,11 +307,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3)
         static_for<1, D + 1>([&](auto T) __attribute__((always_inline)) {
             constexpr int t = T.value;
             const int rr = s - t;
+            constexpr bool red = PRE ? (t & 1) : !(t & 1);
+            // the red cell of row rr is column c0 when rr is even
+            constexpr int K = red ? ((P - t) & 1) : 1 - ((P - t) & 1);
+            const Faces<K, F1> fw(w[slot(t)], w[slot(t + 1)]);
+            // formed whether or not rr is a row of the grid, so that no cache
+            // slot keeps an older value beside the new one
+            double rdiag;
+            if constexpr (MU == 2) {
+                double &rd = (t & 1) ? rdA[(J - t) & 3] : rdB[(J - t) & 3];
+                if constexpr (t <= 2) rd = frcp_s(fw.diag());
+                rdiag = rd;
+            } else {
+                rdiag = frcp_s(fw.diag());
+            }
             if (rr >= 0 && rr < n && lane) {
-                constexpr bool red = PRE ? (t & 1) : !(t & 1);
-                // the red cell of row rr is column c0 when rr is even
-                constexpr int K = red ? ((P - t) & 1) : 1 - ((P - t) & 1);
-                const Faces<K, F1> fw(w[slot(t)], w[slot(t + 1)]);
                 double *row = u_ring + slot(t) * n;
                 const double *up = u_ring + slot(t - 1) * n;
                 const double *dn = u_ring + slot(t + 1) * n;
@@ -318,7 +333,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3)
                 if (c > 0) num = fma(fw.w, row[c - 1], num);
                 if (rr + 1 < n) num = fma(fw.nn, up[c], num);
                 if (rr > 0) num = fma(fw.s, dn[c], num);
-                row[c] = num * frcp_s(fw.diag());
+                row[c] = num * rdiag;
             }
         });
 
