@@ -61,8 +61,8 @@ __global__ __launch_bounds__(FNT) void k_field_mfma64(const double *__restrict__
         for (int q = 0; q < 4; ++q) Bs[bk][bc + q] = bv[q];
         __syncthreads();
         if (k0 + FKB < s) fetch(k0 + FKB);
-#pragma unroll
-        for (int ks = 0; ks < FKB / 4; ++ks) {
+        // one group of 4 modes on the matrix cores
+        auto mma = [&](int ks) __attribute__((always_inline)) {
             const int kr = 4 * ks + (lane >> 4);
             double a[2], b[4];
 #pragma unroll
@@ -75,7 +75,14 @@ __global__ __launch_bounds__(FNT) void k_field_mfma64(const double *__restrict__
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] =
                         __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
+        };
+        // in the last, partial stage only the groups that hold a mode below
+        // s (the rest is zero padding; a uniform branch)
+        const int ksn = s - k0 >= FKB ? FKB / 4 : (s - k0 + 3) / 4;
+        mma(0);
+#pragma unroll
+        for (int ks = 1; ks < FKB / 4; ++ks)
+            if (ks < ksn) mma(ks);
         __syncthreads();
     }
 #pragma unroll
