@@ -41,8 +41,8 @@ KERNEL_NAMES = dict(
     points="k_points", field="k_field_mfma64", smooth="k_rbgs (one colour)",
     restrict="k_resid_restrict", prolong="k_prolong", coarse="k_coarse_solve", qoi="k_qoi",
     sums="k_sums",
-    pre="pre pass (2 red-black sweeps + residual + restriction): k_stream<2,pre> on 64^2.."
-        "256^2, k_pre_tile<32,256,2,double> on 32^2",
+    pre="pre pass (2 red-black sweeps + residual + restriction): k_stream<2,pre> on 32^2.."
+        "256^2 (2 and 4 samples per workgroup on 64^2 and 32^2)",
     post="post pass (prolongation + correction + 2 sweeps): k_stream<2,post> on 32^2..256^2 "
          "(2 and 4 samples per workgroup on 64^2 and 32^2)",
     lds="k_lds_fmg_fixed, k_lds_vcycle (LDS-resident grids <= 16^2)",

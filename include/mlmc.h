@@ -321,8 +321,8 @@ mlmc_status mlmc_profile_end(mlmc_ctx ctx, mlmc_profile_result *out);
  * chunk).  A new context starts from defaults measured on MI355X, a rule in
  * c and the number of 32 x 32 tiles of the pass, t = 4^c (n/32)^2: TILE16
  * for t <= 256, TILE32 otherwise; where STREAM exists (FP64) it takes the
- * post pass for t >= 65536 (t >= 16384 when n <= 64) and the pre pass by
- * the same rule when n >= 64.  A server's slots take the first slot's
+ * pre and the post pass for t >= 65536 (t >= 16384 when n <= 64).  A
+ * server's slots take the first slot's
  * table. */
 enum { MLMC_PASS_TILE32 = 0, MLMC_PASS_TILE16 = 1, MLMC_PASS_STREAM = 2 };
 enum { MLMC_BATCH_CLASSES = 10 };

@@ -426,9 +426,8 @@ bool kind_allowed(mlmc_ctx c, int g, int kind)
 // t = 4^c (n/32)^2: up to 256 tiles (one per CU or fewer) 16 x 16 tiles,
 // which give four times the workgroups; 32 x 32 tiles otherwise; where the
 // FP64 row-streaming passes exist (32^2 .. 512^2), they take the post pass
-// from t = 65536 on (from t = 16384 on 32^2 and 64^2, where a workgroup
-// packs 4 or 2 samples), and the pre pass by the same rule on grids of 64^2
-// and more.
+// for both passes from t = 65536 on (from t = 16384 on 32^2 and 64^2, where
+// a workgroup packs 4 or 2 samples).
 void default_tuning(mlmc_ctx c)
 {
     for (int g = 0; g < kMaxMgLevels; ++g) {
@@ -439,7 +438,7 @@ void default_tuning(mlmc_ctx c)
             const int64_t tiles = ((int64_t)1 << (2 * cl)) * side * side;
             const int8_t tile = tiles <= 256 ? kTile16 : kTile32;
             const bool big = tiles >= 65536 || (n <= 64 && tiles >= 16384);
-            c->pre_kind[g][cl] = stream && n >= 64 && big ? kStream : tile;
+            c->pre_kind[g][cl] = stream && big ? kStream : tile;
             c->post_kind[g][cl] = stream && big ? kStream : tile;
         }
     }

@@ -216,14 +216,14 @@ def test_tuning_table_defaults_and_validation():
         tile = m.MLMC_PASS_TILE16 if tiles <= 256 else m.MLMC_PASS_TILE32
         has_stream = 32 <= n <= 512
         big = tiles >= 65536 or (n <= 64 and tiles >= 16384)
-        pre = m.MLMC_PASS_STREAM if has_stream and n >= 64 and big else tile
+        pre = m.MLMC_PASS_STREAM if has_stream and big else tile
         post = m.MLMC_PASS_STREAM if has_stream and big else tile
         assert e["pre"] == pre and e["pre_ms"] == 0.0, e
         assert e["post"] == post, e
     kinds = {(e["n"], e["batch_class"]): (e["pre"], e["post"]) for e in t}
     assert kinds[(256, 1)] == (m.MLMC_PASS_TILE16,) * 2            # 4 samples: 256 tiles
     assert kinds[(256, 7)] == (m.MLMC_PASS_STREAM,) * 2            # 16384 samples
-    assert kinds[(32, 7)] == (m.MLMC_PASS_TILE32, m.MLMC_PASS_STREAM)
+    assert kinds[(32, 7)] == (m.MLMC_PASS_STREAM,) * 2             # 16384 samples of 32^2
     assert kinds[(32, 6)] == (m.MLMC_PASS_TILE32,) * 2
     assert kinds[(64, 6)] == (m.MLMC_PASS_STREAM,) * 2             # 4096 samples of 64^2
     with pytest.raises(m.MlmcError):
