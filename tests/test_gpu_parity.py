@@ -136,6 +136,32 @@ def test_fmg_fixed_cycles_match_oracle_fmg(oracle_mod, name, ks, B):
             assert _rel(qg[b], qo) <= 1e-12, (k, b, qg[b], qo)
 
 
+@pytest.mark.parametrize("mu1,mu2", [(1, 1), (1, 2), (2, 1)])
+def test_fmg_one_sweep_cycles_every_pass_kind(oracle_mod, mu1, mu2):
+    """V(1,1), V(1,2) and V(2,1) cycles (Section 4: mu1 pre- and mu2
+    post-smoothing sweeps): with the large grids 32^2 .. 128^2 forced to each
+    pass kind (32x32 tiles, 16x16 tiles, row streaming, and tiles before
+    streaming), the QoIs match the oracle's FMG on the same field and are
+    bitwise the same for every kind."""
+    dev = _dev()
+    w, ctx = _ctx("mlqmc_fp64_s100", mu1=mu1, mu2=mu2)
+    P = _oracle_problem(oracle_mod, w)
+    k, B = 5, 4                                     # finest MG grid 128^2
+    ys = np.random.default_rng(7 + 10 * mu1 + mu2).standard_normal((B, w["s"]))
+    zs = np.stack([P.field(y, k) for y in ys])
+    qo = np.stack([P.sample_from_field(k, zs[b], 0)["qoi"][:, : ctx.nq] for b in range(B)])
+    T32, T16, ST = m.MLMC_PASS_TILE32, m.MLMC_PASS_TILE16, m.MLMC_PASS_STREAM
+    first = None
+    for pre, post in [(T32, T32), (T16, T16), (ST, ST), (T32, ST), (ST, T16)]:
+        ctx.set_tuning(dict(e, pre=pre, post=post) for e in ctx.tuning())
+        pts = ctx.explicit(k, torch.tensor(ys, device=dev))
+        qg, _, _ = _solve(ctx, pts, k + 1, z=torch.tensor(zs, device=dev))
+        assert _rel(qg, qo) <= 1e-12, (pre, post)
+        if first is None:
+            first = qg
+        assert np.array_equal(qg, first), (pre, post)
+
+
 def test_full_path_matches_oracle(oracle_mod):
     """Points, field, FMG and QoI all on the GPU for lattice samples."""
     _dev()
