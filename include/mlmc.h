@@ -313,17 +313,19 @@ mlmc_status mlmc_profile_end(mlmc_ctx ctx, mlmc_profile_result *out);
  *                     workgroups: for batches too small to fill the chip)
  *   MLMC_PASS_STREAM  rows streamed through LDS, one sample per workgroup
  *                     (2 or 4 per workgroup on 64^2 and 32^2, so that they
- *                     fill a wavefront); FP64 V-cycles, 32 <= n <= 512 only
+ *                     fill a wavefront); FP64 and FP32 V-cycles, 32 <= n
+ *                     <= 512 only
  * All kinds give the bits of the same global sweep order, so the choice
  * changes only the time.  The choice is kept per context for each grid side
  * n and batch class c: chunks of Bc samples with 4^(c-1) < Bc <= 4^c (c = 0
  * for one sample), c < MLMC_BATCH_CLASSES (the last class takes every larger
  * chunk).  A new context starts from defaults measured on MI355X, a rule in
  * c and the number of 32 x 32 tiles of the pass, t = 4^c (n/32)^2: TILE16
- * for t <= 256, TILE32 otherwise; where STREAM exists (FP64) it takes the
- * pre and the post pass for t >= 65536 (t >= 16384 when n <= 64).  A
- * server's slots take the first slot's
- * table. */
+ * for t <= 256, TILE32 otherwise; with FP64 V-cycles STREAM takes the pre
+ * and the post pass for t >= 65536 (t >= 16384 when n <= 64).  FP32
+ * V-cycles (the mixed path) start from tiles everywhere (streaming measured
+ * slower at its batch sizes) and stream where mlmc_autotune measures it
+ * faster.  A server's slots take the first slot's table. */
 enum { MLMC_PASS_TILE32 = 0, MLMC_PASS_TILE16 = 1, MLMC_PASS_STREAM = 2 };
 enum { MLMC_BATCH_CLASSES = 10 };
 typedef struct {

@@ -416,24 +416,26 @@ int lds_top(mlmc_ctx c) { return c->cfg.rtol > 0.0 ? kLdsMaxLevel : kLdsMaxLevel
 bool kind_allowed(mlmc_ctx c, int g, int kind)
 {
     if (kind == kTile32 || kind == kTile16) return true;
-    // the row-streaming passes exist for FP64 V-cycles
-    return kind == kStream && c->cfg.precision == MLMC_FP64 && stream_supported(2 << g);
+    // the row-streaming passes exist for FP64 and FP32 V-cycles
+    return kind == kStream && stream_supported(2 << g);
 }
 
 // Defaults: the choices mlmc_autotune made on MI355X for the s = 100 FP64
 // workload (grids 32^2 .. 256^2, batch classes up to 16384 samples), as a
 // rule in the batch class c and the number of 32 x 32 tiles a pass covers,
 // t = 4^c (n/32)^2: up to 256 tiles (one per CU or fewer) 16 x 16 tiles,
-// which give four times the workgroups; 32 x 32 tiles otherwise; where the
-// FP64 row-streaming passes exist (32^2 .. 512^2), they take the post pass
-// for both passes from t = 65536 on (from t = 16384 on 32^2 and 64^2, where
-// a workgroup packs 4 or 2 samples).
+// which give four times the workgroups; 32 x 32 tiles otherwise; for FP64
+// V-cycles the row-streaming passes (32^2 .. 512^2) take both passes from
+// t = 65536 on (from t = 16384 on 32^2 and 64^2, where a workgroup packs 4
+// or 2 samples).  FP32 V-cycles keep tiles: their streaming passes give the
+// same bits but measured slower at the mixed workload's batch sizes.
 void default_tuning(mlmc_ctx c)
 {
     for (int g = 0; g < kMaxMgLevels; ++g) {
         const int n = 2 << g;
         const int64_t side = std::max(1, n / 32);
-        const bool stream = kind_allowed(c, g, kStream);
+        // defaults stream the FP64 V-cycles only (FP32: measured per context)
+        const bool stream = kind_allowed(c, g, kStream) && c->cfg.precision == MLMC_FP64;
         for (int cl = 0; cl < MLMC_BATCH_CLASSES; ++cl) {
             const int64_t tiles = ((int64_t)1 << (2 * cl)) * side * side;
             const int8_t tile = tiles <= 256 ? kTile16 : kTile32;
@@ -512,12 +514,10 @@ struct FusedRunner {
                            (init == 2 ? 0.25 : 0.0);
             ProfScope ps(c, st, MLMC_KERNEL_PRE, W * cells(n) * words, 0.0);
             const int kind = c->pre_kind[l][cls];
-            if constexpr (std::is_same<T, double>::value) {
-                if (kind == kStream) {
-                    launch_pre_stream(st, c->cfg.mu1, h.a[l], f, u, h.ua[l], h.u[l - 1], n, h.Bc,
-                                      init, h.f[l - 1], active);
-                    continue;
-                }
+            if (kind == kStream) {
+                launch_pre_stream<T>(st, c->cfg.mu1, h.a[l], f, u, h.ua[l], h.u[l - 1], n, h.Bc,
+                                     init, h.f[l - 1], active);
+                continue;
             }
             launch_pre_tile<T>(st, kind, c->cfg.mu1, h.a[l], f, u, h.ua[l], h.u[l - 1], n, h.Bc,
                                init, h.f[l - 1], active);
@@ -529,12 +529,10 @@ struct FusedRunner {
             T *u = (l == g) ? top_u : h.u[l];
             ProfScope ps(c, st, MLMC_KERNEL_POST, W * cells(n) * (3.25 + (f ? 1.0 : 0.0)), 0.0);
             const int kind = c->post_kind[l][cls];
-            if constexpr (std::is_same<T, double>::value) {
-                if (kind == kStream) {
-                    launch_post_stream(st, c->cfg.mu2, h.a[l], f, h.ua[l], u, h.u[l - 1], n, h.Bc,
-                                       active);
-                    continue;
-                }
+            if (kind == kStream) {
+                launch_post_stream<T>(st, c->cfg.mu2, h.a[l], f, h.ua[l], u, h.u[l - 1], n, h.Bc,
+                                      active);
+                continue;
             }
             launch_post_tile<T>(st, kind, c->cfg.mu2, h.a[l], f, h.ua[l], u, h.u[l - 1], n, h.Bc,
                                 active);
@@ -1037,23 +1035,19 @@ mlmc_status tune_grid(mlmc_ctx c, hipStream_t st, int g, int64_t Bc, int cls, hi
     for (int kind : kinds) {
         if (!kind_allowed(c, g, kind)) continue;
         auto pre = [&] {
-            if constexpr (std::is_same<T, double>::value) {
-                if (kind == kStream) {
-                    launch_pre_stream(st, c->cfg.mu1, h.a[g], h.f[g], h.u[g], h.ua[g], h.u[g - 1],
-                                      n, Bc, 1, h.f[g - 1], nullptr);
-                    return;
-                }
+            if (kind == kStream) {
+                launch_pre_stream<T>(st, c->cfg.mu1, h.a[g], h.f[g], h.u[g], h.ua[g], h.u[g - 1],
+                                     n, Bc, 1, h.f[g - 1], nullptr);
+                return;
             }
             launch_pre_tile<T>(st, kind, c->cfg.mu1, h.a[g], h.f[g], h.u[g], h.ua[g], h.u[g - 1], n,
                                Bc, 1, h.f[g - 1], nullptr);
         };
         auto post = [&] {
-            if constexpr (std::is_same<T, double>::value) {
-                if (kind == kStream) {
-                    launch_post_stream(st, c->cfg.mu2, h.a[g], h.f[g], h.ua[g], h.u[g], h.u[g - 1],
-                                       n, Bc, nullptr);
-                    return;
-                }
+            if (kind == kStream) {
+                launch_post_stream<T>(st, c->cfg.mu2, h.a[g], h.f[g], h.ua[g], h.u[g], h.u[g - 1],
+                                      n, Bc, nullptr);
+                return;
             }
             launch_post_tile<T>(st, kind, c->cfg.mu2, h.a[g], h.f[g], h.ua[g], h.u[g], h.u[g - 1],
                                 n, Bc, nullptr);

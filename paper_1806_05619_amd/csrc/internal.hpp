@@ -182,13 +182,14 @@ void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho
 std::string matern_basis(int Q, double nu, double lam, double sigma, int s, int G, double *basis,
                          int64_t ld, std::vector<double> &theta);
 
-// ---- row-streaming passes (kernels_stream.hip), one workgroup per sample ----
+// ---- row-streaming passes (kernels_stream.hip), SPB samples per workgroup;
+// T = double or float (instantiated for both) ----
 bool stream_supported(int n);
-void launch_pre_stream(hipStream_t st, int mu1, const double *a, const double *f,
-                       const double *u_in, double *u_out, const double *uc, int n, int64_t Bc,
-                       int init, double *fc, const int32_t *active);
-void launch_post_stream(hipStream_t st, int mu2, const double *a, const double *f,
-                        const double *u_in, double *u_out, const double *ec, int n, int64_t Bc,
-                        const int32_t *active);
+template <typename T>
+void launch_pre_stream(hipStream_t st, int mu1, const T *a, const T *f, const T *u_in, T *u_out,
+                       const T *uc, int n, int64_t Bc, int init, T *fc, const int32_t *active);
+template <typename T>
+void launch_post_stream(hipStream_t st, int mu2, const T *a, const T *f, const T *u_in, T *u_out,
+                        const T *ec, int n, int64_t Bc, const int32_t *active);
 
 }  // namespace mlmc

@@ -34,7 +34,16 @@ __device__ __forceinline__ double frcp_s(double x)
     return fma(y, e, y);
 }
 
-__device__ __forceinline__ double hmean(double ap, double an) { return 2.0 * ap * an * frcp_s(ap + an); }
+// FP32 (the mixed path's V-cycles): one Newton step, as the tile passes
+__device__ __forceinline__ float frcp_s(float x)
+{
+    float y = __builtin_amdgcn_rcpf(x);
+    float e = fmaf(-x, y, 1.0f);
+    return fmaf(y, e, y);
+}
+
+template <typename T>
+__device__ __forceinline__ T hmean(T ap, T an) { return T(2) * ap * an * frcp_s(ap + an); }
 
 
 // compile-time loop: f(integral_constant<int, I>) for I = B .. E-1, so that
@@ -55,17 +64,17 @@ __device__ __forceinline__ void static_for(F &&f)
 // diagonal and its reciprocal are formed again at each use from the same
 // rounded weights in the same order, so they carry the same bits as a
 // stored copy would, and the window needs 5 doubles a row (7 with f).
-template <bool F1>
+template <bool F1, typename T>
 struct RowW {
-    double wW0, wC, wE1, wN0, wN1;   // W face of c0, c0|c1, E face of c1, N faces
-    double rhs0, rhs1;                // h^2 f (unused when f = 1)
+    T wW0, wC, wE1, wN0, wN1;   // W face of c0, c0|c1, E face of c1, N faces
+    T rhs0, rhs1;               // h^2 f (unused when f = 1)
 };
 
-template <bool F1>
-__device__ __forceinline__ void zero_row(RowW<F1> &d)
+template <bool F1, typename T>
+__device__ __forceinline__ void zero_row(RowW<F1, T> &d)
 {
-    d.wW0 = d.wC = d.wE1 = d.wN0 = d.wN1 = 0.0;
-    d.rhs0 = d.rhs1 = 0.0;
+    d.wW0 = d.wC = d.wE1 = d.wN0 = d.wN1 = T(0);
+    d.rhs0 = d.rhs1 = T(0);
 }
 
 // coarse values of row R's prolongation for lane L: columns L-1, L, L+1 of
@@ -73,18 +82,20 @@ __device__ __forceinline__ void zero_row(RowW<F1> &d)
 // continued oddly (reflected, sign flipped).  The loads take the clamped
 // indices only and the signs are applied when the row is used, so that the
 // loads of the next row stay in flight through a whole row step.
+template <typename T>
 struct Coarse6 {
-    double m0, c0, p0, m1, c1, p1;
+    T m0, c0, p0, m1, c1, p1;
 };
 
-__device__ __forceinline__ void load_coarse_raw(Coarse6 &k, const double *__restrict__ e, int nc,
+template <typename T>
+__device__ __forceinline__ void load_coarse_raw(Coarse6<T> &k, const T *__restrict__ e, int nc,
                                                 int L, int R)
 {
     const int J = R >> 1;
     int J2 = J + ((R & 1) ? 1 : -1);
     J2 = J2 < 0 ? 0 : (J2 >= nc ? nc - 1 : J2);
     const int Im = L > 0 ? L - 1 : 0, Ip = L + 1 < nc ? L + 1 : nc - 1;
-    const double *r0 = e + (int64_t)nc * J, *r1 = e + (int64_t)nc * J2;
+    const T *r0 = e + (int64_t)nc * J, *r1 = e + (int64_t)nc * J2;
     k.m0 = r0[Im];
     k.c0 = r0[L];
     k.p0 = r0[Ip];
@@ -95,7 +106,8 @@ __device__ __forceinline__ void load_coarse_raw(Coarse6 &k, const double *__rest
 
 // the reflection signs of load_coarse_raw's values (products of exact -1
 // factors: the bits of the reflected values themselves)
-__device__ __forceinline__ void sign_coarse(Coarse6 &k, int nc, int L, int R, int n)
+template <typename T>
+__device__ __forceinline__ void sign_coarse(Coarse6<T> &k, int nc, int L, int R, int n)
 {
     if (L == 0) { k.m0 = -k.m0; k.m1 = -k.m1; }
     if (L == nc - 1) { k.p0 = -k.p0; k.p1 = -k.p1; }
@@ -103,7 +115,8 @@ __device__ __forceinline__ void sign_coarse(Coarse6 &k, int nc, int L, int R, in
 }
 
 // (9 e_IJ + 3 e_{I+sx,J} + 3 e_{I,J+sy} + e_{I+sx,J+sy}) / 16 for columns 2L (sx=-1), 2L+1 (sx=+1)
-__device__ __forceinline__ void prolong2(const Coarse6 &k, double &v0, double &v1)
+template <typename T>
+__device__ __forceinline__ void prolong2(const Coarse6<T> &k, T &v0, T &v1)
 {
     v0 = prolong_9331(k.c0, k.m0, k.c1, k.m1);
     v1 = prolong_9331(k.c0, k.p0, k.c1, k.p1);
@@ -111,10 +124,10 @@ __device__ __forceinline__ void prolong2(const Coarse6 &k, double &v0, double &v
 
 // Faces of the lane's cell in column K (0: c0, 1: c1) of a row: r the row,
 // rs the row below.
-template <int K, bool F1>
+template <int K, bool F1, typename T>
 struct Faces {
-    double e, w, nn, s;
-    __device__ __forceinline__ Faces(const RowW<F1> &r, const RowW<F1> &rs)
+    T e, w, nn, s;
+    __device__ __forceinline__ Faces(const RowW<F1, T> &r, const RowW<F1, T> &rs)
     {
         e = K == 0 ? r.wC : r.wE1;
         w = K == 0 ? r.wW0 : r.wC;
@@ -122,10 +135,10 @@ struct Faces {
         s = K == 0 ? rs.wN0 : rs.wN1;
     }
     // the diagonal as the tile passes form it: E + W + N + S, no contraction
-    __device__ __forceinline__ double diag() const
+    __device__ __forceinline__ T diag() const
     {
 #pragma clang fp contract(off)
-        double d = e;
+        T d = e;
         d += w;
         d += nn;
         d += s;
@@ -139,21 +152,23 @@ struct Faces {
 // The result goes to u_out (may equal u_in: rows are read before written).
 // F1: f = 1 (the top level of a stage), so every rhs is h^2 and no row of
 // the register window carries one.
+// T: double (FP64 path) or float (the mixed path's V-cycles), with the
+// arithmetic of the tile passes of the same type.
 // Register budget: 128 (4 waves per SIMD) with f = 1, whose window carries
-// no right-hand side, else 168 (3 waves); both measured against the other.
-template <int MU, bool PRE, bool F1, int SPB, int INIT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3))) void k_stream(const double *__restrict__ a,
-                                                 const double *__restrict__ f,
-                                                 const double *u_in, double *u_out,
-                                                 const double *__restrict__ ec, int n, int64_t Bc,
-                                                 double *__restrict__ fc,
-                                                 const int32_t *__restrict__ active)
+// no right-hand side, or in FP32, else 168 (3 waves); measured against each
+// other in FP64.
+template <int MU, bool PRE, bool F1, int SPB, int INIT, typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 || sizeof(T) == 4 ? 4 : 3)))
+void k_stream(const T *__restrict__ a, const T *__restrict__ f, const T *u_in, T *u_out,
+              const T *__restrict__ ec, int n, int64_t Bc, T *__restrict__ fc,
+              const int32_t *__restrict__ active)
 {
     constexpr int D = 2 * MU;                  // half-sweeps in the pass
     constexpr int NS = PRE ? D + 2 : D + 1;    // rows s-1 .. s-NS in the register window
     // rows fetched ahead (two, in the post pass with f = 1, measured slower)
     constexpr int PD = 1;
-    extern __shared__ double smem[];
+    extern __shared__ double smem_words[];
+    T *smem = reinterpret_cast<T *>(smem_words);
     const int nc = n / 2;
     // sample `sub` of the block: lanes sub * n/2 .. (sub+1) * n/2 - 1; a
     // sample past the batch or inactive keeps its lanes idle but passes every
@@ -167,27 +182,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3)
     }
     const bool lane = SPB == 1 ? L < nc : (sub < SPB && bs < Bc && (!active || active[bs]));
     const int64_t b = (SPB == 1 || lane) ? bs : 0;
-    double *u_ring = smem + (SPB == 1 || !lane ? 0 : sub) * 10 * n;   // [8][n]
-    double *a_ring = u_ring + 8 * n;                                  // [2][n]
+    T *u_ring = smem + (SPB == 1 || !lane ? 0 : sub) * 10 * n;   // [8][n]
+    T *a_ring = u_ring + 8 * n;                                  // [2][n]
     const int c0 = 2 * L, c1 = 2 * L + 1;
     const int64_t cells = (int64_t)n * n;
-    const double *ab = a + b * cells;
-    const double *fb = f ? f + b * cells : nullptr;
-    const double *ub = u_in ? u_in + b * cells : nullptr;
-    double *ob = u_out + b * cells;
-    const double *eb = ec ? ec + b * (int64_t)nc * nc : nullptr;
-    double *fcb = PRE ? fc + b * (int64_t)nc * nc : nullptr;
-    const double h2 = 1.0 / ((double)n * (double)n);
-    const double inv_h2 = (double)n * (double)n;
+    const T *ab = a + b * cells;
+    const T *fb = f ? f + b * cells : nullptr;
+    const T *ub = u_in ? u_in + b * cells : nullptr;
+    T *ob = u_out + b * cells;
+    const T *eb = ec ? ec + b * (int64_t)nc * nc : nullptr;
+    T *fcb = PRE ? fc + b * (int64_t)nc * nc : nullptr;
+    const T h2 = T(1) / (T(n) * T(n));
+    const T inv_h2 = T(n) * T(n);
     constexpr bool need_coarse = PRE ? INIT == 2 : true;
 
-    for (int q = threadIdx.x; q < SPB * 10 * n; q += blockDim.x) smem[q] = 0.0;
+    for (int q = threadIdx.x; q < SPB * 10 * n; q += blockDim.x) smem[q] = T(0);
 
     // prefetch registers: row R is fetched PD row steps before it enters,
     // into set R % PD
     struct Prefetch {
-        double a0 = 0, a1 = 0, u0 = 0, u1 = 0, f0 = 1.0, f1 = 1.0;
-        Coarse6 k{};
+        T a0 = 0, a1 = 0, u0 = 0, u1 = 0, f0 = 1, f1 = 1;
+        Coarse6<T> k{};
     };
     Prefetch pre[PD];
     // In the post pass unconditional, so that no register keeps an older
@@ -221,14 +236,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3)
     // the window needs no moves and the ring rows sit at fixed offsets.  At
     // most NS <= 8 window slots are live.
     static_assert(NS <= 8 && D + 2 <= 8, "window and ring hold 8 rows");
-    RowW<F1> w[8];
+    RowW<F1, T> w[8];
     static_for<0, 8>([&](auto K) __attribute__((always_inline)) { zero_row(w[K.value]); });
-    double rhs_cur0 = 0, rhs_cur1 = 0, rkeep0 = 0, rkeep1 = 0;
+    T rhs_cur0 = 0, rhs_cur1 = 0, rkeep0 = 0, rkeep1 = 0;
     // With mu = 2, half-sweeps t and t + 2 update the same cell of a row, two
     // steps apart: the reciprocal of its diagonal is formed at the first and
     // kept for the second (the same bits), by row mod 4, for the colour of
     // half-sweeps 1 and 3 (rdA) and of 2 and 4 (rdB).
-    double rdA[4] = {}, rdB[4] = {};
+    T rdA[4] = {}, rdB[4] = {};
     const int s_end = PRE ? n + D : n + D - 1;
 
     // One pipeline step for row s entering; J = s & 8 - 1 and P = s & 1 are
@@ -251,19 +266,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3)
         // neighbours).  What a lane reads of its own columns it wrote itself.
         __syncthreads();
         // (A) row s enters the rings; fetch row s + 1
-        const double rhs_prev0 = rhs_cur0, rhs_prev1 = rhs_cur1;
+        const T rhs_prev0 = rhs_cur0, rhs_prev1 = rhs_cur1;
         Prefetch &pp = pre[P % PD];
         if (s < n && lane) {
-            double u0 = pp.u0, u1 = pp.u1;
+            T u0 = pp.u0, u1 = pp.u1;
             if constexpr (need_coarse) {
-                Coarse6 k = pp.k;
+                Coarse6<T> k = pp.k;
                 sign_coarse(k, nc, L, s, n);
-                double v0, v1;
+                T v0, v1;
                 prolong2(k, v0, v1);
                 if (PRE) { u0 = v0; u1 = v1; }
                 else { u0 += v0; u1 += v1; }
             } else if (PRE && INIT == 1) {
-                u0 = u1 = 0.0;
+                u0 = u1 = T(0);
             }
             u_ring[J * n + c0] = u0;
             u_ring[J * n + c1] = u1;
@@ -285,50 +300,50 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3)
         // the workgroup's rings.
         const int q = s - 1;
         {
-            const double *aq = a_ring + (1 - P) * n, *aq1 = a_ring + P * n;
-            const double ap0 = aq[c0], ap1 = aq[c1];
-            RowW<F1> &r = w[slot(1)];
+            const T *aq = a_ring + (1 - P) * n, *aq1 = a_ring + P * n;
+            const T ap0 = aq[c0], ap1 = aq[c1];
+            RowW<F1, T> &r = w[slot(1)];
             r.wC = hmean(ap0, ap1);
-            r.wW0 = c0 > 0 ? hmean(ap0, aq[c0 - 1]) : 2.0 * ap0;
-            r.wE1 = c1 + 1 < n ? hmean(ap1, aq[c1 + 1]) : 2.0 * ap1;
-            r.wN0 = q + 1 < n ? hmean(ap0, aq1[c0]) : 2.0 * ap0;
-            r.wN1 = q + 1 < n ? hmean(ap1, aq1[c1]) : 2.0 * ap1;
+            r.wW0 = c0 > 0 ? hmean(ap0, aq[c0 - 1]) : T(2) * ap0;
+            r.wE1 = c1 + 1 < n ? hmean(ap1, aq[c1 + 1]) : T(2) * ap1;
+            r.wN0 = q + 1 < n ? hmean(ap0, aq1[c0]) : T(2) * ap0;
+            r.wN1 = q + 1 < n ? hmean(ap1, aq1[c1]) : T(2) * ap1;
             if constexpr (!F1) {
                 r.rhs0 = rhs_prev0;
                 r.rhs1 = rhs_prev1;
             }
             if (q == 0) {          // south wall of row 0, in the slot of row -1
-                w[slot(2)].wN0 = 2.0 * ap0;
-                w[slot(2)].wN1 = 2.0 * ap1;
+                w[slot(2)].wN0 = T(2) * ap0;
+                w[slot(2)].wN1 = T(2) * ap1;
             }
         }
 
         // (C) half-sweep t on row s - t
-        static_for<1, D + 1>([&](auto T) __attribute__((always_inline)) {
-            constexpr int t = T.value;
+        static_for<1, D + 1>([&](auto Tc) __attribute__((always_inline)) {
+            constexpr int t = Tc.value;
             const int rr = s - t;
             constexpr bool red = PRE ? (t & 1) : !(t & 1);
             // the red cell of row rr is column c0 when rr is even
             constexpr int K = red ? ((P - t) & 1) : 1 - ((P - t) & 1);
-            const Faces<K, F1> fw(w[slot(t)], w[slot(t + 1)]);
+            const Faces<K, F1, T> fw(w[slot(t)], w[slot(t + 1)]);
             // formed whether or not rr is a row of the grid, so that no cache
             // slot keeps an older value beside the new one
-            double rdiag;
+            T rdiag;
             if constexpr (MU == 2) {
-                double &rd = (t & 1) ? rdA[(J - t) & 3] : rdB[(J - t) & 3];
+                T &rd = (t & 1) ? rdA[(J - t) & 3] : rdB[(J - t) & 3];
                 if constexpr (t <= 2) rd = frcp_s(fw.diag());
                 rdiag = rd;
             } else {
                 rdiag = frcp_s(fw.diag());
             }
             if (rr >= 0 && rr < n && lane) {
-                double *row = u_ring + slot(t) * n;
-                const double *up = u_ring + slot(t - 1) * n;
-                const double *dn = u_ring + slot(t + 1) * n;
+                T *row = u_ring + slot(t) * n;
+                const T *up = u_ring + slot(t - 1) * n;
+                const T *dn = u_ring + slot(t + 1) * n;
                 const int c = K == 0 ? c0 : c1;
                 // explicit fma in the face order E, W, N, S of the tile passes
                 // (a wall face meets a neighbour of value 0 there: skipped)
-                double num = F1 ? h2 : (K == 0 ? w[slot(t)].rhs0 : w[slot(t)].rhs1);
+                T num = F1 ? h2 : (K == 0 ? w[slot(t)].rhs0 : w[slot(t)].rhs1);
                 if (c + 1 < n) num = fma(fw.e, row[c + 1], num);
                 if (c > 0) num = fma(fw.w, row[c - 1], num);
                 if (rr + 1 < n) num = fma(fw.nn, up[c], num);
@@ -341,37 +356,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3)
         if constexpr (PRE) {
             const int rr = s - D - 1;
             if (rr >= 0 && rr < n && lane) {
-                const double *row = u_ring + slot(D + 1) * n;
-                const double *up = u_ring + slot(D) * n, *dn = u_ring + slot(D + 2) * n;
+                const T *row = u_ring + slot(D + 1) * n;
+                const T *up = u_ring + slot(D) * n, *dn = u_ring + slot(D + 2) * n;
                 // net flux face by face, w (u_P - u_nbr) in the order E, W, N,
                 // S with explicit fma, a wall face as 2 a_P (u_P - 0): the
                 // rounding of the tile passes
                 auto flux = [&](auto Kc) __attribute__((always_inline)) {
                     constexpr int K = decltype(Kc)::value;
-                    const Faces<K, F1> fw(w[slot(D + 1)], w[slot(D + 2)]);
+                    const Faces<K, F1, T> fw(w[slot(D + 1)], w[slot(D + 2)]);
                     const int c = K == 0 ? c0 : c1;
-                    const double u = row[c];
-                    double v = fw.e * (u - (c + 1 < n ? row[c + 1] : 0.0));
-                    v = fma(fw.w, u - (c > 0 ? row[c - 1] : 0.0), v);
-                    v = fma(fw.nn, u - (rr + 1 < n ? up[c] : 0.0), v);
-                    v = fma(fw.s, u - (rr > 0 ? dn[c] : 0.0), v);
+                    const T u = row[c];
+                    T v = fw.e * (u - (c + 1 < n ? row[c + 1] : T(0)));
+                    v = fma(fw.w, u - (c > 0 ? row[c - 1] : T(0)), v);
+                    v = fma(fw.nn, u - (rr + 1 < n ? up[c] : T(0)), v);
+                    v = fma(fw.s, u - (rr > 0 ? dn[c] : T(0)), v);
                     return v;
                 };
-                const double res0 =
+                const T res0 =
                     inv_h2 * ((F1 ? h2 : w[slot(D + 1)].rhs0) - flux(std::integral_constant<int, 0>{}));
-                const double res1 =
+                const T res1 =
                     inv_h2 * ((F1 ? h2 : w[slot(D + 1)].rhs1) - flux(std::integral_constant<int, 1>{}));
                 const int64_t o = (int64_t)rr * n;
                 ob[o + c0] = row[c0];
                 ob[o + c1] = row[c1];
                 constexpr bool odd = ((P - D - 1) & 1) != 0;
-                if constexpr (odd) fcb[L + (int64_t)nc * (rr >> 1)] = 0.25 * (rkeep0 + rkeep1 + res0 + res1);
+                if constexpr (odd) fcb[L + (int64_t)nc * (rr >> 1)] = T(0.25) * (rkeep0 + rkeep1 + res0 + res1);
                 else { rkeep0 = res0; rkeep1 = res1; }
             }
         } else {
             const int rr = s - D;
             if (rr >= 0 && rr < n && lane) {
-                const double *row = u_ring + slot(D) * n;
+                const T *row = u_ring + slot(D) * n;
                 const int64_t o = (int64_t)rr * n;
                 ob[o + c0] = row[c0];
                 ob[o + c1] = row[c1];
@@ -384,29 +399,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 ? 4 : 3)
         static_for<0, 8>([&](auto Jc) __attribute__((always_inline)) { step(s0 + Jc.value, Jc); });
 }
 
-template <int MU, bool PRE, bool F1, int SPB, int INIT>
-void launch_spb(hipStream_t st, const double *a, const double *f, const double *u_in,
-                double *u_out, const double *ec, int n, int64_t Bc, double *fc,
-                const int32_t *active)
+template <int MU, bool PRE, bool F1, int SPB, int INIT, typename T>
+void launch_spb(hipStream_t st, const T *a, const T *f, const T *u_in, T *u_out, const T *ec,
+                int n, int64_t Bc, T *fc, const int32_t *active)
 {
     // once per instantiation; the static's initialisation is thread-safe
     static const bool attr_set = [] {
-        (void)hipFuncSetAttribute((const void *)k_stream<MU, PRE, F1, SPB, INIT>,
+        (void)hipFuncSetAttribute((const void *)k_stream<MU, PRE, F1, SPB, INIT, T>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         return true;
     }();
     (void)attr_set;
-    const size_t lds = sizeof(double) * 10 * (size_t)n * SPB;
+    const size_t lds = sizeof(T) * 10 * (size_t)n * SPB;
     const int threads = SPB * (n / 2) < 64 ? 64 : SPB * (n / 2);
     const unsigned blocks = (unsigned)((Bc + SPB - 1) / SPB);
-    hipLaunchKernelGGL((k_stream<MU, PRE, F1, SPB, INIT>), dim3(blocks), dim3(threads), lds, st, a,
-                       f, u_in, u_out, ec, n, Bc, fc, active);
+    hipLaunchKernelGGL((k_stream<MU, PRE, F1, SPB, INIT, T>), dim3(blocks), dim3(threads), lds, st,
+                       a, f, u_in, u_out, ec, n, Bc, fc, active);
 }
 
-template <int MU, bool PRE, bool F1, int SPB>
-void launch_init(hipStream_t st, const double *a, const double *f, const double *u_in,
-                 double *u_out, const double *ec, int n, int64_t Bc, int init, double *fc,
-                 const int32_t *active)
+template <int MU, bool PRE, bool F1, int SPB, typename T>
+void launch_init(hipStream_t st, const T *a, const T *f, const T *u_in, T *u_out, const T *ec,
+                 int n, int64_t Bc, int init, T *fc, const int32_t *active)
 {
     if constexpr (PRE) {
         if (init == 1) {
@@ -421,10 +434,9 @@ void launch_init(hipStream_t st, const double *a, const double *f, const double 
     launch_spb<MU, PRE, F1, SPB, 0>(st, a, f, u_in, u_out, ec, n, Bc, fc, active);
 }
 
-template <int MU, bool PRE, bool F1>
-void launch_one(hipStream_t st, const double *a, const double *f, const double *u_in,
-                double *u_out, const double *ec, int n, int64_t Bc, int init, double *fc,
-                const int32_t *active)
+template <int MU, bool PRE, bool F1, typename T>
+void launch_one(hipStream_t st, const T *a, const T *f, const T *u_in, T *u_out, const T *ec,
+                int n, int64_t Bc, int init, T *fc, const int32_t *active)
 {
     // as many samples per workgroup as fill one wavefront
     if (n >= 128) launch_init<MU, PRE, F1, 1>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
@@ -436,9 +448,9 @@ void launch_one(hipStream_t st, const double *a, const double *f, const double *
 
 bool stream_supported(int n) { return n >= 32 && n <= 512; }
 
-void launch_pre_stream(hipStream_t st, int mu1, const double *a, const double *f,
-                       const double *u_in, double *u_out, const double *uc, int n, int64_t Bc,
-                       int init, double *fc, const int32_t *active)
+template <typename T>
+void launch_pre_stream(hipStream_t st, int mu1, const T *a, const T *f, const T *u_in, T *u_out,
+                       const T *uc, int n, int64_t Bc, int init, T *fc, const int32_t *active)
 {
     if (mu1 == 2)
         f ? launch_one<2, true, false>(st, a, f, u_in, u_out, uc, n, Bc, init, fc, active)
@@ -448,16 +460,29 @@ void launch_pre_stream(hipStream_t st, int mu1, const double *a, const double *f
           : launch_one<1, true, true>(st, a, f, u_in, u_out, uc, n, Bc, init, fc, active);
 }
 
-void launch_post_stream(hipStream_t st, int mu2, const double *a, const double *f,
-                        const double *u_in, double *u_out, const double *ec, int n, int64_t Bc,
-                        const int32_t *active)
+template <typename T>
+void launch_post_stream(hipStream_t st, int mu2, const T *a, const T *f, const T *u_in, T *u_out,
+                        const T *ec, int n, int64_t Bc, const int32_t *active)
 {
     if (mu2 == 2)
-        f ? launch_one<2, false, false>(st, a, f, u_in, u_out, ec, n, Bc, 0, nullptr, active)
-          : launch_one<2, false, true>(st, a, f, u_in, u_out, ec, n, Bc, 0, nullptr, active);
+        f ? launch_one<2, false, false>(st, a, f, u_in, u_out, ec, n, Bc, 0, (T *)nullptr, active)
+          : launch_one<2, false, true>(st, a, f, u_in, u_out, ec, n, Bc, 0, (T *)nullptr, active);
     else
-        f ? launch_one<1, false, false>(st, a, f, u_in, u_out, ec, n, Bc, 0, nullptr, active)
-          : launch_one<1, false, true>(st, a, f, u_in, u_out, ec, n, Bc, 0, nullptr, active);
+        f ? launch_one<1, false, false>(st, a, f, u_in, u_out, ec, n, Bc, 0, (T *)nullptr, active)
+          : launch_one<1, false, true>(st, a, f, u_in, u_out, ec, n, Bc, 0, (T *)nullptr, active);
 }
+
+template void launch_pre_stream<double>(hipStream_t, int, const double *, const double *,
+                                        const double *, double *, const double *, int, int64_t,
+                                        int, double *, const int32_t *);
+template void launch_pre_stream<float>(hipStream_t, int, const float *, const float *,
+                                       const float *, float *, const float *, int, int64_t, int,
+                                       float *, const int32_t *);
+template void launch_post_stream<double>(hipStream_t, int, const double *, const double *,
+                                         const double *, double *, const double *, int, int64_t,
+                                         const int32_t *);
+template void launch_post_stream<float>(hipStream_t, int, const float *, const float *,
+                                        const float *, float *, const float *, int, int64_t,
+                                        const int32_t *);
 
 }  // namespace mlmc

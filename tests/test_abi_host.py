@@ -246,14 +246,16 @@ def test_tuning_table_defaults_and_validation():
     t2 = {(e["n"], e["batch_class"]): (e["pre"], e["post"]) for e in ctx.tuning()}
     assert t2[(128, 2)] == (T16, ST) and t2[(32, 9)] == (T16, T16)
     assert sum(t2[k] != (e["pre"], e["post"]) for e in t for k in [(e["n"], e["batch_class"])]) == 2
-    # mixed precision: FP32 V-cycles have no streaming passes; rtol mode keeps
-    # 32^2 LDS-resident
+    # mixed precision: the FP32 V-cycles stream only where the table says so
+    # (the defaults keep tiles); rtol mode keeps 32^2 LDS-resident
     mx = _host_ctx(n0=4, num_levels=7, precision=1, rtol=1e-10, max_iters=50)
     tm = mx.tuning()
     assert [e["n"] for e in tm[::m.MLMC_BATCH_CLASSES]] == [64, 128, 256]
     assert all(e["pre"] == e["post"] != ST for e in tm)
-    with pytest.raises(m.MlmcError):
-        mx.set_tuning([dict(n=256, batch_class=7, pre=T32, post=ST)])
+    mx.set_tuning([dict(n=256, batch_class=7, pre=T32, post=ST)])
+    assert {(e["n"], e["batch_class"]): (e["pre"], e["post"]) for e in mx.tuning()}[(256, 7)] == (T32, ST)
+    with pytest.raises(m.MlmcError):                 # no streaming pass above 512^2
+        _host_ctx(n0=4, num_levels=9).set_tuning([dict(n=1024, batch_class=0, pre=ST, post=T32)])
     with pytest.raises(m.MlmcError):                 # rtol mode: 32^2 is LDS-resident
         mx.set_tuning([dict(n=32, batch_class=0, pre=T32, post=T32)])
     assert _host_ctx(n0=4, num_levels=3).tuning() == []          # all grids LDS-resident

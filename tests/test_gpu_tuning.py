@@ -61,8 +61,8 @@ def test_every_pass_kind_gives_the_same_bits(name, precision, level, sizes):
     fixed = w["rtol"] <= 0
     levels = (level, 3) if fixed else (level,)
     want = {(lv, r): _solve(ctx, lv, *r) for lv in levels for r in sizes}
-    small = [T32, T16] + ([ST] if precision == m.MLMC_FP64 else []) if fixed else []
-    large = [T32, T16] + ([ST] if precision == m.MLMC_FP64 else [])
+    small = [T32, T16, ST] if fixed else []
+    large = [T32, T16, ST]
     for k32 in small or [None]:
         for pre, post in itertools.product(large, large):
             ent = []
@@ -103,17 +103,16 @@ def test_autotune_installs_measured_kinds_and_keeps_results():
 
 @pytest.mark.parametrize("precision", [m.MLMC_FP64, m.MLMC_MIXED])
 def test_autotune_refinement_contexts(precision):
-    """rtol contexts: 64^2 and up are tile grids (32^2 is LDS-resident); the
-    mixed context's FP32 V-cycles may only take tiles.  The tuned table keeps
-    every result bitwise."""
+    """rtol contexts: 64^2 and up are tile grids (32^2 is LDS-resident), and
+    every kind is open to both V-cycle precisions (the FP32 ones stream too).
+    The tuned table keeps every result bitwise."""
     _dev()
     w, ctx = _ctx("mlqmc_mixed_s400", precision, max_batch=32)
     before = _solve(ctx, 5, 0, 3, 2, 4)
     table = ctx.autotune(5)
     assert [e["n"] for e in table[::m.MLMC_BATCH_CLASSES]][:3] == [64, 128, 256]
     for e in table:
-        if precision == m.MLMC_MIXED:
-            assert e["pre"] in (T32, T16) and e["post"] in (T32, T16), e
+        assert e["pre"] in (T32, T16, ST) and e["post"] in (T32, T16, ST), e
         if e["n"] <= 128 and e["batch_class"] == 0:      # tuned: levels <= 5 reach 128^2
             assert e["pre_ms"] > 0 and e["post_ms"] > 0, e
         if e["n"] > 128:
