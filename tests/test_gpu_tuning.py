@@ -118,3 +118,33 @@ def test_autotune_refinement_contexts(precision):
         if e["n"] > 128:
             assert e["pre_ms"] == 0, e
     assert np.array_equal(_solve(ctx, 5, 0, 3, 2, 4), before)
+
+
+@pytest.mark.parametrize("name,precision", [("mlqmc_fp64_s100", m.MLMC_FP64),
+                                            ("mlqmc_mixed_s400", m.MLMC_FP64),
+                                            ("mlqmc_mixed_s400", m.MLMC_MIXED)])
+def test_streaming_at_512_matches_tiles(name, precision):
+    """512^2, the largest streaming grid and the only one whose workgroup
+    holds four wavefronts per sample (one barrier per row step): streaming,
+    tiles and a mix give the same bits, fixed-cycle and refinement mode,
+    FP64 and FP32 V-cycles."""
+    _dev()
+    w = synth.workload(name)
+    L = 8                                           # MG grids up to 512^2
+    ctx = m.Context(n0=w["n0"], num_levels=L, s=w["s"], corr_len=w["corr_len"], sigma2=w["sigma2"],
+                    mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"],
+                    max_iters=w["max_iters"], precision=precision,
+                    qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
+                    genvec=synth.korobov_vector(w["seed"], w["s"]),
+                    shifts=synth.shift_table(w["seed"], L, w["num_shifts"], w["s"]),
+                    max_batch=8, device=0)
+    base = [dict(e) for e in ctx.tuning()]
+    want = None
+    for pre, post in [(T32, T32), (ST, ST), (T16, ST), (ST, T32)]:
+        ctx.set_tuning(dict(e, pre=pre, post=post) for e in base)
+        print(f"{name} precision {precision}: pre {pre} post {post}", flush=True)
+        q = _solve(ctx, L - 1, 0, 3, 1, 2)
+        assert np.all(np.isfinite(q))
+        if want is None:
+            want = q
+        assert np.array_equal(q, want), (pre, post)
