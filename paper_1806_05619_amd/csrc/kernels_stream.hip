@@ -1,4 +1,5 @@
-// Row-streaming multigrid passes for gfx950 (Section 4), FP64.
+// Row-streaming multigrid passes for gfx950 (Section 4), FP64 and FP32 (the
+// mixed path's V-cycles), each with the arithmetic of the tile passes of its type.
 //
 // One workgroup solves the grids of SPB samples of n x n cells (32 <= n <=
 // 512; SPB = 64 / (n/2) samples on grids narrower than a wavefront, so that no
