@@ -81,6 +81,14 @@ def lib():
     L.oracle_sample.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int, _dp]
     L.oracle_batch.restype = C.c_int
     L.oracle_batch.argtypes = [C.c_void_p, C.c_int, C.c_int, _dp, C.c_int, _dp, C.c_int]
+    L.oracle_restrict.restype = None
+    L.oracle_restrict.argtypes = [C.c_int, _dp, _dp]
+    L.oracle_prolong.restype = None
+    L.oracle_prolong.argtypes = [C.c_int, _dp, _dp, C.c_int]
+    L.oracle_rb_sweep.restype = None
+    L.oracle_rb_sweep.argtypes = [C.c_int, _dp, _dp, _dp, C.c_int]
+    L.oracle_vcycle.restype = C.c_int
+    L.oracle_vcycle.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
     _lib = L
     return L
 
@@ -166,6 +174,35 @@ def qoi(n: int, u: np.ndarray):
     return qm.value, qc.value
 
 
+# ---- Section 4: pieces of the V-cycle --------------------------------------
+def restrict(nc: int, r: np.ndarray) -> np.ndarray:
+    """Mean of the four children: fine (2nc)^2 -> coarse nc^2."""
+    r = np.ascontiguousarray(r, dtype=np.float64).reshape(-1)
+    assert r.size == 4 * nc * nc
+    fc = np.empty(nc * nc)
+    lib().oracle_restrict(int(nc), r, fc)
+    return fc
+
+
+def prolong(nc: int, e: np.ndarray, out: np.ndarray | None = None) -> np.ndarray:
+    """Bilinear prolongation of e (nc^2) to (2nc)^2; added to `out` if given."""
+    e = np.ascontiguousarray(e, dtype=np.float64).reshape(-1)
+    assert e.size == nc * nc
+    add = out is not None
+    o = np.ascontiguousarray(out, dtype=np.float64).reshape(-1).copy() if add else np.empty(4 * nc * nc)
+    lib().oracle_prolong(int(nc), e, o, int(add))
+    return o
+
+
+def rb_sweep(n: int, a: np.ndarray, f: np.ndarray, u: np.ndarray, colour: int) -> np.ndarray:
+    """One Gauss-Seidel half-sweep over the cells of `colour` (0 red); returns the new u."""
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1).copy()
+    lib().oracle_rb_sweep(int(n), a, f, u, int(colour))
+    return u
+
+
 class Problem:
     """One configured problem: n0, levels, KL (s, corr_len, sigma2) and the
     FMG cycle (mu0, mu1, mu2; rtol > 0 switches to refinement to rtol)."""
@@ -204,6 +241,18 @@ class Problem:
             out.append((g, n, slice(off, off + n * n)))
             off += n * n
         return out
+
+    def vcycle(self, g: int, a_all: np.ndarray, u: np.ndarray, f: np.ndarray) -> np.ndarray:
+        """One V(mu1, mu2) cycle on multigrid level g; a_all holds levels 0..g."""
+        a_all = np.ascontiguousarray(a_all, dtype=np.float64).reshape(-1)
+        n = 2 << g
+        assert a_all.size == sum((2 << l) ** 2 for l in range(g + 1))
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1).copy()
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        assert u.size == n * n and f.size == n * n
+        if lib().oracle_vcycle(self._h, int(g), a_all, u, f) != 0:
+            raise MemoryError("oracle_vcycle")
+        return u
 
     def field(self, y: np.ndarray, k: int) -> np.ndarray:
         y = np.ascontiguousarray(y, dtype=np.float64).reshape(-1)

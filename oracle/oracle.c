@@ -579,6 +579,52 @@ static void vcycle(fmg_state *S, int g, double *u, const double *f)
     }
 }
 
+/* The transfer operators, one red-black half-sweep and one V-cycle, exported
+ * so that the tests can pin each of them against dense matrices built from
+ * their definitions. */
+void oracle_restrict(int nc, const double *r, double *fc)
+{
+    restrict_mean(nc, r, fc);
+}
+
+void oracle_prolong(int nc, const double *e, double *out, int add)
+{
+    prolong(nc, e, out, add);
+}
+
+void oracle_rb_sweep(int n, const double *a, const double *f, double *u, int colour)
+{
+    rb_sweep(n, a, f, u, colour);
+}
+
+int oracle_vcycle(const oracle_problem *P, int g, const double *a_all, double *u,
+                  const double *f)
+{
+    fmg_state S;
+    memset(&S, 0, sizeof(S));
+    S.P = P;
+    S.G = g;
+    int64_t off = 0;
+    int ok = 1;
+    for (int l = 0; l <= g; ++l) {
+        int64_t m = (int64_t)(2 << l) * (2 << l);
+        S.a[l] = a_all + off;
+        S.e[l] = (double *)calloc(m, sizeof(double));
+        S.f[l] = (double *)calloc(m, sizeof(double));
+        S.r[l] = (double *)calloc(m, sizeof(double));
+        ok &= S.e[l] && S.f[l] && S.r[l];
+        off += m;
+    }
+    if (ok)
+        vcycle(&S, g, u, f);
+    for (int l = 0; l <= g; ++l) {
+        free(S.e[l]);
+        free(S.f[l]);
+        free(S.r[l]);
+    }
+    return ok ? 0 : -1;
+}
+
 static double dot(int64_t m, const double *x, const double *y)
 {
     ksum k = {0.0, 0.0};

@@ -82,6 +82,21 @@ int oracle_fmg(const oracle_problem *P, int G, const double *a_all,
                double *qoi, int *iters, double *relres, double *u_out,
                int *trace, int *marks, int trace_cap, int *trace_len);
 
+/* The pieces of the V-cycle, for the tests that pin them one by one:
+ * fc = R r, the mean of the four children (fine grid 2nc x 2nc);
+ * out = P e (add = 0) or out += P e (add = 1), bilinear (9,3,3,1)/16 with
+ * coarse values reflected oddly across the walls;
+ * one Gauss-Seidel half-sweep over the cells of one colour
+ * (0 = red = (i+j) even, 1 = black) for A u = f;
+ * one V(mu1, mu2) cycle on multigrid level g for A_g u = f, u updated in
+ * place, a_all the coefficients of levels 0..g (level-major), mu1 and mu2
+ * from the problem.  Returns 0, or -1 if out of memory. */
+void oracle_restrict(int nc, const double *r, double *fc);
+void oracle_prolong(int nc, const double *e, double *out, int add);
+void oracle_rb_sweep(int n, const double *a, const double *f, double *u, int colour);
+int oracle_vcycle(const oracle_problem *P, int g, const double *a_all, double *u,
+                  const double *f);
+
 /* ---- one sample / a batch ------------------------------------------------ */
 /* method 0: FMG (fixed cycles or rtol, as configured); 1: direct solve per level.
  * qoi [k+1][2] for MLMC levels 0..k.  Returns 0 / nonzero as oracle_fmg. */
