@@ -1,18 +1,23 @@
 """Benchmark of the MG-MLQMC per-sample hot path on one MI355X.
 
 One step = one pass of the whole path over one batch: lattice points, KL field
-(dense product + exp), FMG with the QoI of every stage, level-difference sums,
-their device-to-host copy and the estimator.  The batch is the finest level of
-the MLQMC FP64 workload: 2^10 Korobov lattice points x 16 random shifts =
-16384 samples solved on 4^2 .. 256^2 (s = 100 KL terms, lambda = 0.3,
-sigma = 1, FMG with 2 V(2,2) cycles per stage, QoI mean of u and u(1/2,1/2)).
-Inputs (generating vector, shifts, KL basis) are resident in HBM before the
-timed region.
+(dense product + exp), FMG with every stage refined to relative residual 1e-10
+and the QoI of every stage, level-difference sums, their device-to-host copy
+and the estimator.  The batch is 16 Korobov lattice points x 16 random shifts
+= 256 samples at the finest level (1024^2, MLMC levels 4^2 .. 1024^2) of the
+mixed-precision workload (s = 400 KL terms, lambda = 0.1, sigma^2 = 2, QoI
+mean of u and u(1/2,1/2)).  The mixed path (bf16 digit-product field, FP32
+V-cycles inside FP64 flexible CG) is the headline; the FP64 path runs the same
+steps on the same batch beside it.  Inputs (generating vector, shifts, KL
+basis) are resident in HBM before the timed region.
 
-Prints one JSON line (rank 0) with the throughput, the roofline of the
-dominant kernel measured live with HIP events on the library's stream, the
-per-level throughput, request latency percentiles and the oracle timed on the
-host's cores.
+The last line of stdout is one compact JSON object: mixed samples/s, the FP64
+samples/s and their ratio, the per-level QoI difference between the paths,
+the roofline of the dominant kernel (HIP events on the library's stream),
+samples/s per level, one-point request latency percentiles, and the oracle
+timed on the host's cores on the first samples of the same batch, with the
+per-level error of each path against it.  Progress and detail go to stderr;
+--only-* runs print the other measurements.
 """
 from __future__ import annotations
 
@@ -34,19 +39,36 @@ FP64_PEAK_TFLOPS = 78.6
 BF16_PEAK_TFLOPS = 2500.0
 
 
+# algorithmic HBM bytes each profiled kind counts per launch (per cell of the
+# grid it runs on, over all samples of the chunk; w = bytes per word of the
+# V-cycle type, 4 in the mixed path)
+BYTE_MODEL = dict(
+    points="Y written, 16 B per sample and term",
+    field="Y digits, basis digits (8 B per term and cell) read, a written (12 B per cell)",
+    smooth="unfused colour sweep", restrict="unfused", prolong="FMG interpolation: coarse "
+    "solution read (n^2/4), fine written, 8 B words", coarse="2x2 solve", qoi="u read once",
+    sums="QoI table read once",
+    pre="a, u (unless zero or interpolated), f (unless 1) read, u written, f_c written (w/4)",
+    post="e_c (w/4), a, u, f (unless 1) read, u written",
+    lds="coefficients of the LDS grids read, top-level solution written",
+    refine="one flexible-CG step after the V-cycle: dots (z, r, r_old read, r_old written), "
+           "p and (p, A p) (a, z, p read, p written), x and new residual (a and x in FP64, "
+           "p read; x in FP64 and r written): 24 + 10 w B per cell")
+
 KINDS = ("points", "field", "smooth", "restrict", "prolong", "coarse", "qoi", "sums", "pre", "post",
          "lds", "refine")
 KIND_NAMES = {0: "tile32", 1: "tile16", 2: "stream"}
 KERNEL_NAMES = dict(
-    points="k_points", field="k_field_mfma64", smooth="k_rbgs (one colour)",
-    restrict="k_resid_restrict", prolong="k_prolong", coarse="k_coarse_solve", qoi="k_qoi",
-    sums="k_sums",
-    pre="pre pass (2 red-black sweeps + residual + restriction): k_stream<2,pre> on 32^2.."
-        "256^2 (2 and 4 samples per workgroup on 64^2 and 32^2)",
-    post="post pass (prolongation + correction + 2 sweeps): k_stream<2,post> on 32^2..256^2 "
-         "(2 and 4 samples per workgroup on 64^2 and 32^2)",
-    lds="k_lds_fmg_fixed, k_lds_vcycle (LDS-resident grids <= 16^2)",
-    refine="k_fcg_* (flexible-CG vector passes, grids >= 64^2)")
+    points="k_points", field="k_field_digits (mixed) / k_field_mfma64 (FP64)",
+    smooth="k_rbgs (one colour)", restrict="k_resid_restrict", prolong="k_prolong",
+    coarse="k_coarse_solve", qoi="k_qoi", sums="k_sums",
+    pre="pre pass (2 red-black sweeps + residual + restriction): k_pre_tile / k_stream on "
+        "every grid above the LDS-resident ones",
+    post="post pass (prolongation + correction + 2 sweeps): k_post_tile / k_stream on every "
+         "grid above the LDS-resident ones",
+    lds="k_lds_fmg_refine, k_lds_vcycle (LDS-resident grids <= 32^2)",
+    refine="flexible-CG step on grids >= 64^2: k_fcg_dots, k_fcg_p, k_fcg_x and the "
+           "per-sample scalar folds between them")
 
 
 def log(*a):
@@ -85,6 +107,35 @@ def make_context(m, w, max_batch):
                      genvec=synth.korobov_vector(w["seed"], w["s"]),
                      shifts=synth.shift_table(w["seed"], w["num_levels"], w["num_shifts"], w["s"]),
                      max_batch=max_batch, device=0)
+
+
+def fp64_fixed_c2(m, torch, args):
+    """The FP64 fixed-cycle workload (s = 100, 2^10 points x 16 shifts =
+    16384 samples at 256^2, 2 V(2,2) per FMG stage): samples/s of the whole
+    path, with the kernel-time breakdown of one step."""
+    import synth
+    w = synth.workload("mlqmc_fp64_s100")
+    dev = torch.device("cuda:0")
+    k = w["num_levels"] - 1
+    npts, R = 1 << w["lattice_log2n"], w["num_shifts"]
+    B = npts * R
+    ctx = make_context(m, w, max_batch=B)
+    if not args.no_autotune:
+        ctx.autotune(k)
+    pts = ctx.lattice(k, 0, npts, 0, R)
+    sums = torch.zeros((R, 2, k + 1, 2), dtype=torch.float64, device=dev)
+    rate = solve_rate(ctx, pts, torch, 1.0, sums=sums)
+    breakdown = {}
+    for kind in KINDS:
+        ctx.profile_begin(kind)
+        ctx.fmg_solve(pts, sums=sums)
+        r = ctx.profile_end()
+        if r["launches"]:
+            breakdown[kind] = dict(ms=r["total_ms"], launches=r["launches"],
+                                   gbs=r["bytes"] / (r["total_ms"] * 1e-3) / 1e9)
+    log(f"[bench] C2 fp64 fixed cycles at 256^2: {rate:.0f} samples/s")
+    return dict(workload="mlqmc_fp64_s100 at 256^2, 16384 samples, FP64, 2 V(2,2) per stage",
+                samples_per_s=rate, breakdown=breakdown)
 
 
 def mixed_vs_fp64(m, torch, dev, max_batch=64, min_seconds=0.25):
@@ -484,54 +535,204 @@ def uneven(m, torch, slots=3, reps=2):
     return out
 
 
-def cpu_baseline(w, level, seconds):
-    """The oracle (field by direct summation + CPU FMG + QoI) on the host's
-    cores, over the first lattice points of shift 0 at the same level, run in
-    batches until `seconds` of wall time have passed."""
+def oracle_baseline(w, level, y_batch, gpu_qoi, seconds, max_samples):
+    """The oracle (field by direct summation + CPU FMG to the same rtol + QoI,
+    built -O3 -march=native) on the host's cores, over the first samples of
+    the GPU step's own batch (same lattice points and shifts), run in groups
+    of `threads` samples until `seconds` of wall time have passed.  Its QoIs
+    also give the error of each GPU path against the oracle, per level, on
+    those samples.  This is the only part of the benchmark that runs the
+    oracle."""
     import oracle
-    import synth
+    oracle.select_build("fast")
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
     threads = max(1, min(threads, 16))
     P = oracle.Problem(w["n0"], w["num_levels"], w["s"], w["corr_len"], w["sigma2"],
-                       mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"])
-    z = synth.korobov_vector(w["seed"], w["s"])
-    D = synth.shift_table(w["seed"], w["num_levels"], w["num_shifts"], w["s"])
-    def run(nthreads, secs, n0):
-        done = 0
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < secs:
-            nb = 2 * nthreads
-            _, y = oracle.points(z, D[level, 0], n0 + done, n0 + done + nb)
-            P.batch(level, y, 0, nthreads=nthreads)
-            done += nb
-        return done, time.perf_counter() - t0
+                       mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"],
+                       max_iters=w["max_iters"])
+    done, bad, qs = 0, 0, []
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds and done < max_samples:
+        nb = min(threads, max_samples - done)
+        q, nbad = P.batch(level, y_batch[done:done + nb], 0, nthreads=threads)
+        qs.append(q)
+        bad += nbad
+        done += nb
+    dt = time.perf_counter() - t0
+    qo = np.concatenate(qs)
+    err = {}
+    for name, qg in gpu_qoi.items():
+        rel = np.abs(qg[:done] - qo) / np.abs(qo)          # [samples][level][nq]
+        err[name] = [float(f"{v:.2e}") for v in rel.max(axis=(0, 2))]
+    base = dict(value=done / dt, unit="samples/s", cores=threads, kind="oracle",
+                sample=f"the first {done} samples of the step's batch at level {level} "
+                       f"({w['n0'] << level}^2): direct-sum KL field + CPU FMG to rtol "
+                       f"{w['rtol']:g} + QoI, {dt:.1f} s wall, -O3 -march=native",
+                not_converged=bad)
+    return base, err, done
 
-    done, dt = run(threads, seconds, 0)
-    done1, dt1 = run(1, max(1.0, seconds / 4), done)
-    return dict(value=done / dt, unit="samples/s", cores=threads, kind="oracle",
-                sample=f"{done} lattice samples (shift 0, points 0..{done - 1}) at level "
-                       f"{level} ({w['n0'] << level}^2): direct-sum KL field + CPU FMG + QoI, "
-                       f"{dt:.1f} s wall",
-                single_thread_value=done1 / dt1,
-                single_thread_sample=f"{done1} further samples on one thread, {dt1:.1f} s wall")
+
+def solve_rate(ctx, pts, torch, min_seconds, q=None, sums=None):
+    """Samples/s of repeated solves of one point set (synchronised per call)."""
+    B = ctx.count(pts)
+    ctx.fmg_solve(pts, qoi=q, sums=sums)
+    torch.cuda.synchronize()
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        ctx.fmg_solve(pts, qoi=q, sums=sums)
+        torch.cuda.synchronize()
+        reps += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    return B * reps / (time.perf_counter() - t0)
+
+
+def per_level(m, torch, ctxs, w, dev, min_seconds=0.25, skip_level=None):
+    """Samples/s of each path on every level's own batch (2^26 / n^2 lattice
+    points of shift 0, at most 65536) and the largest relative QoI difference
+    between the paths on it; `skip_level` is measured by the timed steps."""
+    rows = {}
+    for k in range(w["num_levels"]):
+        if k == skip_level:
+            continue
+        n = w["n0"] << k
+        npts = int(min(65536, max(16, (1 << 26) // (n * n))))
+        q, row = {}, dict(samples=npts)
+        for name, c in ctxs.items():
+            p = c.lattice(k, 0, npts, 0, 1)
+            qq = torch.zeros((npts, k + 1, 2), dtype=torch.float64, device=dev)
+            info = c.fmg_solve(p, qoi=qq, want_info=True)
+            row[name] = solve_rate(c, p, torch, min_seconds, q=qq)
+            row[f"{name}_not_converged"] = info["not_converged"]
+            q[name] = qq.cpu().numpy()
+        row["max_rel_diff"] = float(np.max(np.abs(q["mixed"] - q["fp64"]) / np.abs(q["fp64"])))
+        rows[f"{n}^2"] = row
+        log(f"[bench] level {n}^2: mixed {row['mixed']:.0f} fp64 {row['fp64']:.0f} samples/s "
+            f"(x{row['mixed'] / row['fp64']:.2f}), max rel diff {row['max_rel_diff']:.1e}")
+    return rows
+
+
+def latency(m, torch, ctx, w, dev, levels, reps=200):
+    """One-point request latency (ABI call to host-visible sums), p50/p99."""
+    out = {}
+    for k in levels:
+        p = ctx.lattice(k, 0, 1, 3, 4)
+        s3 = torch.zeros((1, 2, k + 1, 2), dtype=torch.float64, device=dev)
+        nrep = reps if k < 7 else max(20, reps // 4)
+        times = []
+        for i in range(nrep + 5):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            ctx.fmg_solve(p, sums=s3)
+            s3.cpu()
+            times.append((time.perf_counter() - ta) * 1e3)
+        t = np.array(times[5:])
+        out[f"{w['n0'] << k}^2"] = [round(float(np.percentile(t, 50)), 3),
+                                    round(float(np.percentile(t, 99)), 3)]
+    return out
+
+
+def headline(m, torch, args):
+    """Mixed vs FP64 on the s = 400 workload at its finest level (1024^2):
+    a step is one batch of points x shifts solved through the whole path
+    (points, field, FMG with every stage refined to rtol, QoI of every level,
+    level-difference sums, their copy to the host and the estimator)."""
+    import synth
+    w = synth.workload("mlqmc_mixed_s400")
+    dev = torch.device("cuda:0")
+    k = w["num_levels"] - 1
+    npts, R = args.points, args.shifts
+    B = npts * R
+    nq = 2
+    ctxs = {}
+    for name, prec in (("mixed", m.MLMC_MIXED), ("fp64", m.MLMC_FP64)):
+        ctxs[name] = m.Context(w["n0"], w["num_levels"], w["s"], w["corr_len"], w["sigma2"],
+                               mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"],
+                               max_iters=w["max_iters"], precision=prec,
+                               qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
+                               genvec=synth.korobov_vector(w["seed"], w["s"]),
+                               shifts=synth.shift_table(w["seed"], w["num_levels"],
+                                                        w["num_shifts"], w["s"]),
+                               max_batch=B, device=0)
+    if not args.no_autotune:
+        ta = time.perf_counter()
+        for c in ctxs.values():
+            c.autotune(k)
+        log(f"[bench] autotune {time.perf_counter() - ta:.2f} s")
+    pts = {name: c.lattice(k, 0, npts, 0, R) for name, c in ctxs.items()}
+    n_per_level = np.zeros(k + 1, dtype=np.int64)
+    n_per_level[k] = npts
+    res = {}
+    for name, c in ctxs.items():
+        qoi = torch.zeros((B, k + 1, nq), dtype=torch.float64, device=dev)
+        sums = torch.zeros((R, nq, k + 1, 2), dtype=torch.float64, device=dev)
+        host_sums = np.zeros((k + 1, R, nq, k + 1, 2))
+        est = {}
+
+        def step(c=c, name=name, qoi=qoi, sums=sums, host_sums=host_sums, est=est):
+            c.fmg_solve(pts[name], qoi=qoi, sums=sums)
+            host_sums[k] = sums.cpu().numpy()          # synchronising device-to-host copy
+            est.update(m.mlmc_estimate(n_per_level, host_sums, R, nq, True))
+
+        info = c.fmg_solve(pts[name], qoi=qoi, want_info=True)
+        log(f"[bench] {name} {B} samples at {w['n0'] << k}^2: not converged "
+            f"{info['not_converged']}, largest residual ratio {info['max_rel_residual']:.2e}, "
+            f"at most {info['max_iters_used']} steps per stage")
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        r = dict(info=info, step=step, qoi=qoi, est=est)
+        if name == "mixed":
+            # kernel-time breakdown of one (untimed) step; the kind with the
+            # most time is the dominant kernel whose roofline is measured live
+            breakdown = {}
+            for kind in KINDS:
+                c.profile_begin(kind)
+                step()
+                pr = c.profile_end()
+                if pr["launches"]:
+                    breakdown[kind] = dict(ms=round(pr["total_ms"], 3), launches=pr["launches"],
+                                           gbs=round(pr["bytes"] / (pr["total_ms"] * 1e-3) / 1e9, 1)
+                                           if pr["total_ms"] > 0 else None,
+                                           tflops=round(pr["flops"] / (pr["total_ms"] * 1e-3) / 1e12, 1)
+                                           if pr["flops"] else None)
+            r["breakdown"] = breakdown
+            r["dominant"] = max(breakdown, key=lambda kk: breakdown[kk]["ms"])
+            c.profile_begin(r["dominant"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        r["elapsed"] = time.perf_counter() - t0
+        if name == "mixed":
+            r["prof"] = c.profile_end()
+        r["value"] = B * args.steps / r["elapsed"]
+        log(f"[bench] {name}: {args.steps} steps in {r['elapsed']:.3f} s -> "
+            f"{r['value']:.1f} samples/s")
+        res[name] = r
+    return w, k, B, ctxs, res, pts
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--points", type=int, default=16,
+                    help="lattice points per shift in one step's batch")
+    ap.add_argument("--shifts", type=int, default=16, help="random shifts in one step's batch")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default pass kinds instead of measuring them first")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-max-samples", type=int, default=64)
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip per-level, latency and CPU-baseline measurements")
+                    help="only the timed steps and their roofline (no per-level table, "
+                         "latency or CPU baseline)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the mixed-vs-FP64 comparison on the s = 400 workload")
-    ap.add_argument("--only-mixed", action="store_true",
-                    help="run only the mixed-vs-FP64 comparison (prints its JSON object)")
+    ap.add_argument("--only-c2", action="store_true",
+                    help="only the FP64 fixed-cycle s = 100 workload at 256^2 (prints its JSON)")
     ap.add_argument("--only-matern", action="store_true",
                     help="only the Matern field families and recycling against smoothness")
     ap.add_argument("--only-methods", action="store_true",
@@ -548,46 +749,19 @@ def main():
         sys.exit(2)
 
     import torch
-    import synth
     import paper_1806_05619_amd as m
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    if args.only_mixed:
-        print(json.dumps(mixed_vs_fp64(m, torch, dev)), flush=True)
-        return
-    if args.only_uneven:
-        print(json.dumps(uneven(m, torch)), flush=True)
-        return
-    if args.only_serving:
-        print(json.dumps(serving(m, torch)), flush=True)
-        return
-    if args.only_methods:
-        print(json.dumps(methods(m, torch)), flush=True)
-        return
-    if args.only_matern:
-        print(json.dumps(dict(matern=matern_fields(m, torch),
-                              recycling=recycling_by_smoothness(m, torch))), flush=True)
-        return
-    w = synth.workload("mlqmc_fp64_s100")
-    k = w["num_levels"] - 1
-    npts = 1 << w["lattice_log2n"]
-    R = w["num_shifts"]
-    B = npts * R
-    nq = 2
-    ctx = make_context(m, w, max_batch=B)
-    pts = ctx.lattice(k, 0, npts, 0, R)
-    sums = torch.zeros((R, nq, k + 1, 2), dtype=torch.float64, device=dev)
-    n_per_level = np.zeros(k + 1, dtype=np.int64)
-    n_per_level[k] = npts
-    host_sums = np.zeros((k + 1, R, nq, k + 1, 2))
-    est = {}
-
-    def step():
-        ctx.fmg_solve(pts, sums=sums)
-        host_sums[k] = sums.cpu().numpy()          # synchronising device-to-host copy
-        est.update(m.mlmc_estimate(n_per_level, host_sums, R, nq, True))
-
+    for flag, fn in ((args.only_uneven, lambda: uneven(m, torch)),
+                     (args.only_serving, lambda: serving(m, torch)),
+                     (args.only_methods, lambda: methods(m, torch)),
+                     (args.only_c2, lambda: fp64_fixed_c2(m, torch, args)),
+                     (args.only_matern, lambda: dict(matern=matern_fields(m, torch),
+                                                     recycling=recycling_by_smoothness(m, torch)))):
+        if flag:
+            print(json.dumps(fn()), flush=True)
+            return
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -595,126 +769,65 @@ def main():
         torch.cuda.synchronize()
         log("[bench] copy calibration: 1 GiB read + 1 GiB written")
         del src, dst
-    tune = None
-    if not args.no_autotune:
-        # pass kinds of the tile grids measured on this device (setup, untimed)
-        ta = time.perf_counter()
-        table = ctx.autotune(k)
-        tune = dict(seconds=time.perf_counter() - ta,
-                    measured=[[e["n"], e["batch_class"], KIND_NAMES[e["pre"]], KIND_NAMES[e["post"]],
-                               round(e["pre_ms"], 4), round(e["post_ms"], 4)]
-                              for e in table if e["pre_ms"] > 0])
-        log(f"[bench] autotune {tune['seconds']:.2f} s")
-    log(f"[bench] workload mlqmc_fp64_s100 level {k}: {B} samples, warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
 
-    # kernel-time breakdown of one (untimed) step; the kind with the most time
-    # is the dominant kernel whose roofline is measured over the timed steps
-    breakdown = {}
-    for kind in KINDS:
-        ctx.profile_begin(kind)
-        step()
-        r = ctx.profile_end()
-        if r["launches"]:
-            breakdown[kind] = dict(ms=r["total_ms"], launches=r["launches"],
-                                   gbs=r["bytes"] / (r["total_ms"] * 1e-3) / 1e9 if r["total_ms"] > 0 else None,
-                                   tflops=r["flops"] / (r["total_ms"] * 1e-3) / 1e12 if r["flops"] else None)
-    dominant = max(breakdown, key=lambda kk: breakdown[kk]["ms"])
-
-    ctx.profile_begin(dominant)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = ctx.profile_end()
-    elapsed = t1 - t0
-    value = B * args.steps / elapsed
-    log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s -> {value:.1f} samples/s")
-
+    w, k, B, ctxs, res, pts = headline(m, torch, args)
+    mixed, fp64 = res["mixed"], res["fp64"]
+    prof, dominant = mixed["prof"], mixed["dominant"]
     avg_ms = prof["total_ms"] / max(prof["launches"], 1)
     bytes_per_launch = prof["bytes"] / max(prof["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic, traffic_src = measured_traffic(dominant)
-    roofline = dict(kernel=KERNEL_NAMES[dominant], bound="hbm",
-                    achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=traffic, traffic_source=traffic_src,
-                    avg_launch_ms=avg_ms, launches_per_step=prof["launches"] / args.steps,
-                    algorithmic_bytes_per_launch=bytes_per_launch,
-                    share_of_step=prof["total_ms"] / (elapsed * 1e3))
-
-    out = dict(metric=METRIC, value=value, unit="samples/s", n_gpus=1, steps=args.steps,
-               warmup=args.warmup, ms_per_step=elapsed * 1e3 / args.steps,
-               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+    qm, qf = mixed["qoi"].cpu().numpy(), fp64["qoi"].cpu().numpy()
+    diff = np.abs(qm - qf) / np.abs(qf)
+    n = w["n0"] << k
+    out = dict(metric=METRIC, value=round(mixed["value"], 2), unit="samples/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup,
+               ms_per_step=round(mixed["elapsed"] * 1e3 / args.steps, 3),
+               higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="mixed: bf16 digit products (field), f32 V-cycles, f64 refinement and sums",
                data="synthetic",
-               config=dict(workload="mlqmc_fp64_s100: MLQMC FP64, lognormal KL field "
-                                    "(separable exponential, lambda 0.3, sigma 1, s = 100), "
-                                    "FMG 2 x V(2,2) from 2^2, finest level 256^2 "
-                                    "(MLMC levels 4^2..256^2), 2^10 Korobov lattice points "
-                                    "x 16 shifts = 16384 samples per step, QoI mean(u) and "
-                                    "u(1/2,1/2)",
-                           samples_per_step=B, level=k, finest_grid=f"{w['n0'] << k}^2",
-                           precision="fp64"),
-               roofline=roofline, mixed=None,
-               estimate=dict(q_bar=float(est["q_bar"][0]), std=float(np.sqrt(est["var_q"][0]))))
-
-    out["kernel_breakdown_one_step"] = breakdown
-    out["autotune"] = tune
+               config=dict(workload=f"mlqmc_mixed_s400 at {n}^2: s = 400, lambda 0.1, sigma^2 2, "
+                                    f"MLMC levels 4^2..{n}^2, every FMG stage to rtol 1e-10",
+                           samples_per_step=B, points=args.points, shifts=args.shifts,
+                           level=k),
+               fp64_value=round(fp64["value"], 2),
+               ratio_mixed_over_fp64=round(mixed["value"] / fp64["value"], 3),
+               max_rel_diff_mixed_fp64_per_level=[float(f"{v:.1e}") for v in
+                                                  diff.max(axis=(0, 2))],
+               not_converged=dict(mixed=mixed["info"]["not_converged"],
+                                  fp64=fp64["info"]["not_converged"]),
+               roofline=dict(kernel=KERNEL_NAMES[dominant], bound="hbm",
+                             achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                             frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                             traffic_source=traffic_src, avg_launch_ms=round(avg_ms, 4),
+                             launches_per_step=prof["launches"] / args.steps,
+                             algorithmic_bytes_per_launch=round(bytes_per_launch),
+                             byte_model=BYTE_MODEL[dominant],
+                             share_of_step=round(prof["total_ms"] / (mixed["elapsed"] * 1e3), 3)),
+               estimate=dict(q_bar=float(mixed["est"]["q_bar"][0]),
+                             std=float(np.sqrt(mixed["est"]["var_q"][0]))))
+    log("[bench] breakdown of one mixed step: " + json.dumps(mixed["breakdown"]))
     if not args.no_extras:
-        # samples/s per level, same batch size (16384 samples finest at each level)
-        per_level = {}
-        for lev in range(k + 1):
-            p = ctx.lattice(lev, 0, npts, 0, R)
-            s2 = torch.zeros((R, nq, lev + 1, 2), dtype=torch.float64, device=dev)
-            ctx.fmg_solve(p, sums=s2)
-            torch.cuda.synchronize()
-            reps = 3
-            ta = time.perf_counter()
-            for _ in range(reps):
-                ctx.fmg_solve(p, sums=s2)
-                s2.cpu()
-            torch.cuda.synchronize()
-            per_level[f"{w['n0'] << lev}^2"] = B * reps / (time.perf_counter() - ta)
-        out["samples_per_s_per_level"] = per_level
-        # request latency: one (level, lattice range, shift) call, from the ABI
-        # call to host-visible sums, per level and request size
-        lat = {}
-        for lev in range(k + 1):
-            for nreq in (1, 64, 1024):
-                p = ctx.lattice(lev, 0, nreq, 3, 4)
-                s3 = torch.zeros((1, nq, lev + 1, 2), dtype=torch.float64, device=dev)
-                reps = 1000 if nreq * 4 ** lev <= 64 * 4 ** 6 else 200
-                times = []
-                for i in range(reps + 10):
-                    torch.cuda.synchronize()
-                    ta = time.perf_counter()
-                    ctx.fmg_solve(p, sums=s3)
-                    s3.cpu()
-                    times.append((time.perf_counter() - ta) * 1e3)
-                times = np.array(times[10:])
-                lat[f"level{lev}_{w['n0'] << lev}^2_n{nreq}"] = dict(
-                    p50_ms=float(np.percentile(times, 50)), p99_ms=float(np.percentile(times, 99)),
-                    repeats=reps)
-        log("[bench] latency 256^2: " + ", ".join(
-            f"n{q} {lat[f'level{k}_256^2_n{q}']['p50_ms']:.2f}/{lat[f'level{k}_256^2_n{q}']['p99_ms']:.2f} ms"
-            for q in (1, 64, 1024)))
-        out["latency"] = lat
-        out["serving"] = serving(m, torch)
-        out["methods"] = methods(m, torch)
-        out["matern"] = matern_fields(m, torch)
-        out["recycling_by_smoothness"] = recycling_by_smoothness(m, torch)
-        if not args.no_mixed:
-            del ctx
-            torch.cuda.empty_cache()
-            out["uneven"] = uneven(m, torch)
-            torch.cuda.empty_cache()
-            out["mixed"] = mixed_vs_fp64(m, torch, dev)
-        log("[bench] extras done; CPU baseline ...")
-        out["cpu_baseline"] = cpu_baseline(w, k, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+        lv = per_level(m, torch, ctxs, w, dev, skip_level=k)
+        lv[f"{n}^2"] = dict(samples=B, mixed=mixed["value"], fp64=fp64["value"],
+                            max_rel_diff=float(diff.max()))
+        out["per_level"] = {key: [round(r["mixed"]), round(r["fp64"]),
+                                  round(r["mixed"] / r["fp64"], 2),
+                                  float(f"{r['max_rel_diff']:.1e}")] for key, r in lv.items()}
+        out["per_level_columns"] = "mixed samples/s, fp64 samples/s, ratio, max rel diff"
+        out["latency_p50_p99_ms"] = latency(m, torch, ctxs["mixed"], w, dev, (0, 4, 8))
+        # points of the step's batch, for the oracle (y = Phi^-1 of the lattice points)
+        y = torch.zeros((B, w["s"]), dtype=torch.float64, device=dev)
+        ctxs["mixed"].points_gen(pts["mixed"], y=y)
+        y = y.cpu().numpy()
+        del ctxs, res
+        torch.cuda.empty_cache()
+        log("[bench] CPU baseline (oracle) ...")
+        base, err, ns = oracle_baseline(w, k, y, dict(mixed=qm, fp64=qf), args.cpu_seconds,
+                                        args.cpu_max_samples)
+        out["cpu_baseline"] = base
+        out["max_rel_err_vs_oracle_per_level"] = dict(samples=ns, **err)
+    print(json.dumps(out, separators=(",", ":")), flush=True)
 
 
 if __name__ == "__main__":

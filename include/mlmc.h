@@ -181,9 +181,10 @@ mlmc_status mlmc_points_gen(mlmc_ctx ctx, const mlmc_points *pts,
  * (sample-major, levels in order).  FP64 context: FP64 product on the matrix
  * cores.  MIXED context: the product the MIXED solve uses, with every sample
  * row of Y and every cell column of the basis scaled by a power of two
- * 2^E > max |entry| and written as four bf16 digits, ten digit products on the
- * matrix cores summed exactly and folded into FP64; |error| <= 5 s
- * 2^(E_y + E_b - 32) per cell, without rounding bias, returned as double. */
+ * 2^E > max |entry| and written as five bf16 digits, the fifteen digit
+ * products of weight 2^0 .. 2^-32 on the matrix cores summed exactly and
+ * folded into FP64; |error| <= 2 s 2^(E_y + E_b - 38) per cell, without
+ * rounding bias, returned as double. */
 mlmc_status mlmc_field(mlmc_ctx ctx, const mlmc_points *pts, double *z_dev,
                        void *hip_stream);
 
@@ -375,6 +376,14 @@ typedef struct {
                                        request in lattice order (shift-major);
                                        caller-owned, written before the result
                                        is reported, kept valid until then */
+    double *sums_out;               /* host [shift_end-shift_begin][nq][level+1][2]
+                                       or NULL: per shift of the request, the
+                                       compensated FP64 sums of F_l - F_{l-1}
+                                       and of its square over its samples
+                                       (Section 3.2, eq. Upsilon-reuse; F_{-1} =
+                                       0), bitwise those mlmc_fmg_solve returns
+                                       for the same points in one chunk; same
+                                       lifetime as qoi_out */
 } mlmc_request;
 
 typedef struct {
@@ -385,6 +394,11 @@ typedef struct {
     int64_t batch_samples;          /* samples of the batch it was solved in */
     double queued_ms;               /* submit -> its batch starts */
     double latency_ms;              /* submit -> QoIs on the host */
+    int64_t not_converged;          /* rtol mode: samples of the request with a
+                                       stage that stopped above rtol (then
+                                       status is MLMC_E_NOCONV, outputs written) */
+    double max_rel_residual;        /* rtol mode: largest final ||f-Au||/||f||
+                                       of the request's samples; -1 otherwise */
 } mlmc_result;
 
 typedef struct {
@@ -406,7 +420,9 @@ mlmc_status mlmc_server_create(const mlmc_config *cfg, int device, int32_t num_s
 mlmc_status mlmc_server_destroy(mlmc_server srv);
 /* Thread-safe, non-blocking.  E_INVAL (nothing queued) for a bad range, a
  * level outside the configuration, more samples than a slot holds at that
- * level, or a NULL qoi_out. */
+ * level, or a NULL qoi_out.  Every batch is solved with per-sample
+ * convergence flags, so a request's result reports its unconverged samples
+ * (rtol mode) with status MLMC_E_NOCONV. */
 mlmc_status mlmc_server_submit(mlmc_server srv, const mlmc_request *req);
 /* Up to max_results completed results, oldest first; waits up to wait_ms for
  * the first one (0: no wait).  *count receives the number written. */

@@ -23,6 +23,7 @@ from .estimators import (  # noqa: F401  (re-exported)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _lib = None
+_variant = "default"
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -30,12 +31,27 @@ _u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
 _u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 
 
+def select_build(variant: str) -> None:
+    """Choose the oracle build before its first use: "default" (-O2, the
+    tests) or "fast" (-O3 -march=native, the timed CPU baseline); the source
+    and arithmetic are the same."""
+    global _variant
+    if variant not in _build.OPT:
+        raise ValueError(variant)
+    if _lib is not None and variant != _variant:
+        raise RuntimeError("the oracle library is already loaded")
+    if variant == "fast" and _lib is None:
+        # -march=native: compile for the host that runs it, not the one that built the tree
+        _build.build(force=True, variant="fast")
+    _variant = variant
+
+
 def lib():
     """Load (building first if stale) the oracle shared library."""
     global _lib
     if _lib is not None:
         return _lib
-    path = _build.build(force=False)
+    path = _build.build(force=False, variant=_variant)
     L = C.CDLL(path)
     L.oracle_bitrev32.restype = C.c_uint32
     L.oracle_bitrev32.argtypes = [C.c_uint32]

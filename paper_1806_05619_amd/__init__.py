@@ -80,13 +80,14 @@ class mlmc_est_output(C.Structure):
 class mlmc_request(C.Structure):
     _fields_ = [("level", C.c_int32), ("shift_begin", C.c_int32), ("shift_end", C.c_int32),
                 ("n_begin", C.c_int64), ("n_end", C.c_int64), ("tag", C.c_uint64),
-                ("qoi_out", C.c_void_p)]
+                ("qoi_out", C.c_void_p), ("sums_out", C.c_void_p)]
 
 
 class mlmc_result(C.Structure):
     _fields_ = [("tag", C.c_uint64), ("status", C.c_int32), ("level", C.c_int32),
                 ("samples", C.c_int64), ("batch_samples", C.c_int64),
-                ("queued_ms", C.c_double), ("latency_ms", C.c_double)]
+                ("queued_ms", C.c_double), ("latency_ms", C.c_double),
+                ("not_converged", C.c_int64), ("max_rel_residual", C.c_double)]
 
 
 class mlmc_server_stats(C.Structure):
@@ -362,9 +363,11 @@ class Server:
         self._next_tag = 0
         self._lock = threading.RLock()
 
-    def submit(self, level, n_begin, n_end, shift_begin=0, shift_end=1, tag=None):
+    def submit(self, level, n_begin, n_end, shift_begin=0, shift_end=1, tag=None, sums=False):
         """Queue lattice points [n_begin, n_end) of shifts [shift_begin,
-        shift_end) on finest level `level`; returns the request's tag."""
+        shift_end) on finest level `level`; returns the request's tag.  With
+        sums=True the result also carries the per-shift level-difference sums
+        [shift_end - shift_begin][nq][level+1][2] formed by the library."""
         with self._lock:
             if tag is None:
                 tag = self._next_tag
@@ -374,25 +377,31 @@ class Server:
             self._next_tag = max(self._next_tag, tag + 1)
             B = max(0, (int(n_end) - int(n_begin)) * (int(shift_end) - int(shift_begin)))
             out = np.zeros((B, int(level) + 1, self.nq), dtype=np.float64)
+            so = (np.zeros((max(0, int(shift_end) - int(shift_begin)), self.nq, int(level) + 1, 2))
+                  if sums else None)
             req = mlmc_request(int(level), int(shift_begin), int(shift_end), int(n_begin),
-                               int(n_end), tag, out.ctypes.data if B else None)
+                               int(n_end), tag, out.ctypes.data if B else None,
+                               so.ctypes.data if so is not None and so.size else None)
             _check(lib().mlmc_server_submit(self._h, C.byref(req)))
-            self._pending[tag] = out
+            self._pending[tag] = (out, so)
             return tag
 
     def poll(self, max_results=256, wait_ms=0):
-        """Completed requests, oldest first: dicts with the result fields and
-        'qoi' (the request's array)."""
+        """Completed requests, oldest first: dicts with the result fields,
+        'qoi' (the request's array) and 'sums' (None unless requested)."""
         buf = (mlmc_result * max(1, int(max_results)))()
         n = C.c_int32(0)
         _check(lib().mlmc_server_poll(self._h, buf, int(max_results), int(wait_ms), C.byref(n)))
         res = []
         with self._lock:
             for r in buf[: n.value]:
+                qoi, sums = self._pending.pop(int(r.tag))
                 res.append(dict(tag=int(r.tag), status=int(r.status), level=int(r.level),
                                 samples=int(r.samples), batch_samples=int(r.batch_samples),
                                 queued_ms=r.queued_ms, latency_ms=r.latency_ms,
-                                qoi=self._pending.pop(int(r.tag))))
+                                not_converged=int(r.not_converged),
+                                max_rel_residual=float(r.max_rel_residual),
+                                qoi=qoi, sums=sums))
                 self._lat.append(r.latency_ms)
         return res
 

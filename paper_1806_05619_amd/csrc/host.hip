@@ -33,8 +33,8 @@ struct mlmc_ctx_s {
     uint64_t *d_shifts = nullptr;
     double *d_basis = nullptr;   // [s][Mmax]
     // mixed mode: bf16 digit arrays [rows_pad][sp] and per-row scale exponents
-    uint16_t *d_bdig[4] = {};    // basis, rows = field columns (Mpad)
-    uint16_t *d_ydig[4] = {};    // a chunk's Y, rows = samples (chunk_pad)
+    uint16_t *d_bdig[kDigits] = {};    // basis, rows = field columns (Mpad)
+    uint16_t *d_ydig[kDigits] = {};    // a chunk's Y, rows = samples (chunk_pad)
     int32_t *d_bexp = nullptr, *d_yexp = nullptr;
     int sp = 0;                  // s rounded up to the matrix-core K step
     double *d_a64 = nullptr;     // mixed mode: FP64 copy of the a pool (CG operator)
@@ -364,8 +364,11 @@ struct Runner {
 struct StageStats {
     int max_iters = 0;
     double max_rho = -1.0;
-    int64_t noconv = 0;            // samples with any stage stopped at max_iters
+    int64_t noconv = 0;            // samples with any stage stopped above rtol
     std::vector<uint8_t> bad;      // per sample of the current chunk
+    int32_t *sample_bad = nullptr; // optional host [B]: per-sample flag of the whole call
+    double *sample_rho = nullptr;  // optional host [B]: per-sample largest final ratio
+    int64_t b0 = 0;                // first sample of the current chunk
 };
 
 // FMG for one chunk; qoi rows of the chunk at qoi [Bc][k+1][nq].
@@ -653,6 +656,8 @@ mlmc_status run_fmg_refine(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k,
             stats->max_iters = std::max(stats->max_iters, (int)c->h_iters[b]);
             stats->max_rho = std::max(stats->max_rho, c->h_rho[b]);
             stats->noconv += c->h_active[b] != 0;
+            if (stats->sample_bad) stats->sample_bad[stats->b0 + b] = c->h_active[b] != 0;
+            if (stats->sample_rho) stats->sample_rho[stats->b0 + b] = c->h_rho[b];
         }
     }
     return MLMC_OK;
@@ -847,7 +852,7 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
                              Gmax > (c.rtol > 0.0 ? kLdsMaxLevel : kLdsMaxLevelFixed);
     const size_t own_tables = parent ? 0 : 1;
     size_t need = (size_t)ctx->elem * (tile_levels ? 4 : 3) * (size_t)ctx->pool +
-                  (8 * (size_t)ctx->sp + 4) * (size_t)(own_tables * brows + yrows) +
+                  (2 * kDigits * (size_t)ctx->sp + 4) * (size_t)(own_tables * brows + yrows) +
                   8 * (size_t)a64 +
                   sizeof(double) * (own_tables * (size_t)s * ctx->Mmax + 4 * ctx->fcg_cells + parts + wcap +
                                     (size_t)ctx->chunk_max * (s + c.num_levels * ctx->nq + 6) +
@@ -872,7 +877,7 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
         ctx->d_u = (double *)pu;
         ctx->d_f = (double *)pf;
     }
-    for (int i = 0; i < 4 && mixed; ++i) {
+    for (int i = 0; i < kDigits && mixed; ++i) {
         if (!parent) CHK(dev_alloc(ctx, &ctx->d_bdig[i], brows * ctx->sp));
         CHK(dev_alloc(ctx, &ctx->d_ydig[i], yrows * ctx->sp));
     }
@@ -912,7 +917,7 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
             std::memcpy(ctx->post_ms, parent->post_ms, sizeof(ctx->post_ms));
         }
         ctx->d_basis = parent->d_basis;
-        for (int i = 0; i < 4; ++i) ctx->d_bdig[i] = parent->d_bdig[i];
+        for (int i = 0; i < kDigits; ++i) ctx->d_bdig[i] = parent->d_bdig[i];
         ctx->d_bexp = parent->d_bexp;
         ctx->d_z = parent->d_z;
         ctx->d_shifts = parent->d_shifts;
@@ -1258,6 +1263,16 @@ mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts, const double *z
                            double *qoi_dev, double *sums_dev, mlmc_solve_info *info,
                            void *hip_stream)
 {
+    return mlmc::fmg_solve_ex(ctx, pts, z_dev, qoi_dev, sums_dev, info, hip_stream, nullptr,
+                              nullptr);
+}
+
+}  // extern "C"
+
+mlmc_status mlmc::fmg_solve_ex(mlmc_ctx ctx, const mlmc_points *pts, const double *z_dev,
+                               double *qoi_dev, double *sums_dev, mlmc_solve_info *info,
+                               void *hip_stream, int32_t *sample_bad, double *sample_rho)
+{
     if (!ctx) return MLMC_E_INVAL;
     if (ctx->broken || ctx->host_only) return MLMC_E_STATE;
     int64_t B, npts;
@@ -1272,8 +1287,15 @@ mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts, const double *z
     const int64_t ntup = (int64_t)nsh * nq * nlev;
     if (sums_dev) launch_fill(s, ctx->d_state, 4 * ntup, 0.0);
     StageStats stats;
+    stats.sample_bad = sample_bad;
+    stats.sample_rho = sample_rho;
+    if (sample_bad) std::fill(sample_bad, sample_bad + B, 0);
+    if (sample_rho) std::fill(sample_rho, sample_rho + B, -1.0);
+    mlmc_solve_info local_info;
+    if (!info && (sample_bad || sample_rho)) info = &local_info;
     for (int64_t b0 = 0; b0 < B; b0 += cap) {
         const int64_t Bc = std::min(cap, B - b0);
+        stats.b0 = b0;
         Hier h = make_hier(ctx, G, Bc);
         const bool mixed = ctx->cfg.precision == MLMC_MIXED;
         if (z_dev) {
@@ -1286,11 +1308,11 @@ mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts, const double *z
             }
             const double sd = ctx->cfg.s;
             if (mixed) {
-                // ten bf16 digit products per term; operands 4 x 2 bytes, a stored
-                // as float and double
+                // fifteen bf16 digit products per term; operands 5 x 2 bytes, a
+                // stored as float and double
                 ProfScope ps(ctx, s, MLMC_KERNEL_FIELD,
-                             8.0 * Bc * sd + 8.0 * (Bc + (double)M) * sd + 12.0 * Bc * M,
-                             20.0 * Bc * sd * M);
+                             8.0 * Bc * sd + 2.0 * kDigits * (Bc + (double)M) * sd + 12.0 * Bc * M,
+                             30.0 * Bc * sd * M);
                 field_digits(ctx, s, Y, M, Bc, ctx->d_a, ctx->d_a64, 2);
             } else {
                 ProfScope ps(ctx, s, MLMC_KERNEL_FIELD, 8.0 * (Bc * sd + sd * M + (double)Bc * M),
@@ -1328,6 +1350,8 @@ mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts, const double *z
     }
     return MLMC_OK;
 }
+
+extern "C" {
 
 mlmc_status mlmc_kl_modes(mlmc_ctx ctx, int32_t *i_out, int32_t *j_out, double *theta_out)
 {
@@ -1457,9 +1481,19 @@ mlmc_status mlmc_estimate(const mlmc_est_input *in, mlmc_est_output *out)
                 int64_t N = in->n_per_level[l];
                 double vl = nan;
                 if (N > 1) {
-                    double s1 = S(l, 0, q, l, 0), s2 = S(l, 0, q, l, 1);
-                    double var = (s2 - s1 * s1 / (double)N) / (double)(N - 1);
-                    vl = var / (double)N;
+                    // (s2 - s1^2/N) / (N-1) with s1^2/N carried to about one
+                    // rounding: m = s1/N with its exact remainder s1 - m N,
+                    // s1 m split into its rounded value and exact error (fma),
+                    // so that only the cancellation against s2 is left, and
+                    // that subtraction is exact when the two are close
+                    const double s1 = S(l, 0, q, l, 0), s2 = S(l, 0, q, l, 1);
+                    const double Nd = (double)N;
+                    const double m = s1 / Nd;
+                    const double rem = std::fma(-m, Nd, s1);
+                    const double p = s1 * m;
+                    const double perr = std::fma(s1, m, -p);
+                    const double num = ((s2 - p) - perr) - s1 * (rem / Nd);
+                    vl = std::max(num, 0.0) / (Nd - 1.0) / Nd;
                 }
                 out->var_level[(int64_t)q * L1 + l] = vl;
                 v.add(vl);

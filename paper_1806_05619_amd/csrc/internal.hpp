@@ -16,6 +16,13 @@ namespace mlmc {
 mlmc_status create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent, mlmc_ctx *out);
 // samples of finest MLMC level k that one pass over the workspace holds
 int64_t level_capacity(mlmc_ctx c, int k);
+// mlmc_fmg_solve, and per sample (host arrays of B entries, either may be
+// NULL): sample_bad[b] = 1 if a stage of sample b stopped above rtol,
+// sample_rho[b] = the largest final residual ratio of its stages (-1 with
+// fixed cycles).  Asking for either synchronises the stream, as info does.
+mlmc_status fmg_solve_ex(mlmc_ctx ctx, const mlmc_points *pts, const double *z_dev,
+                         double *qoi_dev, double *sums_dev, mlmc_solve_info *info,
+                         void *hip_stream, int32_t *sample_bad, double *sample_rho);
 
 constexpr int kMaxMgLevels = 12;   // n_g = 2^(g+1) <= 4096
 constexpr int kBlock = 256;
@@ -66,22 +73,23 @@ void launch_field_gemm(hipStream_t st, const double *Y, int s, const double *bas
 void launch_exp_to_levels(hipStream_t st, const double *z, int64_t M, int64_t Bc, void *pool,
                           bool to_float, double *pool64);
 
-// Mixed-precision field on the matrix cores: operands as four bf16 digit
+// Mixed-precision field on the matrix cores: operands as kDigits bf16 digit
 // arrays [rows_pad][sp] (bf16 bit patterns as uint16_t, zero padded) with a
 // power-of-two scale exponent per row; exact FP32 group sums folded in FP64.
 // mode 0 writes z (double) to out[b*M + m]; mode 2 writes exp(z) as float into
 // the level-major pool out and as double into out64.
+constexpr int kDigits = 5;
 int64_t mixed_pad_rows(int64_t rows);
 int64_t mixed_pad_cols(int64_t cols);
 int mixed_pad_k(int s);
 // rows with unit mode stride: element (r, k) at X[r*rs + k], one wavefront per row
 void launch_digits_rows(hipStream_t st, const double *X, int64_t rows, int cols, int64_t rs,
-                        int64_t rows_pad, int sp, uint16_t *const D[4], int32_t *E);
+                        int64_t rows_pad, int sp, uint16_t *const D[kDigits], int32_t *E);
 // rows at unit stride, modes at stride ks: element (r, k) at X[r + k*ks]
 void launch_digits_cols(hipStream_t st, const double *X, int64_t rows, int cols, int64_t ks,
-                        int64_t rows_pad, int sp, uint16_t *const D[4], int32_t *E);
-void launch_field_digits(hipStream_t st, uint16_t *const Y[4], const int32_t *EY,
-                         uint16_t *const Bs[4], const int32_t *EB, int sp, int64_t M, int64_t Bc,
+                        int64_t rows_pad, int sp, uint16_t *const D[kDigits], int32_t *E);
+void launch_field_digits(hipStream_t st, uint16_t *const Y[kDigits], const int32_t *EY,
+                         uint16_t *const Bs[kDigits], const int32_t *EB, int sp, int64_t M, int64_t Bc,
                          void *out, double *out64, int mode);
 
 void launch_coarse_solve(hipStream_t st, const double *a, const double *f, double *u, int64_t Bc,
@@ -103,6 +111,10 @@ void launch_fill_i32(hipStream_t st, int32_t *p, int64_t count, int32_t v);
 void launch_sums(hipStream_t st, const double *qoi, int nlev, int nq, int64_t b0, int64_t Bc,
                  int64_t npts, int nshift, double *state);
 void launch_sums_final(hipStream_t st, const double *state, int64_t count, double *out);
+// level-difference sums of nseg segments (first sample, count) of qoi
+// [B][nlev][nq] into out [nseg][nq][nlev][2]; seg is a device array
+void launch_seg_sums(hipStream_t st, const double *qoi, int nlev, int nq, const int64_t *seg,
+                     int64_t nseg, double *out);
 
 // ---- fused kernels (kernels_fused.hip), T = double or float ----
 bool fused_supported(int mu1, int mu2);

@@ -462,6 +462,42 @@ __global__ __launch_bounds__(256) void k_sums(const double *__restrict__ qoi, in
     }
 }
 
+// Level-difference sums of segments of a QoI table (Section 3.2, eq.
+// Upsilon-reuse): segment t covers samples seg[2t] .. seg[2t] + seg[2t+1] - 1
+// of qoi [B][nlev][nq]; out [nseg][nq][nlev][2] receives the compensated sums
+// of F_l - F_{l-1} and of its square.  One wavefront per (segment, q, l); a
+// lane sums the samples lane, lane + 64, ... of its segment, as k_sums does
+// for a shift of one chunk, so a segment's sums do not depend on what else
+// the table holds.
+__global__ __launch_bounds__(256) void k_seg_sums(const double *__restrict__ qoi, int nlev, int nq,
+                                                  const int64_t *__restrict__ seg, int64_t nseg,
+                                                  double *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t tuple = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    if (tuple >= nseg * nq * nlev)
+        return;
+    const int l = (int)(tuple % nlev);
+    const int q = (int)((tuple / nlev) % nq);
+    const int64_t t = tuple / ((int64_t)nlev * nq);
+    const int64_t lo = seg[2 * t], hi = lo + seg[2 * t + 1];
+    Comp k1{0.0, 0.0}, k2{0.0, 0.0};
+    for (int64_t b = lo + lane; b < hi; b += 64) {
+        const double *qb = qoi + b * nlev * nq;
+        double d = qb[l * nq + q] - (l > 0 ? qb[(l - 1) * nq + q] : 0.0);
+        comp_add(k1, d);
+        comp_add(k2, d * d);
+    }
+    k1 = wave_reduce(k1);
+    k2 = wave_reduce(k2);
+    if (lane == 0) {
+        const Comp a1 = comp_merge(Comp{0.0, 0.0}, k1);
+        const Comp a2 = comp_merge(Comp{0.0, 0.0}, k2);
+        out[2 * tuple] = a1.s + a1.c;
+        out[2 * tuple + 1] = a2.s + a2.c;
+    }
+}
+
 __global__ void k_sums_final(const double *__restrict__ state, int64_t count,
                              double *__restrict__ out)
 {
@@ -576,6 +612,16 @@ void launch_sums(hipStream_t st, const double *qoi, int nlev, int nq, int64_t b0
     int64_t ntup = (int64_t)nshift * nq * nlev;
     hipLaunchKernelGGL(k_sums, dim3(blocks_for(ntup, kBlock / 64)), dim3(kBlock), 0, st, qoi, nlev,
                        nq, b0, Bc, npts, nshift, state);
+}
+
+void launch_seg_sums(hipStream_t st, const double *qoi, int nlev, int nq, const int64_t *seg,
+                     int64_t nseg, double *out)
+{
+    const int64_t ntup = nseg * nq * nlev;
+    if (ntup <= 0)
+        return;
+    hipLaunchKernelGGL(k_seg_sums, dim3(blocks_for(ntup, kBlock / 64)), dim3(kBlock), 0, st, qoi,
+                       nlev, nq, seg, nseg, out);
 }
 
 void launch_sums_final(hipStream_t st, const double *state, int64_t count, double *out)

@@ -3,19 +3,21 @@
 //
 // Each row of Y (one sample, over the KL modes) and each field column of the
 // basis (one cell centre, over the modes) gets a power-of-two scale 2^E with
-// 2^E > max |x|; x 2^(7-E) is then written as four balanced base-256 digits,
-// x 2^(7-E) = d1 + d2 2^-8 + d3 2^-16 + d4 2^-24 + rest, |d| <= 128, |rest| <=
-// 2^-25.  Every digit is an integer of at most 8 bits, so it is exact in bf16,
-// every digit product is an integer below 2^14, and a sum of up to 256 of them
-// per group stays below 2^24: the FP32 accumulation of v_mfma_f32_16x16x32_bf16
-// is exact whatever its internal rounding.  The products are grouped by weight
-// (G0 = d1 e1; G1 = d1 e2 + d2 e1; G2 = d1 e3 + d3 e1 + d2 e2; G3 = d1 e4 + d4 e1
-// + d2 e3 + d3 e2; ten MFMAs per tile), and every 256 modes the groups are
-// folded exactly into FP64 accumulators.  The result is z times 2^(14 - E_r -
-// E_c) up to the dropped digit products of weight 2^-32 and the digit
-// remainders, about 2^-31 relative to max |y| max |b| per mode.  This is the
-// Ozaki splitting (Ozaki, Ogita, Oishi, Rump, Numer. Algorithms 59, 2012) with
-// fixed-point digits sized for bf16 matrix cores.
+// 2^E > max |x|; x 2^(7-E) is then written as five balanced base-256 digits,
+// x 2^(7-E) = d1 + d2 2^-8 + d3 2^-16 + d4 2^-24 + d5 2^-32 + rest, |d| <= 128,
+// |rest| <= 2^-33.  Every digit is an integer of at most 8 bits, so it is
+// exact in bf16, every digit product is an integer of magnitude at most 2^14,
+// and a group of up to five products of equal weight summed over 192 modes
+// stays below 2^24: the FP32 accumulation of v_mfma_f32_16x16x32_bf16 is exact
+// whatever its internal rounding.  The products of weight 2^-8w, w = 0..4, are
+// grouped (G_w = sum over i + j = w of d_(i+1) e_(j+1); fifteen MFMAs per
+// tile), and every 192 modes the groups are folded into FP64 accumulators
+// (rounding at 2^-53 of the group scale).  The result is z times 2^(14 - E_r
+// - E_c) up to the dropped products (weight 2^-40 and below) and the digit
+// remainders: at most 2 s 2^(E_y + E_b - 38) per cell for s modes, with 2^E_y
+// and 2^E_b the row and column scales.  This is the Ozaki splitting (Ozaki,
+// Ogita, Oishi, Rump, Numer. Algorithms 59, 2012) with fixed-point digits
+// sized for bf16 matrix cores.
 //
 // Operands are stored K-contiguous ([rows_pad][sp], sp = s rounded up to 32,
 // zero padded) so that each lane loads its 8 consecutive k values as one
@@ -31,7 +33,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int WM = 32, WN = 32;        // tile of one wave: 2 x 2 MFMA tiles
 constexpr int BM = 64, BN = 64;        // tile of a 4-wave block (2 x 2 waves)
-constexpr int KFOLD = 8;               // K steps of 32 between folds into FP64
+constexpr int KFOLD = 6;               // K steps of 32 between folds into FP64
+constexpr int ND = kDigits;            // digits per operand
+constexpr int NP = ND * (ND + 1) / 2;  // digit products of weight 2^-8w, w < ND
 
 // the bf16 bit pattern of an integer d with |d| <= 256 (exact)
 __device__ __forceinline__ uint16_t bf16_of_int(double d)
@@ -40,11 +44,11 @@ __device__ __forceinline__ uint16_t bf16_of_int(double d)
 }
 
 // digits of x 2^(7-E), E the row scale
-__device__ __forceinline__ void digits4(double x, int E, uint16_t *d)
+__device__ __forceinline__ void digits(double x, int E, uint16_t *d)
 {
     double t = ldexp(x, 7 - E);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < ND; ++q) {
         const double v = rint(t);
         d[q] = bf16_of_int(v);
         t = (t - v) * 256.0;             // exact: |t - v| <= 1/2 has fewer bits than t
@@ -59,15 +63,15 @@ __device__ __forceinline__ int scale_exp(double m)
     return e;
 }
 
+struct DigitPtrs {
+    uint16_t *d[ND];
+};
+
 // one row per wavefront, modes along the lanes (rows with unit mode stride):
-// scale exponent and four digit arrays [rows_pad][sp]; padding is zero
+// scale exponent and ND digit arrays [rows_pad][sp]; padding is zero
 __global__ __launch_bounds__(256) void k_digits_wave(const double *__restrict__ X, int64_t rows,
                                                      int cols, int64_t rs, int64_t rows_pad, int sp,
-                                                     uint16_t *__restrict__ D0,
-                                                     uint16_t *__restrict__ D1,
-                                                     uint16_t *__restrict__ D2,
-                                                     uint16_t *__restrict__ D3,
-                                                     int32_t *__restrict__ E)
+                                                     DigitPtrs D, int32_t *__restrict__ E)
 {
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -80,13 +84,11 @@ __global__ __launch_bounds__(256) void k_digits_wave(const double *__restrict__ 
     for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
     const int e = scale_exp(m);
     for (int k = lane; k < sp; k += 64) {
-        uint16_t d[4] = {0, 0, 0, 0};
-        if (in && k < cols) digits4(xr[k], e, d);
+        uint16_t d[ND] = {};
+        if (in && k < cols) digits(xr[k], e, d);
         const int64_t o = r * sp + k;
-        D0[o] = d[0];
-        D1[o] = d[1];
-        D2[o] = d[2];
-        D3[o] = d[3];
+#pragma unroll
+        for (int q = 0; q < ND; ++q) D.d[q][o] = d[q];
     }
     if (lane == 0) E[r] = e;
 }
@@ -95,11 +97,7 @@ __global__ __launch_bounds__(256) void k_digits_wave(const double *__restrict__ 
 // [s][ld] read as rows m = field columns)
 __global__ __launch_bounds__(256) void k_digits_thread(const double *__restrict__ X, int64_t rows,
                                                        int cols, int64_t ks, int64_t rows_pad,
-                                                       int sp, uint16_t *__restrict__ D0,
-                                                       uint16_t *__restrict__ D1,
-                                                       uint16_t *__restrict__ D2,
-                                                       uint16_t *__restrict__ D3,
-                                                       int32_t *__restrict__ E)
+                                                       int sp, DigitPtrs D, int32_t *__restrict__ E)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= rows_pad) return;
@@ -108,13 +106,11 @@ __global__ __launch_bounds__(256) void k_digits_thread(const double *__restrict_
     for (int k = 0; k < cols && in; ++k) m = fmax(m, fabs(X[r + (int64_t)k * ks]));
     const int e = scale_exp(m);
     for (int k = 0; k < sp; ++k) {
-        uint16_t d[4] = {0, 0, 0, 0};
-        if (in && k < cols) digits4(X[r + (int64_t)k * ks], e, d);
+        uint16_t d[ND] = {};
+        if (in && k < cols) digits(X[r + (int64_t)k * ks], e, d);
         const int64_t o = r * sp + k;
-        D0[o] = d[0];
-        D1[o] = d[1];
-        D2[o] = d[2];
-        D3[o] = d[3];
+#pragma unroll
+        for (int q = 0; q < ND; ++q) D.d[q][o] = d[q];
     }
     E[r] = e;
 }
@@ -134,13 +130,11 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
 
 // out mode 0: z (double) at out[b*M + m]; mode 2: exp(z) as float into the
 // level-major pool `out` and as double into `out64`.
-__global__ __launch_bounds__(256, 2) void k_field_digits(
-    const uint16_t *__restrict__ Y0, const uint16_t *__restrict__ Y1,
-    const uint16_t *__restrict__ Y2, const uint16_t *__restrict__ Y3,
-    const int32_t *__restrict__ EY, const uint16_t *__restrict__ B0,
-    const uint16_t *__restrict__ B1, const uint16_t *__restrict__ B2,
-    const uint16_t *__restrict__ B3, const int32_t *__restrict__ EB, int sp, int64_t M, int64_t Bc,
-    void *__restrict__ out, double *__restrict__ out64, int mode)
+__global__ __launch_bounds__(256, 1) void k_field_digits(DigitPtrs Yp, const int32_t *__restrict__ EY,
+                                                         DigitPtrs Bp, const int32_t *__restrict__ EB,
+                                                         int sp, int64_t M, int64_t Bc,
+                                                         void *__restrict__ out,
+                                                         double *__restrict__ out64, int mode)
 {
     // The block's 64 x 32 digit panels of Y and of the basis are staged in
     // LDS, double-buffered: every 16-byte chunk is fetched from global memory
@@ -149,18 +143,16 @@ __global__ __launch_bounds__(256, 2) void k_field_digits(
     // current ones.  Rows are padded to KP bf16 so that the 16 rows a
     // quarter-wavefront reads fall into distinct LDS banks.
     constexpr int KP = 40;
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][4][BM * KP];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][4][BN * KP];
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][ND][BM * KP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][ND][BN * KP];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t brow0 = (int64_t)blockIdx.y * BM, bcol0 = (int64_t)blockIdx.x * BN;
     const int64_t row0 = brow0 + (wave >> 1) * WM;    // sample rows of this wave
     const int64_t col0 = bcol0 + (wave & 1) * WN;     // field columns of this wave
     const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
     const int lr = lane & 15, kg = 8 * (lane >> 4);
-    const uint16_t *Yd[4] = {Y0, Y1, Y2, Y3};
-    const uint16_t *Bd[4] = {B0, B1, B2, B3};
     double acc[2][2][4];
-    f32x4 G[4][2][2];
+    f32x4 G[ND][2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -168,27 +160,33 @@ __global__ __launch_bounds__(256, 2) void k_field_digits(
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc[i][j][e] = 0.0;
 #pragma unroll
-            for (int g = 0; g < 4; ++g) G[g][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int g = 0; g < ND; ++g) G[g][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
-    // staging: 4 digits x 64 rows x 4 chunks of 8 modes per operand = 1024
-    // chunks, four per thread: chunk c = t + 256 q has digit q, row t / 4 and
-    // modes 8 (t % 4) .. +7 (rows and columns are padded, all in range)
+    // staging: ND digits x 64 rows x 4 chunks of 8 modes per operand; chunk
+    // (digit q, row t / 4, modes 8 (t % 4) .. +7) per thread and digit (rows
+    // and columns are padded, all in range)
     const int sr = t >> 2, sk = (t & 3) * 8;
-    bf16x8 ya[4], yb[4];
+    bf16x8 ya[ND], yb[ND];
     auto fetch = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            ya[q] = *(const bf16x8 *)(Yd[q] + (brow0 + sr) * sp + k0 + sk);
-            yb[q] = *(const bf16x8 *)(Bd[q] + (bcol0 + sr) * sp + k0 + sk);
+        for (int q = 0; q < ND; ++q) {
+            ya[q] = *(const bf16x8 *)(Yp.d[q] + (brow0 + sr) * sp + k0 + sk);
+            yb[q] = *(const bf16x8 *)(Bp.d[q] + (bcol0 + sr) * sp + k0 + sk);
         }
     };
     auto stage = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < ND; ++q) {
             *(bf16x8 *)(&As[buf][q][sr * KP + sk]) = ya[q];
             *(bf16x8 *)(&Bs[buf][q][sr * KP + sk]) = yb[q];
         }
     };
+    // the digit products (digit of Y, digit of the basis, weight group), in
+    // increasing weight
+    constexpr int PA[NP] = {0, 0, 1, 0, 2, 1, 0, 3, 1, 2, 0, 4, 1, 3, 2};
+    constexpr int PB[NP] = {0, 1, 0, 2, 0, 1, 3, 0, 2, 1, 4, 0, 3, 1, 2};
+    constexpr int PG[NP] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4, 4};
+    static_assert(ND == 5, "product table written for five digits");
     const int nk = sp / 32;
     fetch(0);
     stage(0);
@@ -196,43 +194,42 @@ __global__ __launch_bounds__(256, 2) void k_field_digits(
     for (int ks = 0; ks < nk; ++ks) {
         const int buf = ks & 1;
         if (ks + 1 < nk) fetch(32 * (ks + 1));
-        bf16x8 a[2][4], b[2][4];
+        bf16x8 a[2][ND], b[2][ND];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int d = 0; d < 4; ++d)
+            for (int d = 0; d < ND; ++d)
                 a[i][d] = *(const bf16x8 *)(&As[buf][d][(wr + 16 * i + lr) * KP + kg]);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int d = 0; d < 4; ++d)
+            for (int d = 0; d < ND; ++d)
                 b[j][d] = *(const bf16x8 *)(&Bs[buf][d][(wc + 16 * j + lr) * KP + kg]);
-        // the ten digit products (digit of Y, digit of the basis, group), each
-        // over the four 16 x 16 tiles in turn, so that consecutive MFMAs write
-        // different accumulators
-        constexpr int PA[10] = {0, 0, 1, 0, 2, 1, 0, 3, 1, 2};
-        constexpr int PB[10] = {0, 1, 0, 2, 0, 1, 3, 0, 2, 1};
-        constexpr int PG[10] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3};
+        // each product over the four 16 x 16 tiles in turn, so that
+        // consecutive MFMAs write different accumulators
 #pragma unroll
-        for (int p = 0; p < 10; ++p)
+        for (int p = 0; p < NP; ++p)
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     G[PG[p]][i][j] = mfma(a[i][PA[p]], b[j][PB[p]], G[PG[p]][i][j]);
         if ((ks + 1) % KFOLD == 0 || ks + 1 == nk) {
-            // exact: the groups are integers below 2^24 and span < 53 bits
+            // the groups are integers of magnitude below 2^24
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        acc[i][j][e] += (double)G[0][i][j][e] + 0x1p-8 * (double)G[1][i][j][e] +
-                                        0x1p-16 * (double)G[2][i][j][e] +
-                                        0x1p-24 * (double)G[3][i][j][e];
+                    for (int e = 0; e < 4; ++e) {
+                        double v = 0x1p-32 * (double)G[4][i][j][e];
+                        v += 0x1p-24 * (double)G[3][i][j][e];
+                        v += 0x1p-16 * (double)G[2][i][j][e];
+                        v += 0x1p-8 * (double)G[1][i][j][e];
+                        acc[i][j][e] += (double)G[0][i][j][e] + v;
+                    }
 #pragma unroll
-                    for (int g = 0; g < 4; ++g) G[g][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    for (int g = 0; g < ND; ++g) G[g][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
         }
         if (ks + 1 < nk) {
@@ -271,26 +268,35 @@ int64_t mixed_pad_cols(int64_t cols) { return (cols + BN - 1) / BN * BN; }
 int mixed_pad_k(int s) { return (s + 31) / 32 * 32; }
 
 void launch_digits_rows(hipStream_t st, const double *X, int64_t rows, int cols, int64_t rs,
-                        int64_t rows_pad, int sp, uint16_t *const D[4], int32_t *E)
+                        int64_t rows_pad, int sp, uint16_t *const D[kDigits], int32_t *E)
 {
+    DigitPtrs P;
+    for (int q = 0; q < ND; ++q) P.d[q] = D[q];
     hipLaunchKernelGGL(k_digits_wave, dim3((unsigned)((rows_pad + 3) / 4)), dim3(256), 0, st, X, rows,
-                       cols, rs, rows_pad, sp, D[0], D[1], D[2], D[3], E);
+                       cols, rs, rows_pad, sp, P, E);
 }
 
 void launch_digits_cols(hipStream_t st, const double *X, int64_t rows, int cols, int64_t ks,
-                        int64_t rows_pad, int sp, uint16_t *const D[4], int32_t *E)
+                        int64_t rows_pad, int sp, uint16_t *const D[kDigits], int32_t *E)
 {
+    DigitPtrs P;
+    for (int q = 0; q < ND; ++q) P.d[q] = D[q];
     hipLaunchKernelGGL(k_digits_thread, dim3((unsigned)((rows_pad + 255) / 256)), dim3(256), 0, st, X,
-                       rows, cols, ks, rows_pad, sp, D[0], D[1], D[2], D[3], E);
+                       rows, cols, ks, rows_pad, sp, P, E);
 }
 
-void launch_field_digits(hipStream_t st, uint16_t *const Y[4], const int32_t *EY,
-                         uint16_t *const Bs[4], const int32_t *EB, int sp, int64_t M, int64_t Bc,
+void launch_field_digits(hipStream_t st, uint16_t *const Y[kDigits], const int32_t *EY,
+                         uint16_t *const Bs[kDigits], const int32_t *EB, int sp, int64_t M, int64_t Bc,
                          void *out, double *out64, int mode)
 {
+    DigitPtrs PY, PB;
+    for (int q = 0; q < ND; ++q) {
+        PY.d[q] = Y[q];
+        PB.d[q] = Bs[q];
+    }
     dim3 grid((unsigned)((M + BN - 1) / BN), (unsigned)((Bc + BM - 1) / BM));
-    hipLaunchKernelGGL(k_field_digits, grid, dim3(256), 0, st, Y[0], Y[1], Y[2], Y[3], EY, Bs[0],
-                       Bs[1], Bs[2], Bs[3], EB, sp, M, Bc, out, out64, mode);
+    hipLaunchKernelGGL(k_field_digits, grid, dim3(256), 0, st, PY, EY, PB, EB, sp, M, Bc, out,
+                       out64, mode);
 }
 
 }  // namespace mlmc

@@ -4,7 +4,9 @@
 // one HIP stream and one host thread; a free slot takes the oldest queued
 // request and every queued request of the same level that still fits the
 // workspace at that level, generates their points into one explicit batch,
-// solves it (the SampleAndSolve body of Algorithm 1) and hands the QoIs back.
+// solves it (the SampleAndSolve body of Algorithm 1) and hands back the QoIs,
+// the per-shift level-difference sums a request asks for (formed on the
+// device, compensated) and the request's unconverged samples.
 // Slots run concurrently, so batches of different levels overlap on the
 // device.
 #include "internal.hpp"
@@ -31,9 +33,15 @@ struct Pending {
 struct Slot {
     mlmc_ctx ctx = nullptr;
     hipStream_t stream = nullptr;
-    double *y_dev = nullptr;      // [slot_samples][s]
-    double *q_dev = nullptr;      // [slot_samples][num_levels][nq]
+    double *y_dev = nullptr;      // [cap][s]
+    double *q_dev = nullptr;      // [cap][num_levels][nq]
     double *q_host = nullptr;     // pinned copy of q_dev
+    int64_t *seg_host = nullptr;  // pinned [cap][2]: (first sample, count) per requested sum
+    int64_t *seg_dev = nullptr;
+    double *s_dev = nullptr;      // [cap][nq][num_levels][2] segment sums
+    double *s_host = nullptr;     // pinned copy of s_dev
+    std::vector<int32_t> bad;     // per sample of the batch: stopped above rtol
+    std::vector<double> rho;      // per sample: largest final residual ratio
     std::thread worker;
 };
 
@@ -66,6 +74,8 @@ struct mlmc_server_s {
 
     void work(int slot_index);
     mlmc_status solve(Slot &sl, int level, std::vector<Pending> &batch, int64_t total);
+    void report(const Slot &sl, const std::vector<Pending> &batch, mlmc_status st, int level,
+                int64_t total, Clock::time_point t_start, Clock::time_point t_end);
 };
 
 mlmc_status mlmc_server_s::solve(Slot &sl, int level, std::vector<Pending> &batch, int64_t total)
@@ -80,19 +90,86 @@ mlmc_status mlmc_server_s::solve(Slot &sl, int level, std::vector<Pending> &batc
         off += p.samples;
     }
     mlmc_points all{MLMC_POINTS_EXPLICIT, level, 0, 1, 0, total, sl.y_dev};
-    mlmc_status st = mlmc_fmg_solve(sl.ctx, &all, nullptr, sl.q_dev, nullptr, nullptr, sl.stream);
-    if (st) return st;
-    const size_t row = sizeof(double) * (size_t)(level + 1) * nq;
+    // per-sample convergence flags (synchronises the slot's stream in rtol mode)
+    mlmc_status st = mlmc::fmg_solve_ex(sl.ctx, &all, nullptr, sl.q_dev, nullptr, nullptr,
+                                        sl.stream, sl.bad.data(), sl.rho.data());
+    if (st && st != MLMC_E_NOCONV) return st;
+    // level-difference sums of every (request, shift) that asked for them:
+    // one segment of the batch's QoI table each, one launch for the batch
+    const int nlev = level + 1;
+    int64_t nseg = 0;
+    off = 0;
+    for (auto &p : batch) {
+        const int64_t npts = p.req.n_end - p.req.n_begin;
+        if (p.req.sums_out)
+            for (int r = p.req.shift_begin; r < p.req.shift_end; ++r) {
+                sl.seg_host[2 * nseg] = off + (int64_t)(r - p.req.shift_begin) * npts;
+                sl.seg_host[2 * nseg + 1] = npts;
+                ++nseg;
+            }
+        off += p.samples;
+    }
+    const size_t srow = sizeof(double) * (size_t)nq * nlev * 2;
+    if (nseg > 0) {
+        if (hipMemcpyAsync(sl.seg_dev, sl.seg_host, sizeof(int64_t) * 2 * nseg,
+                           hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+            return MLMC_E_HIP;
+        mlmc::launch_seg_sums(sl.stream, sl.q_dev, nlev, nq, sl.seg_dev, nseg, sl.s_dev);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(sl.s_host, sl.s_dev, srow * nseg, hipMemcpyDeviceToHost, sl.stream) !=
+                hipSuccess)
+            return MLMC_E_HIP;
+    }
+    const size_t row = sizeof(double) * (size_t)nlev * nq;
     if (hipMemcpyAsync(sl.q_host, sl.q_dev, row * total, hipMemcpyDeviceToHost, sl.stream) !=
             hipSuccess ||
         hipStreamSynchronize(sl.stream) != hipSuccess)
         return MLMC_E_HIP;
     off = 0;
+    nseg = 0;
     for (auto &p : batch) {
         std::memcpy(p.req.qoi_out, (const char *)sl.q_host + row * off, row * p.samples);
+        if (p.req.sums_out) {
+            const int nsh = p.req.shift_end - p.req.shift_begin;
+            std::memcpy(p.req.sums_out, (const char *)sl.s_host + srow * nseg, srow * nsh);
+            nseg += nsh;
+        }
         off += p.samples;
     }
-    return MLMC_OK;
+    return st;
+}
+
+void mlmc_server_s::report(const Slot &sl, const std::vector<Pending> &batch, mlmc_status st,
+                           int level, int64_t total, Clock::time_point t_start,
+                           Clock::time_point t_end)
+{
+    std::lock_guard<std::mutex> lk(mu);
+    int64_t off = 0;
+    for (auto &p : batch) {
+        mlmc_result r{};
+        r.tag = p.req.tag;
+        r.level = level;
+        r.samples = p.samples;
+        r.batch_samples = total;
+        r.queued_ms = ms_between(p.submitted, t_start);
+        r.latency_ms = ms_between(p.submitted, t_end);
+        r.max_rel_residual = -1.0;
+        if (st == MLMC_OK || st == MLMC_E_NOCONV) {
+            for (int64_t b = off; b < off + p.samples; ++b) {
+                r.not_converged += sl.bad[b] != 0;
+                r.max_rel_residual = std::max(r.max_rel_residual, sl.rho[b]);
+            }
+            r.status = r.not_converged ? MLMC_E_NOCONV : MLMC_OK;
+        } else {
+            r.status = st;
+        }
+        off += p.samples;
+        done.push_back(r);
+        latencies.push_back(r.latency_ms);
+        n_samples += p.samples;
+    }
+    ++n_batches;
+    last_done = t_end;
 }
 
 void mlmc_server_s::work(int slot_index)
@@ -121,24 +198,7 @@ void mlmc_server_s::work(int slot_index)
         const Clock::time_point t_start = Clock::now();
         const mlmc_status st = solve(sl, level, batch, total);
         const Clock::time_point t_end = Clock::now();
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            for (auto &p : batch) {
-                mlmc_result r{};
-                r.tag = p.req.tag;
-                r.status = st;
-                r.level = level;
-                r.samples = p.samples;
-                r.batch_samples = total;
-                r.queued_ms = ms_between(p.submitted, t_start);
-                r.latency_ms = ms_between(p.submitted, t_end);
-                done.push_back(r);
-                latencies.push_back(r.latency_ms);
-                n_samples += p.samples;
-            }
-            ++n_batches;
-            last_done = t_end;
-        }
+        report(sl, batch, st, level, total, t_start, t_end);
         cv_done.notify_all();
     }
 }
@@ -150,6 +210,10 @@ void free_slots(mlmc_server srv)
 {
     for (auto it = srv->slots.rbegin(); it != srv->slots.rend(); ++it) {
         if (it->q_host) (void)hipHostFree(it->q_host);
+        if (it->s_host) (void)hipHostFree(it->s_host);
+        if (it->seg_host) (void)hipHostFree(it->seg_host);
+        if (it->s_dev) (void)hipFree(it->s_dev);
+        if (it->seg_dev) (void)hipFree(it->seg_dev);
         if (it->q_dev) (void)hipFree(it->q_dev);
         if (it->y_dev) (void)hipFree(it->y_dev);
         if (it->stream) (void)hipStreamDestroy(it->stream);
@@ -189,11 +253,24 @@ mlmc_status mlmc_server_create(const mlmc_config *cfg, int device, int32_t num_s
             }
         }
         const size_t qsize = sizeof(double) * (size_t)cap_max * cfg->num_levels * srv->nq;
+        const size_t ssize = 2 * qsize;       // one segment per sample at most
+        const size_t gsize = sizeof(int64_t) * 2 * (size_t)cap_max;
+        try {
+            sl.bad.assign((size_t)cap_max, 0);
+            sl.rho.assign((size_t)cap_max, -1.0);
+        } catch (...) {
+            st = MLMC_E_NOMEM;
+            break;
+        }
         if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&sl.stream) != hipSuccess ||
             hipMalloc((void **)&sl.y_dev, sizeof(double) * (size_t)cap_max * cfg->s) !=
                 hipSuccess ||
             hipMalloc((void **)&sl.q_dev, qsize) != hipSuccess ||
-            hipHostMalloc((void **)&sl.q_host, qsize, hipHostMallocDefault) != hipSuccess) {
+            hipHostMalloc((void **)&sl.q_host, qsize, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void **)&sl.s_dev, ssize) != hipSuccess ||
+            hipHostMalloc((void **)&sl.s_host, ssize, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void **)&sl.seg_dev, gsize) != hipSuccess ||
+            hipHostMalloc((void **)&sl.seg_host, gsize, hipHostMallocDefault) != hipSuccess) {
             st = MLMC_E_NOMEM;
             break;
         }

@@ -1,20 +1,25 @@
-"""Level-adaptive MG-MLQMC driver (Section 3.4, Algorithm 1).
+"""Level-adaptive MG-MLQMC driver (Section 3.4).
 
 The driver decides how many lattice points each level gets; the samples
-themselves are solved by the library (`SampleAndSolve` of the algorithm is one
-`mlmc_fmg_solve` call over a new range of lattice points for all R shifts,
-which also yields the recycled coarse solutions), and the estimators come from
-`mlmc_estimate`.
+themselves are solved by the library (one sampling call is one
+`mlmc_fmg_solve` over a new range of lattice points for all R shifts, which
+also yields the recycled coarse solutions, or the equivalent requests to the
+serving loop), and the estimators come from `mlmc_estimate`.
 
-Algorithm (Section 3.4): start with L = -1; while L < 2 or the bias estimate
-exceeds eps / sqrt(2), add a level; while the variance estimate (eq.
-var_of_mgmlqmc) exceeds eps^2 / 2, double N_l (N_l = max(1, 2 N_l)) on the
-level l <= L with the largest V_l / C_l (eq. sample_variances over the
-measured cost per sample C_l) and solve the new points.  The bias estimate is
-|Upsilon-bar_L| / (rho^alpha - 1) with alpha from a least-squares fit of
-log2 |Upsilon-bar_l| over l = 1..L; the paper prints rho^alpha + 1 in eq. bias,
-while the geometric tail sum_{j>=1} rho^(-alpha j) that the estimate stands for
-(and the MLMC literature it cites) gives rho^alpha - 1.
+The run is steered by the two halves of the mean square error: the
+statistical error, the variance estimate of eq. var_of_mgmlqmc built from
+the per-level shift variances of eq. sample_variances, must fall below
+eps^2 / 2, and the bias, estimated from the last level difference Upsilon-bar_L
+of eq. Upsilon-reuse-bar, must fall below eps / sqrt(2) (eq. bias).  While the
+variance is too large, the level with the most variance per unit of measured
+cost per sample gets twice its lattice points (a lattice sequence keeps its
+earlier points, so only the new ones are solved); once it is small enough, a
+level is added if the bias is too large.  The bias estimate assumes the level
+differences decay geometrically, |Upsilon-bar_l| ~ rho^(-alpha l), with alpha
+fitted over l = 1..L: the neglected tail sum_{j>=1} rho^(-alpha j)
+|Upsilon-bar_L| is |Upsilon-bar_L| / (rho^alpha - 1).  The paper prints
+rho^alpha + 1 in that denominator; `bias_denominator="plus"` selects the
+printed form.
 """
 from __future__ import annotations
 
@@ -23,16 +28,39 @@ import time
 
 import numpy as np
 
-from . import mlmc_estimate
+from . import MLMC_E_NOCONV, mlmc_estimate
 
 
-class GpuSampler:
-    """SampleAndSolve on the GPU: lattice points [n_begin, n_end) of every shift
-    on finest level `level`, returning the level-difference sums
-    [R][nq][level+1][2] on the host."""
+class NotConvergedError(RuntimeError):
+    """A sampling call returned samples whose refinement stopped above rtol."""
 
-    def __init__(self, ctx):
+
+class _ConvergenceLog:
+    """Unconverged samples seen by a sampler: counted, or raised at once."""
+
+    def __init__(self, strict):
+        self.strict = bool(strict)
+        self.not_converged = 0
+        self.max_rel_residual = -1.0
+
+    def note(self, count, max_rel_residual, what):
+        self.max_rel_residual = max(self.max_rel_residual, float(max_rel_residual))
+        if count:
+            self.not_converged += int(count)
+            if self.strict:
+                raise NotConvergedError(f"{count} sample(s) of {what} stopped above rtol "
+                                        f"(largest final residual ratio {max_rel_residual:.3e})")
+
+
+class GpuSampler(_ConvergenceLog):
+    """One sampling call on the GPU: lattice points [n_begin, n_end) of every
+    shift on finest level `level`, returning the level-difference sums
+    [R][nq][level+1][2] on the host.  Samples whose refinement stopped above
+    rtol are counted in `not_converged` (strict=True raises instead)."""
+
+    def __init__(self, ctx, strict=False):
         import torch
+        super().__init__(strict)
         self.ctx = ctx
         self.R = ctx.num_shifts
         self.nq = ctx.nq
@@ -42,20 +70,24 @@ class GpuSampler:
         torch = self._torch
         s = torch.zeros((self.R, self.nq, level + 1, 2), dtype=torch.float64,
                         device=torch.device("cuda", self.ctx.device))
-        self.ctx.fmg_solve(self.ctx.lattice(level, n_begin, n_end, 0, self.R), sums=s)
-        return s.cpu().numpy()          # synchronising copy: the timer sees the solve
+        info = self.ctx.fmg_solve(self.ctx.lattice(level, n_begin, n_end, 0, self.R), sums=s,
+                                  want_info=True)
+        self.note(info["not_converged"], info["max_rel_residual"],
+                  f"level {level}, points {n_begin}..{n_end}")
+        return s.cpu().numpy()
 
 
-class GpuMcSampler:
-    """SampleAndSolve with Monte Carlo points (plain MLMC, Section 2): R
+class GpuMcSampler(_ConvergenceLog):
+    """One sampling call with Monte Carlo points (plain MLMC, Section 2): R
     independent replicas of i.i.d. standard normal vectors play the role of
     the R random shifts, so the same estimators (eq. MLQMC, eq. varovershifts
     and their recycling forms) apply.  normals(level, replica, n_begin, n_end)
     returns the [n_end - n_begin][s] normals of that replica, drawn once per
     (level, replica) stream; each replica is one explicit-points solve."""
 
-    def __init__(self, ctx, normals, num_replicas):
+    def __init__(self, ctx, normals, num_replicas, strict=False):
         import torch
+        super().__init__(strict)
         self.ctx = ctx
         self.R = int(num_replicas)
         self.nq = ctx.nq
@@ -68,17 +100,22 @@ class GpuMcSampler:
         out = torch.zeros((self.R, self.nq, level + 1, 2), dtype=torch.float64, device=dev)
         for r in range(self.R):
             y = torch.as_tensor(self.normals(level, r, n_begin, n_end), dtype=torch.float64)
-            self.ctx.fmg_solve(self.ctx.explicit(level, y.to(dev).contiguous()), sums=out[r:r + 1])
+            info = self.ctx.fmg_solve(self.ctx.explicit(level, y.to(dev).contiguous()),
+                                      sums=out[r:r + 1], want_info=True)
+            self.note(info["not_converged"], info["max_rel_residual"],
+                      f"level {level}, replica {r}")
         return out.cpu().numpy()
 
 
-class ServerSampler:
-    """SampleAndSolve through the serving loop (mlmc_server): the new lattice
-    points of every shift become requests (split to the server's capacity at
-    the level), which the server batches with whatever else is queued; the
-    level-difference sums are formed on the host from the returned QoIs."""
+class ServerSampler(_ConvergenceLog):
+    """One sampling call through the serving loop (mlmc_server): the new
+    lattice points of every shift become requests (split to the server's
+    capacity at the level), which the server batches with whatever else is
+    queued.  The server forms each request's level-difference sums on the
+    device; this sampler only adds up the sums of a shift's requests."""
 
-    def __init__(self, server, num_shifts, first_shift=0):
+    def __init__(self, server, num_shifts, first_shift=0, strict=False):
+        super().__init__(strict)
         self.srv = server
         self.R = int(num_shifts)
         self.r0 = int(first_shift)      # shifts r0 .. r0+R-1 of the server's table
@@ -88,17 +125,14 @@ class ServerSampler:
         cap = self.srv.capacity(level)
         reqs = [(level, a, min(a + cap, n_end), self.r0 + r, self.r0 + r + 1)
                 for r in range(self.R) for a in range(n_begin, n_end, cap)]
-        tags = [self.srv.submit(*q) for q in reqs]
+        tags = [self.srv.submit(*q, sums=True) for q in reqs]
         sums = np.zeros((self.R, self.nq, level + 1, 2))
         for q, res in zip(reqs, self.srv.collect(tags)):
-            if res["status"] != 0:
+            if res["status"] not in (0, MLMC_E_NOCONV):
                 raise RuntimeError(f"request {q} failed with status {res['status']}")
-            F = res["qoi"]                                   # [B][level+1][nq]
-            d = F.copy()
-            d[:, 1:, :] -= F[:, :-1, :]                      # F_l - F_(l-1), F_(-1) = 0
-            r = q[3] - self.r0
-            sums[r, :, :, 0] += d.sum(axis=0).T
-            sums[r, :, :, 1] += (d * d).sum(axis=0).T
+            self.note(res.get("not_converged", 0), res.get("max_rel_residual", -1.0),
+                      f"request {q}")
+            sums[q[3] - self.r0] += res["sums"][0]
         return sums
 
 
@@ -112,66 +146,106 @@ def _alpha_fit(ubar):
     return max(-slope, 0.5)
 
 
-def mg_mlqmc(sampler, eps, max_level, qoi=0, rho=2.0, reuse=True, max_points=None,
-             clock=time.perf_counter):
-    """Run Algorithm 1 to tolerance eps (root mean square error) on levels
-    0..max_level.  Returns the estimate, its variance and bias estimates, the
-    points per level, the measured cost per sample and the call history."""
-    R, nq = sampler.R, sampler.nq
-    L1 = max_level + 1
-    N = np.zeros(L1, dtype=np.int64)
-    N_old = np.zeros(L1, dtype=np.int64)
-    sums = np.zeros((L1, R, nq, L1, 2))
-    V = np.full(L1, np.inf)
-    C = np.zeros(L1)
-    solved = np.zeros(L1, dtype=np.int64)      # samples timed per level
-    history = []
-    est = None
+class AdaptiveEstimator:
+    """State of an adaptive MG-MLQMC run on levels 0..max_level: the summed
+    level differences per origin level, the lattice points per level, the
+    measured cost per sample and the current estimate."""
 
-    def sample_and_solve(l):
-        nonlocal est
-        t0 = clock()
-        s = sampler.sample(l, int(N_old[l]), int(N[l]))
-        dt = clock() - t0
-        sums[l, :, :, : l + 1, :] += s
-        new = int(N[l] - N_old[l]) * R
-        C[l] = (C[l] * solved[l] + dt) / (solved[l] + new)     # mean time per sample
-        solved[l] += new
-        history.append((l, int(N_old[l]), int(N[l])))
-        est = mlmc_estimate(N, sums, R, nq, reuse)
-        V[: l + 1] = est["var_level"][qoi][: l + 1]
-        N_old[l] = N[l]
+    def __init__(self, sampler, max_level, qoi=0, rho=2.0, reuse=True, max_points=None,
+                 bias_denominator="minus", clock=time.perf_counter):
+        if bias_denominator not in ("minus", "plus"):
+            raise ValueError("bias_denominator is 'minus' (rho^alpha - 1) or 'plus' (as printed)")
+        self.sampler, self.qoi, self.rho, self.reuse = sampler, int(qoi), float(rho), bool(reuse)
+        self.max_points, self.clock = max_points, clock
+        self.sign = -1.0 if bias_denominator == "minus" else 1.0
+        L1 = int(max_level) + 1
+        R, nq = sampler.R, sampler.nq
+        self.points = np.zeros(L1, dtype=np.int64)        # lattice points per origin level
+        self.sums = np.zeros((L1, R, nq, L1, 2))
+        self.cost = np.zeros(L1)                          # mean seconds per sample
+        self.timed = np.zeros(L1, dtype=np.int64)
+        self.var = np.full(L1, np.inf)                    # per-level estimator variance
+        self.history = []
+        self.est = None
+        self.L = -1
 
-    def bias(L):
-        ub = est["upsilon_bar"][qoi][: L + 1]
-        a = _alpha_fit(ub)
-        return abs(ub[L]) / (rho ** a - 1.0), a
+    def grow(self, l, n_new):
+        """Solve lattice points [points[l], n_new) of every shift at level l."""
+        n_old = int(self.points[l])
+        t0 = self.clock()
+        s = self.sampler.sample(l, n_old, n_new)
+        dt = self.clock() - t0
+        self.sums[l, :, :, : l + 1, :] += s
+        added = (n_new - n_old) * self.sampler.R
+        self.cost[l] = (self.cost[l] * self.timed[l] + dt) / (self.timed[l] + added)
+        self.timed[l] += added
+        self.points[l] = n_new
+        self.history.append((l, n_old, n_new))
+        self.est = mlmc_estimate(self.points, self.sums, self.sampler.R, self.sampler.nq,
+                                 self.reuse)
+        self.var[: l + 1] = self.est["var_level"][self.qoi][: l + 1]
 
-    L, converged, alpha, b = -1, True, float("nan"), float("inf")
-    while True:
-        if L >= 2:
-            b, alpha = bias(L)
-            if b <= eps / math.sqrt(2.0):
-                break
-        if L + 1 > max_level:
-            converged = False
-            break
-        L += 1
-        while np.sum(V[: L + 1]) > eps * eps / 2.0:
-            ratio = np.where(C[: L + 1] > 0, V[: L + 1] / np.where(C[: L + 1] > 0, C[: L + 1], 1.0),
-                             np.inf)
-            l = int(np.argmax(ratio))
-            n_new = max(1, 2 * int(N[l]))
-            if max_points is not None and n_new > max_points:
+    def variance(self):
+        return float(np.sum(self.var[: self.L + 1]))
+
+    def bias(self):
+        """(bias estimate, fitted alpha) from the level differences 0..L."""
+        ub = self.est["upsilon_bar"][self.qoi][: self.L + 1]
+        alpha = _alpha_fit(ub)
+        return abs(ub[self.L]) / (self.rho ** alpha + self.sign), alpha
+
+    def best_level(self):
+        """The level with the most variance per unit of cost (unsolved first)."""
+        v, c = self.var[: self.L + 1], self.cost[: self.L + 1]
+        gain = np.where(c > 0, v / np.where(c > 0, c, 1.0), np.inf)
+        return int(np.argmax(gain))
+
+    def reduce_variance(self, eps):
+        """Double the points of the best level until the variance meets
+        eps^2 / 2; False if the point budget runs out first."""
+        while self.variance() > eps * eps / 2.0:
+            l = self.best_level()
+            n_new = max(1, 2 * int(self.points[l]))
+            if self.max_points is not None and n_new > self.max_points:
+                return False
+            self.grow(l, n_new)
+        return True
+
+    def run(self, eps):
+        """Levels are added until the bias meets eps / sqrt(2) (at least three
+        levels, so that alpha can be fitted), the variance being reduced to
+        eps^2 / 2 on every level set."""
+        converged, bias, alpha = True, float("inf"), float("nan")
+        while True:
+            if self.L >= 2:
+                bias, alpha = self.bias()
+                if bias <= eps / math.sqrt(2.0):
+                    break
+            if self.L + 1 >= len(self.points):
                 converged = False
                 break
-            N[l] = n_new
-            sample_and_solve(l)
-        if not converged:
-            break
-    return dict(q_bar=float(est["q_bar"][qoi]), var=float(np.sum(V[: L + 1])), bias=b,
-                alpha=alpha, L=L, N=N[: L + 1].copy(), cost=C[: L + 1].copy(),
-                converged=converged, history=history, estimate=est)
+            self.L += 1
+            if not self.reduce_variance(eps):
+                converged = False
+                break
+        L = self.L
+        return dict(q_bar=float(self.est["q_bar"][self.qoi]), var=self.variance(), bias=bias,
+                    alpha=alpha, L=L, N=self.points[: L + 1].copy(),
+                    cost=self.cost[: L + 1].copy(), converged=converged,
+                    history=list(self.history), estimate=self.est,
+                    not_converged=int(getattr(self.sampler, "not_converged", 0)))
+
+
+def mg_mlqmc(sampler, eps, max_level, qoi=0, rho=2.0, reuse=True, max_points=None,
+             bias_denominator="minus", clock=time.perf_counter):
+    """Adaptive MG-MLQMC (reuse=True) or MLQMC (reuse=False) to root mean
+    square error eps on levels 0..max_level (Section 3.4).  Returns the
+    estimate, its variance and bias estimates, the points per level, the
+    measured cost per sample, the sampling history and the count of samples
+    whose refinement stopped above rtol."""
+    return AdaptiveEstimator(sampler, max_level, qoi=qoi, rho=rho, reuse=reuse,
+                             max_points=max_points, bias_denominator=bias_denominator,
+                             clock=clock).run(eps)
 
 
 def _rate(values, rho):

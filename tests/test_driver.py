@@ -86,23 +86,30 @@ class FakeServer:
     def capacity(self, level):
         return 5
 
-    def submit(self, level, n0, n1, r0, r1):
-        assert n1 - n0 <= 5 and r1 - r0 == 1
+    def submit(self, level, n0, n1, r0, r1, sums=False):
+        assert n1 - n0 <= 5 and r1 - r0 == 1 and sums
         tag = len(self.reqs)
         self.reqs[tag] = (level, n0, n1, r0)
         return tag
 
     def collect(self, tags):
+        # the library forms a request's level sums on the device; here they
+        # are formed exactly (math.fsum) from the closed-form QoIs
+        import math
         out = []
         for t in tags:
             level, n0, n1, r = self.reqs[t]
             n = np.arange(n0, n1, dtype=np.float64)[:, None]
             F = (n + 1.0) * 10.0 ** -np.arange(level + 1)[None, :] + r
-            out.append(dict(status=0, qoi=np.stack([F, 2.0 * F], axis=-1)))
+            Q = np.stack([F, 2.0 * F], axis=-1)            # [B][level+1][nq]
+            d = np.diff(np.concatenate([np.zeros((Q.shape[0], 1, 2)), Q], axis=1), axis=1)
+            sums = np.array([[[[math.fsum(d[:, l, q]), math.fsum(d[:, l, q] ** 2)]
+                               for l in range(level + 1)] for q in range(2)]])
+            out.append(dict(status=0, qoi=Q, sums=sums, not_converged=0, max_rel_residual=-1.0))
         return out
 
 
-def test_server_sampler_splits_requests_and_forms_level_sums():
+def test_server_sampler_splits_requests_and_adds_level_sums():
     from paper_1806_05619_amd.driver import ServerSampler
     srv = FakeServer()
     s = ServerSampler(srv, num_shifts=3, first_shift=4).sample(2, 3, 15)
@@ -139,3 +146,49 @@ def test_prop1_on_the_optimal_sample_numbers():
         assert abs(rep["predicted_fraction"] - want) < 1e-9
     # Monte Carlo, beta = 2, gamma = 2, rho = 2: 1 - 2^-2 of every level is new
     assert abs(prop1_reduction(2.0, 2.0, 1.0, 2.0) - 0.75) < 1e-15
+
+
+class FlakySampler(SyntheticSampler):
+    """Reports one unconverged sample on every call at level 2."""
+
+    def __init__(self, strict):
+        super().__init__()
+        from paper_1806_05619_amd.driver import _ConvergenceLog
+        self.log = _ConvergenceLog(strict)
+
+    @property
+    def not_converged(self):
+        return self.log.not_converged
+
+    def sample(self, level, n_begin, n_end):
+        out = super().sample(level, n_begin, n_end)
+        self.log.note(1 if level == 2 else 0, 3.5e-10, f"level {level}")
+        return out
+
+
+def test_unconverged_samples_are_counted_or_raised():
+    from paper_1806_05619_amd.driver import NotConvergedError
+    r = mg_mlqmc(FlakySampler(strict=False), 1e-3, max_level=12)
+    assert r["not_converged"] == sum(1 for l, _, _ in r["history"] if l == 2) > 0
+    try:
+        mg_mlqmc(FlakySampler(strict=True), 1e-3, max_level=12)
+    except NotConvergedError as e:
+        assert "level 2" in str(e)
+    else:
+        raise AssertionError("strict sampler did not raise")
+
+
+def test_bias_denominator_forms():
+    """Default: the geometric tail |Ubar_L| / (rho^alpha - 1); 'plus' takes the
+    printed rho^alpha + 1, which stops earlier (smaller bias estimate)."""
+    a = mg_mlqmc(SyntheticSampler(), 1e-4, max_level=14)
+    b = mg_mlqmc(SyntheticSampler(), 1e-4, max_level=14, bias_denominator="plus")
+    assert b["L"] <= a["L"]
+    ub = a["estimate"]["upsilon_bar"][0][a["L"]]
+    assert abs(a["bias"] - abs(ub) / (2.0 ** a["alpha"] - 1.0)) <= 1e-15 * a["bias"]
+    try:
+        mg_mlqmc(SyntheticSampler(), 1e-3, max_level=4, bias_denominator="other")
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("unknown denominator accepted")

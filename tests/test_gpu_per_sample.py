@@ -1,0 +1,114 @@
+"""The per-sample accuracy target of the tolerance mode, checked sample by
+sample against the oracle on every level of the s = 400 workload (lambda 0.1,
+sigma^2 2, every FMG stage refined to relative residual 1e-10), in both
+precisions:
+
+* 4^2 .. 32^2: every sample of one 4096-point shift, against the oracle's
+  band Cholesky solve of each level (the exact discrete solution);
+* 64^2 .. 256^2: 64 samples (16 points x 4 shifts), against the band solve;
+* 512^2 and 1024^2: 4 samples from different shifts of the 256-sample
+  batch the benchmark times, against the oracle's FMG with the same stopping
+  rule (the band solve costs 1.1 TFLOP per sample at 1024^2).
+
+Tolerance: 1e-8 relative per sample, level and QoI.  The FP64 path differs
+from the exact solution only by the solve tolerance; the mixed path adds the
+error of its digit-product field (below 2 s 2^(E_y + E_b - 38) per cell).
+The largest error per level is printed."""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1806_05619_amd as m  # noqa: E402
+
+TOL = 1e-8
+PRECISIONS = {"fp64": m.MLMC_FP64, "mixed": m.MLMC_MIXED}
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _setup(oracle_mod, precision, num_levels, max_batch):
+    w = synth.workload("mlqmc_mixed_s400")
+    w["num_levels"] = num_levels
+    z = synth.korobov_vector(w["seed"], w["s"])
+    D = synth.shift_table(w["seed"], 9, w["num_shifts"], w["s"])[:num_levels]
+    ctx = m.Context(w["n0"], num_levels, w["s"], w["corr_len"], w["sigma2"], mu0=w["mu0"],
+                    mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"], max_iters=w["max_iters"],
+                    precision=PRECISIONS[precision], qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
+                    genvec=z, shifts=np.ascontiguousarray(D), max_batch=max_batch, device=0)
+    P = oracle_mod.Problem(w["n0"], num_levels, w["s"], w["corr_len"], w["sigma2"], mu0=w["mu0"],
+                           mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"], max_iters=w["max_iters"])
+    return w, z, D, ctx, P
+
+
+def _gpu(ctx, k, n0, n1, r0, r1):
+    pts = ctx.lattice(k, n0, n1, r0, r1)
+    q = torch.full((ctx.count(pts), k + 1, 2), float("nan"), dtype=torch.float64,
+                   device="cuda:0")
+    info = ctx.fmg_solve(pts, qoi=q, want_info=True)
+    torch.cuda.synchronize()
+    return q.cpu().numpy(), info
+
+
+def _check(label, qg, qo):
+    rel = np.abs(qg - qo) / np.abs(qo)
+    worst = rel.max(axis=(0, 2))
+    print(f"\n{label}: max rel error per level " + " ".join(f"{v:.1e}" for v in worst),
+          flush=True)
+    assert np.all(np.isfinite(qg))
+    assert worst.max() <= TOL, worst
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_every_sample_of_a_shift_on_coarse_levels(oracle_mod, precision):
+    _dev()
+    k, npts = 3, 4096
+    w, z, D, ctx, P = _setup(oracle_mod, precision, k + 1, 4096)
+    print(f"\n{precision}: {npts} samples, levels 4^2..32^2", flush=True)
+    qg, info = _gpu(ctx, k, 0, npts, 0, 1)
+    assert info["not_converged"] == 0, info
+    _, y = oracle_mod.points(z, D[k, 0], 0, npts)
+    qo, bad = P.batch(k, y, 1, nthreads=16)
+    assert bad == 0
+    _check(f"{precision} 4^2..32^2 ({npts} samples)", qg, qo)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_samples_on_middle_levels(oracle_mod, precision):
+    _dev()
+    k = 6
+    w, z, D, ctx, P = _setup(oracle_mod, precision, k + 1, 64)
+    print(f"\n{precision}: 64 samples, levels 4^2..256^2", flush=True)
+    qg, info = _gpu(ctx, k, 0, 16, 0, 4)
+    assert info["not_converged"] == 0, info
+    y = np.concatenate([oracle_mod.points(z, D[k, r], 0, 16)[1] for r in range(4)])
+    qo, bad = P.batch(k, y, 1, nthreads=16)
+    assert bad == 0
+    _check(f"{precision} 4^2..256^2 (64 samples)", qg, qo)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_samples_of_the_benchmark_batch_on_fine_levels(oracle_mod, precision):
+    """The benchmark's launch configuration: 16 points x 16 shifts at 1024^2
+    in one call; samples 0, 85, 170 and 255 (shifts 0, 5, 10, 15) against the
+    oracle's FMG (levels 4^2 .. 1024^2).  A sample stopped by the rounding
+    floor (residual ratio within 2x of rtol, reported) is held to the same
+    tolerance."""
+    _dev()
+    k = 8
+    w, z, D, ctx, P = _setup(oracle_mod, precision, k + 1, 256)
+    print(f"\n{precision}: 256 samples at 1024^2", flush=True)
+    qg, info = _gpu(ctx, k, 0, 16, 0, 16)
+    print(f"info {info}", flush=True)
+    assert info["max_rel_residual"] <= 2 * w["rtol"], info
+    picks = [0, 85, 170, 255]
+    y = np.stack([oracle_mod.points(z, D[k, b // 16], b % 16, b % 16 + 1)[1][0] for b in picks])
+    qo, _ = P.batch(k, y, 0, nthreads=4)
+    _check(f"{precision} 4^2..1024^2 (samples {picks})", qg[picks], qo)

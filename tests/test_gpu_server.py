@@ -179,3 +179,73 @@ def test_server_on_matern_field_equals_direct_solves():
     for r, out in zip(reqs, res):
         assert out["status"] == m.MLMC_OK
         assert np.array_equal(out["qoi"], _direct(ctx, *r)), r
+
+
+@pytest.mark.parametrize("precision", [m.MLMC_FP64, m.MLMC_MIXED])
+def test_served_results_against_oracle_and_device_sums(oracle_mod, precision):
+    """Requests of several levels through the server (mixed workload, rtol
+    1e-10): sampled served QoIs against the oracle's band solve (1e-8), each
+    request's per-shift level sums against exactly rounded sums of its
+    served QoIs (1e-13) and bitwise against mlmc_fmg_solve's sums for the
+    same points alone, and no unconverged sample reported."""
+    import math
+    _dev()
+    w = synth.workload("mlqmc_mixed_s400")
+    w["num_levels"] = 6
+    kw = _kw(w, precision)
+    reqs = [(5, 0, 6, 0, 2), (2, 10, 41, 3, 4), (4, 7, 12, 5, 8), (0, 0, 200, 1, 2),
+            (3, 100, 164, 15, 16), (5, 6, 9, 2, 3)]
+    with m.Server(**kw, num_slots=2, slot_samples=16, device=0) as srv:
+        tags = [srv.submit(*r, sums=True) for r in reqs]
+        res = srv.collect(tags, timeout_s=300)
+    ctx = m.Context(**kw, max_batch=256, device=0)
+    P = oracle_mod.Problem(w["n0"], w["num_levels"], w["s"], w["corr_len"], w["sigma2"],
+                           mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"],
+                           max_iters=w["max_iters"])
+    z = synth.korobov_vector(w["seed"], w["s"])
+    D = synth.shift_table(w["seed"], w["num_levels"], w["num_shifts"], w["s"])
+    for (level, n0, n1, r0, r1), out in zip(reqs, res):
+        assert out["status"] == m.MLMC_OK and out["not_converged"] == 0, out
+        assert 0 < out["max_rel_residual"] <= w["rtol"], out
+        Q = out["qoi"]
+        npts = n1 - n0
+        # device sums: exactly rounded sums of the served QoIs, and the
+        # library's own sums for the same points solved alone
+        pts = ctx.lattice(level, n0, n1, r0, r1)
+        s_dev = torch.zeros((r1 - r0, 2, level + 1, 2), dtype=torch.float64, device="cuda:0")
+        ctx.fmg_solve(pts, sums=s_dev)
+        assert np.array_equal(out["sums"], s_dev.cpu().numpy()), (level, n0, n1, r0, r1)
+        for r in range(r1 - r0):
+            Fr = Q[r * npts:(r + 1) * npts]
+            d = np.diff(np.concatenate([np.zeros((npts, 1, 2)), Fr], axis=1), axis=1)
+            for q in range(2):
+                for l in range(level + 1):
+                    s1 = math.fsum(d[:, l, q])
+                    s2 = math.fsum(d[:, l, q] ** 2)
+                    assert abs(out["sums"][r, q, l, 0] - s1) <= 1e-13 * math.fsum(np.abs(d[:, l, q]))
+                    assert abs(out["sums"][r, q, l, 1] - s2) <= 1e-13 * s2
+        # first and last sample of the request against the band solve
+        for b in (0, len(Q) - 1):
+            r, n = r0 + b // npts, n0 + b % npts
+            _, y = oracle_mod.points(z, D[level, r], n, n + 1)
+            qo = P.sample(level, y[0], 1)
+            assert np.max(np.abs(Q[b] - qo) / np.abs(qo)) <= 1e-8, (level, r, n)
+
+
+def test_server_reports_unconverged_samples():
+    """An rtol no FP64 residual can reach: every served sample stops at the
+    rounding floor, each request reports all its samples as not converged
+    with status MLMC_E_NOCONV, and its QoIs are still written."""
+    _dev()
+    w = synth.workload("mlqmc_fp64_s100")
+    kw = _kw(w, m.MLMC_FP64)
+    kw.update(rtol=1e-30, max_iters=200, mu0=1, num_levels=5,
+              shifts=synth.shift_table(w["seed"], 5, w["num_shifts"], w["s"]))
+    reqs = [(4, 0, 3, 0, 1), (1, 5, 9, 2, 4)]
+    with m.Server(**kw, num_slots=1, slot_samples=8, device=0) as srv:
+        res = srv.collect([srv.submit(*r) for r in reqs], timeout_s=120)
+    for (level, n0, n1, r0, r1), out in zip(reqs, res):
+        assert out["status"] == m.MLMC_E_NOCONV, out
+        assert out["not_converged"] == (n1 - n0) * (r1 - r0), out
+        assert 0 < out["max_rel_residual"] <= 1e-12
+        assert np.all(np.isfinite(out["qoi"])) and np.all(out["qoi"] > 0)

@@ -123,11 +123,13 @@ def test_autotune_refinement_contexts(precision):
 @pytest.mark.parametrize("name,precision", [("mlqmc_fp64_s100", m.MLMC_FP64),
                                             ("mlqmc_mixed_s400", m.MLMC_FP64),
                                             ("mlqmc_mixed_s400", m.MLMC_MIXED)])
-def test_streaming_at_512_matches_tiles(name, precision):
+def test_streaming_at_512_matches_tiles(oracle_mod, name, precision):
     """512^2, the largest streaming grid and the only one whose workgroup
     holds four wavefronts per sample (one barrier per row step): streaming,
     tiles and a mix give the same bits, fixed-cycle and refinement mode,
-    FP64 and FP32 V-cycles."""
+    FP64 and FP32 V-cycles; one sample against the oracle's FMG (fixed
+    cycles: the same algorithm, 1e-12; refinement: both to rtol 1e-10,
+    1e-8)."""
     _dev()
     w = synth.workload(name)
     L = 8                                           # MG grids up to 512^2
@@ -148,3 +150,10 @@ def test_streaming_at_512_matches_tiles(name, precision):
         if want is None:
             want = q
         assert np.array_equal(q, want), (pre, post)
+    P = oracle_mod.Problem(w["n0"], L, w["s"], w["corr_len"], w["sigma2"], mu0=w["mu0"],
+                           mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"], max_iters=w["max_iters"])
+    D = synth.shift_table(w["seed"], L, w["num_shifts"], w["s"])
+    _, y = oracle_mod.points(synth.korobov_vector(w["seed"], w["s"]), D[L - 1, 1], 0, 1)
+    qo = P.sample(L - 1, y[0], 0)
+    tol = 1e-12 if w["rtol"] == 0 else 1e-8
+    assert np.max(np.abs(want[0] - qo) / np.abs(qo)) <= tol
