@@ -51,9 +51,9 @@ BYTE_MODEL = dict(
     pre="a, u (unless zero or interpolated), f (unless 1) read, u written, f_c written (w/4)",
     post="e_c (w/4), a, u, f (unless 1) read, u written",
     lds="coefficients of the LDS grids read, top-level solution written",
-    refine="one flexible-CG step after the V-cycle: dots (z, r, r_old read, r_old written), "
-           "p and (p, A p) (a, z, p read, p written), x and new residual (a and x in FP64, "
-           "p read; x in FP64 and r written): 24 + 10 w B per cell")
+    refine="one flexible-CG step: dots (z, r, r_old read), p and (p, A p) (a, z, p read, p "
+           "written), x and r (a, x in FP64 and p read, x in FP64 and r written): 24 + 9 w B "
+           "per cell")
 
 KINDS = ("points", "field", "smooth", "restrict", "prolong", "coarse", "qoi", "sums", "pre", "post",
          "lds", "refine")

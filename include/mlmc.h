@@ -289,12 +289,12 @@ enum {
                               cycles, 32^2 with rtol): a of all its grids
                               read, f of its top grid read (V-cycle mode), u of
                               its top grid written */
-    MLMC_KERNEL_REFINE = 11 /* rtol mode on grids >= 64^2, the flexible-CG passes
-                              of a stage: initial residual (FP64 a, x read; f
-                              written), then per step dots (z, r, r_old read;
-                              r_old written), p with (p, A p) (a, z, previous p
-                              read; p written), x with the new residual (FP64
-                              a, x, p read; x, f written), all on n^2 */
+    MLMC_KERNEL_REFINE = 11 /* rtol mode on grids >= 64^2, one flexible-CG step
+                              after the V-cycle, per cell: dots (z, r, r_old
+                              read), p with (p, A p) (a, z, previous p read; p
+                              written), x with the new residual (FP64 a, x, p
+                              read; x, r written): 24 + 9 w bytes, w the
+                              V-cycle word size */
 };
 typedef struct {
     int64_t launches;

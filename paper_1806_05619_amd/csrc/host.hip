@@ -622,18 +622,20 @@ mlmc_status run_fmg_refine(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k,
         }
         launch_fcg_fin_rho(st, c->d_part, n, Bc, c->d_rho, c->d_rho_hist, c->d_active, c->d_iters,
                            c->cfg.rtol, c->cfg.max_iters, 1);
-        for (;;) {
+        for (int step = 1;; ++step) {
             HIPCHK(c, hipMemcpyAsync(c->h_active, c->d_active, sizeof(int32_t) * Bc,
                                      hipMemcpyDeviceToHost, st));
             HIPCHK(c, hipStreamSynchronize(st));
             int64_t nact = 0;
             for (int64_t b = 0; b < Bc; ++b) nact += c->h_active[b];
             if (nact == 0) break;
-            R.vcycle(g, h.u[g], 1, h.f[g], c->d_active);
+            // every active sample is at this step; its residual r_{step-1}
+            // is in f for odd steps and in fo for even ones
+            R.vcycle(g, h.u[g], 1, (step & 1) ? v.f : v.fo, c->d_active);
             {
-                // dots: z, r, r_old read, r_old written; p: a, z, p_prev read, p
-                // written; x: a (FP64), x_prev, p read, x and r written
-                ProfScope ps(c, st, MLMC_KERNEL_REFINE, vec * (24.0 + 10.0 * R.W), 0.0);
+                // dots: z, r, r_old read; p: a, z, p_prev read, p written;
+                // x: a (FP64), x_prev, p read, x and r written
+                ProfScope ps(c, st, MLMC_KERNEL_REFINE, vec * (24.0 + 9.0 * R.W), 0.0);
                 launch_fcg_step<T>(st, v, n, Bc, c->cfg.rtol, c->cfg.max_iters);
             }
         }

@@ -149,25 +149,27 @@ void launch_lds_fmg_refine(hipStream_t st, const T *a_pool, const double *a64_po
                            double *u64_pool, int64_t Bc, int G, int mu1, int mu2, double rtol,
                            int max_iters, int g0, double *qoi, int nlev, uint32_t mask,
                            int32_t *st_iters, double *st_rho, int32_t *st_bad);
-// flexible CG of one stage on a large grid (Bc samples of n x n).  Iterate x
-// in FP64 in two buffers (x0 = the stage solution pool), residual only as
-// f = T(r), r_old and the search direction (two buffers) in T; FP64
-// coefficients for the residual, T coefficients for (p, A p).
-// Partial-sum scratch: fcg_partials doubles; fs: 4 doubles per sample.
+// flexible CG of one stage on a large grid (Bc samples of n x n, n >= 64).
+// Iterate x in FP64 in two buffers (x0 = the stage solution pool), residual
+// only as T(r) in two buffers (r_k in f for even k, fo for odd k: the
+// preconditioner of step k takes the other one), the search direction in T
+// (two buffers); FP64 coefficients for the residual, T coefficients for
+// (p, A p).  Partial-sum scratch: fcg_partials doubles; fs: 4 doubles per
+// sample.
 int64_t fcg_partials(int n, int64_t Bc);
 template <typename T>
 struct FcgBufs {
     const T *a;             // V-cycle coefficients (level n)
     const double *a64;      // FP64 coefficients (level n)
     const T *z;             // preconditioner output
-    T *f, *fo;              // r and r_old
+    T *f, *fo;              // r_k for even and for odd k
     T *p0, *p1;             // search directions
     double *x0, *x1;        // iterates
     double *part, *fs, *rho;
     double *hist;           // stagnation state, 4 doubles per sample
     int32_t *active, *iters;
 };
-// r = 1 - A x0 (every sample), f = T(r), partial ||r||^2
+// r_0 = 1 - A x0 (every sample), f = T(r_0), partial ||r_0||^2
 template <typename T>
 void launch_fcg_resid(hipStream_t st, const double *a, const double *x, int n, int64_t Bc, T *f,
                       double *part);
@@ -176,7 +178,7 @@ void launch_fcg_resid(hipStream_t st, const double *a, const double *x, int n, i
 void launch_fcg_fin_rho(hipStream_t st, const double *part, int n, int64_t Bc, double *rho,
                         double *hist, int32_t *active, int32_t *iters, double rtol, int max_iters,
                         int first);
-// one step after z = B r: beta, p, alpha, x, new residual, convergence flags
+// step k after z = B r_{k-1}: beta, p, alpha, x, r_k, convergence flags
 template <typename T>
 void launch_fcg_step(hipStream_t st, const FcgBufs<T> &v, int n, int64_t Bc, double rtol,
                      int max_iters);

@@ -885,38 +885,132 @@ __global__ __launch_bounds__(LT, LT == 64 ? 4 : 1) void k_lds_fmg_refine(
 // ---------------------------------------------------------------------------
 // Flexible CG of one FMG stage on a large grid (the same iteration as the
 // LDS-resident kernel above), one pass per vector operation over all active
-// samples.  A block owns FCH consecutive cells of one sample and leaves one
-// compensated partial sum (or two) per block; a wavefront per sample folds the
-// partials in a fixed order, so every sum is reproducible.
-constexpr int FCH = 1024;                 // cells per block (256 threads x 4)
+// samples.  Geometry (grids n >= 64): a thread owns a quad of four
+// consecutive cells of a row and marches down the QH rows of its strip; the
+// 256 threads of a block take 256 consecutive quads of the sample's strip
+// space (quad g: strip g / (n/4), columns 4 (g mod n/4) .. +3), so a block
+// covers 1024 QH cells of one sample.  Quads are moved with 16-byte vector
+// loads and stores; a stencil pass keeps the rows above and below in
+// registers as it marches, takes the horizontal neighbours from the adjacent
+// lanes (a global load only at the two ends of a wavefront), and forms each
+// harmonic face weight once (an E face is the next cell's W face, an N face
+// the next row's S face: the same bits, hm being symmetric).  Every block
+// leaves one compensated partial sum (or two); a wavefront per sample folds
+// the partials in block order, so every sum is reproducible and a sample's
+// result does not depend on its batch.
+__host__ __device__ inline int fcg_qh(int n) { return n >= 128 ? 8 : 4; }
+__host__ __device__ inline int fcg_nch(int n) { return (int)((int64_t)n * n / (1024 * fcg_qh(n))); }
 
 struct FcgMap {
-    int64_t b, c0;   // sample, first cell of the block
+    int64_t b;       // sample
+    int blk;         // block of the sample (partial-sum index)
     int nch;         // blocks per sample
+    int i0, j0;      // first column and first row of the thread's quad strip
 };
+// Blocks are dealt round-robin over the 8 XCDs.  This bijection of a grid of
+// nb = 8 q + r blocks hands XCD x the contiguous logical range starting at
+// x q + min(x, r), so that the strips above and below a block's rows (the
+// stencil's neighbours) are read by blocks of the same XCD, through its L2.
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t bid, int64_t nb)
+{
+    const int64_t q = nb / 8, r = nb % 8, x = bid % 8;
+    return x * q + (x < r ? x : r) + bid / 8;
+}
+
+template <int QH>
 __device__ __forceinline__ bool fcg_map(int n, int64_t Bc, const int32_t *active, FcgMap &m)
 {
-    const int64_t cells = (int64_t)n * n;
-    m.nch = (int)((cells + FCH - 1) / FCH);
-    const int64_t bid = blockIdx.x;
-    m.b = bid / m.nch;
-    m.c0 = (bid - m.b * m.nch) * (int64_t)FCH;
+    m.nch = fcg_nch(n);
+    const int64_t L = xcd_contiguous(blockIdx.x, gridDim.x);
+    m.b = L / m.nch;
+    m.blk = (int)(L - m.b * m.nch);
     if (m.b >= Bc) return false;
+    const int W = n >> 2;                                  // quads per row
+    const int64_t g = (int64_t)m.blk * 256 + threadIdx.x;  // quad of the strip space
+    m.j0 = (int)(g / W) * QH;
+    m.i0 = (int)(g % W) * 4;
     return !active || active[m.b];
 }
 
-// (A u)_P in FP64 for cell p = i + n j of one sample (a, u at the sample base)
-template <typename TA>
-__device__ __forceinline__ double apply_cell(const TA *__restrict__ a, const double *__restrict__ u,
-                                             int n, int i, int j, int64_t p)
+template <typename T>
+__device__ __forceinline__ void ld4(const T *__restrict__ p, T (&v)[4])
 {
-    const double ap = double(a[p]), up = u[p];
-    double v = 0.0;   // net flux, face by face
-    v += (i + 1 < n) ? hm(ap, double(a[p + 1])) * (up - u[p + 1]) : 2.0 * ap * up;
-    v += (i > 0) ? hm(ap, double(a[p - 1])) * (up - u[p - 1]) : 2.0 * ap * up;
-    v += (j + 1 < n) ? hm(ap, double(a[p + n])) * (up - u[p + n]) : 2.0 * ap * up;
-    v += (j > 0) ? hm(ap, double(a[p - n])) * (up - u[p - n]) : 2.0 * ap * up;
-    return double(n) * double(n) * v;
+    if constexpr (sizeof(T) == 4) {
+        const float4 t = *(const float4 *)p;
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else {
+        const double2 t0 = *(const double2 *)p, t1 = *(const double2 *)(p + 2);
+        v[0] = t0.x; v[1] = t0.y; v[2] = t1.x; v[3] = t1.y;
+    }
+}
+template <typename T>
+__device__ __forceinline__ void st4(T *__restrict__ p, const T (&v)[4])
+{
+    if constexpr (sizeof(T) == 4) {
+        *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+        *(double2 *)p = make_double2(v[0], v[1]);
+        *(double2 *)(p + 2) = make_double2(v[2], v[3]);
+    }
+}
+
+// Values of a stencil pass on the quad rows of one sample: the coefficient
+// (TA) and the vector the operator is applied to (TV), formed from the
+// stored arrays by the functor (the iterate x + alpha p, or z + beta p).
+template <typename TA, typename TV>
+struct QuadRow {
+    TA a[4];
+    TV v[4];
+};
+
+// left/right neighbours (cells i0-1 and i0+4) of the quad row held by the
+// lanes of a wavefront; lanes at the wavefront's ends load them
+template <typename TA, typename TV, typename Get>
+__device__ __forceinline__ void row_ends(const QuadRow<TA, TV> &q, const TA *__restrict__ arow,
+                                         int64_t rowoff, int i0, int n, Get get, TA &al, TV &vl,
+                                         TA &ar, TV &vr)
+{
+    const int lane = threadIdx.x & 63;
+    al = __shfl_up(q.a[3], 1, 64);
+    vl = __shfl_up(q.v[3], 1, 64);
+    ar = __shfl_down(q.a[0], 1, 64);
+    vr = __shfl_down(q.v[0], 1, 64);
+    if (lane == 0 && i0 > 0) {
+        al = arow[i0 - 1];
+        vl = get(rowoff + i0 - 1);
+    }
+    if (lane == 63 && i0 + 4 < n) {
+        ar = arow[i0 + 4];
+        vr = get(rowoff + i0 + 4);
+    }
+}
+
+// Net flux h^2 (A v)_P of the four cells of a quad row, faces summed in the
+// order E, W, N, S (walls: 2 a_P v_P), as TS; hN[c] holds the N face weights
+// of this row on return (the S face weights of the next row)
+template <typename TS, typename TA, typename TV>
+__device__ __forceinline__ void quad_flux(const QuadRow<TA, TV> &c, TA al, TV vl, TA ar, TV vr,
+                                          const QuadRow<TA, TV> *up, const QuadRow<TA, TV> *dn,
+                                          TS (&hS)[4], TS (&hN)[4], int i0, int n, TS (&flux)[4])
+{
+    TS hx[5];   // faces between columns i0-1 | i0 | .. | i0+4
+    hx[0] = i0 > 0 ? hm(TS(al), TS(c.a[0])) : TS(0);
+#pragma unroll
+    for (int k = 1; k < 4; ++k) hx[k] = hm(TS(c.a[k - 1]), TS(c.a[k]));
+    hx[4] = i0 + 4 < n ? hm(TS(c.a[3]), TS(ar)) : TS(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const TS ap = TS(c.a[k]), xp = TS(c.v[k]);
+        const TS xe = k < 3 ? TS(c.v[k + 1]) : TS(vr);
+        const TS xw = k > 0 ? TS(c.v[k - 1]) : TS(vl);
+        hN[k] = up ? hm(ap, TS(up->a[k])) : TS(0);
+        TS v = TS(0);
+        v += (i0 + k + 1 < n) ? hx[k + 1] * (xp - xe) : TS(2) * ap * xp;
+        v += (i0 + k > 0) ? hx[k] * (xp - xw) : TS(2) * ap * xp;
+        v += up ? hN[k] * (xp - TS(up->v[k])) : TS(2) * ap * xp;
+        v += dn ? hS[k] * (xp - TS(dn->v[k])) : TS(2) * ap * xp;
+        flux[k] = v;
+    }
 }
 
 // block (256 threads) compensated sums of NV values -> out[2 NV] (sum, comp)
@@ -963,34 +1057,95 @@ __device__ __forceinline__ double fold_partials(const double *__restrict__ part,
     return s + c;
 }
 
-// Step k >= 1 of a stage (iters[b] = k while it runs).  The residual lives only
-// as f = T(r) (the preconditioner's right-hand side), r_old as T, the search
-// direction p as T in two buffers (p_k written from p_{k-1}), the iterate x in
+// Step k >= 1 of a stage (iters[b] = k while it runs; every active sample of
+// a chunk is at the same step).  The residual lives only as T(r), in two
+// buffers: r_k in F[k & 1] (F[0] = f, the stage's right-hand-side pool, holds
+// r_0), so the preconditioner of step k reads F[(k-1) & 1] and r_{k-2} is
+// still in F[k & 1] when the inner products of step k need it.  The search
+// direction p is T in two buffers (p_k written from p_{k-1}), the iterate x
 // FP64 in two buffers (x_k in X[k & 1], X[0] being the stage solution pool).
 // Inner products and step lengths see T-rounded r and p; the residual that
-// decides convergence is recomputed from x in FP64 with the FP64 coefficients.
+// decides convergence is recomputed from x in FP64 with the FP64
+// coefficients.
 
-// r = 1 - A x (FP64, from X[0]); f = TF(r); partial ||r||^2
-template <typename TF>
-__global__ __launch_bounds__(256) void k_fcg_resid(const double *__restrict__ a,
-                                                   const double *__restrict__ x, int n, int64_t Bc,
-                                                   TF *__restrict__ f, double *__restrict__ part)
+// x_k = x_{k-1} + alpha p_k into X[k & 1] and r = 1 - A x_k in FP64 (UPDATE),
+// or r = 1 - A x_0 (the stage's first residual, from X[0]); F[k & 1] = T(r),
+// partial ||r||^2
+template <typename T, int QH, bool UPDATE>
+__global__ __launch_bounds__(256, 4) void k_fcg_x(const double *__restrict__ a64, double *__restrict__ X0,
+                                               double *__restrict__ X1, const T *__restrict__ P0,
+                                               const T *__restrict__ P1, T *__restrict__ F0,
+                                               T *__restrict__ F1, int n, int64_t Bc,
+                                               const double *__restrict__ fs,
+                                               double *__restrict__ part,
+                                               const int32_t *__restrict__ active,
+                                               const int32_t *__restrict__ iters)
 {
     FcgMap m;
-    if (!fcg_map(n, Bc, nullptr, m)) return;
+    if (!fcg_map<QH>(n, Bc, UPDATE ? active : nullptr, m)) return;
     const int64_t cells = (int64_t)n * n, base = m.b * cells;
-    double s[1] = {0.0}, c[1] = {0.0};
+    const int k = UPDATE ? iters[m.b] : 0;
+    const double alpha = UPDATE ? fs[4 * m.b + 2] : 0.0;
+    const double *ab = a64 + base;
+    const double *xold = (UPDATE && ((k - 1) & 1) ? X1 : X0) + base;
+    double *xnew = (k & 1 ? X1 : X0) + base;
+    const T *pb = UPDATE ? (k & 1 ? P1 : P0) + base : nullptr;
+    T *fb = (k & 1 ? F1 : F0) + base;
+    auto xk = [&](int64_t q) {
+        return UPDATE ? xold[q] + alpha * double(pb[q]) : ((const double *)X0 + base)[q];
+    };
+    auto load = [&](int j, QuadRow<double, double> &r) {
+        const int64_t o = (int64_t)j * n + m.i0;
+        ld4(ab + o, r.a);
+        if (UPDATE) {
+            double xo[4];
+            T pp[4];
+            ld4(xold + o, xo);
+            ld4(pb + o, pp);
 #pragma unroll
-    for (int q = 0; q < FCH / 256; ++q) {
-        const int64_t p = m.c0 + threadIdx.x + 256 * q;
-        if (p < cells) {
-            const int j = (int)p >> __builtin_ctz(n), i = (int)p & (n - 1);
-            const double v = 1.0 - apply_cell(a + base, x + base, n, i, j, p);
-            f[base + p] = TF(v);
-            neumaier(s[0], c[0], v * v);
+            for (int c = 0; c < 4; ++c) r.v[c] = xo[c] + alpha * double(pp[c]);
+        } else {
+            ld4(X0 + base + o, r.v);
         }
+    };
+    const double n2 = double(n) * double(n);
+    // rows j-1, j, j+1 and j+2: the loads of row j+2 are in flight while row
+    // j is computed
+    QuadRow<double, double> prv, cur, nxt, nn;
+    double hS[4], hN[4];
+    load(m.j0, cur);
+    if (m.j0 + 1 < n) load(m.j0 + 1, nxt);
+    if (m.j0 > 0) {
+        load(m.j0 - 1, prv);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) hS[c] = hm(cur.a[c], prv.a[c]);
     }
-    block_partials<1>(s, c, part + (m.b * m.nch + m.c0 / FCH) * 2);
+    double s[1] = {0.0}, c[1] = {0.0};
+#pragma unroll 1
+    for (int t = 0; t < QH; ++t) {
+        const int j = m.j0 + t;
+        if (t + 1 < QH && j + 2 < n) load(j + 2, nn);
+        double al, vl, ar, vr;
+        row_ends(cur, ab + (int64_t)j * n, (int64_t)j * n, m.i0, n, xk, al, vl, ar, vr);
+        double flux[4];
+        quad_flux<double>(cur, al, vl, ar, vr, j + 1 < n ? &nxt : nullptr, j > 0 ? &prv : nullptr,
+                          hS, hN, m.i0, n, flux);
+        T fv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double r = 1.0 - n2 * flux[q];
+            fv[q] = T(r);
+            neumaier(s[0], c[0], r * r);
+            hS[q] = hN[q];
+        }
+        const int64_t o = (int64_t)j * n + m.i0;
+        if (UPDATE) st4(xnew + o, cur.v);
+        st4(fb + o, fv);
+        prv = cur;
+        cur = nxt;
+        nxt = nn;
+    }
+    block_partials<1>(s, c, part + (m.b * m.nch + m.blk) * 2);
 }
 
 // rho_b = ||r|| / ||1||.  first: every sample starts with iters = 0.  Then,
@@ -1006,8 +1161,7 @@ __global__ __launch_bounds__(256) void k_fcg_fin_rho(const double *__restrict__ 
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= Bc) return;
     if (!first && !active[b]) return;
-    const int nch = (int)(((int64_t)n * n + FCH - 1) / FCH);
-    const double v = sqrt(fold_partials<1>(part, b, nch, 0)) / (double)n;
+    const double v = sqrt(fold_partials<1>(part, b, fcg_nch(n), 0)) / (double)n;
     if ((threadIdx.x & 63) == 0) {
         const int it = first ? 0 : iters[b];
         // attainable accuracy: stop once four steps in a row have not brought
@@ -1029,31 +1183,35 @@ __global__ __launch_bounds__(256) void k_fcg_fin_rho(const double *__restrict__ 
     }
 }
 
-// partials of (r, z) and (r_old, z) (the second 0 at the first step); r_old = r
-template <typename T>
-__global__ __launch_bounds__(256) void k_fcg_dots(const T *__restrict__ z, const T *__restrict__ f,
-                                                  T *__restrict__ fo, int n, int64_t Bc,
+// partials of (r_{k-1}, z) and (r_{k-2}, z) (the second 0 at the first step)
+template <typename T, int QH>
+__global__ __launch_bounds__(256) void k_fcg_dots(const T *__restrict__ z, const T *__restrict__ F0,
+                                                  const T *__restrict__ F1, int n, int64_t Bc,
                                                   double *__restrict__ part,
                                                   const int32_t *__restrict__ active,
                                                   const int32_t *__restrict__ iters)
 {
     FcgMap m;
-    if (!fcg_map(n, Bc, active, m)) return;
+    if (!fcg_map<QH>(n, Bc, active, m)) return;
     const int64_t cells = (int64_t)n * n, base = m.b * cells;
-    const bool first = iters[m.b] == 1;
+    const int k = iters[m.b];
+    const T *rb = ((k - 1) & 1 ? F1 : F0) + base;
+    const T *rob = (k & 1 ? F1 : F0) + base;
     double s[2] = {0.0, 0.0}, c[2] = {0.0, 0.0};
+#pragma unroll 2
+    for (int t = 0; t < QH; ++t) {
+        const int64_t o = (int64_t)(m.j0 + t) * n + m.i0;
+        T zv[4], rv[4], ro[4];
+        ld4(z + base + o, zv);
+        ld4(rb + o, rv);
+        if (k > 1) ld4(rob + o, ro);
 #pragma unroll
-    for (int q = 0; q < FCH / 256; ++q) {
-        const int64_t p = m.c0 + threadIdx.x + 256 * q;
-        if (p < cells) {
-            const T rv = f[base + p];
-            const double zv = double(z[base + p]);
-            neumaier(s[0], c[0], double(rv) * zv);
-            neumaier(s[1], c[1], first ? 0.0 : double(fo[base + p]) * zv);
-            fo[base + p] = rv;
+        for (int q = 0; q < 4; ++q) {
+            neumaier(s[0], c[0], double(rv[q]) * double(zv[q]));
+            neumaier(s[1], c[1], k > 1 ? double(ro[q]) * double(zv[q]) : 0.0);
         }
     }
-    block_partials<2>(s, c, part + (m.b * m.nch + m.c0 / FCH) * 4);
+    block_partials<2>(s, c, part + (m.b * m.nch + m.blk) * 4);
 }
 
 // fs[b] = {rz, rz_old, alpha, beta}: rz = (r, z), beta = (rz - (r_old, z)) / rz_old
@@ -1064,7 +1222,7 @@ __global__ __launch_bounds__(256) void k_fcg_fin_beta(const double *__restrict__
 {
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= Bc || !active[b]) return;
-    const int nch = (int)(((int64_t)n * n + FCH - 1) / FCH);
+    const int nch = fcg_nch(n);
     const double rz = fold_partials<2>(part, b, nch, 0);
     const double rzo = fold_partials<2>(part, b, nch, 1);
     if ((threadIdx.x & 63) == 0) {
@@ -1074,9 +1232,11 @@ __global__ __launch_bounds__(256) void k_fcg_fin_beta(const double *__restrict__
 }
 
 // p_k = z + beta p_{k-1} (p_1 = z), written to P[k & 1]; partial (p_k, A p_k)
-// with the neighbours' p_k formed from z and p_{k-1} on the fly
-template <typename T>
-__global__ __launch_bounds__(256) void k_fcg_p(const T *__restrict__ a, const T *__restrict__ z,
+// with A p_k in the V-cycle type T (p is stored in T; the step length only
+// scales the update of the FP64 iterate, whose residual is recomputed in
+// FP64), the products summed in FP64
+template <typename T, int QH>
+__global__ __launch_bounds__(256, 4) void k_fcg_p(const T *__restrict__ a, const T *__restrict__ z,
                                                T *__restrict__ P0, T *__restrict__ P1, int n,
                                                int64_t Bc, const double *__restrict__ fs,
                                                double *__restrict__ part,
@@ -1084,35 +1244,56 @@ __global__ __launch_bounds__(256) void k_fcg_p(const T *__restrict__ a, const T 
                                                const int32_t *__restrict__ iters)
 {
     FcgMap m;
-    if (!fcg_map(n, Bc, active, m)) return;
+    if (!fcg_map<QH>(n, Bc, active, m)) return;
     const int64_t cells = (int64_t)n * n, base = m.b * cells;
     const int k = iters[m.b];
-    const double beta = k == 1 ? 0.0 : fs[4 * m.b + 3];
+    const T bt = T(k == 1 ? 0.0 : fs[4 * m.b + 3]);
     const T *ab = a + base, *zb = z + base;
     const T *pold = ((k - 1) & 1 ? P1 : P0) + base;
     T *pnew = (k & 1 ? P1 : P0) + base;
-    // p = z + beta p_old and A p in the V-cycle type T (p is stored in T; the
-    // step length only scales the update of the FP64 iterate, whose residual
-    // is recomputed in FP64), the products (p, A p) summed in FP64
-    const T bt = T(beta);
     auto pk = [&](int64_t q) { return k == 1 ? zb[q] : T(zb[q] + bt * pold[q]); };
-    double s[1] = {0.0}, c[1] = {0.0};
+    auto load = [&](int j, QuadRow<T, T> &r) {
+        const int64_t o = (int64_t)j * n + m.i0;
+        ld4(ab + o, r.a);
+        ld4(zb + o, r.v);
+        if (k > 1) {
+            T po[4];
+            ld4(pold + o, po);
 #pragma unroll
-    for (int qq = 0; qq < FCH / 256; ++qq) {
-        const int64_t p = m.c0 + threadIdx.x + 256 * qq;
-        if (p < cells) {
-            const int j = (int)p >> __builtin_ctz(n), i = (int)p & (n - 1);
-            const T ap = ab[p], pp = pk(p);
-            T v = T(0);   // net flux of p, face by face
-            v += (i + 1 < n) ? hm(ap, ab[p + 1]) * (pp - pk(p + 1)) : T(2) * ap * pp;
-            v += (i > 0) ? hm(ap, ab[p - 1]) * (pp - pk(p - 1)) : T(2) * ap * pp;
-            v += (j + 1 < n) ? hm(ap, ab[p + n]) * (pp - pk(p + n)) : T(2) * ap * pp;
-            v += (j > 0) ? hm(ap, ab[p - n]) * (pp - pk(p - n)) : T(2) * ap * pp;
-            pnew[p] = pp;
-            neumaier(s[0], c[0], double(pp) * double(n) * double(n) * double(v));
+            for (int c = 0; c < 4; ++c) r.v[c] = T(r.v[c] + bt * po[c]);
         }
+    };
+    const double n2 = double(n) * double(n);
+    QuadRow<T, T> prv, cur, nxt, nn;           // rows j-1 .. j+2 (j+2 in flight)
+    T hS[4], hN[4];
+    load(m.j0, cur);
+    if (m.j0 + 1 < n) load(m.j0 + 1, nxt);
+    if (m.j0 > 0) {
+        load(m.j0 - 1, prv);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) hS[c] = hm(cur.a[c], prv.a[c]);
     }
-    block_partials<1>(s, c, part + (m.b * m.nch + m.c0 / FCH) * 2);
+    double s[1] = {0.0}, c[1] = {0.0};
+#pragma unroll 1
+    for (int t = 0; t < QH; ++t) {
+        const int j = m.j0 + t;
+        if (t + 1 < QH && j + 2 < n) load(j + 2, nn);
+        T al, vl, ar, vr;
+        row_ends(cur, ab + (int64_t)j * n, (int64_t)j * n, m.i0, n, pk, al, vl, ar, vr);
+        T flux[4];
+        quad_flux<T>(cur, al, vl, ar, vr, j + 1 < n ? &nxt : nullptr, j > 0 ? &prv : nullptr, hS,
+                     hN, m.i0, n, flux);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            neumaier(s[0], c[0], double(cur.v[q]) * n2 * double(flux[q]));
+            hS[q] = hN[q];
+        }
+        st4(pnew + (int64_t)j * n + m.i0, cur.v);
+        prv = cur;
+        cur = nxt;
+        nxt = nn;
+    }
+    block_partials<1>(s, c, part + (m.b * m.nch + m.blk) * 2);
 }
 
 // alpha = rz / (p, A p); rz_old = rz
@@ -1122,69 +1303,29 @@ __global__ __launch_bounds__(256) void k_fcg_fin_alpha(const double *__restrict_
 {
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= Bc || !active[b]) return;
-    const int nch = (int)(((int64_t)n * n + FCH - 1) / FCH);
-    const double pq = fold_partials<1>(part, b, nch, 0);
+    const double pq = fold_partials<1>(part, b, fcg_nch(n), 0);
     if ((threadIdx.x & 63) == 0) {
         fs[4 * b + 2] = fs[4 * b] / pq;
         fs[4 * b + 1] = fs[4 * b];
     }
 }
 
-// x_k = x_{k-1} + alpha p_k into X[k & 1]; r = 1 - A x_k in FP64 (neighbours'
-// x_k formed on the fly) -> f = T(r); partial ||r||^2
-template <typename T>
-__global__ __launch_bounds__(256) void k_fcg_x(const double *__restrict__ a64, double *__restrict__ X0,
-                                               double *__restrict__ X1, const T *__restrict__ P0,
-                                               const T *__restrict__ P1, T *__restrict__ f, int n,
-                                               int64_t Bc, const double *__restrict__ fs,
-                                               double *__restrict__ part,
-                                               const int32_t *__restrict__ active,
-                                               const int32_t *__restrict__ iters)
-{
-    FcgMap m;
-    if (!fcg_map(n, Bc, active, m)) return;
-    const int64_t cells = (int64_t)n * n, base = m.b * cells;
-    const int k = iters[m.b];
-    const double alpha = fs[4 * m.b + 2];
-    const double *ab = a64 + base;
-    const double *xold = ((k - 1) & 1 ? X1 : X0) + base;
-    double *xnew = (k & 1 ? X1 : X0) + base;
-    const T *pb = (k & 1 ? P1 : P0) + base;
-    auto xk = [&](int64_t q) { return xold[q] + alpha * double(pb[q]); };
-    double s[1] = {0.0}, c[1] = {0.0};
-#pragma unroll
-    for (int qq = 0; qq < FCH / 256; ++qq) {
-        const int64_t p = m.c0 + threadIdx.x + 256 * qq;
-        if (p < cells) {
-            const int j = (int)p >> __builtin_ctz(n), i = (int)p & (n - 1);
-            const double ap = ab[p], xp = xk(p);
-            double v = 0.0;   // net flux of x_k, face by face
-            v += (i + 1 < n) ? hm(ap, ab[p + 1]) * (xp - xk(p + 1)) : 2.0 * ap * xp;
-            v += (i > 0) ? hm(ap, ab[p - 1]) * (xp - xk(p - 1)) : 2.0 * ap * xp;
-            v += (j + 1 < n) ? hm(ap, ab[p + n]) * (xp - xk(p + n)) : 2.0 * ap * xp;
-            v += (j > 0) ? hm(ap, ab[p - n]) * (xp - xk(p - n)) : 2.0 * ap * xp;
-            const double r = 1.0 - double(n) * double(n) * v;
-            xnew[p] = xp;
-            f[base + p] = T(r);
-            neumaier(s[0], c[0], r * r);
-        }
-    }
-    block_partials<1>(s, c, part + (m.b * m.nch + m.c0 / FCH) * 2);
-}
-
 // samples whose last step wrote X[1]: copy it to the stage solution X[0]
+template <int QH>
 __global__ __launch_bounds__(256) void k_fcg_copyback(double *__restrict__ X0,
                                                       const double *__restrict__ X1, int n,
                                                       int64_t Bc, const int32_t *__restrict__ iters)
 {
     FcgMap m;
-    if (!fcg_map(n, Bc, nullptr, m)) return;
+    if (!fcg_map<QH>(n, Bc, nullptr, m)) return;
     if (!(iters[m.b] & 1)) return;
-    const int64_t cells = (int64_t)n * n, base = m.b * cells;
-#pragma unroll
-    for (int q = 0; q < FCH / 256; ++q) {
-        const int64_t p = m.c0 + threadIdx.x + 256 * q;
-        if (p < cells) X0[base + p] = X1[base + p];
+    const int64_t base = m.b * (int64_t)n * n;
+#pragma unroll 2
+    for (int t = 0; t < QH; ++t) {
+        const int64_t o = base + (int64_t)(m.j0 + t) * n + m.i0;
+        double v[4];
+        ld4(X1 + o, v);
+        st4(X0 + o, v);
     }
 }
 
@@ -1294,14 +1435,28 @@ void launch_lds_fmg_refine(hipStream_t st, const T *a_pool, const double *a64_po
 }
 #undef MLMC_LDS_DISPATCH
 
-int64_t fcg_partials(int n, int64_t Bc) { return Bc * (((int64_t)n * n + FCH - 1) / FCH) * 4; }
+int64_t fcg_partials(int n, int64_t Bc) { return Bc * fcg_nch(n) * 4; }
+
+// the CG passes' strip height: 4 rows on 64^2 (one block per sample), 8 above
+#define MLMC_FCG_QH(n, LAUNCH)      \
+    do {                            \
+        if (fcg_qh(n) == 4) {       \
+            constexpr int QH = 4;   \
+            LAUNCH;                 \
+        } else {                    \
+            constexpr int QH = 8;   \
+            LAUNCH;                 \
+        }                           \
+    } while (0)
 
 template <typename T>
 void launch_fcg_resid(hipStream_t st, const double *a, const double *x, int n, int64_t Bc, T *f,
                       double *part)
 {
-    const int64_t nb = Bc * (((int64_t)n * n + FCH - 1) / FCH);
-    hipLaunchKernelGGL((k_fcg_resid<T>), dim3(nblocks(nb)), dim3(256), 0, st, a, x, n, Bc, f, part);
+    const unsigned nb = nblocks(Bc * fcg_nch(n));
+    MLMC_FCG_QH(n, hipLaunchKernelGGL((k_fcg_x<T, QH, false>), dim3(nb), dim3(256), 0, st, a,
+                                      const_cast<double *>(x), nullptr, nullptr, nullptr, f,
+                                      nullptr, n, Bc, nullptr, part, nullptr, nullptr));
 }
 
 void launch_fcg_fin_rho(hipStream_t st, const double *part, int n, int64_t Bc, double *rho,
@@ -1316,17 +1471,18 @@ template <typename T>
 void launch_fcg_step(hipStream_t st, const FcgBufs<T> &v, int n, int64_t Bc, double rtol,
                      int max_iters)
 {
-    const unsigned nb = nblocks(Bc * (((int64_t)n * n + FCH - 1) / FCH));
+    const unsigned nb = nblocks(Bc * fcg_nch(n));
     const unsigned ns = blocks_of(Bc, 4);
-    hipLaunchKernelGGL((k_fcg_dots<T>), dim3(nb), dim3(256), 0, st, v.z, v.f, v.fo, n, Bc, v.part,
-                       v.active, v.iters);
+    MLMC_FCG_QH(n, hipLaunchKernelGGL((k_fcg_dots<T, QH>), dim3(nb), dim3(256), 0, st, v.z, v.f,
+                                      v.fo, n, Bc, v.part, v.active, v.iters));
     hipLaunchKernelGGL(k_fcg_fin_beta, dim3(ns), dim3(256), 0, st, v.part, n, Bc, v.fs, v.active,
                        v.iters);
-    hipLaunchKernelGGL((k_fcg_p<T>), dim3(nb), dim3(256), 0, st, v.a, v.z, v.p0, v.p1, n, Bc, v.fs,
-                       v.part, v.active, v.iters);
+    MLMC_FCG_QH(n, hipLaunchKernelGGL((k_fcg_p<T, QH>), dim3(nb), dim3(256), 0, st, v.a, v.z, v.p0,
+                                      v.p1, n, Bc, v.fs, v.part, v.active, v.iters));
     hipLaunchKernelGGL(k_fcg_fin_alpha, dim3(ns), dim3(256), 0, st, v.part, n, Bc, v.fs, v.active);
-    hipLaunchKernelGGL((k_fcg_x<T>), dim3(nb), dim3(256), 0, st, v.a64, v.x0, v.x1, v.p0, v.p1, v.f,
-                       n, Bc, v.fs, v.part, v.active, v.iters);
+    MLMC_FCG_QH(n, hipLaunchKernelGGL((k_fcg_x<T, QH, true>), dim3(nb), dim3(256), 0, st, v.a64,
+                                      v.x0, v.x1, v.p0, v.p1, v.f, v.fo, n, Bc, v.fs, v.part,
+                                      v.active, v.iters));
     hipLaunchKernelGGL(k_fcg_fin_rho, dim3(ns), dim3(256), 0, st, v.part, n, Bc, v.rho, v.hist, v.active,
                        v.iters, rtol, max_iters, 0);
 }
@@ -1334,9 +1490,11 @@ void launch_fcg_step(hipStream_t st, const FcgBufs<T> &v, int n, int64_t Bc, dou
 void launch_fcg_copyback(hipStream_t st, double *x0, const double *x1, int n, int64_t Bc,
                          const int32_t *iters)
 {
-    const int64_t nb = Bc * (((int64_t)n * n + FCH - 1) / FCH);
-    hipLaunchKernelGGL(k_fcg_copyback, dim3(nblocks(nb)), dim3(256), 0, st, x0, x1, n, Bc, iters);
+    const unsigned nb = nblocks(Bc * fcg_nch(n));
+    MLMC_FCG_QH(n, hipLaunchKernelGGL((k_fcg_copyback<QH>), dim3(nb), dim3(256), 0, st, x0, x1, n,
+                                      Bc, iters));
 }
+#undef MLMC_FCG_QH
 
 void launch_refine_stats(hipStream_t st, const int32_t *iters, const double *rho, int64_t Bc,
                          double rtol, int32_t *st_iters, double *st_rho, int32_t *st_bad)
