@@ -188,6 +188,21 @@ mlmc_status mlmc_points_gen(mlmc_ctx ctx, const mlmc_points *pts,
 mlmc_status mlmc_field(mlmc_ctx ctx, const mlmc_points *pts, double *z_dev,
                        void *hip_stream);
 
+/* mlmc_field for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same z, bit for bit, with the points' staging (Y for lattice points) and,
+ * in a MIXED context, their digits and scale exponents held in a static
+ * device array of the library (32 MiB per GPU, resolved once per device at
+ * mlmc_create and held until the process ends) instead of the context's
+ * workspace.  The call allocates nothing.  E_INVAL if the set needs more
+ * than the 32 MiB: 8 B s per lattice sample, plus in a MIXED context 10 B
+ * per padded sample row and mode (rows padded to 64, modes to 32) and 4 B
+ * per padded row, each part rounded up to 256 bytes.  Every call on a GPU
+ * shares that GPU's array: calls whose device work overlaps (on different
+ * streams or host threads) race; calls ordered on one stream do not. */
+mlmc_status mlmc_field_static(mlmc_ctx ctx, const mlmc_points *pts, double *z_dev,
+                              void *hip_stream);
+
 /* The hot path for one set of samples (Algorithm 1, SampleAndSolve body):
  * field (unless z_dev is given) -> a = exp(z) -> FMG from the 2x2 grid up to
  * level g0+pts->level, recording the QoI at the end of every stage that is an

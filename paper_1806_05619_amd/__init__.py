@@ -102,7 +102,7 @@ EXPORTS = [
     "mlmc_status_str", "mlmc_last_error", "mlmc_profile_begin", "mlmc_profile_end",
     "mlmc_server_create", "mlmc_server_destroy", "mlmc_server_submit", "mlmc_server_poll",
     "mlmc_server_stats_get", "mlmc_server_capacity", "mlmc_autotune", "mlmc_tuning_get",
-    "mlmc_tuning_set",
+    "mlmc_tuning_set", "mlmc_field_static",
 ]
 
 _lib = None
@@ -130,6 +130,7 @@ def lib():
         "mlmc_num_qoi": (i32, [vp]),
         "mlmc_points_gen": (i32, [vp, C.POINTER(mlmc_points), vp, vp, vp]),
         "mlmc_field": (i32, [vp, C.POINTER(mlmc_points), vp, vp]),
+        "mlmc_field_static": (i32, [vp, C.POINTER(mlmc_points), vp, vp]),
         "mlmc_fmg_solve": (i32, [vp, C.POINTER(mlmc_points), vp, vp, vp,
                                  C.POINTER(mlmc_solve_info), vp]),
         "mlmc_estimate": (i32, [C.POINTER(mlmc_est_input), C.POINTER(mlmc_est_output)]),
@@ -273,6 +274,10 @@ class Context:
 
     def field(self, pts, z):
         _check(lib().mlmc_field(self._h, C.byref(pts), _ptr(z), self._stream()), self._h)
+
+    def field_static(self, pts, z):
+        """mlmc_field_static: the field with no allocation (static scratch)."""
+        _check(lib().mlmc_field_static(self._h, C.byref(pts), _ptr(z), self._stream()), self._h)
 
     def fmg_solve(self, pts, z=None, qoi=None, sums=None, want_info=False):
         info = mlmc_solve_info()

@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include <new>
 #include <string>
@@ -83,6 +85,36 @@ struct mlmc_ctx_s {
 namespace {
 
 thread_local std::string g_create_error;
+
+// Device memory of mlmc_field_static, for callers that cannot allocate: one
+// copy per GPU, held until the process ends.  Its host-side name is not a
+// device address: kernels get the address resolved per device at context
+// creation (static_scratch_ptr), never the symbol.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;      // device -> address of its copy
+
+// resolve (once per device, with that device current) the device address of
+// the static scratch; "" on success
+std::string resolve_static_scratch(int device)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr.count(device)) return "";
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    g_scratch_ptr[device] = p;
+    return "";
+}
+
+void *static_scratch_ptr(int device)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
 
 const char *kStatusText[] = {"ok", "invalid argument", "out of device memory", "HIP error",
                              "not converged", "context unusable"};
@@ -778,7 +810,14 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
     } while (0)
 
     ctx->host_only = device < 0;
-    if (!ctx->host_only) CHK(hipSetDevice(device));
+    if (!ctx->host_only) {
+        CHK(hipSetDevice(device));
+        const std::string serr = resolve_static_scratch(device);
+        if (!serr.empty()) {
+            ctx->err = serr;
+            return fail(MLMC_E_HIP);
+        }
+    }
 
     // KL mode table: the s largest products theta_i theta_j (i, j <= s),
     // descending, exact ties ordered by i ascending (separable kernel; the
@@ -1256,6 +1295,79 @@ mlmc_status mlmc_field(mlmc_ctx ctx, const mlmc_points *pts, double *z_dev, void
             field_digits(ctx, s, Y, M, Bc, z_dev + b0 * M, nullptr, 0);
         else
             launch_field_gemm(s, Y, ctx->cfg.s, ctx->d_basis, ctx->Mmax, M, Bc, z_dev + b0 * M, 0);
+    }
+    HIPCHK(ctx, hipGetLastError());
+    return MLMC_OK;
+}
+
+// mlmc_field with the staging of the points (Y for lattice points) and, in
+// a mixed context, of their bf16 digits and scale exponents in the static
+// scratch instead of the context's workspace.  Layout (each part aligned to
+// 256 bytes): Y [B][s] FP64 (lattice points only), then kDigits digit arrays
+// [B_pad][sp] and the exponents [B_pad].
+static int64_t static_field_bytes(mlmc_ctx c, int64_t B, bool lattice)
+{
+    auto up = [](int64_t v) { return (v + 255) / 256 * 256; };
+    int64_t bytes = lattice ? up(8 * B * c->cfg.s) : 0;
+    if (c->cfg.precision == MLMC_MIXED) {
+        const int64_t rows = mixed_pad_rows(B);
+        bytes += kDigits * up(2 * rows * c->sp) + up(4 * rows);
+    }
+    return bytes;
+}
+
+mlmc_status mlmc_field_static(mlmc_ctx ctx, const mlmc_points *pts, double *z_dev,
+                              void *hip_stream)
+{
+    if (!ctx) return MLMC_E_INVAL;
+    if (ctx->broken || ctx->host_only) return MLMC_E_STATE;
+    int64_t B, npts;
+    int nsh;
+    mlmc_status st = check_points(ctx, pts, &B, &npts, &nsh);
+    if (st) return st;
+    if (!z_dev && B > 0) return inval(ctx, "z_dev is NULL");
+    const bool lattice = pts->kind == MLMC_POINTS_LATTICE;
+    if (static_field_bytes(ctx, B, lattice) > (int64_t)kStaticScratchBytes) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "mlmc_field_static: %lld samples need %lld bytes of scratch, "
+                 "more than its %zu", (long long)B, (long long)static_field_bytes(ctx, B, lattice),
+                 kStaticScratchBytes);
+        ctx->err = msg;
+        return MLMC_E_INVAL;
+    }
+    if (B == 0) return MLMC_OK;
+    unsigned char *base = (unsigned char *)static_scratch_ptr(ctx->device);
+    if (!base) {
+        ctx->err = "static scratch not resolved on this device";
+        return MLMC_E_STATE;
+    }
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    auto up = [](int64_t v) { return (v + 255) / 256 * 256; };
+    const int sd = ctx->cfg.s;
+    const int64_t M = field_size_g(ctx->g0 + pts->level);
+    const double *Y = pts->y_dev;
+    int64_t off = 0;
+    if (lattice) {
+        double *y = (double *)base;
+        launch_points(s, ctx->d_z, ctx->d_shifts, sd, ctx->cfg.num_shifts, pts->level,
+                      pts->shift_begin, pts->n_begin, npts, 0, B, nullptr, y);
+        Y = y;
+        off = up(8 * B * sd);
+    }
+    if (ctx->cfg.precision == MLMC_MIXED) {
+        const int64_t rows = mixed_pad_rows(B);
+        uint16_t *dig[kDigits];
+        for (int q = 0; q < kDigits; ++q) {
+            dig[q] = (uint16_t *)(base + off);
+            off += up(2 * rows * ctx->sp);
+        }
+        int32_t *ey = (int32_t *)(base + off);
+        launch_digits_rows(s, Y, B, sd, sd, rows, ctx->sp, dig, ey);
+        launch_field_digits(s, dig, ey, ctx->d_bdig, ctx->d_bexp, ctx->sp, M, B, z_dev, nullptr,
+                            0);
+    } else {
+        launch_field_gemm(s, Y, sd, ctx->d_basis, ctx->Mmax, M, B, z_dev, 0);
     }
     HIPCHK(ctx, hipGetLastError());
     return MLMC_OK;
