@@ -51,9 +51,8 @@ BYTE_MODEL = dict(
     pre="a, u (unless zero or interpolated), f (unless 1) read, u written, f_c written (w/4)",
     post="e_c (w/4), a, u, f (unless 1) read, u written",
     lds="coefficients of the LDS grids read, top-level solution written",
-    refine="one flexible-CG step: dots (z, r, r_old read), p and (p, A p) (a, z, p read, p "
-           "written), x and r (a, x in FP64 and p read, x in FP64 and r written): 24 + 9 w B "
-           "per cell")
+    refine="24 + 9w B per cell of the samples still iterating (24 + 7w at a stage's first "
+           "step), w = V-cycle word size")
 
 KINDS = ("points", "field", "smooth", "restrict", "prolong", "coarse", "qoi", "sums", "pre", "post",
          "lds", "refine")
@@ -67,8 +66,7 @@ KERNEL_NAMES = dict(
     post="post pass (prolongation + correction + 2 sweeps): k_post_tile / k_stream on every "
          "grid above the LDS-resident ones",
     lds="k_lds_fmg_refine, k_lds_vcycle (LDS-resident grids <= 32^2)",
-    refine="flexible-CG step on grids >= 64^2: k_fcg_dots, k_fcg_p, k_fcg_x and the "
-           "per-sample scalar folds between them")
+    refine="one flexible-CG step (>= 64^2): k_fcg_dots + k_fcg_p + k_fcg_x + folds")
 
 
 def log(*a):
@@ -78,8 +76,7 @@ def log(*a):
 # HBM bytes per launch of a kernel from two rocprofv3 --pmc passes (FETCH_SIZE,
 # WRITE_SIZE), scaled by the same counters on a 1 GiB copy; valid only while
 # the kernel source is the one the counters were taken on.
-TRAFFIC_RECORDS = dict(pre="profiles/pre_pass_mlqmc_fp64_s100_256_traffic.txt",
-                       post="profiles/post_pass_mlqmc_fp64_s100_256_traffic.txt")
+TRAFFIC_RECORDS = dict(refine="profiles/refine_step_mlqmc_mixed_s400_1024_traffic.txt")
 
 
 def measured_traffic(kind):
@@ -784,7 +781,7 @@ def main():
                steps=args.steps, warmup=args.warmup,
                ms_per_step=round(mixed["elapsed"] * 1e3 / args.steps, 3),
                higher_is_better=True, scaling="weak", vs_baseline=None,
-               dtype="mixed: bf16 digit products (field), f32 V-cycles, f64 refinement and sums",
+               dtype="mixed: bf16 field digits, f32 V-cycles, f64 CG and sums",
                data="synthetic",
                config=dict(workload=f"mlqmc_mixed_s400 at {n}^2: s = 400, lambda 0.1, sigma^2 2, "
                                     f"MLMC levels 4^2..{n}^2, every FMG stage to rtol 1e-10",

@@ -305,11 +305,15 @@ enum {
                               read, f of its top grid read (V-cycle mode), u of
                               its top grid written */
     MLMC_KERNEL_REFINE = 11 /* rtol mode on grids >= 64^2, one flexible-CG step
-                              after the V-cycle, per cell: dots (z, r, r_old
-                              read), p with (p, A p) (a, z, previous p read; p
-                              written), x with the new residual (FP64 a, x, p
-                              read; x, r written): 24 + 9 w bytes, w the
-                              V-cycle word size */
+                              after the V-cycle, per cell of the samples still
+                              iterating: dots (z, r, r_old read), p with
+                              (p, A p) (a, z, previous p read; p written), x
+                              with the new residual (FP64 a, x, p read; x, r
+                              written): 24 + 9 w bytes, w the V-cycle word
+                              size (24 + 7 w at a stage's first step, which
+                              has no r_old or previous p).  The PRE, POST and
+                              LDS passes of a refinement step count only the
+                              samples still iterating, too */
 };
 typedef struct {
     int64_t launches;

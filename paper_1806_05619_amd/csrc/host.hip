@@ -522,14 +522,18 @@ struct FusedRunner {
     HierT<T> h;
     int Gs;
     static constexpr double W = sizeof(T);
+    // samples the masked passes work on (the active ones of a refinement
+    // step; -1: the whole chunk), for the profiled byte counts
+    int64_t nact = -1;
 
-    double cells(int n) const { return (double)h.Bc * n * n; }
+    double samples() const { return (double)(nact >= 0 ? nact : h.Bc); }
+    double cells(int n) const { return samples() * n * n; }
 
     // one V-cycle on the LDS-resident levels <= Gs (zero guess, f from the pool)
     void lds_vcycle(const int32_t *active)
     {
         const int n = 2 << Gs;
-        ProfScope ps(c, st, MLMC_KERNEL_LDS, W * h.Bc * level_offset(Gs + 1) + W * cells(n) * 2.0, 0.0);
+        ProfScope ps(c, st, MLMC_KERNEL_LDS, W * samples() * level_offset(Gs + 1) + W * cells(n) * 2.0, 0.0);
         launch_lds_vcycle<T>(st, h.a[0], h.f[0], h.u[0], h.Bc, Gs, c->cfg.mu1, c->cfg.mu2, active);
     }
 
@@ -663,13 +667,17 @@ mlmc_status run_fmg_refine(mlmc_ctx c, hipStream_t st, int G, int64_t Bc, int k,
             if (nact == 0) break;
             // every active sample is at this step; its residual r_{step-1}
             // is in f for odd steps and in fo for even ones
+            R.nact = nact;
             R.vcycle(g, h.u[g], 1, (step & 1) ? v.f : v.fo, c->d_active);
             {
-                // dots: z, r, r_old read; p: a, z, p_prev read, p written;
-                // x: a (FP64), x_prev, p read, x and r written
-                ProfScope ps(c, st, MLMC_KERNEL_REFINE, vec * (24.0 + 9.0 * R.W), 0.0);
+                // per cell of the active samples: dots: z, r, r_old read; p:
+                // a, z, p_prev read, p written; x: a (FP64), x_prev, p read,
+                // x and r written (no r_old or p_prev at the first step)
+                ProfScope ps(c, st, MLMC_KERNEL_REFINE,
+                             R.cells(n) * (24.0 + (step > 1 ? 9.0 : 7.0) * R.W), 0.0);
                 launch_fcg_step<T>(st, v, n, Bc, c->cfg.rtol, c->cfg.max_iters);
             }
+            R.nact = -1;
         }
         launch_fcg_copyback(st, h.w[g], v.x1, n, Bc, c->d_iters);
         launch_refine_stats(st, c->d_iters, c->d_rho, Bc, c->cfg.rtol, c->d_st_iters, c->d_st_rho,

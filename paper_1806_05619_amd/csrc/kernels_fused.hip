@@ -885,27 +885,30 @@ __global__ __launch_bounds__(LT, LT == 64 ? 4 : 1) void k_lds_fmg_refine(
 // ---------------------------------------------------------------------------
 // Flexible CG of one FMG stage on a large grid (the same iteration as the
 // LDS-resident kernel above), one pass per vector operation over all active
-// samples.  Geometry (grids n >= 64): a thread owns a quad of four
-// consecutive cells of a row and marches down the QH rows of its strip; the
-// 256 threads of a block take 256 consecutive quads of the sample's strip
-// space (quad g: strip g / (n/4), columns 4 (g mod n/4) .. +3), so a block
-// covers 1024 QH cells of one sample.  Quads are moved with 16-byte vector
-// loads and stores; a stencil pass keeps the rows above and below in
-// registers as it marches, takes the horizontal neighbours from the adjacent
+// samples.  Geometry (grids n >= 64): a thread owns CW consecutive cells of a
+// row, CW = 16 bytes over the widest element type the pass moves (2 for
+// FP64 arrays, 4 for FP32), so that each lane of a wavefront loads and stores
+// 16 contiguous bytes per array and row; it marches down the QH = 4 q / CW
+// rows of its strip (q = 4 on 64^2, 8 above).  The 256 threads of a block
+// take 256 consecutive cell groups of the sample's strip space (group g:
+// strip g / (n/CW), columns CW (g mod n/CW) .. +CW-1), so every pass covers
+// 1024 q cells per block and n^2 / (1024 q) blocks per sample.  A stencil
+// pass keeps the rows above and below in registers as it marches (the row
+// two ahead in flight), takes the horizontal neighbours from the adjacent
 // lanes (a global load only at the two ends of a wavefront), and forms each
 // harmonic face weight once (an E face is the next cell's W face, an N face
 // the next row's S face: the same bits, hm being symmetric).  Every block
 // leaves one compensated partial sum (or two); a wavefront per sample folds
 // the partials in block order, so every sum is reproducible and a sample's
 // result does not depend on its batch.
-__host__ __device__ inline int fcg_qh(int n) { return n >= 128 ? 8 : 4; }
-__host__ __device__ inline int fcg_nch(int n) { return (int)((int64_t)n * n / (1024 * fcg_qh(n))); }
+__host__ __device__ inline int fcg_q(int n) { return n >= 128 ? 8 : 4; }
+__host__ __device__ inline int fcg_nch(int n) { return (int)((int64_t)n * n / (1024 * fcg_q(n))); }
 
 struct FcgMap {
     int64_t b;       // sample
     int blk;         // block of the sample (partial-sum index)
     int nch;         // blocks per sample
-    int i0, j0;      // first column and first row of the thread's quad strip
+    int i0, j0;      // first column and first row of the thread's strip
 };
 // Blocks are dealt round-robin over the 8 XCDs.  This bijection of a grid of
 // nb = 8 q + r blocks hands XCD x the contiguous logical range starting at
@@ -917,7 +920,7 @@ __device__ __forceinline__ int64_t xcd_contiguous(int64_t bid, int64_t nb)
     return x * q + (x < r ? x : r) + bid / 8;
 }
 
-template <int QH>
+template <int CW, int QH>
 __device__ __forceinline__ bool fcg_map(int n, int64_t Bc, const int32_t *active, FcgMap &m)
 {
     m.nch = fcg_nch(n);
@@ -925,90 +928,101 @@ __device__ __forceinline__ bool fcg_map(int n, int64_t Bc, const int32_t *active
     m.b = L / m.nch;
     m.blk = (int)(L - m.b * m.nch);
     if (m.b >= Bc) return false;
-    const int W = n >> 2;                                  // quads per row
-    const int64_t g = (int64_t)m.blk * 256 + threadIdx.x;  // quad of the strip space
+    const int W = n / CW;                                  // cell groups per row
+    const int64_t g = (int64_t)m.blk * 256 + threadIdx.x;  // group of the strip space
     m.j0 = (int)(g / W) * QH;
-    m.i0 = (int)(g % W) * 4;
+    m.i0 = (int)(g % W) * CW;
     return !active || active[m.b];
 }
 
-template <typename T>
-__device__ __forceinline__ void ld4(const T *__restrict__ p, T (&v)[4])
+// CW consecutive elements as 16 bytes (or 8 for two floats)
+template <int CW, typename T>
+__device__ __forceinline__ void ldv(const T *__restrict__ p, T (&v)[CW])
 {
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 4 && CW == 4) {
         const float4 t = *(const float4 *)p;
         v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else if constexpr (sizeof(T) == 4 && CW == 2) {
+        const float2 t = *(const float2 *)p;
+        v[0] = t.x; v[1] = t.y;
     } else {
-        const double2 t0 = *(const double2 *)p, t1 = *(const double2 *)(p + 2);
-        v[0] = t0.x; v[1] = t0.y; v[2] = t1.x; v[3] = t1.y;
+        static_assert(sizeof(T) == 8 && CW == 2, "FP64 cell groups are pairs");
+        const double2 t = *(const double2 *)p;
+        v[0] = t.x; v[1] = t.y;
     }
 }
-template <typename T>
-__device__ __forceinline__ void st4(T *__restrict__ p, const T (&v)[4])
+template <int CW, typename T>
+__device__ __forceinline__ void stv(T *__restrict__ p, const T (&v)[CW])
 {
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 4 && CW == 4) {
         *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
+    } else if constexpr (sizeof(T) == 4 && CW == 2) {
+        *(float2 *)p = make_float2(v[0], v[1]);
     } else {
+        static_assert(sizeof(T) == 8 && CW == 2, "FP64 cell groups are pairs");
         *(double2 *)p = make_double2(v[0], v[1]);
-        *(double2 *)(p + 2) = make_double2(v[2], v[3]);
     }
 }
 
-// Values of a stencil pass on the quad rows of one sample: the coefficient
-// (TA) and the vector the operator is applied to (TV), formed from the
-// stored arrays by the functor (the iterate x + alpha p, or z + beta p).
-template <typename TA, typename TV>
-struct QuadRow {
-    TA a[4];
-    TV v[4];
+// One row of a thread's cell group in a stencil pass: the coefficient (TA)
+// and the vector the operator is applied to (TV), formed from the stored
+// arrays (the iterate x + alpha p, or z + beta p).
+template <typename TA, typename TV, int CW>
+struct GroupRow {
+    TA a[CW];
+    TV v[CW];
 };
 
-// left/right neighbours (cells i0-1 and i0+4) of the quad row held by the
+// left/right neighbours (cells i0-1 and i0+CW) of the group row held by the
 // lanes of a wavefront; lanes at the wavefront's ends load them
-template <typename TA, typename TV, typename Get>
-__device__ __forceinline__ void row_ends(const QuadRow<TA, TV> &q, const TA *__restrict__ arow,
+template <int CW, typename TA, typename TV, typename Get>
+__device__ __forceinline__ void row_ends(const GroupRow<TA, TV, CW> &q, const TA *__restrict__ arow,
                                          int64_t rowoff, int i0, int n, Get get, TA &al, TV &vl,
                                          TA &ar, TV &vr)
 {
     const int lane = threadIdx.x & 63;
-    al = __shfl_up(q.a[3], 1, 64);
-    vl = __shfl_up(q.v[3], 1, 64);
+    al = __shfl_up(q.a[CW - 1], 1, 64);
+    vl = __shfl_up(q.v[CW - 1], 1, 64);
     ar = __shfl_down(q.a[0], 1, 64);
     vr = __shfl_down(q.v[0], 1, 64);
     if (lane == 0 && i0 > 0) {
         al = arow[i0 - 1];
         vl = get(rowoff + i0 - 1);
     }
-    if (lane == 63 && i0 + 4 < n) {
-        ar = arow[i0 + 4];
-        vr = get(rowoff + i0 + 4);
+    if (lane == 63 && i0 + CW < n) {
+        ar = arow[i0 + CW];
+        vr = get(rowoff + i0 + CW);
     }
 }
 
-// Net flux h^2 (A v)_P of the four cells of a quad row, faces summed in the
-// order E, W, N, S (walls: 2 a_P v_P), as TS; hN[c] holds the N face weights
-// of this row on return (the S face weights of the next row)
-template <typename TS, typename TA, typename TV>
-__device__ __forceinline__ void quad_flux(const QuadRow<TA, TV> &c, TA al, TV vl, TA ar, TV vr,
-                                          const QuadRow<TA, TV> *up, const QuadRow<TA, TV> *dn,
-                                          TS (&hS)[4], TS (&hN)[4], int i0, int n, TS (&flux)[4])
+// Net flux h^2 (A v)_P of the cells of a group row, faces summed in the
+// order E, W, N, S (walls: 2 a_P v_P), as TS; hN holds the N face weights of
+// this row on return (the S face weights of the next row)
+// (the rows above and below are passed by reference with flags, never as
+// pointers that may be null: a select between the addresses of two register
+// arrays would force them into scratch memory)
+template <typename TS, int CW, typename TA, typename TV>
+__device__ __forceinline__ void row_flux(const GroupRow<TA, TV, CW> &c, TA al, TV vl, TA ar, TV vr,
+                                         const GroupRow<TA, TV, CW> &up, bool has_up,
+                                         const GroupRow<TA, TV, CW> &dn, bool has_dn, TS (&hS)[CW],
+                                         TS (&hN)[CW], int i0, int n, TS (&flux)[CW])
 {
-    TS hx[5];   // faces between columns i0-1 | i0 | .. | i0+4
+    TS hx[CW + 1];   // faces between columns i0-1 | i0 | .. | i0+CW
     hx[0] = i0 > 0 ? hm(TS(al), TS(c.a[0])) : TS(0);
 #pragma unroll
-    for (int k = 1; k < 4; ++k) hx[k] = hm(TS(c.a[k - 1]), TS(c.a[k]));
-    hx[4] = i0 + 4 < n ? hm(TS(c.a[3]), TS(ar)) : TS(0);
+    for (int k = 1; k < CW; ++k) hx[k] = hm(TS(c.a[k - 1]), TS(c.a[k]));
+    hx[CW] = i0 + CW < n ? hm(TS(c.a[CW - 1]), TS(ar)) : TS(0);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < CW; ++k) {
         const TS ap = TS(c.a[k]), xp = TS(c.v[k]);
-        const TS xe = k < 3 ? TS(c.v[k + 1]) : TS(vr);
+        const TS xe = k < CW - 1 ? TS(c.v[k + 1]) : TS(vr);
         const TS xw = k > 0 ? TS(c.v[k - 1]) : TS(vl);
-        hN[k] = up ? hm(ap, TS(up->a[k])) : TS(0);
+        hN[k] = has_up ? hm(ap, TS(up.a[k])) : TS(0);
         TS v = TS(0);
         v += (i0 + k + 1 < n) ? hx[k + 1] * (xp - xe) : TS(2) * ap * xp;
         v += (i0 + k > 0) ? hx[k] * (xp - xw) : TS(2) * ap * xp;
-        v += up ? hN[k] * (xp - TS(up->v[k])) : TS(2) * ap * xp;
-        v += dn ? hS[k] * (xp - TS(dn->v[k])) : TS(2) * ap * xp;
+        v += has_up ? hN[k] * (xp - TS(up.v[k])) : TS(2) * ap * xp;
+        v += has_dn ? hS[k] * (xp - TS(dn.v[k])) : TS(2) * ap * xp;
         flux[k] = v;
     }
 }
@@ -1070,19 +1084,20 @@ __device__ __forceinline__ double fold_partials(const double *__restrict__ part,
 
 // x_k = x_{k-1} + alpha p_k into X[k & 1] and r = 1 - A x_k in FP64 (UPDATE),
 // or r = 1 - A x_0 (the stage's first residual, from X[0]); F[k & 1] = T(r),
-// partial ||r||^2
+// partial ||r||^2.  FP64 arrays: cell pairs.
 template <typename T, int QH, bool UPDATE>
 __global__ __launch_bounds__(256, 4) void k_fcg_x(const double *__restrict__ a64, double *__restrict__ X0,
-                                               double *__restrict__ X1, const T *__restrict__ P0,
-                                               const T *__restrict__ P1, T *__restrict__ F0,
-                                               T *__restrict__ F1, int n, int64_t Bc,
-                                               const double *__restrict__ fs,
-                                               double *__restrict__ part,
-                                               const int32_t *__restrict__ active,
-                                               const int32_t *__restrict__ iters)
+                                                  double *__restrict__ X1, const T *__restrict__ P0,
+                                                  const T *__restrict__ P1, T *__restrict__ F0,
+                                                  T *__restrict__ F1, int n, int64_t Bc,
+                                                  const double *__restrict__ fs,
+                                                  double *__restrict__ part,
+                                                  const int32_t *__restrict__ active,
+                                                  const int32_t *__restrict__ iters)
 {
+    constexpr int CW = 2;
     FcgMap m;
-    if (!fcg_map<QH>(n, Bc, UPDATE ? active : nullptr, m)) return;
+    if (!fcg_map<CW, QH>(n, Bc, UPDATE ? active : nullptr, m)) return;
     const int64_t cells = (int64_t)n * n, base = m.b * cells;
     const int k = UPDATE ? iters[m.b] : 0;
     const double alpha = UPDATE ? fs[4 * m.b + 2] : 0.0;
@@ -1091,34 +1106,30 @@ __global__ __launch_bounds__(256, 4) void k_fcg_x(const double *__restrict__ a64
     double *xnew = (k & 1 ? X1 : X0) + base;
     const T *pb = UPDATE ? (k & 1 ? P1 : P0) + base : nullptr;
     T *fb = (k & 1 ? F1 : F0) + base;
-    auto xk = [&](int64_t q) {
-        return UPDATE ? xold[q] + alpha * double(pb[q]) : ((const double *)X0 + base)[q];
-    };
-    auto load = [&](int j, QuadRow<double, double> &r) {
+    auto xk = [&](int64_t q) { return UPDATE ? xold[q] + alpha * double(pb[q]) : xold[q]; };
+    using Row = GroupRow<double, double, CW>;
+    auto load = [&](int j, Row &r) {
         const int64_t o = (int64_t)j * n + m.i0;
-        ld4(ab + o, r.a);
+        ldv<CW>(ab + o, r.a);
+        ldv<CW>(xold + o, r.v);
         if (UPDATE) {
-            double xo[4];
-            T pp[4];
-            ld4(xold + o, xo);
-            ld4(pb + o, pp);
+            T pp[CW];
+            ldv<CW>(pb + o, pp);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) r.v[c] = xo[c] + alpha * double(pp[c]);
-        } else {
-            ld4(X0 + base + o, r.v);
+            for (int c = 0; c < CW; ++c) r.v[c] = r.v[c] + alpha * double(pp[c]);
         }
     };
     const double n2 = double(n) * double(n);
     // rows j-1, j, j+1 and j+2: the loads of row j+2 are in flight while row
     // j is computed
-    QuadRow<double, double> prv, cur, nxt, nn;
-    double hS[4], hN[4];
+    Row prv, cur, nxt, nn;
+    double hS[CW], hN[CW];
     load(m.j0, cur);
     if (m.j0 + 1 < n) load(m.j0 + 1, nxt);
     if (m.j0 > 0) {
         load(m.j0 - 1, prv);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) hS[c] = hm(cur.a[c], prv.a[c]);
+        for (int c = 0; c < CW; ++c) hS[c] = hm(cur.a[c], prv.a[c]);
     }
     double s[1] = {0.0}, c[1] = {0.0};
 #pragma unroll 1
@@ -1126,21 +1137,21 @@ __global__ __launch_bounds__(256, 4) void k_fcg_x(const double *__restrict__ a64
         const int j = m.j0 + t;
         if (t + 1 < QH && j + 2 < n) load(j + 2, nn);
         double al, vl, ar, vr;
-        row_ends(cur, ab + (int64_t)j * n, (int64_t)j * n, m.i0, n, xk, al, vl, ar, vr);
-        double flux[4];
-        quad_flux<double>(cur, al, vl, ar, vr, j + 1 < n ? &nxt : nullptr, j > 0 ? &prv : nullptr,
-                          hS, hN, m.i0, n, flux);
-        T fv[4];
+        row_ends<CW>(cur, ab + (int64_t)j * n, (int64_t)j * n, m.i0, n, xk, al, vl, ar, vr);
+        double flux[CW];
+        row_flux<double, CW>(cur, al, vl, ar, vr, nxt, j + 1 < n, prv, j > 0, hS, hN, m.i0, n,
+                             flux);
+        T fv[CW];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < CW; ++q) {
             const double r = 1.0 - n2 * flux[q];
             fv[q] = T(r);
             neumaier(s[0], c[0], r * r);
             hS[q] = hN[q];
         }
         const int64_t o = (int64_t)j * n + m.i0;
-        if (UPDATE) st4(xnew + o, cur.v);
-        st4(fb + o, fv);
+        if (UPDATE) stv<CW>(xnew + o, cur.v);
+        stv<CW>(fb + o, fv);
         prv = cur;
         cur = nxt;
         nxt = nn;
@@ -1191,8 +1202,9 @@ __global__ __launch_bounds__(256) void k_fcg_dots(const T *__restrict__ z, const
                                                   const int32_t *__restrict__ active,
                                                   const int32_t *__restrict__ iters)
 {
+    constexpr int CW = 16 / sizeof(T);
     FcgMap m;
-    if (!fcg_map<QH>(n, Bc, active, m)) return;
+    if (!fcg_map<CW, QH>(n, Bc, active, m)) return;
     const int64_t cells = (int64_t)n * n, base = m.b * cells;
     const int k = iters[m.b];
     const T *rb = ((k - 1) & 1 ? F1 : F0) + base;
@@ -1201,12 +1213,12 @@ __global__ __launch_bounds__(256) void k_fcg_dots(const T *__restrict__ z, const
 #pragma unroll 2
     for (int t = 0; t < QH; ++t) {
         const int64_t o = (int64_t)(m.j0 + t) * n + m.i0;
-        T zv[4], rv[4], ro[4];
-        ld4(z + base + o, zv);
-        ld4(rb + o, rv);
-        if (k > 1) ld4(rob + o, ro);
+        T zv[CW], rv[CW], ro[CW];
+        ldv<CW>(z + base + o, zv);
+        ldv<CW>(rb + o, rv);
+        if (k > 1) ldv<CW>(rob + o, ro);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < CW; ++q) {
             neumaier(s[0], c[0], double(rv[q]) * double(zv[q]));
             neumaier(s[1], c[1], k > 1 ? double(ro[q]) * double(zv[q]) : 0.0);
         }
@@ -1237,14 +1249,15 @@ __global__ __launch_bounds__(256) void k_fcg_fin_beta(const double *__restrict__
 // FP64), the products summed in FP64
 template <typename T, int QH>
 __global__ __launch_bounds__(256, 4) void k_fcg_p(const T *__restrict__ a, const T *__restrict__ z,
-                                               T *__restrict__ P0, T *__restrict__ P1, int n,
-                                               int64_t Bc, const double *__restrict__ fs,
-                                               double *__restrict__ part,
-                                               const int32_t *__restrict__ active,
-                                               const int32_t *__restrict__ iters)
+                                                  T *__restrict__ P0, T *__restrict__ P1, int n,
+                                                  int64_t Bc, const double *__restrict__ fs,
+                                                  double *__restrict__ part,
+                                                  const int32_t *__restrict__ active,
+                                                  const int32_t *__restrict__ iters)
 {
+    constexpr int CW = 16 / sizeof(T);
     FcgMap m;
-    if (!fcg_map<QH>(n, Bc, active, m)) return;
+    if (!fcg_map<CW, QH>(n, Bc, active, m)) return;
     const int64_t cells = (int64_t)n * n, base = m.b * cells;
     const int k = iters[m.b];
     const T bt = T(k == 1 ? 0.0 : fs[4 * m.b + 3]);
@@ -1252,26 +1265,27 @@ __global__ __launch_bounds__(256, 4) void k_fcg_p(const T *__restrict__ a, const
     const T *pold = ((k - 1) & 1 ? P1 : P0) + base;
     T *pnew = (k & 1 ? P1 : P0) + base;
     auto pk = [&](int64_t q) { return k == 1 ? zb[q] : T(zb[q] + bt * pold[q]); };
-    auto load = [&](int j, QuadRow<T, T> &r) {
+    using Row = GroupRow<T, T, CW>;
+    auto load = [&](int j, Row &r) {
         const int64_t o = (int64_t)j * n + m.i0;
-        ld4(ab + o, r.a);
-        ld4(zb + o, r.v);
+        ldv<CW>(ab + o, r.a);
+        ldv<CW>(zb + o, r.v);
         if (k > 1) {
-            T po[4];
-            ld4(pold + o, po);
+            T po[CW];
+            ldv<CW>(pold + o, po);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) r.v[c] = T(r.v[c] + bt * po[c]);
+            for (int c = 0; c < CW; ++c) r.v[c] = T(r.v[c] + bt * po[c]);
         }
     };
     const double n2 = double(n) * double(n);
-    QuadRow<T, T> prv, cur, nxt, nn;           // rows j-1 .. j+2 (j+2 in flight)
-    T hS[4], hN[4];
+    Row prv, cur, nxt, nn;                     // rows j-1 .. j+2 (j+2 in flight)
+    T hS[CW], hN[CW];
     load(m.j0, cur);
     if (m.j0 + 1 < n) load(m.j0 + 1, nxt);
     if (m.j0 > 0) {
         load(m.j0 - 1, prv);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) hS[c] = hm(cur.a[c], prv.a[c]);
+        for (int c = 0; c < CW; ++c) hS[c] = hm(cur.a[c], prv.a[c]);
     }
     double s[1] = {0.0}, c[1] = {0.0};
 #pragma unroll 1
@@ -1279,16 +1293,15 @@ __global__ __launch_bounds__(256, 4) void k_fcg_p(const T *__restrict__ a, const
         const int j = m.j0 + t;
         if (t + 1 < QH && j + 2 < n) load(j + 2, nn);
         T al, vl, ar, vr;
-        row_ends(cur, ab + (int64_t)j * n, (int64_t)j * n, m.i0, n, pk, al, vl, ar, vr);
-        T flux[4];
-        quad_flux<T>(cur, al, vl, ar, vr, j + 1 < n ? &nxt : nullptr, j > 0 ? &prv : nullptr, hS,
-                     hN, m.i0, n, flux);
+        row_ends<CW>(cur, ab + (int64_t)j * n, (int64_t)j * n, m.i0, n, pk, al, vl, ar, vr);
+        T flux[CW];
+        row_flux<T, CW>(cur, al, vl, ar, vr, nxt, j + 1 < n, prv, j > 0, hS, hN, m.i0, n, flux);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < CW; ++q) {
             neumaier(s[0], c[0], double(cur.v[q]) * n2 * double(flux[q]));
             hS[q] = hN[q];
         }
-        st4(pnew + (int64_t)j * n + m.i0, cur.v);
+        stv<CW>(pnew + (int64_t)j * n + m.i0, cur.v);
         prv = cur;
         cur = nxt;
         nxt = nn;
@@ -1316,16 +1329,17 @@ __global__ __launch_bounds__(256) void k_fcg_copyback(double *__restrict__ X0,
                                                       const double *__restrict__ X1, int n,
                                                       int64_t Bc, const int32_t *__restrict__ iters)
 {
+    constexpr int CW = 2;
     FcgMap m;
-    if (!fcg_map<QH>(n, Bc, nullptr, m)) return;
+    if (!fcg_map<CW, QH>(n, Bc, nullptr, m)) return;
     if (!(iters[m.b] & 1)) return;
     const int64_t base = m.b * (int64_t)n * n;
 #pragma unroll 2
     for (int t = 0; t < QH; ++t) {
         const int64_t o = base + (int64_t)(m.j0 + t) * n + m.i0;
-        double v[4];
-        ld4(X1 + o, v);
-        st4(X0 + o, v);
+        double v[CW];
+        ldv<CW>(X1 + o, v);
+        stv<CW>(X0 + o, v);
     }
 }
 
@@ -1437,16 +1451,16 @@ void launch_lds_fmg_refine(hipStream_t st, const T *a_pool, const double *a64_po
 
 int64_t fcg_partials(int n, int64_t Bc) { return Bc * fcg_nch(n) * 4; }
 
-// the CG passes' strip height: 4 rows on 64^2 (one block per sample), 8 above
-#define MLMC_FCG_QH(n, LAUNCH)      \
-    do {                            \
-        if (fcg_qh(n) == 4) {       \
-            constexpr int QH = 4;   \
-            LAUNCH;                 \
-        } else {                    \
-            constexpr int QH = 8;   \
-            LAUNCH;                 \
-        }                           \
+// the CG passes' strip height: QH = 4 q / CW rows (q = 4 on 64^2, 8 above)
+#define MLMC_FCG_QH(n, CW, LAUNCH)          \
+    do {                                    \
+        if (fcg_q(n) == 4) {                \
+            constexpr int QH = 16 / (CW);   \
+            LAUNCH;                         \
+        } else {                            \
+            constexpr int QH = 32 / (CW);   \
+            LAUNCH;                         \
+        }                                   \
     } while (0)
 
 template <typename T>
@@ -1454,9 +1468,9 @@ void launch_fcg_resid(hipStream_t st, const double *a, const double *x, int n, i
                       double *part)
 {
     const unsigned nb = nblocks(Bc * fcg_nch(n));
-    MLMC_FCG_QH(n, hipLaunchKernelGGL((k_fcg_x<T, QH, false>), dim3(nb), dim3(256), 0, st, a,
-                                      const_cast<double *>(x), nullptr, nullptr, nullptr, f,
-                                      nullptr, n, Bc, nullptr, part, nullptr, nullptr));
+    MLMC_FCG_QH(n, 2, hipLaunchKernelGGL((k_fcg_x<T, QH, false>), dim3(nb), dim3(256), 0, st, a,
+                                         const_cast<double *>(x), nullptr, nullptr, nullptr, f,
+                                         nullptr, n, Bc, nullptr, part, nullptr, nullptr));
 }
 
 void launch_fcg_fin_rho(hipStream_t st, const double *part, int n, int64_t Bc, double *rho,
@@ -1471,18 +1485,19 @@ template <typename T>
 void launch_fcg_step(hipStream_t st, const FcgBufs<T> &v, int n, int64_t Bc, double rtol,
                      int max_iters)
 {
+    constexpr int CWT = 16 / sizeof(T);
     const unsigned nb = nblocks(Bc * fcg_nch(n));
     const unsigned ns = blocks_of(Bc, 4);
-    MLMC_FCG_QH(n, hipLaunchKernelGGL((k_fcg_dots<T, QH>), dim3(nb), dim3(256), 0, st, v.z, v.f,
-                                      v.fo, n, Bc, v.part, v.active, v.iters));
+    MLMC_FCG_QH(n, CWT, hipLaunchKernelGGL((k_fcg_dots<T, QH>), dim3(nb), dim3(256), 0, st, v.z,
+                                           v.f, v.fo, n, Bc, v.part, v.active, v.iters));
     hipLaunchKernelGGL(k_fcg_fin_beta, dim3(ns), dim3(256), 0, st, v.part, n, Bc, v.fs, v.active,
                        v.iters);
-    MLMC_FCG_QH(n, hipLaunchKernelGGL((k_fcg_p<T, QH>), dim3(nb), dim3(256), 0, st, v.a, v.z, v.p0,
-                                      v.p1, n, Bc, v.fs, v.part, v.active, v.iters));
+    MLMC_FCG_QH(n, CWT, hipLaunchKernelGGL((k_fcg_p<T, QH>), dim3(nb), dim3(256), 0, st, v.a, v.z,
+                                           v.p0, v.p1, n, Bc, v.fs, v.part, v.active, v.iters));
     hipLaunchKernelGGL(k_fcg_fin_alpha, dim3(ns), dim3(256), 0, st, v.part, n, Bc, v.fs, v.active);
-    MLMC_FCG_QH(n, hipLaunchKernelGGL((k_fcg_x<T, QH, true>), dim3(nb), dim3(256), 0, st, v.a64,
-                                      v.x0, v.x1, v.p0, v.p1, v.f, v.fo, n, Bc, v.fs, v.part,
-                                      v.active, v.iters));
+    MLMC_FCG_QH(n, 2, hipLaunchKernelGGL((k_fcg_x<T, QH, true>), dim3(nb), dim3(256), 0, st, v.a64,
+                                         v.x0, v.x1, v.p0, v.p1, v.f, v.fo, n, Bc, v.fs, v.part,
+                                         v.active, v.iters));
     hipLaunchKernelGGL(k_fcg_fin_rho, dim3(ns), dim3(256), 0, st, v.part, n, Bc, v.rho, v.hist, v.active,
                        v.iters, rtol, max_iters, 0);
 }
@@ -1491,8 +1506,8 @@ void launch_fcg_copyback(hipStream_t st, double *x0, const double *x1, int n, in
                          const int32_t *iters)
 {
     const unsigned nb = nblocks(Bc * fcg_nch(n));
-    MLMC_FCG_QH(n, hipLaunchKernelGGL((k_fcg_copyback<QH>), dim3(nb), dim3(256), 0, st, x0, x1, n,
-                                      Bc, iters));
+    MLMC_FCG_QH(n, 2, hipLaunchKernelGGL((k_fcg_copyback<QH>), dim3(nb), dim3(256), 0, st, x0, x1,
+                                         n, Bc, iters));
 }
 #undef MLMC_FCG_QH
 
