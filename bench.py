@@ -3,8 +3,8 @@
 One step = one pass of the whole path over one batch: lattice points, KL field
 (dense product + exp), FMG with every stage refined to relative residual 1e-10
 and the QoI of every stage, level-difference sums, their device-to-host copy
-and the estimator.  The batch is 16 Korobov lattice points x 16 random shifts
-= 256 samples at the finest level (1024^2, MLMC levels 4^2 .. 1024^2) of the
+and the estimator.  The batch is 64 Korobov lattice points x 16 random shifts
+= 1024 samples at the finest level (1024^2, MLMC levels 4^2 .. 1024^2) of the
 mixed-precision workload (s = 400 KL terms, lambda = 0.1, sigma^2 = 2, QoI
 mean of u and u(1/2,1/2)).  The mixed path (bf16 digit-product field, FP32
 V-cycles inside FP64 flexible CG) is the headline; the FP64 path runs the same
@@ -747,9 +747,9 @@ def headline(m, torch, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--points", type=int, default=16,
+    ap.add_argument("--points", type=int, default=64,
                     help="lattice points per shift in one step's batch")
     ap.add_argument("--shifts", type=int, default=16, help="random shifts in one step's batch")
     ap.add_argument("--no-autotune", action="store_true",

@@ -6,7 +6,7 @@ precisions:
 * 4^2 .. 32^2: every sample of one 4096-point shift, against the oracle's
   band Cholesky solve of each level (the exact discrete solution);
 * 64^2 .. 256^2: 64 samples (16 points x 4 shifts), against the band solve;
-* 512^2 and 1024^2: 4 samples from different shifts of the 256-sample
+* 512^2 and 1024^2: 4 samples from different shifts of the 1024-sample
   batch the benchmark times, against the oracle's FMG with the same stopping
   rule (the band solve costs 1.1 TFLOP per sample at 1024^2).
 
@@ -96,19 +96,19 @@ def test_samples_on_middle_levels(oracle_mod, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_samples_of_the_benchmark_batch_on_fine_levels(oracle_mod, precision):
-    """The benchmark's launch configuration: 16 points x 16 shifts at 1024^2
-    in one call; samples 0, 85, 170 and 255 (shifts 0, 5, 10, 15) against the
-    oracle's FMG (levels 4^2 .. 1024^2).  A sample stopped by the rounding
-    floor (residual ratio within 2x of rtol, reported) is held to the same
-    tolerance."""
+    """The benchmark's launch configuration: 64 points x 16 shifts at 1024^2
+    in one call; samples 0, 341, 682 and 1023 (shifts 0, 5, 10, 15) against
+    the oracle's FMG (levels 4^2 .. 1024^2).  A sample stopped by the
+    rounding floor (residual ratio within 2x of rtol, reported) is held to the
+    same tolerance."""
     _dev()
     k = 8
-    w, z, D, ctx, P = _setup(oracle_mod, precision, k + 1, 256)
-    print(f"\n{precision}: 256 samples at 1024^2", flush=True)
-    qg, info = _gpu(ctx, k, 0, 16, 0, 16)
+    w, z, D, ctx, P = _setup(oracle_mod, precision, k + 1, 1024)
+    print(f"\n{precision}: 1024 samples at 1024^2", flush=True)
+    qg, info = _gpu(ctx, k, 0, 64, 0, 16)
     print(f"info {info}", flush=True)
     assert info["max_rel_residual"] <= 2 * w["rtol"], info
-    picks = [0, 85, 170, 255]
-    y = np.stack([oracle_mod.points(z, D[k, b // 16], b % 16, b % 16 + 1)[1][0] for b in picks])
+    picks = [0, 341, 682, 1023]
+    y = np.stack([oracle_mod.points(z, D[k, b // 64], b % 64, b % 64 + 1)[1][0] for b in picks])
     qo, _ = P.batch(k, y, 0, nthreads=4)
     _check(f"{precision} 4^2..1024^2 (samples {picks})", qg[picks], qo)
