@@ -332,20 +332,20 @@ mlmc_status mlmc_profile_end(mlmc_ctx ctx, mlmc_profile_result *out);
  *   MLMC_PASS_TILE16  16 x 16 cells per 128-thread workgroup (four times the
  *                     workgroups: for batches too small to fill the chip)
  *   MLMC_PASS_STREAM  rows streamed through LDS, one sample per workgroup
- *                     (2 or 4 per workgroup on 64^2 and 32^2, so that they
- *                     fill a wavefront); FP64 and FP32 V-cycles, 32 <= n
- *                     <= 512 only
+ *                     of n/2 threads (at least 256; 2 or 4 samples per
+ *                     workgroup on 64^2 and 32^2, so that they fill a
+ *                     wavefront); FP64 and FP32 V-cycles, 32 <= n <= 2048
  * All kinds give the bits of the same global sweep order, so the choice
  * changes only the time.  The choice is kept per context for each grid side
  * n and batch class c: chunks of Bc samples with 4^(c-1) < Bc <= 4^c (c = 0
  * for one sample), c < MLMC_BATCH_CLASSES (the last class takes every larger
  * chunk).  A new context starts from defaults measured on MI355X, a rule in
- * c and the number of 32 x 32 tiles of the pass, t = 4^c (n/32)^2: TILE16
- * for t <= 256, TILE32 otherwise; with FP64 V-cycles STREAM takes the pre
- * and the post pass for t >= 65536 (t >= 16384 when n <= 64).  FP32
- * V-cycles (the mixed path) start from tiles everywhere (streaming measured
- * slower at its batch sizes) and stream where mlmc_autotune measures it
- * faster.  A server's slots take the first slot's table. */
+ * c, the number of 32 x 32 tiles of the pass, t = 4^c (n/32)^2, and the
+ * lanes of a streaming pass, 4^c n/2: TILE16 for t <= 256, TILE32
+ * otherwise; STREAM takes the pre and the post pass once it has at least
+ * 131072 lanes and t >= 65536 (FP64 V-cycles: t >= 16384 when n <= 64), with
+ * FP64 V-cycles up to 1024^2 only.  mlmc_autotune replaces the defaults by
+ * what it measures.  A server's slots take the first slot's table. */
 enum { MLMC_PASS_TILE32 = 0, MLMC_PASS_TILE16 = 1, MLMC_PASS_STREAM = 2 };
 enum { MLMC_BATCH_CLASSES = 10 };
 typedef struct {

@@ -455,26 +455,29 @@ bool kind_allowed(mlmc_ctx c, int g, int kind)
     return kind == kStream && stream_supported(2 << g);
 }
 
-// Defaults: the choices mlmc_autotune made on MI355X for the s = 100 FP64
-// workload (grids 32^2 .. 256^2, batch classes up to 16384 samples), as a
-// rule in the batch class c and the number of 32 x 32 tiles a pass covers,
-// t = 4^c (n/32)^2: up to 256 tiles (one per CU or fewer) 16 x 16 tiles,
-// which give four times the workgroups; 32 x 32 tiles otherwise; for FP64
-// V-cycles the row-streaming passes (32^2 .. 512^2) take both passes from
-// t = 65536 on (from t = 16384 on 32^2 and 64^2, where a workgroup packs 4
-// or 2 samples).  FP32 V-cycles keep tiles: their streaming passes give the
-// same bits but measured slower at the mixed workload's batch sizes.
+// Defaults: the choices mlmc_autotune made on MI355X for the FP64 s = 100
+// workload (grids 32^2 .. 256^2) and for both V-cycle types of the s = 400
+// workloads (64^2 .. 2048^2), batch classes up to 16384 samples, as a rule in
+// the batch class c, the number of 32 x 32 tiles a pass covers, t = 4^c
+// (n/32)^2, and the lanes the row-streaming passes would run, 4^c n/2: up to
+// 256 tiles (one per CU or fewer) 16 x 16 tiles, which give four times the
+// workgroups; 32 x 32 tiles otherwise; the row-streaming passes take both
+// passes once they have 131072 lanes and t >= 65536 (FP64 from t = 16384 on
+// 32^2 and 64^2, where a workgroup packs 4 or 2 samples), in FP64 up to
+// 1024^2 (the 2048^2 FP64 workgroup of 1024 lanes spills registers and
+// measured slower than tiles).
 void default_tuning(mlmc_ctx c)
 {
+    const bool fp64 = c->cfg.precision == MLMC_FP64;
     for (int g = 0; g < kMaxMgLevels; ++g) {
         const int n = 2 << g;
         const int64_t side = std::max(1, n / 32);
-        // defaults stream the FP64 V-cycles only (FP32: measured per context)
-        const bool stream = kind_allowed(c, g, kStream) && c->cfg.precision == MLMC_FP64;
+        const bool stream = kind_allowed(c, g, kStream) && (!fp64 || n <= 1024);
         for (int cl = 0; cl < MLMC_BATCH_CLASSES; ++cl) {
             const int64_t tiles = ((int64_t)1 << (2 * cl)) * side * side;
+            const int64_t lanes = ((int64_t)1 << (2 * cl)) * (n / 2);
             const int8_t tile = tiles <= 256 ? kTile16 : kTile32;
-            const bool big = tiles >= 65536 || (n <= 64 && tiles >= 16384);
+            const bool big = (tiles >= 65536 || (fp64 && n <= 64 && tiles >= 16384)) && lanes >= 131072;
             c->pre_kind[g][cl] = stream && big ? kStream : tile;
             c->post_kind[g][cl] = stream && big ? kStream : tile;
         }

@@ -2,8 +2,9 @@
 // mixed path's V-cycles), each with the arithmetic of the tile passes of its type.
 //
 // One workgroup solves the grids of SPB samples of n x n cells (32 <= n <=
-// 512; SPB = 64 / (n/2) samples on grids narrower than a wavefront, so that no
-// lane idles, else 1).  Lane L of a sample owns the two columns 2L and 2L+1,
+// 2048; SPB = 64 / (n/2) samples on grids narrower than a wavefront, so that no
+// lane idles, else 1, with n/2 threads: up to 1024 on 2048^2, the largest
+// workgroup).  Lane L of a sample owns the two columns 2L and 2L+1,
 // so every row gives each lane one red and one black cell, and the lanes of a
 // sample span the full width: no halo is recomputed.  Rows stream bottom to
 // top through a ring of 8 rows of u and 2 rows of a in LDS; the 2*mu
@@ -157,9 +158,10 @@ struct Faces {
 // arithmetic of the tile passes of the same type.
 // Register budget: 128 (4 waves per SIMD) with f = 1, whose window carries
 // no right-hand side, or in FP32, else 168 (3 waves); measured against each
-// other in FP64.
-template <int MU, bool PRE, bool F1, int SPB, int INIT, typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F1 || sizeof(T) == 4 ? 4 : 3)))
+// other in FP64.  NT: the workgroup size the launch uses (256, or n/2 above
+// 512^2; a 1024-thread workgroup holds 4 waves per SIMD, so 128 registers).
+template <int MU, bool PRE, bool F1, int SPB, int INIT, typename T, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(F1 || sizeof(T) == 4 || NT > 512 ? 4 : 3)))
 void k_stream(const T *__restrict__ a, const T *__restrict__ f, const T *u_in, T *u_out,
               const T *__restrict__ ec, int n, int64_t Bc, T *__restrict__ fc,
               const int32_t *__restrict__ active)
@@ -400,13 +402,13 @@ void k_stream(const T *__restrict__ a, const T *__restrict__ f, const T *u_in, T
         static_for<0, 8>([&](auto Jc) __attribute__((always_inline)) { step(s0 + Jc.value, Jc); });
 }
 
-template <int MU, bool PRE, bool F1, int SPB, int INIT, typename T>
+template <int MU, bool PRE, bool F1, int SPB, int INIT, typename T, int NT>
 void launch_spb(hipStream_t st, const T *a, const T *f, const T *u_in, T *u_out, const T *ec,
                 int n, int64_t Bc, T *fc, const int32_t *active)
 {
     // once per instantiation; the static's initialisation is thread-safe
     static const bool attr_set = [] {
-        (void)hipFuncSetAttribute((const void *)k_stream<MU, PRE, F1, SPB, INIT, T>,
+        (void)hipFuncSetAttribute((const void *)k_stream<MU, PRE, F1, SPB, INIT, T, NT>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         return true;
     }();
@@ -414,40 +416,44 @@ void launch_spb(hipStream_t st, const T *a, const T *f, const T *u_in, T *u_out,
     const size_t lds = sizeof(T) * 10 * (size_t)n * SPB;
     const int threads = SPB * (n / 2) < 64 ? 64 : SPB * (n / 2);
     const unsigned blocks = (unsigned)((Bc + SPB - 1) / SPB);
-    hipLaunchKernelGGL((k_stream<MU, PRE, F1, SPB, INIT, T>), dim3(blocks), dim3(threads), lds, st,
-                       a, f, u_in, u_out, ec, n, Bc, fc, active);
+    hipLaunchKernelGGL((k_stream<MU, PRE, F1, SPB, INIT, T, NT>), dim3(blocks), dim3(threads), lds,
+                       st, a, f, u_in, u_out, ec, n, Bc, fc, active);
 }
 
-template <int MU, bool PRE, bool F1, int SPB, typename T>
+template <int MU, bool PRE, bool F1, int SPB, int NT, typename T>
 void launch_init(hipStream_t st, const T *a, const T *f, const T *u_in, T *u_out, const T *ec,
                  int n, int64_t Bc, int init, T *fc, const int32_t *active)
 {
     if constexpr (PRE) {
         if (init == 1) {
-            launch_spb<MU, PRE, F1, SPB, 1>(st, a, f, u_in, u_out, ec, n, Bc, fc, active);
+            launch_spb<MU, PRE, F1, SPB, 1, T, NT>(st, a, f, u_in, u_out, ec, n, Bc, fc, active);
             return;
         }
         if (init == 2) {
-            launch_spb<MU, PRE, F1, SPB, 2>(st, a, f, u_in, u_out, ec, n, Bc, fc, active);
+            launch_spb<MU, PRE, F1, SPB, 2, T, NT>(st, a, f, u_in, u_out, ec, n, Bc, fc, active);
             return;
         }
     }
-    launch_spb<MU, PRE, F1, SPB, 0>(st, a, f, u_in, u_out, ec, n, Bc, fc, active);
+    launch_spb<MU, PRE, F1, SPB, 0, T, NT>(st, a, f, u_in, u_out, ec, n, Bc, fc, active);
 }
 
 template <int MU, bool PRE, bool F1, typename T>
 void launch_one(hipStream_t st, const T *a, const T *f, const T *u_in, T *u_out, const T *ec,
                 int n, int64_t Bc, int init, T *fc, const int32_t *active)
 {
-    // as many samples per workgroup as fill one wavefront
-    if (n >= 128) launch_init<MU, PRE, F1, 1>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
-    else if (n == 64) launch_init<MU, PRE, F1, 2>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
-    else launch_init<MU, PRE, F1, 4>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
+    // as many samples per workgroup as fill one wavefront; from 1024^2 on the
+    // workgroup of one sample grows to n/2 threads
+    if (n == 2048) launch_init<MU, PRE, F1, 1, 1024>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
+    else if (n == 1024) launch_init<MU, PRE, F1, 1, 512>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
+    else if (n >= 128) launch_init<MU, PRE, F1, 1, 256>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
+    else if (n == 64) launch_init<MU, PRE, F1, 2, 256>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
+    else launch_init<MU, PRE, F1, 4, 256>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
 }
 
 }  // namespace
 
-bool stream_supported(int n) { return n >= 32 && n <= 512; }
+// the rings of a 2048^2 FP64 grid take 160 KiB, all of a CU's LDS
+bool stream_supported(int n) { return n >= 32 && n <= 2048; }
 
 template <typename T>
 void launch_pre_stream(hipStream_t st, int mu1, const T *a, const T *f, const T *u_in, T *u_out,

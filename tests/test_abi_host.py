@@ -202,24 +202,42 @@ def test_server_calls_reject_null_handles():
     assert L.mlmc_server_stats_get(None, C.byref(st)) == m.MLMC_E_INVAL
 
 
+def _default_kind(n, c, fp64):
+    """The documented default of grid side n and batch class c."""
+    tiles = 4 ** c * max(1, n // 32) ** 2
+    lanes = 4 ** c * (n // 2)
+    tile = m.MLMC_PASS_TILE16 if tiles <= 256 else m.MLMC_PASS_TILE32
+    has_stream = 32 <= n <= (1024 if fp64 else 2048)
+    big = (tiles >= 65536 or (fp64 and n <= 64 and tiles >= 16384)) and lanes >= 131072
+    return m.MLMC_PASS_STREAM if has_stream and big else tile
+
+
 def test_tuning_table_defaults_and_validation():
     """Pass-kind table of a context (host-only: no measurement): one entry per
     tile grid and batch class with the documented defaults; mlmc_tuning_set
     checks every entry before changing any."""
+    # refinement contexts: tile grids 64^2 .. 2048^2, FP64 and FP32 V-cycles
+    for prec in (m.MLMC_FP64, m.MLMC_MIXED):
+        c2 = _host_ctx(n0=4, num_levels=10, rtol=1e-10, max_iters=60, precision=prec)
+        t2 = c2.tuning()
+        assert sorted({e["n"] for e in t2}) == [64, 128, 256, 512, 1024, 2048]
+        for e in t2:
+            k = _default_kind(e["n"], e["batch_class"], prec == m.MLMC_FP64)
+            assert (e["pre"], e["post"]) == (k, k), (prec, e)
+        kinds = {(e["n"], e["batch_class"]): e["pre"] for e in t2}
+        assert kinds[(1024, 4)] == m.MLMC_PASS_STREAM              # 256 samples of 1024^2
+        assert kinds[(1024, 3)] == m.MLMC_PASS_TILE32              # 64 samples
+        assert kinds[(512, 4)] == m.MLMC_PASS_TILE32               # 256 samples: 65536 lanes
+        assert kinds[(2048, 4)] == (m.MLMC_PASS_TILE32 if prec == m.MLMC_FP64
+                                    else m.MLMC_PASS_STREAM)
     ctx = _host_ctx(n0=4, num_levels=7)             # tile grids 32^2 .. 256^2
     t = ctx.tuning()
     assert [(e["n"], e["batch_class"]) for e in t] == [
         (n, c) for n in (32, 64, 128, 256) for c in range(m.MLMC_BATCH_CLASSES)]
     for e in t:
-        c, n = e["batch_class"], e["n"]
-        tiles = 4 ** c * (n // 32) ** 2
-        tile = m.MLMC_PASS_TILE16 if tiles <= 256 else m.MLMC_PASS_TILE32
-        has_stream = 32 <= n <= 512
-        big = tiles >= 65536 or (n <= 64 and tiles >= 16384)
-        pre = m.MLMC_PASS_STREAM if has_stream and big else tile
-        post = m.MLMC_PASS_STREAM if has_stream and big else tile
-        assert e["pre"] == pre and e["pre_ms"] == 0.0, e
-        assert e["post"] == post, e
+        k = _default_kind(e["n"], e["batch_class"], True)
+        assert e["pre"] == k and e["pre_ms"] == 0.0, e
+        assert e["post"] == k, e
     kinds = {(e["n"], e["batch_class"]): (e["pre"], e["post"]) for e in t}
     assert kinds[(256, 1)] == (m.MLMC_PASS_TILE16,) * 2            # 4 samples: 256 tiles
     assert kinds[(256, 7)] == (m.MLMC_PASS_STREAM,) * 2            # 16384 samples
@@ -246,16 +264,16 @@ def test_tuning_table_defaults_and_validation():
     t2 = {(e["n"], e["batch_class"]): (e["pre"], e["post"]) for e in ctx.tuning()}
     assert t2[(128, 2)] == (T16, ST) and t2[(32, 9)] == (T16, T16)
     assert sum(t2[k] != (e["pre"], e["post"]) for e in t for k in [(e["n"], e["batch_class"])]) == 2
-    # mixed precision: the FP32 V-cycles stream only where the table says so
-    # (the defaults keep tiles); rtol mode keeps 32^2 LDS-resident
+    # mixed precision: the FP32 V-cycles' defaults and an installed choice;
+    # rtol mode keeps 32^2 LDS-resident
     mx = _host_ctx(n0=4, num_levels=7, precision=1, rtol=1e-10, max_iters=50)
     tm = mx.tuning()
     assert [e["n"] for e in tm[::m.MLMC_BATCH_CLASSES]] == [64, 128, 256]
-    assert all(e["pre"] == e["post"] != ST for e in tm)
+    assert all(e["pre"] == e["post"] == _default_kind(e["n"], e["batch_class"], False) for e in tm)
     mx.set_tuning([dict(n=256, batch_class=7, pre=T32, post=ST)])
     assert {(e["n"], e["batch_class"]): (e["pre"], e["post"]) for e in mx.tuning()}[(256, 7)] == (T32, ST)
-    with pytest.raises(m.MlmcError):                 # no streaming pass above 512^2
-        _host_ctx(n0=4, num_levels=9).set_tuning([dict(n=1024, batch_class=0, pre=ST, post=T32)])
+    with pytest.raises(m.MlmcError):                 # no streaming pass above 2048^2
+        _host_ctx(n0=4, num_levels=11).set_tuning([dict(n=4096, batch_class=0, pre=ST, post=T32)])
     with pytest.raises(m.MlmcError):                 # rtol mode: 32^2 is LDS-resident
         mx.set_tuning([dict(n=32, batch_class=0, pre=T32, post=T32)])
     assert _host_ctx(n0=4, num_levels=3).tuning() == []          # all grids LDS-resident

@@ -120,19 +120,19 @@ def test_autotune_refinement_contexts(precision):
     assert np.array_equal(_solve(ctx, 5, 0, 3, 2, 4), before)
 
 
+@pytest.mark.parametrize("L", [8, 9, 10])
 @pytest.mark.parametrize("name,precision", [("mlqmc_fp64_s100", m.MLMC_FP64),
                                             ("mlqmc_mixed_s400", m.MLMC_FP64),
                                             ("mlqmc_mixed_s400", m.MLMC_MIXED)])
-def test_streaming_at_512_matches_tiles(oracle_mod, name, precision):
-    """512^2, the largest streaming grid and the only one whose workgroup
-    holds four wavefronts per sample (one barrier per row step): streaming,
-    tiles and a mix give the same bits, fixed-cycle and refinement mode,
-    FP64 and FP32 V-cycles; one sample against the oracle's FMG (fixed
-    cycles: the same algorithm, 1e-12; refinement: both to rtol 1e-10,
-    1e-8)."""
+def test_streaming_large_grids_match_tiles(oracle_mod, name, precision, L):
+    """Grids up to 512^2 (L = 8), 1024^2 and 2048^2, whose streaming
+    workgroups hold 4, 8 and 16 wavefronts per sample (one barrier per row
+    step): streaming, tiles and a mix give the same bits, fixed-cycle and
+    refinement mode, FP64 and FP32 V-cycles; up to 1024^2 one sample against
+    the oracle's FMG (fixed cycles: the same algorithm, 1e-12; refinement:
+    both to rtol 1e-10, 1e-8)."""
     _dev()
     w = synth.workload(name)
-    L = 8                                           # MG grids up to 512^2
     ctx = m.Context(n0=w["n0"], num_levels=L, s=w["s"], corr_len=w["corr_len"], sigma2=w["sigma2"],
                     mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"],
                     max_iters=w["max_iters"], precision=precision,
@@ -150,6 +150,8 @@ def test_streaming_at_512_matches_tiles(oracle_mod, name, precision):
         if want is None:
             want = q
         assert np.array_equal(q, want), (pre, post)
+    if L > 9:
+        return
     P = oracle_mod.Problem(w["n0"], L, w["s"], w["corr_len"], w["sigma2"], mu0=w["mu0"],
                            mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"], max_iters=w["max_iters"])
     D = synth.shift_table(w["seed"], L, w["num_shifts"], w["s"])
