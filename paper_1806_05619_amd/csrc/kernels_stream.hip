@@ -7,7 +7,12 @@
 // workgroup).  Lane L of a sample owns the two columns 2L and 2L+1,
 // so every row gives each lane one red and one black cell, and the lanes of a
 // sample span the full width: no halo is recomputed.  Rows stream bottom to
-// top through a ring of 8 rows of u and 2 rows of a in LDS; the 2*mu
+// top through a ring of 8 rows of u and 2 rows of a in LDS, each row stored
+// as its even columns followed by its odd columns, so that the lanes of a
+// wavefront touch consecutive words in every access (a cell's E and W
+// neighbours sit in the other plane, at the lane's own or the next or
+// previous lane's slot): no bank conflicts.  Lanes load and store their two
+// cells of a row as one 8- or 16-byte vector.  The 2*mu
 // red-black half-sweeps run as a pipeline one row apart (half-sweep t works
 // on row s - t while row s + 1 is being fetched), which reproduces the global
 // sweep order exactly:
@@ -158,21 +163,34 @@ struct Faces {
 // arithmetic of the tile passes of the same type.
 // Register budget: 128 (4 waves per SIMD) with f = 1, whose window carries
 // no right-hand side, or in FP32, else 168 (3 waves); measured against each
-// other in FP64.  NT: the workgroup size the launch uses (256, or n/2 above
-// 512^2; a 1024-thread workgroup holds 4 waves per SIMD, so 128 registers).
-template <int MU, bool PRE, bool F1, int SPB, int INIT, typename T, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(F1 || sizeof(T) == 4 || NT > 512 ? 4 : 3)))
+// other in FP64.  The grid side N is a template parameter, so that every
+// LDS address of a ring row is one lane offset plus an immediate.
+// SPB: samples per workgroup; NT: the launch bound (256, or N/2 above 512^2;
+// a 1024-thread workgroup holds 4 waves per SIMD, so 128 registers).
+template <int N>
+struct StreamShape {
+    static constexpr int SPB = N >= 128 ? 1 : 64 / (N / 2);
+    static constexpr int NT = N <= 512 ? 256 : N / 2;
+    static constexpr int THREADS = SPB * (N / 2);
+};
+
+template <int MU, bool PRE, bool F1, int N, int INIT, typename T>
+__global__ __launch_bounds__(StreamShape<N>::NT)
+__attribute__((amdgpu_waves_per_eu(F1 || sizeof(T) == 4 || N > 1024 ? 4 : 3)))
 void k_stream(const T *__restrict__ a, const T *__restrict__ f, const T *u_in, T *u_out,
-              const T *__restrict__ ec, int n, int64_t Bc, T *__restrict__ fc,
+              const T *__restrict__ ec, int64_t Bc, T *__restrict__ fc,
               const int32_t *__restrict__ active)
 {
+    constexpr int n = N;
+    constexpr int SPB = StreamShape<N>::SPB;
     constexpr int D = 2 * MU;                  // half-sweeps in the pass
     constexpr int NS = PRE ? D + 2 : D + 1;    // rows s-1 .. s-NS in the register window
-    // rows fetched ahead (two, in the post pass with f = 1, measured slower)
-    constexpr int PD = 1;
+    // rows fetched ahead: two in FP32; one in FP64, whose second row of
+    // registers measured no faster (or spills)
+    constexpr int PD = sizeof(T) == 4 ? 2 : 1;
     extern __shared__ double smem_words[];
     T *smem = reinterpret_cast<T *>(smem_words);
-    const int nc = n / 2;
+    constexpr int nc = n / 2;
     // sample `sub` of the block: lanes sub * n/2 .. (sub+1) * n/2 - 1; a
     // sample past the batch or inactive keeps its lanes idle but passes every
     // barrier with the others
@@ -188,6 +206,22 @@ void k_stream(const T *__restrict__ a, const T *__restrict__ f, const T *u_in, T
     T *u_ring = smem + (SPB == 1 || !lane ? 0 : sub) * 10 * n;   // [8][n]
     T *a_ring = u_ring + 8 * n;                                  // [2][n]
     const int c0 = 2 * L, c1 = 2 * L + 1;
+    // LDS slots of a row (even columns, then odd ones): the lane's cells c0
+    // and c1, and their outer neighbours c0 - 1 (odd plane, lane L-1) and
+    // c1 + 1 (even plane, lane L+1)
+    const int l0 = L, l1 = nc + L, lw = nc + L - 1, le = L + 1;
+    using V2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+    auto ld2 = [](const T *p, T &x, T &y) __attribute__((always_inline)) {
+        const V2 v = *reinterpret_cast<const V2 *>(p);
+        x = v.x;
+        y = v.y;
+    };
+    auto st2 = [](T *p, T x, T y) __attribute__((always_inline)) {
+        V2 v;
+        v.x = x;
+        v.y = y;
+        *reinterpret_cast<V2 *>(p) = v;
+    };
     const int64_t cells = (int64_t)n * n;
     const T *ab = a + b * cells;
     const T *fb = f ? f + b * cells : nullptr;
@@ -219,18 +253,11 @@ void k_stream(const T *__restrict__ a, const T *__restrict__ f, const T *u_in, T
         } else {
             R = R < n ? R : n - 1;
         }
-        const int64_t o = (int64_t)R * n;
-        pp.a0 = ab[o + c0];
-        pp.a1 = ab[o + c1];
-        if (!F1) {
-            pp.f0 = fb[o + c0];
-            pp.f1 = fb[o + c1];
-        }
+        const int64_t o = (int64_t)R * n + c0;
+        ld2(ab + o, pp.a0, pp.a1);
+        if (!F1) ld2(fb + o, pp.f0, pp.f1);
         if constexpr (need_coarse) load_coarse_raw(pp.k, eb, nc, L, R);
-        if constexpr (!PRE || INIT == 0) {
-            pp.u0 = ub[o + c0];
-            pp.u1 = ub[o + c1];
-        }
+        if constexpr (!PRE || INIT == 0) ld2(ub + o, pp.u0, pp.u1);
     };
     static_for<0, PD>([&](auto K) __attribute__((always_inline)) { fetch(K.value, pre[K.value]); });
 
@@ -283,10 +310,10 @@ void k_stream(const T *__restrict__ a, const T *__restrict__ f, const T *u_in, T
             } else if (PRE && INIT == 1) {
                 u0 = u1 = T(0);
             }
-            u_ring[J * n + c0] = u0;
-            u_ring[J * n + c1] = u1;
-            a_ring[P * n + c0] = pp.a0;
-            a_ring[P * n + c1] = pp.a1;
+            u_ring[J * n + l0] = u0;
+            u_ring[J * n + l1] = u1;
+            a_ring[P * n + l0] = pp.a0;
+            a_ring[P * n + l1] = pp.a1;
         }
         if (!F1) {
             rhs_cur0 = h2 * pp.f0;
@@ -304,13 +331,13 @@ void k_stream(const T *__restrict__ a, const T *__restrict__ f, const T *u_in, T
         const int q = s - 1;
         {
             const T *aq = a_ring + (1 - P) * n, *aq1 = a_ring + P * n;
-            const T ap0 = aq[c0], ap1 = aq[c1];
+            const T ap0 = aq[l0], ap1 = aq[l1];
             RowW<F1, T> &r = w[slot(1)];
             r.wC = hmean(ap0, ap1);
-            r.wW0 = c0 > 0 ? hmean(ap0, aq[c0 - 1]) : T(2) * ap0;
-            r.wE1 = c1 + 1 < n ? hmean(ap1, aq[c1 + 1]) : T(2) * ap1;
-            r.wN0 = q + 1 < n ? hmean(ap0, aq1[c0]) : T(2) * ap0;
-            r.wN1 = q + 1 < n ? hmean(ap1, aq1[c1]) : T(2) * ap1;
+            r.wW0 = c0 > 0 ? hmean(ap0, aq[lw]) : T(2) * ap0;
+            r.wE1 = c1 + 1 < n ? hmean(ap1, aq[le]) : T(2) * ap1;
+            r.wN0 = q + 1 < n ? hmean(ap0, aq1[l0]) : T(2) * ap0;
+            r.wN1 = q + 1 < n ? hmean(ap1, aq1[l1]) : T(2) * ap1;
             if constexpr (!F1) {
                 r.rhs0 = rhs_prev0;
                 r.rhs1 = rhs_prev1;
@@ -344,14 +371,16 @@ void k_stream(const T *__restrict__ a, const T *__restrict__ f, const T *u_in, T
                 const T *up = u_ring + slot(t - 1) * n;
                 const T *dn = u_ring + slot(t + 1) * n;
                 const int c = K == 0 ? c0 : c1;
+                // slots of the cell and of its E and W neighbours
+                const int lc = K == 0 ? l0 : l1, lE = K == 0 ? l1 : le, lW = K == 0 ? lw : l0;
                 // explicit fma in the face order E, W, N, S of the tile passes
                 // (a wall face meets a neighbour of value 0 there: skipped)
                 T num = F1 ? h2 : (K == 0 ? w[slot(t)].rhs0 : w[slot(t)].rhs1);
-                if (c + 1 < n) num = fma(fw.e, row[c + 1], num);
-                if (c > 0) num = fma(fw.w, row[c - 1], num);
-                if (rr + 1 < n) num = fma(fw.nn, up[c], num);
-                if (rr > 0) num = fma(fw.s, dn[c], num);
-                row[c] = num * rdiag;
+                if (c + 1 < n) num = fma(fw.e, row[lE], num);
+                if (c > 0) num = fma(fw.w, row[lW], num);
+                if (rr + 1 < n) num = fma(fw.nn, up[lc], num);
+                if (rr > 0) num = fma(fw.s, dn[lc], num);
+                row[lc] = num * rdiag;
             }
         });
 
@@ -368,20 +397,19 @@ void k_stream(const T *__restrict__ a, const T *__restrict__ f, const T *u_in, T
                     constexpr int K = decltype(Kc)::value;
                     const Faces<K, F1, T> fw(w[slot(D + 1)], w[slot(D + 2)]);
                     const int c = K == 0 ? c0 : c1;
-                    const T u = row[c];
-                    T v = fw.e * (u - (c + 1 < n ? row[c + 1] : T(0)));
-                    v = fma(fw.w, u - (c > 0 ? row[c - 1] : T(0)), v);
-                    v = fma(fw.nn, u - (rr + 1 < n ? up[c] : T(0)), v);
-                    v = fma(fw.s, u - (rr > 0 ? dn[c] : T(0)), v);
+                    const int lc = K == 0 ? l0 : l1, lE = K == 0 ? l1 : le, lW = K == 0 ? lw : l0;
+                    const T u = row[lc];
+                    T v = fw.e * (u - (c + 1 < n ? row[lE] : T(0)));
+                    v = fma(fw.w, u - (c > 0 ? row[lW] : T(0)), v);
+                    v = fma(fw.nn, u - (rr + 1 < n ? up[lc] : T(0)), v);
+                    v = fma(fw.s, u - (rr > 0 ? dn[lc] : T(0)), v);
                     return v;
                 };
                 const T res0 =
                     inv_h2 * ((F1 ? h2 : w[slot(D + 1)].rhs0) - flux(std::integral_constant<int, 0>{}));
                 const T res1 =
                     inv_h2 * ((F1 ? h2 : w[slot(D + 1)].rhs1) - flux(std::integral_constant<int, 1>{}));
-                const int64_t o = (int64_t)rr * n;
-                ob[o + c0] = row[c0];
-                ob[o + c1] = row[c1];
+                st2(ob + (int64_t)rr * n + c0, row[l0], row[l1]);
                 constexpr bool odd = ((P - D - 1) & 1) != 0;
                 if constexpr (odd) fcb[L + (int64_t)nc * (rr >> 1)] = T(0.25) * (rkeep0 + rkeep1 + res0 + res1);
                 else { rkeep0 = res0; rkeep1 = res1; }
@@ -390,9 +418,7 @@ void k_stream(const T *__restrict__ a, const T *__restrict__ f, const T *u_in, T
             const int rr = s - D;
             if (rr >= 0 && rr < n && lane) {
                 const T *row = u_ring + slot(D) * n;
-                const int64_t o = (int64_t)rr * n;
-                ob[o + c0] = row[c0];
-                ob[o + c1] = row[c1];
+                st2(ob + (int64_t)rr * n + c0, row[l0], row[l1]);
             }
         }
     };
@@ -402,58 +428,61 @@ void k_stream(const T *__restrict__ a, const T *__restrict__ f, const T *u_in, T
         static_for<0, 8>([&](auto Jc) __attribute__((always_inline)) { step(s0 + Jc.value, Jc); });
 }
 
-template <int MU, bool PRE, bool F1, int SPB, int INIT, typename T, int NT>
-void launch_spb(hipStream_t st, const T *a, const T *f, const T *u_in, T *u_out, const T *ec,
-                int n, int64_t Bc, T *fc, const int32_t *active)
+template <int MU, bool PRE, bool F1, int N, int INIT, typename T>
+void launch_n(hipStream_t st, const T *a, const T *f, const T *u_in, T *u_out, const T *ec,
+              int64_t Bc, T *fc, const int32_t *active)
 {
+    using S = StreamShape<N>;
     // once per instantiation; the static's initialisation is thread-safe
     static const bool attr_set = [] {
-        (void)hipFuncSetAttribute((const void *)k_stream<MU, PRE, F1, SPB, INIT, T, NT>,
+        (void)hipFuncSetAttribute((const void *)k_stream<MU, PRE, F1, N, INIT, T>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         return true;
     }();
     (void)attr_set;
-    const size_t lds = sizeof(T) * 10 * (size_t)n * SPB;
-    const int threads = SPB * (n / 2) < 64 ? 64 : SPB * (n / 2);
-    const unsigned blocks = (unsigned)((Bc + SPB - 1) / SPB);
-    hipLaunchKernelGGL((k_stream<MU, PRE, F1, SPB, INIT, T, NT>), dim3(blocks), dim3(threads), lds,
-                       st, a, f, u_in, u_out, ec, n, Bc, fc, active);
+    const size_t lds = sizeof(T) * 10 * (size_t)N * S::SPB;
+    const unsigned blocks = (unsigned)((Bc + S::SPB - 1) / S::SPB);
+    hipLaunchKernelGGL((k_stream<MU, PRE, F1, N, INIT, T>), dim3(blocks), dim3(S::THREADS), lds, st,
+                       a, f, u_in, u_out, ec, Bc, fc, active);
 }
 
-template <int MU, bool PRE, bool F1, int SPB, int NT, typename T>
+template <int MU, bool PRE, bool F1, int N, typename T>
 void launch_init(hipStream_t st, const T *a, const T *f, const T *u_in, T *u_out, const T *ec,
-                 int n, int64_t Bc, int init, T *fc, const int32_t *active)
+                 int64_t Bc, int init, T *fc, const int32_t *active)
 {
     if constexpr (PRE) {
         if (init == 1) {
-            launch_spb<MU, PRE, F1, SPB, 1, T, NT>(st, a, f, u_in, u_out, ec, n, Bc, fc, active);
+            launch_n<MU, PRE, F1, N, 1>(st, a, f, u_in, u_out, ec, Bc, fc, active);
             return;
         }
         if (init == 2) {
-            launch_spb<MU, PRE, F1, SPB, 2, T, NT>(st, a, f, u_in, u_out, ec, n, Bc, fc, active);
+            launch_n<MU, PRE, F1, N, 2>(st, a, f, u_in, u_out, ec, Bc, fc, active);
             return;
         }
     }
-    launch_spb<MU, PRE, F1, SPB, 0, T, NT>(st, a, f, u_in, u_out, ec, n, Bc, fc, active);
+    launch_n<MU, PRE, F1, N, 0>(st, a, f, u_in, u_out, ec, Bc, fc, active);
 }
 
 template <int MU, bool PRE, bool F1, typename T>
 void launch_one(hipStream_t st, const T *a, const T *f, const T *u_in, T *u_out, const T *ec,
                 int n, int64_t Bc, int init, T *fc, const int32_t *active)
 {
-    // as many samples per workgroup as fill one wavefront; from 1024^2 on the
-    // workgroup of one sample grows to n/2 threads
-    if (n == 2048) launch_init<MU, PRE, F1, 1, 1024>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
-    else if (n == 1024) launch_init<MU, PRE, F1, 1, 512>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
-    else if (n >= 128) launch_init<MU, PRE, F1, 1, 256>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
-    else if (n == 64) launch_init<MU, PRE, F1, 2, 256>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
-    else launch_init<MU, PRE, F1, 4, 256>(st, a, f, u_in, u_out, ec, n, Bc, init, fc, active);
+    switch (n) {
+    case 32: launch_init<MU, PRE, F1, 32>(st, a, f, u_in, u_out, ec, Bc, init, fc, active); break;
+    case 64: launch_init<MU, PRE, F1, 64>(st, a, f, u_in, u_out, ec, Bc, init, fc, active); break;
+    case 128: launch_init<MU, PRE, F1, 128>(st, a, f, u_in, u_out, ec, Bc, init, fc, active); break;
+    case 256: launch_init<MU, PRE, F1, 256>(st, a, f, u_in, u_out, ec, Bc, init, fc, active); break;
+    case 512: launch_init<MU, PRE, F1, 512>(st, a, f, u_in, u_out, ec, Bc, init, fc, active); break;
+    case 1024: launch_init<MU, PRE, F1, 1024>(st, a, f, u_in, u_out, ec, Bc, init, fc, active); break;
+    case 2048: launch_init<MU, PRE, F1, 2048>(st, a, f, u_in, u_out, ec, Bc, init, fc, active); break;
+    default: break;   // stream_supported() admits only these sides
+    }
 }
 
 }  // namespace
 
 // the rings of a 2048^2 FP64 grid take 160 KiB, all of a CU's LDS
-bool stream_supported(int n) { return n >= 32 && n <= 2048; }
+bool stream_supported(int n) { return n >= 32 && n <= 2048 && (n & (n - 1)) == 0; }
 
 template <typename T>
 void launch_pre_stream(hipStream_t st, int mu1, const T *a, const T *f, const T *u_in, T *u_out,
