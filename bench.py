@@ -594,10 +594,10 @@ def oracle_baseline(w, level, y_batch, gpu_qoi, seconds, max_samples):
     for name, qg in gpu_qoi.items():
         rel = np.abs(qg[:done] - qo) / np.abs(qo)          # [samples][level][nq]
         err[name] = [float(f"{v:.2e}") for v in rel.max(axis=(0, 2))]
-    base = dict(value=done / dt, unit="samples/s", cores=threads, kind="oracle",
-                sample=f"the first {done} samples of the step's batch at level {level} "
-                       f"({w['n0'] << level}^2): direct-sum KL field + CPU FMG to rtol "
-                       f"{w['rtol']:g} + QoI, {dt:.1f} s wall, -O3 -march=native",
+    base = dict(value=round(done / dt, 3), unit="samples/s", cores=threads, kind="oracle",
+                sample=f"first {done} samples of the step's batch, level {level} "
+                       f"({w['n0'] << level}^2): direct-sum KL + CPU FMG to rtol "
+                       f"{w['rtol']:g} + QoI; {dt:.1f} s; -O3 -march=native",
                 not_converged=bad)
     return base, err, done
 
@@ -816,27 +816,28 @@ def main():
                higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="mixed: bf16 field digits, f32 V-cycles, f64 CG and sums",
                data="synthetic",
-               config=dict(workload=f"mlqmc_mixed_s400 at {n}^2: s = 400, lambda 0.1, sigma^2 2, "
-                                    f"MLMC levels 4^2..{n}^2, every FMG stage to rtol 1e-10",
+               config=dict(workload=f"mlqmc_mixed_s400 at {n}^2 (s 400, lambda 0.1, sigma^2 2, "
+                                    f"levels 4^2..{n}^2, FMG stages to rtol 1e-10)",
                            samples_per_step=B, points=args.points, shifts=args.shifts,
                            level=k),
                fp64_value=round(fp64["value"], 2),
                ratio_mixed_over_fp64=round(mixed["value"] / fp64["value"], 3),
-               max_rel_diff_mixed_fp64_per_level=[float(f"{v:.1e}") for v in
-                                                  diff.max(axis=(0, 2))],
                not_converged=dict(mixed=mixed["info"]["not_converged"],
                                   fp64=fp64["info"]["not_converged"]),
                roofline=dict(kernel=KERNEL_NAMES[dominant], bound="hbm",
                              achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                             frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                             frac=round(achieved / HBM_PEAK_GBS, 4),
+                             traffic=None if traffic is None else round(traffic),
                              traffic_source=traffic_src, avg_launch_ms=round(avg_ms, 4),
                              launches_per_step=prof["launches"] / args.steps,
                              algorithmic_bytes_per_launch=round(bytes_per_launch),
                              byte_model=BYTE_MODEL[dominant],
-                             share_of_step=round(prof["total_ms"] / (mixed["elapsed"] * 1e3), 3)),
-               estimate=dict(q_bar=float(mixed["est"]["q_bar"][0]),
-                             std=float(np.sqrt(mixed["est"]["var_q"][0]))))
+                             share_of_step=round(prof["total_ms"] / (mixed["elapsed"] * 1e3), 3)))
+    log(f"[bench] estimate of the step's batch: q_bar {mixed['est']['q_bar'][0]:.10g}, "
+        f"std {np.sqrt(mixed['est']['var_q'][0]):.4g}")
     log("[bench] breakdown of one mixed step: " + json.dumps(mixed["breakdown"]))
+    log("[bench] max rel diff mixed vs fp64 on the step's QoI table, per MLMC level: " +
+        json.dumps([float(f"{v:.1e}") for v in diff.max(axis=(0, 2))]))
     if not args.no_extras:
         lv = per_level(m, torch, ctxs, w, dev, skip_level=k)
         lv[f"{n}^2"] = dict(samples=B, mixed=mixed["value"], fp64=fp64["value"],
@@ -844,7 +845,7 @@ def main():
         out["per_level"] = {key: [round(r["mixed"]), round(r["fp64"]),
                                   round(r["mixed"] / r["fp64"], 2),
                                   float(f"{r['max_rel_diff']:.1e}")] for key, r in lv.items()}
-        out["per_level_columns"] = "mixed samples/s, fp64 samples/s, ratio, max rel diff"
+        out["per_level_columns"] = "mixed/s, fp64/s, ratio, max rel diff"
         out["latency_p50_p99_ms"] = latency(m, torch, ctxs["mixed"], w, dev, (0, 4, 8))
         # points of the step's batch, for the oracle (y = Phi^-1 of the lattice points)
         y = torch.zeros((B, w["s"]), dtype=torch.float64, device=dev)

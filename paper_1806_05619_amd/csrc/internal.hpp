@@ -34,6 +34,17 @@ constexpr int kLdsMaxLevelFixed = 3;   // fixed-cycle mode: up to 16^2; 32^2 run
 __host__ __device__ inline int64_t level_offset(int g) { return 4 * (((int64_t)1 << (2 * g)) - 1) / 3; }
 __host__ __device__ inline int64_t level_cells(int g) { return (int64_t)4 << (2 * g); }
 
+// Blocks are dealt round-robin over the 8 XCDs.  This bijection of a grid of
+// nb = 8 q + r blocks hands XCD x the contiguous logical range starting at
+// x q + min(x, r), so that blocks whose work shares data (neighbouring strips
+// of a stencil, the sample tiles of one basis panel) read it through the
+// same L2.
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t bid, int64_t nb)
+{
+    const int64_t q = nb / 8, r = nb % 8, x = bid % 8;
+    return x * q + (x < r ? x : r) + bid / 8;
+}
+
 // Bilinear prolongation of a cell-centred coarse correction (Section 4): the
 // fine cell gets (9 c + 3 x + 3 y + d) / 16 from its coarse parent c, the two
 // coarse neighbours x, y on its side and the diagonal one d.  The rounding

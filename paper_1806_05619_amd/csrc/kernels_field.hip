@@ -20,13 +20,16 @@ constexpr int FBM = 128, FBN = 128, FKB = 16, FNT = 512;
 // mode 0: z to out[b*M + m]; mode 1: exp(z) into the level-major FP64 pool
 __global__ __launch_bounds__(FNT) void k_field_mfma64(const double *__restrict__ Y, int s,
                                                       const double *__restrict__ basis, int64_t ld,
-                                                      int64_t M, int64_t Bc,
+                                                      int64_t M, int64_t Bc, int64_t nbm,
                                                       double *__restrict__ out, int mode)
 {
     __shared__ double As[FKB][FBM];      // Y tile, mode-major
     __shared__ double Bs[FKB][FBN];      // basis tile
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t row0 = (int64_t)blockIdx.y * FBM, col0 = (int64_t)blockIdx.x * FBN;
+    // the sample tiles of one basis panel take consecutive work indices on
+    // one XCD: the panel comes from HBM once, then from that XCD's L2
+    const int64_t L = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int64_t row0 = (L % nbm) * FBM, col0 = (L / nbm) * FBN;
     const int wr = wave >> 1, wc = wave & 1;      // 4 x 2 waves
     d4 acc[2][4];
 #pragma unroll
@@ -114,9 +117,9 @@ __global__ __launch_bounds__(FNT) void k_field_mfma64(const double *__restrict__
 void launch_field_gemm(hipStream_t st, const double *Y, int s, const double *basis, int64_t ld,
                        int64_t M, int64_t Bc, void *out, int mode)
 {
-    dim3 grid((unsigned)((M + FBN - 1) / FBN), (unsigned)((Bc + FBM - 1) / FBM));
-    hipLaunchKernelGGL(k_field_mfma64, grid, dim3(FNT), 0, st, Y, s, basis, ld, M, Bc,
-                       (double *)out, mode);
+    const int64_t nbm = (Bc + FBM - 1) / FBM, nbn = (M + FBN - 1) / FBN;
+    hipLaunchKernelGGL(k_field_mfma64, dim3((unsigned)(nbm * nbn)), dim3(FNT), 0, st, Y, s, basis,
+                       ld, M, Bc, nbm, (double *)out, mode);
 }
 
 }  // namespace mlmc

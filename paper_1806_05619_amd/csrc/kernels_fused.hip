@@ -910,15 +910,8 @@ struct FcgMap {
     int nch;         // blocks per sample
     int i0, j0;      // first column and first row of the thread's strip
 };
-// Blocks are dealt round-robin over the 8 XCDs.  This bijection of a grid of
-// nb = 8 q + r blocks hands XCD x the contiguous logical range starting at
-// x q + min(x, r), so that the strips above and below a block's rows (the
-// stencil's neighbours) are read by blocks of the same XCD, through its L2.
-__device__ __forceinline__ int64_t xcd_contiguous(int64_t bid, int64_t nb)
-{
-    const int64_t q = nb / 8, r = nb % 8, x = bid % 8;
-    return x * q + (x < r ? x : r) + bid / 8;
-}
+// Blocks go through xcd_contiguous, so that the strips above and below a
+// block's rows (the stencil's neighbours) are read by blocks of the same XCD.
 
 template <int CW, int QH>
 __device__ __forceinline__ bool fcg_map(int n, int64_t Bc, const int32_t *active, FcgMap &m)

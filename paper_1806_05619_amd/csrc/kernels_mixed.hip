@@ -132,7 +132,7 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
 // level-major pool `out` and as double into `out64`.
 __global__ __launch_bounds__(256, 1) void k_field_digits(DigitPtrs Yp, const int32_t *__restrict__ EY,
                                                          DigitPtrs Bp, const int32_t *__restrict__ EB,
-                                                         int sp, int64_t M, int64_t Bc,
+                                                         int sp, int64_t M, int64_t Bc, int64_t nbm,
                                                          void *__restrict__ out,
                                                          double *__restrict__ out64, int mode)
 {
@@ -146,7 +146,11 @@ __global__ __launch_bounds__(256, 1) void k_field_digits(DigitPtrs Yp, const int
     __shared__ __attribute__((aligned(16))) uint16_t As[2][ND][BM * KP];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[2][ND][BN * KP];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t brow0 = (int64_t)blockIdx.y * BM, bcol0 = (int64_t)blockIdx.x * BN;
+    // the sample tiles of one basis panel take consecutive work indices on
+    // one XCD, so that the panel's digits come from HBM once and from that
+    // XCD's L2 for the other sample tiles
+    const int64_t L = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int64_t brow0 = (L % nbm) * BM, bcol0 = (L / nbm) * BN;
     const int64_t row0 = brow0 + (wave >> 1) * WM;    // sample rows of this wave
     const int64_t col0 = bcol0 + (wave & 1) * WN;     // field columns of this wave
     const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
@@ -294,9 +298,9 @@ void launch_field_digits(hipStream_t st, uint16_t *const Y[kDigits], const int32
         PY.d[q] = Y[q];
         PB.d[q] = Bs[q];
     }
-    dim3 grid((unsigned)((M + BN - 1) / BN), (unsigned)((Bc + BM - 1) / BM));
-    hipLaunchKernelGGL(k_field_digits, grid, dim3(256), 0, st, PY, EY, PB, EB, sp, M, Bc, out,
-                       out64, mode);
+    const int64_t nbm = (Bc + BM - 1) / BM, nbn = (M + BN - 1) / BN;
+    hipLaunchKernelGGL(k_field_digits, dim3((unsigned)(nbm * nbn)), dim3(256), 0, st, PY, EY, PB, EB,
+                       sp, M, Bc, nbm, out, out64, mode);
 }
 
 }  // namespace mlmc

@@ -188,6 +188,7 @@ void k_stream(const T *__restrict__ a, const T *__restrict__ f, const T *u_in, T
     // rows fetched ahead: two in FP32; one in FP64, whose second row of
     // registers measured no faster (or spills)
     constexpr int PD = sizeof(T) == 4 ? 2 : 1;
+    static_assert(8 % PD == 0, "prefetch sets are indexed by row mod 8");
     extern __shared__ double smem_words[];
     T *smem = reinterpret_cast<T *>(smem_words);
     constexpr int nc = n / 2;
@@ -297,7 +298,7 @@ void k_stream(const T *__restrict__ a, const T *__restrict__ f, const T *u_in, T
         __syncthreads();
         // (A) row s enters the rings; fetch row s + 1
         const T rhs_prev0 = rhs_cur0, rhs_prev1 = rhs_cur1;
-        Prefetch &pp = pre[P % PD];
+        Prefetch &pp = pre[J % PD];      // row s's set (row mod PD)
         if (s < n && lane) {
             T u0 = pp.u0, u1 = pp.u1;
             if constexpr (need_coarse) {
