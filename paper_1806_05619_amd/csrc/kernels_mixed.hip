@@ -115,12 +115,16 @@ __global__ __launch_bounds__(256) void k_digits_thread(const double *__restrict_
     E[r] = e;
 }
 
-__device__ __forceinline__ int64_t level_major_index_m(int64_t m, int64_t b, int64_t Bc)
+// field column m (cells of all levels, coarsest first) in the level-major
+// pool of Bc samples: sample b's value sits at base + b * stride
+__device__ __forceinline__ void level_major_column(int64_t m, int64_t Bc, int64_t &base,
+                                                   int64_t &stride)
 {
     int g = 0;
     while (g < kMaxMgLevels - 1 && level_offset(g + 1) <= m) ++g;
     const int64_t lo = level_offset(g);
-    return Bc * lo + b * level_cells(g) + (m - lo);
+    base = Bc * lo + (m - lo);
+    stride = level_cells(g);
 }
 
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
@@ -128,24 +132,33 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// LDS place of 16-byte chunk c (modes 8c .. 8c+7) of panel row r: slot
+// 4 r + (c ^ swz(r)).  The 16 rows that the lanes of a quarter-wavefront read
+// at one chunk fall into 16 distinct 4-bank groups of a 64-bank LDS, and the
+// rows of each eighth of a wavefront into 8 distinct groups of a 32-bank one.
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
 // out mode 0: z (double) at out[b*M + m]; mode 2: exp(z) as float into the
 // level-major pool `out` and as double into `out64`.
-__global__ __launch_bounds__(256, 1) void k_field_digits(DigitPtrs Yp, const int32_t *__restrict__ EY,
+// Two workgroups per CU (registers <= 256, LDS 80 KiB each): one's loads and
+// epilogue overlap the other's matrix-core work.
+__global__ __launch_bounds__(256, 2) void k_field_digits(DigitPtrs Yp, const int32_t *__restrict__ EY,
                                                          DigitPtrs Bp, const int32_t *__restrict__ EB,
                                                          int sp, int64_t M, int64_t Bc, int64_t nbm,
                                                          void *__restrict__ out,
                                                          double *__restrict__ out64, int mode)
 {
-    // The block's 64 x 32 digit panels of Y and of the basis are staged in
-    // LDS, double-buffered: every 16-byte chunk is fetched from global memory
-    // once per block (not once per wavefront that uses it), and the chunks of
-    // the next 32 modes are in flight while the matrix cores work on the
-    // current ones.  Rows are padded to KP bf16 so that the 16 rows a
-    // quarter-wavefront reads fall into distinct LDS banks.
-    constexpr int KP = 40;
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][ND][BM * KP];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][ND][BN * KP];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    // The block's 64 x 32 digit panels of Y and of the basis go from global
+    // memory straight into LDS (global_load_lds, 16 bytes a lane), double
+    // buffered: every chunk is fetched once per block, and the panels of the
+    // next 32 modes are in flight while the matrix cores work on the current
+    // ones.  A load instruction of a wavefront fills 64 consecutive slots
+    // (16 rows of one digit of one operand); lane l takes slot l, i.e. row
+    // l / 4 of the group and the chunk that the swizzle places there.
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][ND][BM * 32];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][ND][BN * 32];
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     // the sample tiles of one basis panel take consecutive work indices on
     // one XCD, so that the panel's digits come from HBM once and from that
     // XCD's L2 for the other sample tiles
@@ -154,7 +167,7 @@ __global__ __launch_bounds__(256, 1) void k_field_digits(DigitPtrs Yp, const int
     const int64_t row0 = brow0 + (wave >> 1) * WM;    // sample rows of this wave
     const int64_t col0 = bcol0 + (wave & 1) * WN;     // field columns of this wave
     const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
-    const int lr = lane & 15, kg = 8 * (lane >> 4);
+    const int lr = lane & 15, q4 = lane >> 4;
     double acc[2][2][4];
     f32x4 G[ND][2][2];
 #pragma unroll
@@ -166,25 +179,36 @@ __global__ __launch_bounds__(256, 1) void k_field_digits(DigitPtrs Yp, const int
 #pragma unroll
             for (int g = 0; g < ND; ++g) G[g][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
-    // staging: ND digits x 64 rows x 4 chunks of 8 modes per operand; chunk
-    // (digit q, row t / 4, modes 8 (t % 4) .. +7) per thread and digit (rows
-    // and columns are padded, all in range)
-    const int sr = t >> 2, sk = (t & 3) * 8;
-    bf16x8 ya[ND], yb[ND];
-    auto fetch = [&](int k0) {
+    // wave w loads row group w (rows 16 w .. 16 w + 15) of every digit of
+    // both operands: 2 ND instructions per K step (rows and columns are
+    // padded, all in range)
+    const int ldr = 16 * wave + (lane >> 2);
+    const int ldc = 8 * ((lane & 3) ^ swz(ldr));
+    const uint16_t *ysrc[ND], *bsrc[ND];
+#pragma unroll
+    for (int q = 0; q < ND; ++q) {
+        ysrc[q] = Yp.d[q] + (brow0 + ldr) * sp + ldc;
+        bsrc[q] = Bp.d[q] + (bcol0 + ldr) * sp + ldc;
+    }
+    auto issue = [&](int k0, int buf) {
 #pragma unroll
         for (int q = 0; q < ND; ++q) {
-            ya[q] = *(const bf16x8 *)(Yp.d[q] + (brow0 + sr) * sp + k0 + sk);
-            yb[q] = *(const bf16x8 *)(Bp.d[q] + (bcol0 + sr) * sp + k0 + sk);
+            __builtin_amdgcn_global_load_lds(ysrc[q] + k0,
+                                             (__attribute__((address_space(3))) void *)&As[buf][q][512 * wave],
+                                             16, 0, 0);
+            __builtin_amdgcn_global_load_lds(bsrc[q] + k0,
+                                             (__attribute__((address_space(3))) void *)&Bs[buf][q][512 * wave],
+                                             16, 0, 0);
         }
     };
-    auto stage = [&](int buf) {
+    // LDS element offsets of the operand chunks this lane reads (row, chunk q4)
+    int aoff[2], boff[2];
 #pragma unroll
-        for (int q = 0; q < ND; ++q) {
-            *(bf16x8 *)(&As[buf][q][sr * KP + sk]) = ya[q];
-            *(bf16x8 *)(&Bs[buf][q][sr * KP + sk]) = yb[q];
-        }
-    };
+    for (int i = 0; i < 2; ++i) {
+        const int ra = wr + 16 * i + lr, rb = wc + 16 * i + lr;
+        aoff[i] = 8 * (4 * ra + (q4 ^ swz(ra)));
+        boff[i] = 8 * (4 * rb + (q4 ^ swz(rb)));
+    }
     // the digit products (digit of Y, digit of the basis, weight group), in
     // increasing weight
     constexpr int PA[NP] = {0, 0, 1, 0, 2, 1, 0, 3, 1, 2, 0, 4, 1, 3, 2};
@@ -192,23 +216,28 @@ __global__ __launch_bounds__(256, 1) void k_field_digits(DigitPtrs Yp, const int
     constexpr int PG[NP] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4, 4};
     static_assert(ND == 5, "product table written for five digits");
     const int nk = sp / 32;
-    fetch(0);
-    stage(0);
-    __syncthreads();
+    issue(0, 0);
     for (int ks = 0; ks < nk; ++ks) {
         const int buf = ks & 1;
-        if (ks + 1 < nk) fetch(32 * (ks + 1));
+        // this wave's loads of step ks have landed; after the barrier every
+        // wave's have, and buffer buf ^ 1 is free (its readers of step ks - 1
+        // passed the barrier)
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
         bf16x8 a[2][ND], b[2][ND];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int d = 0; d < ND; ++d)
-                a[i][d] = *(const bf16x8 *)(&As[buf][d][(wr + 16 * i + lr) * KP + kg]);
+                a[i][d] = *(const bf16x8 *)(&As[buf][d][aoff[i]]);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int d = 0; d < ND; ++d)
-                b[j][d] = *(const bf16x8 *)(&Bs[buf][d][(wc + 16 * j + lr) * KP + kg]);
+                b[j][d] = *(const bf16x8 *)(&Bs[buf][d][boff[j]]);
+        // the next panels' loads go out after this step's reads, so that no
+        // wait for them falls before the matrix-core work of this step
+        if (ks + 1 < nk) issue(32 * (ks + 1), buf ^ 1);
         // each product over the four 16 x 16 tiles in turn, so that
         // consecutive MFMAs write different accumulators
 #pragma unroll
@@ -236,16 +265,14 @@ __global__ __launch_bounds__(256, 1) void k_field_digits(DigitPtrs Yp, const int
                     for (int g = 0; g < ND; ++g) G[g][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
         }
-        if (ks + 1 < nk) {
-            stage(buf ^ 1);      // its last readers finished before the previous barrier
-            __syncthreads();
-        }
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int64_t m = col0 + 16 * j + lr;
         if (m >= M) continue;
         const int ec = EB[m];
+        int64_t base = 0, stride = 0;
+        if (mode != 0) level_major_column(m, Bc, base, stride);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -256,7 +283,7 @@ __global__ __launch_bounds__(256, 1) void k_field_digits(DigitPtrs Yp, const int
                 if (mode == 0) {
                     ((double *)out)[b * M + m] = z;
                 } else {
-                    const int64_t q = level_major_index_m(m, b, Bc);
+                    const int64_t q = base + b * stride;
                     const double av = exp(z);
                     ((float *)out)[q] = (float)av;
                     out64[q] = av;
