@@ -145,7 +145,7 @@ __device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 __global__ __launch_bounds__(256, 2) void k_field_digits(DigitPtrs Yp, const int32_t *__restrict__ EY,
                                                          DigitPtrs Bp, const int32_t *__restrict__ EB,
                                                          int sp, int64_t M, int64_t Bc, int64_t nbm,
-                                                         void *__restrict__ out,
+                                                         int ng, void *__restrict__ out,
                                                          double *__restrict__ out64, int mode)
 {
     // The block's 64 x 32 digit panels of Y and of the basis go from global
@@ -159,11 +159,16 @@ __global__ __launch_bounds__(256, 2) void k_field_digits(DigitPtrs Yp, const int
     __shared__ __attribute__((aligned(16))) uint16_t Bs[2][ND][BN * 32];
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-    // the sample tiles of one basis panel take consecutive work indices on
-    // one XCD, so that the panel's digits come from HBM once and from that
-    // XCD's L2 for the other sample tiles
+    // Work order: ng groups of sample tiles, each taking every column tile in
+    // turn with the group's sample tiles innermost; xcd_contiguous hands
+    // every XCD a contiguous range of it.  A basis panel then comes from HBM
+    // once per group (the XCDs of different groups read it at about the same
+    // time, through the shared last-level cache), and the digits of Y that an
+    // XCD cycles through (one group's sample tiles) stay in its L2.
     const int64_t L = xcd_contiguous(blockIdx.x, gridDim.x);
-    const int64_t brow0 = (L % nbm) * BM, bcol0 = (L / nbm) * BN;
+    const int64_t per = nbm / ng, span = per * (gridDim.x / nbm);
+    const int64_t grp = L / span, rem = L - grp * span;
+    const int64_t brow0 = (grp * per + rem % per) * BM, bcol0 = (rem / per) * BN;
     const int64_t row0 = brow0 + (wave >> 1) * WM;    // sample rows of this wave
     const int64_t col0 = bcol0 + (wave & 1) * WN;     // field columns of this wave
     const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
@@ -217,6 +222,21 @@ __global__ __launch_bounds__(256, 2) void k_field_digits(DigitPtrs Yp, const int
     static_assert(ND == 5, "product table written for five digits");
     const int nk = sp / 32;
     issue(0, 0);
+    // scale exponents and level-major addresses of the epilogue, fetched
+    // while the first panels load (the exponent arrays are padded like the
+    // digit rows, so every index is in range)
+    int ey[2][4], eb[2];
+    int64_t base[2] = {0, 0}, stride[2] = {0, 0};
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ey[i][e] = EY[row0 + 16 * i + 4 * q4 + e];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int64_t m = col0 + 16 * j + lr;
+        eb[j] = EB[m];
+        if (mode != 0 && m < M) level_major_column(m, Bc, base[j], stride[j]);
+    }
     for (int ks = 0; ks < nk; ++ks) {
         const int buf = ks & 1;
         // this wave's loads of step ks have landed; after the barrier every
@@ -270,20 +290,17 @@ __global__ __launch_bounds__(256, 2) void k_field_digits(DigitPtrs Yp, const int
     for (int j = 0; j < 2; ++j) {
         const int64_t m = col0 + 16 * j + lr;
         if (m >= M) continue;
-        const int ec = EB[m];
-        int64_t base = 0, stride = 0;
-        if (mode != 0) level_major_column(m, Bc, base, stride);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t b = row0 + 16 * i + 4 * (lane >> 4) + e;
+                const int64_t b = row0 + 16 * i + 4 * q4 + e;
                 if (b >= Bc) continue;
-                const double z = ldexp(acc[i][j][e], EY[b] + ec - 14);
+                const double z = ldexp(acc[i][j][e], ey[i][e] + eb[j] - 14);
                 if (mode == 0) {
                     ((double *)out)[b * M + m] = z;
                 } else {
-                    const int64_t q = base + b * stride;
+                    const int64_t q = base[j] + b * stride[j];
                     const double av = exp(z);
                     ((float *)out)[q] = (float)av;
                     out64[q] = av;
@@ -326,8 +343,11 @@ void launch_field_digits(hipStream_t st, uint16_t *const Y[kDigits], const int32
         PB.d[q] = Bs[q];
     }
     const int64_t nbm = (Bc + BM - 1) / BM, nbn = (M + BN - 1) / BN;
+    // two groups of sample tiles once Y's digits (nbm x 266 KB at s = 400)
+    // outgrow an XCD's 4 MB L2
+    const int ng = (nbm >= 8 && nbm % 2 == 0) ? 2 : 1;
     hipLaunchKernelGGL(k_field_digits, dim3((unsigned)(nbm * nbn)), dim3(256), 0, st, PY, EY, PB, EB,
-                       sp, M, Bc, nbm, out, out64, mode);
+                       sp, M, Bc, nbm, ng, out, out64, mode);
 }
 
 }  // namespace mlmc
