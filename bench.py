@@ -51,8 +51,8 @@ BYTE_MODEL = dict(
     pre="a, u (unless zero or interpolated), f (unless 1) read, u written, f_c written (w/4)",
     post="e_c (w/4), a, u, f (unless 1) read, u written",
     lds="coefficients of the LDS grids read, top-level solution written",
-    refine="24 + 9w B per cell of the samples still iterating (24 + 7w at a stage's first "
-           "step), w = V-cycle word size")
+    refine="24+9w B per cell of the samples still iterating (24+7w at a stage's first "
+           "step), w = V-cycle word bytes")
 
 KINDS = ("points", "field", "smooth", "restrict", "prolong", "coarse", "qoi", "sums", "pre", "post",
          "lds", "refine")
@@ -66,7 +66,7 @@ KERNEL_NAMES = dict(
     post="post pass (prolongation + correction + 2 sweeps): k_post_tile / k_stream on every "
          "grid above the LDS-resident ones",
     lds="k_lds_fmg_refine, k_lds_vcycle (LDS-resident grids <= 32^2)",
-    refine="one flexible-CG step (>= 64^2): k_fcg_dots + k_fcg_p + k_fcg_x + folds")
+    refine="one flexible-CG step (>= 64^2): k_fcg_dots+k_fcg_p+k_fcg_x+folds")
 
 
 def log(*a):
@@ -95,11 +95,12 @@ def measured_traffic(kind):
     return r["hbm_bytes_per_launch"], rec
 
 
-def make_context(m, w, max_batch):
+def make_context(m, w, max_batch, precision=None):
     import synth
     return m.Context(w["n0"], w["num_levels"], w["s"], w["corr_len"], w["sigma2"],
                      mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"],
-                     max_iters=w["max_iters"], precision=m.MLMC_FP64,
+                     max_iters=w["max_iters"],
+                     precision=m.MLMC_FP64 if precision is None else precision,
                      qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
                      genvec=synth.korobov_vector(w["seed"], w["s"]),
                      shifts=synth.shift_table(w["seed"], w["num_levels"], w["num_shifts"], w["s"]),
@@ -595,9 +596,9 @@ def oracle_baseline(w, level, y_batch, gpu_qoi, seconds, max_samples):
         rel = np.abs(qg[:done] - qo) / np.abs(qo)          # [samples][level][nq]
         err[name] = [float(f"{v:.2e}") for v in rel.max(axis=(0, 2))]
     base = dict(value=round(done / dt, 3), unit="samples/s", cores=threads, kind="oracle",
-                sample=f"first {done} samples of the step's batch, level {level} "
-                       f"({w['n0'] << level}^2): direct-sum KL + CPU FMG to rtol "
-                       f"{w['rtol']:g} + QoI; {dt:.1f} s; -O3 -march=native",
+                sample=f"first {done} samples of the step's batch at {w['n0'] << level}^2: "
+                       f"direct-sum KL + CPU FMG to {w['rtol']:g} + QoI; {dt:.1f} s; "
+                       f"-O3 -march=native",
                 not_converged=bad)
     return base, err, done
 
@@ -615,6 +616,23 @@ def solve_rate(ctx, pts, torch, min_seconds, q=None, sums=None):
         if time.perf_counter() - t0 >= min_seconds:
             break
     return B * reps / (time.perf_counter() - t0)
+
+
+def levels_only(m, torch, args):
+    """The per-level table of the s = 400 workload on its own (every level's
+    own batch, both paths, the finest level included), autotuned contexts
+    sized for the benchmark's batch."""
+    import synth
+    w = synth.workload("mlqmc_mixed_s400")
+    dev = torch.device("cuda:0")
+    ctxs = {name: make_context(m, w, args.points * args.shifts, precision=prec)
+            for name, prec in (("mixed", m.MLMC_MIXED), ("fp64", m.MLMC_FP64))}
+    if not args.no_autotune:
+        for c in ctxs.values():
+            c.autotune(w["num_levels"] - 1)
+    lv = per_level(m, torch, ctxs, w, dev)
+    return {key: [round(r["mixed"]), round(r["fp64"]), round(r["mixed"] / r["fp64"], 2),
+                  float(f"{r['max_rel_diff']:.1e}")] for key, r in lv.items()}
 
 
 def per_level(m, torch, ctxs, w, dev, min_seconds=0.25, skip_level=None):
@@ -771,11 +789,13 @@ def main():
                     help="run only the serving-loop measurement (prints its JSON object)")
     ap.add_argument("--only-uneven", action="store_true",
                     help="run only the uneven-level comparison (prints its JSON object)")
+    ap.add_argument("--only-levels", action="store_true",
+                    help="run only the per-level mixed vs FP64 table (prints its JSON object)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path "
               "shards by shift or lattice range with one small all-reduce of the sums, "
-              "which this build does not run.", file=sys.stderr)
+              "which this program does not run.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -784,6 +804,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     for flag, fn in ((args.only_uneven, lambda: uneven(m, torch)),
+                     (args.only_levels, lambda: levels_only(m, torch, args)),
                      (args.only_serving, lambda: serving(m, torch)),
                      (args.only_methods, lambda: methods(m, torch)),
                      (args.only_c2, lambda: fp64_fixed_c2(m, torch, args)),

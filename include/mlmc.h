@@ -343,9 +343,11 @@ mlmc_status mlmc_profile_end(mlmc_ctx ctx, mlmc_profile_result *out);
  * c, the number of 32 x 32 tiles of the pass, t = 4^c (n/32)^2, and the
  * lanes of a streaming pass, 4^c n/2: TILE16 for t <= 256, TILE32
  * otherwise; STREAM takes the pre and the post pass once it has at least
- * 131072 lanes and t >= 65536 (FP64 V-cycles: t >= 16384 when n <= 64), with
- * FP64 V-cycles up to 1024^2 only.  mlmc_autotune replaces the defaults by
- * what it measures.  A server's slots take the first slot's table. */
+ * 131072 lanes and t >= 65536 (FP64 V-cycles: t >= 16384 when n <= 64) and
+ * the smallest chunk of the class, 4^(c-1) + 1 samples, fills 256
+ * workgroups, with FP64 V-cycles up to 1024^2 only.  mlmc_autotune replaces
+ * the defaults by what it measures.  A server's slots take the first slot's
+ * table. */
 enum { MLMC_PASS_TILE32 = 0, MLMC_PASS_TILE16 = 1, MLMC_PASS_STREAM = 2 };
 enum { MLMC_BATCH_CLASSES = 10 };
 typedef struct {

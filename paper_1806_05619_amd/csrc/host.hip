@@ -463,21 +463,26 @@ bool kind_allowed(mlmc_ctx c, int g, int kind)
 // 256 tiles (one per CU or fewer) 16 x 16 tiles, which give four times the
 // workgroups; 32 x 32 tiles otherwise; the row-streaming passes take both
 // passes once they have 131072 lanes and t >= 65536 (FP64 from t = 16384 on
-// 32^2 and 64^2, where a workgroup packs 4 or 2 samples), in FP64 up to
-// 1024^2 (the 2048^2 FP64 workgroup of 1024 lanes spills registers and
-// measured slower than tiles).
+// 32^2 and 64^2, where a workgroup packs 4 or 2 samples) and the smallest
+// chunk of the class still gives every CU a workgroup (a streaming workgroup
+// holds one sample from 128^2 up, so 128 samples of 2048^2 streamed leave
+// half the CUs idle), in FP64 up to 1024^2 (the 2048^2 FP64
+// workgroup of 1024 lanes spills registers and measured slower than tiles).
 void default_tuning(mlmc_ctx c)
 {
     const bool fp64 = c->cfg.precision == MLMC_FP64;
     for (int g = 0; g < kMaxMgLevels; ++g) {
         const int n = 2 << g;
         const int64_t side = std::max(1, n / 32);
+        const int64_t spb = n >= 128 ? 1 : 64 / (n / 2);
         const bool stream = kind_allowed(c, g, kStream) && (!fp64 || n <= 1024);
         for (int cl = 0; cl < MLMC_BATCH_CLASSES; ++cl) {
             const int64_t tiles = ((int64_t)1 << (2 * cl)) * side * side;
             const int64_t lanes = ((int64_t)1 << (2 * cl)) * (n / 2);
+            const int64_t smallest = cl == 0 ? 1 : ((int64_t)1 << (2 * (cl - 1))) + 1;
             const int8_t tile = tiles <= 256 ? kTile16 : kTile32;
-            const bool big = (tiles >= 65536 || (fp64 && n <= 64 && tiles >= 16384)) && lanes >= 131072;
+            const bool big = (tiles >= 65536 || (fp64 && n <= 64 && tiles >= 16384)) &&
+                             lanes >= 131072 && smallest / spb >= 256;
             c->pre_kind[g][cl] = stream && big ? kStream : tile;
             c->post_kind[g][cl] = stream && big ? kStream : tile;
         }

@@ -21,15 +21,18 @@ constexpr int FBM = 128, FBN = 128, FKB = 16, FNT = 512;
 __global__ __launch_bounds__(FNT) void k_field_mfma64(const double *__restrict__ Y, int s,
                                                       const double *__restrict__ basis, int64_t ld,
                                                       int64_t M, int64_t Bc, int64_t nbm,
-                                                      double *__restrict__ out, int mode)
+                                                      int64_t per, double *__restrict__ out,
+                                                      int mode)
 {
     __shared__ double As[FKB][FBM];      // Y tile, mode-major
     __shared__ double Bs[FKB][FBN];      // basis tile
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    // the sample tiles of one basis panel take consecutive work indices on
-    // one XCD: the panel comes from HBM once, then from that XCD's L2
-    const int64_t L = xcd_contiguous(blockIdx.x, gridDim.x);
-    const int64_t row0 = (L % nbm) * FBM, col0 = (L / nbm) * FBN;
+    // groups of `per` sample tiles over every basis panel (grouped_tile): the
+    // rows of Y an XCD cycles through stay in its L2, and a basis panel
+    // comes from HBM about once
+    int64_t mt, nt;
+    grouped_tile(xcd_contiguous(blockIdx.x, gridDim.x), nbm, gridDim.x / nbm, per, mt, nt);
+    const int64_t row0 = mt * FBM, col0 = nt * FBN;
     const int wr = wave >> 1, wc = wave & 1;      // 4 x 2 waves
     d4 acc[2][4];
 #pragma unroll
@@ -118,8 +121,9 @@ void launch_field_gemm(hipStream_t st, const double *Y, int s, const double *bas
                        int64_t M, int64_t Bc, void *out, int mode)
 {
     const int64_t nbm = (Bc + FBM - 1) / FBM, nbn = (M + FBN - 1) / FBN;
+    const int64_t per = grouped_tile_per(nbm, (int64_t)FBM * s * 8, M * s * 8);
     hipLaunchKernelGGL(k_field_mfma64, dim3((unsigned)(nbm * nbn)), dim3(FNT), 0, st, Y, s, basis,
-                       ld, M, Bc, nbm, (double *)out, mode);
+                       ld, M, Bc, nbm, per, (double *)out, mode);
 }
 
 }  // namespace mlmc

@@ -145,7 +145,7 @@ __device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 __global__ __launch_bounds__(256, 2) void k_field_digits(DigitPtrs Yp, const int32_t *__restrict__ EY,
                                                          DigitPtrs Bp, const int32_t *__restrict__ EB,
                                                          int sp, int64_t M, int64_t Bc, int64_t nbm,
-                                                         int ng, void *__restrict__ out,
+                                                         int64_t per, void *__restrict__ out,
                                                          double *__restrict__ out64, int mode)
 {
     // The block's 64 x 32 digit panels of Y and of the basis go from global
@@ -159,16 +159,12 @@ __global__ __launch_bounds__(256, 2) void k_field_digits(DigitPtrs Yp, const int
     __shared__ __attribute__((aligned(16))) uint16_t Bs[2][ND][BN * 32];
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-    // Work order: ng groups of sample tiles, each taking every column tile in
-    // turn with the group's sample tiles innermost; xcd_contiguous hands
-    // every XCD a contiguous range of it.  A basis panel then comes from HBM
-    // once per group (the XCDs of different groups read it at about the same
-    // time, through the shared last-level cache), and the digits of Y that an
-    // XCD cycles through (one group's sample tiles) stay in its L2.
-    const int64_t L = xcd_contiguous(blockIdx.x, gridDim.x);
-    const int64_t per = nbm / ng, span = per * (gridDim.x / nbm);
-    const int64_t grp = L / span, rem = L - grp * span;
-    const int64_t brow0 = (grp * per + rem % per) * BM, bcol0 = (rem / per) * BN;
+    // groups of `per` sample tiles over every basis panel (grouped_tile): the
+    // digits of Y an XCD cycles through stay in its L2, and a basis panel
+    // comes from HBM about once
+    int64_t mt, nt;
+    grouped_tile(xcd_contiguous(blockIdx.x, gridDim.x), nbm, gridDim.x / nbm, per, mt, nt);
+    const int64_t brow0 = mt * BM, bcol0 = nt * BN;
     const int64_t row0 = brow0 + (wave >> 1) * WM;    // sample rows of this wave
     const int64_t col0 = bcol0 + (wave & 1) * WN;     // field columns of this wave
     const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
@@ -343,11 +339,9 @@ void launch_field_digits(hipStream_t st, uint16_t *const Y[kDigits], const int32
         PB.d[q] = Bs[q];
     }
     const int64_t nbm = (Bc + BM - 1) / BM, nbn = (M + BN - 1) / BN;
-    // two groups of sample tiles once Y's digits (nbm x 266 KB at s = 400)
-    // outgrow an XCD's 4 MB L2
-    const int ng = (nbm >= 8 && nbm % 2 == 0) ? 2 : 1;
+    const int64_t per = grouped_tile_per(nbm, (int64_t)BM * sp * 2 * ND, nbn * BN * sp * 2 * ND);
     hipLaunchKernelGGL(k_field_digits, dim3((unsigned)(nbm * nbn)), dim3(256), 0, st, PY, EY, PB, EB,
-                       sp, M, Bc, nbm, ng, out, out64, mode);
+                       sp, M, Bc, nbm, per, out, out64, mode);
 }
 
 }  // namespace mlmc

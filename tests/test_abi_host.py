@@ -206,9 +206,12 @@ def _default_kind(n, c, fp64):
     """The documented default of grid side n and batch class c."""
     tiles = 4 ** c * max(1, n // 32) ** 2
     lanes = 4 ** c * (n // 2)
+    smallest = 1 if c == 0 else 4 ** (c - 1) + 1               # smallest chunk of the class
+    spb = 1 if n >= 128 else 64 // (n // 2)
     tile = m.MLMC_PASS_TILE16 if tiles <= 256 else m.MLMC_PASS_TILE32
     has_stream = 32 <= n <= (1024 if fp64 else 2048)
-    big = (tiles >= 65536 or (fp64 and n <= 64 and tiles >= 16384)) and lanes >= 131072
+    big = ((tiles >= 65536 or (fp64 and n <= 64 and tiles >= 16384)) and lanes >= 131072
+           and smallest // spb >= 256)
     return m.MLMC_PASS_STREAM if has_stream and big else tile
 
 
@@ -225,10 +228,11 @@ def test_tuning_table_defaults_and_validation():
             k = _default_kind(e["n"], e["batch_class"], prec == m.MLMC_FP64)
             assert (e["pre"], e["post"]) == (k, k), (prec, e)
         kinds = {(e["n"], e["batch_class"]): e["pre"] for e in t2}
-        assert kinds[(1024, 4)] == m.MLMC_PASS_STREAM              # 256 samples of 1024^2
-        assert kinds[(1024, 3)] == m.MLMC_PASS_TILE32              # 64 samples
+        assert kinds[(1024, 5)] == m.MLMC_PASS_STREAM              # 257 .. 1024 samples of 1024^2
+        assert kinds[(1024, 4)] == m.MLMC_PASS_TILE32              # from 65: fewer workgroups than CUs
         assert kinds[(512, 4)] == m.MLMC_PASS_TILE32               # 256 samples: 65536 lanes
-        assert kinds[(2048, 4)] == (m.MLMC_PASS_TILE32 if prec == m.MLMC_FP64
+        assert kinds[(2048, 4)] == m.MLMC_PASS_TILE32              # 128 samples of 2048^2
+        assert kinds[(2048, 5)] == (m.MLMC_PASS_TILE32 if prec == m.MLMC_FP64
                                     else m.MLMC_PASS_STREAM)
     ctx = _host_ctx(n0=4, num_levels=7)             # tile grids 32^2 .. 256^2
     t = ctx.tuning()
