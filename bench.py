@@ -594,11 +594,11 @@ def oracle_baseline(w, level, y_batch, gpu_qoi, seconds, max_samples):
     err = {}
     for name, qg in gpu_qoi.items():
         rel = np.abs(qg[:done] - qo) / np.abs(qo)          # [samples][level][nq]
-        err[name] = [float(f"{v:.2e}") for v in rel.max(axis=(0, 2))]
+        err[name] = [float(f"{v:.1e}") for v in rel.max(axis=(0, 2))]
     base = dict(value=round(done / dt, 3), unit="samples/s", cores=threads, kind="oracle",
-                sample=f"first {done} samples of the step's batch at {w['n0'] << level}^2: "
-                       f"direct-sum KL + CPU FMG to {w['rtol']:g} + QoI; {dt:.1f} s; "
-                       f"-O3 -march=native",
+                sample=f"{done} samples of the step's batch, {w['n0'] << level}^2: KL "
+                       f"direct sum + CPU FMG to {w['rtol']:g} + QoI, {dt:.1f} s, -O3 "
+                       f"-march=native",
                 not_converged=bad)
     return base, err, done
 
@@ -835,7 +835,7 @@ def main():
                steps=args.steps, warmup=args.warmup,
                ms_per_step=round(mixed["elapsed"] * 1e3 / args.steps, 3),
                higher_is_better=True, scaling="weak", vs_baseline=None,
-               dtype="mixed: bf16 field digits, f32 V-cycles, f64 CG and sums",
+               dtype="bf16 field digits, f32 V-cycles, f64 CG and sums",
                data="synthetic",
                config=dict(workload=f"mlqmc_mixed_s400 at {n}^2 (s 400, lambda 0.1, sigma^2 2, "
                                     f"levels 4^2..{n}^2, FMG stages to rtol 1e-10)",
