@@ -358,9 +358,11 @@ typedef struct {
                                 min(4^c, capacity) samples); 0 if not measured */
 } mlmc_tune_entry;
 /* Measures every allowed kind of both passes on every tile grid of levels
- * <= level, for every batch class up to the level's chunk capacity, on the
- * context's own workspace (its contents are overwritten; stream-ordered on
- * hip_stream, synchronous on return), and installs the fastest.  Solves
+ * <= level, for every batch class up to the level's chunk capacity, at the
+ * class's largest and smallest chunk, on the context's own workspace (its
+ * contents are overwritten; stream-ordered on hip_stream, synchronous on
+ * return), and installs per pass the kind whose larger ratio to the fastest
+ * kind at the two sizes is smallest.  Solves
  * already enqueued on other streams must have finished.  E_INVAL for a level
  * out of range, E_STATE for a host-only context. */
 mlmc_status mlmc_autotune(mlmc_ctx ctx, int32_t level, void *hip_stream);

@@ -1054,29 +1054,33 @@ mlmc_status mlmc::create_ctx(const mlmc_config *cfg, int device, mlmc_ctx parent
 namespace {
 
 // Durations of one pre and one post pass of every allowed kind on tile grid g
-// for Bc samples, on the workspace (a = f = 1, u = 0: the time does not depend
-// on the values).  Each: one warm-up launch, then the best of two runs of
-// `reps` launches between events.
+// for the largest (Bc) and the smallest (Blo) chunk of batch class cls, on
+// the workspace (a = f = 1, u = 0: the time does not depend on the values).
+// Each: one warm-up launch, then the best of two runs of `reps` launches
+// between events.  A pass takes the kind whose larger ratio to the fastest
+// kind at the two chunk sizes is smallest (ties: the faster at Bc), so that
+// no chunk of the class gets a kind that leaves most of the GPU idle (a
+// streaming workgroup holds one sample on grids from 128^2).
 template <typename T>
-mlmc_status tune_grid(mlmc_ctx c, hipStream_t st, int g, int64_t Bc, int cls, hipEvent_t e0,
-                      hipEvent_t e1)
+mlmc_status tune_grid(mlmc_ctx c, hipStream_t st, int g, int64_t Bc, int64_t Blo, int cls,
+                      hipEvent_t e0, hipEvent_t e1)
 {
-    HierT<T> h = make_hier_t<T>(c, g, Bc);
     const int n = 2 << g;
-    const int64_t cells = Bc * (int64_t)n * n;
     const int64_t all = Bc * level_offset(g + 1);     // levels 0..g, level-major
-    if constexpr (std::is_same<T, double>::value) {
-        launch_fill(st, h.a[0], all, 1.0);
-        launch_fill(st, h.f[0], all, 1.0);
-        launch_fill(st, h.u[0], all, 0.0);
-    } else {
-        launch_fill_f32(st, h.a[0], all, 1.0f);
-        launch_fill_f32(st, h.f[0], all, 1.0f);
-        launch_fill_f32(st, h.u[0], all, 0.0f);
+    {
+        HierT<T> h = make_hier_t<T>(c, g, Bc);        // its fill covers the Blo layout too
+        if constexpr (std::is_same<T, double>::value) {
+            launch_fill(st, h.a[0], all, 1.0);
+            launch_fill(st, h.f[0], all, 1.0);
+            launch_fill(st, h.u[0], all, 0.0);
+        } else {
+            launch_fill_f32(st, h.a[0], all, 1.0f);
+            launch_fill_f32(st, h.f[0], all, 1.0f);
+            launch_fill_f32(st, h.u[0], all, 0.0f);
+        }
     }
-    const int reps = cells >= ((int64_t)1 << 22) ? 3 : 10;
     double ms_best = 0.0;
-    auto time_it = [&](auto launch) -> hipError_t {
+    auto time_it = [&](auto launch, int reps) -> hipError_t {
         launch();
         ms_best = 1e300;
         for (int r = 0; r < 2; ++r) {
@@ -1093,40 +1097,62 @@ mlmc_status tune_grid(mlmc_ctx c, hipStream_t st, int g, int64_t Bc, int cls, hi
         return hipSuccess;
     };
     const int kinds[] = {kTile32, kTile16, kStream};
-    double best_pre = 1e300, best_post = 1e300;
-    for (int kind : kinds) {
-        if (!kind_allowed(c, g, kind)) continue;
-        auto pre = [&] {
-            if (kind == kStream) {
-                launch_pre_stream<T>(st, c->cfg.mu1, h.a[g], h.f[g], h.u[g], h.ua[g], h.u[g - 1],
-                                     n, Bc, 1, h.f[g - 1], nullptr);
-                return;
-            }
-            launch_pre_tile<T>(st, kind, c->cfg.mu1, h.a[g], h.f[g], h.u[g], h.ua[g], h.u[g - 1], n,
-                               Bc, 1, h.f[g - 1], nullptr);
-        };
-        auto post = [&] {
-            if (kind == kStream) {
-                launch_post_stream<T>(st, c->cfg.mu2, h.a[g], h.f[g], h.ua[g], h.u[g], h.u[g - 1],
-                                      n, Bc, nullptr);
-                return;
-            }
-            launch_post_tile<T>(st, kind, c->cfg.mu2, h.a[g], h.f[g], h.ua[g], h.u[g], h.u[g - 1],
-                                n, Bc, nullptr);
-        };
-        HIPCHK(c, time_it(pre));
-        if (ms_best < best_pre) {
-            best_pre = ms_best;
-            c->pre_kind[g][cls] = (int8_t)kind;
-        }
-        HIPCHK(c, time_it(post));
-        if (ms_best < best_post) {
-            best_post = ms_best;
-            c->post_kind[g][cls] = (int8_t)kind;
+    // [size: 0 = Bc, 1 = Blo][kind] -> ms (infinite where not allowed)
+    double pre_ms[2][3], post_ms[2][3];
+    const int64_t sizes[2] = {Bc, Blo};
+    const int nsizes = Blo < Bc ? 2 : 1;
+    for (int z = 0; z < nsizes; ++z) {
+        const int64_t B = sizes[z];
+        HierT<T> h = make_hier_t<T>(c, g, B);
+        const int reps = B * (int64_t)n * n >= ((int64_t)1 << 22) ? 3 : 10;
+        for (int q = 0; q < 3; ++q) {
+            const int kind = kinds[q];
+            pre_ms[z][q] = post_ms[z][q] = 1e300;
+            if (!kind_allowed(c, g, kind)) continue;
+            auto pre = [&] {
+                if (kind == kStream) {
+                    launch_pre_stream<T>(st, c->cfg.mu1, h.a[g], h.f[g], h.u[g], h.ua[g], h.u[g - 1],
+                                         n, B, 1, h.f[g - 1], nullptr);
+                    return;
+                }
+                launch_pre_tile<T>(st, kind, c->cfg.mu1, h.a[g], h.f[g], h.u[g], h.ua[g], h.u[g - 1],
+                                   n, B, 1, h.f[g - 1], nullptr);
+            };
+            auto post = [&] {
+                if (kind == kStream) {
+                    launch_post_stream<T>(st, c->cfg.mu2, h.a[g], h.f[g], h.ua[g], h.u[g], h.u[g - 1],
+                                          n, B, nullptr);
+                    return;
+                }
+                launch_post_tile<T>(st, kind, c->cfg.mu2, h.a[g], h.f[g], h.ua[g], h.u[g], h.u[g - 1],
+                                    n, B, nullptr);
+            };
+            HIPCHK(c, time_it(pre, reps));
+            pre_ms[z][q] = ms_best;
+            HIPCHK(c, time_it(post, reps));
+            post_ms[z][q] = ms_best;
         }
     }
-    c->pre_ms[g][cls] = best_pre;
-    c->post_ms[g][cls] = best_post;
+    auto choose = [&](double (*t)[3], int8_t &kind_out, double &ms_out) {
+        double best[2] = {1e300, 1e300};
+        for (int z = 0; z < nsizes; ++z)
+            for (int q = 0; q < 3; ++q) best[z] = std::min(best[z], t[z][q]);
+        int pick = -1;
+        double pick_score = 1e300;
+        for (int q = 0; q < 3; ++q) {
+            if (t[0][q] >= 1e300) continue;
+            double score = 0.0;
+            for (int z = 0; z < nsizes; ++z) score = std::max(score, t[z][q] / best[z]);
+            if (pick < 0 || score < pick_score || (score == pick_score && t[0][q] < t[0][pick])) {
+                pick = q;
+                pick_score = score;
+            }
+        }
+        kind_out = (int8_t)kinds[pick];
+        ms_out = t[0][pick];
+    };
+    choose(pre_ms, c->pre_kind[g][cls], c->pre_ms[g][cls]);
+    choose(post_ms, c->post_kind[g][cls], c->post_ms[g][cls]);
     return MLMC_OK;
 }
 
@@ -1167,8 +1193,9 @@ mlmc_status mlmc_autotune(mlmc_ctx ctx, int32_t level, void *hip_stream)
             const int64_t Bc = cl + 1 == MLMC_BATCH_CLASSES
                                    ? cap
                                    : std::min<int64_t>((int64_t)1 << (2 * cl), cap);
-            r = ctx->cfg.precision == MLMC_MIXED ? tune_grid<float>(ctx, st, g, Bc, cl, e0, e1)
-                                                 : tune_grid<double>(ctx, st, g, Bc, cl, e0, e1);
+            r = ctx->cfg.precision == MLMC_MIXED
+                    ? tune_grid<float>(ctx, st, g, Bc, std::min(lo, Bc), cl, e0, e1)
+                    : tune_grid<double>(ctx, st, g, Bc, std::min(lo, Bc), cl, e0, e1);
         }
     }
     (void)hipEventDestroy(e0);
