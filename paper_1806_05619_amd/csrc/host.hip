@@ -551,7 +551,11 @@ struct FusedRunner {
     // u (top_u on the top level), so no pass reads the array it writes.
     void vcycle(int g, T *top_u, int init_top, const T *top_f, const int32_t *active)
     {
-        const int cls = batch_class(h.Bc);
+        // the pass kinds of the samples the masked passes work on: in a
+        // refinement step only the active ones have workgroups with work, so
+        // a chunk whose active set has shrunk takes the kinds of that smaller
+        // class (every kind gives the same bits)
+        const int cls = batch_class(nact >= 0 ? nact : h.Bc);
         for (int l = g; l > Gs; --l) {
             const int n = 2 << l;
             const int init = (l == g) ? init_top : 1;
