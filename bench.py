@@ -36,7 +36,6 @@ if ROOT not in sys.path:
 METRIC = ("samples/s per level (KL+FMG) mixed vs FP64 at equal QoI error; p50/p99 latency")
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-BF16_PEAK_TFLOPS = 2500.0
 
 
 # algorithmic HBM bytes each profiled kind counts per launch (per cell of the
@@ -134,69 +133,6 @@ def fp64_fixed_c2(m, torch, args):
     log(f"[bench] C2 fp64 fixed cycles at 256^2: {rate:.0f} samples/s")
     return dict(workload="mlqmc_fp64_s100 at 256^2, 16384 samples, FP64, 2 V(2,2) per stage",
                 samples_per_s=rate, breakdown=breakdown)
-
-
-def mixed_vs_fp64(m, torch, dev, max_batch=64, min_seconds=0.25):
-    """The s = 400 workload (lambda 0.1, sigma^2 2, 4^2 .. 1024^2) with both
-    paths run to the same stopping rule (relative residual 1e-10 per FMG
-    stage): FP64 CG with FP64 V-cycles and an FP64 product field, against
-    FP64 CG with FP32 V-cycles and the bf16 digit-product field.  Per level:
-    samples/s of each (lattice points of shift 0, 2^26 / n^2 of them, at most
-    65536), their ratio, the largest relative QoI difference between the two,
-    step counts and unconverged samples; the field product's time and
-    TFLOP/s (issued digit-product flops in the mixed path, 20 s M per sample,
-    against the bf16 matrix-core peak; 2 s M in FP64)."""
-    import synth
-    w = synth.workload("mlqmc_mixed_s400")
-    out = dict(workload="mlqmc_mixed_s400: lambda 0.1, sigma^2 2, s = 400, levels 4^2..1024^2, "
-                        "FMG with every stage solved to relative residual 1e-10 by V(2,2)-"
-                        "preconditioned flexible CG", rtol=w["rtol"], levels={})
-    ctxs = {}
-    for name, prec in (("fp64", m.MLMC_FP64), ("mixed", m.MLMC_MIXED)):
-        ctxs[name] = m.Context(w["n0"], w["num_levels"], w["s"], w["corr_len"], w["sigma2"],
-                               mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"],
-                               max_iters=w["max_iters"], precision=prec,
-                               qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
-                               genvec=synth.korobov_vector(w["seed"], w["s"]),
-                               shifts=synth.shift_table(w["seed"], w["num_levels"],
-                                                        w["num_shifts"], w["s"]),
-                               max_batch=max_batch, device=0)
-    for k in range(w["num_levels"]):
-        n = w["n0"] << k
-        npts = int(min(65536, max(16, (1 << 26) // (n * n))))
-        row = dict(samples=npts)
-        q = {}
-        for name, c in ctxs.items():
-            p = c.lattice(k, 0, npts, 0, 1)
-            qq = torch.zeros((npts, k + 1, 2), dtype=torch.float64, device=dev)
-            info = c.fmg_solve(p, qoi=qq, want_info=True)
-            torch.cuda.synchronize()
-            reps, t0 = 0, time.perf_counter()
-            while True:
-                c.fmg_solve(p, qoi=qq)
-                torch.cuda.synchronize()
-                reps += 1
-                if time.perf_counter() - t0 >= min_seconds:
-                    break
-            dt = (time.perf_counter() - t0) / reps
-            c.profile_begin("field")
-            c.fmg_solve(p, qoi=qq)
-            fr = c.profile_end()
-            row[f"{name}_field_ms"] = fr["total_ms"]
-            row[f"{name}_field_tflops"] = fr["flops"] / (fr["total_ms"] * 1e-3) / 1e12
-            row[f"{name}_samples_per_s"] = npts / dt
-            row[f"{name}_max_steps"] = info["max_iters_used"]
-            row[f"{name}_not_converged"] = info["not_converged"]
-            q[name] = qq.cpu().numpy()
-        row["ratio_mixed_over_fp64"] = row["mixed_samples_per_s"] / row["fp64_samples_per_s"]
-        row["max_rel_qoi_diff"] = float(np.max(np.abs(q["mixed"] - q["fp64"]) / np.abs(q["fp64"])))
-        out["levels"][f"{n}^2"] = row
-        row["field_digits_frac_of_bf16_peak"] = row["mixed_field_tflops"] / BF16_PEAK_TFLOPS
-        log(f"[bench] mixed vs fp64 {n}^2: {row['mixed_samples_per_s']:.0f} vs "
-            f"{row['fp64_samples_per_s']:.0f} samples/s (x{row['ratio_mixed_over_fp64']:.2f}), "
-            f"max rel diff {row['max_rel_qoi_diff']:.1e}")
-    del ctxs
-    return out
 
 
 def serving(m, torch, seconds=4.0, rate=500.0, clients=4, slots=4, slot_samples=64,
@@ -620,40 +556,51 @@ def solve_rate(ctx, pts, torch, min_seconds, q=None, sums=None):
 
 def levels_only(m, torch, args):
     """The per-level table of the s = 400 workload on its own (every level's
-    own batch, both paths, the finest level included), autotuned contexts
-    sized for the benchmark's batch."""
+    own batch, both paths, the finest level included)."""
     import synth
     w = synth.workload("mlqmc_mixed_s400")
-    dev = torch.device("cuda:0")
-    ctxs = {name: make_context(m, w, args.points * args.shifts, precision=prec)
-            for name, prec in (("mixed", m.MLMC_MIXED), ("fp64", m.MLMC_FP64))}
-    if not args.no_autotune:
-        for c in ctxs.values():
-            c.autotune(w["num_levels"] - 1)
-    lv = per_level(m, torch, ctxs, w, dev)
+    lv = per_level(m, torch, w, torch.device("cuda:0"), autotune=not args.no_autotune)
     return {key: [round(r["mixed"]), round(r["fp64"]), round(r["mixed"] / r["fp64"], 2),
                   float(f"{r['max_rel_diff']:.1e}")] for key, r in lv.items()}
 
 
-def per_level(m, torch, ctxs, w, dev, min_seconds=0.25, skip_level=None):
+# samples a per-level context is sized for (chunk capacity scales from it)
+LEVEL_CTX_BATCH = 1024
+
+
+def per_level(m, torch, w, dev, min_seconds=0.25, skip_level=None, autotune=True):
     """Samples/s of each path on every level's own batch (2^26 / n^2 lattice
     points of shift 0, at most 65536) and the largest relative QoI difference
-    between the paths on it; `skip_level` is measured by the timed steps."""
-    rows = {}
-    for k in range(w["num_levels"]):
-        if k == skip_level:
-            continue
-        n = w["n0"] << k
-        npts = int(min(65536, max(16, (1 << 26) // (n * n))))
-        q, row = {}, dict(samples=npts)
-        for name, c in ctxs.items():
+    between the paths on it; `skip_level` is measured by the timed steps.
+    One path after the other, each on an autotuned context of its own."""
+    levels = [k for k in range(w["num_levels"]) if k != skip_level]
+    rate, noconv, q = {}, {}, {}
+    for name, prec in (("mixed", m.MLMC_MIXED), ("fp64", m.MLMC_FP64)):
+        c = make_context(m, w, LEVEL_CTX_BATCH, precision=prec)
+        if autotune:
+            c.autotune(max(levels))
+        for k in levels:
+            n = w["n0"] << k
+            npts = int(min(65536, max(16, (1 << 26) // (n * n))))
             p = c.lattice(k, 0, npts, 0, 1)
             qq = torch.zeros((npts, k + 1, 2), dtype=torch.float64, device=dev)
             info = c.fmg_solve(p, qoi=qq, want_info=True)
-            row[name] = solve_rate(c, p, torch, min_seconds, q=qq)
-            row[f"{name}_not_converged"] = info["not_converged"]
-            q[name] = qq.cpu().numpy()
-        row["max_rel_diff"] = float(np.max(np.abs(q["mixed"] - q["fp64"]) / np.abs(q["fp64"])))
+            rate[(name, k)] = solve_rate(c, p, torch, min_seconds, q=qq)
+            noconv[(name, k)] = info["not_converged"]
+            q[(name, k)] = qq.cpu().numpy()
+            del qq
+        c.close()
+        del c
+        torch.cuda.empty_cache()
+    rows = {}
+    for k in levels:
+        n = w["n0"] << k
+        row = dict(samples=q[("mixed", k)].shape[0])
+        for name in ("mixed", "fp64"):
+            row[name] = rate[(name, k)]
+            row[f"{name}_not_converged"] = noconv[(name, k)]
+        row["max_rel_diff"] = float(np.max(np.abs(q[("mixed", k)] - q[("fp64", k)]) /
+                                           np.abs(q[("fp64", k)])))
         rows[f"{n}^2"] = row
         log(f"[bench] level {n}^2: mixed {row['mixed']:.0f} fp64 {row['fp64']:.0f} samples/s "
             f"(x{row['mixed'] / row['fp64']:.2f}), max rel diff {row['max_rel_diff']:.1e}")
@@ -684,7 +631,10 @@ def headline(m, torch, args):
     """Mixed vs FP64 on the s = 400 workload at its finest level (1024^2):
     a step is one batch of points x shifts solved through the whole path
     (points, field, FMG with every stage refined to rtol, QoI of every level,
-    level-difference sums, their copy to the host and the estimator)."""
+    level-difference sums, their copy to the host and the estimator).  The
+    two paths are measured one after the other, each on a context of its own
+    that is released before the next is made (a 1536-sample context at
+    1024^2 takes about half of the GPU's memory)."""
     import synth
     w = synth.workload("mlqmc_mixed_s400")
     dev = torch.device("cuda:0")
@@ -692,44 +642,34 @@ def headline(m, torch, args):
     npts, R = args.points, args.shifts
     B = npts * R
     nq = 2
-    ctxs = {}
-    for name, prec in (("mixed", m.MLMC_MIXED), ("fp64", m.MLMC_FP64)):
-        ctxs[name] = m.Context(w["n0"], w["num_levels"], w["s"], w["corr_len"], w["sigma2"],
-                               mu0=w["mu0"], mu1=w["mu1"], mu2=w["mu2"], rtol=w["rtol"],
-                               max_iters=w["max_iters"], precision=prec,
-                               qoi_mask=m.MLMC_QOI_MEAN | m.MLMC_QOI_CENTER,
-                               genvec=synth.korobov_vector(w["seed"], w["s"]),
-                               shifts=synth.shift_table(w["seed"], w["num_levels"],
-                                                        w["num_shifts"], w["s"]),
-                               max_batch=B, device=0)
-    if not args.no_autotune:
-        ta = time.perf_counter()
-        for c in ctxs.values():
-            c.autotune(k)
-        log(f"[bench] autotune {time.perf_counter() - ta:.2f} s")
-    pts = {name: c.lattice(k, 0, npts, 0, R) for name, c in ctxs.items()}
     n_per_level = np.zeros(k + 1, dtype=np.int64)
     n_per_level[k] = npts
-    res = {}
-    for name, c in ctxs.items():
+    res, y = {}, None
+    for name, prec in (("mixed", m.MLMC_MIXED), ("fp64", m.MLMC_FP64)):
+        c = make_context(m, w, B, precision=prec)
+        if not args.no_autotune:
+            ta = time.perf_counter()
+            c.autotune(k)
+            log(f"[bench] {name} autotune {time.perf_counter() - ta:.2f} s")
+        pts = c.lattice(k, 0, npts, 0, R)
         qoi = torch.zeros((B, k + 1, nq), dtype=torch.float64, device=dev)
         sums = torch.zeros((R, nq, k + 1, 2), dtype=torch.float64, device=dev)
         host_sums = np.zeros((k + 1, R, nq, k + 1, 2))
         est = {}
 
-        def step(c=c, name=name, qoi=qoi, sums=sums, host_sums=host_sums, est=est):
-            c.fmg_solve(pts[name], qoi=qoi, sums=sums)
+        def step(c=c, pts=pts, qoi=qoi, sums=sums, host_sums=host_sums, est=est):
+            c.fmg_solve(pts, qoi=qoi, sums=sums)
             host_sums[k] = sums.cpu().numpy()          # synchronising device-to-host copy
             est.update(m.mlmc_estimate(n_per_level, host_sums, R, nq, True))
 
-        info = c.fmg_solve(pts[name], qoi=qoi, want_info=True)
+        info = c.fmg_solve(pts, qoi=qoi, want_info=True)
         log(f"[bench] {name} {B} samples at {w['n0'] << k}^2: not converged "
             f"{info['not_converged']}, largest residual ratio {info['max_rel_residual']:.2e}, "
             f"at most {info['max_iters_used']} steps per stage")
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        r = dict(info=info, step=step, qoi=qoi, est=est)
+        r = dict(info=info, est=est)
         if name == "mixed":
             # kernel-time breakdown of one (untimed) step; the kind with the
             # most time is the dominant kernel whose roofline is measured live
@@ -755,11 +695,20 @@ def headline(m, torch, args):
         r["elapsed"] = time.perf_counter() - t0
         if name == "mixed":
             r["prof"] = c.profile_end()
+            # points of the step's batch, for the oracle (y = Phi^-1 of the lattice points)
+            yd = torch.zeros((B, w["s"]), dtype=torch.float64, device=dev)
+            c.points_gen(pts, y=yd)
+            y = yd.cpu().numpy()
+            del yd
+        r["qoi"] = qoi.cpu().numpy()
         r["value"] = B * args.steps / r["elapsed"]
         log(f"[bench] {name}: {args.steps} steps in {r['elapsed']:.3f} s -> "
             f"{r['value']:.1f} samples/s")
         res[name] = r
-    return w, k, B, ctxs, res, pts
+        c.close()
+        del c, qoi, sums, step
+        torch.cuda.empty_cache()
+    return w, k, B, res, y
 
 
 def main():
@@ -767,7 +716,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--points", type=int, default=64,
+    ap.add_argument("--points", type=int, default=96,
                     help="lattice points per shift in one step's batch")
     ap.add_argument("--shifts", type=int, default=16, help="random shifts in one step's batch")
     ap.add_argument("--no-autotune", action="store_true",
@@ -821,14 +770,14 @@ def main():
         log("[bench] copy calibration: 1 GiB read + 1 GiB written")
         del src, dst
 
-    w, k, B, ctxs, res, pts = headline(m, torch, args)
+    w, k, B, res, y = headline(m, torch, args)
     mixed, fp64 = res["mixed"], res["fp64"]
     prof, dominant = mixed["prof"], mixed["dominant"]
     avg_ms = prof["total_ms"] / max(prof["launches"], 1)
     bytes_per_launch = prof["bytes"] / max(prof["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic, traffic_src = measured_traffic(dominant)
-    qm, qf = mixed["qoi"].cpu().numpy(), fp64["qoi"].cpu().numpy()
+    qm, qf = mixed["qoi"], fp64["qoi"]
     diff = np.abs(qm - qf) / np.abs(qf)
     n = w["n0"] << k
     out = dict(metric=METRIC, value=round(mixed["value"], 2), unit="samples/s", n_gpus=1,
@@ -860,19 +809,17 @@ def main():
     log("[bench] max rel diff mixed vs fp64 on the step's QoI table, per MLMC level: " +
         json.dumps([float(f"{v:.1e}") for v in diff.max(axis=(0, 2))]))
     if not args.no_extras:
-        lv = per_level(m, torch, ctxs, w, dev, skip_level=k)
+        lv = per_level(m, torch, w, dev, skip_level=k, autotune=not args.no_autotune)
         lv[f"{n}^2"] = dict(samples=B, mixed=mixed["value"], fp64=fp64["value"],
                             max_rel_diff=float(diff.max()))
         out["per_level"] = {key: [round(r["mixed"]), round(r["fp64"]),
                                   round(r["mixed"] / r["fp64"], 2),
                                   float(f"{r['max_rel_diff']:.1e}")] for key, r in lv.items()}
         out["per_level_columns"] = "mixed/s, fp64/s, ratio, max rel diff"
-        out["latency_p50_p99_ms"] = latency(m, torch, ctxs["mixed"], w, dev, (0, 4, 8))
-        # points of the step's batch, for the oracle (y = Phi^-1 of the lattice points)
-        y = torch.zeros((B, w["s"]), dtype=torch.float64, device=dev)
-        ctxs["mixed"].points_gen(pts["mixed"], y=y)
-        y = y.cpu().numpy()
-        del ctxs, res
+        lc = make_context(m, w, 64, precision=m.MLMC_MIXED)
+        out["latency_p50_p99_ms"] = latency(m, torch, lc, w, dev, (0, 4, 8))
+        lc.close()
+        del lc, res
         torch.cuda.empty_cache()
         log("[bench] CPU baseline (oracle) ...")
         base, err, ns = oracle_baseline(w, k, y, dict(mixed=qm, fp64=qf), args.cpu_seconds,

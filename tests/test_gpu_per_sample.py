@@ -6,7 +6,7 @@ precisions:
 * 4^2 .. 32^2: every sample of one 4096-point shift, against the oracle's
   band Cholesky solve of each level (the exact discrete solution);
 * 64^2 .. 256^2: 64 samples (16 points x 4 shifts), against the band solve;
-* 512^2 and 1024^2: 4 samples from different shifts of the 1024-sample
+* 512^2 and 1024^2: 4 samples from different shifts of the 1536-sample
   batch the benchmark times, against the oracle's FMG with the same stopping
   rule (the band solve costs 1.1 TFLOP per sample at 1024^2).
 
@@ -96,22 +96,29 @@ def test_samples_on_middle_levels(oracle_mod, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_samples_of_the_benchmark_batch_on_fine_levels(oracle_mod, precision):
-    """The benchmark's launch configuration: 64 points x 16 shifts at 1024^2
-    in one call, pass kinds autotuned; samples 0, 341, 682 and 1023 (shifts
+    """The benchmark's launch configuration: 96 points x 16 shifts at 1024^2
+    in one call, pass kinds autotuned; samples 0, 511, 1023 and 1535 (shifts
     0, 5, 10, 15) against the oracle's FMG (levels 4^2 .. 1024^2).  A sample
-    stopped by the rounding floor (residual ratio within 2x of rtol, reported) is held to the
-    same tolerance."""
+    stopped by the rounding floor (residual ratio within 2x of rtol,
+    reported) is held to the same tolerance.  The context (about half of the
+    GPU's memory) is released before the test returns."""
     _dev()
     k = 8
-    w, z, D, ctx, P = _setup(oracle_mod, precision, k + 1, 1024)
-    # the pass kinds the benchmark measures and installs for its batch
-    tuned = [(e["n"], e["batch_class"], e["pre"], e["post"]) for e in ctx.autotune(k)
-             if e["n"] == 1024 and e["pre_ms"] > 0]
-    print(f"\n{precision}: 1024 samples at 1024^2, kinds {tuned}", flush=True)
-    qg, info = _gpu(ctx, k, 0, 64, 0, 16)
-    print(f"info {info}", flush=True)
+    npts, R = 96, 16
+    w, z, D, ctx, P = _setup(oracle_mod, precision, k + 1, npts * R)
+    try:
+        # the pass kinds the benchmark measures and installs for its batch
+        tuned = [(e["n"], e["batch_class"], e["pre"], e["post"]) for e in ctx.autotune(k)
+                 if e["n"] == 1024 and e["pre_ms"] > 0]
+        print(f"\n{precision}: {npts * R} samples at 1024^2, kinds {tuned}", flush=True)
+        qg, info = _gpu(ctx, k, 0, npts, 0, R)
+        print(f"info {info}", flush=True)
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
     assert info["max_rel_residual"] <= 2 * w["rtol"], info
-    picks = [0, 341, 682, 1023]
-    y = np.stack([oracle_mod.points(z, D[k, b // 64], b % 64, b % 64 + 1)[1][0] for b in picks])
+    picks = [0, 511, 1023, 1535]
+    y = np.stack([oracle_mod.points(z, D[k, b // npts], b % npts, b % npts + 1)[1][0]
+                  for b in picks])
     qo, _ = P.batch(k, y, 0, nthreads=4)
     _check(f"{precision} 4^2..1024^2 (samples {picks})", qg[picks], qo)
