@@ -279,28 +279,44 @@ __device__ __forceinline__ double coarse_odd(const double *e, int nc, int I, int
 
 // Bilinear (9,3,3,1)/16 prolongation with odd reflection at the walls:
 // u = P ec (add == 0, FMG interpolation) or u += P ec (coarse-grid correction).
+// u = P ec (add = 0) or u += P ec on n x n grids (n a power of two, at
+// least 4): one thread per pair of horizontally adjacent fine cells 2I, 2I+1
+// of row j, which share the coarse cells they interpolate from; the pair is
+// stored as one 16-byte vector.  Index arithmetic by shifts (per-sample
+// offsets and rows are powers of two).
 __global__ void k_prolong(const double *__restrict__ ec, double *__restrict__ u, int n,
                           int64_t Bc, int add, const int32_t *__restrict__ active)
 {
-    const int64_t per = (int64_t)n * n;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= Bc * per)
+    const int lg = __builtin_ctz(n);                   // n = 2^lg
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = t >> (2 * lg - 1);               // n^2 / 2 pairs per sample
+    if (b >= Bc)
         return;
-    int64_t b = t / per;
     if (active && !active[b])
         return;
-    int p = (int)(t - b * per);
-    int j = p / n, i = p - j * n;
+    const int q = (int)(t & (((int64_t)1 << (2 * lg - 1)) - 1));
+    const int j = q >> (lg - 1), I = q & ((n >> 1) - 1);
     const int nc = n / 2;
     const double *eb = ec + b * nc * nc;
-    int I = i / 2, J = j / 2;
-    int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1;
-    double v = prolong_9331(coarse_odd(eb, nc, I, J), coarse_odd(eb, nc, I + sx, J),
-                            coarse_odd(eb, nc, I, J + sy), coarse_odd(eb, nc, I + sx, J + sy));
-    if (add)
-        u[t] += v;
-    else
-        u[t] = v;
+    const int J = j >> 1, sy = (j & 1) ? 1 : -1;
+    const double c0 = coarse_odd(eb, nc, I, J), c1 = coarse_odd(eb, nc, I, J + sy);
+    // fine column 2I takes the coarse column I-1 as its horizontal neighbour,
+    // 2I+1 the column I+1
+    const double v0 = prolong_9331(c0, coarse_odd(eb, nc, I - 1, J), c1,
+                                   coarse_odd(eb, nc, I - 1, J + sy));
+    const double v1 = prolong_9331(c0, coarse_odd(eb, nc, I + 1, J), c1,
+                                   coarse_odd(eb, nc, I + 1, J + sy));
+    double2 *dst = reinterpret_cast<double2 *>(u + (b << (2 * lg)) + ((int64_t)j << lg) + 2 * I);
+    double2 o;
+    if (add) {
+        o = *dst;
+        o.x += v0;
+        o.y += v1;
+    } else {
+        o.x = v0;
+        o.y = v1;
+    }
+    *dst = o;
 }
 
 // QoI of one level, one wavefront per sample: mean (compensated) and centre.
@@ -564,7 +580,7 @@ void launch_resid_restrict(hipStream_t st, const double *a, const double *f, con
 void launch_prolong(hipStream_t st, const double *ec, double *u, int n, int64_t Bc, int add,
                     const int32_t *active)
 {
-    int64_t cnt = Bc * (int64_t)n * n;
+    int64_t cnt = Bc * (int64_t)n * n / 2;         // pairs of fine cells
     hipLaunchKernelGGL(k_prolong, dim3(blocks_for(cnt)), dim3(kBlock), 0, st, ec, u, n, Bc, add,
                        active);
 }
