@@ -633,8 +633,8 @@ def headline(m, torch, args):
     (points, field, FMG with every stage refined to rtol, QoI of every level,
     level-difference sums, their copy to the host and the estimator).  The
     two paths are measured one after the other, each on a context of its own
-    that is released before the next is made (a 1536-sample context at
-    1024^2 takes about half of the GPU's memory)."""
+    that is released before the next is made (a 2304-sample context at
+    1024^2 takes about 212 GB of the GPU's 288)."""
     import synth
     w = synth.workload("mlqmc_mixed_s400")
     dev = torch.device("cuda:0")
@@ -716,7 +716,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--points", type=int, default=96,
+    ap.add_argument("--points", type=int, default=144,
                     help="lattice points per shift in one step's batch")
     ap.add_argument("--shifts", type=int, default=16, help="random shifts in one step's batch")
     ap.add_argument("--no-autotune", action="store_true",

@@ -6,7 +6,7 @@ precisions:
 * 4^2 .. 32^2: every sample of one 4096-point shift, against the oracle's
   band Cholesky solve of each level (the exact discrete solution);
 * 64^2 .. 256^2: 64 samples (16 points x 4 shifts), against the band solve;
-* 512^2 and 1024^2: 4 samples from different shifts of the 1536-sample
+* 512^2 and 1024^2: 4 samples from different shifts of the 2304-sample
   batch the benchmark times, against the oracle's FMG with the same stopping
   rule (the band solve costs 1.1 TFLOP per sample at 1024^2).
 
@@ -96,15 +96,19 @@ def test_samples_on_middle_levels(oracle_mod, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_samples_of_the_benchmark_batch_on_fine_levels(oracle_mod, precision):
-    """The benchmark's launch configuration: 96 points x 16 shifts at 1024^2
-    in one call, pass kinds autotuned; samples 0, 511, 1023 and 1535 (shifts
+    """The benchmark's launch configuration: 144 points x 16 shifts at 1024^2
+    in one call, pass kinds autotuned; samples 0, 767, 1535 and 2303 (shifts
     0, 5, 10, 15) against the oracle's FMG (levels 4^2 .. 1024^2).  A sample
     stopped by the rounding floor (residual ratio within 2x of rtol,
-    reported) is held to the same tolerance.  The context (about half of the
-    GPU's memory) is released before the test returns."""
+    reported) is held to the same tolerance.  The context (about 212 GB of
+    the GPU's memory) is made after the memory of earlier tests has been
+    returned and is released before the test returns."""
+    import gc
     _dev()
     k = 8
-    npts, R = 96, 16
+    npts, R = 144, 16
+    gc.collect()
+    torch.cuda.empty_cache()
     w, z, D, ctx, P = _setup(oracle_mod, precision, k + 1, npts * R)
     try:
         # the pass kinds the benchmark measures and installs for its batch
@@ -117,7 +121,7 @@ def test_samples_of_the_benchmark_batch_on_fine_levels(oracle_mod, precision):
         ctx.close()
         torch.cuda.empty_cache()
     assert info["max_rel_residual"] <= 2 * w["rtol"], info
-    picks = [0, 511, 1023, 1535]
+    picks = [0, 767, 1535, 2303]
     y = np.stack([oracle_mod.points(z, D[k, b // npts], b % npts, b % npts + 1)[1][0]
                   for b in picks])
     qo, _ = P.batch(k, y, 0, nthreads=4)
