@@ -35,7 +35,6 @@ if ROOT not in sys.path:
 
 METRIC = ("samples/s per level (KL+FMG) mixed vs FP64 at equal QoI error; p50/p99 latency")
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
 
 
 # algorithmic HBM bytes each profiled kind counts per launch (per cell of the
@@ -43,7 +42,7 @@ FP64_PEAK_TFLOPS = 78.6
 # V-cycle type, 4 in the mixed path)
 BYTE_MODEL = dict(
     points="Y written, 16 B per sample and term",
-    field="Y digits, basis digits (8 B per term and cell) read, a written (12 B per cell)",
+    field="Y, Y digits and basis digits (10 B per term and cell) read, a written (12 B per cell)",
     smooth="unfused colour sweep", restrict="unfused", prolong="FMG interpolation: coarse "
     "solution read (n^2/4), fine written, 8 B words", coarse="2x2 solve", qoi="u read once",
     sums="QoI table read once",
@@ -55,7 +54,6 @@ BYTE_MODEL = dict(
 
 KINDS = ("points", "field", "smooth", "restrict", "prolong", "coarse", "qoi", "sums", "pre", "post",
          "lds", "refine")
-KIND_NAMES = {0: "tile32", 1: "tile16", 2: "stream"}
 KERNEL_NAMES = dict(
     points="k_points", field="k_field_digits (mixed) / k_field_mfma64 (FP64)",
     smooth="k_rbgs (one colour)", restrict="k_resid_restrict", prolong="k_prolong",
