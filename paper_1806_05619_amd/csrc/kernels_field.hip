@@ -27,9 +27,8 @@ __global__ __launch_bounds__(FNT) void k_field_mfma64(const double *__restrict__
     __shared__ double As[FKB][FBM];      // Y tile, mode-major
     __shared__ double Bs[FKB][FBN];      // basis tile
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    // groups of `per` sample tiles over every basis panel (grouped_tile): the
-    // rows of Y an XCD cycles through stay in its L2, and a basis panel
-    // comes from HBM about once
+    // groups of `per` sample tiles over every basis panel (grouped_tile), so
+    // that the rows of Y an XCD cycles through stay in its L2
     int64_t mt, nt;
     grouped_tile(xcd_contiguous(blockIdx.x, gridDim.x), nbm, gridDim.x / nbm, per, mt, nt);
     const int64_t row0 = mt * FBM, col0 = nt * FBN;

@@ -159,9 +159,8 @@ __global__ __launch_bounds__(256, 2) void k_field_digits(DigitPtrs Yp, const int
     __shared__ __attribute__((aligned(16))) uint16_t Bs[2][ND][BN * 32];
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-    // groups of `per` sample tiles over every basis panel (grouped_tile): the
-    // digits of Y an XCD cycles through stay in its L2, and a basis panel
-    // comes from HBM about once
+    // groups of `per` sample tiles over every basis panel (grouped_tile), so
+    // that the digits of Y an XCD cycles through stay in its L2
     int64_t mt, nt;
     grouped_tile(xcd_contiguous(blockIdx.x, gridDim.x), nbm, gridDim.x / nbm, per, mt, nt);
     const int64_t brow0 = mt * BM, bcol0 = nt * BN;
