@@ -888,8 +888,9 @@ __global__ __launch_bounds__(LT, LT == 64 ? 4 : 1) void k_lds_fmg_refine(
 // samples.  Geometry (grids n >= 64): a thread owns CW consecutive cells of a
 // row, CW = 16 bytes over the widest element type the pass moves (2 for
 // FP64 arrays, 4 for FP32), so that each lane of a wavefront loads and stores
-// 16 contiguous bytes per array and row; it marches down the QH = 4 q / CW
-// rows of its strip (q = 4 on 64^2, 8 above).  The 256 threads of a block
+// 16 contiguous bytes per array and row; it marches along the QH = 4 q / CW
+// rows of its strip (q = 4 on 64^2, 8 above; upwards, or downwards for odd
+// strips, see strip_march).  The 256 threads of a block
 // take 256 consecutive cell groups of the sample's strip space (group g:
 // strip g / (n/CW), columns CW (g mod n/CW) .. +CW-1), so every pass covers
 // 1024 q cells per block and n^2 / (1024 q) blocks per sample.  A stencil
@@ -989,35 +990,103 @@ __device__ __forceinline__ void row_ends(const GroupRow<TA, TV, CW> &q, const TA
 }
 
 // Net flux h^2 (A v)_P of the cells of a group row, faces summed in the
-// order E, W, N, S (walls: 2 a_P v_P), as TS; hN holds the N face weights of
-// this row on return (the S face weights of the next row)
+// order E, W, N, S (walls: 2 a_P v_P), as TS.  A strip marched upwards
+// carries the S face weights from the row below and forms the N ones, which
+// it returns in `fresh` (the next row's S faces); a strip marched downwards
+// (down) carries the N faces and forms the S ones.  Either way each cell sees
+// the same face weights (hm is symmetric) and the same sum.
 // (the rows above and below are passed by reference with flags, never as
 // pointers that may be null: a select between the addresses of two register
 // arrays would force them into scratch memory)
 template <typename TS, int CW, typename TA, typename TV>
 __device__ __forceinline__ void row_flux(const GroupRow<TA, TV, CW> &c, TA al, TV vl, TA ar, TV vr,
                                          const GroupRow<TA, TV, CW> &up, bool has_up,
-                                         const GroupRow<TA, TV, CW> &dn, bool has_dn, TS (&hS)[CW],
-                                         TS (&hN)[CW], int i0, int n, TS (&flux)[CW])
+                                         const GroupRow<TA, TV, CW> &dn, bool has_dn, bool down,
+                                         const TS (&carried)[CW], TS (&fresh)[CW], int i0, int n,
+                                         TS (&flux)[CW])
 {
     TS hx[CW + 1];   // faces between columns i0-1 | i0 | .. | i0+CW
     hx[0] = i0 > 0 ? hm(TS(al), TS(c.a[0])) : TS(0);
 #pragma unroll
     for (int k = 1; k < CW; ++k) hx[k] = hm(TS(c.a[k - 1]), TS(c.a[k]));
     hx[CW] = i0 + CW < n ? hm(TS(c.a[CW - 1]), TS(ar)) : TS(0);
+    const bool has_nb = down ? has_dn : has_up;
 #pragma unroll
     for (int k = 0; k < CW; ++k) {
         const TS ap = TS(c.a[k]), xp = TS(c.v[k]);
         const TS xe = k < CW - 1 ? TS(c.v[k + 1]) : TS(vr);
         const TS xw = k > 0 ? TS(c.v[k - 1]) : TS(vl);
-        hN[k] = has_up ? hm(ap, TS(up.a[k])) : TS(0);
+        const TS anb = TS(down ? dn.a[k] : up.a[k]);
+        fresh[k] = has_nb ? hm(ap, anb) : TS(0);
+        const TS fN = down ? carried[k] : fresh[k], fS = down ? fresh[k] : carried[k];
         TS v = TS(0);
         v += (i0 + k + 1 < n) ? hx[k + 1] * (xp - xe) : TS(2) * ap * xp;
         v += (i0 + k > 0) ? hx[k] * (xp - xw) : TS(2) * ap * xp;
-        v += has_up ? hN[k] * (xp - TS(up.v[k])) : TS(2) * ap * xp;
-        v += has_dn ? hS[k] * (xp - TS(dn.v[k])) : TS(2) * ap * xp;
+        v += has_up ? fN * (xp - TS(up.v[k])) : TS(2) * ap * xp;
+        v += has_dn ? fS * (xp - TS(dn.v[k])) : TS(2) * ap * xp;
         flux[k] = v;
     }
+}
+
+// the rows of a pass, moved as values (a select between two register arrays'
+// addresses would put them in scratch memory)
+template <typename TA, typename TV, int CW>
+__device__ __forceinline__ void row_pick(GroupRow<TA, TV, CW> &dst, bool take,
+                                         const GroupRow<TA, TV, CW> &src)
+{
+#pragma unroll
+    for (int k = 0; k < CW; ++k) {
+        dst.a[k] = take ? src.a[k] : dst.a[k];
+        dst.v[k] = take ? src.v[k] : dst.v[k];
+    }
+}
+
+// The rows of a thread's strip in marching order: strips whose index is odd
+// march downwards when a wavefront's lanes share one strip, so that the two
+// rows on either side of a strip boundary are read by both strips at the same
+// end of their marches, close together in time (the second read hits the
+// L2; with every strip marching upwards, a boundary row is read at the start
+// of one march and at the end of the other, after the XCD has streamed far
+// more than its L2 holds).  `load(j, row)` fills row j; `body(j, cur, up, dn,
+// carried, fresh)` handles row j with the rows above and below it.  The row
+// two ahead is in flight while a row is handled.
+template <int QH, typename TS, int CW, typename Row, typename Load, typename Body>
+__device__ __forceinline__ void strip_march(bool down, int j0, int n, Load load, Body body)
+{
+    const int d = down ? -1 : 1;
+    const int js = down ? j0 + QH - 1 : j0;
+    Row up, cur, dn, nn;              // rows j+1, j, j-1 and the one two ahead
+    TS carried[CW], fresh[CW];
+    load(js, cur);
+    if (js + 1 < n) load(js + 1, up);
+    if (js > 0) load(js - 1, dn);
+    // the face to the row behind in marching order
+    const bool has_bhd = down ? js + 1 < n : js > 0;
+#pragma unroll
+    for (int q = 0; q < CW; ++q)
+        carried[q] = has_bhd ? hm(TS(cur.a[q]), TS(down ? up.a[q] : dn.a[q])) : TS(0);
+#pragma unroll 1
+    for (int t = 0; t < QH; ++t) {
+        const int j = js + d * t;
+        if (t + 1 < QH && j + 2 * d >= 0 && j + 2 * d < n) load(j + 2 * d, nn);
+        body(j, cur, up, dn, carried, fresh);
+#pragma unroll
+        for (int q = 0; q < CW; ++q) carried[q] = fresh[q];
+        // upwards: dn <- cur, cur <- up, up <- nn; downwards: up <- cur,
+        // cur <- dn, dn <- nn
+        Row nc = up;
+        row_pick(nc, down, dn);
+        row_pick(dn, !down, cur);
+        row_pick(up, down, cur);
+        row_pick(dn, down, nn);
+        row_pick(up, !down, nn);
+        cur = nc;
+    }
+}
+
+__device__ __forceinline__ bool strip_down(int n, int CW, int j0, int QH)
+{
+    return n / CW >= 64 && ((j0 / QH) & 1);
 }
 
 // block (256 threads) compensated sums of NV values -> out[2 NV] (sum, comp)
@@ -1113,42 +1182,27 @@ __global__ __launch_bounds__(256, 4) void k_fcg_x(const double *__restrict__ a64
         }
     };
     const double n2 = double(n) * double(n);
-    // rows j-1, j, j+1 and j+2: the loads of row j+2 are in flight while row
-    // j is computed
-    Row prv, cur, nxt, nn;
-    double hS[CW], hN[CW];
-    load(m.j0, cur);
-    if (m.j0 + 1 < n) load(m.j0 + 1, nxt);
-    if (m.j0 > 0) {
-        load(m.j0 - 1, prv);
-#pragma unroll
-        for (int c = 0; c < CW; ++c) hS[c] = hm(cur.a[c], prv.a[c]);
-    }
+    const bool down = strip_down(n, CW, m.j0, QH);
     double s[1] = {0.0}, c[1] = {0.0};
-#pragma unroll 1
-    for (int t = 0; t < QH; ++t) {
-        const int j = m.j0 + t;
-        if (t + 1 < QH && j + 2 < n) load(j + 2, nn);
+    auto body = [&](int j, const Row &cur, const Row &up, const Row &dn,
+                    const double (&carried)[CW], double (&fresh)[CW]) {
         double al, vl, ar, vr;
         row_ends<CW>(cur, ab + (int64_t)j * n, (int64_t)j * n, m.i0, n, xk, al, vl, ar, vr);
         double flux[CW];
-        row_flux<double, CW>(cur, al, vl, ar, vr, nxt, j + 1 < n, prv, j > 0, hS, hN, m.i0, n,
-                             flux);
+        row_flux<double, CW>(cur, al, vl, ar, vr, up, j + 1 < n, dn, j > 0, down, carried, fresh,
+                             m.i0, n, flux);
         T fv[CW];
 #pragma unroll
         for (int q = 0; q < CW; ++q) {
             const double r = 1.0 - n2 * flux[q];
             fv[q] = T(r);
             neumaier(s[0], c[0], r * r);
-            hS[q] = hN[q];
         }
         const int64_t o = (int64_t)j * n + m.i0;
         if (UPDATE) stv<CW>(xnew + o, cur.v);
         stv<CW>(fb + o, fv);
-        prv = cur;
-        cur = nxt;
-        nxt = nn;
-    }
+    };
+    strip_march<QH, double, CW, Row>(down, m.j0, n, load, body);
     block_partials<1>(s, c, part + (m.b * m.nch + m.blk) * 2);
 }
 
@@ -1271,34 +1325,20 @@ __global__ __launch_bounds__(256, 4) void k_fcg_p(const T *__restrict__ a, const
         }
     };
     const double n2 = double(n) * double(n);
-    Row prv, cur, nxt, nn;                     // rows j-1 .. j+2 (j+2 in flight)
-    T hS[CW], hN[CW];
-    load(m.j0, cur);
-    if (m.j0 + 1 < n) load(m.j0 + 1, nxt);
-    if (m.j0 > 0) {
-        load(m.j0 - 1, prv);
-#pragma unroll
-        for (int c = 0; c < CW; ++c) hS[c] = hm(cur.a[c], prv.a[c]);
-    }
+    const bool down = strip_down(n, CW, m.j0, QH);
     double s[1] = {0.0}, c[1] = {0.0};
-#pragma unroll 1
-    for (int t = 0; t < QH; ++t) {
-        const int j = m.j0 + t;
-        if (t + 1 < QH && j + 2 < n) load(j + 2, nn);
+    auto body = [&](int j, const Row &cur, const Row &up, const Row &dn,
+                    const T (&carried)[CW], T (&fresh)[CW]) {
         T al, vl, ar, vr;
         row_ends<CW>(cur, ab + (int64_t)j * n, (int64_t)j * n, m.i0, n, pk, al, vl, ar, vr);
         T flux[CW];
-        row_flux<T, CW>(cur, al, vl, ar, vr, nxt, j + 1 < n, prv, j > 0, hS, hN, m.i0, n, flux);
+        row_flux<T, CW>(cur, al, vl, ar, vr, up, j + 1 < n, dn, j > 0, down, carried, fresh, m.i0,
+                        n, flux);
 #pragma unroll
-        for (int q = 0; q < CW; ++q) {
-            neumaier(s[0], c[0], double(cur.v[q]) * n2 * double(flux[q]));
-            hS[q] = hN[q];
-        }
+        for (int q = 0; q < CW; ++q) neumaier(s[0], c[0], double(cur.v[q]) * n2 * double(flux[q]));
         stv<CW>(pnew + (int64_t)j * n + m.i0, cur.v);
-        prv = cur;
-        cur = nxt;
-        nxt = nn;
-    }
+    };
+    strip_march<QH, T, CW, Row>(down, m.j0, n, load, body);
     block_partials<1>(s, c, part + (m.b * m.nch + m.blk) * 2);
 }
 
