@@ -215,7 +215,15 @@ mlmc_status mlmc_field_static(mlmc_ctx ctx, const mlmc_points *pts, double *z_de
  *            square (F_{-1} = 0), compensated FP64 sums.
  *   info     host, optional; filling it synchronises the stream.
  * Returns MLMC_E_NOCONV (outputs still written) if info was requested and
- * some sample has a stage that stopped above rtol. */
+ * some sample has a stage that stopped above rtol.
+ * With rtol == 0 (fixed cycles) and info == NULL the call only enqueues
+ * kernels on hip_stream (no host synchronisation, no allocation, no memset),
+ * so it may be captured into a HIP graph and replayed: a replay recomputes
+ * the points, the field and the solve into the same qoi_dev and sums_dev.
+ * The context's workspace is shared by every call on it, so replays and
+ * other calls on the context must not overlap.  With rtol > 0 the host reads
+ * the convergence flags after every refinement step on grids >= 64^2, and
+ * the call cannot be captured. */
 mlmc_status mlmc_fmg_solve(mlmc_ctx ctx, const mlmc_points *pts,
                            const double *z_dev, double *qoi_dev,
                            double *sums_dev, mlmc_solve_info *info,
