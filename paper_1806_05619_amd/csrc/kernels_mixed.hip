@@ -221,17 +221,16 @@ __global__ __launch_bounds__(256, 2) void k_field_digits(DigitPtrs Yp, const int
     // while the first panels load (the exponent arrays are padded like the
     // digit rows, so every index is in range)
     int ey[2][4], eb[2];
-    int64_t base[2] = {0, 0}, stride[2] = {0, 0};
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int e = 0; e < 4; ++e) ey[i][e] = EY[row0 + 16 * i + 4 * q4 + e];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int64_t m = col0 + 16 * j + lr;
-        eb[j] = EB[m];
-        if (mode != 0 && m < M) level_major_column(m, Bc, base[j], stride[j]);
-    }
+    for (int j = 0; j < 2; ++j) eb[j] = EB[col0 + 16 * j + lr];
+    // the epilogue writes whole rows of the block: lane l takes column l
+    const int64_t mcol = bcol0 + lane;
+    int64_t base = 0, stride = 0;
+    if (mode != 0 && mcol < M) level_major_column(mcol, Bc, base, stride);
     for (int ks = 0; ks < nk; ++ks) {
         const int buf = ks & 1;
         // this wave's loads of step ks have landed; after the barrier every
@@ -281,26 +280,39 @@ __global__ __launch_bounds__(256, 2) void k_field_digits(DigitPtrs Yp, const int
                 }
         }
     }
+    // The block's 64 x 64 results go through LDS (rows of ZS doubles, the
+    // padding spreading the four row groups of a store over the banks), so
+    // that every store instruction writes 64 consecutive cells of one sample
+    // (256 bytes of float, 512 of double) instead of four rows of 16.
+    constexpr int ZS = 68;
+    static_assert(sizeof(As) >= sizeof(double) * BM * ZS, "staging fits the Y panels");
+    double *Zs = reinterpret_cast<double *>(&As[0][0][0]);
+    __syncthreads();   // every wavefront has read its last panels
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int64_t m = col0 + 16 * j + lr;
-        if (m >= M) continue;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t b = row0 + 16 * i + 4 * q4 + e;
-                if (b >= Bc) continue;
                 const double z = ldexp(acc[i][j][e], ey[i][e] + eb[j] - 14);
-                if (mode == 0) {
-                    ((double *)out)[b * M + m] = z;
-                } else {
-                    const int64_t q = base[j] + b * stride[j];
-                    const double av = exp(z);
-                    ((float *)out)[q] = (float)av;
-                    out64[q] = av;
-                }
+                Zs[(wr + 16 * i + 4 * q4 + e) * ZS + wc + 16 * j + lr] = mode == 0 ? z : exp(z);
             }
+    __syncthreads();
+    if (mcol < M) {
+#pragma unroll 4
+        for (int r = 0; r < 16; ++r) {
+            const int R = 16 * wave + r;
+            const int64_t b = brow0 + R;
+            if (b >= Bc) break;
+            const double v = Zs[R * ZS + lane];
+            if (mode == 0) {
+                ((double *)out)[b * M + mcol] = v;
+            } else {
+                const int64_t q = base + b * stride;
+                ((float *)out)[q] = (float)v;
+                out64[q] = v;
+            }
+        }
     }
 }
 
