@@ -49,8 +49,8 @@ BYTE_MODEL = dict(
     pre="a, u (unless zero or interpolated), f (unless 1) read, u written, f_c written (w/4)",
     post="e_c (w/4), a, u, f (unless 1) read, u written",
     lds="coefficients of the LDS grids read, top-level solution written",
-    refine="24+9w B per cell of the samples still iterating (24+7w at a stage's first "
-           "step), w = V-cycle word bytes")
+    refine="24+9w B per cell of iterating samples (24+7w at a stage's first step), "
+           "w = V-cycle word bytes")
 
 KINDS = ("points", "field", "smooth", "restrict", "prolong", "coarse", "qoi", "sums", "pre", "post",
          "lds", "refine")
