@@ -280,43 +280,51 @@ __device__ __forceinline__ double coarse_odd(const double *e, int nc, int I, int
 // Bilinear (9,3,3,1)/16 prolongation with odd reflection at the walls:
 // u = P ec (add == 0, FMG interpolation) or u += P ec (coarse-grid correction).
 // u = P ec (add = 0) or u += P ec on n x n grids (n a power of two, at
-// least 4): one thread per pair of horizontally adjacent fine cells 2I, 2I+1
-// of row j, which share the coarse cells they interpolate from; the pair is
-// stored as one 16-byte vector.  Index arithmetic by shifts (per-sample
-// offsets and rows are powers of two).
+// least 4): one thread per coarse cell (I, J), i.e. per 2 x 2 block of fine
+// cells, which interpolate from the 3 x 3 coarse cells around it (nine
+// loads for four cells); each of the block's two rows is stored as one
+// 16-byte vector, so a wavefront writes 128 consecutive cells of a row per
+// store.  Index arithmetic by shifts (per-sample offsets and rows are powers
+// of two).
 __global__ void k_prolong(const double *__restrict__ ec, double *__restrict__ u, int n,
                           int64_t Bc, int add, const int32_t *__restrict__ active)
 {
     const int lg = __builtin_ctz(n);                   // n = 2^lg
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t b = t >> (2 * lg - 1);               // n^2 / 2 pairs per sample
+    const int64_t b = t >> (2 * lg - 2);               // n^2 / 4 blocks per sample
     if (b >= Bc)
         return;
     if (active && !active[b])
         return;
-    const int q = (int)(t & (((int64_t)1 << (2 * lg - 1)) - 1));
-    const int j = q >> (lg - 1), I = q & ((n >> 1) - 1);
+    const int q = (int)(t & (((int64_t)1 << (2 * lg - 2)) - 1));
     const int nc = n / 2;
+    const int J = q >> (lg - 1), I = q & (nc - 1);
     const double *eb = ec + b * nc * nc;
-    const int J = j >> 1, sy = (j & 1) ? 1 : -1;
-    const double c0 = coarse_odd(eb, nc, I, J), c1 = coarse_odd(eb, nc, I, J + sy);
-    // fine column 2I takes the coarse column I-1 as its horizontal neighbour,
-    // 2I+1 the column I+1
-    const double v0 = prolong_9331(c0, coarse_odd(eb, nc, I - 1, J), c1,
-                                   coarse_odd(eb, nc, I - 1, J + sy));
-    const double v1 = prolong_9331(c0, coarse_odd(eb, nc, I + 1, J), c1,
-                                   coarse_odd(eb, nc, I + 1, J + sy));
-    double2 *dst = reinterpret_cast<double2 *>(u + (b << (2 * lg)) + ((int64_t)j << lg) + 2 * I);
-    double2 o;
-    if (add) {
-        o = *dst;
-        o.x += v0;
-        o.y += v1;
-    } else {
-        o.x = v0;
-        o.y = v1;
+    double c[3][3];                                    // c[dy + 1][dx + 1] = e(I + dx, J + dy)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) c[dy + 1][dx + 1] = coarse_odd(eb, nc, I + dx, J + dy);
+    // fine cell (2I + a, 2J + r) takes the horizontal neighbour column
+    // I - 1 + 2a and the vertical neighbour row J - 1 + 2r
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int vy = 2 * r;                          // row index of the vertical neighbour in c
+        const double v0 = prolong_9331(c[1][1], c[1][0], c[vy][1], c[vy][0]);
+        const double v1 = prolong_9331(c[1][1], c[1][2], c[vy][1], c[vy][2]);
+        double2 *dst = reinterpret_cast<double2 *>(u + (b << (2 * lg)) +
+                                                   ((int64_t)(2 * J + r) << lg) + 2 * I);
+        double2 o;
+        if (add) {
+            o = *dst;
+            o.x += v0;
+            o.y += v1;
+        } else {
+            o.x = v0;
+            o.y = v1;
+        }
+        *dst = o;
     }
-    *dst = o;
 }
 
 // QoI of one level, one wavefront per sample: mean (compensated) and centre.
@@ -580,7 +588,7 @@ void launch_resid_restrict(hipStream_t st, const double *a, const double *f, con
 void launch_prolong(hipStream_t st, const double *ec, double *u, int n, int64_t Bc, int add,
                     const int32_t *active)
 {
-    int64_t cnt = Bc * (int64_t)n * n / 2;         // pairs of fine cells
+    int64_t cnt = Bc * (int64_t)n * n / 4;         // 2 x 2 blocks of fine cells
     hipLaunchKernelGGL(k_prolong, dim3(blocks_for(cnt)), dim3(kBlock), 0, st, ec, u, n, Bc, add,
                        active);
 }
