@@ -278,9 +278,9 @@ __device__ __forceinline__ double coarse_odd(const double *e, int nc, int I, int
 }
 
 // Bilinear (9,3,3,1)/16 prolongation with odd reflection at the walls:
-// u = P ec (add == 0, FMG interpolation) or u += P ec (coarse-grid correction).
-// u = P ec (add = 0) or u += P ec on n x n grids (n a power of two, at
-// least 4): one thread per coarse cell (I, J), i.e. per 2 x 2 block of fine
+// u = P ec (add == 0, FMG interpolation) or u += P ec (coarse-grid
+// correction) on n x n grids (n a power of two, at least 4).  One thread per
+// coarse cell (I, J), i.e. per 2 x 2 block of fine
 // cells, which interpolate from the 3 x 3 coarse cells around it (nine
 // loads for four cells); each of the block's two rows is stored as one
 // 16-byte vector, so a wavefront writes 128 consecutive cells of a row per
